@@ -1,0 +1,255 @@
+"""FP64 CPU oracle for complex 2D Gaussian CGH -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It never imports the GPU package and the GPU package never
+imports it; the two share nothing but the seeded input generators.
+
+The heavy loops (rasterization, DFT, transfer function, adjoints) live in
+``cgh_oracle.c``; this module marshals NumPy arrays and composes the steps in
+the order of the paper's optimisation loop (Alg. 1): rasterize, zero-pad,
+propagate, loss, and the adjoint chain.  The loss (Sec. 3.2, L_MSE), the
+Adam update (Kingma & Ba, Algorithm 1, as configured for the 1080p workload)
+and the finite-difference harness are plain NumPy.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+PARAM_KEYS = ("mean_pre", "log_scale", "rotation", "amplitude", "phase", "opacity_pre")
+FLAG_PAPER_ALPHA = 2
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        d = ctypes.POINTER(ctypes.c_double)
+        i = ctypes.c_int
+        f = ctypes.c_double
+        u8 = ctypes.POINTER(ctypes.c_ubyte)
+        L.orc_geometry.argtypes = [i, i, i, d, d, d, d, d]
+        L.orc_raster_brute.argtypes = [i, i, i, i, f, i, d, d, d, d, d, d, d, d]
+        L.orc_raster.argtypes = [i, i, i, i, f, i, d, d, d, d, d, d, d, d, d, d, d]
+        L.orc_ambiguous_pixels.argtypes = [i, i, i, f, f, d, d, d, d, u8]
+        L.orc_ambiguous_pixels.restype = ctypes.c_long
+        L.orc_fft1.argtypes = [i, d, i]
+        L.orc_fft2.argtypes = [i, i, d, i]
+        L.orc_transfer.argtypes = [i, i, f, f, f, d]
+        L.orc_propagate.argtypes = [i, i, i, i, i, f, d, i, d, d, d]
+        L.orc_propagate_adjoint.argtypes = [i, i, i, i, i, f, d, i, d, d, d]
+        L.orc_raster_adjoint.argtypes = [i, i, i, i, f, i, d, d, d, d, d, d, d, d, d, d, d, d, d]
+        _LIB = L
+    return _LIB
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Optics:
+    """Problem geometry: canvas H x W, C channels, padded grid Hp x Wp,
+    pixel pitch, one wavelength per channel, L propagation distances, support
+    radius k (in standard deviations; k <= 0 means unbounded)."""
+
+    def __init__(self, H, W, C, Hp, Wp, pitch, lambdas, zs, k=3.0, flags=0):
+        self.H, self.W, self.C, self.Hp, self.Wp = int(H), int(W), int(C), int(Hp), int(Wp)
+        self.pitch = float(pitch)
+        self.lambdas = _f64(lambdas).reshape(-1)
+        self.zs = _f64(zs).reshape(-1)
+        self.k = float(k)
+        self.flags = int(flags)
+        assert self.lambdas.size == self.C
+
+    @property
+    def L(self):
+        return self.zs.size
+
+
+def widen(params):
+    """FP32 parameter arrays -> exact FP64 copies (same keys)."""
+    return {k: _f64(params[k]) for k in PARAM_KEYS}
+
+
+def geometry(params, W, H):
+    """Per-Gaussian activated quantities (Suppl. activations, covariance, inverse).
+    Returns an [N, 12] array: mx, my, sx, sy, s00, s01, s11, det, i00, i01, i11, alpha."""
+    p = widen(params)
+    n = p["rotation"].shape[0]
+    out = np.zeros((n, 12))
+    lib().orc_geometry(n, W, H, _p(p["mean_pre"]), _p(p["log_scale"]), _p(p["rotation"]),
+                       _p(p["opacity_pre"]), _p(out))
+    return out
+
+
+def raster(params, opt, brute=False, support=None):
+    """Complex SLM field [C, H, W] = coherent sum of the Gaussians (Sec. 3.1).
+    ``support``: optional parameter set whose geometry decides the k-sigma
+    support predicate (holds the support fixed for finite differences)."""
+    p = widen(params)
+    n = p["rotation"].shape[0]
+    C, H, W = opt.C, opt.H, opt.W
+    re = np.zeros((C, H, W))
+    im = np.zeros((C, H, W))
+    if brute:
+        assert support is None
+        lib().orc_raster_brute(n, C, W, H, opt.k, opt.flags, _p(p["mean_pre"]),
+                               _p(p["log_scale"]), _p(p["rotation"]), _p(p["amplitude"]),
+                               _p(p["phase"]), _p(p["opacity_pre"]), _p(re), _p(im))
+    else:
+        s = widen(support) if support is not None else None
+        null = ctypes.POINTER(ctypes.c_double)()
+        lib().orc_raster(n, C, W, H, opt.k, opt.flags, _p(p["mean_pre"]), _p(p["log_scale"]),
+                         _p(p["rotation"]), _p(p["amplitude"]), _p(p["phase"]),
+                         _p(p["opacity_pre"]), _p(s["mean_pre"]) if s else null,
+                         _p(s["log_scale"]) if s else null, _p(s["rotation"]) if s else null,
+                         _p(re), _p(im))
+    return re + 1j * im
+
+
+def ambiguous_mask(params, opt, rel_band=1e-4):
+    """Pixels touched by a (Gaussian, pixel) pair whose Mahalanobis distance lies
+    within ``rel_band * k^2`` of the support boundary.  Returns (mask [H, W] bool,
+    number of such pairs)."""
+    p = widen(params)
+    n = p["rotation"].shape[0]
+    mask = np.zeros((opt.H, opt.W), dtype=np.uint8)
+    cnt = lib().orc_ambiguous_pixels(n, opt.W, opt.H, opt.k, rel_band, _p(p["mean_pre"]),
+                                     _p(p["log_scale"]), _p(p["rotation"]),
+                                     _p(p["opacity_pre"]),
+                                     mask.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+    return mask.astype(bool), int(cnt)
+
+
+def fft(x, inverse=False):
+    """1-D DFT (own mixed-radix recursion); forward unnormalised, inverse 1/N."""
+    a = np.ascontiguousarray(x, dtype=np.complex128).copy()
+    lib().orc_fft1(a.shape[0], _p(a.view(np.float64)), int(inverse))
+    return a
+
+
+def fft2(x, inverse=False):
+    a = np.ascontiguousarray(x, dtype=np.complex128).copy()
+    lib().orc_fft2(a.shape[0], a.shape[1], _p(a.view(np.float64)), int(inverse))
+    return a
+
+
+def transfer(Hp, Wp, pitch, lam, z):
+    """Band-limited angular-spectrum transfer function on the natural-order
+    [Hp, Wp] frequency grid (Sec. 2; suppl. BLASM section)."""
+    h = np.zeros((Hp, Wp), dtype=np.complex128)
+    lib().orc_transfer(Hp, Wp, float(pitch), float(lam), float(z), _p(h.view(np.float64)))
+    return h
+
+
+def propagate(field, opt):
+    """[C, H, W] complex -> [L, C, H, W] complex: pad, FFT2, x H, IFFT2, crop."""
+    f = np.ascontiguousarray(field, dtype=np.complex128)
+    out = np.zeros((opt.L, opt.C, opt.H, opt.W), dtype=np.complex128)
+    lib().orc_propagate(opt.C, opt.H, opt.W, opt.Hp, opt.Wp, opt.pitch, _p(opt.lambdas), opt.L,
+                        _p(opt.zs), _p(f.view(np.float64)), _p(out.view(np.float64)))
+    return out
+
+
+def propagate_adjoint(grad_u, opt):
+    """Adjoint of ``propagate``: conjugate transfer function, same band limit,
+    summed over planes.  [L, C, H, W] -> [C, H, W]."""
+    g = np.ascontiguousarray(grad_u, dtype=np.complex128)
+    out = np.zeros((opt.C, opt.H, opt.W), dtype=np.complex128)
+    lib().orc_propagate_adjoint(opt.C, opt.H, opt.W, opt.Hp, opt.Wp, opt.pitch,
+                                _p(opt.lambdas), opt.L, _p(opt.zs), _p(g.view(np.float64)),
+                                _p(out.view(np.float64)))
+    return out
+
+
+def mse(u, target):
+    """L_MSE over all L*C*H*W intensities (Sec. 3.2), I = |u|^2.
+    Returns (loss, intensity, grad_u) with grad_u = dL/dRe(u) + j dL/dIm(u)."""
+    I = u.real ** 2 + u.imag ** 2
+    T = np.asarray(target, dtype=np.float64).reshape(I.shape)
+    M = I.size
+    diff = I - T
+    loss = float(np.sum(diff * diff) / M)
+    dL_dI = 2.0 * diff / M
+    grad_u = dL_dI * 2.0 * u
+    return loss, I, grad_u
+
+
+def raster_adjoint(params, grad_field, opt):
+    """Gradients of the pre-activation parameters from dL/dU0 (suppl. Backward Pass)."""
+    p = widen(params)
+    n = p["rotation"].shape[0]
+    C = opt.C
+    g = np.ascontiguousarray(grad_field, dtype=np.complex128)
+    out = {"mean_pre": np.zeros((n, 2)), "log_scale": np.zeros((n, 2)),
+           "rotation": np.zeros(n), "amplitude": np.zeros((n, C)), "phase": np.zeros((n, C)),
+           "opacity_pre": np.zeros(n)}
+    lib().orc_raster_adjoint(n, C, opt.W, opt.H, opt.k, opt.flags, _p(p["mean_pre"]),
+                             _p(p["log_scale"]), _p(p["rotation"]), _p(p["amplitude"]),
+                             _p(p["phase"]), _p(p["opacity_pre"]), _p(g.view(np.float64)),
+                             _p(out["mean_pre"]), _p(out["log_scale"]), _p(out["rotation"]),
+                             _p(out["amplitude"]), _p(out["phase"]), _p(out["opacity_pre"]))
+    return out
+
+
+def forward(params, target, opt, support=None):
+    """Alg. 1 forward: rasterize -> pad -> propagate -> |u|^2 -> L_MSE."""
+    field = raster(params, opt, support=support)
+    u = propagate(field, opt)
+    loss, I, grad_u = mse(u, target)
+    return {"field": field, "u": u, "intensity": I, "loss": loss, "grad_u": grad_u}
+
+
+def forward_backward(params, target, opt):
+    """Forward plus the analytic adjoint chain; returns the forward dict with
+    ``grad_field`` (dL/dU0) and ``grads`` (pre-activation parameter gradients)."""
+    fwd = forward(params, target, opt)
+    fwd["grad_field"] = propagate_adjoint(fwd["grad_u"], opt)
+    fwd["grads"] = raster_adjoint(params, fwd["grad_field"], opt)
+    return fwd
+
+
+def loss_only(params, target, opt, support=None):
+    return forward(params, target, opt, support=support)["loss"]
+
+
+def fd_gradient(params, target, opt, key, index, h=None):
+    """Central finite difference of L_MSE w.r.t. one pre-activation parameter
+    entry, in FP64, with the support held at the unperturbed parameters."""
+    base = widen(params)
+    flat = base[key].reshape(-1)
+    x0 = float(flat[index])
+    if h is None:
+        h = 1e-6 * max(1.0, abs(x0))
+    plus = {k: v.copy() for k, v in base.items()}
+    minus = {k: v.copy() for k, v in base.items()}
+    plus[key].reshape(-1)[index] = x0 + h
+    minus[key].reshape(-1)[index] = x0 - h
+    lp = loss_only(plus, target, opt, support=base)
+    lm = loss_only(minus, target, opt, support=base)
+    return (lp - lm) / (2.0 * h)
+
+
+def adam(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Textbook Adam (Kingma & Ba 2015, Algorithm 1), FP64; returns new (p, m, v)."""
+    p, g, m, v = (np.asarray(a, dtype=np.float64) for a in (p, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def psnr(loss):
+    """PSNR for intensities in [0, 1] from the mean squared error."""
+    return 10.0 * np.log10(1.0 / loss)

@@ -1,0 +1,191 @@
+"""Pins for the oracle's rasterizer (Sec. 3.1 coherent sum; supplementary
+activations, covariance, inversion, evaluation): the Gaussian's closed-form
+Fourier transform, lattice-point counts of the k-sigma support, and
+symmetries of the sum."""
+import math
+
+import numpy as np
+import pytest
+
+
+def one(mean_pre, log_scale, rotation, amplitude, phase, opacity_pre):
+    C = len(amplitude)
+    return {
+        "mean_pre": np.array([mean_pre], np.float32).reshape(1, 2),
+        "log_scale": np.array([log_scale], np.float32).reshape(1, 2),
+        "rotation": np.array([rotation], np.float32),
+        "amplitude": np.array([amplitude], np.float32).reshape(1, C),
+        "phase": np.array([phase], np.float32).reshape(1, C),
+        "opacity_pre": np.array([opacity_pre], np.float32),
+    }
+
+
+def cat(*ps):
+    return {k: np.concatenate([p[k] for p in ps]) for k in ps[0]}
+
+
+def opt(O, H, W, C=1, k=3.0, flags=0):
+    return O.Optics(H, W, C, 2 * H, 2 * W, 8e-6, [515e-9] * C, [1e-3], k=k, flags=flags)
+
+
+def sigmoid(x):
+    return 1.0 / (1.0 + math.exp(-x))
+
+
+def test_single_gaussian_matches_closed_form_spectrum(O):
+    """The DFT of one untruncated sampled Gaussian equals the periodised
+    continuous transform (Poisson summation):
+        X[k] = sum_m  A e^{j phi} 2 pi sqrt(det S) exp(-2 pi^2 nu^T S nu) e^{-2 pi j nu.mu},
+        nu = (k_x / W + m_x, k_y / H + m_y),
+    with S = R(theta) diag(s)^2 R(theta)^T + 0.1 I in matrix form.  Pins the
+    activations, the regularised covariance, the pixel origin (phase ramp) and
+    the DFT sign."""
+    H, W = 64, 80
+    xt, yt, sxt, syt, th, c, ph, at = 0.13, -0.21, 0.9, 0.4, 0.7, 0.8, 1.1, 0.3
+    p = one((xt, yt), (sxt, syt), th, (c,), (ph,), at)
+    f64 = {k: v.astype(np.float64) for k, v in p.items()}
+    xt, yt = f64["mean_pre"][0]
+    sxt, syt = f64["log_scale"][0]
+    th, c, ph, at = f64["rotation"][0], f64["amplitude"][0, 0], f64["phase"][0, 0], f64["opacity_pre"][0]
+    field = O.raster(p, opt(O, H, W, k=0.0))[0]
+    X = O.fft2(field)
+    mu = np.array([W * sigmoid(2 * xt), H * sigmoid(2 * yt)])   # (tanh u + 1)/2 = sigmoid(2u)
+    R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    S = R @ np.diag([math.exp(sxt) + 0.1, math.exp(syt) + 0.1]) ** 2 @ R.T + 0.1 * np.eye(2)
+    A = sigmoid(at) * c * np.exp(1j * ph)
+    ky, kx = np.mgrid[0:H, 0:W]
+    ref = np.zeros((H, W), complex)
+    for my in (-1, 0, 1):
+        for mx in (-1, 0, 1):
+            nx = kx / W + mx
+            ny = ky / H + my
+            quad = S[0, 0] * nx * nx + 2 * S[0, 1] * nx * ny + S[1, 1] * ny * ny
+            ref += (A * 2 * math.pi * math.sqrt(np.linalg.det(S)) * np.exp(-2 * math.pi ** 2 * quad)
+                    * np.exp(-2j * math.pi * (nx * mu[0] + ny * mu[1])))
+    assert np.max(np.abs(X - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("s2, expected", [(24.5 / 9.0, 81), (4.0, 113), (1.0, 29)])
+def test_support_is_k_sigma_ellipse_lattice_count(O, s2, expected):
+    """An isotropic Gaussian centred on a pixel (x~ = 0 puts the mean at W/2,
+    H/2 exactly) has support {i^2 + j^2 <= 9 (s^2 + 0.1)}: its pixel count is
+    the Gauss circle count N(r^2) (OEIS A057655).  s^2 = 24.5/9 gives
+    r^2 = 25.4 -> N = 81 (without the +0.1 regulariser it would be N(24.5) = 69);
+    s^2 = 4 -> r^2 = 36.9 -> 113; s^2 = 1 -> 9.9 -> 29."""
+    ls = math.log(math.sqrt(s2) - 0.1)
+    p = one((0.0, 0.0), (ls, ls), 0.3, (1.0,), (0.0,), 0.0)
+    f = O.raster(p, opt(O, 32, 32))[0]
+    assert int(np.count_nonzero(f)) == expected
+    assert f[16, 16] == pytest.approx(0.5, abs=1e-15)   # alpha = sigmoid(0), G(mean) = 1
+
+
+def test_axis_aligned_gaussian_is_separable(O):
+    p = one((0.05, -0.1), (0.6, 1.1), 0.0, (0.9,), (0.4,), 0.2)
+    f = O.raster(p, opt(O, 40, 48, k=0.0))[0]
+    # rank one: an outer product of a column profile and a row profile
+    s = np.linalg.svd(f, compute_uv=False)
+    assert s[1] < 1e-13 * s[0]
+
+
+def test_isotropic_gaussian_ignores_rotation(O):
+    a = O.raster(one((0.1, 0.1), (0.7, 0.7), 0.0, (1.0,), (0.2,), 0.0), opt(O, 30, 30))
+    b = O.raster(one((0.1, 0.1), (0.7, 0.7), 1.234, (1.0,), (0.2,), 0.0), opt(O, 30, 30))
+    assert np.max(np.abs(a - b)) < 1e-14
+
+
+def test_rotation_direction(O):
+    """With s_x > s_y the major axis points along (cos theta, sin theta) in
+    (column, row) coordinates: R(theta) = [[cos, -sin], [sin, cos]]."""
+    p = one((0.0, 0.0), (1.2, 0.0), math.pi / 4, (1.0,), (0.0,), 0.0)
+    f = np.abs(O.raster(p, opt(O, 40, 40, k=0.0))[0])
+    # mean at (20, 20); compare (+3, +3) and (+3, -3) offsets (x = column, y = row)
+    assert f[23, 23] > 1.5 * f[17, 23]
+    p2 = one((0.0, 0.0), (1.2, 0.0), -math.pi / 4, (1.0,), (0.0,), 0.0)
+    f2 = np.abs(O.raster(p2, opt(O, 40, 40, k=0.0))[0])
+    assert f2[17, 23] > 1.5 * f2[23, 23]
+
+
+def test_quarter_turn_swaps_axes(O):
+    a = O.raster(one((0.1, -0.2), (1.0, 0.3), math.pi / 2, (1.0,), (0.0,), 0.0), opt(O, 32, 32))
+    b = O.raster(one((0.1, -0.2), (0.3, 1.0), 0.0, (1.0,), (0.0,), 0.0), opt(O, 32, 32))
+    assert np.max(np.abs(a - b)) < 1e-6   # float32 rotation pi/2 is not exact
+
+
+def test_transpose_symmetry(O):
+    """Reflecting the canvas across its diagonal maps (mu_x, mu_y, theta) to
+    (mu_y, mu_x, pi/2 - theta)."""
+    a = O.raster(one((0.1, -0.25), (0.8, 0.2), 0.4, (1.0,), (0.3,), 0.0), opt(O, 36, 36))[0]
+    b = O.raster(one((-0.25, 0.1), (0.8, 0.2), math.pi / 2 - 0.4, (1.0,), (0.3,), 0.0),
+                 opt(O, 36, 36))[0]
+    assert np.max(np.abs(a.T - b)) < 1e-6
+
+
+def test_coherent_sum_properties(O):
+    """Order independence, superposition, global phase and channel amplitude
+    linearity (Sec. 3.1: H = sum_n alpha_n c_n g_n e^{j phi_n})."""
+    rng = np.random.default_rng(5)
+    from paper_2511_15022_amd import synth
+    p = synth.params(11, 40, 24, 28, 2)
+    o = opt(O, 24, 28, C=2)
+    f = O.raster(p, o)
+    perm = rng.permutation(40)
+    fp = O.raster({k: v[perm] for k, v in p.items()}, o)
+    assert np.max(np.abs(f - fp)) < 1e-13
+    a = {k: v[:17] for k, v in p.items()}
+    b = {k: v[17:] for k, v in p.items()}
+    assert np.max(np.abs(O.raster(a, o) + O.raster(b, o) - f)) < 1e-13
+    q = dict(p)
+    q["phase"] = (p["phase"].astype(np.float64) + 0.5).astype(np.float32)
+    # phase shift is exact only up to float32 rounding of the shifted phases
+    assert np.max(np.abs(O.raster(q, o) - np.exp(0.5j) * f)) < 1e-5
+    r = dict(p)
+    r["amplitude"] = p["amplitude"] * np.float32(2.0)
+    assert np.max(np.abs(O.raster(r, o) - 2.0 * f)) < 1e-13
+
+
+def test_box_restricted_loop_equals_brute_force(O):
+    from paper_2511_15022_amd import synth
+    for seed, (H, W, C, n) in enumerate([(16, 16, 1, 8), (37, 29, 3, 60), (64, 48, 2, 300)]):
+        p = synth.params(100 + seed, n, H, W, C)
+        o = opt(O, H, W, C=C)
+        assert np.max(np.abs(O.raster(p, o) - O.raster(p, o, brute=True))) < 1e-13
+
+
+def test_hand_sum_tiny(O):
+    """Two Gaussians on a 5x5 canvas, evaluated entry by entry from the
+    paper's per-pixel formulas written in matrix form."""
+    p = cat(one((0.0, 0.0), (0.0, -0.5), 0.5, (0.7, 0.2), (0.3, 2.0), 0.5),
+            one((0.2, -0.3), (-0.3, 0.1), 2.0, (0.4, 0.9), (-1.0, 0.1), -1.0))
+    o = O.Optics(5, 5, 2, 10, 10, 8e-6, [515e-9, 639e-9], [1e-3], k=3.0)
+    f = O.raster(p, o, brute=True)
+    ref = np.zeros((2, 5, 5), complex)
+    P = {k: v.astype(np.float64) for k, v in p.items()}
+    for n in range(2):
+        mu = np.array([5 * sigmoid(2 * P["mean_pre"][n, 0]), 5 * sigmoid(2 * P["mean_pre"][n, 1])])
+        th = P["rotation"][n]
+        R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+        S = R @ np.diag(np.exp(P["log_scale"][n]) + 0.1) ** 2 @ R.T + 0.1 * np.eye(2)
+        Si = np.linalg.inv(S)
+        for j in range(5):
+            for i in range(5):
+                d = np.array([i, j]) - mu
+                q = d @ Si @ d
+                if q <= 9.0:
+                    for c in range(2):
+                        ref[c, j, i] += (sigmoid(P["opacity_pre"][n]) * P["amplitude"][n, c]
+                                         * math.exp(-q / 2) * np.exp(1j * P["phase"][n, c]))
+    assert np.max(np.abs(f - ref)) < 1e-14
+
+
+def test_paper_alpha_flag(O):
+    """Alg. 2 variant: alpha_eff = min(0.99, alpha G), skipped below 1/255."""
+    p = one((0.0, 0.0), (1.0, 1.0), 0.0, (0.5,), (0.0,), 8.0)   # alpha ~ 0.99966
+    f = O.raster(p, opt(O, 40, 40, k=0.0, flags=O.FLAG_PAPER_ALPHA))[0]
+    assert f[20, 20] == pytest.approx(0.5 * 0.99, abs=1e-15)
+    plain = O.raster(p, opt(O, 40, 40, k=0.0))[0]
+    alpha = sigmoid(8.0)
+    w = plain.real / 0.5                       # alpha G per pixel (phase 0)
+    kept = w >= 1.0 / 255.0
+    assert np.all(f[~kept] == 0.0)
+    assert np.allclose(f[kept].real, 0.5 * np.minimum(0.99, w[kept]), rtol=0, atol=1e-15)
+    assert alpha > 0.99
