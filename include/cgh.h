@@ -1,0 +1,190 @@
+/*
+ * cgh.h -- C ABI of the MI355X (gfx950) library for complex-valued 2D Gaussian
+ * computer-generated holography: differentiable rasterization of N complex 2D
+ * Gaussians into the SLM-plane field, band-limited angular-spectrum (BLASM)
+ * propagation, the MSE loss on |u|^2, their adjoints, and an Adam step.
+ *
+ * The calls follow the paper's optimisation loop (Alg. 1): ComplexRasterize2D
+ * -> ZeroPad -> MultiPlanePropagate -> loss -> optimiser step, with the
+ * problem statement of Sec. 3 (target I in R^{C x H x W}, hologram in
+ * C^{C x H x W}).
+ *
+ * Conventions shared by every entry point
+ *  - Memory: every buffer pointer is a DEVICE pointer owned by the caller and
+ *    must stay valid until the work queued on `stream` has finished.  The
+ *    library allocates no device memory: all scratch lives in the caller's
+ *    workspace (size from cgh_workspace_size), so peak memory is the caller's.
+ *    Pointers must be 16-byte aligned.
+ *  - Streams: `stream` is a hipStream_t (NULL = legacy default stream).  Every
+ *    call only enqueues work on it and returns without waiting, except
+ *    cgh_create (which builds its tables on the stream and waits for them)
+ *    and cgh_read_status (which waits for the stream).
+ *  - Errors: argument errors are detected on the host before anything is
+ *    enqueued and return a non-zero cgh_status; cgh_last_error() then returns
+ *    a message (thread-local).  Launch failures return CGH_ERR_DEVICE.
+ *    Pair-list overflow is detected on the device and reported by
+ *    cgh_read_status.  No C++ exception crosses this interface.
+ *  - Threads: a context may be used by one host thread at a time.
+ *
+ * Layouts
+ *  - Complex values are interleaved float pairs (re, im), cgh_c64 below --
+ *    the layout of torch.complex64.
+ *  - Field:     [C][H][W] complex, row-major, x (column) fastest.
+ *  - Intensity: [L][C][H][W] float.  Target: same layout.
+ *  - Parameters (pre-activation, Sec. 3.1 and the supplementary activation
+ *    functions), one flat float array of n * (6 + 2C) values holding, in this
+ *    order, contiguous blocks:
+ *        mean_pre [n][2]  (x~: mean = (tanh(x~) + 1)/2 * [W, H], pixels)
+ *        log_scale[n][2]  (s~: scale = exp(s~) + 0.1)
+ *        rotation [n]     (theta, radians)
+ *        amplitude[n][C]  (c, unconstrained)
+ *        phase    [n][C]  (phi, radians)
+ *        opacity  [n]     (alpha~: alpha = sigmoid(alpha~))
+ *    Gradients use the same layout.  Pixel (i, j) sits at the point (i, j)
+ *    of the same frame as the mean (0-based, i = column).
+ */
+#ifndef CGH_H
+#define CGH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  float re, im;
+} cgh_c64;
+
+typedef enum {
+  CGH_OK = 0,
+  CGH_ERR_INVALID_ARG = 1, /* bad size, null or misaligned pointer, unsupported value */
+  CGH_ERR_WORKSPACE = 2,   /* workspace smaller than cgh_workspace_size            */
+  CGH_ERR_CAPACITY = 3,    /* pair list overflowed (see cgh_read_status)            */
+  CGH_ERR_DEVICE = 4,      /* HIP runtime error                                     */
+  CGH_ERR_UNSUPPORTED = 5, /* valid request this build does not implement           */
+  CGH_ERR_STATE = 6        /* call order violated (e.g. adjoint before rasterize)   */
+} cgh_status;
+
+#define CGH_MAX_CHANNELS 4
+#define CGH_MAX_PLANES 8
+
+/* Geometry and optics of one hologram problem. */
+typedef struct {
+  int32_t height, width;         /* H, W: SLM pixels (1 .. 8192 each)                     */
+  int32_t channels;              /* C: 1 .. CGH_MAX_CHANNELS, one wavelength each          */
+  int32_t pad_height, pad_width; /* padded FFT grid Hp >= H, Wp >= W; each must factor     */
+                                 /* into 2, 3, 5 and be <= 8192 (0 = 2H, 2W)               */
+  double pitch_m;                /* pixel pitch (square pixels), metres                   */
+  double wavelength_m[CGH_MAX_CHANNELS]; /* lambda per channel, metres                   */
+  int32_t num_planes;            /* L: propagation distances (this build: 1)              */
+  double z_m[CGH_MAX_PLANES];    /* propagation distance per plane, metres (any sign)     */
+  float support_sigma;           /* k: a Gaussian covers the pixels with Mahalanobis      */
+                                 /* distance q <= k^2 (k <= 0: every pixel)               */
+  int32_t max_gaussians;         /* capacity for n                                        */
+  int64_t max_pairs;             /* capacity of the (tile, Gaussian) list (0: default     */
+                                 /* 8 * max_gaussians + 65536)                            */
+  int32_t flags;                 /* reserved, must be 0                                   */
+} cgh_config;
+
+typedef struct cgh_ctx cgh_ctx;
+
+/* Bytes of device workspace a context with this configuration needs.
+ * Host-only; validates the configuration (CGH_ERR_INVALID_ARG on a bad one). */
+cgh_status cgh_workspace_size(const cgh_config *cfg, size_t *bytes);
+
+/* Creates a context over a caller-owned device workspace (>= cgh_workspace_size
+ * bytes, 256-byte aligned).  Builds, on `stream`, the FFT twiddle tables and the
+ * band-limited transfer function H(fx, fy; lambda_c, z_l) of every channel and
+ * plane in FP64 (Sec. 2 equation for H; supplementary "Spatial Frequency
+ * Computation", "Bandlimit Computation", "Transfer Function Evaluation"), rounds
+ * it to complex64, and waits for the stream.  *out receives a host handle. */
+cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_bytes,
+                      void *stream, cgh_ctx **out);
+
+/* Releases the host handle (the workspace stays the caller's). */
+cgh_status cgh_destroy(cgh_ctx *ctx);
+
+/* ComplexRasterize2D (Alg. 2; Sec. 3.1 coherent sum; supplementary Forward
+ * Pass): field[c][j][i] = sum_n alpha_n c_{n,c} G_n(i, j) exp(j phi_{n,c}) over
+ * the Gaussians whose k-sigma ellipse contains (i, j), with
+ * G = exp(max(-q/2, -50)).  params: n * (6 + 2C) floats (layout above),
+ * 0 <= n <= max_gaussians.  field: [C][H][W] complex, overwritten.
+ * Keeps the per-tile Gaussian lists in the workspace for the adjoint. */
+cgh_status cgh_rasterize(cgh_ctx *ctx, const float *params, int32_t n, cgh_c64 *field,
+                         void *stream);
+
+/* Render path (Alg. 1 ZeroPad + MultiPlanePropagate): for each plane l and
+ * channel c, u = crop(IFFT2(H(lambda_c, z_l) . FFT2(pad(field_c)))), where pad
+ * embeds the field centred in the Hp x Wp grid and crop takes the same window.
+ * intensity: [L][C][H][W] = |u|^2 (may be NULL); field_out: [L][C][H][W] complex
+ * u (may be NULL).  field is not modified. */
+cgh_status cgh_propagate(cgh_ctx *ctx, const cgh_c64 *field, float *intensity,
+                         cgh_c64 *field_out, void *stream);
+
+/* Fused loss and adjoint of one optimisation step (Sec. 3.2 L_MSE; supplementary
+ * BLASM Backward Pass and rasterizer Backward Pass): propagates `field` (the
+ * output of cgh_rasterize for these params), evaluates
+ *   L = (1 / (L C H W)) sum (|u|^2 - target)^2,
+ * and back-propagates it through |.|^2, the conjugate transfer function with the
+ * same band limit, and the rasterizer.
+ *   target   : [L][C][H][W] float.
+ *   loss     : device double[2] <- {L, 10 log10(1 / L)} (may be NULL).
+ *   grad_field: [C][H][W] complex <- dL/dRe(U0) + j dL/dIm(U0) (may be NULL:
+ *              the workspace holds it).
+ *   grads    : n * (6 + 2C) floats <- dL/dparams (pre-activation; layout above).
+ * Precondition: the last cgh_rasterize on this context used the same n and
+ * params (CGH_ERR_STATE if n differs). */
+cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_c64 *field,
+                        const float *target, double *loss, cgh_c64 *grad_field, float *grads,
+                        void *stream);
+
+/* Adjoint of cgh_propagate's intensity for an arbitrary loss: given
+ * grad_intensity = dL/dI ([L][C][H][W]) at I = |u(field)|^2, writes
+ * grad_field = dL/dRe(field) + j dL/dIm(field) ([C][H][W]).  Recomputes u. */
+cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
+                                 const float *grad_intensity, cgh_c64 *grad_field,
+                                 void *stream);
+
+/* Adjoint of cgh_rasterize (supplementary rasterizer Backward Pass, items 1-7):
+ * grads <- dL/dparams from grad_field = dL/dRe(U0) + j dL/dIm(U0) ([C][H][W]).
+ * Same precondition as cgh_backward. */
+cgh_status cgh_rasterize_adjoint(cgh_ctx *ctx, const float *params, int32_t n,
+                                 const cgh_c64 *grad_field, float *grads, void *stream);
+
+/* Adam step (Kingma & Ba, Algorithm 1) over `count` floats, in place:
+ *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
+ *   p <- p - lr / (1 - b1^t) * m / (sqrt(v) / sqrt(1 - b2^t) + eps).
+ * t >= 1 is the step number.  lr_groups: optional HOST array of 6 learning
+ * rates for the six parameter blocks of the layout above (then count must be
+ * n * (6 + 2C) with n = count / (6 + 2 * channels)); NULL: `lr` everywhere.
+ * channels is used only with lr_groups. */
+cgh_status cgh_step(float *params, const float *grads, float *m, float *v, int64_t count,
+                    int32_t t, float lr, float beta1, float beta2, float eps,
+                    const float *lr_groups, int32_t channels, void *stream);
+
+/* Copies the transfer function of (channel, plane) into `out`, a device array of
+ * (Hp/2 + 1) x (Wp/2 + 1) complex: entry [qy][qx] is H at |fy| = qy / (Hp pitch),
+ * |fx| = qx / (Wp pitch) (H depends on the frequency only through |fx|, |fy|). */
+cgh_status cgh_get_transfer(cgh_ctx *ctx, int32_t channel, int32_t plane, cgh_c64 *out,
+                            void *stream);
+
+/* Waits for `stream`, then reports the device-side status of the last
+ * rasterize: *pairs <- number of (tile, Gaussian) pairs it needed (may be NULL).
+ * Returns CGH_ERR_CAPACITY if that exceeded max_pairs (the field and gradients of
+ * that call are then incomplete), CGH_OK otherwise. */
+cgh_status cgh_read_status(cgh_ctx *ctx, void *stream, int64_t *pairs);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *cgh_last_error(void);
+
+/* ABI version of this header (CGH_ABI_VERSION). */
+#define CGH_ABI_VERSION 1
+int32_t cgh_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGH_H */

@@ -1,0 +1,266 @@
+"""ctypes binding of libcgh (include/cgh.h): argument marshalling only.
+
+Every computation runs in the HIP library; PyTorch supplies device memory and
+the current stream.  If libcgh.so is missing, every call raises -- there is no
+fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcgh.so")
+
+MAX_CHANNELS = 4
+MAX_PLANES = 8
+PARAM_KEYS = ("mean_pre", "log_scale", "rotation", "amplitude", "phase", "opacity_pre")
+
+STATUS = {0: "CGH_OK", 1: "CGH_ERR_INVALID_ARG", 2: "CGH_ERR_WORKSPACE", 3: "CGH_ERR_CAPACITY",
+          4: "CGH_ERR_DEVICE", 5: "CGH_ERR_UNSUPPORTED", 6: "CGH_ERR_STATE"}
+
+
+class CghError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class cgh_config(ctypes.Structure):
+    _fields_ = [
+        ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("channels", ctypes.c_int32),
+        ("pad_height", ctypes.c_int32), ("pad_width", ctypes.c_int32),
+        ("pitch_m", ctypes.c_double),
+        ("wavelength_m", ctypes.c_double * MAX_CHANNELS),
+        ("num_planes", ctypes.c_int32),
+        ("z_m", ctypes.c_double * MAX_PLANES),
+        ("support_sigma", ctypes.c_float),
+        ("max_gaussians", ctypes.c_int32),
+        ("max_pairs", ctypes.c_int64),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+# (name, restype, argtypes) for every entry point of include/cgh.h
+_VP = ctypes.c_void_p
+_SIGS = [
+    ("cgh_workspace_size", ctypes.c_int, [ctypes.POINTER(cgh_config), ctypes.POINTER(ctypes.c_size_t)]),
+    ("cgh_create", ctypes.c_int, [ctypes.POINTER(cgh_config), _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    ("cgh_destroy", ctypes.c_int, [_VP]),
+    ("cgh_rasterize", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
+    ("cgh_propagate", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    ("cgh_backward", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("cgh_propagate_adjoint", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    ("cgh_rasterize_adjoint", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
+    ("cgh_step", ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP, ctypes.c_int32, _VP]),
+    ("cgh_get_transfer", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP]),
+    ("cgh_read_status", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_int64)]),
+    ("cgh_last_error", ctypes.c_char_p, []),
+    ("cgh_abi_version", ctypes.c_int32, []),
+]
+EXPORTS = tuple(name for name, _, _ in _SIGS)
+
+_lib = None
+
+
+def lib():
+    """The loaded libcgh (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libcgh.so not found at {LIB_PATH}; build it with "
+                               "paper_2511_15022_amd/build.py (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise CghError(status, lib().cgh_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need(t, dtype, numel, name, device):
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel or t.device != device:
+        raise ValueError(f"{name}: expected contiguous {dtype} with {numel} elements on {device}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+def param_count(n, C):
+    return n * (6 + 2 * C)
+
+
+def pack(params, device=None):
+    """Dict of the six pre-activation arrays -> one flat float32 tensor in the
+    library's layout (mean_pre, log_scale, rotation, amplitude, phase, opacity_pre)."""
+    parts = [torch.as_tensor(params[k], dtype=torch.float32).reshape(-1) for k in PARAM_KEYS]
+    flat = torch.cat(parts)
+    return flat.to(device) if device is not None else flat
+
+
+def unpack(flat, n, C):
+    """Views of a flat parameter (or gradient) tensor as the six arrays."""
+    sizes = [2 * n, 2 * n, n, C * n, C * n, n]
+    shapes = [(n, 2), (n, 2), (n,), (n, C), (n, C), (n,)]
+    out, o = {}, 0
+    for k, sz, sh in zip(PARAM_KEYS, sizes, shapes):
+        out[k] = flat[o:o + sz].view(sh)
+        o += sz
+    return out
+
+
+class Context:
+    """One hologram problem on one device (cgh_create / cgh_destroy).  The
+    device workspace is a torch tensor owned by this object."""
+
+    def __init__(self, height, width, channels, pitch, wavelengths, zs, pad=None,
+                 support_sigma=3.0, max_gaussians=0, max_pairs=0, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.H, self.W, self.C = int(height), int(width), int(channels)
+        zs = list(zs)
+        wavelengths = list(wavelengths)
+        if len(wavelengths) != self.C:
+            raise ValueError("one wavelength per channel")
+        cfg = cgh_config()
+        cfg.height, cfg.width, cfg.channels = self.H, self.W, self.C
+        hp, wp = pad if pad is not None else (0, 0)
+        cfg.pad_height, cfg.pad_width = int(hp), int(wp)
+        cfg.pitch_m = float(pitch)
+        for i, lam in enumerate(wavelengths):
+            cfg.wavelength_m[i] = float(lam)
+        cfg.num_planes = len(zs)
+        for i, z in enumerate(zs):
+            cfg.z_m[i] = float(z)
+        cfg.support_sigma = float(support_sigma)
+        cfg.max_gaussians = int(max_gaussians)
+        cfg.max_pairs = int(max_pairs)
+        cfg.flags = 0
+        self.cfg = cfg
+        self.L = len(zs)
+        self.Hp = cfg.pad_height or 2 * self.H
+        self.Wp = cfg.pad_width or 2 * self.W
+        size = ctypes.c_size_t(0)
+        _check(lib().cgh_workspace_size(ctypes.byref(cfg), ctypes.byref(size)))
+        self.workspace_bytes = size.value
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
+                                     device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        handle = ctypes.c_void_p()
+        _check(lib().cgh_create(ctypes.byref(cfg), ctypes.c_void_p(aligned), self.workspace_bytes,
+                                _stream(self.device), ctypes.byref(handle)))
+        self.handle = handle
+        self.last_n = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cgh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- shapes -------------------------------------------------------------
+    def field_shape(self):
+        return (self.C, self.H, self.W)
+
+    def plane_shape(self):
+        return (self.L, self.C, self.H, self.W)
+
+    # -- entry points -------------------------------------------------------
+    def rasterize(self, params, n, field=None):
+        _need(params, torch.float32, param_count(n, self.C), "params", self.device)
+        if field is None:
+            field = torch.empty(self.field_shape(), dtype=torch.complex64, device=self.device)
+        _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)
+        _check(lib().cgh_rasterize(self.handle, _ptr(params), int(n), _ptr(field),
+                                   _stream(self.device)))
+        self.last_n = n
+        return field
+
+    def propagate(self, field, intensity=True, field_out=False):
+        _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)
+        I = torch.empty(self.plane_shape(), dtype=torch.float32, device=self.device) if intensity else None
+        u = torch.empty(self.plane_shape(), dtype=torch.complex64, device=self.device) if field_out else None
+        _check(lib().cgh_propagate(self.handle, _ptr(field), _ptr(I), _ptr(u), _stream(self.device)))
+        return I, u
+
+    def backward(self, params, n, field, target, loss=None, grad_field=None, grads=None):
+        _need(params, torch.float32, param_count(n, self.C), "params", self.device)
+        _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)
+        _need(target, torch.float32, self.L * self.C * self.H * self.W, "target", self.device)
+        if grads is None:
+            grads = torch.empty_like(params)
+        if loss is not None:
+            _need(loss, torch.float64, 2, "loss", self.device)
+        if grad_field is not None:
+            _need(grad_field, torch.complex64, self.C * self.H * self.W, "grad_field", self.device)
+        _check(lib().cgh_backward(self.handle, _ptr(params), int(n), _ptr(field), _ptr(target),
+                                  _ptr(loss), _ptr(grad_field), _ptr(grads), _stream(self.device)))
+        return grads
+
+    def propagate_adjoint(self, field, grad_intensity, grad_field=None):
+        _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)
+        _need(grad_intensity, torch.float32, self.L * self.C * self.H * self.W, "grad_intensity",
+              self.device)
+        if grad_field is None:
+            grad_field = torch.empty(self.field_shape(), dtype=torch.complex64, device=self.device)
+        _check(lib().cgh_propagate_adjoint(self.handle, _ptr(field), _ptr(grad_intensity),
+                                           _ptr(grad_field), _stream(self.device)))
+        return grad_field
+
+    def rasterize_adjoint(self, params, n, grad_field, grads=None):
+        _need(params, torch.float32, param_count(n, self.C), "params", self.device)
+        _need(grad_field, torch.complex64, self.C * self.H * self.W, "grad_field", self.device)
+        if grads is None:
+            grads = torch.empty_like(params)
+        _check(lib().cgh_rasterize_adjoint(self.handle, _ptr(params), int(n), _ptr(grad_field),
+                                           _ptr(grads), _stream(self.device)))
+        return grads
+
+    def get_transfer(self, channel=0, plane=0):
+        out = torch.empty((self.Hp // 2 + 1, self.Wp // 2 + 1), dtype=torch.complex64,
+                          device=self.device)
+        _check(lib().cgh_get_transfer(self.handle, int(channel), int(plane), _ptr(out),
+                                      _stream(self.device)))
+        return out
+
+    def read_status(self, raise_on_overflow=True):
+        pairs = ctypes.c_int64(0)
+        st = lib().cgh_read_status(self.handle, _stream(self.device), ctypes.byref(pairs))
+        if st != 0 and (raise_on_overflow or st != 3):
+            _check(st)
+        return pairs.value, st == 0
+
+
+def step(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, lr_groups=None,
+         channels=1):
+    """cgh_step: in-place Adam over flat tensors of equal size."""
+    for name, x in (("grads", grads), ("m", m), ("v", v)):
+        _need(x, torch.float32, params.numel(), name, params.device)
+    _need(params, torch.float32, params.numel(), "params", params.device)
+    groups = None
+    if lr_groups is not None:
+        groups = (ctypes.c_float * 6)(*[float(x) for x in lr_groups])
+    _check(lib().cgh_step(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(), int(t),
+                          float(lr), float(beta1), float(beta2), float(eps),
+                          ctypes.cast(groups, ctypes.c_void_p) if groups is not None else None,
+                          int(channels), _stream(params.device)))

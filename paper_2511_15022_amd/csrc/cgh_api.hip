@@ -1,0 +1,378 @@
+// C ABI of libcgh: argument validation, workspace carving, and the sequence of
+// kernel launches behind each entry point.  No device allocation happens here:
+// every buffer is the caller's or lives in the caller's workspace.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "cgh_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+cgh_status fail(cgh_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+cgh_status device_fail(hipError_t e, const char *where) {
+  return fail(CGH_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+#define CGH_CHECK_LAUNCH(expr, where)              \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return device_fail(e_, where); \
+  } while (0)
+
+// Validates cfg and fills the derived sizes of ctx (no pointers).
+cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
+  using namespace cgh;
+  if (!cfg) return fail(CGH_ERR_INVALID_ARG, "config is NULL");
+  const cgh_config &f = *cfg;
+  if (f.height < 1 || f.width < 1 || f.height > kMaxFft || f.width > kMaxFft)
+    return fail(CGH_ERR_INVALID_ARG, "height/width must be in [1, %d] (got %d x %d)", kMaxFft,
+                f.height, f.width);
+  if (f.channels < 1 || f.channels > CGH_MAX_CHANNELS)
+    return fail(CGH_ERR_INVALID_ARG, "channels must be in [1, %d] (got %d)", CGH_MAX_CHANNELS,
+                f.channels);
+  if (f.num_planes < 1 || f.num_planes > CGH_MAX_PLANES)
+    return fail(CGH_ERR_INVALID_ARG, "num_planes must be in [1, %d] (got %d)", CGH_MAX_PLANES,
+                f.num_planes);
+  if (f.num_planes != 1)
+    return fail(CGH_ERR_UNSUPPORTED, "this build propagates to one plane (num_planes = %d)",
+                f.num_planes);
+  const int Hp = f.pad_height ? f.pad_height : 2 * f.height;
+  const int Wp = f.pad_width ? f.pad_width : 2 * f.width;
+  if (Hp < f.height || Wp < f.width)
+    return fail(CGH_ERR_INVALID_ARG, "padded grid %d x %d smaller than the SLM %d x %d", Hp, Wp,
+                f.height, f.width);
+  if (!smooth235(Hp) || !smooth235(Wp) || Hp > kMaxFft || Wp > kMaxFft)
+    return fail(CGH_ERR_INVALID_ARG,
+                "padded grid %d x %d: each side must factor into 2, 3, 5 and be <= %d", Hp, Wp,
+                kMaxFft);
+  if (!(f.pitch_m > 0.0) || !std::isfinite(f.pitch_m))
+    return fail(CGH_ERR_INVALID_ARG, "pitch must be positive and finite");
+  for (int ch = 0; ch < f.channels; ++ch)
+    if (!(f.wavelength_m[ch] > 0.0) || !std::isfinite(f.wavelength_m[ch]))
+      return fail(CGH_ERR_INVALID_ARG, "wavelength of channel %d must be positive", ch);
+  for (int l = 0; l < f.num_planes; ++l)
+    if (!std::isfinite(f.z_m[l])) return fail(CGH_ERR_INVALID_ARG, "z of plane %d not finite", l);
+  if (!std::isfinite(f.support_sigma))
+    return fail(CGH_ERR_INVALID_ARG, "support_sigma must be finite");
+  if (f.max_gaussians < 0 || f.max_gaussians > (1 << 28))
+    return fail(CGH_ERR_INVALID_ARG, "max_gaussians must be in [0, 2^28]");
+  if (f.max_pairs < 0 || f.max_pairs > 0x7fffffffLL)
+    return fail(CGH_ERR_INVALID_ARG, "max_pairs must be in [0, 2^31)");
+  if (f.flags != 0) return fail(CGH_ERR_INVALID_ARG, "flags must be 0 in this build");
+
+  c->cfg = f;
+  c->cfg.pad_height = Hp;
+  c->cfg.pad_width = Wp;
+  c->H = f.height;
+  c->W = f.width;
+  c->C = f.channels;
+  c->L = f.num_planes;
+  c->Hp = Hp;
+  c->Wp = Wp;
+  c->Hq = Hp / 2 + 1;
+  c->Wq = Wp / 2 + 1;
+  c->tiles_x = (f.width + kTile - 1) / kTile;
+  c->tiles_y = (f.height + kTile - 1) / kTile;
+  c->num_tiles = c->tiles_x * c->tiles_y;
+  int bits = 0;
+  while ((1 << bits) < c->num_tiles) ++bits;
+  c->sort_passes = (bits + kSortBits - 1) / kSortBits;
+  int64_t cap = f.max_pairs ? f.max_pairs : 8LL * f.max_gaussians + 65536;
+  if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
+  c->pair_cap = cap;
+  c->sort_blocks = (int)((cap + kSortItems - 1) / kSortItems);
+  c->rec_stride = rec_stride(c->C);
+  c->part_stride = partial_stride(c->C);
+  c->last_n = -1;
+  c->sorted = 0;
+  if (!make_plan(Wp, &c->plan_x) || !make_plan(Hp, &c->plan_y))
+    return fail(CGH_ERR_INVALID_ARG, "cannot plan FFTs of %d and %d", Wp, Hp);
+  return CGH_OK;
+}
+
+}  // namespace
+
+namespace cgh {
+
+size_t carve(Ctx *c, char *base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char * {
+    off = (off + 255) & ~(size_t)255;
+    char *p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  const size_t N = (size_t)c->cfg.max_gaussians;
+  const size_t cap = (size_t)c->pair_cap;
+  const size_t HW = (size_t)c->H * c->W;
+  c->tw_x = (float2 *)take(sizeof(float2) * c->Wp);
+  c->tw_y = (float2 *)take(sizeof(float2) * c->Hp);
+  c->htab = (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq);
+  c->spec = (float2 *)take(sizeof(float2) * c->L * c->C * (size_t)c->H * c->Wp);
+  c->field_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
+  c->gfield_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
+  c->rec = (float *)take(sizeof(float) * c->rec_stride * (N ? N : 1));
+  c->rect = (uint2 *)take(sizeof(uint2) * (N ? N : 1));
+  c->counts = (uint32_t *)take(sizeof(uint32_t) * (N ? N : 1));
+  c->offsets = (uint32_t *)take(sizeof(uint32_t) * (N + 1));
+  for (int b = 0; b < 2; ++b) {
+    c->keys[b] = (uint32_t *)take(sizeof(uint32_t) * cap);
+    c->vals[b] = (uint32_t *)take(sizeof(uint32_t) * cap);
+  }
+  c->ranges = (uint2 *)take(sizeof(uint2) * c->num_tiles);
+  c->hist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)c->sort_blocks);
+  const size_t scan_len = std::max(N + 1, (size_t)256 * c->sort_blocks);
+  c->scan_tmp = (uint32_t *)take(sizeof(uint32_t) * (scan_len / kScanItems + 2));
+  c->partials = (float *)take(sizeof(float) * c->part_stride * cap);
+  c->loss_part = (double *)take(sizeof(double) * c->L * c->C * (size_t)c->H);
+  c->status = (uint32_t *)take(sizeof(uint32_t) * 4);
+  return (off + 255) & ~(size_t)255;
+}
+
+}  // namespace cgh
+
+using cgh::Ctx;
+
+struct cgh_ctx {
+  Ctx c;
+};
+
+extern "C" {
+
+int32_t cgh_abi_version(void) { return CGH_ABI_VERSION; }
+
+const char *cgh_last_error(void) { return g_err; }
+
+cgh_status cgh_workspace_size(const cgh_config *cfg, size_t *bytes) {
+  if (!bytes) return fail(CGH_ERR_INVALID_ARG, "bytes is NULL");
+  Ctx c;
+  cgh_status st = setup(cfg, &c);
+  if (st != CGH_OK) return st;
+  *bytes = cgh::carve(&c, nullptr);
+  return CGH_OK;
+}
+
+cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_bytes,
+                      void *stream, cgh_ctx **out) {
+  if (!out) return fail(CGH_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  Ctx c;
+  cgh_status st = setup(cfg, &c);
+  if (st != CGH_OK) return st;
+  const size_t need = cgh::carve(&c, nullptr);
+  if (!workspace) return fail(CGH_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)workspace & 255u) != 0)
+    return fail(CGH_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (workspace_bytes < need)
+    return fail(CGH_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  cgh::carve(&c, (char *)workspace);
+  hipStream_t s = (hipStream_t)stream;
+  CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_x, c.Wp, s), "twiddles");
+  CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_y, c.Hp, s), "twiddles");
+  CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, s), "transfer function");
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return device_fail(e, "cgh_create");
+  cgh_ctx *h = new (std::nothrow) cgh_ctx;
+  if (!h) return fail(CGH_ERR_INVALID_ARG, "host allocation failed");
+  h->c = c;
+  *out = h;
+  return CGH_OK;
+}
+
+cgh_status cgh_destroy(cgh_ctx *ctx) {
+  delete ctx;
+  return CGH_OK;
+}
+
+static cgh_status check_n(const Ctx &c, int32_t n) {
+  if (n < 0 || n > c.cfg.max_gaussians)
+    return fail(CGH_ERR_INVALID_ARG, "n = %d outside [0, max_gaussians = %d]", n,
+                c.cfg.max_gaussians);
+  return CGH_OK;
+}
+
+cgh_status cgh_rasterize(cgh_ctx *ctx, const float *params, int32_t n, cgh_c64 *field,
+                         void *stream) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  Ctx &c = ctx->c;
+  cgh_status st = check_n(c, n);
+  if (st != CGH_OK) return st;
+  if ((n > 0 && !params) || !field) return fail(CGH_ERR_INVALID_ARG, "params/field is NULL");
+  if (!aligned16(field)) return fail(CGH_ERR_INVALID_ARG, "field must be 16-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  CGH_CHECK_LAUNCH(cgh::launch_preprocess(c, params, n, s), "preprocess");
+  CGH_CHECK_LAUNCH(cgh::launch_binning(c, n, s), "binning");
+  CGH_CHECK_LAUNCH(cgh::launch_raster_fwd(c, reinterpret_cast<float2 *>(field), s), "raster");
+  c.last_n = n;
+  return CGH_OK;
+}
+
+// F1 + F2: field -> column-pass output in c.spec
+static cgh_status forward_spectrum(Ctx &c, const cgh_c64 *field, hipStream_t s) {
+  const float2 *f = reinterpret_cast<const float2 *>(field);
+  CGH_CHECK_LAUNCH(cgh::launch_row_fft(c, f, c.W, c.W, c.spec, c.Wp, c.Wp, c.C * c.H, 0, s),
+                   "row fft");
+  CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, c.spec, 0, s), "column pass");
+  return CGH_OK;
+}
+
+// B1 + B2: adjoint seed in c.spec -> dL/dU0
+static cgh_status adjoint_spectrum(Ctx &c, float2 *grad_field, hipStream_t s) {
+  CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, c.spec, 1, s), "adjoint column pass");
+  CGH_CHECK_LAUNCH(cgh::launch_row_fft(c, c.spec, c.Wp, c.Wp, grad_field, c.W, c.W, c.C * c.H,
+                                       1, s),
+                   "adjoint row fft");
+  return CGH_OK;
+}
+
+cgh_status cgh_propagate(cgh_ctx *ctx, const cgh_c64 *field, float *intensity,
+                         cgh_c64 *field_out, void *stream) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  Ctx &c = ctx->c;
+  if (!field) return fail(CGH_ERR_INVALID_ARG, "field is NULL");
+  if (!aligned16(field) || !aligned16(intensity) || !aligned16(field_out))
+    return fail(CGH_ERR_INVALID_ARG, "buffers must be 16-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  cgh_status st = forward_spectrum(c, field, s);
+  if (st != CGH_OK) return st;
+  CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, nullptr, nullptr, intensity,
+                                        reinterpret_cast<float2 *>(field_out), 0, s),
+                   "intensity row pass");
+  return CGH_OK;
+}
+
+cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_c64 *field,
+                        const float *target, double *loss, cgh_c64 *grad_field, float *grads,
+                        void *stream) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  Ctx &c = ctx->c;
+  cgh_status st = check_n(c, n);
+  if (st != CGH_OK) return st;
+  if (n != c.last_n)
+    return fail(CGH_ERR_STATE, "backward with n = %d after rasterize with n = %d", n, c.last_n);
+  if (!field || !target || (n > 0 && (!params || !grads)))
+    return fail(CGH_ERR_INVALID_ARG, "field/target/params/grads is NULL");
+  if (!aligned16(field) || !aligned16(grad_field) || ((uintptr_t)loss & 7u))
+    return fail(CGH_ERR_INVALID_ARG, "misaligned buffer");
+  hipStream_t s = (hipStream_t)stream;
+  float2 *gf = grad_field ? reinterpret_cast<float2 *>(grad_field) : c.gfield_tmp;
+  st = forward_spectrum(c, field, s);
+  if (st != CGH_OK) return st;
+  CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, target, nullptr, nullptr, nullptr, 1, s),
+                   "loss row pass");
+  if (loss) CGH_CHECK_LAUNCH(cgh::launch_loss_finalize(c, loss, s), "loss");
+  st = adjoint_spectrum(c, gf, s);
+  if (st != CGH_OK) return st;
+  CGH_CHECK_LAUNCH(cgh::launch_raster_adjoint(c, params, n, gf, grads, s), "raster adjoint");
+  return CGH_OK;
+}
+
+cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
+                                 const float *grad_intensity, cgh_c64 *grad_field,
+                                 void *stream) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  Ctx &c = ctx->c;
+  if (!field || !grad_intensity || !grad_field)
+    return fail(CGH_ERR_INVALID_ARG, "field/grad_intensity/grad_field is NULL");
+  if (!aligned16(field) || !aligned16(grad_field))
+    return fail(CGH_ERR_INVALID_ARG, "misaligned buffer");
+  hipStream_t s = (hipStream_t)stream;
+  cgh_status st = forward_spectrum(c, field, s);
+  if (st != CGH_OK) return st;
+  CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, nullptr, grad_intensity, nullptr, nullptr, 1,
+                                        s),
+                   "adjoint seed row pass");
+  return adjoint_spectrum(c, reinterpret_cast<float2 *>(grad_field), s);
+}
+
+cgh_status cgh_rasterize_adjoint(cgh_ctx *ctx, const float *params, int32_t n,
+                                 const cgh_c64 *grad_field, float *grads, void *stream) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  Ctx &c = ctx->c;
+  cgh_status st = check_n(c, n);
+  if (st != CGH_OK) return st;
+  if (n != c.last_n)
+    return fail(CGH_ERR_STATE, "adjoint with n = %d after rasterize with n = %d", n, c.last_n);
+  if (!grad_field || (n > 0 && (!params || !grads)))
+    return fail(CGH_ERR_INVALID_ARG, "grad_field/params/grads is NULL");
+  if (!aligned16(grad_field)) return fail(CGH_ERR_INVALID_ARG, "misaligned grad_field");
+  hipStream_t s = (hipStream_t)stream;
+  CGH_CHECK_LAUNCH(cgh::launch_raster_adjoint(c, params, n,
+                                              reinterpret_cast<const float2 *>(grad_field),
+                                              grads, s),
+                   "raster adjoint");
+  return CGH_OK;
+}
+
+cgh_status cgh_step(float *params, const float *grads, float *m, float *v, int64_t count,
+                    int32_t t, float lr, float beta1, float beta2, float eps,
+                    const float *lr_groups, int32_t channels, void *stream) {
+  if (count < 0) return fail(CGH_ERR_INVALID_ARG, "count < 0");
+  if (count == 0) return CGH_OK;
+  if (!params || !grads || !m || !v) return fail(CGH_ERR_INVALID_ARG, "NULL buffer");
+  if (!aligned16(params) || !aligned16(grads) || !aligned16(m) || !aligned16(v))
+    return fail(CGH_ERR_INVALID_ARG, "buffers must be 16-byte aligned");
+  if (t < 1) return fail(CGH_ERR_INVALID_ARG, "step number t must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+    return fail(CGH_ERR_INVALID_ARG, "betas must be in [0, 1) and eps >= 0");
+  int n = 0;
+  if (lr_groups) {
+    if (channels < 1 || channels > CGH_MAX_CHANNELS)
+      return fail(CGH_ERR_INVALID_ARG, "channels must be in [1, %d]", CGH_MAX_CHANNELS);
+    const int64_t per = 6 + 2 * channels;
+    if (count % per) return fail(CGH_ERR_INVALID_ARG, "count not a multiple of 6 + 2C");
+    n = (int)(count / per);
+  }
+  const double bc1 = 1.0 - std::pow((double)beta1, (double)t);
+  const double bc2 = 1.0 - std::pow((double)beta2, (double)t);
+  CGH_CHECK_LAUNCH(cgh::launch_adam(params, grads, m, v, count, lr, (float)(1.0 / bc1), beta1,
+                                    beta2, eps, (float)(1.0 / std::sqrt(bc2)), lr_groups, n,
+                                    channels, (hipStream_t)stream),
+                   "adam");
+  return CGH_OK;
+}
+
+cgh_status cgh_get_transfer(cgh_ctx *ctx, int32_t channel, int32_t plane, cgh_c64 *out,
+                            void *stream) {
+  if (!ctx || !out) return fail(CGH_ERR_INVALID_ARG, "ctx/out is NULL");
+  Ctx &c = ctx->c;
+  if (channel < 0 || channel >= c.C || plane < 0 || plane >= c.L)
+    return fail(CGH_ERR_INVALID_ARG, "channel/plane out of range");
+  const size_t elems = (size_t)c.Hq * c.Wq;
+  hipError_t e = hipMemcpyAsync(out, c.htab + ((size_t)channel * c.L + plane) * elems,
+                                elems * sizeof(float2), hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "cgh_get_transfer");
+  return CGH_OK;
+}
+
+cgh_status cgh_read_status(cgh_ctx *ctx, void *stream, int64_t *pairs) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  Ctx &c = ctx->c;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "cgh_read_status");
+  uint32_t st[2] = {0, 0};
+  e = hipMemcpy(st, c.status, sizeof(st), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return device_fail(e, "cgh_read_status");
+  if (pairs) *pairs = (int64_t)st[1];
+  if (st[0])
+    return fail(CGH_ERR_CAPACITY, "pair list needed %u entries, capacity is %lld", st[1],
+                (long long)c.pair_cap);
+  return CGH_OK;
+}
+
+}  // extern "C"

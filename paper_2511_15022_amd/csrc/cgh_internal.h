@@ -1,0 +1,107 @@
+// Internal declarations shared by the HIP translation units of libcgh.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "cgh.h"
+
+namespace cgh {
+
+constexpr int kTile = 16;          // rasterizer tile edge, pixels
+constexpr int kMaxStages = 16;     // radix stages per FFT length
+constexpr int kMaxFft = 8192;      // longest supported FFT
+constexpr int kSortBits = 8;       // bits per radix-sort pass
+constexpr int kSortItems = 4096;   // keys per radix-sort block (256 threads x 16)
+constexpr int kScanItems = 2048;   // elements per scan block (256 threads x 8)
+
+// Mixed-radix (2, 3, 4, 5, 8) Stockham plan for one transform length.
+// Stage s has radix r[s]; ns[s] is the product of the radices before it;
+// magic[s] = ceil(2^32 / ns[s]) divides exactly for indices < 2^13;
+// tws[s] = n / (ns[s] r[s]) is the stride into the length-n twiddle table.
+struct FftPlan {
+  int n;
+  int nstages;
+  int radix[kMaxStages];
+  int ns[kMaxStages];
+  uint32_t magic[kMaxStages];
+  int tws[kMaxStages];
+};
+
+bool make_plan(int n, FftPlan *plan);
+bool smooth235(int n);
+
+// Record of one Gaussian for the rasterizer (FP32, written by the FP64
+// preprocess).  Offsets within a record of rec_stride floats:
+enum RecField {
+  R_MIX = 0,   // floor(mean_x), stored as int bits
+  R_MIY = 1,   // floor(mean_y), int bits
+  R_MFX = 2,   // mean_x - floor(mean_x)
+  R_MFY = 3,
+  R_A = 4,     // -0.5 log2(e) inv00
+  R_B = 5,     // -log2(e) inv01
+  R_C = 6,     // -0.5 log2(e) inv11   (log2 G = a dx^2 + b dx dy + c dy^2)
+  R_RX = 7,    // k sqrt(Sigma00): half-width of the support box, pixels
+  R_RY = 8,    // k sqrt(Sigma11)
+  R_AMP = 9    // then alpha c_c cos(phi_c), alpha c_c sin(phi_c) for c < C
+};
+inline int rec_stride(int C) { return ((R_AMP + 2 * C) + 3) & ~3; }
+inline int partial_stride(int C) { return ((2 * C + 5) + 3) & ~3; }
+
+struct Ctx {
+  cgh_config cfg;
+  int H, W, C, L, Hp, Wp, Hq, Wq;   // Hq, Wq: quarter-table extents Hp/2+1, Wp/2+1
+  int tiles_x, tiles_y, num_tiles, sort_passes;
+  int64_t pair_cap;
+  int rec_stride, part_stride;
+  int sort_blocks;                  // radix-sort grid (covers pair_cap)
+  FftPlan plan_x, plan_y;
+  int last_n;                       // n of the last rasterize (-1: none)
+  // workspace carve (device pointers)
+  float2 *tw_x, *tw_y;              // twiddles exp(-2 pi i k / n), n = Wp, Hp
+  float2 *htab;                     // [C][L][Hq][Wq]
+  float2 *spec;                     // [L][C][H][Wp] row/column-pass buffer
+  float2 *field_tmp;                // [C][H][W]
+  float2 *gfield_tmp;               // [C][H][W]
+  float *rec;                       // [max_gaussians][rec_stride]
+  uint2 *rect;                      // [max_gaussians] tile rectangles (x0|x1<<16, y0|y1<<16)
+  uint32_t *counts;                 // [max_gaussians]
+  uint32_t *offsets;                // [max_gaussians + 1]
+  uint32_t *keys[2], *vals[2];      // [pair_cap] ping-pong
+  uint2 *ranges;                    // [num_tiles] [start, end) into the sorted list
+  uint32_t *hist;                   // [256 * sort_blocks]
+  uint32_t *scan_tmp;               // partial sums for scans
+  float *partials;                  // [pair_cap][part_stride] raster-adjoint partials
+  double *loss_part;                // [L*C*H]
+  uint32_t *status;                 // [0] overflow flag, [1] pair total
+  int sorted;                       // which ping-pong buffer holds the sorted pairs
+};
+
+size_t carve(Ctx *c, char *base);   // returns bytes used (base may be null)
+
+// ---- launchers (all enqueue on `s`; return hipSuccess or the launch error) ----
+hipError_t launch_build_twiddles(float2 *tw, int n, hipStream_t s);
+hipError_t launch_build_transfer(const Ctx &c, hipStream_t s);
+hipError_t launch_row_fft(const Ctx &c, const float2 *in, int in_len, long in_stride,
+                          float2 *out, int out_len, long out_stride, int rows, int inverse,
+                          hipStream_t s);
+hipError_t launch_col_pass(const Ctx &c, float2 *data, int conj_h, hipStream_t s);
+hipError_t launch_row_loss(const Ctx &c, float2 *data, const float *target,
+                           const float *grad_intensity, float *intensity, float2 *u_out,
+                           int make_grad, hipStream_t s);
+hipError_t launch_loss_finalize(const Ctx &c, double *loss, hipStream_t s);
+
+hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s);
+hipError_t launch_binning(Ctx &c, int n, hipStream_t s);
+hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s);
+hipError_t launch_raster_adjoint(const Ctx &c, const float *params, int n,
+                                 const float2 *grad_field, float *grads, hipStream_t s);
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr,
+                       float step_size_scale, float beta1, float beta2, float eps,
+                       float inv_sqrt_bc2, const float *lr_groups, int n, int C,
+                       hipStream_t s);
+
+}  // namespace cgh

@@ -1,0 +1,690 @@
+// Complex 2D Gaussian rasterizer on gfx950 (Alg. 2; Sec. 3.1 coherent sum;
+// supplementary Forward and Backward Pass).
+//
+//   preprocess (FP64)  activations, covariance, inverse, support box, tile
+//                      rectangle; writes one FP32 record per Gaussian
+//   binning            exclusive scan of tile counts -> emit (tile, gaussian)
+//                      pairs in Gaussian order -> stable LSD radix sort on the
+//                      tile id -> [start, end) per tile.  Deterministic: each
+//                      tile lists its Gaussians in increasing index.
+//   forward            one 16x16 tile per workgroup, one 8x8 sub-block per
+//                      wavefront; Gaussian records staged in LDS, culled per
+//                      sub-block with a ballot, summed per pixel in FP32
+//   adjoint            per tile, the tile's dL/dU0 staged in LDS; one lane per
+//                      (tile, Gaussian) pair walks the pair's pixels and keeps
+//                      its 2C + 5 partial sums in registers (no per-pixel
+//                      storage, no atomics); the per-pair partials are summed in
+//                      a fixed order per Gaussian by the FP64 preprocess adjoint
+#include <cmath>
+
+#include "cgh_internal.h"
+
+namespace cgh {
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr float kPowerFloor2 = -50.0f * 1.4426950408889634f;  // clamp of the exponent, base 2
+
+constexpr int rec_stride_c(int C) { return ((R_AMP + 2 * C) + 3) & ~3; }
+constexpr int part_stride_c(int C) { return ((2 * C + 5) + 3) & ~3; }
+
+// ----------------------------------------------------------------------------
+// Preprocess (FP64): supplementary "Parameter Activation Functions",
+// "2D Covariance Matrix Computation", "2D Covariance Matrix Inversion".
+// ----------------------------------------------------------------------------
+struct Geom {
+  double mx, my, sx, sy, ct, st, s00, s01, s11, det, dsafe, i00, i01, i11, alpha;
+};
+
+__device__ __forceinline__ Geom geometry(const float *__restrict__ params, int n, int C, int g,
+                                         int W, int H) {
+  const float *mp = params;
+  const float *ls = params + 2 * (size_t)n;
+  const float *rot = params + 4 * (size_t)n;
+  const float *op = params + (size_t)(5 + 2 * C) * n;
+  Geom q;
+  q.mx = 0.5 * (tanh((double)mp[2 * g]) + 1.0) * (double)W;
+  q.my = 0.5 * (tanh((double)mp[2 * g + 1]) + 1.0) * (double)H;
+  q.sx = exp((double)ls[2 * g]) + 0.1;
+  q.sy = exp((double)ls[2 * g + 1]) + 0.1;
+  sincos((double)rot[g], &q.st, &q.ct);
+  const double sx2 = q.sx * q.sx, sy2 = q.sy * q.sy;
+  q.s00 = sx2 * q.ct * q.ct + sy2 * q.st * q.st + 0.1;
+  q.s01 = (sx2 - sy2) * q.ct * q.st;
+  q.s11 = sx2 * q.st * q.st + sy2 * q.ct * q.ct + 0.1;
+  q.det = q.s00 * q.s11 - q.s01 * q.s01;
+  q.dsafe = q.det > 1e-10 ? q.det : 1e-10;
+  q.i00 = q.s11 / q.dsafe;
+  q.i01 = -q.s01 / q.dsafe;
+  q.i11 = q.s00 / q.dsafe;
+  q.alpha = 1.0 / (1.0 + exp(-(double)op[g]));
+  return q;
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ params, int n,
+                                                    int W, int H, float k, int tiles_x,
+                                                    float *__restrict__ rec,
+                                                    uint2 *__restrict__ rect,
+                                                    uint32_t *__restrict__ counts) {
+  constexpr int RS = rec_stride_c(C);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const Geom q = geometry(params, n, C, g, W, H);
+  const float *amp = params + 5 * (size_t)n;
+  const float *ph = params + (size_t)(5 + C) * n;
+  float r[RS];
+#pragma unroll
+  for (int i = 0; i < RS; ++i) r[i] = 0.f;
+  const double fx = floor(q.mx), fy = floor(q.my);
+  r[R_MIX] = __int_as_float((int)fx);
+  r[R_MIY] = __int_as_float((int)fy);
+  r[R_MFX] = (float)(q.mx - fx);
+  r[R_MFY] = (float)(q.my - fy);
+  r[R_A] = (float)(-0.5 * kLog2e * q.i00);
+  r[R_B] = (float)(-kLog2e * q.i01);
+  r[R_C] = (float)(-0.5 * kLog2e * q.i11);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    double s, co;
+    sincos((double)ph[(size_t)g * C + c], &s, &co);
+    const double a = q.alpha * (double)amp[(size_t)g * C + c];
+    r[R_AMP + 2 * c] = (float)(a * co);
+    r[R_AMP + 2 * c + 1] = (float)(a * s);
+  }
+  // support box (k sqrt(Sigma00), k sqrt(Sigma11)) -> inclusive pixel range
+  uint32_t cnt = 0;
+  uint2 rc = make_uint2(0u, 0u);
+  double i0, i1, j0, j1;
+  if (k > 0.f) {
+    const double rx = (double)k * sqrt(q.s00), ry = (double)k * sqrt(q.s11);
+    r[R_RX] = (float)rx;
+    r[R_RY] = (float)ry;
+    const double pad = 1e-3;  // keeps every pixel the FP32 predicate could accept
+    i0 = fmax(0.0, ceil(q.mx - rx - pad));
+    i1 = fmin((double)(W - 1), floor(q.mx + rx + pad));
+    j0 = fmax(0.0, ceil(q.my - ry - pad));
+    j1 = fmin((double)(H - 1), floor(q.my + ry + pad));
+  } else {
+    r[R_RX] = 1e30f;
+    r[R_RY] = 1e30f;
+    i0 = 0; i1 = W - 1; j0 = 0; j1 = H - 1;
+  }
+  if (i0 <= i1 && j0 <= j1) {
+    const uint32_t tx0 = (uint32_t)i0 / kTile, tx1 = (uint32_t)i1 / kTile;
+    const uint32_t ty0 = (uint32_t)j0 / kTile, ty1 = (uint32_t)j1 / kTile;
+    cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+  }
+  float4 *dst = reinterpret_cast<float4 *>(rec + (size_t)g * RS);
+#pragma unroll
+  for (int i = 0; i < RS / 4; ++i) dst[i] = make_float4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
+  counts[g] = cnt;
+  rect[g] = rc;
+  (void)tiles_x;
+}
+
+hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid((n + 255) / 256), block(256);
+  const float k = c.cfg.support_sigma;
+  switch (c.C) {
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts); break;
+    case 3: hipLaunchKernelGGL(k_preprocess<3>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts); break;
+    default: hipLaunchKernelGGL(k_preprocess<4>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts); break;
+  }
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Exclusive scan of u32 (three kernels: per-block scan, scan of block sums,
+// add).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+// block-wide exclusive scan of one value per thread (256 threads); returns the
+// thread's exclusive prefix, *total gets the block sum
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total) {
+  __shared__ uint32_t wsum[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t incl = wave_inclusive_scan(v);
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int w = 0; w < wave; ++w) off += wsum[w];
+  *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  __syncthreads();
+  return off + incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_local(const uint32_t *__restrict__ in,
+                                                    uint32_t *__restrict__ out, int len,
+                                                    uint32_t *__restrict__ block_sums) {
+  const int base = blockIdx.x * kScanItems + threadIdx.x * 8;
+  uint32_t v[8];
+  uint32_t s = 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t x = base + e < len ? in[base + e] : 0u;
+    v[e] = s;
+    s += x;
+  }
+  uint32_t total;
+  const uint32_t off = block_exclusive_scan(s, &total);
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    if (base + e < len) out[base + e] = v[e] + off;
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// exclusive scan of the block sums in one block; writes the grand total to
+// total_out[0] (and total_out[1] if total_out2 is set)
+__global__ __launch_bounds__(256) void k_scan_sums(uint32_t *__restrict__ sums, int nb,
+                                                   uint32_t *__restrict__ total_out,
+                                                   uint32_t *__restrict__ total_out2) {
+  uint32_t carry = 0;
+  for (int base = 0; base < nb; base += 256) {
+    const int i = base + threadIdx.x;
+    const uint32_t x = i < nb ? sums[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(x, &tot);
+    if (i < nb) sums[i] = ex + carry;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    if (total_out) *total_out = carry;
+    if (total_out2) *total_out2 = carry;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(uint32_t *__restrict__ out, int len,
+                                                  const uint32_t *__restrict__ sums) {
+  const int base = blockIdx.x * kScanItems + threadIdx.x * 8;
+  const uint32_t add = sums[blockIdx.x];
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    if (base + e < len) out[base + e] += add;
+}
+
+static hipError_t scan_u32(const uint32_t *in, uint32_t *out, int len, uint32_t *tmp,
+                           uint32_t *total, uint32_t *total2, hipStream_t s) {
+  const int nb = (len + kScanItems - 1) / kScanItems;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, in, out, len, tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, tmp, nb, total, total2);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, s, out, len, tmp);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Binning: emit (tile, gaussian) pairs, stable radix sort, tile ranges.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict__ counts,
+                                              const uint32_t *__restrict__ offsets,
+                                              const uint2 *__restrict__ rect, int tiles_x,
+                                              int64_t cap, uint32_t *__restrict__ keys,
+                                              uint32_t *__restrict__ vals,
+                                              uint32_t *__restrict__ status) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const uint32_t cnt = counts[g];
+  if (cnt == 0) return;
+  const uint64_t off = offsets[g];
+  const uint2 rc = rect[g];
+  const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
+  const uint32_t w = tx1 - tx0 + 1;
+  uint32_t tx = tx0, ty = ty0;
+  for (uint32_t t = 0; t < cnt; ++t) {
+    const uint64_t pos = off + t;
+    if ((int64_t)pos >= cap) {
+      atomicOr(&status[0], 1u);
+      break;
+    }
+    keys[pos] = ty * (uint32_t)tiles_x + tx;
+    vals[pos] = (uint32_t)g;
+    if (++tx > tx1) { tx = tx0; ++ty; }
+  }
+  (void)w;
+}
+
+__device__ __forceinline__ uint32_t pair_count(const uint32_t *status, int64_t cap) {
+  const uint64_t total = status[1];
+  return (uint32_t)((int64_t)total < cap ? total : cap);
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys,
+                                                    const uint32_t *__restrict__ status,
+                                                    int64_t cap, int shift,
+                                                    uint32_t *__restrict__ hist, int nblocks) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t count = pair_count(status, cap);
+  const uint32_t base = blockIdx.x * kSortItems;
+  for (int e = 0; e < kSortItems / 256; ++e) {
+    const uint32_t i = base + e * 256 + threadIdx.x;
+    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: keys are taken in index order, 256 per round; a key's rank
+// among equal digits is (earlier rounds) + (earlier waves this round) + (earlier
+// lanes of its wave), the last from ballots over the digit bits.
+__global__ __launch_bounds__(256) void k_radix_scatter(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+    const uint32_t *__restrict__ status, int64_t cap, int shift,
+    const uint32_t *__restrict__ hist_scan, int nblocks) {
+  __shared__ uint32_t running[256];
+  __shared__ uint32_t wcnt[4][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  running[tid] = hist_scan[(size_t)tid * nblocks + blockIdx.x];
+  for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+  __syncthreads();
+  const uint32_t count = pair_count(status, cap);
+  const uint32_t base = blockIdx.x * kSortItems;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int e = 0; e < kSortItems / 256; ++e) {
+    const uint32_t i = base + e * 256 + tid;
+    const bool valid = i < count;
+    const uint32_t key = valid ? kin[i] : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t bb = __ballot(on);
+      m &= on ? bb : ~bb;
+    }
+    const uint32_t rank = __popcll(m & lt);
+    const bool leader = valid && (m & lt) == 0;
+    if (leader) wcnt[wave][d] = __popcll(m);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = running[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      if (pos < count) {  // always true for a consistent histogram; guards the write
+        kout[pos] = key;
+        vout[pos] = vin[i];
+      }
+    }
+    __syncthreads();
+    running[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+    for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_ranges(uint2 *__restrict__ ranges, int num_tiles) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < num_tiles) ranges[t] = make_uint2(0u, 0u);
+}
+
+__global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ status,
+                         int64_t cap, uint2 *__restrict__ ranges, uint32_t num_tiles) {
+  const uint32_t count = pair_count(status, cap);
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t k = keys[i];
+  if (k >= num_tiles) return;  // keys are tile ids; guards the write
+  if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
+  if (i + 1 == count || keys[i + 1] != k) ranges[k].y = i + 1;
+}
+
+__global__ void k_zero_u32(uint32_t *p, int len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) p[i] = 0u;
+}
+
+hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
+  // status[0] (overflow) and status[1] (pair total) restart at zero
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c.status, 4);
+  if (n > 0) {
+    hipError_t e = scan_u32(c.counts, c.offsets, n, c.scan_tmp, c.offsets + n, c.status + 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, s, n, c.counts, c.offsets,
+                       c.rect, c.tiles_x, c.pair_cap, c.keys[0], c.vals[0], c.status);
+  }
+  int cur = 0;
+  for (int pass = 0; pass < c.sort_passes; ++pass) {
+    const int shift = pass * kSortBits;
+    hipLaunchKernelGGL(k_radix_hist, dim3(c.sort_blocks), dim3(256), 0, s, c.keys[cur],
+                       c.status, c.pair_cap, shift, c.hist, c.sort_blocks);
+    hipError_t e = scan_u32(c.hist, c.hist, 256 * c.sort_blocks, c.scan_tmp, nullptr, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(c.sort_blocks), dim3(256), 0, s, c.keys[cur],
+                       c.vals[cur], c.keys[cur ^ 1], c.vals[cur ^ 1], c.status, c.pair_cap,
+                       shift, c.hist, c.sort_blocks);
+    cur ^= 1;
+  }
+  c.sorted = cur;
+  hipLaunchKernelGGL(k_fill_ranges, dim3((c.num_tiles + 255) / 256), dim3(256), 0, s, c.ranges,
+                     c.num_tiles);
+  const int64_t grid = (c.pair_cap + 255) / 256;
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, s, c.keys[cur], c.status,
+                     c.pair_cap, c.ranges, (uint32_t)c.num_tiles);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Forward: U_c(p) = sum over the tile's Gaussians with log2 G(p) >= -k^2/2 log2 e
+// of G(p) (alpha c cos phi + j alpha c sin phi).
+// ----------------------------------------------------------------------------
+template <int C>
+__global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ rec,
+                                                    const uint32_t *__restrict__ vals,
+                                                    const uint2 *__restrict__ ranges, int W,
+                                                    int H, int tiles_x, float thr,
+                                                    float2 *__restrict__ field) {
+  constexpr int RS = rec_stride_c(C);
+  __shared__ float4 srec[256 * RS / 4];
+  const float *sr = reinterpret_cast<const float *>(srec);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tile = blockIdx.x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int X0 = tx * kTile + (wave & 1) * 8, Y0 = ty * kTile + (wave >> 1) * 8;
+  const int lx = lane & 7, ly = lane >> 3;
+  const float flx = (float)lx, fly = (float)ly;
+  float ar[C], ai[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) { ar[c] = 0.f; ai[c] = 0.f; }
+  const uint2 rg = ranges[tile];
+  for (uint32_t base = rg.x; base < rg.y; base += 256) {
+    const int cnt = (int)min(256u, rg.y - base);
+    if (tid < cnt) {
+      const uint32_t g = vals[base + tid];
+      const float4 *src = reinterpret_cast<const float4 *>(rec + (size_t)g * RS);
+#pragma unroll
+      for (int i = 0; i < RS / 4; ++i) srec[tid * (RS / 4) + i] = src[i];
+    }
+    __syncthreads();
+    uint64_t mask[4];
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {
+      const int idx = qd * 64 + lane;
+      bool hit = false;
+      if (idx < cnt) {
+        const float *s = sr + idx * RS;
+        const float ox = (float)(__float_as_int(s[R_MIX]) - X0) + s[R_MFX];
+        const float oy = (float)(__float_as_int(s[R_MIY]) - Y0) + s[R_MFY];
+        const float rx = s[R_RX] + 0.01f, ry = s[R_RY] + 0.01f;
+        hit = (ox + rx >= 0.f) && (ox - rx <= 7.f) && (oy + ry >= 0.f) && (oy - ry <= 7.f);
+      }
+      mask[qd] = __ballot(hit);
+    }
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {
+      uint64_t m = mask[qd];
+      while (m) {
+        const int b = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const float *s = sr + (qd * 64 + b) * RS;
+        // offset of the sub-block origin from the mean; then per-lane d = l + off
+        const float offx = (float)(X0 - __float_as_int(s[R_MIX])) - s[R_MFX];
+        const float offy = (float)(Y0 - __float_as_int(s[R_MIY])) - s[R_MFY];
+        const float dx = flx + offx, dy = fly + offy;
+        const float p2 = fmaf(dx, fmaf(s[R_A], dx, s[R_B] * dy), s[R_C] * dy * dy);
+        const float G = p2 >= thr ? __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2)) : 0.f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          ar[c] = fmaf(G, s[R_AMP + 2 * c], ar[c]);
+          ai[c] = fmaf(G, s[R_AMP + 2 * c + 1], ai[c]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int px = X0 + lx, py = Y0 + ly;
+  if (px < W && py < H) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) field[((size_t)c * H + py) * W + px] = make_float2(ar[c], ai[c]);
+  }
+}
+
+static float support_threshold(float k) {
+  // log2 G >= -k^2/2 log2(e)  <=>  q <= k^2 ; k <= 0: everything
+  if (k <= 0.f) return -INFINITY;
+  return (float)(-0.5 * (double)k * (double)k * kLog2e);
+}
+
+hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
+  const float thr = support_threshold(c.cfg.support_sigma);
+  const uint32_t *vals = c.vals[c.sorted];
+  dim3 grid(c.num_tiles), block(256);
+  switch (c.C) {
+    case 1: hipLaunchKernelGGL(k_raster_fwd<1>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, field); break;
+    case 2: hipLaunchKernelGGL(k_raster_fwd<2>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, field); break;
+    case 3: hipLaunchKernelGGL(k_raster_fwd<3>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, field); break;
+    default: hipLaunchKernelGGL(k_raster_fwd<4>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, field); break;
+  }
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint, tile stage.  For a pair (tile, Gaussian) and every pixel of the
+// tile inside the Gaussian's support, with g = dL/dU0 (per channel) and
+// w = dL/dpower = G sum_c (g_re P_c + g_im Q_c)  (P + jQ = alpha c e^{j phi}):
+//   S[2c] += G g_re, S[2c+1] += G g_im           (dL/dP_c, dL/dQ_c)
+//   S[2C] += w dx, S[2C+1] += w dy                (-> dL/dmean)
+//   S[2C+2] += w dx^2, S[2C+3] += w dx dy, S[2C+4] += w dy^2   (-> dL/dSigma^{-1})
+// with dx, dy = pixel - mean.  The clamped exponent has zero derivative.
+// ----------------------------------------------------------------------------
+template <int C>
+__global__ __launch_bounds__(256) void k_raster_adj(
+    const float *__restrict__ rec, const uint32_t *__restrict__ vals,
+    const uint2 *__restrict__ ranges, const uint2 *__restrict__ rect,
+    const uint32_t *__restrict__ offsets, int W, int H, int tiles_x, float thr,
+    const float2 *__restrict__ gfield, int64_t cap, float *__restrict__ partials) {
+  constexpr int RS = rec_stride_c(C);
+  constexpr int PS = part_stride_c(C);
+  __shared__ float2 sg[C][kTile * kTile];
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int X0 = tx * kTile, Y0 = ty * kTile;
+  for (int i = tid; i < C * kTile * kTile; i += 256) {
+    const int c = i / (kTile * kTile), p = i % (kTile * kTile);
+    const int x = X0 + (p % kTile), y = Y0 + (p / kTile);
+    sg[c][p] = (x < W && y < H) ? gfield[((size_t)c * H + y) * W + x] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const uint2 rg = ranges[tile];
+  for (uint32_t i = rg.x + tid; i < rg.y; i += 256) {
+    const uint32_t g = vals[i];
+    float r[RS];
+    const float4 *src = reinterpret_cast<const float4 *>(rec + (size_t)g * RS);
+#pragma unroll
+    for (int k = 0; k < RS / 4; ++k) {
+      const float4 v = src[k];
+      r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
+    }
+    const int mix = __float_as_int(r[R_MIX]), miy = __float_as_int(r[R_MIY]);
+    const float mfx = r[R_MFX], mfy = r[R_MFY];
+    // pixel box of the support inside this tile (local coordinates 0..15)
+    const float rx = fminf(r[R_RX], 1e6f) + 0.01f, ry = fminf(r[R_RY], 1e6f) + 0.01f;
+    const float cx = (float)(mix - X0) + mfx, cy = (float)(miy - Y0) + mfy;
+    const int xa = max(0, (int)ceilf(fmaxf(cx - rx, -1.f)));
+    const int xb = min(kTile - 1, (int)floorf(fminf(cx + rx, (float)kTile)));
+    const int ya = max(0, (int)ceilf(fmaxf(cy - ry, -1.f)));
+    const int yb = min(kTile - 1, (int)floorf(fminf(cy + ry, (float)kTile)));
+    float S[2 * C + 5];
+#pragma unroll
+    for (int k = 0; k < 2 * C + 5; ++k) S[k] = 0.f;
+    const float a = r[R_A], b = r[R_B], cc = r[R_C];
+    // same FP32 operations as the forward: d = (pixel offset in its 8x8
+    // sub-block) + ((sub-block origin - floor(mean)) - frac(mean))
+    const float offx0 = (float)(X0 - mix) - mfx, offx1 = (float)(X0 + 8 - mix) - mfx;
+    const float offy0 = (float)(Y0 - miy) - mfy, offy1 = (float)(Y0 + 8 - miy) - mfy;
+    for (int ly = ya; ly <= yb; ++ly) {
+      const float dy = (float)(ly & 7) + (ly < 8 ? offy0 : offy1);
+      for (int lx = xa; lx <= xb; ++lx) {
+        const float dx = (float)(lx & 7) + (lx < 8 ? offx0 : offx1);
+        const float p2 = fmaf(dx, fmaf(a, dx, b * dy), cc * dy * dy);
+        if (p2 >= thr) {
+          const float G = __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2));
+          const int p = ly * kTile + lx;
+          float gp = 0.f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const float2 gv = sg[c][p];
+            gp = fmaf(gv.x, r[R_AMP + 2 * c], fmaf(gv.y, r[R_AMP + 2 * c + 1], gp));
+            S[2 * c] = fmaf(G, gv.x, S[2 * c]);
+            S[2 * c + 1] = fmaf(G, gv.y, S[2 * c + 1]);
+          }
+          const float w = p2 > kPowerFloor2 ? gp * G : 0.f;
+          const float wx = w * dx, wy = w * dy;
+          S[2 * C] += wx;
+          S[2 * C + 1] += wy;
+          S[2 * C + 2] = fmaf(wx, dx, S[2 * C + 2]);
+          S[2 * C + 3] = fmaf(wx, dy, S[2 * C + 3]);
+          S[2 * C + 4] = fmaf(wy, dy, S[2 * C + 4]);
+        }
+      }
+    }
+    const uint2 rc = rect[g];
+    const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
+    const uint64_t pos = (uint64_t)offsets[g] + (uint64_t)(ty - (int)ty0) * (tx1 - tx0 + 1) +
+                         (uint64_t)(tx - (int)tx0);
+    if ((int64_t)pos < cap) {
+      float4 *dst = reinterpret_cast<float4 *>(partials + pos * PS);
+      float o[PS];
+#pragma unroll
+      for (int k = 0; k < PS; ++k) o[k] = k < 2 * C + 5 ? S[k] : 0.f;
+#pragma unroll
+      for (int k = 0; k < PS / 4; ++k) dst[k] = make_float4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint, Gaussian stage (FP64): sum the pair partials of each Gaussian in a
+// fixed order, then chain rule through the preprocess (supplementary Backward
+// Pass items 1-7):
+//   dL/dc_c   = alpha (cos phi dP_c + sin phi dQ_c)
+//   dL/dphi_c = alpha c (-sin phi dP_c + cos phi dQ_c)
+//   dL/dalpha = sum_c c (cos phi dP_c + sin phi dQ_c);  dalpha/dalpha~ = alpha (1 - alpha)
+//   dL/dmean  = Sigma^{-1} (sum w d);  dmean/dx~ = [W, H]/2 (1 - tanh^2 x~)
+//   dL/dSigma^{-1} entries (inv00, inv01 stored once, inv11) = -(1/2, 1, 1/2) sum w d d
+//   dL/dSigma = -Sigma^{-1} G Sigma^{-1} (G the symmetric gradient matrix), off-
+//   diagonal counted twice for the single stored Sigma01; clamped determinant:
+//   inv = adj(Sigma) / eps_d
+//   Sigma -> (s_x, s_y, theta) and s = exp(s~) + eps_s.
+// ----------------------------------------------------------------------------
+template <int C>
+__global__ __launch_bounds__(256) void k_preprocess_adj(
+    const float *__restrict__ params, int n, int W, int H,
+    const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets, int64_t cap,
+    const float *__restrict__ partials, float *__restrict__ grads) {
+  constexpr int PS = part_stride_c(C);
+  constexpr int NP = 2 * C + 5;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  double S[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) S[k] = 0.0;
+  const uint64_t off = offsets[g];
+  uint64_t end = off + counts[g];
+  if ((int64_t)end > cap) end = (uint64_t)cap;
+  for (uint64_t p = off; p < end; ++p) {
+    const float4 *src = reinterpret_cast<const float4 *>(partials + p * PS);
+    float v[PS];
+#pragma unroll
+    for (int k = 0; k < PS / 4; ++k) {
+      const float4 t = src[k];
+      v[4 * k] = t.x; v[4 * k + 1] = t.y; v[4 * k + 2] = t.z; v[4 * k + 3] = t.w;
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) S[k] += (double)v[k];
+  }
+  const Geom q = geometry(params, n, C, g, W, H);
+  const float *amp = params + 5 * (size_t)n;
+  const float *ph = params + (size_t)(5 + C) * n;
+  float *g_mean = grads;
+  float *g_ls = grads + 2 * (size_t)n;
+  float *g_rot = grads + 4 * (size_t)n;
+  float *g_amp = grads + 5 * (size_t)n;
+  float *g_ph = grads + (size_t)(5 + C) * n;
+  float *g_op = grads + (size_t)(5 + 2 * C) * n;
+  double dalpha = 0.0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    double sn, cs;
+    sincos((double)ph[(size_t)g * C + c], &sn, &cs);
+    const double cc = amp[(size_t)g * C + c];
+    const double dP = S[2 * c], dQ = S[2 * c + 1];
+    const double proj = cs * dP + sn * dQ;
+    g_amp[(size_t)g * C + c] = (float)(q.alpha * proj);
+    g_ph[(size_t)g * C + c] = (float)(q.alpha * cc * (-sn * dP + cs * dQ));
+    dalpha += cc * proj;
+  }
+  g_op[g] = (float)(dalpha * q.alpha * (1.0 - q.alpha));
+  const double W1 = S[2 * C], W2 = S[2 * C + 1], W3 = S[2 * C + 2], W4 = S[2 * C + 3],
+               W5 = S[2 * C + 4];
+  const double dmx = q.i00 * W1 + q.i01 * W2;
+  const double dmy = q.i01 * W1 + q.i11 * W2;
+  const double tx = tanh((double)params[2 * g]), ty = tanh((double)params[2 * g + 1]);
+  g_mean[2 * g] = (float)(dmx * 0.5 * W * (1.0 - tx * tx));
+  g_mean[2 * g + 1] = (float)(dmy * 0.5 * H * (1.0 - ty * ty));
+  // gradient w.r.t. the stored inverse entries
+  const double g00 = -0.5 * W3, g01 = -W4, g11 = -0.5 * W5;
+  double d00, d01, d11;  // dL/dSigma00, dL/dSigma01 (stored once), dL/dSigma11
+  if (q.det > 1e-10) {
+    // symmetric gradient matrix Gm = [[g00, g01/2], [g01/2, g11]]; M = Sigma^{-1}
+    const double h01 = 0.5 * g01;
+    // T = M Gm
+    const double t00 = q.i00 * g00 + q.i01 * h01, t01 = q.i00 * h01 + q.i01 * g11;
+    const double t10 = q.i01 * g00 + q.i11 * h01, t11 = q.i01 * h01 + q.i11 * g11;
+    // -(T M)
+    d00 = -(t00 * q.i00 + t01 * q.i01);
+    d11 = -(t10 * q.i01 + t11 * q.i11);
+    d01 = -2.0 * (t00 * q.i01 + t01 * q.i11);
+  } else {
+    d00 = g11 / q.dsafe;
+    d11 = g00 / q.dsafe;
+    d01 = -g01 / q.dsafe;
+  }
+  const double c = q.ct, s = q.st, sx = q.sx, sy = q.sy;
+  const double dsx = 2.0 * sx * (c * c * d00 + c * s * d01 + s * s * d11);
+  const double dsy = 2.0 * sy * (s * s * d00 - c * s * d01 + c * c * d11);
+  const double dth = 2.0 * (sy * sy - sx * sx) * c * s * d00 +
+                     (sx * sx - sy * sy) * (c * c - s * s) * d01 +
+                     2.0 * (sx * sx - sy * sy) * c * s * d11;
+  g_ls[2 * g] = (float)(dsx * (sx - 0.1));      // d s / d s~ = exp(s~)
+  g_ls[2 * g + 1] = (float)(dsy * (sy - 0.1));
+  g_rot[g] = (float)dth;
+}
+
+hipError_t launch_raster_adjoint(const Ctx &c, const float *params, int n,
+                                 const float2 *grad_field, float *grads, hipStream_t s) {
+  const float thr = support_threshold(c.cfg.support_sigma);
+  const uint32_t *vals = c.vals[c.sorted];
+  dim3 grid(c.num_tiles), block(256);
+  switch (c.C) {
+    case 1: hipLaunchKernelGGL(k_raster_adj<1>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
+    case 2: hipLaunchKernelGGL(k_raster_adj<2>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
+    case 3: hipLaunchKernelGGL(k_raster_adj<3>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
+    default: hipLaunchKernelGGL(k_raster_adj<4>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n <= 0) return e;
+  dim3 g2((n + 255) / 256);
+  switch (c.C) {
+    case 1: hipLaunchKernelGGL(k_preprocess_adj<1>, g2, block, 0, s, params, n, c.W, c.H, c.counts, c.offsets, c.pair_cap, c.partials, grads); break;
+    case 2: hipLaunchKernelGGL(k_preprocess_adj<2>, g2, block, 0, s, params, n, c.W, c.H, c.counts, c.offsets, c.pair_cap, c.partials, grads); break;
+    case 3: hipLaunchKernelGGL(k_preprocess_adj<3>, g2, block, 0, s, params, n, c.W, c.H, c.counts, c.offsets, c.pair_cap, c.partials, grads); break;
+    default: hipLaunchKernelGGL(k_preprocess_adj<4>, g2, block, 0, s, params, n, c.W, c.H, c.counts, c.offsets, c.pair_cap, c.partials, grads); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace cgh

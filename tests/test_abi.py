@@ -1,0 +1,102 @@
+"""The C-ABI library loads and exports every entry point include/cgh.h declares;
+host-only calls (configuration validation, workspace sizing) behave as the
+header documents.  No device work is issued here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2511_15022_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cgh.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cgh_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert L.cgh_abi_version() == 1
+
+
+def cfg(**kw):
+    c = binding.cgh_config()
+    c.height, c.width, c.channels = kw.get("H", 256), kw.get("W", 256), kw.get("C", 1)
+    c.pad_height, c.pad_width = kw.get("Hp", 0), kw.get("Wp", 0)
+    c.pitch_m = kw.get("pitch", 8e-6)
+    for i, lam in enumerate(kw.get("lambdas", [515e-9] * min(c.channels, 4))):
+        c.wavelength_m[i] = lam
+    zs = kw.get("zs", [2e-3])
+    c.num_planes = len(zs)
+    for i, z in enumerate(zs):
+        c.z_m[i] = z
+    c.support_sigma = kw.get("k", 3.0)
+    c.max_gaussians = kw.get("n", 4096)
+    c.max_pairs = kw.get("pairs", 0)
+    c.flags = kw.get("flags", 0)
+    return c
+
+
+def ws(c):
+    size = ctypes.c_size_t(0)
+    st = binding.lib().cgh_workspace_size(ctypes.byref(c), ctypes.byref(size))
+    return st, size.value
+
+
+def test_workspace_size_for_workloads():
+    st, small = ws(cfg())
+    assert st == 0 and small > 0
+    st, big = ws(cfg(H=1080, W=1920, C=3, lambdas=[639e-9, 515e-9, 473e-9], zs=[5e-3],
+                     n=414720))
+    assert st == 0
+    # the 1080p problem needs at least its [C][H][Wp] spectrum buffer and pair lists
+    assert big > 3 * 1080 * 3840 * 8
+    assert big < 2 * 1024 ** 3
+
+
+@pytest.mark.parametrize("bad, status", [
+    (dict(H=0), 1), (dict(W=9000), 1), (dict(C=5), 1), (dict(C=0), 1),
+    (dict(Hp=514), 1),            # 514 = 2 * 257 does not factor into 2, 3, 5
+    (dict(Hp=200), 1),            # smaller than H
+    (dict(pitch=0.0), 1), (dict(lambdas=[-1.0]), 1), (dict(n=-1), 1),
+    (dict(flags=1), 1), (dict(pairs=-5), 1),
+    (dict(zs=[1e-3, 2e-3]), 5),   # several planes: not in this build
+])
+def test_invalid_configs_are_rejected(bad, status):
+    st, _ = ws(cfg(**bad))
+    assert st == status
+    assert binding.lib().cgh_last_error()
+
+
+def test_null_arguments_are_rejected_without_device_work():
+    L = binding.lib()
+    assert L.cgh_workspace_size(None, None) == 1
+    assert L.cgh_rasterize(None, None, 0, None, None) == 1
+    assert L.cgh_backward(None, None, 0, None, None, None, None, None, None) == 1
+    assert L.cgh_step(None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None, 1, None) == 0
+    assert L.cgh_step(None, None, None, None, 10, 1, 1e-3, 0.9, 0.999, 1e-8, None, 1, None) == 1
+    c = cfg()
+    out = ctypes.c_void_p()
+    assert L.cgh_create(ctypes.byref(c), None, 0, None, ctypes.byref(out)) == 1
+
+
+def test_pack_unpack_layout_roundtrip():
+    import numpy as np
+    from paper_2511_15022_amd import synth
+    p = synth.params(0, 10, 16, 16, 3)
+    flat = binding.pack(p)
+    assert flat.numel() == binding.param_count(10, 3)
+    views = binding.unpack(flat, 10, 3)
+    for k in binding.PARAM_KEYS:
+        assert np.array_equal(views[k].numpy(), p[k])

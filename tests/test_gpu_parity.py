@@ -1,0 +1,317 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Bars: field and intensity relative L2 <= 1e-4; gradients
+relative L2 <= 1e-3 per parameter group; FD agreement <= 1e-3 of the group
+scale.  Pixels touched by a (Gaussian, pixel) pair whose Mahalanobis distance
+lies within 1e-4 k^2 of the support boundary are excluded from the field
+comparison (the in/out decision there depends on rounding; FP32 on the GPU,
+FP64 in the oracle); their count is asserted to be tiny."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2511_15022_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-4
+GRAD_TOL = 1e-3
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b, mask=None):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if mask is not None:
+        a = a[..., ~mask]
+        b = b[..., ~mask]
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def make(O, H, W, C, n, lambdas, zs, pitch=8e-6, Hp=None, Wp=None, k=3.0, pseed=0, tseed=1,
+         max_pairs=0, target_scale=1.0):
+    Hp = Hp or 2 * H
+    Wp = Wp or 2 * W
+    p = synth.params(pseed, n, H, W, C)
+    T = synth.target(tseed, C, H, W) * np.float32(target_scale)
+    opt = O.Optics(H, W, C, Hp, Wp, pitch, lambdas, zs, k=k)
+    ctx = binding.Context(H, W, C, pitch, lambdas, zs, pad=(Hp, Wp), support_sigma=k,
+                          max_gaussians=max(n, 1), max_pairs=max_pairs)
+    return p, T, opt, ctx
+
+
+def gpu_params(p):
+    return binding.pack(p, device="cuda")
+
+
+WORK = synth.WORKLOADS
+
+
+def tiny(O, **kw):
+    w = dict(WORK["tiny_256"])
+    w.update(kw)
+    return make(O, w["H"], w["W"], w["C"], w["n"], w["lambdas"], w["zs"], w["pitch"], w["Hp"],
+                w["Wp"], pseed=w["pseed"], tseed=w["tseed"], k=w.get("k", 3.0))
+
+
+# ---------------------------------------------------------------------------
+def test_transfer_table_matches_oracle(O):
+    for name in ("tiny_256", "bandlimit_stress"):
+        w = WORK[name]
+        say("transfer", name)
+        ctx = binding.Context(w["H"], w["W"], w["C"], w["pitch"], w["lambdas"], w["zs"],
+                              pad=(w["Hp"], w["Wp"]), max_gaussians=1)
+        h = ctx.get_transfer(0, 0).cpu().numpy()
+        full = O.transfer(w["Hp"], w["Wp"], w["pitch"], w["lambdas"][0], w["zs"][0])
+        quarter = full[: w["Hp"] // 2 + 1, : w["Wp"] // 2 + 1]
+        assert np.array_equal(np.abs(h) > 0, np.abs(quarter) > 0)
+        assert np.max(np.abs(h - quarter)) < 2e-7
+
+
+@pytest.mark.parametrize("case", [
+    dict(H=256, W=256, C=1, n=4096, lambdas=[515e-9], zs=[2e-3]),            # tiny workload
+    dict(H=37, W=53, C=2, n=300, lambdas=[639e-9, 473e-9], zs=[3e-3]),       # ragged tiles
+    dict(H=48, W=80, C=3, n=500, lambdas=[639e-9, 515e-9, 473e-9], zs=[5e-3],
+         Hp=90, Wp=160),                                                     # 3, 5 in the pads
+    dict(H=20, W=20, C=4, n=40, lambdas=[639e-9, 515e-9, 473e-9, 700e-9], zs=[1e-3]),
+])
+def test_field_parity(O, case):
+    say("field", case)
+    case = dict(case)
+    p, T, opt, ctx = make(O, **case)
+    n = case["n"]
+    f_gpu = ctx.rasterize(gpu_params(p), n).cpu().numpy()
+    f_ref = O.raster(p, opt)
+    mask, amb = O.ambiguous_mask(p, opt)
+    assert mask.sum() <= max(3, 1e-3 * mask.size)
+    err = rel_l2(f_gpu, f_ref, mask)
+    say("field rel-L2", err, "ambiguous pairs", amb)
+    assert err <= FIELD_TOL
+
+
+def test_propagation_parity(O):
+    """GPU propagation of the oracle's own field (rounded to complex64)."""
+    for w in (WORK["tiny_256"], dict(H=48, W=80, C=3, Hp=90, Wp=160, pitch=8e-6,
+                                     lambdas=[639e-9, 515e-9, 473e-9], zs=[5e-3])):
+        say("propagate", w["H"], w["W"], w["Hp"], w["Wp"])
+        C = w["C"]
+        rng = np.random.default_rng(3)
+        field = (rng.standard_normal((C, w["H"], w["W"])) + 1j * rng.standard_normal((C, w["H"], w["W"]))).astype(np.complex64)
+        opt = O.Optics(w["H"], w["W"], C, w["Hp"], w["Wp"], w["pitch"], w["lambdas"], w["zs"])
+        ctx = binding.Context(w["H"], w["W"], C, w["pitch"], w["lambdas"], w["zs"],
+                              pad=(w["Hp"], w["Wp"]), max_gaussians=1)
+        I, u = ctx.propagate(torch.from_numpy(field).cuda(), intensity=True, field_out=True)
+        u_ref = O.propagate(field.astype(np.complex128), opt)
+        assert rel_l2(u.cpu().numpy(), u_ref) <= FIELD_TOL
+        assert rel_l2(I.cpu().numpy(), np.abs(u_ref) ** 2) <= FIELD_TOL
+
+
+def test_propagation_adjoint_parity(O):
+    w = dict(H=48, W=80, C=2, Hp=90, Wp=160, pitch=8e-6, lambdas=[639e-9, 473e-9], zs=[4e-3])
+    say("propagate adjoint", w)
+    rng = np.random.default_rng(4)
+    C, H, W = w["C"], w["H"], w["W"]
+    field = (rng.standard_normal((C, H, W)) + 1j * rng.standard_normal((C, H, W))).astype(np.complex64)
+    gI = rng.standard_normal((1, C, H, W)).astype(np.float32)
+    opt = O.Optics(H, W, C, w["Hp"], w["Wp"], w["pitch"], w["lambdas"], w["zs"])
+    ctx = binding.Context(H, W, C, w["pitch"], w["lambdas"], w["zs"], pad=(w["Hp"], w["Wp"]),
+                          max_gaussians=1)
+    g = ctx.propagate_adjoint(torch.from_numpy(field).cuda(), torch.from_numpy(gI).cuda())
+    u = O.propagate(field.astype(np.complex128), opt)
+    g_ref = O.propagate_adjoint(2.0 * gI.astype(np.float64) * u, opt)
+    assert rel_l2(g.cpu().numpy(), g_ref) <= FIELD_TOL
+
+
+def group_errors(g_gpu, g_ref, n, C):
+    views = binding.unpack(torch.from_numpy(g_gpu), n, C)
+    out = {}
+    for k in binding.PARAM_KEYS:
+        out[k] = rel_l2(views[k].numpy(), g_ref[k])
+    return out
+
+
+@pytest.mark.parametrize("case", [
+    dict(H=256, W=256, C=1, n=4096, lambdas=[515e-9], zs=[2e-3]),
+    dict(H=37, W=53, C=2, n=300, lambdas=[639e-9, 473e-9], zs=[3e-3]),
+    dict(H=48, W=80, C=3, n=500, lambdas=[639e-9, 515e-9, 473e-9], zs=[5e-3], Hp=90, Wp=160),
+])
+def test_backward_parity(O, case):
+    say("backward", case)
+    case = dict(case)
+    p, T, opt, ctx = make(O, **case)
+    n, C = case["n"], case["C"]
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss, grad_field=gfield)
+    torch.cuda.synchronize()
+    ref = O.forward_backward(p, T, opt)
+    lg = loss.cpu().numpy()
+    say("loss gpu", lg[0], "oracle", ref["loss"])
+    assert abs(lg[0] - ref["loss"]) <= 1e-4 * ref["loss"]
+    assert abs(lg[1] - 10 * math.log10(1 / ref["loss"])) < 1e-3
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= FIELD_TOL * 10
+    errs = group_errors(grads.cpu().numpy(), ref["grads"], n, C)
+    say("grad rel-L2 per group", errs)
+    for k, e in errs.items():
+        assert e <= GRAD_TOL, (k, e)
+
+
+def test_gradients_against_finite_differences(O):
+    case = dict(H=37, W=53, C=2, n=60, lambdas=[639e-9, 473e-9], zs=[3e-3])
+    say("finite differences", case)
+    p, T, opt, ctx = make(O, **case, target_scale=0.3)
+    n, C = case["n"], case["C"]
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda()).cpu()
+    views = binding.unpack(grads, n, C)
+    rng = np.random.default_rng(9)
+    for key in binding.PARAM_KEYS:
+        g = views[key].numpy().reshape(-1).astype(np.float64)
+        scale = np.max(np.abs(g))
+        for idx in rng.choice(g.size, size=3, replace=False):
+            fd = O.fd_gradient(p, T, opt, key, int(idx))
+            assert abs(fd - g[idx]) <= GRAD_TOL * scale, (key, idx, fd, g[idx])
+
+
+def test_autograd_wrappers_match_fused_backward(O):
+    from paper_2511_15022_amd import autograd
+    p, T, opt, ctx = tiny(O)
+    n, C = 4096, 1
+    say("autograd wrappers")
+    P = gpu_params(p)
+    Tt = torch.from_numpy(T).cuda()
+    x = P.clone().requires_grad_(True)
+    field = autograd.rasterize(x, ctx, n)
+    I = autograd.propagate(field, ctx)
+    loss = torch.mean((I - Tt) ** 2)
+    loss.backward()
+    f2 = ctx.rasterize(P, n)
+    fused = ctx.backward(P, n, f2, Tt)
+    assert rel_l2(x.grad.cpu().numpy(), fused.cpu().numpy()) <= 1e-4
+
+
+def test_determinism_and_permutation(O):
+    p, T, opt, ctx = tiny(O)
+    n = 4096
+    say("determinism")
+    P = gpu_params(p)
+    f1 = ctx.rasterize(P, n).clone()
+    g1 = ctx.backward(P, n, f1, torch.from_numpy(T).cuda()).clone()
+    f2 = ctx.rasterize(P, n).clone()
+    g2 = ctx.backward(P, n, f2, torch.from_numpy(T).cuda()).clone()
+    assert torch.equal(f1, f2)
+    assert torch.equal(g1, g2)
+    perm = np.random.default_rng(1).permutation(n)
+    q = {k: v[perm] for k, v in p.items()}
+    f3 = ctx.rasterize(gpu_params(q), n)
+    assert rel_l2(f3.cpu().numpy(), f1.cpu().numpy()) < 1e-6
+
+
+def test_edge_cases(O):
+    say("edge: n = 0")
+    ctx = binding.Context(40, 56, 2, 8e-6, [639e-9, 473e-9], [2e-3], max_gaussians=8)
+    empty = torch.empty(0, dtype=torch.float32, device="cuda")
+    f = ctx.rasterize(empty, 0)
+    assert torch.count_nonzero(f).item() == 0
+    T = torch.rand(1, 2, 40, 56, device="cuda")
+    g = ctx.backward(empty, 0, f, T)
+    assert g.numel() == 0
+    say("edge: off-canvas, huge and tiny Gaussians")
+    p = synth.params(21, 8, 40, 56, 2)
+    p["log_scale"][0] = [4.0, 3.5]           # covers the whole canvas
+    p["log_scale"][1] = [-6.0, -6.0]         # sub-pixel (scale -> eps_s)
+    p["mean_pre"][2] = [9.0, 9.0]            # pinned to the far corner
+    p["mean_pre"][3] = [-9.0, 0.0]
+    opt = O.Optics(40, 56, 2, 80, 112, 8e-6, [639e-9, 473e-9], [2e-3])
+    fg = ctx.rasterize(gpu_params(p), 8).cpu().numpy()
+    fr = O.raster(p, opt)
+    mask, _ = O.ambiguous_mask(p, opt)
+    assert rel_l2(fg, fr, mask) <= FIELD_TOL
+    Tn = synth.target(3, 2, 40, 56)
+    gg = ctx.backward(gpu_params(p), 8, torch.from_numpy(fg).cuda(), torch.from_numpy(Tn).cuda())
+    ref = O.forward_backward(p, Tn, opt)
+    errs = group_errors(gg.cpu().numpy(), ref["grads"], 8, 2)
+    for k, e in errs.items():
+        assert e <= GRAD_TOL, (k, e)
+
+
+def test_unbounded_support_small(O):
+    """k <= 0: every pixel of every Gaussian (exponent clamped at -50)."""
+    say("unbounded support")
+    p = synth.params(31, 12, 24, 32, 1)
+    opt = O.Optics(24, 32, 1, 48, 64, 8e-6, [515e-9], [2e-3], k=0.0)
+    ctx = binding.Context(24, 32, 1, 8e-6, [515e-9], [2e-3], support_sigma=0.0,
+                          max_gaussians=12)
+    fg = ctx.rasterize(gpu_params(p), 12).cpu().numpy()
+    assert rel_l2(fg, O.raster(p, opt)) <= FIELD_TOL
+    T = synth.target(4, 1, 24, 32)
+    gg = ctx.backward(gpu_params(p), 12, torch.from_numpy(fg).cuda(), torch.from_numpy(T).cuda())
+    ref = O.forward_backward(p, T, opt)
+    for k, e in group_errors(gg.cpu().numpy(), ref["grads"], 12, 1).items():
+        assert e <= GRAD_TOL, (k, e)
+
+
+def test_capacity_overflow_is_reported(O):
+    say("capacity overflow")
+    p = synth.params(0, 500, 64, 64, 1)
+    ctx = binding.Context(64, 64, 1, 8e-6, [515e-9], [2e-3], max_gaussians=500, max_pairs=100)
+    ctx.rasterize(gpu_params(p), 500)
+    pairs, ok = ctx.read_status(raise_on_overflow=False)
+    assert not ok and pairs > 100
+    with pytest.raises(binding.CghError):
+        ctx.read_status()
+
+
+def test_adam_step_matches_oracle(O):
+    say("adam")
+    rng = np.random.default_rng(0)
+    n = 1001
+    p0 = rng.standard_normal(n).astype(np.float32)
+    m0 = np.zeros(n, np.float32)
+    v0 = np.zeros(n, np.float32)
+    P, M, V = (torch.from_numpy(a).cuda() for a in (p0, m0, v0))
+    pp, mm, vv = p0.astype(np.float64), m0.astype(np.float64), v0.astype(np.float64)
+    for t in range(1, 4):
+        g = rng.standard_normal(n).astype(np.float32)
+        binding.step(P, torch.from_numpy(g).cuda(), M, V, t, 1e-3)
+        pp, mm, vv = O.adam(pp, g, mm, vv, t, 1e-3)
+    assert np.max(np.abs(P.cpu().numpy() - pp)) < 1e-6
+    assert np.max(np.abs(M.cpu().numpy() - mm)) < 1e-6
+
+
+def test_rgb_1080p_full_size_parity(O):
+    """The 1080p RGB workload (414,720 Gaussians, 2160 x 3840 padding) in the
+    launch configuration the benchmark times: field at every pixel, loss,
+    dL/dU0 and parameter gradients against the oracle."""
+    w = WORK["rgb_1080p"]
+    say("rgb_1080p full size")
+    p, T, opt, ctx = make(O, w["H"], w["W"], w["C"], w["n"], w["lambdas"], w["zs"], w["pitch"],
+                          w["Hp"], w["Wp"], pseed=w["pseed"], tseed=w["tseed"])
+    n, C = w["n"], w["C"]
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    pairs, ok = ctx.read_status()
+    assert ok
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss, grad_field=gfield)
+    torch.cuda.synchronize()
+    say("gpu done, pairs", pairs, "; running oracle")
+    ref = O.forward_backward(p, T, opt)
+    mask, amb = O.ambiguous_mask(p, opt)
+    say("ambiguous pairs", amb)
+    assert rel_l2(field.cpu().numpy(), ref["field"], mask) <= FIELD_TOL
+    assert abs(loss[0].item() - ref["loss"]) <= 1e-4 * ref["loss"]
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= FIELD_TOL * 10
+    for k, e in group_errors(grads.cpu().numpy(), ref["grads"], n, C).items():
+        say("grad", k, e)
+        assert e <= GRAD_TOL, (k, e)
