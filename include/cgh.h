@@ -176,6 +176,26 @@ cgh_status cgh_get_transfer(cgh_ctx *ctx, int32_t channel, int32_t plane, cgh_c6
  * that call are then incomplete), CGH_OK otherwise. */
 cgh_status cgh_read_status(cgh_ctx *ctx, void *stream, int64_t *pairs);
 
+/* Kernel classes for cgh_profile_begin. */
+#define CGH_KERNEL_PREPROCESS 1         /* FP64 per-Gaussian preprocess                 */
+#define CGH_KERNEL_BINNING 2            /* scan, emit, radix sort, tile ranges          */
+#define CGH_KERNEL_RASTER 3             /* forward rasterizer                           */
+#define CGH_KERNEL_ROW_FFT 4            /* first forward and last adjoint row pass      */
+#define CGH_KERNEL_COL_PASS 5           /* column passes (H and conj H)                 */
+#define CGH_KERNEL_ROW_LOSS 6           /* middle row pass: |u|^2, loss, adjoint seed   */
+#define CGH_KERNEL_LOSS 7               /* loss reduction                               */
+#define CGH_KERNEL_RASTER_ADJOINT 8     /* rasterizer adjoint, tile stage               */
+#define CGH_KERNEL_PREPROCESS_ADJOINT 9 /* rasterizer adjoint, per-Gaussian FP64 stage  */
+
+/* Timing of one kernel class: after cgh_profile_begin, every launch of that
+ * class on this context is bracketed by two HIP events recorded on the stream
+ * of the call (at most 256 launches).  cgh_profile_end waits for `stream`
+ * and returns the summed event time in ms and the number of launches timed,
+ * then stops timing.  Other classes are unaffected; the events add no device
+ * work beyond the two timestamps. */
+cgh_status cgh_profile_begin(cgh_ctx *ctx, int32_t kernel_class);
+cgh_status cgh_profile_end(cgh_ctx *ctx, void *stream, double *total_ms, int32_t *launches);
+
 /* Message for the last non-OK status returned on this thread. */
 const char *cgh_last_error(void);
 

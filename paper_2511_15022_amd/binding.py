@@ -16,6 +16,9 @@ MAX_CHANNELS = 4
 MAX_PLANES = 8
 PARAM_KEYS = ("mean_pre", "log_scale", "rotation", "amplitude", "phase", "opacity_pre")
 
+KERNEL_CLASSES = {"preprocess": 1, "binning": 2, "raster": 3, "row_fft": 4, "col_pass": 5,
+                  "row_loss": 6, "loss": 7, "raster_adjoint": 8, "preprocess_adjoint": 9}
+
 STATUS = {0: "CGH_OK", 1: "CGH_ERR_INVALID_ARG", 2: "CGH_ERR_WORKSPACE", 3: "CGH_ERR_CAPACITY",
           4: "CGH_ERR_DEVICE", 5: "CGH_ERR_UNSUPPORTED", 6: "CGH_ERR_STATE"}
 
@@ -56,6 +59,9 @@ _SIGS = [
                                 ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP, ctypes.c_int32, _VP]),
     ("cgh_get_transfer", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP]),
     ("cgh_read_status", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_int64)]),
+    ("cgh_profile_begin", ctypes.c_int, [_VP, ctypes.c_int32]),
+    ("cgh_profile_end", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int32)]),
     ("cgh_last_error", ctypes.c_char_p, []),
     ("cgh_abi_version", ctypes.c_int32, []),
 ]
@@ -242,6 +248,16 @@ class Context:
         _check(lib().cgh_get_transfer(self.handle, int(channel), int(plane), _ptr(out),
                                       _stream(self.device)))
         return out
+
+    def profile_begin(self, kernel_class):
+        _check(lib().cgh_profile_begin(self.handle, int(KERNEL_CLASSES[kernel_class])))
+
+    def profile_end(self):
+        ms = ctypes.c_double(0.0)
+        cnt = ctypes.c_int32(0)
+        _check(lib().cgh_profile_end(self.handle, _stream(self.device), ctypes.byref(ms),
+                                     ctypes.byref(cnt)))
+        return ms.value, cnt.value
 
     def read_status(self, raise_on_overflow=True):
         pairs = ctypes.c_int64(0)

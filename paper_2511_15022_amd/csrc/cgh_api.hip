@@ -99,10 +99,31 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
   c->part_stride = partial_stride(c->C);
   c->last_n = -1;
   c->sorted = 0;
+  c->prof_class = 0;
+  c->prof_n = 0;
+  c->prof_ev = nullptr;
   if (!make_plan(Wp, &c->plan_x) || !make_plan(Hp, &c->plan_y))
     return fail(CGH_ERR_INVALID_ARG, "cannot plan FFTs of %d and %d", Wp, Hp);
   return CGH_OK;
 }
+
+// Brackets the launches of one kernel class with HIP events while that class
+// is being profiled (cgh_profile_begin); a no-op otherwise.
+struct ProfScope {
+  cgh::Ctx &c;
+  hipStream_t s;
+  bool on;
+  ProfScope(cgh::Ctx &c_, int cls, hipStream_t s_) : c(c_), s(s_) {
+    on = c.prof_ev && c.prof_class == cls && c.prof_n < cgh::kMaxProf;
+    if (on) hipEventRecord(c.prof_ev[2 * c.prof_n], s);
+  }
+  ~ProfScope() {
+    if (on) {
+      hipEventRecord(c.prof_ev[2 * c.prof_n + 1], s);
+      ++c.prof_n;
+    }
+  }
+};
 
 }  // namespace
 
@@ -194,6 +215,10 @@ cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_b
 }
 
 cgh_status cgh_destroy(cgh_ctx *ctx) {
+  if (ctx && ctx->c.prof_ev) {
+    for (int i = 0; i < 2 * cgh::kMaxProf; ++i) hipEventDestroy(ctx->c.prof_ev[i]);
+    delete[] ctx->c.prof_ev;
+  }
   delete ctx;
   return CGH_OK;
 }
@@ -214,9 +239,18 @@ cgh_status cgh_rasterize(cgh_ctx *ctx, const float *params, int32_t n, cgh_c64 *
   if ((n > 0 && !params) || !field) return fail(CGH_ERR_INVALID_ARG, "params/field is NULL");
   if (!aligned16(field)) return fail(CGH_ERR_INVALID_ARG, "field must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  CGH_CHECK_LAUNCH(cgh::launch_preprocess(c, params, n, s), "preprocess");
-  CGH_CHECK_LAUNCH(cgh::launch_binning(c, n, s), "binning");
-  CGH_CHECK_LAUNCH(cgh::launch_raster_fwd(c, reinterpret_cast<float2 *>(field), s), "raster");
+  {
+    ProfScope p(c, CGH_KERNEL_PREPROCESS, s);
+    CGH_CHECK_LAUNCH(cgh::launch_preprocess(c, params, n, s), "preprocess");
+  }
+  {
+    ProfScope p(c, CGH_KERNEL_BINNING, s);
+    CGH_CHECK_LAUNCH(cgh::launch_binning(c, n, s), "binning");
+  }
+  {
+    ProfScope p(c, CGH_KERNEL_RASTER, s);
+    CGH_CHECK_LAUNCH(cgh::launch_raster_fwd(c, reinterpret_cast<float2 *>(field), s), "raster");
+  }
   c.last_n = n;
   return CGH_OK;
 }
@@ -224,18 +258,45 @@ cgh_status cgh_rasterize(cgh_ctx *ctx, const float *params, int32_t n, cgh_c64 *
 // F1 + F2: field -> column-pass output in c.spec
 static cgh_status forward_spectrum(Ctx &c, const cgh_c64 *field, hipStream_t s) {
   const float2 *f = reinterpret_cast<const float2 *>(field);
-  CGH_CHECK_LAUNCH(cgh::launch_row_fft(c, f, c.W, c.W, c.spec, c.Wp, c.Wp, c.C * c.H, 0, s),
-                   "row fft");
-  CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, c.spec, 0, s), "column pass");
+  {
+    ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
+    CGH_CHECK_LAUNCH(cgh::launch_row_fft(c, f, c.W, c.W, c.spec, c.Wp, c.Wp, c.C * c.H, 0, s),
+                     "row fft");
+  }
+  {
+    ProfScope p(c, CGH_KERNEL_COL_PASS, s);
+    CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, c.spec, 0, s), "column pass");
+  }
+  return CGH_OK;
+}
+
+// rasterizer adjoint: tile stage, then the FP64 per-Gaussian stage
+static cgh_status raster_adjoint(Ctx &c, const float *params, int n, const float2 *gf,
+                                 float *grads, hipStream_t s) {
+  {
+    ProfScope p(c, CGH_KERNEL_RASTER_ADJOINT, s);
+    CGH_CHECK_LAUNCH(cgh::launch_raster_adjoint(c, gf, s), "raster adjoint");
+  }
+  {
+    ProfScope p(c, CGH_KERNEL_PREPROCESS_ADJOINT, s);
+    CGH_CHECK_LAUNCH(cgh::launch_preprocess_adjoint(c, params, n, grads, s),
+                     "preprocess adjoint");
+  }
   return CGH_OK;
 }
 
 // B1 + B2: adjoint seed in c.spec -> dL/dU0
 static cgh_status adjoint_spectrum(Ctx &c, float2 *grad_field, hipStream_t s) {
-  CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, c.spec, 1, s), "adjoint column pass");
-  CGH_CHECK_LAUNCH(cgh::launch_row_fft(c, c.spec, c.Wp, c.Wp, grad_field, c.W, c.W, c.C * c.H,
-                                       1, s),
-                   "adjoint row fft");
+  {
+    ProfScope p(c, CGH_KERNEL_COL_PASS, s);
+    CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, c.spec, 1, s), "adjoint column pass");
+  }
+  {
+    ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
+    CGH_CHECK_LAUNCH(cgh::launch_row_fft(c, c.spec, c.Wp, c.Wp, grad_field, c.W, c.W,
+                                         c.C * c.H, 1, s),
+                     "adjoint row fft");
+  }
   return CGH_OK;
 }
 
@@ -249,6 +310,7 @@ cgh_status cgh_propagate(cgh_ctx *ctx, const cgh_c64 *field, float *intensity,
   hipStream_t s = (hipStream_t)stream;
   cgh_status st = forward_spectrum(c, field, s);
   if (st != CGH_OK) return st;
+  ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
   CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, nullptr, nullptr, intensity,
                                         reinterpret_cast<float2 *>(field_out), 0, s),
                    "intensity row pass");
@@ -272,13 +334,18 @@ cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_
   float2 *gf = grad_field ? reinterpret_cast<float2 *>(grad_field) : c.gfield_tmp;
   st = forward_spectrum(c, field, s);
   if (st != CGH_OK) return st;
-  CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, target, nullptr, nullptr, nullptr, 1, s),
-                   "loss row pass");
-  if (loss) CGH_CHECK_LAUNCH(cgh::launch_loss_finalize(c, loss, s), "loss");
+  {
+    ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
+    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, target, nullptr, nullptr, nullptr, 1, s),
+                     "loss row pass");
+  }
+  if (loss) {
+    ProfScope p(c, CGH_KERNEL_LOSS, s);
+    CGH_CHECK_LAUNCH(cgh::launch_loss_finalize(c, loss, s), "loss");
+  }
   st = adjoint_spectrum(c, gf, s);
   if (st != CGH_OK) return st;
-  CGH_CHECK_LAUNCH(cgh::launch_raster_adjoint(c, params, n, gf, grads, s), "raster adjoint");
-  return CGH_OK;
+  return raster_adjoint(c, params, n, gf, grads, s);
 }
 
 cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
@@ -293,9 +360,12 @@ cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
   hipStream_t s = (hipStream_t)stream;
   cgh_status st = forward_spectrum(c, field, s);
   if (st != CGH_OK) return st;
-  CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, nullptr, grad_intensity, nullptr, nullptr, 1,
-                                        s),
-                   "adjoint seed row pass");
+  {
+    ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
+    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, nullptr, grad_intensity, nullptr, nullptr,
+                                          1, s),
+                     "adjoint seed row pass");
+  }
   return adjoint_spectrum(c, reinterpret_cast<float2 *>(grad_field), s);
 }
 
@@ -310,12 +380,8 @@ cgh_status cgh_rasterize_adjoint(cgh_ctx *ctx, const float *params, int32_t n,
   if (!grad_field || (n > 0 && (!params || !grads)))
     return fail(CGH_ERR_INVALID_ARG, "grad_field/params/grads is NULL");
   if (!aligned16(grad_field)) return fail(CGH_ERR_INVALID_ARG, "misaligned grad_field");
-  hipStream_t s = (hipStream_t)stream;
-  CGH_CHECK_LAUNCH(cgh::launch_raster_adjoint(c, params, n,
-                                              reinterpret_cast<const float2 *>(grad_field),
-                                              grads, s),
-                   "raster adjoint");
-  return CGH_OK;
+  return raster_adjoint(c, params, n, reinterpret_cast<const float2 *>(grad_field), grads,
+                        (hipStream_t)stream);
 }
 
 cgh_status cgh_step(float *params, const float *grads, float *m, float *v, int64_t count,
@@ -357,6 +423,48 @@ cgh_status cgh_get_transfer(cgh_ctx *ctx, int32_t channel, int32_t plane, cgh_c6
                                 elems * sizeof(float2), hipMemcpyDeviceToDevice,
                                 (hipStream_t)stream);
   if (e != hipSuccess) return device_fail(e, "cgh_get_transfer");
+  return CGH_OK;
+}
+
+cgh_status cgh_profile_begin(cgh_ctx *ctx, int32_t kernel_class) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  if (kernel_class < CGH_KERNEL_PREPROCESS || kernel_class > CGH_KERNEL_PREPROCESS_ADJOINT)
+    return fail(CGH_ERR_INVALID_ARG, "unknown kernel class %d", kernel_class);
+  Ctx &c = ctx->c;
+  if (!c.prof_ev) {
+    hipEvent_t *ev = new (std::nothrow) hipEvent_t[2 * cgh::kMaxProf];
+    if (!ev) return fail(CGH_ERR_INVALID_ARG, "host allocation failed");
+    for (int i = 0; i < 2 * cgh::kMaxProf; ++i) {
+      hipError_t e = hipEventCreate(&ev[i]);
+      if (e != hipSuccess) {
+        for (int j = 0; j < i; ++j) hipEventDestroy(ev[j]);
+        delete[] ev;
+        return device_fail(e, "cgh_profile_begin");
+      }
+    }
+    c.prof_ev = ev;
+  }
+  c.prof_class = kernel_class;
+  c.prof_n = 0;
+  return CGH_OK;
+}
+
+cgh_status cgh_profile_end(cgh_ctx *ctx, void *stream, double *total_ms, int32_t *launches) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  Ctx &c = ctx->c;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "cgh_profile_end");
+  double sum = 0.0;
+  for (int i = 0; i < c.prof_n; ++i) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, c.prof_ev[2 * i], c.prof_ev[2 * i + 1]);
+    if (e != hipSuccess) return device_fail(e, "cgh_profile_end");
+    sum += ms;
+  }
+  if (total_ms) *total_ms = sum;
+  if (launches) *launches = c.prof_n;
+  c.prof_class = 0;
+  c.prof_n = 0;
   return CGH_OK;
 }
 

@@ -77,7 +77,12 @@ struct Ctx {
   double *loss_part;                // [L*C*H]
   uint32_t *status;                 // [0] overflow flag, [1] pair total
   int sorted;                       // which ping-pong buffer holds the sorted pairs
+  // kernel-class timing (cgh_profile_begin / _end)
+  int prof_class;                   // 0: off
+  int prof_n;                       // launches recorded
+  hipEvent_t *prof_ev;              // 2 * kMaxProf events, created on first use
 };
+constexpr int kMaxProf = 256;
 
 size_t carve(Ctx *c, char *base);   // returns bytes used (base may be null)
 
@@ -94,10 +99,11 @@ hipError_t launch_row_loss(const Ctx &c, float2 *data, const float *target,
 hipError_t launch_loss_finalize(const Ctx &c, double *loss, hipStream_t s);
 
 hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s);
-hipError_t launch_binning(Ctx &c, int n, hipStream_t s);
+hipError_t launch_binning(Ctx &c, int n, hipStream_t s);  // sets c.sorted
 hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s);
-hipError_t launch_raster_adjoint(const Ctx &c, const float *params, int n,
-                                 const float2 *grad_field, float *grads, hipStream_t s);
+hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStream_t s);
+hipError_t launch_preprocess_adjoint(const Ctx &c, const float *params, int n, float *grads,
+                                     hipStream_t s);
 
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr,
                        float step_size_scale, float beta1, float beta2, float eps,

@@ -664,8 +664,7 @@ __global__ __launch_bounds__(256) void k_preprocess_adj(
   g_rot[g] = (float)dth;
 }
 
-hipError_t launch_raster_adjoint(const Ctx &c, const float *params, int n,
-                                 const float2 *grad_field, float *grads, hipStream_t s) {
+hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStream_t s) {
   const float thr = support_threshold(c.cfg.support_sigma);
   const uint32_t *vals = c.vals[c.sorted];
   dim3 grid(c.num_tiles), block(256);
@@ -675,9 +674,13 @@ hipError_t launch_raster_adjoint(const Ctx &c, const float *params, int n,
     case 3: hipLaunchKernelGGL(k_raster_adj<3>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
     default: hipLaunchKernelGGL(k_raster_adj<4>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || n <= 0) return e;
-  dim3 g2((n + 255) / 256);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_adjoint(const Ctx &c, const float *params, int n, float *grads,
+                                     hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 g2((n + 255) / 256), block(256);
   switch (c.C) {
     case 1: hipLaunchKernelGGL(k_preprocess_adj<1>, g2, block, 0, s, params, n, c.W, c.H, c.counts, c.offsets, c.pair_cap, c.partials, grads); break;
     case 2: hipLaunchKernelGGL(k_preprocess_adj<2>, g2, block, 0, s, params, n, c.W, c.H, c.counts, c.offsets, c.pair_cap, c.partials, grads); break;

@@ -68,7 +68,11 @@ def target(seed, C, H, W, L=1):
                 cx, cy = rng.uniform(0, W), rng.uniform(0, H)
                 r = rng.uniform(0.02, 0.15) * min(H, W)
                 val = rng.uniform(0.0, 1.0)
-                shapes[(xx - cx) ** 2 + (yy - cy) ** 2 <= r * r] = val
+                # paint inside the disk's bounding box only (same pixels as a full test)
+                y0, y1 = max(0, int(math.floor(cy - r))), min(H, int(math.ceil(cy + r)) + 1)
+                x0, x1 = max(0, int(math.floor(cx - r))), min(W, int(math.ceil(cx + r)) + 1)
+                sub = (xx[y0:y1, x0:x1] - cx) ** 2 + (yy[y0:y1, x0:x1] - cy) ** 2 <= r * r
+                shapes[y0:y1, x0:x1][sub] = val
             for _ in range(4):
                 ang = rng.uniform(0.0, 2.0 * math.pi)
                 ox, oy = rng.uniform(0, W), rng.uniform(0, H)

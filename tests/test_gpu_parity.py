@@ -2,7 +2,7 @@
 same seeded inputs.  Bars: field and intensity relative L2 <= 1e-4; gradients
 relative L2 <= 1e-3 per parameter group; FD agreement <= 1e-3 of the group
 scale.  Pixels touched by a (Gaussian, pixel) pair whose Mahalanobis distance
-lies within 1e-4 k^2 of the support boundary are excluded from the field
+lies within 1e-5 k^2 of the support boundary are excluded from the field
 comparison (the in/out decision there depends on rounding; FP32 on the GPU,
 FP64 in the oracle); their count is asserted to be tiny."""
 import math
@@ -18,6 +18,9 @@ pytestmark = pytest.mark.gpu
 
 FIELD_TOL = 1e-4
 GRAD_TOL = 1e-3
+# half-width of the ambiguous band around q = k^2, relative to k^2: about 50x
+# the FP32 error of the kernel's q (a few ulp of terms of size ~10)
+AMBIGUOUS_BAND = 1e-5
 
 
 def say(*a):
@@ -76,7 +79,7 @@ def test_transfer_table_matches_oracle(O):
 
 @pytest.mark.parametrize("case", [
     dict(H=256, W=256, C=1, n=4096, lambdas=[515e-9], zs=[2e-3]),            # tiny workload
-    dict(H=37, W=53, C=2, n=300, lambdas=[639e-9, 473e-9], zs=[3e-3]),       # ragged tiles
+    dict(H=37, W=53, C=2, n=300, lambdas=[639e-9, 473e-9], zs=[3e-3], Hp=75, Wp=108),  # ragged
     dict(H=48, W=80, C=3, n=500, lambdas=[639e-9, 515e-9, 473e-9], zs=[5e-3],
          Hp=90, Wp=160),                                                     # 3, 5 in the pads
     dict(H=20, W=20, C=4, n=40, lambdas=[639e-9, 515e-9, 473e-9, 700e-9], zs=[1e-3]),
@@ -88,10 +91,10 @@ def test_field_parity(O, case):
     n = case["n"]
     f_gpu = ctx.rasterize(gpu_params(p), n).cpu().numpy()
     f_ref = O.raster(p, opt)
-    mask, amb = O.ambiguous_mask(p, opt)
-    assert mask.sum() <= max(3, 1e-3 * mask.size)
+    mask, amb = O.ambiguous_mask(p, opt, AMBIGUOUS_BAND)
     err = rel_l2(f_gpu, f_ref, mask)
-    say("field rel-L2", err, "ambiguous pairs", amb)
+    say("field rel-L2", err, "ambiguous pairs", amb, "masked pixels", int(mask.sum()))
+    assert mask.sum() <= max(3, 1e-3 * mask.size)
     assert err <= FIELD_TOL
 
 
@@ -138,7 +141,7 @@ def group_errors(g_gpu, g_ref, n, C):
 
 @pytest.mark.parametrize("case", [
     dict(H=256, W=256, C=1, n=4096, lambdas=[515e-9], zs=[2e-3]),
-    dict(H=37, W=53, C=2, n=300, lambdas=[639e-9, 473e-9], zs=[3e-3]),
+    dict(H=37, W=53, C=2, n=300, lambdas=[639e-9, 473e-9], zs=[3e-3], Hp=75, Wp=108),
     dict(H=48, W=80, C=3, n=500, lambdas=[639e-9, 515e-9, 473e-9], zs=[5e-3], Hp=90, Wp=160),
 ])
 def test_backward_parity(O, case):
@@ -157,7 +160,7 @@ def test_backward_parity(O, case):
     say("loss gpu", lg[0], "oracle", ref["loss"])
     assert abs(lg[0] - ref["loss"]) <= 1e-4 * ref["loss"]
     assert abs(lg[1] - 10 * math.log10(1 / ref["loss"])) < 1e-3
-    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= FIELD_TOL * 10
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
     errs = group_errors(grads.cpu().numpy(), ref["grads"], n, C)
     say("grad rel-L2 per group", errs)
     for k, e in errs.items():
@@ -165,7 +168,7 @@ def test_backward_parity(O, case):
 
 
 def test_gradients_against_finite_differences(O):
-    case = dict(H=37, W=53, C=2, n=60, lambdas=[639e-9, 473e-9], zs=[3e-3])
+    case = dict(H=37, W=53, C=2, n=60, lambdas=[639e-9, 473e-9], zs=[3e-3], Hp=75, Wp=108)
     say("finite differences", case)
     p, T, opt, ctx = make(O, **case, target_scale=0.3)
     n, C = case["n"], case["C"]
@@ -218,7 +221,8 @@ def test_determinism_and_permutation(O):
 
 def test_edge_cases(O):
     say("edge: n = 0")
-    ctx = binding.Context(40, 56, 2, 8e-6, [639e-9, 473e-9], [2e-3], max_gaussians=8)
+    ctx = binding.Context(40, 56, 2, 8e-6, [639e-9, 473e-9], [2e-3], pad=(80, 120),
+                          max_gaussians=8)
     empty = torch.empty(0, dtype=torch.float32, device="cuda")
     f = ctx.rasterize(empty, 0)
     assert torch.count_nonzero(f).item() == 0
@@ -231,10 +235,10 @@ def test_edge_cases(O):
     p["log_scale"][1] = [-6.0, -6.0]         # sub-pixel (scale -> eps_s)
     p["mean_pre"][2] = [9.0, 9.0]            # pinned to the far corner
     p["mean_pre"][3] = [-9.0, 0.0]
-    opt = O.Optics(40, 56, 2, 80, 112, 8e-6, [639e-9, 473e-9], [2e-3])
+    opt = O.Optics(40, 56, 2, 80, 120, 8e-6, [639e-9, 473e-9], [2e-3])
     fg = ctx.rasterize(gpu_params(p), 8).cpu().numpy()
     fr = O.raster(p, opt)
-    mask, _ = O.ambiguous_mask(p, opt)
+    mask, _ = O.ambiguous_mask(p, opt, AMBIGUOUS_BAND)
     assert rel_l2(fg, fr, mask) <= FIELD_TOL
     Tn = synth.target(3, 2, 40, 56)
     gg = ctx.backward(gpu_params(p), 8, torch.from_numpy(fg).cuda(), torch.from_numpy(Tn).cuda())
@@ -307,11 +311,11 @@ def test_rgb_1080p_full_size_parity(O):
     torch.cuda.synchronize()
     say("gpu done, pairs", pairs, "; running oracle")
     ref = O.forward_backward(p, T, opt)
-    mask, amb = O.ambiguous_mask(p, opt)
+    mask, amb = O.ambiguous_mask(p, opt, AMBIGUOUS_BAND)
     say("ambiguous pairs", amb)
     assert rel_l2(field.cpu().numpy(), ref["field"], mask) <= FIELD_TOL
     assert abs(loss[0].item() - ref["loss"]) <= 1e-4 * ref["loss"]
-    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= FIELD_TOL * 10
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
     for k, e in group_errors(grads.cpu().numpy(), ref["grads"], n, C).items():
         say("grad", k, e)
         assert e <= GRAD_TOL, (k, e)
