@@ -59,6 +59,10 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
     return fail(CGH_ERR_INVALID_ARG,
                 "padded grid %d x %d: each side must factor into 2, 3, 5 and be <= %d", Hp, Wp,
                 kMaxFft);
+  if (!col_supported(Hp))
+    return fail(CGH_ERR_UNSUPPORTED,
+                "padded height %d: this build supports even values up to %d and odd values "
+                "up to %d", Hp, 2 * kColHalfMax, kColFullMax);
   if (!(f.pitch_m > 0.0) || !std::isfinite(f.pitch_m))
     return fail(CGH_ERR_INVALID_ARG, "pitch must be positive and finite");
   for (int ch = 0; ch < f.channels; ++ch)
@@ -85,6 +89,7 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
   c->Wp = Wp;
   c->Hq = Hp / 2 + 1;
   c->Wq = Wp / 2 + 1;
+  c->Wt = (Wp + 7) / 8;
   c->tiles_x = (f.width + kTile - 1) / kTile;
   c->tiles_y = (f.height + kTile - 1) / kTile;
   c->num_tiles = c->tiles_x * c->tiles_y;
@@ -102,7 +107,8 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
   c->prof_class = 0;
   c->prof_n = 0;
   c->prof_ev = nullptr;
-  if (!make_plan(Wp, &c->plan_x) || !make_plan(Hp, &c->plan_y))
+  if (!make_plan(Wp, &c->plan_x) || !make_plan(Hp, &c->plan_y) ||
+      !make_plan(Hp % 2 == 0 ? Hp / 2 : Hp, &c->plan_m))
     return fail(CGH_ERR_INVALID_ARG, "cannot plan FFTs of %d and %d", Wp, Hp);
   return CGH_OK;
 }
@@ -140,10 +146,13 @@ size_t carve(Ctx *c, char *base) {
   const size_t N = (size_t)c->cfg.max_gaussians;
   const size_t cap = (size_t)c->pair_cap;
   const size_t HW = (size_t)c->H * c->W;
-  c->tw_x = (float2 *)take(sizeof(float2) * c->Wp);
-  c->tw_y = (float2 *)take(sizeof(float2) * c->Hp);
+  c->tw_x = (float2 *)take(sizeof(float2) * kTwTable);
+  c->tw_y = (float2 *)take(sizeof(float2) * kTwTable);
+  c->tw_m = (float2 *)take(sizeof(float2) * kTwTable);
+  c->twf_x = (float2 *)take(sizeof(float2) * c->Wp);
+  c->twf_m = (float2 *)take(sizeof(float2) * c->plan_m.n);
   c->htab = (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq);
-  c->spec = (float2 *)take(sizeof(float2) * c->L * c->C * (size_t)c->H * c->Wp);
+  c->spec = (float2 *)take(sizeof(float2) * c->C * (size_t)c->Wt * c->H * 8);
   c->field_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
   c->gfield_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
   c->rec = (float *)take(sizeof(float) * c->rec_stride * (N ? N : 1));
@@ -159,7 +168,7 @@ size_t carve(Ctx *c, char *base) {
   const size_t scan_len = std::max(N + 1, (size_t)256 * c->sort_blocks);
   c->scan_tmp = (uint32_t *)take(sizeof(uint32_t) * (scan_len / kScanItems + 2));
   c->partials = (float *)take(sizeof(float) * c->part_stride * cap);
-  c->loss_part = (double *)take(sizeof(double) * c->L * c->C * (size_t)c->H);
+  c->loss_part = (double *)take(sizeof(double) * c->C * (size_t)((c->H + 1) / 2));
   c->status = (uint32_t *)take(sizeof(uint32_t) * 4);
   return (off + 255) & ~(size_t)255;
 }
@@ -204,6 +213,9 @@ cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_b
   hipStream_t s = (hipStream_t)stream;
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_x, c.Wp, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_y, c.Hp, s), "twiddles");
+  CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_m, c.plan_m.n, s), "twiddles");
+  CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_x, c.Wp, s), "twiddles");
+  CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_m, c.plan_m.n, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, s), "transfer function");
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return device_fail(e, "cgh_create");
@@ -260,12 +272,11 @@ static cgh_status forward_spectrum(Ctx &c, const cgh_c64 *field, hipStream_t s) 
   const float2 *f = reinterpret_cast<const float2 *>(field);
   {
     ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
-    CGH_CHECK_LAUNCH(cgh::launch_row_fft(c, f, c.W, c.W, c.spec, c.Wp, c.Wp, c.C * c.H, 0, s),
-                     "row fft");
+    CGH_CHECK_LAUNCH(cgh::launch_row_fwd(c, f, s), "row fft");
   }
   {
     ProfScope p(c, CGH_KERNEL_COL_PASS, s);
-    CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, c.spec, 0, s), "column pass");
+    CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, 0, s), "column pass");
   }
   return CGH_OK;
 }
@@ -289,13 +300,11 @@ static cgh_status raster_adjoint(Ctx &c, const float *params, int n, const float
 static cgh_status adjoint_spectrum(Ctx &c, float2 *grad_field, hipStream_t s) {
   {
     ProfScope p(c, CGH_KERNEL_COL_PASS, s);
-    CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, c.spec, 1, s), "adjoint column pass");
+    CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, 1, s), "adjoint column pass");
   }
   {
     ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
-    CGH_CHECK_LAUNCH(cgh::launch_row_fft(c, c.spec, c.Wp, c.Wp, grad_field, c.W, c.W,
-                                         c.C * c.H, 1, s),
-                     "adjoint row fft");
+    CGH_CHECK_LAUNCH(cgh::launch_row_inv(c, grad_field, s), "adjoint row fft");
   }
   return CGH_OK;
 }
@@ -311,7 +320,7 @@ cgh_status cgh_propagate(cgh_ctx *ctx, const cgh_c64 *field, float *intensity,
   cgh_status st = forward_spectrum(c, field, s);
   if (st != CGH_OK) return st;
   ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
-  CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, nullptr, nullptr, intensity,
+  CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, nullptr, nullptr, intensity,
                                         reinterpret_cast<float2 *>(field_out), 0, s),
                    "intensity row pass");
   return CGH_OK;
@@ -336,7 +345,7 @@ cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_
   if (st != CGH_OK) return st;
   {
     ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
-    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, target, nullptr, nullptr, nullptr, 1, s),
+    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, target, nullptr, nullptr, nullptr, 1, s),
                      "loss row pass");
   }
   if (loss) {
@@ -362,7 +371,7 @@ cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
   if (st != CGH_OK) return st;
   {
     ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
-    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, c.spec, nullptr, grad_intensity, nullptr, nullptr,
+    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, nullptr, grad_intensity, nullptr, nullptr,
                                           1, s),
                      "adjoint seed row pass");
   }

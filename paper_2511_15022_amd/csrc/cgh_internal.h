@@ -33,6 +33,15 @@ struct FftPlan {
 bool make_plan(int n, FftPlan *plan);
 bool smooth235(int n);
 
+// Column-pass limits: even Hp runs as two Hp/2-point chains (Hp/2 <= 1152 in a
+// 77 KB LDS block, <= 2400 in 150 KB); odd Hp runs one Hp-point transform
+// (<= 2400).  1024-thread workgroups.
+constexpr int kColHalfSmall = 1152;
+constexpr int kColHalfMax = 2400;
+constexpr int kColFullMax = 2400;
+bool col_supported(int Hp);
+constexpr int kTwTable = 256;      // float2 slots reserved per two-level twiddle table
+
 // Record of one Gaussian for the rasterizer (FP32, written by the FP64
 // preprocess).  Offsets within a record of rec_stride floats:
 enum RecField {
@@ -53,16 +62,18 @@ inline int partial_stride(int C) { return ((2 * C + 5) + 3) & ~3; }
 struct Ctx {
   cgh_config cfg;
   int H, W, C, L, Hp, Wp, Hq, Wq;   // Hq, Wq: quarter-table extents Hp/2+1, Wp/2+1
+  int Wt;                           // column tiles of 8 in the propagation buffer
   int tiles_x, tiles_y, num_tiles, sort_passes;
   int64_t pair_cap;
   int rec_stride, part_stride;
   int sort_blocks;                  // radix-sort grid (covers pair_cap)
-  FftPlan plan_x, plan_y;
+  FftPlan plan_x, plan_y, plan_m;   // lengths Wp, Hp, Hp/2 (plan_m unused for odd Hp)
   int last_n;                       // n of the last rasterize (-1: none)
   // workspace carve (device pointers)
-  float2 *tw_x, *tw_y;              // twiddles exp(-2 pi i k / n), n = Wp, Hp
+  float2 *tw_x, *tw_y, *tw_m;       // two-level twiddle tables for Wp, Hp, Hp/2
+  float2 *twf_x, *twf_m;            // full twiddle tables for Wp and Hp/2 (Hp if odd)
   float2 *htab;                     // [C][L][Hq][Wq]
-  float2 *spec;                     // [L][C][H][Wp] row/column-pass buffer
+  float2 *spec;                     // [C][Wt][H][8] column-tiled propagation buffer
   float2 *field_tmp;                // [C][H][W]
   float2 *gfield_tmp;               // [C][H][W]
   float *rec;                       // [max_gaussians][rec_stride]
@@ -74,7 +85,7 @@ struct Ctx {
   uint32_t *hist;                   // [256 * sort_blocks]
   uint32_t *scan_tmp;               // partial sums for scans
   float *partials;                  // [pair_cap][part_stride] raster-adjoint partials
-  double *loss_part;                // [L*C*H]
+  double *loss_part;                // [C * ceil(H/2)] one per row-pass workgroup
   uint32_t *status;                 // [0] overflow flag, [1] pair total
   int sorted;                       // which ping-pong buffer holds the sorted pairs
   // kernel-class timing (cgh_profile_begin / _end)
@@ -88,14 +99,14 @@ size_t carve(Ctx *c, char *base);   // returns bytes used (base may be null)
 
 // ---- launchers (all enqueue on `s`; return hipSuccess or the launch error) ----
 hipError_t launch_build_twiddles(float2 *tw, int n, hipStream_t s);
+hipError_t launch_build_twiddles_full(float2 *tw, int n, hipStream_t s);
+int row_group_rows(const Ctx &c);   // rows per row-pass workgroup
 hipError_t launch_build_transfer(const Ctx &c, hipStream_t s);
-hipError_t launch_row_fft(const Ctx &c, const float2 *in, int in_len, long in_stride,
-                          float2 *out, int out_len, long out_stride, int rows, int inverse,
-                          hipStream_t s);
-hipError_t launch_col_pass(const Ctx &c, float2 *data, int conj_h, hipStream_t s);
-hipError_t launch_row_loss(const Ctx &c, float2 *data, const float *target,
-                           const float *grad_intensity, float *intensity, float2 *u_out,
-                           int make_grad, hipStream_t s);
+hipError_t launch_row_fwd(const Ctx &c, const float2 *field, hipStream_t s);
+hipError_t launch_row_inv(const Ctx &c, float2 *out, hipStream_t s);
+hipError_t launch_col_pass(const Ctx &c, int conj_h, hipStream_t s);
+hipError_t launch_row_loss(const Ctx &c, const float *target, const float *grad_intensity,
+                           float *intensity, float2 *u_out, int make_grad, hipStream_t s);
 hipError_t launch_loss_finalize(const Ctx &c, double *loss, hipStream_t s);
 
 hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s);

@@ -6,118 +6,55 @@
 // (Sec. 2; Alg. 1 ZeroPad + MultiPlanePropagate).  Because FFT2 -> H -> IFFT2
 // is a circular convolution, padding the field at the start of each row and
 // column (instead of centring it) and cropping the same leading window gives
-// the same u; the kernels use that placement so rows and columns never touch
-// the zero padding in memory:
-//   F1  row FFT:    U0 [C][H][W] -> X [C][H][Wp]           (rows zero-extended)
-//   F2  column pass X: FFT over Hp (zero-extended), x H/(Hp Wp), IFFT, keep H rows
+// the same u; the kernels use that placement so the zero padding never exists
+// in memory:
+//   F1  row FFT:    U0 [C][H][W] -> S (rows zero-extended to Wp)
+//   F2  column pass on S: FFT over Hp (zero-extended), x H/(Hp Wp), IFFT, keep H rows
 //   F3  row pass:   IFFT, crop W -> u; I = |u|^2; loss; g = dL/du; zero-extend; FFT
 //   B1  column pass with conj(H) (the adjoint, supplementary BLASM Backward Pass)
 //   B2  row IFFT, crop W -> dL/dU0
+// S is column-tiled: [C][ceil(Wp/8)][H][8] complex, so a column workgroup
+// reads and writes one contiguous block and a row workgroup (two rows) moves
+// whole 128-byte lines.
+//
+// Column pass for even Hp = 2M: the input occupies rows [0, H) and only rows
+// [0, H) of the output are kept, so the Hp-point transform splits into two
+// M-point chains (radix-2 first and last stages done in registers):
+//   even chain: FFT_M(x[n] + x[n+M])             -> x H(ky = 2m)   -> IFFT_M -> e
+//   odd chain:  FFT_M((x[n] - x[n+M]) w^n)       -> x H(ky = 2m+1) -> IFFT_M -> o
+//   y[n] = e[n] + w^-n o[n],  y[n+M] = e[n] - w^-n o[n],   w = exp(-2 pi i / Hp)
+// which halves the LDS footprint of a column block.
 #include <cmath>
 
 #include "cgh_internal.h"
+#include "fft_reg.h"
 
 namespace cgh {
 
 // ----------------------------------------------------------------------------
-// complex helpers
+// Twiddles w^e = exp(-2 pi i e / n) from a two-level table kept in LDS:
+// hi[j] = w^{64 j} (j <= n/64), lo[j] = w^j (j < 64); w^e = hi[e >> 6] lo[e & 63].
+// The global copy of a table is kTwEntries float2: hi at [0, 129), lo at [129, 193).
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+constexpr int kTwHi = 129;
+constexpr int kTwEntries = kTwHi + 64;
+
+struct TwLds {
+  float2 hi[kTwHi];
+  float2 lo[64];
+};
+
+__device__ __forceinline__ float2 tw_at(const TwLds &t, int e) {
+  return cmul(t.hi[e >> 6], t.lo[e & 63]);
 }
-// multiply by DIR * i  (DIR = -1: forward kernel e^{-i}, +1: inverse)
-template <int DIR>
-__device__ __forceinline__ float2 rot90(float2 a) {
-  return DIR > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+
+template <int T>
+__device__ __forceinline__ void load_tw(TwLds &dst, const float2 *__restrict__ src, int tid) {
+  for (int i = tid; i < kTwEntries; i += T) {
+    if (i < kTwHi) dst.hi[i] = src[i];
+    else dst.lo[i - kTwHi] = src[i];
+  }
 }
-
-// ----------------------------------------------------------------------------
-// small DFTs: y_k = sum_q x_q exp(DIR 2 pi i q k / R)
-// ----------------------------------------------------------------------------
-template <int R, int DIR>
-struct Dft;
-
-template <int DIR>
-struct Dft<2, DIR> {
-  static __device__ __forceinline__ void run(float2 *x) {
-    float2 a = x[0], b = x[1];
-    x[0] = cadd(a, b);
-    x[1] = csub(a, b);
-  }
-};
-
-template <int DIR>
-struct Dft<3, DIR> {
-  static __device__ __forceinline__ void run(float2 *x) {
-    const float h = 0.86602540378443864676f;  // sin(2 pi / 3)
-    float2 s = cadd(x[1], x[2]), d = csub(x[1], x[2]);
-    float2 t = make_float2(x[0].x - 0.5f * s.x, x[0].y - 0.5f * s.y);
-    float2 r = rot90<DIR>(cscale(d, h));
-    x[0] = cadd(x[0], s);
-    x[1] = cadd(t, r);
-    x[2] = csub(t, r);
-  }
-};
-
-template <int DIR>
-struct Dft<4, DIR> {
-  static __device__ __forceinline__ void run(float2 *x) {
-    float2 a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
-    float2 c = cadd(x[1], x[3]), d = rot90<DIR>(csub(x[1], x[3]));
-    x[0] = cadd(a, c);
-    x[2] = csub(a, c);
-    x[1] = cadd(b, d);
-    x[3] = csub(b, d);
-  }
-};
-
-template <int DIR>
-struct Dft<5, DIR> {
-  static __device__ __forceinline__ void run(float2 *x) {
-    const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
-    const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
-    const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
-    const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
-    float2 s14 = cadd(x[1], x[4]), d14 = csub(x[1], x[4]);
-    float2 s23 = cadd(x[2], x[3]), d23 = csub(x[2], x[3]);
-    float2 x0 = x[0];
-    float2 ta = make_float2(x0.x + c1 * s14.x + c2 * s23.x, x0.y + c1 * s14.y + c2 * s23.y);
-    float2 tb = make_float2(x0.x + c2 * s14.x + c1 * s23.x, x0.y + c2 * s14.y + c1 * s23.y);
-    float2 tc = rot90<DIR>(make_float2(s1 * d14.x + s2 * d23.x, s1 * d14.y + s2 * d23.y));
-    float2 td = rot90<DIR>(make_float2(s2 * d14.x - s1 * d23.x, s2 * d14.y - s1 * d23.y));
-    x[0] = cadd(x0, cadd(s14, s23));
-    x[1] = cadd(ta, tc);
-    x[4] = csub(ta, tc);
-    x[2] = cadd(tb, td);
-    x[3] = csub(tb, td);
-  }
-};
-
-template <int DIR>
-struct Dft<8, DIR> {
-  static __device__ __forceinline__ void run(float2 *x) {
-    const float r = 0.70710678118654752440f;
-    float2 e[4] = {x[0], x[2], x[4], x[6]};
-    float2 o[4] = {x[1], x[3], x[5], x[7]};
-    Dft<4, DIR>::run(e);
-    Dft<4, DIR>::run(o);
-    // twiddles w8^k = exp(DIR 2 pi i k / 8)
-    float2 o1 = cscale(cadd(o[1], rot90<DIR>(o[1])), r);
-    float2 o2 = rot90<DIR>(o[2]);
-    float2 o3 = cscale(csub(rot90<DIR>(o[3]), o[3]), r);
-    x[0] = cadd(e[0], o[0]);
-    x[4] = csub(e[0], o[0]);
-    x[1] = cadd(e[1], o1);
-    x[5] = csub(e[1], o1);
-    x[2] = cadd(e[2], o2);
-    x[6] = csub(e[2], o2);
-    x[3] = cadd(e[3], o3);
-    x[7] = csub(e[3], o3);
-  }
-};
 
 // ----------------------------------------------------------------------------
 // One Stockham stage over B interleaved transforms held in LDS:
@@ -129,8 +66,8 @@ struct Dft<8, DIR> {
 // ----------------------------------------------------------------------------
 template <int R, int DIR, int B, int T, int MAXN>
 __device__ __forceinline__ void fft_stage(float2 *__restrict__ buf, int n, int Ns,
-                                          uint32_t magic, int tws,
-                                          const float2 *__restrict__ tw, int tid) {
+                                          uint32_t magic, int tws, const TwLds &tw,
+                                          int tid) {
   constexpr int MAXIT = (B * ((MAXN + R - 1) / R) + T - 1) / T;
   const int nb = n / R;
   const int items = nb * B;
@@ -144,11 +81,13 @@ __device__ __forceinline__ void fft_stage(float2 *__restrict__ buf, int n, int N
       for (int q = 0; q < R; ++q) v[it][q] = buf[(j + q * nb) * B + b];
       if (Ns > 1) {
         const int grp = (int)__umulhi((uint32_t)j, magic);
-        const int e = (j - grp * Ns) * tws;
+        float2 w1 = tw_at(tw, (j - grp * Ns) * tws);
+        if (DIR > 0) w1.y = -w1.y;
+        float2 w = w1;
+        v[it][1] = cmul(v[it][1], w);
 #pragma unroll
-        for (int q = 1; q < R; ++q) {
-          float2 w = tw[q * e];
-          if (DIR > 0) w.y = -w.y;
+        for (int q = 2; q < R; ++q) {
+          w = cmul(w, w1);
           v[it][q] = cmul(v[it][q], w);
         }
       }
@@ -171,20 +110,24 @@ __device__ __forceinline__ void fft_stage(float2 *__restrict__ buf, int n, int N
 }
 
 template <int DIR, int B, int T, int MAXN>
-__device__ void fft_lds(float2 *__restrict__ buf, const FftPlan &p,
-                        const float2 *__restrict__ tw, int tid) {
+__device__ void fft_lds(float2 *__restrict__ buf, const FftPlan &p, const TwLds &tw, int tid) {
   for (int s = 0; s < p.nstages; ++s) {
     const int r = p.radix[s];
+    // An opaque per-stage copy of the thread index: without it the compiler
+    // hoists every radix variant's per-butterfly index math out of this loop
+    // and keeps it all live (about 2x the registers).
+    int ts = tid;
+    asm volatile("" : "+v"(ts));
     if (r == 8)
-      fft_stage<8, DIR, B, T, MAXN>(buf, p.n, p.ns[s], p.magic[s], p.tws[s], tw, tid);
+      fft_stage<8, DIR, B, T, MAXN>(buf, p.n, p.ns[s], p.magic[s], p.tws[s], tw, ts);
     else if (r == 4)
-      fft_stage<4, DIR, B, T, MAXN>(buf, p.n, p.ns[s], p.magic[s], p.tws[s], tw, tid);
+      fft_stage<4, DIR, B, T, MAXN>(buf, p.n, p.ns[s], p.magic[s], p.tws[s], tw, ts);
     else if (r == 3)
-      fft_stage<3, DIR, B, T, MAXN>(buf, p.n, p.ns[s], p.magic[s], p.tws[s], tw, tid);
+      fft_stage<3, DIR, B, T, MAXN>(buf, p.n, p.ns[s], p.magic[s], p.tws[s], tw, ts);
     else if (r == 5)
-      fft_stage<5, DIR, B, T, MAXN>(buf, p.n, p.ns[s], p.magic[s], p.tws[s], tw, tid);
+      fft_stage<5, DIR, B, T, MAXN>(buf, p.n, p.ns[s], p.magic[s], p.tws[s], tw, ts);
     else
-      fft_stage<2, DIR, B, T, MAXN>(buf, p.n, p.ns[s], p.magic[s], p.tws[s], tw, tid);
+      fft_stage<2, DIR, B, T, MAXN>(buf, p.n, p.ns[s], p.magic[s], p.tws[s], tw, ts);
   }
 }
 
@@ -204,7 +147,7 @@ bool make_plan(int n, FftPlan *plan) {
   int ns = 0, m = n, twos = 0;
   while (m % 2 == 0) { m /= 2; ++twos; }
   // powers of two as radix 8 where possible, leftovers as 4 (or one 2)
-  while (twos >= 3 && !(twos == 4)) { rad[ns++] = 8; twos -= 3; }
+  while (twos >= 3 && twos != 4) { rad[ns++] = 8; twos -= 3; }
   while (twos >= 2) { rad[ns++] = 4; twos -= 2; }
   if (twos == 1) rad[ns++] = 2;
   while (m % 3 == 0) { rad[ns++] = 3; m /= 3; }
@@ -226,19 +169,39 @@ bool make_plan(int n, FftPlan *plan) {
   return true;
 }
 
+bool col_supported(int Hp) {
+  if (Hp % 2 == 0) return Hp / 2 <= kColHalfMax;
+  return Hp <= kColFullMax;
+}
+
 // ----------------------------------------------------------------------------
 // Tables (FP64 on the device, rounded to FP32 once)
 // ----------------------------------------------------------------------------
 __global__ void k_twiddles(float2 *tw, int n) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kTwEntries) return;
+  const long e = j < kTwHi ? (64L * j) % n : (long)(j - kTwHi) % n;
   double s, c;
-  sincospi(2.0 * (double)k / (double)n, &s, &c);
-  tw[k] = make_float2((float)c, (float)(-s));  // exp(-2 pi i k / n)
+  sincospi(2.0 * (double)e / (double)n, &s, &c);
+  tw[j] = make_float2((float)c, (float)(-s));  // exp(-2 pi i e / n)
 }
 
 hipError_t launch_build_twiddles(float2 *tw, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, tw, n);
+  hipLaunchKernelGGL(k_twiddles, dim3(1), dim3(256), 0, s, tw, n);
+  return hipGetLastError();
+}
+
+// full table tw[e] = exp(-2 pi i e / n), e < n
+__global__ void k_twiddles_full(float2 *tw, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s, c;
+  sincospi(2.0 * (double)e / (double)n, &s, &c);
+  tw[e] = make_float2((float)c, (float)(-s));
+}
+
+hipError_t launch_build_twiddles_full(float2 *tw, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_twiddles_full, dim3((n + 255) / 256), dim3(256), 0, s, tw, n);
   return hipGetLastError();
 }
 
@@ -281,201 +244,553 @@ hipError_t launch_build_transfer(const Ctx &c, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------
-// Row transform: load in_len values of a row (zero-extend to n), transform,
-// store the first out_len values.  One workgroup per row, row in LDS.
+// Row passes: two rows (y0, y0+1) of one channel per workgroup, interleaved in
+// LDS as element (x, b) at sbuf[2 x + b].  Column-tiled global layout:
+//   S[c][x / 8][y][x % 8]
+// so sixteen consecutive threads move one 128-byte line (rows y0, y0+1 of a tile).
 // ----------------------------------------------------------------------------
-constexpr int kRowThreads = 256;
+constexpr int kRowThreads = 512;
 
-template <int DIR>
-__global__ __launch_bounds__(kRowThreads) void k_row_fft(const float2 *__restrict__ in,
-                                                         int in_len, long in_stride,
-                                                         float2 *__restrict__ out,
-                                                         int out_len, long out_stride,
-                                                         FftPlan p,
-                                                         const float2 *__restrict__ tw) {
-  extern __shared__ float2 sbuf[];
-  const int tid = threadIdx.x;
-  const int n = p.n;
-  const float2 *src = in + (size_t)blockIdx.x * in_stride;
-  for (int i = tid; i < n; i += kRowThreads) sbuf[i] = i < in_len ? src[i] : make_float2(0.f, 0.f);
-  __syncthreads();
-  fft_lds<DIR, 1, kRowThreads, kMaxFft>(sbuf, p, tw, tid);
-  float2 *dst = out + (size_t)blockIdx.x * out_stride;
-  for (int i = tid; i < out_len; i += kRowThreads) dst[i] = sbuf[i];
+__device__ __forceinline__ size_t tiled(int c, int y, int x, int H, int Wt) {
+  return (((size_t)c * Wt + (x >> 3)) * H + y) * 8 + (x & 7);
 }
 
-hipError_t launch_row_fft(const Ctx &c, const float2 *in, int in_len, long in_stride,
-                          float2 *out, int out_len, long out_stride, int rows, int inverse,
-                          hipStream_t s) {
-  if (rows <= 0) return hipSuccess;
-  const size_t lds = (size_t)c.plan_x.n * sizeof(float2);
-  if (inverse)
-    hipLaunchKernelGGL(k_row_fft<+1>, dim3(rows), dim3(kRowThreads), lds, s, in, in_len,
-                       in_stride, out, out_len, out_stride, c.plan_x, c.tw_x);
-  else
-    hipLaunchKernelGGL(k_row_fft<-1>, dim3(rows), dim3(kRowThreads), lds, s, in, in_len,
-                       in_stride, out, out_len, out_stride, c.plan_x, c.tw_x);
-  return hipGetLastError();
-}
-
-// ----------------------------------------------------------------------------
-// Column pass: B adjacent columns of one channel.  Load H rows (zero-extend
-// to Hp), FFT, multiply by H (or conj H) / (Hp Wp), IFFT, store H rows back in
-// place.  The columns are disjoint between workgroups, so in place is safe.
-// ----------------------------------------------------------------------------
-constexpr int kColThreads = 1024;
-constexpr int kColLdsElems = 19200;  // 150 KiB of float2
-
-template <int B>
-__global__ __launch_bounds__(kColThreads) void k_col_pass(float2 *__restrict__ data, int H,
-                                                          int Wp, FftPlan py,
-                                                          const float2 *__restrict__ tw,
-                                                          const float2 *__restrict__ htab,
-                                                          int Hq, int Wq, int L, int conj_h,
-                                                          float scale) {
-  constexpr int MAXN = kColLdsElems / B;
-  __shared__ float2 sbuf[B * MAXN];
-  const int tid = threadIdx.x;
-  const int ch = blockIdx.y;
-  const int col0 = blockIdx.x * B;
-  const int Hp = py.n;
-  float2 *base = data + (size_t)ch * H * Wp + col0;
-  const int total = Hp * B;
-  for (int i = tid; i < total; i += kColThreads) {
-    const int r = i / B, b = i % B;
-    float2 v = make_float2(0.f, 0.f);
-    if (r < H && col0 + b < Wp) v = base[(size_t)r * Wp + b];
-    sbuf[i] = v;
-  }
-  __syncthreads();
-  fft_lds<-1, B, kColThreads, MAXN>(sbuf, py, tw, tid);
-  const float2 *hc = htab + (size_t)ch * L * Hq * Wq;  // plane 0
-  for (int i = tid; i < total; i += kColThreads) {
-    const int r = i / B, b = i % B;
-    const int kx = col0 + b;
-    float2 v = make_float2(0.f, 0.f);
-    if (kx < Wp) {
-      const int qx = min(kx, Wp - kx), qy = min(r, Hp - r);
-      float2 h = hc[(size_t)qy * Wq + qx];
-      if (conj_h) h.y = -h.y;
-      v = cscale(cmul(sbuf[i], h), scale);
+// load the two rows of S into LDS (zero beyond Wp or H)
+__device__ __forceinline__ void load_rows_tiled(float2 *sbuf, const float2 *__restrict__ S,
+                                                int c, int y0, int H, int Wp, int Wt,
+                                                int tid) {
+  for (int i = tid; i < Wt * 16; i += kRowThreads) {
+    const int t = i >> 4, b = (i >> 3) & 1, x = t * 8 + (i & 7);
+    if (x < Wp) {
+      float2 v = make_float2(0.f, 0.f);
+      if (y0 + b < H) v = S[tiled(c, y0 + b, x, H, Wt)];
+      sbuf[2 * x + b] = v;
     }
-    sbuf[i] = v;
+  }
+}
+
+__device__ __forceinline__ void store_rows_tiled(const float2 *sbuf, float2 *__restrict__ S,
+                                                 int c, int y0, int H, int Wp, int Wt,
+                                                 int tid) {
+  for (int i = tid; i < Wt * 16; i += kRowThreads) {
+    const int t = i >> 4, b = (i >> 3) & 1, x = t * 8 + (i & 7);
+    if (x < Wp && y0 + b < H) S[tiled(c, y0 + b, x, H, Wt)] = sbuf[2 * x + b];
+  }
+}
+
+// F1: field rows (zero-extended to Wp) -> forward FFT -> S
+template <int MAXN>
+__global__ __launch_bounds__(kRowThreads) void k_row_fwd(const float2 *__restrict__ field,
+                                                         int H, int W, int Wt, FftPlan p,
+                                                         const float2 *__restrict__ twx,
+                                                         float2 *__restrict__ S) {
+  extern __shared__ float2 sbuf[];
+  __shared__ TwLds tw;
+  const int tid = threadIdx.x, n = p.n;
+  const int pairs = (H + 1) >> 1;
+  const int c = blockIdx.x / pairs, y0 = 2 * (blockIdx.x % pairs);
+  load_tw<kRowThreads>(tw, twx, tid);
+  for (int b = 0; b < 2; ++b) {
+    const bool ok = y0 + b < H;
+    const float2 *src = field + ((size_t)c * H + y0 + b) * W;
+    for (int x = tid; x < n; x += kRowThreads)
+      sbuf[2 * x + b] = (ok && x < W) ? src[x] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_lds<+1, B, kColThreads, MAXN>(sbuf, py, tw, tid);
-  const int keep = H * B;
-  for (int i = tid; i < keep; i += kColThreads) {
-    const int r = i / B, b = i % B;
-    if (col0 + b < Wp) base[(size_t)r * Wp + b] = sbuf[i];
+  fft_lds<-1, 2, kRowThreads, MAXN>(sbuf, p, tw, tid);
+  store_rows_tiled(sbuf, S, c, y0, H, n, Wt, tid);
+}
+
+// B2: S -> inverse FFT -> first W values of each row -> grad field
+template <int MAXN>
+__global__ __launch_bounds__(kRowThreads) void k_row_inv(const float2 *__restrict__ S, int H,
+                                                         int W, int Wt, FftPlan p,
+                                                         const float2 *__restrict__ twx,
+                                                         float2 *__restrict__ out) {
+  extern __shared__ float2 sbuf[];
+  __shared__ TwLds tw;
+  const int tid = threadIdx.x, n = p.n;
+  const int pairs = (H + 1) >> 1;
+  const int c = blockIdx.x / pairs, y0 = 2 * (blockIdx.x % pairs);
+  load_tw<kRowThreads>(tw, twx, tid);
+  load_rows_tiled(sbuf, S, c, y0, H, n, Wt, tid);
+  __syncthreads();
+  fft_lds<+1, 2, kRowThreads, MAXN>(sbuf, p, tw, tid);
+  for (int b = 0; b < 2; ++b) {
+    if (y0 + b >= H) break;
+    float2 *dst = out + ((size_t)c * H + y0 + b) * W;
+    for (int x = tid; x < W; x += kRowThreads) dst[x] = sbuf[2 * x + b];
   }
 }
 
-static int col_batch(int Hp) {
-  // widest column batch whose Hp x B block fits the LDS budget (B <= 16)
-  for (int b : {16, 8, 4, 2})
-    if (Hp * b <= kColLdsElems) return b;
-  return 0;
-}
-
-hipError_t launch_col_pass(const Ctx &c, float2 *data, int conj_h, hipStream_t s) {
-  const int B = col_batch(c.Hp);
-  const float scale = (float)(1.0 / ((double)c.Hp * (double)c.Wp));
-  dim3 grid((c.Wp + B - 1) / B, c.C);
-  switch (B) {
-    case 16:
-      hipLaunchKernelGGL(k_col_pass<16>, grid, dim3(kColThreads), 0, s, data, c.H, c.Wp,
-                         c.plan_y, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h, scale);
-      break;
-    case 8:
-      hipLaunchKernelGGL(k_col_pass<8>, grid, dim3(kColThreads), 0, s, data, c.H, c.Wp,
-                         c.plan_y, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h, scale);
-      break;
-    case 4:
-      hipLaunchKernelGGL(k_col_pass<4>, grid, dim3(kColThreads), 0, s, data, c.H, c.Wp,
-                         c.plan_y, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h, scale);
-      break;
-    default:
-      hipLaunchKernelGGL(k_col_pass<2>, grid, dim3(kColThreads), 0, s, data, c.H, c.Wp,
-                         c.plan_y, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h, scale);
-      break;
-  }
-  return hipGetLastError();
-}
-
-// ----------------------------------------------------------------------------
-// Middle row pass (F3): IFFT a row of the column-pass output, crop the first W
-// values -> u, I = |u|^2 (optionally stored, with u), and if make_grad:
-//   dL/dI = 2 (I - T) / M (MSE, Sec. 3.2) or the caller's dL/dI,
-//   g = 2 dL/dI u = dL/dRe(u) + j dL/dIm(u),
-// zero-extend g and FFT it back into the row (seed of the adjoint pass).
-// Per-row FP64 partial sums of (I - T)^2 go to loss_part.
-// ----------------------------------------------------------------------------
+// F3: S -> inverse FFT -> u (first W values) -> I = |u|^2 (optionally stored,
+// with u); if make_grad: dL/dI = 2 (I - T) / M (MSE, Sec. 3.2) or the caller's
+// dL/dI, g = 2 dL/dI u = dL/dRe(u) + j dL/dIm(u), zero-extended, forward FFT,
+// back into S.  FP64 partial sums of (I - T)^2 per workgroup into loss_part.
+template <int MAXN>
 __global__ __launch_bounds__(kRowThreads) void k_row_loss(
-    float2 *__restrict__ data, int W, int Wp, FftPlan px, const float2 *__restrict__ tw,
+    float2 *__restrict__ S, int H, int W, int Wt, FftPlan p, const float2 *__restrict__ twx,
     const float *__restrict__ target, const float *__restrict__ grad_I,
     float *__restrict__ intensity, float2 *__restrict__ u_out, double *__restrict__ loss_part,
     float gscale, int make_grad) {
   extern __shared__ float2 sbuf[];
-  __shared__ double red[kRowThreads];
-  const int tid = threadIdx.x;
-  const size_t row = blockIdx.x;
-  float2 *rp = data + row * Wp;
-  for (int i = tid; i < Wp; i += kRowThreads) sbuf[i] = rp[i];
+  __shared__ TwLds tw;
+  __shared__ double red[kRowThreads / 64];
+  const int tid = threadIdx.x, n = p.n;
+  const int pairs = (H + 1) >> 1;
+  const int c = blockIdx.x / pairs, y0 = 2 * (blockIdx.x % pairs);
+  load_tw<kRowThreads>(tw, twx, tid);
+  load_rows_tiled(sbuf, S, c, y0, H, n, Wt, tid);
   __syncthreads();
-  fft_lds<+1, 1, kRowThreads, kMaxFft>(sbuf, px, tw, tid);
+  fft_lds<+1, 2, kRowThreads, MAXN>(sbuf, p, tw, tid);
   double acc = 0.0;
-  for (int i = tid; i < Wp; i += kRowThreads) {
-    if (i < W) {
-      const float2 u = sbuf[i];
+  for (int i = tid; i < 2 * n; i += kRowThreads) {
+    const int b = i >= n, x = i - b * n;
+    const int y = y0 + b;
+    if (x < W && y < H) {
+      const float2 u = sbuf[2 * x + b];
       const float I = u.x * u.x + u.y * u.y;
-      const size_t o = row * W + i;
+      const size_t o = ((size_t)c * H + y) * W + x;
       if (intensity) intensity[o] = I;
       if (u_out) u_out[o] = u;
-      if (make_grad) {
-        float f;
-        if (target) {
-          const float d = I - target[o];
-          acc += (double)d * (double)d;
-          f = gscale * d;  // 4 (I - T) / M
-        } else {
-          f = 2.0f * grad_I[o];
-        }
-        sbuf[i] = make_float2(f * u.x, f * u.y);
-      } else if (target) {
+      float f = 0.f;
+      if (target) {
         const float d = I - target[o];
         acc += (double)d * (double)d;
+        f = gscale * d;  // 4 (I - T) / M
+      } else if (grad_I) {
+        f = 2.0f * grad_I[o];
       }
+      if (make_grad) sbuf[2 * x + b] = make_float2(f * u.x, f * u.y);
     } else if (make_grad) {
-      sbuf[i] = make_float2(0.f, 0.f);
+      sbuf[2 * x + b] = make_float2(0.f, 0.f);
     }
   }
   if (target) {
-    red[tid] = acc;
+    // wave sums, then a fixed-order sum over the waves
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
     __syncthreads();
-    for (int w = kRowThreads / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < kRowThreads / 64; ++w) s += red[w];
+      loss_part[blockIdx.x] = s;
     }
-    if (tid == 0) loss_part[row] = red[0];
   }
   if (make_grad) {
     __syncthreads();
-    fft_lds<-1, 1, kRowThreads, kMaxFft>(sbuf, px, tw, tid);
-    for (int i = tid; i < Wp; i += kRowThreads) rp[i] = sbuf[i];
+    fft_lds<-1, 2, kRowThreads, MAXN>(sbuf, p, tw, tid);
+    store_rows_tiled(sbuf, S, c, y0, H, n, Wt, tid);
   }
 }
 
-hipError_t launch_row_loss(const Ctx &c, float2 *data, const float *target,
-                           const float *grad_intensity, float *intensity, float2 *u_out,
-                           int make_grad, hipStream_t s) {
-  const int rows = c.L * c.C * c.H;
+// ----------------------------------------------------------------------------
+// Size-specialised row passes: compile-time plan (three large-radix stages for
+// the workload lengths), ROWS rows per workgroup, full twiddle table in LDS.
+// ----------------------------------------------------------------------------
+template <int N, int ROWS, int T>
+__device__ __forceinline__ void load_rows_c(float2 *sbuf, const float2 *__restrict__ S, int c,
+                                            int y0, int H, int Wt, int tid) {
+  for (int i = tid; i < Wt * 8 * ROWS; i += T) {
+    const int t = i / (8 * ROWS), r = i % (8 * ROWS), b = r >> 3, x = t * 8 + (r & 7);
+    if (x < N) sbuf[ROWS * x + b] = (y0 + b < H) ? S[tiled(c, y0 + b, x, H, Wt)]
+                                                  : make_float2(0.f, 0.f);
+  }
+}
+
+template <int N, int ROWS, int T>
+__device__ __forceinline__ void store_rows_c(const float2 *sbuf, float2 *__restrict__ S, int c,
+                                             int y0, int H, int Wt, int tid) {
+  for (int i = tid; i < Wt * 8 * ROWS; i += T) {
+    const int t = i / (8 * ROWS), r = i % (8 * ROWS), b = r >> 3, x = t * 8 + (r & 7);
+    if (x < N && y0 + b < H) S[tiled(c, y0 + b, x, H, Wt)] = sbuf[ROWS * x + b];
+  }
+}
+
+template <int N, int T>
+__device__ __forceinline__ void load_table(float2 *tw, const float2 *__restrict__ src, int tid) {
+  for (int i = tid; i < N; i += T) tw[i] = src[i];
+}
+
+template <int N, int ROWS, int T>
+__global__ __launch_bounds__(T) void k_row_fwd_c(const float2 *__restrict__ field, int H, int W,
+                                                 int Wt, const float2 *__restrict__ twf,
+                                                 float2 *__restrict__ S) {
+  __shared__ float2 sbuf[ROWS * N];
+  __shared__ float2 tw[N];
+  const int tid = threadIdx.x;
+  const int groups = (H + ROWS - 1) / ROWS;
+  const int c = blockIdx.x / groups, y0 = ROWS * (blockIdx.x % groups);
+  load_table<N, T>(tw, twf, tid);
+  for (int b = 0; b < ROWS; ++b) {
+    const bool ok = y0 + b < H;
+    const float2 *src = field + ((size_t)c * H + y0 + b) * W;
+    for (int x = tid; x < N; x += T)
+      sbuf[ROWS * x + b] = (ok && x < W) ? src[x] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  cfft<-1, ROWS, T, N>(sbuf, tw, tid);
+  store_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
+}
+
+template <int N, int ROWS, int T>
+__global__ __launch_bounds__(T) void k_row_inv_c(const float2 *__restrict__ S, int H, int W,
+                                                 int Wt, const float2 *__restrict__ twf,
+                                                 float2 *__restrict__ out) {
+  __shared__ float2 sbuf[ROWS * N];
+  __shared__ float2 tw[N];
+  const int tid = threadIdx.x;
+  const int groups = (H + ROWS - 1) / ROWS;
+  const int c = blockIdx.x / groups, y0 = ROWS * (blockIdx.x % groups);
+  load_table<N, T>(tw, twf, tid);
+  load_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
+  __syncthreads();
+  cfft<+1, ROWS, T, N>(sbuf, tw, tid);
+  for (int b = 0; b < ROWS; ++b) {
+    if (y0 + b >= H) break;
+    float2 *dst = out + ((size_t)c * H + y0 + b) * W;
+    for (int x = tid; x < W; x += T) dst[x] = sbuf[ROWS * x + b];
+  }
+}
+
+template <int N, int ROWS, int T>
+__global__ __launch_bounds__(T) void k_row_loss_c(
+    float2 *__restrict__ S, int H, int W, int Wt, const float2 *__restrict__ twf,
+    const float *__restrict__ target, const float *__restrict__ grad_I,
+    float *__restrict__ intensity, float2 *__restrict__ u_out, double *__restrict__ loss_part,
+    float gscale, int make_grad) {
+  __shared__ float2 sbuf[ROWS * N];
+  __shared__ float2 tw[N];
+  __shared__ double red[T / 64];
+  const int tid = threadIdx.x;
+  const int groups = (H + ROWS - 1) / ROWS;
+  const int c = blockIdx.x / groups, y0 = ROWS * (blockIdx.x % groups);
+  load_table<N, T>(tw, twf, tid);
+  load_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
+  __syncthreads();
+  cfft<+1, ROWS, T, N>(sbuf, tw, tid);
+  double acc = 0.0;
+  for (int i = tid; i < ROWS * N; i += T) {
+    const int b = i / N, x = i - b * N;
+    const int y = y0 + b;
+    if (x < W && y < H) {
+      const float2 u = sbuf[ROWS * x + b];
+      const float I = u.x * u.x + u.y * u.y;
+      const size_t o = ((size_t)c * H + y) * W + x;
+      if (intensity) intensity[o] = I;
+      if (u_out) u_out[o] = u;
+      float f = 0.f;
+      if (target) {
+        const float d = I - target[o];
+        acc += (double)d * (double)d;
+        f = gscale * d;  // 4 (I - T) / M
+      } else if (grad_I) {
+        f = 2.0f * grad_I[o];
+      }
+      if (make_grad) sbuf[ROWS * x + b] = make_float2(f * u.x, f * u.y);
+    } else if (make_grad) {
+      sbuf[ROWS * x + b] = make_float2(0.f, 0.f);
+    }
+  }
+  if (target) {
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < T / 64; ++w) sum += red[w];
+      loss_part[blockIdx.x] = sum;
+    }
+  }
+  if (make_grad) {
+    __syncthreads();
+    cfft<-1, ROWS, T, N>(sbuf, tw, tid);
+    store_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
+  }
+}
+
+// rows per row-pass workgroup (specialised lengths use 4, the runtime path 2)
+static bool row_specialised(int Wp) { return Wp == 3840 || Wp == 512; }
+int row_group_rows(const Ctx &c) { return row_specialised(c.Wp) ? 4 : 2; }
+static int row_blocks(const Ctx &c) {
+  const int r = row_group_rows(c);
+  return c.C * ((c.H + r - 1) / r);
+}
+static size_t row_lds(const Ctx &c) { return (size_t)2 * c.Wp * sizeof(float2); }
+
+hipError_t launch_row_fwd(const Ctx &c, const float2 *field, hipStream_t s) {
+  if (c.Wp == 3840)
+    hipLaunchKernelGGL((k_row_fwd_c<3840, 4, 1024>), dim3(row_blocks(c)), dim3(1024), 0, s,
+                       field, c.H, c.W, c.Wt, c.twf_x, c.spec);
+  else if (c.Wp == 512)
+    hipLaunchKernelGGL((k_row_fwd_c<512, 4, 256>), dim3(row_blocks(c)), dim3(256), 0, s, field,
+                       c.H, c.W, c.Wt, c.twf_x, c.spec);
+  else if (c.Wp <= 4096)
+    hipLaunchKernelGGL(k_row_fwd<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
+                       field, c.H, c.W, c.Wt, c.plan_x, c.tw_x, c.spec);
+  else
+    hipLaunchKernelGGL(k_row_fwd<8192>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
+                       field, c.H, c.W, c.Wt, c.plan_x, c.tw_x, c.spec);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_inv(const Ctx &c, float2 *out, hipStream_t s) {
+  if (c.Wp == 3840)
+    hipLaunchKernelGGL((k_row_inv_c<3840, 4, 1024>), dim3(row_blocks(c)), dim3(1024), 0, s,
+                       c.spec, c.H, c.W, c.Wt, c.twf_x, out);
+  else if (c.Wp == 512)
+    hipLaunchKernelGGL((k_row_inv_c<512, 4, 256>), dim3(row_blocks(c)), dim3(256), 0, s, c.spec,
+                       c.H, c.W, c.Wt, c.twf_x, out);
+  else if (c.Wp <= 4096)
+    hipLaunchKernelGGL(k_row_inv<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
+                       c.spec, c.H, c.W, c.Wt, c.plan_x, c.tw_x, out);
+  else
+    hipLaunchKernelGGL(k_row_inv<8192>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
+                       c.spec, c.H, c.W, c.Wt, c.plan_x, c.tw_x, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_loss(const Ctx &c, const float *target, const float *grad_intensity,
+                           float *intensity, float2 *u_out, int make_grad, hipStream_t s) {
   const double M = (double)c.L * c.C * c.H * c.W;
   const float gscale = (float)(4.0 / M);
-  const size_t lds = (size_t)c.Wp * sizeof(float2);
-  hipLaunchKernelGGL(k_row_loss, dim3(rows), dim3(kRowThreads), lds, s, data, c.W, c.Wp,
-                     c.plan_x, c.tw_x, target, grad_intensity, intensity, u_out, c.loss_part,
-                     gscale, make_grad);
+  if (c.Wp == 3840)
+    hipLaunchKernelGGL((k_row_loss_c<3840, 4, 1024>), dim3(row_blocks(c)), dim3(1024), 0, s,
+                       c.spec, c.H, c.W, c.Wt, c.twf_x, target, grad_intensity, intensity, u_out,
+                       c.loss_part, gscale, make_grad);
+  else if (c.Wp == 512)
+    hipLaunchKernelGGL((k_row_loss_c<512, 4, 256>), dim3(row_blocks(c)), dim3(256), 0, s,
+                       c.spec, c.H, c.W, c.Wt, c.twf_x, target, grad_intensity, intensity, u_out,
+                       c.loss_part, gscale, make_grad);
+  else if (c.Wp <= 4096)
+    hipLaunchKernelGGL(k_row_loss<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
+                       c.spec, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity,
+                       intensity, u_out, c.loss_part, gscale, make_grad);
+  else
+    hipLaunchKernelGGL(k_row_loss<8192>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
+                       c.spec, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity,
+                       intensity, u_out, c.loss_part, gscale, make_grad);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Column passes over one 8-column tile of one channel (a contiguous block of
+// H x 8 complex in S), in place.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float2 transfer_at(const float2 *__restrict__ hc, int ky, int kx,
+                                              int Hp, int Wp, int Wq, int conj_h, float scale) {
+  const int qx = min(kx, Wp - kx), qy = min(ky, Hp - ky);
+  float2 h = hc[(size_t)qy * Wq + qx];
+  if (conj_h) h.y = -h.y;
+  return cscale(h, scale);
+}
+
+// even Hp = 2M: two M-point chains (see the file header)
+template <int MAXM, int T>
+__global__ __launch_bounds__(T, 2048 / T) void k_col_half(float2 *__restrict__ S, int H, int Wp, int Wt,
+                                                FftPlan pm, const float2 *__restrict__ twm,
+                                                const float2 *__restrict__ twh,
+                                                const float2 *__restrict__ htab, int Hq, int Wq,
+                                                int L, int conj_h, float scale) {
+  __shared__ float2 sbuf[8 * MAXM];
+  __shared__ TwLds tm, th;
+  constexpr int K = (8 * MAXM + T - 1) / T;
+  const int tid = threadIdx.x;
+  const int M = pm.n, Hp = 2 * M;
+  const int t = blockIdx.x, ch = blockIdx.y;
+  float2 *base = S + ((size_t)ch * Wt + t) * H * 8;
+  const float2 *hc = htab + (size_t)ch * L * Hq * Wq;  // plane 0
+  const int total = 8 * M;
+  load_tw<T>(tm, twm, tid);
+  load_tw<T>(th, twh, tid);
+  __syncthreads();
+  float2 keep[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T;
+    keep[k] = make_float2(0.f, 0.f);
+    if (i < total) {
+      const int n = i >> 3, kx = t * 8 + (i & 7);
+      float2 x0 = make_float2(0.f, 0.f), x1 = x0;
+      if (kx < Wp) {
+        if (n < H) x0 = base[i];
+        if (n + M < H) x1 = base[i + 8 * M];
+      }
+      sbuf[i] = cadd(x0, x1);
+      keep[k] = cmul(csub(x0, x1), tw_at(th, n));
+    }
+  }
+  __syncthreads();
+  for (int parity = 0; parity < 2; ++parity) {
+    fft_lds<-1, 8, T, MAXM>(sbuf, pm, tm, tid);
+    for (int i = tid; i < total; i += T) {
+      const int m = i >> 3, kx = t * 8 + (i & 7);
+      sbuf[i] = kx < Wp ? cmul(sbuf[i], transfer_at(hc, 2 * m + parity, kx, Hp, Wp, Wq, conj_h,
+                                                     scale))
+                        : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_lds<+1, 8, T, MAXM>(sbuf, pm, tm, tid);
+    if (parity == 0) {
+      // even result to registers, odd-chain input to LDS (each thread its own slots)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = tid + k * T;
+        if (i < total) {
+          const float2 e = sbuf[i];
+          sbuf[i] = keep[k];
+          keep[k] = e;
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T;
+    if (i < total) {
+      const int n = i >> 3, kx = t * 8 + (i & 7);
+      if (kx < Wp) {
+        const float2 wo = cmul(cconj(tw_at(th, n)), sbuf[i]);
+        if (n < H) base[i] = cadd(keep[k], wo);
+        if (n + M < H) base[i + 8 * M] = csub(keep[k], wo);
+      }
+    }
+  }
+}
+
+// odd Hp: one Hp-point transform per column
+template <int MAXN, int T>
+__global__ __launch_bounds__(T) void k_col_full(float2 *__restrict__ S, int H, int Wp, int Wt,
+                                                FftPlan py, const float2 *__restrict__ twy,
+                                                const float2 *__restrict__ htab, int Hq, int Wq,
+                                                int L, int conj_h, float scale) {
+  __shared__ float2 sbuf[8 * MAXN];
+  __shared__ TwLds ty;
+  const int tid = threadIdx.x;
+  const int Hp = py.n;
+  const int t = blockIdx.x, ch = blockIdx.y;
+  float2 *base = S + ((size_t)ch * Wt + t) * H * 8;
+  const float2 *hc = htab + (size_t)ch * L * Hq * Wq;
+  const int total = 8 * Hp;
+  load_tw<T>(ty, twy, tid);
+  for (int i = tid; i < total; i += T) {
+    const int r = i >> 3, kx = t * 8 + (i & 7);
+    sbuf[i] = (r < H && kx < Wp) ? base[i] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_lds<-1, 8, T, MAXN>(sbuf, py, ty, tid);
+  for (int i = tid; i < total; i += T) {
+    const int r = i >> 3, kx = t * 8 + (i & 7);
+    sbuf[i] = kx < Wp ? cmul(sbuf[i], transfer_at(hc, r, kx, Hp, Wp, Wq, conj_h, scale))
+                      : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_lds<+1, 8, T, MAXN>(sbuf, py, ty, tid);
+  for (int i = tid; i < 8 * H; i += T) {
+    const int kx = t * 8 + (i & 7);
+    if (kx < Wp) base[i] = sbuf[i];
+  }
+}
+
+// size-specialised even/odd column pass: compile-time M-point plan, full
+// M-entry twiddle table in LDS (the Hp-point pre/post twiddles use the small
+// two-level table)
+template <int M, int T>
+__global__ __launch_bounds__(T) void k_col_half_c(
+    float2 *__restrict__ S, int H, int Wp, int Wt, const float2 *__restrict__ twf_m,
+    const float2 *__restrict__ twh, const float2 *__restrict__ htab, int Hq, int Wq, int L,
+    int conj_h, float scale) {
+  __shared__ float2 sbuf[8 * M];
+  __shared__ float2 tw[M];
+  __shared__ TwLds th;
+  constexpr int K = (8 * M + T - 1) / T;
+  constexpr int total = 8 * M;
+  constexpr int Hp = 2 * M;
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x, ch = blockIdx.y;
+  float2 *base = S + ((size_t)ch * Wt + t) * H * 8;
+  const float2 *hc = htab + (size_t)ch * L * Hq * Wq;  // plane 0
+  load_table<M, T>(tw, twf_m, tid);
+  load_tw<T>(th, twh, tid);
+  __syncthreads();
+  float2 keep[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T;
+    keep[k] = make_float2(0.f, 0.f);
+    if (total % T == 0 || i < total) {
+      const int n = i >> 3, kx = t * 8 + (i & 7);
+      float2 x0 = make_float2(0.f, 0.f), x1 = x0;
+      if (kx < Wp) {
+        if (n < H) x0 = base[i];
+        if (n + M < H) x1 = base[i + 8 * M];
+      }
+      sbuf[i] = cadd(x0, x1);
+      keep[k] = cmul(csub(x0, x1), tw_at(th, n));
+    }
+  }
+  __syncthreads();
+  for (int parity = 0; parity < 2; ++parity) {
+    cfft<-1, 8, T, M>(sbuf, tw, tid);
+    for (int i = tid; i < total; i += T) {
+      const int m = i >> 3, kx = t * 8 + (i & 7);
+      sbuf[i] = kx < Wp ? cmul(sbuf[i], transfer_at(hc, 2 * m + parity, kx, Hp, Wp, Wq, conj_h,
+                                                     scale))
+                        : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    cfft<+1, 8, T, M>(sbuf, tw, tid);
+    if (parity == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = tid + k * T;
+        if (total % T == 0 || i < total) {
+          const float2 e = sbuf[i];
+          sbuf[i] = keep[k];
+          keep[k] = e;
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T;
+    if (total % T == 0 || i < total) {
+      const int n = i >> 3, kx = t * 8 + (i & 7);
+      if (kx < Wp) {
+        const float2 wo = cmul(cconj(tw_at(th, n)), sbuf[i]);
+        if (n < H) base[i] = cadd(keep[k], wo);
+        if (n + M < H) base[i + 8 * M] = csub(keep[k], wo);
+      }
+    }
+  }
+}
+
+hipError_t launch_col_pass(const Ctx &c, int conj_h, hipStream_t s) {
+  const float scale = (float)(1.0 / ((double)c.Hp * (double)c.Wp));
+  dim3 grid(c.Wt, c.C);
+  if (c.Hp == 2160) {
+    hipLaunchKernelGGL((k_col_half_c<1080, 1024>), grid, dim3(1024), 0, s, c.spec, c.H, c.Wp,
+                       c.Wt, c.twf_m, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h, scale);
+  } else if (c.Hp == 512) {
+    hipLaunchKernelGGL((k_col_half_c<256, 256>), grid, dim3(256), 0, s, c.spec, c.H, c.Wp,
+                       c.Wt, c.twf_m, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h, scale);
+  } else if (c.Hp % 2 == 0) {
+    const int M = c.Hp / 2;
+    if (M <= kColHalfSmall)
+      hipLaunchKernelGGL((k_col_half<kColHalfSmall, 512>), grid, dim3(512), 0, s, c.spec, c.H,
+                         c.Wp, c.Wt, c.plan_m, c.tw_m, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h,
+                         scale);
+    else
+      hipLaunchKernelGGL((k_col_half<kColHalfMax, 1024>), grid, dim3(1024), 0, s, c.spec, c.H,
+                         c.Wp, c.Wt, c.plan_m, c.tw_m, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h,
+                         scale);
+  } else {
+    hipLaunchKernelGGL((k_col_full<kColFullMax, 1024>), grid, dim3(1024), 0, s, c.spec, c.H,
+                       c.Wp, c.Wt, c.plan_y, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h, scale);
+  }
   return hipGetLastError();
 }
 
@@ -500,9 +815,9 @@ __global__ __launch_bounds__(256) void k_loss_finalize(const double *__restrict_
 }
 
 hipError_t launch_loss_finalize(const Ctx &c, double *loss, hipStream_t s) {
-  const int rows = c.L * c.C * c.H;
   const double inv_m = 1.0 / ((double)c.L * c.C * c.H * c.W);
-  hipLaunchKernelGGL(k_loss_finalize, dim3(1), dim3(256), 0, s, c.loss_part, rows, inv_m, loss);
+  hipLaunchKernelGGL(k_loss_finalize, dim3(1), dim3(256), 0, s, c.loss_part, row_blocks(c),
+                     inv_m, loss);
   return hipGetLastError();
 }
 

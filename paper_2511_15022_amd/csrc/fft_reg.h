@@ -1,0 +1,342 @@
+// Register-resident DFTs of compile-time length and compile-time Stockham
+// plans: the building blocks of the size-specialised propagation kernels.
+//
+// RFft<N, DIR> transforms N complex values held in registers (natural order in
+// and out), y_k = sum_n x_n exp(DIR 2 pi i n k / N), by splitting N = N1 N2
+// (N1 a base radix 2, 3, 4, 5 or 8): N2 DFTs of length N1, a multiply by the
+// compile-time twiddles exp(DIR 2 pi i n2 k1 / N), then N1 DFTs of length N2.
+// All twiddles are constants evaluated at compile time in double precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+// arithmetic helpers are host-callable too, so the transforms can be checked on a CPU
+#define CGH_HD __host__ __device__ __forceinline__
+
+namespace cgh {
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+CGH_HD float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+CGH_HD float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+CGH_HD float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+CGH_HD float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+CGH_HD float2 cneg(float2 a) { return make_float2(-a.x, -a.y); }
+CGH_HD float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// multiply by DIR * i
+template <int DIR>
+CGH_HD float2 rot90(float2 a) {
+  return DIR > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------
+// compile-time unit roots exp(2 pi i m / n): exact integer reduction to an
+// angle in [0, pi/4], then Taylor series in double
+// ---------------------------------------------------------------------------
+struct CDouble {
+  double re, im;
+};
+
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+
+constexpr double sin_series(double x) {
+  double x2 = x * x, t = x, s = x;
+  for (int i = 1; i < 14; ++i) {
+    t *= -x2 / ((2.0 * i) * (2.0 * i + 1.0));
+    s += t;
+  }
+  return s;
+}
+
+constexpr double cos_series(double x) {
+  double x2 = x * x, t = 1.0, s = 1.0;
+  for (int i = 1; i < 14; ++i) {
+    t *= -x2 / ((2.0 * i - 1.0) * (2.0 * i));
+    s += t;
+  }
+  return s;
+}
+
+constexpr CDouble unit_root(long m, long n) {
+  m %= n;
+  if (m < 0) m += n;
+  const long q = (4 * m) / n;      // quarter turns
+  const long r = 4 * m - q * n;    // remainder, angle (pi/2) r / n in [0, pi/2)
+  const bool comp = 2 * r > n;
+  const double a = comp ? (kPiD / 2) * (double)(n - r) / (double)n : (kPiD / 2) * (double)r / (double)n;
+  double c = cos_series(a), s = sin_series(a);
+  if (comp) {
+    const double t = c;
+    c = s;
+    s = t;
+  }
+  CDouble v{c, s};
+  for (long i = 0; i < q; ++i) v = CDouble{-v.im, v.re};
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// compile-time loop
+// ---------------------------------------------------------------------------
+template <int I, int E, class F>
+CGH_HD void static_for(F &&f) {
+  if constexpr (I < E) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, E>(f);
+  }
+}
+
+// x * exp(DIR 2 pi i M / N) with M, N compile-time
+template <int N, int DIR, int M>
+CGH_HD float2 twiddle_const(float2 x) {
+  constexpr int m = ((M % N) + N) % N;
+  if constexpr (m == 0) {
+    return x;
+  } else if constexpr (4 * m == N) {
+    return rot90<DIR>(x);
+  } else if constexpr (2 * m == N) {
+    return cneg(x);
+  } else if constexpr (4 * m == 3 * N) {
+    return rot90<-DIR>(x);
+  } else {
+    constexpr CDouble w = unit_root((long)DIR * m, N);
+    return cmul(x, make_float2((float)w.re, (float)w.im));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// base DFTs: y_k = sum_q x_q exp(DIR 2 pi i q k / R)
+// ---------------------------------------------------------------------------
+template <int R, int DIR>
+struct Dft;
+
+template <int DIR>
+struct Dft<2, DIR> {
+  static CGH_HD void run(float2 *x) {
+    float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <int DIR>
+struct Dft<3, DIR> {
+  static CGH_HD void run(float2 *x) {
+    const float h = 0.86602540378443864676f;  // sin(2 pi / 3)
+    float2 s = cadd(x[1], x[2]), d = csub(x[1], x[2]);
+    float2 t = make_float2(x[0].x - 0.5f * s.x, x[0].y - 0.5f * s.y);
+    float2 r = rot90<DIR>(cscale(d, h));
+    x[0] = cadd(x[0], s);
+    x[1] = cadd(t, r);
+    x[2] = csub(t, r);
+  }
+};
+
+template <int DIR>
+struct Dft<4, DIR> {
+  static CGH_HD void run(float2 *x) {
+    float2 a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+    float2 c = cadd(x[1], x[3]), d = rot90<DIR>(csub(x[1], x[3]));
+    x[0] = cadd(a, c);
+    x[2] = csub(a, c);
+    x[1] = cadd(b, d);
+    x[3] = csub(b, d);
+  }
+};
+
+template <int DIR>
+struct Dft<5, DIR> {
+  static CGH_HD void run(float2 *x) {
+    const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+    const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+    const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+    const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+    float2 s14 = cadd(x[1], x[4]), d14 = csub(x[1], x[4]);
+    float2 s23 = cadd(x[2], x[3]), d23 = csub(x[2], x[3]);
+    float2 x0 = x[0];
+    float2 ta = make_float2(x0.x + c1 * s14.x + c2 * s23.x, x0.y + c1 * s14.y + c2 * s23.y);
+    float2 tb = make_float2(x0.x + c2 * s14.x + c1 * s23.x, x0.y + c2 * s14.y + c1 * s23.y);
+    float2 tc = rot90<DIR>(make_float2(s1 * d14.x + s2 * d23.x, s1 * d14.y + s2 * d23.y));
+    float2 td = rot90<DIR>(make_float2(s2 * d14.x - s1 * d23.x, s2 * d14.y - s1 * d23.y));
+    x[0] = cadd(x0, cadd(s14, s23));
+    x[1] = cadd(ta, tc);
+    x[4] = csub(ta, tc);
+    x[2] = cadd(tb, td);
+    x[3] = csub(tb, td);
+  }
+};
+
+template <int DIR>
+struct Dft<8, DIR> {
+  static CGH_HD void run(float2 *x) {
+    const float r = 0.70710678118654752440f;
+    float2 e[4] = {x[0], x[2], x[4], x[6]};
+    float2 o[4] = {x[1], x[3], x[5], x[7]};
+    Dft<4, DIR>::run(e);
+    Dft<4, DIR>::run(o);
+    // twiddles w8^k = exp(DIR 2 pi i k / 8)
+    float2 o1 = cscale(cadd(o[1], rot90<DIR>(o[1])), r);
+    float2 o2 = rot90<DIR>(o[2]);
+    float2 o3 = cscale(csub(rot90<DIR>(o[3]), o[3]), r);
+    x[0] = cadd(e[0], o[0]);
+    x[4] = csub(e[0], o[0]);
+    x[1] = cadd(e[1], o1);
+    x[5] = csub(e[1], o1);
+    x[2] = cadd(e[2], o2);
+    x[6] = csub(e[2], o2);
+    x[3] = cadd(e[3], o3);
+    x[7] = csub(e[3], o3);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// composite register DFT
+// ---------------------------------------------------------------------------
+constexpr bool is_base_radix(int n) { return n == 2 || n == 3 || n == 4 || n == 5 || n == 8; }
+
+constexpr int base_factor(int n) {
+  // first factor of a composite length: a power-of-two part up to 8 if present,
+  // otherwise 5, then 3
+  if (n % 8 == 0 && n != 8) return 8;
+  if (n % 4 == 0 && n != 4) return 4;
+  if (n % 2 == 0 && n != 2) return 2;
+  if (n % 5 == 0 && n != 5) return 5;
+  return 3;
+}
+
+template <int N, int DIR>
+struct RFft {
+  static CGH_HD void run(float2 *x) {
+    if constexpr (N == 1) {
+    } else if constexpr (is_base_radix(N)) {
+      Dft<N, DIR>::run(x);
+    } else {
+      constexpr int N1 = base_factor(N);
+      constexpr int N2 = N / N1;
+      float2 t[N];
+      static_for<0, N2>([&](auto n2c) {
+        constexpr int n2 = decltype(n2c)::value;
+        float2 s[N1];
+        static_for<0, N1>([&](auto n1c) {
+          constexpr int n1 = decltype(n1c)::value;
+          s[n1] = x[N2 * n1 + n2];
+        });
+        Dft<N1, DIR>::run(s);
+        static_for<0, N1>([&](auto k1c) {
+          constexpr int k1 = decltype(k1c)::value;
+          t[k1 * N2 + n2] = twiddle_const<N, DIR, n2 * k1>(s[k1]);
+        });
+      });
+      static_for<0, N1>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        float2 u[N2];
+        static_for<0, N2>([&](auto n2c) {
+          constexpr int n2 = decltype(n2c)::value;
+          u[n2] = t[k1 * N2 + n2];
+        });
+        RFft<N2, DIR>::run(u);
+        static_for<0, N2>([&](auto k2c) {
+          constexpr int k2 = decltype(k2c)::value;
+          x[k1 + N1 * k2] = u[k2];
+        });
+      });
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// compile-time Stockham plan: radices chosen greedily from the list below
+// (fewest LDS passes with at most 16 values per butterfly)
+// ---------------------------------------------------------------------------
+constexpr int pick_radix(int n) {
+  constexpr int cand[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+  for (int r : cand)
+    if (n % r == 0) return r;
+  return n;
+}
+
+template <int N>
+struct CPlan {
+  static constexpr int stages() {
+    int n = N, s = 0;
+    while (n > 1) {
+      n /= pick_radix(n);
+      ++s;
+    }
+    return s;
+  }
+  static constexpr int radix(int s) {
+    int n = N;
+    for (int i = 0; i < s; ++i) n /= pick_radix(n);
+    return pick_radix(n);
+  }
+  static constexpr int ns(int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= radix(i);
+    return p;
+  }
+};
+
+// One compile-time Stockham stage over B interleaved transforms in LDS
+// (element (r, b) at buf[r * B + b]); stage twiddles exp(DIR 2 pi i q k / (Ns R))
+// read from the full length-N table tw[e] = exp(-2 pi i e / N) in LDS.
+template <int R, int DIR, int B, int T, int N, int NS>
+__device__ __forceinline__ void cstage(float2 *__restrict__ buf, const float2 *__restrict__ tw,
+                                       int tid) {
+  constexpr int NB = N / R;
+  constexpr int ITEMS = NB * B;
+  constexpr int MAXIT = (ITEMS + T - 1) / T;
+  constexpr int TWS = N / (NS * R);
+  float2 v[MAXIT][R];
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    const int i = tid + it * T;
+    if (ITEMS % T == 0 || i < ITEMS) {
+      const int b = i % B, j = i / B;
+      static_for<0, R>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        v[it][q] = buf[(j + q * NB) * B + b];
+      });
+      if constexpr (NS > 1) {
+        const int e = (j % NS) * TWS;
+        static_for<1, R>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          float2 w = tw[q * e];
+          if constexpr (DIR > 0) w.y = -w.y;
+          v[it][q] = cmul(v[it][q], w);
+        });
+      }
+      RFft<R, DIR>::run(v[it]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    const int i = tid + it * T;
+    if (ITEMS % T == 0 || i < ITEMS) {
+      const int b = i % B, j = i / B;
+      const int base = (j / NS) * NS * R + (j % NS);
+      static_for<0, R>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        buf[(base + q * NS) * B + b] = v[it][q];
+      });
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIR, int B, int T, int N, int S = 0>
+__device__ __forceinline__ void cfft(float2 *__restrict__ buf, const float2 *__restrict__ tw,
+                                     int tid) {
+  if constexpr (S < CPlan<N>::stages()) {
+    cstage<CPlan<N>::radix(S), DIR, B, T, N, CPlan<N>::ns(S)>(buf, tw, tid);
+    cfft<DIR, B, T, N, S + 1>(buf, tw, tid);
+  }
+}
+
+}  // namespace cgh
