@@ -412,16 +412,38 @@ __device__ __forceinline__ void load_table(float2 *tw, const float2 *__restrict_
   for (int i = tid; i < N; i += T) tw[i] = src[i];
 }
 
-template <int N, int ROWS, int T>
+// Twiddles of a specialised row pass: the full length-N table when it fits in
+// LDS beside the rows (FULL), otherwise the two-level table.
+template <int N, bool FULL>
+struct RowTw;
+template <int N>
+struct RowTw<N, true> {
+  float2 t[N];
+  template <int T>
+  __device__ void load(const float2 *full, const float2 *, int tid) { load_table<N, T>(t, full, tid); }
+  template <int DIR, int B, int T>
+  __device__ void fft(float2 *buf, int tid) const { cfft<DIR, B, T, N>(buf, t, tid); }
+};
+template <int N>
+struct RowTw<N, false> {
+  TwLds t;
+  template <int T>
+  __device__ void load(const float2 *, const float2 *two, int tid) { load_tw<T>(t, two, tid); }
+  template <int DIR, int B, int T>
+  __device__ void fft(float2 *buf, int tid) const { cfft2<DIR, B, T, N>(buf, t, tid); }
+};
+
+template <int N, int ROWS, int T, bool FULL>
 __global__ __launch_bounds__(T) void k_row_fwd_c(const float2 *__restrict__ field, int H, int W,
                                                  int Wt, const float2 *__restrict__ twf,
+                                                 const float2 *__restrict__ tw2,
                                                  float2 *__restrict__ S) {
   __shared__ float2 sbuf[ROWS * N];
-  __shared__ float2 tw[N];
+  __shared__ RowTw<N, FULL> tw;
   const int tid = threadIdx.x;
   const int groups = (H + ROWS - 1) / ROWS;
   const int c = blockIdx.x / groups, y0 = ROWS * (blockIdx.x % groups);
-  load_table<N, T>(tw, twf, tid);
+  tw.template load<T>(twf, tw2, tid);
   for (int b = 0; b < ROWS; ++b) {
     const bool ok = y0 + b < H;
     const float2 *src = field + ((size_t)c * H + y0 + b) * W;
@@ -429,23 +451,24 @@ __global__ __launch_bounds__(T) void k_row_fwd_c(const float2 *__restrict__ fiel
       sbuf[ROWS * x + b] = (ok && x < W) ? src[x] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  cfft<-1, ROWS, T, N>(sbuf, tw, tid);
+  tw.template fft<-1, ROWS, T>(sbuf, tid);
   store_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
 }
 
-template <int N, int ROWS, int T>
+template <int N, int ROWS, int T, bool FULL>
 __global__ __launch_bounds__(T) void k_row_inv_c(const float2 *__restrict__ S, int H, int W,
                                                  int Wt, const float2 *__restrict__ twf,
+                                                 const float2 *__restrict__ tw2,
                                                  float2 *__restrict__ out) {
   __shared__ float2 sbuf[ROWS * N];
-  __shared__ float2 tw[N];
+  __shared__ RowTw<N, FULL> tw;
   const int tid = threadIdx.x;
   const int groups = (H + ROWS - 1) / ROWS;
   const int c = blockIdx.x / groups, y0 = ROWS * (blockIdx.x % groups);
-  load_table<N, T>(tw, twf, tid);
+  tw.template load<T>(twf, tw2, tid);
   load_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
   __syncthreads();
-  cfft<+1, ROWS, T, N>(sbuf, tw, tid);
+  tw.template fft<+1, ROWS, T>(sbuf, tid);
   for (int b = 0; b < ROWS; ++b) {
     if (y0 + b >= H) break;
     float2 *dst = out + ((size_t)c * H + y0 + b) * W;
@@ -453,22 +476,22 @@ __global__ __launch_bounds__(T) void k_row_inv_c(const float2 *__restrict__ S, i
   }
 }
 
-template <int N, int ROWS, int T>
+template <int N, int ROWS, int T, bool FULL>
 __global__ __launch_bounds__(T) void k_row_loss_c(
     float2 *__restrict__ S, int H, int W, int Wt, const float2 *__restrict__ twf,
-    const float *__restrict__ target, const float *__restrict__ grad_I,
-    float *__restrict__ intensity, float2 *__restrict__ u_out, double *__restrict__ loss_part,
-    float gscale, int make_grad) {
+    const float2 *__restrict__ tw2, const float *__restrict__ target,
+    const float *__restrict__ grad_I, float *__restrict__ intensity, float2 *__restrict__ u_out,
+    double *__restrict__ loss_part, float gscale, int make_grad) {
   __shared__ float2 sbuf[ROWS * N];
-  __shared__ float2 tw[N];
+  __shared__ RowTw<N, FULL> tw;
   __shared__ double red[T / 64];
   const int tid = threadIdx.x;
   const int groups = (H + ROWS - 1) / ROWS;
   const int c = blockIdx.x / groups, y0 = ROWS * (blockIdx.x % groups);
-  load_table<N, T>(tw, twf, tid);
+  tw.template load<T>(twf, tw2, tid);
   load_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
   __syncthreads();
-  cfft<+1, ROWS, T, N>(sbuf, tw, tid);
+  tw.template fft<+1, ROWS, T>(sbuf, tid);
   double acc = 0.0;
   for (int i = tid; i < ROWS * N; i += T) {
     const int b = i / N, x = i - b * N;
@@ -504,14 +527,14 @@ __global__ __launch_bounds__(T) void k_row_loss_c(
   }
   if (make_grad) {
     __syncthreads();
-    cfft<-1, ROWS, T, N>(sbuf, tw, tid);
+    tw.template fft<-1, ROWS, T>(sbuf, tid);
     store_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
   }
 }
 
 // rows per row-pass workgroup (specialised lengths use 4, the runtime path 2)
 static bool row_specialised(int Wp) { return Wp == 3840 || Wp == 512; }
-int row_group_rows(const Ctx &c) { return row_specialised(c.Wp) ? 4 : 2; }
+int row_group_rows(const Ctx &c) { return c.Wp == 512 ? 4 : 2; }
 static int row_blocks(const Ctx &c) {
   const int r = row_group_rows(c);
   return c.C * ((c.H + r - 1) / r);
@@ -520,11 +543,11 @@ static size_t row_lds(const Ctx &c) { return (size_t)2 * c.Wp * sizeof(float2); 
 
 hipError_t launch_row_fwd(const Ctx &c, const float2 *field, hipStream_t s) {
   if (c.Wp == 3840)
-    hipLaunchKernelGGL((k_row_fwd_c<3840, 4, 1024>), dim3(row_blocks(c)), dim3(1024), 0, s,
-                       field, c.H, c.W, c.Wt, c.twf_x, c.spec);
+    hipLaunchKernelGGL((k_row_fwd_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
+                       field, c.H, c.W, c.Wt, c.twf_x, c.tw_x, c.spec);
   else if (c.Wp == 512)
-    hipLaunchKernelGGL((k_row_fwd_c<512, 4, 256>), dim3(row_blocks(c)), dim3(256), 0, s, field,
-                       c.H, c.W, c.Wt, c.twf_x, c.spec);
+    hipLaunchKernelGGL((k_row_fwd_c<512, 4, 256, true>), dim3(row_blocks(c)), dim3(256), 0, s,
+                       field, c.H, c.W, c.Wt, c.twf_x, c.tw_x, c.spec);
   else if (c.Wp <= 4096)
     hipLaunchKernelGGL(k_row_fwd<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
                        field, c.H, c.W, c.Wt, c.plan_x, c.tw_x, c.spec);
@@ -536,11 +559,11 @@ hipError_t launch_row_fwd(const Ctx &c, const float2 *field, hipStream_t s) {
 
 hipError_t launch_row_inv(const Ctx &c, float2 *out, hipStream_t s) {
   if (c.Wp == 3840)
-    hipLaunchKernelGGL((k_row_inv_c<3840, 4, 1024>), dim3(row_blocks(c)), dim3(1024), 0, s,
-                       c.spec, c.H, c.W, c.Wt, c.twf_x, out);
+    hipLaunchKernelGGL((k_row_inv_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
+                       c.spec, c.H, c.W, c.Wt, c.twf_x, c.tw_x, out);
   else if (c.Wp == 512)
-    hipLaunchKernelGGL((k_row_inv_c<512, 4, 256>), dim3(row_blocks(c)), dim3(256), 0, s, c.spec,
-                       c.H, c.W, c.Wt, c.twf_x, out);
+    hipLaunchKernelGGL((k_row_inv_c<512, 4, 256, true>), dim3(row_blocks(c)), dim3(256), 0, s,
+                       c.spec, c.H, c.W, c.Wt, c.twf_x, c.tw_x, out);
   else if (c.Wp <= 4096)
     hipLaunchKernelGGL(k_row_inv<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
                        c.spec, c.H, c.W, c.Wt, c.plan_x, c.tw_x, out);
@@ -555,13 +578,13 @@ hipError_t launch_row_loss(const Ctx &c, const float *target, const float *grad_
   const double M = (double)c.L * c.C * c.H * c.W;
   const float gscale = (float)(4.0 / M);
   if (c.Wp == 3840)
-    hipLaunchKernelGGL((k_row_loss_c<3840, 4, 1024>), dim3(row_blocks(c)), dim3(1024), 0, s,
-                       c.spec, c.H, c.W, c.Wt, c.twf_x, target, grad_intensity, intensity, u_out,
-                       c.loss_part, gscale, make_grad);
+    hipLaunchKernelGGL((k_row_loss_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
+                       c.spec, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, intensity,
+                       u_out, c.loss_part, gscale, make_grad);
   else if (c.Wp == 512)
-    hipLaunchKernelGGL((k_row_loss_c<512, 4, 256>), dim3(row_blocks(c)), dim3(256), 0, s,
-                       c.spec, c.H, c.W, c.Wt, c.twf_x, target, grad_intensity, intensity, u_out,
-                       c.loss_part, gscale, make_grad);
+    hipLaunchKernelGGL((k_row_loss_c<512, 4, 256, true>), dim3(row_blocks(c)), dim3(256), 0, s,
+                       c.spec, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, intensity,
+                       u_out, c.loss_part, gscale, make_grad);
   else if (c.Wp <= 4096)
     hipLaunchKernelGGL(k_row_loss<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
                        c.spec, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity,

@@ -251,7 +251,9 @@ struct RFft {
 
 // ---------------------------------------------------------------------------
 // compile-time Stockham plan: radices chosen greedily from the list below
-// (fewest LDS passes with at most 16 values per butterfly)
+// (fewest LDS passes with at most 16 values per butterfly), then ordered odd
+// radices first: the first stage writes at stride R, and an odd stride
+// spreads those writes over the LDS banks where a power of two would not.
 // ---------------------------------------------------------------------------
 constexpr int pick_radix(int n) {
   constexpr int cand[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
@@ -262,6 +264,11 @@ constexpr int pick_radix(int n) {
 
 template <int N>
 struct CPlan {
+  static constexpr int greedy(int s) {
+    int n = N;
+    for (int i = 0; i < s; ++i) n /= pick_radix(n);
+    return pick_radix(n);
+  }
   static constexpr int stages() {
     int n = N, s = 0;
     while (n > 1) {
@@ -270,10 +277,14 @@ struct CPlan {
     }
     return s;
   }
+  // s-th radix after moving the odd radices (in greedy order) to the front
   static constexpr int radix(int s) {
-    int n = N;
-    for (int i = 0; i < s; ++i) n /= pick_radix(n);
-    return pick_radix(n);
+    int k = 0;
+    for (int i = 0; i < stages(); ++i)
+      if (greedy(i) % 2 == 1 && k++ == s) return greedy(i);
+    for (int i = 0; i < stages(); ++i)
+      if (greedy(i) % 2 == 0 && k++ == s) return greedy(i);
+    return 1;
   }
   static constexpr int ns(int s) {
     int p = 1;
@@ -328,6 +339,61 @@ __device__ __forceinline__ void cstage(float2 *__restrict__ buf, const float2 *_
     }
   }
   __syncthreads();
+}
+
+// Same stage with twiddles from a two-level table (hi[e >> 6] lo[e & 63]),
+// for lengths whose full table does not fit beside the data.
+template <int R, int DIR, int B, int T, int N, int NS, class TW>
+__device__ __forceinline__ void cstage2(float2 *__restrict__ buf, const TW &tw, int tid) {
+  constexpr int NB = N / R;
+  constexpr int ITEMS = NB * B;
+  constexpr int MAXIT = (ITEMS + T - 1) / T;
+  constexpr int TWS = N / (NS * R);
+  float2 v[MAXIT][R];
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    const int i = tid + it * T;
+    if (ITEMS % T == 0 || i < ITEMS) {
+      const int b = i % B, j = i / B;
+      static_for<0, R>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        v[it][q] = buf[(j + q * NB) * B + b];
+      });
+      if constexpr (NS > 1) {
+        const int e = (j % NS) * TWS;
+        static_for<1, R>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          const int eq = q * e;
+          float2 w = cmul(tw.hi[eq >> 6], tw.lo[eq & 63]);
+          if constexpr (DIR > 0) w.y = -w.y;
+          v[it][q] = cmul(v[it][q], w);
+        });
+      }
+      RFft<R, DIR>::run(v[it]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    const int i = tid + it * T;
+    if (ITEMS % T == 0 || i < ITEMS) {
+      const int b = i % B, j = i / B;
+      const int base = (j / NS) * NS * R + (j % NS);
+      static_for<0, R>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        buf[(base + q * NS) * B + b] = v[it][q];
+      });
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIR, int B, int T, int N, class TW, int S = 0>
+__device__ __forceinline__ void cfft2(float2 *__restrict__ buf, const TW &tw, int tid) {
+  if constexpr (S < CPlan<N>::stages()) {
+    cstage2<CPlan<N>::radix(S), DIR, B, T, N, CPlan<N>::ns(S)>(buf, tw, tid);
+    cfft2<DIR, B, T, N, TW, S + 1>(buf, tw, tid);
+  }
 }
 
 template <int DIR, int B, int T, int N, int S = 0>
