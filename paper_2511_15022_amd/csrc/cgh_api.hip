@@ -155,7 +155,7 @@ size_t carve(Ctx *c, char *base) {
   c->spec = (float2 *)take(sizeof(float2) * c->C * (size_t)c->Wt * c->H * 8);
   c->field_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
   c->gfield_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
-  c->rec = (float *)take(sizeof(float) * c->rec_stride * (N ? N : 1));
+  c->rec = (float *)take(sizeof(float) * c->rec_stride * (N + 1));
   c->rect = (uint2 *)take(sizeof(uint2) * (N ? N : 1));
   c->counts = (uint32_t *)take(sizeof(uint32_t) * (N ? N : 1));
   c->offsets = (uint32_t *)take(sizeof(uint32_t) * (N + 1));
@@ -217,6 +217,7 @@ cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_b
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_x, c.Wp, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_m, c.plan_m.n, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, s), "transfer function");
+  CGH_CHECK_LAUNCH(cgh::launch_zero_record(c, s), "zero record");
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return device_fail(e, "cgh_create");
   cgh_ctx *h = new (std::nothrow) cgh_ctx;

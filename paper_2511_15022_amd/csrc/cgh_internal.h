@@ -76,7 +76,7 @@ struct Ctx {
   float2 *spec;                     // [C][Wt][H][8] column-tiled propagation buffer
   float2 *field_tmp;                // [C][H][W]
   float2 *gfield_tmp;               // [C][H][W]
-  float *rec;                       // [max_gaussians][rec_stride]
+  float *rec;                       // [max_gaussians + 1][rec_stride]; the last is all zeros
   uint2 *rect;                      // [max_gaussians] tile rectangles (x0|x1<<16, y0|y1<<16)
   uint32_t *counts;                 // [max_gaussians]
   uint32_t *offsets;                // [max_gaussians + 1]
@@ -110,6 +110,7 @@ hipError_t launch_row_loss(const Ctx &c, const float *target, const float *grad_
 hipError_t launch_loss_finalize(const Ctx &c, double *loss, hipStream_t s);
 
 hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s);
+hipError_t launch_zero_record(const Ctx &c, hipStream_t s);
 hipError_t launch_binning(Ctx &c, int n, hipStream_t s);  // sets c.sorted
 hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s);
 hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStream_t s);

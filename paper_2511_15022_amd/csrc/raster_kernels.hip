@@ -341,6 +341,18 @@ __global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__re
   if (i + 1 == count || keys[i + 1] != k) ranges[k].y = i + 1;
 }
 
+// the record after the last Gaussian slot: all zeros (zero amplitude), used to
+// pad per-wave lists in the forward rasterizer
+__global__ void k_zero_record(float *rec, int slot, int rs) {
+  if ((int)threadIdx.x < rs) rec[(size_t)slot * rs + threadIdx.x] = 0.f;
+}
+
+hipError_t launch_zero_record(const Ctx &c, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_record, dim3(1), dim3(64), 0, s, c.rec, c.cfg.max_gaussians,
+                     c.rec_stride);
+  return hipGetLastError();
+}
+
 __global__ void k_zero_u32(uint32_t *p, int len) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) p[i] = 0u;
@@ -379,70 +391,92 @@ hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
 // ----------------------------------------------------------------------------
 // Forward: U_c(p) = sum over the tile's Gaussians with log2 G(p) >= -k^2/2 log2 e
 // of G(p) (alpha c cos phi + j alpha c sin phi).
+// Each wave owns an 8x8 sub-block: it culls the LDS-staged records against its
+// sub-block, writes the survivors' slots to a per-wave list, and walks the list
+// two records at a time (both loaded before use, hiding LDS latency).  Slot
+// kBatch holds a record with zero amplitude that pads the list to even length.
 // ----------------------------------------------------------------------------
+constexpr int kBatch = 256;
+
+template <int C>
+__device__ __forceinline__ void accumulate(const float *r, int X0, int Y0, float flx, float fly,
+                                           float thr, float *ar, float *ai) {
+  const float offx = (float)(X0 - __float_as_int(r[R_MIX])) - r[R_MFX];
+  const float offy = (float)(Y0 - __float_as_int(r[R_MIY])) - r[R_MFY];
+  const float dx = flx + offx, dy = fly + offy;
+  const float p2 = fmaf(dx, fmaf(r[R_A], dx, r[R_B] * dy), r[R_C] * dy * dy);
+  const float G = p2 >= thr ? __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2)) : 0.f;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    ar[c] = fmaf(G, r[R_AMP + 2 * c], ar[c]);
+    ai[c] = fmaf(G, r[R_AMP + 2 * c + 1], ai[c]);
+  }
+}
+
+// zero_id: index of an all-zero record (after the last Gaussian slot)
 template <int C>
 __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ rec,
                                                     const uint32_t *__restrict__ vals,
                                                     const uint2 *__restrict__ ranges, int W,
                                                     int H, int tiles_x, float thr,
+                                                    uint32_t zero_id,
                                                     float2 *__restrict__ field) {
   constexpr int RS = rec_stride_c(C);
-  __shared__ float4 srec[256 * RS / 4];
-  const float *sr = reinterpret_cast<const float *>(srec);
+  __shared__ uint32_t list[4][kBatch + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int X0 = tx * kTile + (wave & 1) * 8, Y0 = ty * kTile + (wave >> 1) * 8;
   const int lx = lane & 7, ly = lane >> 3;
   const float flx = (float)lx, fly = (float)ly;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   float ar[C], ai[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) { ar[c] = 0.f; ai[c] = 0.f; }
   const uint2 rg = ranges[tile];
-  for (uint32_t base = rg.x; base < rg.y; base += 256) {
-    const int cnt = (int)min(256u, rg.y - base);
-    if (tid < cnt) {
-      const uint32_t g = vals[base + tid];
-      const float4 *src = reinterpret_cast<const float4 *>(rec + (size_t)g * RS);
-#pragma unroll
-      for (int i = 0; i < RS / 4; ++i) srec[tid * (RS / 4) + i] = src[i];
-    }
-    __syncthreads();
-    uint64_t mask[4];
-#pragma unroll
-    for (int qd = 0; qd < 4; ++qd) {
+  for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
+    const int cnt = (int)min((uint32_t)kBatch, rg.y - base);
+    // cull the batch against this wave's sub-block (one Gaussian per lane per
+    // round); the ids of the survivors go to list[wave], in list order
+    int n = 0;
+    for (int qd = 0; qd < (cnt + 63) / 64; ++qd) {
       const int idx = qd * 64 + lane;
       bool hit = false;
+      uint32_t g = 0;
       if (idx < cnt) {
-        const float *s = sr + idx * RS;
-        const float ox = (float)(__float_as_int(s[R_MIX]) - X0) + s[R_MFX];
-        const float oy = (float)(__float_as_int(s[R_MIY]) - Y0) + s[R_MFY];
-        const float rx = s[R_RX] + 0.01f, ry = s[R_RY] + 0.01f;
+        g = vals[base + idx];
+        const float4 r0 = reinterpret_cast<const float4 *>(rec + (size_t)g * RS)[0];
+        const float4 r1 = reinterpret_cast<const float4 *>(rec + (size_t)g * RS)[1];
+        // r0 = (mix, miy, mfx, mfy), r1 = (a, b, c, rx); ry is element 8
+        const float ryv = rec[(size_t)g * RS + R_RY];
+        const float ox = (float)(__float_as_int(r0.x) - X0) + r0.z;
+        const float oy = (float)(__float_as_int(r0.y) - Y0) + r0.w;
+        const float rx = r1.w + 0.01f, ry = ryv + 0.01f;
         hit = (ox + rx >= 0.f) && (ox - rx <= 7.f) && (oy + ry >= 0.f) && (oy - ry <= 7.f);
       }
-      mask[qd] = __ballot(hit);
+      const uint64_t m = __ballot(hit);
+      if (hit) list[wave][n + __popcll(m & lt)] = g;
+      n += __popcll(m);
     }
+    if (lane == 0) list[wave][n] = zero_id;  // pad to even length (zero-amplitude record)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // walk the list two at a time: the record addresses are wave-uniform, so
+    // the records come in through scalar loads and feed the VALU as scalar
+    // operands; both pairs of loads are issued before either is used
+    for (int k = 0; k < n; k += 2) {
+      const uint32_t g0 = __builtin_amdgcn_readfirstlane(list[wave][k]);
+      const uint32_t g1 = __builtin_amdgcn_readfirstlane(list[wave][k + 1]);
+      const float *s0 = rec + (size_t)g0 * RS;
+      const float *s1 = rec + (size_t)g1 * RS;
+      float r0[R_AMP + 2 * C], r1[R_AMP + 2 * C];
 #pragma unroll
-    for (int qd = 0; qd < 4; ++qd) {
-      uint64_t m = mask[qd];
-      while (m) {
-        const int b = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        const float *s = sr + (qd * 64 + b) * RS;
-        // offset of the sub-block origin from the mean; then per-lane d = l + off
-        const float offx = (float)(X0 - __float_as_int(s[R_MIX])) - s[R_MFX];
-        const float offy = (float)(Y0 - __float_as_int(s[R_MIY])) - s[R_MFY];
-        const float dx = flx + offx, dy = fly + offy;
-        const float p2 = fmaf(dx, fmaf(s[R_A], dx, s[R_B] * dy), s[R_C] * dy * dy);
-        const float G = p2 >= thr ? __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2)) : 0.f;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          ar[c] = fmaf(G, s[R_AMP + 2 * c], ar[c]);
-          ai[c] = fmaf(G, s[R_AMP + 2 * c + 1], ai[c]);
-        }
-      }
+      for (int i = 0; i < R_AMP + 2 * C; ++i) { r0[i] = s0[i]; r1[i] = s1[i]; }
+      accumulate<C>(r0, X0, Y0, flx, fly, thr, ar, ai);
+      accumulate<C>(r1, X0, Y0, flx, fly, thr, ar, ai);
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
   }
   const int px = X0 + lx, py = Y0 + ly;
   if (px < W && py < H) {
@@ -459,13 +493,14 @@ static float support_threshold(float k) {
 
 hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
   const float thr = support_threshold(c.cfg.support_sigma);
+  const uint32_t zid = (uint32_t)c.cfg.max_gaussians;  // the zero record
   const uint32_t *vals = c.vals[c.sorted];
   dim3 grid(c.num_tiles), block(256);
   switch (c.C) {
-    case 1: hipLaunchKernelGGL(k_raster_fwd<1>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, field); break;
-    case 2: hipLaunchKernelGGL(k_raster_fwd<2>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, field); break;
-    case 3: hipLaunchKernelGGL(k_raster_fwd<3>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, field); break;
-    default: hipLaunchKernelGGL(k_raster_fwd<4>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, field); break;
+    case 1: hipLaunchKernelGGL(k_raster_fwd<1>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, zid, field); break;
+    case 2: hipLaunchKernelGGL(k_raster_fwd<2>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, zid, field); break;
+    case 3: hipLaunchKernelGGL(k_raster_fwd<3>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, zid, field); break;
+    default: hipLaunchKernelGGL(k_raster_fwd<4>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, zid, field); break;
   }
   return hipGetLastError();
 }
@@ -478,68 +513,182 @@ hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
 //   S[2C] += w dx, S[2C+1] += w dy                (-> dL/dmean)
 //   S[2C+2] += w dx^2, S[2C+3] += w dx dy, S[2C+4] += w dy^2   (-> dL/dSigma^{-1})
 // with dx, dy = pixel - mean.  The clamped exponent has zero derivative.
+//
+// Work balance.  One wave owns a tile and takes its pair list in batches of
+// 64.  The pixel boxes of a batch are laid end to end (an exclusive scan of the
+// box areas) and the concatenated pixel range is cut into 64 equal contiguous
+// pieces, one per lane, so every lane walks the same number of pixels whatever
+// the mix of box sizes.  A pair that lies inside one lane's piece is written
+// straight to its partial slot.  A pair cut by piece boundaries is finished by
+// the lane where it starts: that lane adds, in lane order, the first part of
+// each following lane the pair reaches (shuffled across the wave).  The cut
+// points depend only on the box areas, so the result is bitwise reproducible.
 // ----------------------------------------------------------------------------
+constexpr int kAdjBatch = 64;
+
+// per-pair quantities kept in LDS for the walk (floats):
+//   0-3 offx0, offx1, offy0, offy1 (sub-block origin - floor(mean) - frac(mean))
+//   4-6 a, b, c;  7.. amplitude (2C);  then box, start, slot (int bits)
+template <int C> struct AdjQ {
+  static constexpr int AMP = 7;
+  static constexpr int BOX = 7 + 2 * C, START = BOX + 1, SLOT = BOX + 2;
+  static constexpr int N = ((SLOT + 1) + 3) & ~3;
+};
+
 template <int C>
-__global__ __launch_bounds__(256) void k_raster_adj(
+__global__ __launch_bounds__(64) void k_raster_adj(
     const float *__restrict__ rec, const uint32_t *__restrict__ vals,
     const uint2 *__restrict__ ranges, const uint2 *__restrict__ rect,
     const uint32_t *__restrict__ offsets, int W, int H, int tiles_x, float thr,
     const float2 *__restrict__ gfield, int64_t cap, float *__restrict__ partials) {
   constexpr int RS = rec_stride_c(C);
   constexpr int PS = part_stride_c(C);
-  __shared__ float2 sg[C][kTile * kTile];
-  const int tid = threadIdx.x;
+  constexpr int NS = 2 * C + 5;
+  using Q = AdjQ<C>;
+  __shared__ float2 sg[kTile * kTile][C];
+  __shared__ float4 sq4[kAdjBatch * Q::N / 4];
+  float *sq = reinterpret_cast<float *>(sq4);
+  const int lane = threadIdx.x;
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int X0 = tx * kTile, Y0 = ty * kTile;
-  for (int i = tid; i < C * kTile * kTile; i += 256) {
+  for (int i = lane; i < C * kTile * kTile; i += 64) {
     const int c = i / (kTile * kTile), p = i % (kTile * kTile);
     const int x = X0 + (p % kTile), y = Y0 + (p / kTile);
-    sg[c][p] = (x < W && y < H) ? gfield[((size_t)c * H + y) * W + x] : make_float2(0.f, 0.f);
+    sg[p][c] = (x < W && y < H) ? gfield[((size_t)c * H + y) * W + x] : make_float2(0.f, 0.f);
   }
-  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint2 rg = ranges[tile];
-  for (uint32_t i = rg.x + tid; i < rg.y; i += 256) {
-    const uint32_t g = vals[i];
+  for (uint32_t base = rg.x; base < rg.y; base += kAdjBatch) {
+    // ---- set-up: one pair per lane --------------------------------------
+    const int cnt = (int)min((uint32_t)kAdjBatch, rg.y - base);
+    int area = 0;
+    int xa = 0, xb = -1, ya = 0, yb = -1;
+    uint32_t slot = 0xffffffffu;
     float r[RS];
-    const float4 *src = reinterpret_cast<const float4 *>(rec + (size_t)g * RS);
 #pragma unroll
-    for (int k = 0; k < RS / 4; ++k) {
-      const float4 v = src[k];
-      r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
+    for (int k = 0; k < RS; ++k) r[k] = 0.f;
+    if (lane < cnt) {
+      const uint32_t g = vals[base + lane];
+      const float4 *src = reinterpret_cast<const float4 *>(rec + (size_t)g * RS);
+#pragma unroll
+      for (int k = 0; k < RS / 4; ++k) {
+        const float4 v = src[k];
+        r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
+      }
+      const int mix = __float_as_int(r[R_MIX]), miy = __float_as_int(r[R_MIY]);
+      // pixel box of the support inside this tile (local coordinates 0..15)
+      const float rx = fminf(r[R_RX], 1e6f) + 0.01f, ry = fminf(r[R_RY], 1e6f) + 0.01f;
+      const float cx = (float)(mix - X0) + r[R_MFX], cy = (float)(miy - Y0) + r[R_MFY];
+      xa = max(0, (int)ceilf(fmaxf(cx - rx, -1.f)));
+      xb = min(kTile - 1, (int)floorf(fminf(cx + rx, (float)kTile)));
+      ya = max(0, (int)ceilf(fmaxf(cy - ry, -1.f)));
+      yb = min(kTile - 1, (int)floorf(fminf(cy + ry, (float)kTile)));
+      if (xb >= xa && yb >= ya) area = (xb - xa + 1) * (yb - ya + 1);
+      const uint2 rc = rect[g];
+      const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
+      const uint64_t pos = (uint64_t)offsets[g] + (uint64_t)(ty - (int)ty0) * (tx1 - tx0 + 1) +
+                           (uint64_t)(tx - (int)tx0);
+      if ((int64_t)pos < cap) slot = (uint32_t)pos;
+      if (area == 0 && slot != 0xffffffffu) {  // nothing of the support in this tile
+        float4 *dst = reinterpret_cast<float4 *>(partials + (size_t)slot * PS);
+#pragma unroll
+        for (int k = 0; k < PS / 4; ++k) dst[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     }
-    const int mix = __float_as_int(r[R_MIX]), miy = __float_as_int(r[R_MIY]);
-    const float mfx = r[R_MFX], mfy = r[R_MFY];
-    // pixel box of the support inside this tile (local coordinates 0..15)
-    const float rx = fminf(r[R_RX], 1e6f) + 0.01f, ry = fminf(r[R_RY], 1e6f) + 0.01f;
-    const float cx = (float)(mix - X0) + mfx, cy = (float)(miy - Y0) + mfy;
-    const int xa = max(0, (int)ceilf(fmaxf(cx - rx, -1.f)));
-    const int xb = min(kTile - 1, (int)floorf(fminf(cx + rx, (float)kTile)));
-    const int ya = max(0, (int)ceilf(fmaxf(cy - ry, -1.f)));
-    const int yb = min(kTile - 1, (int)floorf(fminf(cy + ry, (float)kTile)));
-    float S[2 * C + 5];
+    // exclusive scan of the areas (lane order); the non-empty pairs are
+    // compacted to the front of the LDS table in the same order
+    int incl = area;
 #pragma unroll
-    for (int k = 0; k < 2 * C + 5; ++k) S[k] = 0.f;
-    const float a = r[R_A], b = r[R_B], cc = r[R_C];
-    // same FP32 operations as the forward: d = (pixel offset in its 8x8
-    // sub-block) + ((sub-block origin - floor(mean)) - frac(mean))
-    const float offx0 = (float)(X0 - mix) - mfx, offx1 = (float)(X0 + 8 - mix) - mfx;
-    const float offy0 = (float)(Y0 - miy) - mfy, offy1 = (float)(Y0 + 8 - miy) - mfy;
-    for (int ly = ya; ly <= yb; ++ly) {
-      const float dy = (float)(ly & 7) + (ly < 8 ? offy0 : offy1);
-      for (int lx = xa; lx <= xb; ++lx) {
-        const float dx = (float)(lx & 7) + (lx < 8 ? offx0 : offx1);
-        const float p2 = fmaf(dx, fmaf(a, dx, b * dy), cc * dy * dy);
-        if (p2 >= thr) {
-          const float G = __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2));
-          const int p = ly * kTile + lx;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    const int start = incl - area;
+    const int total = __shfl(incl, 63);
+    const uint64_t nem = __ballot(area > 0);
+    const int np = __popcll(nem);
+    if (area > 0) {
+      const int j = __popcll(nem & lt);
+      float *q = sq + j * Q::N;
+      const int mix = __float_as_int(r[R_MIX]), miy = __float_as_int(r[R_MIY]);
+      // same FP32 operations as the forward: d = (pixel offset in its 8x8
+      // sub-block) + ((sub-block origin - floor(mean)) - frac(mean))
+      q[0] = (float)(X0 - mix) - r[R_MFX];
+      q[1] = (float)(X0 + 8 - mix) - r[R_MFX];
+      q[2] = (float)(Y0 - miy) - r[R_MFY];
+      q[3] = (float)(Y0 + 8 - miy) - r[R_MFY];
+      q[4] = r[R_A]; q[5] = r[R_B]; q[6] = r[R_C];
+#pragma unroll
+      for (int k = 0; k < 2 * C; ++k) q[Q::AMP + k] = r[R_AMP + k];
+      q[Q::BOX] = __int_as_float(xa | (xb << 8) | (ya << 16) | (yb << 24));
+      q[Q::START] = __int_as_float(start);
+      q[Q::SLOT] = __uint_as_float(slot);
+    }
+    __syncthreads();
+    if (total > 0) {
+      // ---- walk: this lane owns pixels [f0, f1) of the concatenated boxes --
+      const int chunk = (total + 63) / 64;
+      const int f0 = min(total, lane * chunk), f1 = min(total, f0 + chunk);
+      // first pair whose box contains f0: the last j with start_j <= f0
+      int j = 0;
+      for (int step = 32; step > 0; step >>= 1) {
+        const int t = j + step;
+        if (t < np && __float_as_int(sq[t * Q::N + Q::START]) <= f0) j = t;
+      }
+      float offx0, offx1, offy0, offy1, qa, qb, qc, amp[2 * C];
+      int bxa, bxb, rem, lx, ly, sj, span = 0;
+      auto load_pair = [&](int jj) {
+        const float *q = sq + jj * Q::N;
+        offx0 = q[0]; offx1 = q[1]; offy0 = q[2]; offy1 = q[3];
+        qa = q[4]; qb = q[5]; qc = q[6];
+#pragma unroll
+        for (int k = 0; k < 2 * C; ++k) amp[k] = q[Q::AMP + k];
+        const int bx = __float_as_int(q[Q::BOX]);
+        bxa = bx & 0xff; bxb = (bx >> 8) & 0xff;
+        const int bya = (bx >> 16) & 0xff, byb = (bx >> 24) & 0xff;
+        sj = __float_as_int(q[Q::START]);
+        rem = (bxb - bxa + 1) * (byb - bya + 1);
+        lx = bxa; ly = bya;
+      };
+      auto flush_global = [&](int jj, const float *v) {
+        const uint32_t sl = __float_as_uint(sq[jj * Q::N + Q::SLOT]);
+        if (sl != 0xffffffffu) {
+          float4 *dst = reinterpret_cast<float4 *>(partials + (size_t)sl * PS);
+          float o[PS];
+#pragma unroll
+          for (int k = 0; k < PS; ++k) o[k] = k < NS ? v[k] : 0.f;
+#pragma unroll
+          for (int k = 0; k < PS / 4; ++k)
+            dst[k] = make_float4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+        }
+      };
+      float S[NS], F[NS];  // running sums; F: the first part when it began before f0
+#pragma unroll
+      for (int k = 0; k < NS; ++k) { S[k] = 0.f; F[k] = 0.f; }
+      if (f0 < f1) {
+        load_pair(j);
+        bool head = sj < f0;
+        {
+          const int o = f0 - sj, wb = bxb - bxa + 1;
+          const int oy = o / wb;
+          ly += oy;
+          lx = bxa + (o - oy * wb);
+          rem -= o;
+        }
+        for (int f = f0; f < f1; ++f) {
+          const float dy = (float)(ly & 7) + (ly < 8 ? offy0 : offy1);
+          const float dx = (float)(lx & 7) + (lx < 8 ? offx0 : offx1);
+          const float p2 = fmaf(dx, fmaf(qa, dx, qb * dy), qc * dy * dy);
+          const float G = p2 >= thr ? __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2)) : 0.f;
+          const float2 *gv = sg[ly * kTile + lx];
           float gp = 0.f;
 #pragma unroll
           for (int c = 0; c < C; ++c) {
-            const float2 gv = sg[c][p];
-            gp = fmaf(gv.x, r[R_AMP + 2 * c], fmaf(gv.y, r[R_AMP + 2 * c + 1], gp));
-            S[2 * c] = fmaf(G, gv.x, S[2 * c]);
-            S[2 * c + 1] = fmaf(G, gv.y, S[2 * c + 1]);
+            const float2 v = gv[c];
+            gp = fmaf(v.x, amp[2 * c], fmaf(v.y, amp[2 * c + 1], gp));
+            S[2 * c] = fmaf(G, v.x, S[2 * c]);
+            S[2 * c + 1] = fmaf(G, v.y, S[2 * c + 1]);
           }
           const float w = p2 > kPowerFloor2 ? gp * G : 0.f;
           const float wx = w * dx, wy = w * dy;
@@ -548,21 +697,48 @@ __global__ __launch_bounds__(256) void k_raster_adj(
           S[2 * C + 2] = fmaf(wx, dx, S[2 * C + 2]);
           S[2 * C + 3] = fmaf(wx, dy, S[2 * C + 3]);
           S[2 * C + 4] = fmaf(wy, dy, S[2 * C + 4]);
+          if (++lx > bxb) { lx = bxa; ++ly; }
+          if (--rem == 0) {
+            // the pair ends inside this lane's piece
+            if (head) {
+#pragma unroll
+              for (int k = 0; k < NS; ++k) F[k] = S[k];
+            } else {
+              flush_global(j, S);
+            }
+#pragma unroll
+            for (int k = 0; k < NS; ++k) S[k] = 0.f;
+            head = false;
+            if (f + 1 < f1) load_pair(++j);
+          }
+        }
+        if (rem != 0) {  // the current pair continues into the next lane's piece
+          if (head) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) F[k] = S[k];
+          } else {
+            // this lane started the pair and finishes it: it reaches the
+            // lanes lane+1 .. (last pixel of the pair) / chunk
+            const float *q = sq + j * Q::N;
+            const int bx = __float_as_int(q[Q::BOX]);
+            const int a = (((bx >> 8) & 0xff) - (bx & 0xff) + 1) *
+                          (((bx >> 24) & 0xff) - ((bx >> 16) & 0xff) + 1);
+            span = (sj + a - 1) / chunk - lane;
+          }
         }
       }
-    }
-    const uint2 rc = rect[g];
-    const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
-    const uint64_t pos = (uint64_t)offsets[g] + (uint64_t)(ty - (int)ty0) * (tx1 - tx0 + 1) +
-                         (uint64_t)(tx - (int)tx0);
-    if ((int64_t)pos < cap) {
-      float4 *dst = reinterpret_cast<float4 *>(partials + pos * PS);
-      float o[PS];
+      // ---- pairs cut by piece boundaries: add the parts in lane order ------
+      for (int d = 1; __any(d <= span); ++d) {
+        const int src = min(63, lane + d);
 #pragma unroll
-      for (int k = 0; k < PS; ++k) o[k] = k < 2 * C + 5 ? S[k] : 0.f;
-#pragma unroll
-      for (int k = 0; k < PS / 4; ++k) dst[k] = make_float4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+        for (int k = 0; k < NS; ++k) {
+          const float v = __shfl(F[k], src);
+          if (d <= span) S[k] += v;
+        }
+      }
+      if (span > 0) flush_global(j, S);
     }
+    __syncthreads();
   }
 }
 
@@ -667,7 +843,7 @@ __global__ __launch_bounds__(256) void k_preprocess_adj(
 hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStream_t s) {
   const float thr = support_threshold(c.cfg.support_sigma);
   const uint32_t *vals = c.vals[c.sorted];
-  dim3 grid(c.num_tiles), block(256);
+  dim3 grid(c.num_tiles), block(64);
   switch (c.C) {
     case 1: hipLaunchKernelGGL(k_raster_adj<1>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
     case 2: hipLaunchKernelGGL(k_raster_adj<2>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
