@@ -78,7 +78,7 @@ typedef struct {
                                  /* into 2, 3, 5 and be <= 8192 (0 = 2H, 2W)               */
   double pitch_m;                /* pixel pitch (square pixels), metres                   */
   double wavelength_m[CGH_MAX_CHANNELS]; /* lambda per channel, metres                   */
-  int32_t num_planes;            /* L: propagation distances (this build: 1)              */
+  int32_t num_planes;            /* L: propagation distances, 1 <= L <= CGH_MAX_PLANES    */
   double z_m[CGH_MAX_PLANES];    /* propagation distance per plane, metres (any sign)     */
   float support_sigma;           /* k: a Gaussian covers the pixels with Mahalanobis      */
                                  /* distance q <= k^2 (k <= 0: every pixel)               */

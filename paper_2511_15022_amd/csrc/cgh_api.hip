@@ -47,9 +47,6 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
   if (f.num_planes < 1 || f.num_planes > CGH_MAX_PLANES)
     return fail(CGH_ERR_INVALID_ARG, "num_planes must be in [1, %d] (got %d)", CGH_MAX_PLANES,
                 f.num_planes);
-  if (f.num_planes != 1)
-    return fail(CGH_ERR_UNSUPPORTED, "this build propagates to one plane (num_planes = %d)",
-                f.num_planes);
   const int Hp = f.pad_height ? f.pad_height : 2 * f.height;
   const int Wp = f.pad_width ? f.pad_width : 2 * f.width;
   if (Hp < f.height || Wp < f.width)
@@ -104,6 +101,7 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
   c->part_stride = partial_stride(c->C);
   c->last_n = -1;
   c->sorted = 0;
+  c->num_cu = 1;
   c->prof_class = 0;
   c->prof_n = 0;
   c->prof_ev = nullptr;
@@ -121,13 +119,11 @@ struct ProfScope {
   bool on;
   ProfScope(cgh::Ctx &c_, int cls, hipStream_t s_) : c(c_), s(s_) {
     on = c.prof_ev && c.prof_class == cls && c.prof_n < cgh::kMaxProf;
-    if (on) hipEventRecord(c.prof_ev[2 * c.prof_n], s);
+    // a launch whose events cannot be recorded is simply not timed
+    if (on && hipEventRecord(c.prof_ev[2 * c.prof_n], s) != hipSuccess) on = false;
   }
   ~ProfScope() {
-    if (on) {
-      hipEventRecord(c.prof_ev[2 * c.prof_n + 1], s);
-      ++c.prof_n;
-    }
+    if (on && hipEventRecord(c.prof_ev[2 * c.prof_n + 1], s) == hipSuccess) ++c.prof_n;
   }
 };
 
@@ -152,7 +148,12 @@ size_t carve(Ctx *c, char *base) {
   c->twf_x = (float2 *)take(sizeof(float2) * c->Wp);
   c->twf_m = (float2 *)take(sizeof(float2) * c->plan_m.n);
   c->htab = (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq);
-  c->spec = (float2 *)take(sizeof(float2) * c->C * (size_t)c->Wt * c->H * 8);
+  const size_t spec_len = (size_t)c->C * c->Wt * c->H * 8;
+  c->spec = (float2 *)take(sizeof(float2) * spec_len);
+  // with several planes the shared row spectrum stays in spec; each plane's
+  // column pass writes spec_plane, and the adjoint sums the planes in spec_acc
+  c->spec_plane = c->L > 1 ? (float2 *)take(sizeof(float2) * spec_len) : c->spec;
+  c->spec_acc = c->L > 1 ? (float2 *)take(sizeof(float2) * spec_len) : c->spec;
   c->field_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
   c->gfield_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
   c->rec = (float *)take(sizeof(float) * c->rec_stride * (N + 1));
@@ -168,7 +169,7 @@ size_t carve(Ctx *c, char *base) {
   const size_t scan_len = std::max(N + 1, (size_t)256 * c->sort_blocks);
   c->scan_tmp = (uint32_t *)take(sizeof(uint32_t) * (scan_len / kScanItems + 2));
   c->partials = (float *)take(sizeof(float) * c->part_stride * cap);
-  c->loss_part = (double *)take(sizeof(double) * c->C * (size_t)((c->H + 1) / 2));
+  c->loss_part = (double *)take(sizeof(double) * c->L * c->C * (size_t)((c->H + 1) / 2));
   c->status = (uint32_t *)take(sizeof(uint32_t) * 4);
   return (off + 255) & ~(size_t)255;
 }
@@ -210,6 +211,13 @@ cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_b
   if (workspace_bytes < need)
     return fail(CGH_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
   cgh::carve(&c, (char *)workspace);
+  {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c.num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return device_fail(e, "cgh_create");
+    if (c.num_cu < 1) c.num_cu = 1;
+  }
   hipStream_t s = (hipStream_t)stream;
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_x, c.Wp, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_y, c.Hp, s), "twiddles");
@@ -229,7 +237,8 @@ cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_b
 
 cgh_status cgh_destroy(cgh_ctx *ctx) {
   if (ctx && ctx->c.prof_ev) {
-    for (int i = 0; i < 2 * cgh::kMaxProf; ++i) hipEventDestroy(ctx->c.prof_ev[i]);
+    // teardown: a failure to destroy an event leaves nothing to recover
+    for (int i = 0; i < 2 * cgh::kMaxProf; ++i) (void)hipEventDestroy(ctx->c.prof_ev[i]);
     delete[] ctx->c.prof_ev;
   }
   delete ctx;
@@ -268,17 +277,27 @@ cgh_status cgh_rasterize(cgh_ctx *ctx, const float *params, int32_t n, cgh_c64 *
   return CGH_OK;
 }
 
-// F1 + F2: field -> column-pass output in c.spec
-static cgh_status forward_spectrum(Ctx &c, const cgh_c64 *field, hipStream_t s) {
-  const float2 *f = reinterpret_cast<const float2 *>(field);
-  {
-    ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
-    CGH_CHECK_LAUNCH(cgh::launch_row_fwd(c, f, s), "row fft");
-  }
-  {
-    ProfScope p(c, CGH_KERNEL_COL_PASS, s);
-    CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, 0, s), "column pass");
-  }
+// F1: field -> row spectrum in c.spec (shared by every plane)
+static cgh_status row_spectrum(Ctx &c, const cgh_c64 *field, hipStream_t s) {
+  ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
+  CGH_CHECK_LAUNCH(cgh::launch_row_fwd(c, reinterpret_cast<const float2 *>(field), c.spec, s),
+                   "row fft");
+  return CGH_OK;
+}
+
+// F2 of plane l: c.spec -> c.spec_plane (in place when L = 1)
+static cgh_status plane_spectrum(Ctx &c, int l, hipStream_t s) {
+  ProfScope p(c, CGH_KERNEL_COL_PASS, s);
+  CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, 0, l, c.spec, c.spec_plane, 0, s), "column pass");
+  return CGH_OK;
+}
+
+// B1 of plane l: the adjoint seed in c.spec_plane -> c.spec_acc (summed over
+// planes: the first plane writes, the others add)
+static cgh_status plane_adjoint(Ctx &c, int l, hipStream_t s) {
+  ProfScope p(c, CGH_KERNEL_COL_PASS, s);
+  CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, 1, l, c.spec_plane, c.spec_acc, l > 0, s),
+                   "adjoint column pass");
   return CGH_OK;
 }
 
@@ -297,16 +316,10 @@ static cgh_status raster_adjoint(Ctx &c, const float *params, int n, const float
   return CGH_OK;
 }
 
-// B1 + B2: adjoint seed in c.spec -> dL/dU0
-static cgh_status adjoint_spectrum(Ctx &c, float2 *grad_field, hipStream_t s) {
-  {
-    ProfScope p(c, CGH_KERNEL_COL_PASS, s);
-    CGH_CHECK_LAUNCH(cgh::launch_col_pass(c, 1, s), "adjoint column pass");
-  }
-  {
-    ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
-    CGH_CHECK_LAUNCH(cgh::launch_row_inv(c, grad_field, s), "adjoint row fft");
-  }
+// B2: c.spec_acc -> dL/dU0
+static cgh_status adjoint_rows(Ctx &c, float2 *grad_field, hipStream_t s) {
+  ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
+  CGH_CHECK_LAUNCH(cgh::launch_row_inv(c, c.spec_acc, grad_field, s), "adjoint row fft");
   return CGH_OK;
 }
 
@@ -318,12 +331,16 @@ cgh_status cgh_propagate(cgh_ctx *ctx, const cgh_c64 *field, float *intensity,
   if (!aligned16(field) || !aligned16(intensity) || !aligned16(field_out))
     return fail(CGH_ERR_INVALID_ARG, "buffers must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  cgh_status st = forward_spectrum(c, field, s);
+  cgh_status st = row_spectrum(c, field, s);
   if (st != CGH_OK) return st;
-  ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
-  CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, nullptr, nullptr, intensity,
-                                        reinterpret_cast<float2 *>(field_out), 0, s),
-                   "intensity row pass");
+  for (int l = 0; l < c.L; ++l) {
+    st = plane_spectrum(c, l, s);
+    if (st != CGH_OK) return st;
+    ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
+    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, l, c.spec_plane, nullptr, nullptr, intensity,
+                                          reinterpret_cast<float2 *>(field_out), 0, s),
+                     "intensity row pass");
+  }
   return CGH_OK;
 }
 
@@ -342,18 +359,25 @@ cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_
     return fail(CGH_ERR_INVALID_ARG, "misaligned buffer");
   hipStream_t s = (hipStream_t)stream;
   float2 *gf = grad_field ? reinterpret_cast<float2 *>(grad_field) : c.gfield_tmp;
-  st = forward_spectrum(c, field, s);
+  st = row_spectrum(c, field, s);
   if (st != CGH_OK) return st;
-  {
-    ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
-    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, target, nullptr, nullptr, nullptr, 1, s),
-                     "loss row pass");
+  for (int l = 0; l < c.L; ++l) {
+    st = plane_spectrum(c, l, s);
+    if (st != CGH_OK) return st;
+    {
+      ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
+      CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, l, c.spec_plane, target, nullptr, nullptr,
+                                            nullptr, 1, s),
+                       "loss row pass");
+    }
+    st = plane_adjoint(c, l, s);
+    if (st != CGH_OK) return st;
   }
   if (loss) {
     ProfScope p(c, CGH_KERNEL_LOSS, s);
     CGH_CHECK_LAUNCH(cgh::launch_loss_finalize(c, loss, s), "loss");
   }
-  st = adjoint_spectrum(c, gf, s);
+  st = adjoint_rows(c, gf, s);
   if (st != CGH_OK) return st;
   return raster_adjoint(c, params, n, gf, grads, s);
 }
@@ -368,15 +392,21 @@ cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
   if (!aligned16(field) || !aligned16(grad_field))
     return fail(CGH_ERR_INVALID_ARG, "misaligned buffer");
   hipStream_t s = (hipStream_t)stream;
-  cgh_status st = forward_spectrum(c, field, s);
+  cgh_status st = row_spectrum(c, field, s);
   if (st != CGH_OK) return st;
-  {
-    ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
-    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, nullptr, grad_intensity, nullptr, nullptr,
-                                          1, s),
-                     "adjoint seed row pass");
+  for (int l = 0; l < c.L; ++l) {
+    st = plane_spectrum(c, l, s);
+    if (st != CGH_OK) return st;
+    {
+      ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
+      CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, l, c.spec_plane, nullptr, grad_intensity,
+                                            nullptr, nullptr, 1, s),
+                       "adjoint seed row pass");
+    }
+    st = plane_adjoint(c, l, s);
+    if (st != CGH_OK) return st;
   }
-  return adjoint_spectrum(c, reinterpret_cast<float2 *>(grad_field), s);
+  return adjoint_rows(c, reinterpret_cast<float2 *>(grad_field), s);
 }
 
 cgh_status cgh_rasterize_adjoint(cgh_ctx *ctx, const float *params, int32_t n,
@@ -447,7 +477,7 @@ cgh_status cgh_profile_begin(cgh_ctx *ctx, int32_t kernel_class) {
     for (int i = 0; i < 2 * cgh::kMaxProf; ++i) {
       hipError_t e = hipEventCreate(&ev[i]);
       if (e != hipSuccess) {
-        for (int j = 0; j < i; ++j) hipEventDestroy(ev[j]);
+        for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
         delete[] ev;
         return device_fail(e, "cgh_profile_begin");
       }

@@ -65,27 +65,30 @@ struct Ctx {
   int Wt;                           // column tiles of 8 in the propagation buffer
   int tiles_x, tiles_y, num_tiles, sort_passes;
   int64_t pair_cap;
-  int rec_stride, part_stride;
   int sort_blocks;                  // radix-sort grid (covers pair_cap)
+  int rec_stride, part_stride;
   FftPlan plan_x, plan_y, plan_m;   // lengths Wp, Hp, Hp/2 (plan_m unused for odd Hp)
   int last_n;                       // n of the last rasterize (-1: none)
+  int num_cu;                       // compute units of the device the context was created on
   // workspace carve (device pointers)
   float2 *tw_x, *tw_y, *tw_m;       // two-level twiddle tables for Wp, Hp, Hp/2
   float2 *twf_x, *twf_m;            // full twiddle tables for Wp and Hp/2 (Hp if odd)
   float2 *htab;                     // [C][L][Hq][Wq]
   float2 *spec;                     // [C][Wt][H][8] column-tiled propagation buffer
+  float2 *spec_plane;               // per-plane column-pass output (spec itself when L = 1)
+  float2 *spec_acc;                 // adjoint sum over planes (spec itself when L = 1)
   float2 *field_tmp;                // [C][H][W]
   float2 *gfield_tmp;               // [C][H][W]
   float *rec;                       // [max_gaussians + 1][rec_stride]; the last is all zeros
   uint2 *rect;                      // [max_gaussians] tile rectangles (x0|x1<<16, y0|y1<<16)
   uint32_t *counts;                 // [max_gaussians]
   uint32_t *offsets;                // [max_gaussians + 1]
-  uint32_t *keys[2], *vals[2];      // [pair_cap] ping-pong
+  uint32_t *keys[2], *vals[2];      // [pair_cap] ping-pong (tile id, Gaussian id)
   uint2 *ranges;                    // [num_tiles] [start, end) into the sorted list
-  uint32_t *hist;                   // [256 * sort_blocks]
+  uint32_t *hist;                   // [256 * sort_blocks] digit-major block histograms
   uint32_t *scan_tmp;               // partial sums for scans
   float *partials;                  // [pair_cap][part_stride] raster-adjoint partials
-  double *loss_part;                // [C * ceil(H/2)] one per row-pass workgroup
+  double *loss_part;                // [L][row-pass workgroups] FP64 loss partials
   uint32_t *status;                 // [0] overflow flag, [1] pair total
   int sorted;                       // which ping-pong buffer holds the sorted pairs
   // kernel-class timing (cgh_profile_begin / _end)
@@ -102,11 +105,14 @@ hipError_t launch_build_twiddles(float2 *tw, int n, hipStream_t s);
 hipError_t launch_build_twiddles_full(float2 *tw, int n, hipStream_t s);
 int row_group_rows(const Ctx &c);   // rows per row-pass workgroup
 hipError_t launch_build_transfer(const Ctx &c, hipStream_t s);
-hipError_t launch_row_fwd(const Ctx &c, const float2 *field, hipStream_t s);
-hipError_t launch_row_inv(const Ctx &c, float2 *out, hipStream_t s);
-hipError_t launch_col_pass(const Ctx &c, int conj_h, hipStream_t s);
-hipError_t launch_row_loss(const Ctx &c, const float *target, const float *grad_intensity,
-                           float *intensity, float2 *u_out, int make_grad, hipStream_t s);
+hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStream_t s);
+hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStream_t s);
+// column pass of plane `plane`: src -> dst (may alias); acc adds into dst
+hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *src, float2 *dst,
+                           int acc, hipStream_t s);
+hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *target,
+                           const float *grad_intensity, float *intensity, float2 *u_out,
+                           int make_grad, hipStream_t s);
 hipError_t launch_loss_finalize(const Ctx &c, double *loss, hipStream_t s);
 
 hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s);

@@ -255,18 +255,63 @@ __device__ __forceinline__ size_t tiled(int c, int y, int x, int H, int Wt) {
   return (((size_t)c * Wt + (x >> 3)) * H + y) * 8 + (x & 7);
 }
 
+// Global -> LDS copy of n elements with G loads in flight per thread: every load
+// of a group is issued (at a clamped, always valid index) before the first one
+// is stored, so their latencies overlap instead of adding up.  ld(i) must be
+// callable for every 0 <= i < n; st(i, v) stores element i.
+template <int T, int G, class LD, class ST>
+__device__ __forceinline__ void staged_copy(int n, int tid, LD ld, ST st) {
+  for (int i0 = tid; i0 < n; i0 += T * G) {
+    float2 v[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) v[g] = ld(min(i0 + g * T, n - 1));
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (i0 + g * T < n) st(i0 + g * T, v[g]);
+  }
+}
+
+// row b (< ROWS) and column x of element i of ROWS consecutive rows of length w
+template <int ROWS>
+__device__ __forceinline__ int row_of(int i, int w) {
+  int b = 0;
+#pragma unroll
+  for (int r = 1; r < ROWS; ++r) b += i >= r * w;
+  return b;
+}
+
 // load the two rows of S into LDS (zero beyond Wp or H)
 __device__ __forceinline__ void load_rows_tiled(float2 *sbuf, const float2 *__restrict__ S,
                                                 int c, int y0, int H, int Wp, int Wt,
                                                 int tid) {
-  for (int i = tid; i < Wt * 16; i += kRowThreads) {
-    const int t = i >> 4, b = (i >> 3) & 1, x = t * 8 + (i & 7);
-    if (x < Wp) {
-      float2 v = make_float2(0.f, 0.f);
-      if (y0 + b < H) v = S[tiled(c, y0 + b, x, H, Wt)];
-      sbuf[2 * x + b] = v;
-    }
-  }
+  staged_copy<kRowThreads, 8>(
+      Wt * 16, tid,
+      [&](int i) {
+        const int b = (i >> 3) & 1, x = (i >> 4) * 8 + (i & 7);
+        const float2 v = S[tiled(c, min(y0 + b, H - 1), x, H, Wt)];
+        return y0 + b < H ? v : make_float2(0.f, 0.f);
+      },
+      [&](int i, float2 v) {
+        const int b = (i >> 3) & 1, x = (i >> 4) * 8 + (i & 7);
+        if (x < Wp) sbuf[2 * x + b] = v;
+      });
+}
+
+// rows y0, y0+1 of the field, zero-extended to n, into LDS (interleaved)
+__device__ __forceinline__ void load_field_rows(float2 *sbuf, const float2 *__restrict__ field,
+                                                int c, int y0, int H, int W, int n, int tid) {
+  staged_copy<kRowThreads, 8>(
+      2 * W, tid,
+      [&](int i) {
+        const int b = row_of<2>(i, W), x = i - b * W;
+        const float2 v = field[((size_t)c * H + min(y0 + b, H - 1)) * W + x];
+        return y0 + b < H ? v : make_float2(0.f, 0.f);
+      },
+      [&](int i, float2 v) {
+        const int b = row_of<2>(i, W), x = i - b * W;
+        sbuf[2 * x + b] = v;
+      });
+  for (int i = tid; i < 2 * (n - W); i += kRowThreads) sbuf[2 * W + i] = make_float2(0.f, 0.f);
 }
 
 __device__ __forceinline__ void store_rows_tiled(const float2 *sbuf, float2 *__restrict__ S,
@@ -290,12 +335,7 @@ __global__ __launch_bounds__(kRowThreads) void k_row_fwd(const float2 *__restric
   const int pairs = (H + 1) >> 1;
   const int c = blockIdx.x / pairs, y0 = 2 * (blockIdx.x % pairs);
   load_tw<kRowThreads>(tw, twx, tid);
-  for (int b = 0; b < 2; ++b) {
-    const bool ok = y0 + b < H;
-    const float2 *src = field + ((size_t)c * H + y0 + b) * W;
-    for (int x = tid; x < n; x += kRowThreads)
-      sbuf[2 * x + b] = (ok && x < W) ? src[x] : make_float2(0.f, 0.f);
-  }
+  load_field_rows(sbuf, field, c, y0, H, W, n, tid);
   __syncthreads();
   fft_lds<-1, 2, kRowThreads, MAXN>(sbuf, p, tw, tid);
   store_rows_tiled(sbuf, S, c, y0, H, n, Wt, tid);
@@ -391,11 +431,18 @@ __global__ __launch_bounds__(kRowThreads) void k_row_loss(
 template <int N, int ROWS, int T>
 __device__ __forceinline__ void load_rows_c(float2 *sbuf, const float2 *__restrict__ S, int c,
                                             int y0, int H, int Wt, int tid) {
-  for (int i = tid; i < Wt * 8 * ROWS; i += T) {
-    const int t = i / (8 * ROWS), r = i % (8 * ROWS), b = r >> 3, x = t * 8 + (r & 7);
-    if (x < N) sbuf[ROWS * x + b] = (y0 + b < H) ? S[tiled(c, y0 + b, x, H, Wt)]
-                                                  : make_float2(0.f, 0.f);
-  }
+  constexpr int NT = (N + 7) / 8 * 8 * ROWS, G = (NT + T - 1) / T;
+  staged_copy<T, G>(
+      Wt * 8 * ROWS, tid,
+      [&](int i) {
+        const int t = i / (8 * ROWS), r = i % (8 * ROWS), b = r >> 3, x = t * 8 + (r & 7);
+        const float2 v = S[tiled(c, min(y0 + b, H - 1), x, H, Wt)];
+        return y0 + b < H ? v : make_float2(0.f, 0.f);
+      },
+      [&](int i, float2 v) {
+        const int t = i / (8 * ROWS), r = i % (8 * ROWS), b = r >> 3, x = t * 8 + (r & 7);
+        if (x < N) sbuf[ROWS * x + b] = v;
+      });
 }
 
 template <int N, int ROWS, int T>
@@ -420,17 +467,17 @@ template <int N>
 struct RowTw<N, true> {
   float2 t[N];
   template <int T>
-  __device__ void load(const float2 *full, const float2 *, int tid) { load_table<N, T>(t, full, tid); }
+  __device__ __forceinline__ void load(const float2 *full, const float2 *, int tid) { load_table<N, T>(t, full, tid); }
   template <int DIR, int B, int T>
-  __device__ void fft(float2 *buf, int tid) const { cfft<DIR, B, T, N>(buf, t, tid); }
+  __device__ __forceinline__ void fft(float2 *buf, int tid) const { cfft<DIR, B, T, N>(buf, t, tid); }
 };
 template <int N>
 struct RowTw<N, false> {
   TwLds t;
   template <int T>
-  __device__ void load(const float2 *, const float2 *two, int tid) { load_tw<T>(t, two, tid); }
+  __device__ __forceinline__ void load(const float2 *, const float2 *two, int tid) { load_tw<T>(t, two, tid); }
   template <int DIR, int B, int T>
-  __device__ void fft(float2 *buf, int tid) const { cfft2<DIR, B, T, N>(buf, t, tid); }
+  __device__ __forceinline__ void fft(float2 *buf, int tid) const { cfft2<DIR, B, T, N>(buf, t, tid); }
 };
 
 template <int N, int ROWS, int T, bool FULL>
@@ -444,12 +491,18 @@ __global__ __launch_bounds__(T) void k_row_fwd_c(const float2 *__restrict__ fiel
   const int groups = (H + ROWS - 1) / ROWS;
   const int c = blockIdx.x / groups, y0 = ROWS * (blockIdx.x % groups);
   tw.template load<T>(twf, tw2, tid);
-  for (int b = 0; b < ROWS; ++b) {
-    const bool ok = y0 + b < H;
-    const float2 *src = field + ((size_t)c * H + y0 + b) * W;
-    for (int x = tid; x < N; x += T)
-      sbuf[ROWS * x + b] = (ok && x < W) ? src[x] : make_float2(0.f, 0.f);
-  }
+  staged_copy<T, (ROWS * N + T - 1) / T>(
+      ROWS * W, tid,
+      [&](int i) {
+        const int b = row_of<ROWS>(i, W), x = i - b * W;
+        const float2 v = field[((size_t)c * H + min(y0 + b, H - 1)) * W + x];
+        return y0 + b < H ? v : make_float2(0.f, 0.f);
+      },
+      [&](int i, float2 v) {
+        const int b = row_of<ROWS>(i, W), x = i - b * W;
+        sbuf[ROWS * x + b] = v;
+      });
+  for (int i = tid; i < ROWS * (N - W); i += T) sbuf[ROWS * W + i] = make_float2(0.f, 0.f);
   __syncthreads();
   tw.template fft<-1, ROWS, T>(sbuf, tid);
   store_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
@@ -485,36 +538,54 @@ __global__ __launch_bounds__(T) void k_row_loss_c(
   __shared__ float2 sbuf[ROWS * N];
   __shared__ RowTw<N, FULL> tw;
   __shared__ double red[T / 64];
+  constexpr int KT = (ROWS * N + T - 1) / T;  // cropped elements per thread (W <= N)
   const int tid = threadIdx.x;
   const int groups = (H + ROWS - 1) / ROWS;
   const int c = blockIdx.x / groups, y0 = ROWS * (blockIdx.x % groups);
+  const int nw = ROWS * W;  // element i: row y0 + i / W, column i % W
   tw.template load<T>(twf, tw2, tid);
   load_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
-  __syncthreads();
+  // the target (or the caller's dL/dI) of this thread's elements, fetched
+  // before the transform (whose barriers do not wait for global loads) so
+  // that the loads overlap it
+  const float *tsrc = target ? target : grad_I;
+  float tv[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int i = min(tid + k * T, nw - 1);
+    const int b = row_of<ROWS>(i, W), x = i - b * W;
+    tv[k] = tsrc ? tsrc[((size_t)c * H + min(y0 + b, H - 1)) * W + x] : 0.f;
+  }
+  lds_sync();
   tw.template fft<+1, ROWS, T>(sbuf, tid);
   double acc = 0.0;
-  for (int i = tid; i < ROWS * N; i += T) {
-    const int b = i / N, x = i - b * N;
-    const int y = y0 + b;
-    if (x < W && y < H) {
-      const float2 u = sbuf[ROWS * x + b];
-      const float I = u.x * u.x + u.y * u.y;
-      const size_t o = ((size_t)c * H + y) * W + x;
-      if (intensity) intensity[o] = I;
-      if (u_out) u_out[o] = u;
-      float f = 0.f;
-      if (target) {
-        const float d = I - target[o];
-        acc += (double)d * (double)d;
-        f = gscale * d;  // 4 (I - T) / M
-      } else if (grad_I) {
-        f = 2.0f * grad_I[o];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int i = tid + k * T;
+    if (i < nw) {
+      const int b = row_of<ROWS>(i, W), x = i - b * W, y = y0 + b;
+      if (y < H) {
+        const float2 u = sbuf[ROWS * x + b];
+        const float I = u.x * u.x + u.y * u.y;
+        const size_t o = ((size_t)c * H + y) * W + x;
+        if (intensity) intensity[o] = I;
+        if (u_out) u_out[o] = u;
+        float f = 0.f;
+        if (target) {
+          const float d = I - tv[k];
+          acc += (double)d * (double)d;
+          f = gscale * d;  // 4 (I - T) / M
+        } else if (grad_I) {
+          f = 2.0f * tv[k];
+        }
+        if (make_grad) sbuf[ROWS * x + b] = make_float2(f * u.x, f * u.y);
+      } else if (make_grad) {
+        sbuf[ROWS * x + b] = make_float2(0.f, 0.f);
       }
-      if (make_grad) sbuf[ROWS * x + b] = make_float2(f * u.x, f * u.y);
-    } else if (make_grad) {
-      sbuf[ROWS * x + b] = make_float2(0.f, 0.f);
     }
   }
+  if (make_grad)
+    for (int i = tid; i < ROWS * (N - W); i += T) sbuf[ROWS * W + i] = make_float2(0.f, 0.f);
   if (target) {
     for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
     if ((tid & 63) == 0) red[tid >> 6] = acc;
@@ -541,58 +612,66 @@ static int row_blocks(const Ctx &c) {
 }
 static size_t row_lds(const Ctx &c) { return (size_t)2 * c.Wp * sizeof(float2); }
 
-hipError_t launch_row_fwd(const Ctx &c, const float2 *field, hipStream_t s) {
+hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStream_t s) {
   if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_fwd_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
-                       field, c.H, c.W, c.Wt, c.twf_x, c.tw_x, c.spec);
+                       field, c.H, c.W, c.Wt, c.twf_x, c.tw_x, dst);
   else if (c.Wp == 512)
     hipLaunchKernelGGL((k_row_fwd_c<512, 4, 256, true>), dim3(row_blocks(c)), dim3(256), 0, s,
-                       field, c.H, c.W, c.Wt, c.twf_x, c.tw_x, c.spec);
+                       field, c.H, c.W, c.Wt, c.twf_x, c.tw_x, dst);
   else if (c.Wp <= 4096)
     hipLaunchKernelGGL(k_row_fwd<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
-                       field, c.H, c.W, c.Wt, c.plan_x, c.tw_x, c.spec);
+                       field, c.H, c.W, c.Wt, c.plan_x, c.tw_x, dst);
   else
     hipLaunchKernelGGL(k_row_fwd<8192>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
-                       field, c.H, c.W, c.Wt, c.plan_x, c.tw_x, c.spec);
+                       field, c.H, c.W, c.Wt, c.plan_x, c.tw_x, dst);
   return hipGetLastError();
 }
 
-hipError_t launch_row_inv(const Ctx &c, float2 *out, hipStream_t s) {
+hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStream_t s) {
   if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_inv_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
-                       c.spec, c.H, c.W, c.Wt, c.twf_x, c.tw_x, out);
+                       src, c.H, c.W, c.Wt, c.twf_x, c.tw_x, out);
   else if (c.Wp == 512)
     hipLaunchKernelGGL((k_row_inv_c<512, 4, 256, true>), dim3(row_blocks(c)), dim3(256), 0, s,
-                       c.spec, c.H, c.W, c.Wt, c.twf_x, c.tw_x, out);
+                       src, c.H, c.W, c.Wt, c.twf_x, c.tw_x, out);
   else if (c.Wp <= 4096)
     hipLaunchKernelGGL(k_row_inv<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
-                       c.spec, c.H, c.W, c.Wt, c.plan_x, c.tw_x, out);
+                       src, c.H, c.W, c.Wt, c.plan_x, c.tw_x, out);
   else
     hipLaunchKernelGGL(k_row_inv<8192>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
-                       c.spec, c.H, c.W, c.Wt, c.plan_x, c.tw_x, out);
+                       src, c.H, c.W, c.Wt, c.plan_x, c.tw_x, out);
   return hipGetLastError();
 }
 
-hipError_t launch_row_loss(const Ctx &c, const float *target, const float *grad_intensity,
-                           float *intensity, float2 *u_out, int make_grad, hipStream_t s) {
+hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *target,
+                           const float *grad_intensity, float *intensity, float2 *u_out,
+                           int make_grad, hipStream_t s) {
   const double M = (double)c.L * c.C * c.H * c.W;
   const float gscale = (float)(4.0 / M);
+  // plane l of the [L][C][H][W] arrays; its loss partials after those of planes < l
+  const size_t po = (size_t)plane * c.C * c.H * c.W;
+  if (target) target += po;
+  if (grad_intensity) grad_intensity += po;
+  if (intensity) intensity += po;
+  if (u_out) u_out += po;
+  double *lp = c.loss_part + (size_t)plane * row_blocks(c);
   if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_loss_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
-                       c.spec, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, intensity,
-                       u_out, c.loss_part, gscale, make_grad);
+                       buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, intensity,
+                       u_out, lp, gscale, make_grad);
   else if (c.Wp == 512)
     hipLaunchKernelGGL((k_row_loss_c<512, 4, 256, true>), dim3(row_blocks(c)), dim3(256), 0, s,
-                       c.spec, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, intensity,
-                       u_out, c.loss_part, gscale, make_grad);
+                       buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, intensity,
+                       u_out, lp, gscale, make_grad);
   else if (c.Wp <= 4096)
     hipLaunchKernelGGL(k_row_loss<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
-                       c.spec, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity,
-                       intensity, u_out, c.loss_part, gscale, make_grad);
+                       buf, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity,
+                       intensity, u_out, lp, gscale, make_grad);
   else
     hipLaunchKernelGGL(k_row_loss<8192>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
-                       c.spec, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity,
-                       intensity, u_out, c.loss_part, gscale, make_grad);
+                       buf, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity,
+                       intensity, u_out, lp, gscale, make_grad);
   return hipGetLastError();
 }
 
@@ -600,6 +679,22 @@ hipError_t launch_row_loss(const Ctx &c, const float *target, const float *grad_
 // Column passes over one 8-column tile of one channel (a contiguous block of
 // H x 8 complex in S), in place.
 // ----------------------------------------------------------------------------
+// Source, destination and transfer table of one column pass.  src and dst
+// may be the same buffer (in place).  acc: add the result to dst instead of
+// overwriting it (the adjoint's sum over planes).  htab points at the table
+// of the pass's plane for channel 0; channel ch is at htab + ch * hstride.
+struct ColIO {
+  const float2 *src;
+  float2 *dst;
+  const float2 *htab;
+  size_t hstride;
+  int acc;
+};
+
+__device__ __forceinline__ void col_store(const ColIO &io, size_t i, float2 v) {
+  io.dst[i] = io.acc ? cadd(io.dst[i], v) : v;
+}
+
 __device__ __forceinline__ float2 transfer_at(const float2 *__restrict__ hc, int ky, int kx,
                                               int Hp, int Wp, int Wq, int conj_h, float scale) {
   const int qx = min(kx, Wp - kx), qy = min(ky, Hp - ky);
@@ -608,21 +703,54 @@ __device__ __forceinline__ float2 transfer_at(const float2 *__restrict__ hc, int
   return cscale(h, scale);
 }
 
+// X[i] *= H(2 (i >> 3) + parity, 8 t + (i & 7)) over one column block of M rows:
+// all table loads of a thread are issued before the first is used, so their
+// latencies overlap.
+template <int M, int T>
+__device__ __forceinline__ void apply_transfer(float2 *X, const float2 *__restrict__ hc,
+                                               int parity, int t, int Wp, int Wq, int conj_h,
+                                               float scale, int tid) {
+  constexpr int total = 8 * M, K = (total + T - 1) / T, G = 3;
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += G) {
+    float2 hv[G];
+#pragma unroll
+    for (int k = k0; k < k0 + G && k < K; ++k) {
+      const int i = tid + k * T;
+      hv[k - k0] = make_float2(0.f, 0.f);
+      if (total % T == 0 || i < total) {
+        const int kx = t * 8 + (i & 7), ky = 2 * (i >> 3) + parity;
+        const int qx = min(kx, Wp - kx), qy = min(ky, 2 * M - ky);
+        if (kx < Wp) hv[k - k0] = hc[(uint32_t)(qy * Wq + qx)];
+      }
+    }
+#pragma unroll
+    for (int k = k0; k < k0 + G && k < K; ++k) {
+      const int i = tid + k * T;
+      if (total % T == 0 || i < total) {
+        float2 h = hv[k - k0];
+        if (conj_h) h.y = -h.y;
+        X[i] = cmul(X[i], cscale(h, scale));
+      }
+    }
+  }
+}
+
 // even Hp = 2M: two M-point chains (see the file header)
 template <int MAXM, int T>
-__global__ __launch_bounds__(T, 2048 / T) void k_col_half(float2 *__restrict__ S, int H, int Wp, int Wt,
+__global__ __launch_bounds__(T, 2048 / T) void k_col_half(ColIO io, int H, int Wp, int Wt,
                                                 FftPlan pm, const float2 *__restrict__ twm,
-                                                const float2 *__restrict__ twh,
-                                                const float2 *__restrict__ htab, int Hq, int Wq,
-                                                int L, int conj_h, float scale) {
+                                                const float2 *__restrict__ twh, int Wq,
+                                                int conj_h, float scale) {
   __shared__ float2 sbuf[8 * MAXM];
   __shared__ TwLds tm, th;
   constexpr int K = (8 * MAXM + T - 1) / T;
   const int tid = threadIdx.x;
   const int M = pm.n, Hp = 2 * M;
   const int t = blockIdx.x, ch = blockIdx.y;
-  float2 *base = S + ((size_t)ch * Wt + t) * H * 8;
-  const float2 *hc = htab + (size_t)ch * L * Hq * Wq;  // plane 0
+  const size_t off = ((size_t)ch * Wt + t) * H * 8;
+  const float2 *base = io.src + off;
+  const float2 *hc = io.htab + ch * io.hstride;
   const int total = 8 * M;
   load_tw<T>(tm, twm, tid);
   load_tw<T>(th, twh, tid);
@@ -675,8 +803,8 @@ __global__ __launch_bounds__(T, 2048 / T) void k_col_half(float2 *__restrict__ S
       const int n = i >> 3, kx = t * 8 + (i & 7);
       if (kx < Wp) {
         const float2 wo = cmul(cconj(tw_at(th, n)), sbuf[i]);
-        if (n < H) base[i] = cadd(keep[k], wo);
-        if (n + M < H) base[i + 8 * M] = csub(keep[k], wo);
+        if (n < H) col_store(io, off + i, cadd(keep[k], wo));
+        if (n + M < H) col_store(io, off + i + 8 * M, csub(keep[k], wo));
       }
     }
   }
@@ -684,17 +812,17 @@ __global__ __launch_bounds__(T, 2048 / T) void k_col_half(float2 *__restrict__ S
 
 // odd Hp: one Hp-point transform per column
 template <int MAXN, int T>
-__global__ __launch_bounds__(T) void k_col_full(float2 *__restrict__ S, int H, int Wp, int Wt,
-                                                FftPlan py, const float2 *__restrict__ twy,
-                                                const float2 *__restrict__ htab, int Hq, int Wq,
-                                                int L, int conj_h, float scale) {
+__global__ __launch_bounds__(T) void k_col_full(ColIO io, int H, int Wp, int Wt, FftPlan py,
+                                                const float2 *__restrict__ twy, int Wq,
+                                                int conj_h, float scale) {
   __shared__ float2 sbuf[8 * MAXN];
   __shared__ TwLds ty;
   const int tid = threadIdx.x;
   const int Hp = py.n;
   const int t = blockIdx.x, ch = blockIdx.y;
-  float2 *base = S + ((size_t)ch * Wt + t) * H * 8;
-  const float2 *hc = htab + (size_t)ch * L * Hq * Wq;
+  const size_t off = ((size_t)ch * Wt + t) * H * 8;
+  const float2 *base = io.src + off;
+  const float2 *hc = io.htab + ch * io.hstride;
   const int total = 8 * Hp;
   load_tw<T>(ty, twy, tid);
   for (int i = tid; i < total; i += T) {
@@ -712,7 +840,7 @@ __global__ __launch_bounds__(T) void k_col_full(float2 *__restrict__ S, int H, i
   fft_lds<+1, 8, T, MAXN>(sbuf, py, ty, tid);
   for (int i = tid; i < 8 * H; i += T) {
     const int kx = t * 8 + (i & 7);
-    if (kx < Wp) base[i] = sbuf[i];
+    if (kx < Wp) col_store(io, off + i, sbuf[i]);
   }
 }
 
@@ -720,10 +848,10 @@ __global__ __launch_bounds__(T) void k_col_full(float2 *__restrict__ S, int H, i
 // M-entry twiddle table in LDS (the Hp-point pre/post twiddles use the small
 // two-level table)
 template <int M, int T>
-__global__ __launch_bounds__(T) void k_col_half_c(
-    float2 *__restrict__ S, int H, int Wp, int Wt, const float2 *__restrict__ twf_m,
-    const float2 *__restrict__ twh, const float2 *__restrict__ htab, int Hq, int Wq, int L,
-    int conj_h, float scale) {
+__global__ __launch_bounds__(T) void k_col_half_c(ColIO io, int H, int Wp, int Wt,
+                                                  const float2 *__restrict__ twf_m,
+                                                  const float2 *__restrict__ twh, int Wq,
+                                                  int conj_h, float scale) {
   __shared__ float2 sbuf[8 * M];
   __shared__ float2 tw[M];
   __shared__ TwLds th;
@@ -732,8 +860,9 @@ __global__ __launch_bounds__(T) void k_col_half_c(
   constexpr int Hp = 2 * M;
   const int tid = threadIdx.x;
   const int t = blockIdx.x, ch = blockIdx.y;
-  float2 *base = S + ((size_t)ch * Wt + t) * H * 8;
-  const float2 *hc = htab + (size_t)ch * L * Hq * Wq;  // plane 0
+  const size_t off = ((size_t)ch * Wt + t) * H * 8;
+  const float2 *base = io.src + off;
+  const float2 *hc = io.htab + ch * io.hstride;
   load_table<M, T>(tw, twf_m, tid);
   load_tw<T>(th, twh, tid);
   __syncthreads();
@@ -756,12 +885,7 @@ __global__ __launch_bounds__(T) void k_col_half_c(
   __syncthreads();
   for (int parity = 0; parity < 2; ++parity) {
     cfft<-1, 8, T, M>(sbuf, tw, tid);
-    for (int i = tid; i < total; i += T) {
-      const int m = i >> 3, kx = t * 8 + (i & 7);
-      sbuf[i] = kx < Wp ? cmul(sbuf[i], transfer_at(hc, 2 * m + parity, kx, Hp, Wp, Wq, conj_h,
-                                                     scale))
-                        : make_float2(0.f, 0.f);
-    }
+    apply_transfer<M, T>(sbuf, hc, parity, t, Wp, Wq, conj_h, scale, tid);
     __syncthreads();
     cfft<+1, 8, T, M>(sbuf, tw, tid);
     if (parity == 0) {
@@ -784,35 +908,146 @@ __global__ __launch_bounds__(T) void k_col_half_c(
       const int n = i >> 3, kx = t * 8 + (i & 7);
       if (kx < Wp) {
         const float2 wo = cmul(cconj(tw_at(th, n)), sbuf[i]);
-        if (n < H) base[i] = cadd(keep[k], wo);
-        if (n + M < H) base[i + 8 * M] = csub(keep[k], wo);
+        if (n < H) col_store(io, off + i, cadd(keep[k], wo));
+        if (n + M < H) col_store(io, off + i + 8 * M, csub(keep[k], wo));
       }
     }
   }
 }
 
-hipError_t launch_col_pass(const Ctx &c, int conj_h, hipStream_t s) {
+// Column pass, software-pipelined (even Hp = 2M, H <= M, Wp a multiple of 8):
+// one persistent workgroup per CU walks its tiles.  While it transforms one
+// tile, the next tile it owns streams from HBM into the second LDS buffer
+// through direct global->LDS loads (16 bytes per lane, 1 KiB contiguous per
+// wave), so reading tile i+1 overlaps the FFTs of tile i, and the stores of
+// tile i overlap the start of tile i+1.  With H <= M the odd-chain input is
+// x[n] w^n and the even-chain input is x[n] itself, both read from the LDS
+// copy.  Rows [H, M) of a buffer (the zero upper half of the padded column)
+// are overwritten by the FFTs and cleared again after each tile.
+template <int M, int T>
+__global__ __launch_bounds__(T) void k_col_pipe(ColIO io, int H, int Wp, int Wt, int ntiles,
+                                                const float2 *__restrict__ twf_m,
+                                                const float2 *__restrict__ twh, int Wq,
+                                                int conj_h, float scale) {
+  __shared__ float2 sbuf[2][8 * M];
+  __shared__ float2 tw[M];
+  __shared__ TwLds th;
+  constexpr int K = (8 * M + T - 1) / T;
+  constexpr int total = 8 * M;
+  constexpr int Hp = 2 * M;
+  constexpr int NW = T / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tile_bytes = H * 64;  // H rows of 8 complex
+  // The direct loads are issued from inline assembly so that the compiler does
+  // not track them: its own tracking would wait for them before every LDS read
+  // of either buffer.  Completion is awaited explicitly (s_waitcnt vmcnt(0))
+  // before the buffer is published by a barrier.
+  auto prefetch = [&](int tl, int b) {
+    const char *src = reinterpret_cast<const char *>(io.src + (size_t)tl * H * 8);
+    const uint32_t dst = (uint32_t)(uintptr_t)(
+        (__attribute__((address_space(3))) char *)reinterpret_cast<char *>(sbuf[b]));
+    for (int q = wave; q * 1024 < tile_bytes; q += NW) {
+      const int off = q * 1024 + lane * 16;
+      if (off < tile_bytes) {
+        const uint32_t lds = __builtin_amdgcn_readfirstlane(dst + (uint32_t)q * 1024u);
+        uint32_t saved;
+        // M0 holds the wave's LDS destination; its previous value is restored
+        asm volatile(
+            "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\t"
+            "global_load_lds_dwordx4 %1, off\n\ts_nop 0\n\ts_mov_b32 m0, %0"
+            : "=&s"(saved)
+            : "v"(src + off), "s"(lds)
+            : "memory");
+      }
+    }
+  };
+  load_table<M, T>(tw, twf_m, tid);
+  load_tw<T>(th, twh, tid);
+  for (int i = 8 * H + tid; i < total; i += T) {
+    sbuf[0][i] = make_float2(0.f, 0.f);
+    sbuf[1][i] = make_float2(0.f, 0.f);
+  }
+  int tl = blockIdx.x;
+  if (tl < ntiles) prefetch(tl, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  for (int b = 0; tl < ntiles; tl += gridDim.x, b ^= 1) {
+    // this tile's loads were waited for by every wave (before the loop, or
+    // before the previous tile's stores); the barrier publishes them
+    lds_sync();
+    float2 *X = sbuf[b];
+    const int ch = tl / Wt, t = tl - ch * Wt;
+    const float2 *hc = io.htab + ch * io.hstride;
+    float2 keep[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T;
+      keep[k] = make_float2(0.f, 0.f);
+      if (total % T == 0 || i < total) keep[k] = cmul(X[i], tw_at(th, i >> 3));
+    }
+    for (int parity = 0; parity < 2; ++parity) {
+      cfft<-1, 8, T, M>(X, tw, tid);
+      apply_transfer<M, T>(X, hc, parity, t, Wp, Wq, conj_h, scale, tid);
+      if (parity == 0) {
+        // start streaming the next tile into the other buffer
+        const int nxt = tl + gridDim.x;
+        if (nxt < ntiles) prefetch(nxt, b ^ 1);
+      }
+      lds_sync();
+      cfft<+1, 8, T, M>(X, tw, tid);
+      if (parity == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const int i = tid + k * T;
+          if (total % T == 0 || i < total) {
+            const float2 e = X[i];
+            X[i] = keep[k];
+            keep[k] = e;
+          }
+        }
+        lds_sync();
+      }
+    }
+    // the next tile must be in LDS before the next iteration; waiting here,
+    // before this tile's stores are issued, does not wait for the stores
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const size_t off = (size_t)tl * H * 8;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T;
+      if (i < 8 * H) col_store(io, off + i, cadd(keep[k], cmul(cconj(tw_at(th, i >> 3)), X[i])));
+    }
+    for (int i = 8 * H + tid; i < total; i += T) X[i] = make_float2(0.f, 0.f);
+  }
+}
+
+hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *src, float2 *dst,
+                           int acc, hipStream_t s) {
   const float scale = (float)(1.0 / ((double)c.Hp * (double)c.Wp));
+  const size_t tab = (size_t)c.Hq * c.Wq;
+  const ColIO io{src, dst, c.htab + (size_t)plane * tab, (size_t)c.L * tab, acc};
   dim3 grid(c.Wt, c.C);
-  if (c.Hp == 2160) {
-    hipLaunchKernelGGL((k_col_half_c<1080, 1024>), grid, dim3(1024), 0, s, c.spec, c.H, c.Wp,
-                       c.Wt, c.twf_m, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h, scale);
+  if (c.Hp == 2160 && c.H <= 1080 && c.Wp % 8 == 0) {
+    const int ntiles = c.Wt * c.C;
+    const int blocks = min(ntiles, c.num_cu);
+    hipLaunchKernelGGL((k_col_pipe<1080, 1024>), dim3(blocks), dim3(1024), 0, s, io, c.H, c.Wp,
+                       c.Wt, ntiles, c.twf_m, c.tw_y, c.Wq, conj_h, scale);
+  } else if (c.Hp == 2160) {
+    hipLaunchKernelGGL((k_col_half_c<1080, 1024>), grid, dim3(1024), 0, s, io, c.H, c.Wp, c.Wt,
+                       c.twf_m, c.tw_y, c.Wq, conj_h, scale);
   } else if (c.Hp == 512) {
-    hipLaunchKernelGGL((k_col_half_c<256, 256>), grid, dim3(256), 0, s, c.spec, c.H, c.Wp,
-                       c.Wt, c.twf_m, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h, scale);
+    hipLaunchKernelGGL((k_col_half_c<256, 256>), grid, dim3(256), 0, s, io, c.H, c.Wp, c.Wt,
+                       c.twf_m, c.tw_y, c.Wq, conj_h, scale);
   } else if (c.Hp % 2 == 0) {
     const int M = c.Hp / 2;
     if (M <= kColHalfSmall)
-      hipLaunchKernelGGL((k_col_half<kColHalfSmall, 512>), grid, dim3(512), 0, s, c.spec, c.H,
-                         c.Wp, c.Wt, c.plan_m, c.tw_m, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h,
-                         scale);
+      hipLaunchKernelGGL((k_col_half<kColHalfSmall, 512>), grid, dim3(512), 0, s, io, c.H, c.Wp,
+                         c.Wt, c.plan_m, c.tw_m, c.tw_y, c.Wq, conj_h, scale);
     else
-      hipLaunchKernelGGL((k_col_half<kColHalfMax, 1024>), grid, dim3(1024), 0, s, c.spec, c.H,
-                         c.Wp, c.Wt, c.plan_m, c.tw_m, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h,
-                         scale);
+      hipLaunchKernelGGL((k_col_half<kColHalfMax, 1024>), grid, dim3(1024), 0, s, io, c.H, c.Wp,
+                         c.Wt, c.plan_m, c.tw_m, c.tw_y, c.Wq, conj_h, scale);
   } else {
-    hipLaunchKernelGGL((k_col_full<kColFullMax, 1024>), grid, dim3(1024), 0, s, c.spec, c.H,
-                       c.Wp, c.Wt, c.plan_y, c.tw_y, c.htab, c.Hq, c.Wq, c.L, conj_h, scale);
+    hipLaunchKernelGGL((k_col_full<kColFullMax, 1024>), grid, dim3(1024), 0, s, io, c.H, c.Wp,
+                       c.Wt, c.plan_y, c.tw_y, c.Wq, conj_h, scale);
   }
   return hipGetLastError();
 }
@@ -839,8 +1074,8 @@ __global__ __launch_bounds__(256) void k_loss_finalize(const double *__restrict_
 
 hipError_t launch_loss_finalize(const Ctx &c, double *loss, hipStream_t s) {
   const double inv_m = 1.0 / ((double)c.L * c.C * c.H * c.W);
-  hipLaunchKernelGGL(k_loss_finalize, dim3(1), dim3(256), 0, s, c.loss_part, row_blocks(c),
-                     inv_m, loss);
+  hipLaunchKernelGGL(k_loss_finalize, dim3(1), dim3(256), 0, s, c.loss_part,
+                     c.L * row_blocks(c), inv_m, loss);
   return hipGetLastError();
 }
 

@@ -209,12 +209,55 @@ constexpr int base_factor(int n) {
   return 3;
 }
 
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+// multiplicative inverse of a modulo m (m > 1, gcd(a, m) = 1)
+constexpr int inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 0;
+}
+
 template <int N, int DIR>
 struct RFft {
   static CGH_HD void run(float2 *x) {
     if constexpr (N == 1) {
     } else if constexpr (is_base_radix(N)) {
       Dft<N, DIR>::run(x);
+    } else if constexpr (gcd_c(base_factor(N), N / base_factor(N)) == 1) {
+      // coprime factors: prime-factor (Good-Thomas) split, no twiddles.
+      // Input n = (N2 n1 + N1 n2) mod N; output k = (N2 a k1 + N1 b k2) mod N
+      // with a = N2^-1 mod N1, b = N1^-1 mod N2; then exp(2 pi i n k / N)
+      // factors into exp(2 pi i n1 k1 / N1) exp(2 pi i n2 k2 / N2).
+      constexpr int N1 = base_factor(N);
+      constexpr int N2 = N / N1;
+      constexpr int A = inv_mod(N2 % N1, N1), B = inv_mod(N1 % N2, N2);
+      float2 t[N];
+      static_for<0, N1>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        float2 u[N2];
+        static_for<0, N2>([&](auto n2c) {
+          constexpr int n2 = decltype(n2c)::value;
+          u[n2] = x[(N2 * n1 + N1 * n2) % N];
+        });
+        RFft<N2, DIR>::run(u);
+        static_for<0, N2>([&](auto k2c) {
+          constexpr int k2 = decltype(k2c)::value;
+          t[n1 * N2 + k2] = u[k2];
+        });
+      });
+      static_for<0, N2>([&](auto k2c) {
+        constexpr int k2 = decltype(k2c)::value;
+        float2 v[N1];
+        static_for<0, N1>([&](auto n1c) {
+          constexpr int n1 = decltype(n1c)::value;
+          v[n1] = t[n1 * N2 + k2];
+        });
+        RFft<N1, DIR>::run(v);
+        static_for<0, N1>([&](auto k1c) {
+          constexpr int k1 = decltype(k1c)::value;
+          x[(N2 * A * k1 + N1 * B * k2) % N] = v[k1];
+        });
+      });
     } else {
       constexpr int N1 = base_factor(N);
       constexpr int N2 = N / N1;
@@ -293,6 +336,14 @@ struct CPlan {
   }
 };
 
+// Workgroup barrier that orders LDS only: wait for this wave's LDS operations,
+// then s_barrier.  Unlike __syncthreads() it does not wait for outstanding
+// global memory operations (such as a prefetch streaming into another LDS
+// buffer, or stores that nothing in the workgroup reads back).
+__device__ __forceinline__ void lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // One compile-time Stockham stage over B interleaved transforms in LDS
 // (element (r, b) at buf[r * B + b]); stage twiddles exp(DIR 2 pi i q k / (Ns R))
 // read from the full length-N table tw[e] = exp(-2 pi i e / N) in LDS.
@@ -325,7 +376,7 @@ __device__ __forceinline__ void cstage(float2 *__restrict__ buf, const float2 *_
       RFft<R, DIR>::run(v[it]);
     }
   }
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int it = 0; it < MAXIT; ++it) {
     const int i = tid + it * T;
@@ -338,7 +389,7 @@ __device__ __forceinline__ void cstage(float2 *__restrict__ buf, const float2 *_
       });
     }
   }
-  __syncthreads();
+  lds_sync();
 }
 
 // Same stage with twiddles from a two-level table (hi[e >> 6] lo[e & 63]),
@@ -372,7 +423,7 @@ __device__ __forceinline__ void cstage2(float2 *__restrict__ buf, const TW &tw, 
       RFft<R, DIR>::run(v[it]);
     }
   }
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int it = 0; it < MAXIT; ++it) {
     const int i = tid + it * T;
@@ -385,7 +436,7 @@ __device__ __forceinline__ void cstage2(float2 *__restrict__ buf, const TW &tw, 
       });
     }
   }
-  __syncthreads();
+  lds_sync();
 }
 
 template <int DIR, int B, int T, int N, class TW, int S = 0>

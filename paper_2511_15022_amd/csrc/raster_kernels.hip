@@ -260,45 +260,66 @@ __device__ __forceinline__ uint32_t pair_count(const uint32_t *status, int64_t c
   return (uint32_t)((int64_t)total < cap ? total : cap);
 }
 
+// Per-block digit histograms, digit-major: hist[d * nblocks + b].  Each thread
+// loads its 16 keys before counting them.
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                     const uint32_t *__restrict__ status,
                                                     int64_t cap, int shift,
                                                     uint32_t *__restrict__ hist, int nblocks) {
   __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  const int tid = threadIdx.x;
+  h[tid] = 0;
   __syncthreads();
   const uint32_t count = pair_count(status, cap);
   const uint32_t base = blockIdx.x * kSortItems;
-  for (int e = 0; e < kSortItems / 256; ++e) {
-    const uint32_t i = base + e * 256 + threadIdx.x;
-    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  if (base < count) {
+    constexpr int PER = kSortItems / 256;
+    uint32_t k[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) k[j] = keys[min(base + j * 256 + tid, count - 1)];
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      if (base + j * 256 + tid < count) atomicAdd(&h[(k[j] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  hist[(size_t)tid * nblocks + blockIdx.x] = h[tid];
 }
 
-// Stable scatter: keys are taken in index order, 256 per round; a key's rank
-// among equal digits is (earlier rounds) + (earlier waves this round) + (earlier
-// lanes of its wave), the last from ballots over the digit bits.
+// Stable scatter of one 8-bit digit.  Wave w of block b owns the 1024 keys
+// [4096 b + 1024 w, +1024), taken in index order 64 at a time; a key's rank
+// among equal digits of its wave is (the wave's running count of the digit) +
+// (earlier lanes of its round with that digit, from ballots over the digit
+// bits).  The waves of a block then add the counts of earlier waves, and the
+// blocks the exclusive scan of the digit-major histogram: equal keys keep
+// their order.
 __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
     const uint32_t *__restrict__ status, int64_t cap, int shift,
     const uint32_t *__restrict__ hist_scan, int nblocks) {
-  __shared__ uint32_t running[256];
+  constexpr int R = kSortItems / 256;  // rounds of 64 keys per wave
   __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t woff[4][256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  running[tid] = hist_scan[(size_t)tid * nblocks + blockIdx.x];
-  for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
-  __syncthreads();
   const uint32_t count = pair_count(status, cap);
   const uint32_t base = blockIdx.x * kSortItems;
+  if (base >= count) return;  // the whole block is past the end (uniform)
+#pragma unroll
+  for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+  const uint32_t first = base + 1024u * wave + lane;
+  uint32_t key[R], val[R], rank[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = min(first + 64u * r, count - 1);
+    key[r] = kin[i];
+    val[r] = vin[i];
+  }
+  __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int e = 0; e < kSortItems / 256; ++e) {
-    const uint32_t i = base + e * 256 + tid;
-    const bool valid = i < count;
-    const uint32_t key = valid ? kin[i] : 0u;
-    const uint32_t d = (key >> shift) & 255u;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool valid = first + 64u * r < count;
+    const uint32_t d = (key[r] >> shift) & 255u;
     uint64_t m = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
@@ -306,22 +327,33 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
       const uint64_t bb = __ballot(on);
       m &= on ? bb : ~bb;
     }
-    const uint32_t rank = __popcll(m & lt);
-    const bool leader = valid && (m & lt) == 0;
-    if (leader) wcnt[wave][d] = __popcll(m);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = running[d] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+    const uint32_t before = __popcll(m & lt);
+    const uint32_t prev = wcnt[wave][d];
+    rank[r] = prev + before;
+    // the lowest lane of each digit group advances the wave's count; this
+    // wave's LDS accesses complete in order, so the next round reads it
+    if (valid && before == 0) wcnt[wave][d] = prev + (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  {
+    uint32_t run = hist_scan[(size_t)tid * nblocks + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      woff[w][tid] = run;
+      run += wcnt[w][tid];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (first + 64u * r < count) {
+      const uint32_t d = (key[r] >> shift) & 255u;
+      const uint32_t pos = woff[wave][d] + rank[r];
       if (pos < count) {  // always true for a consistent histogram; guards the write
-        kout[pos] = key;
-        vout[pos] = vin[i];
+        kout[pos] = key[r];
+        vout[pos] = val[r];
       }
     }
-    __syncthreads();
-    running[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-    for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
   }
 }
 
@@ -438,24 +470,57 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
     const int cnt = (int)min((uint32_t)kBatch, rg.y - base);
     // cull the batch against this wave's sub-block (one Gaussian per lane per
     // round); the ids of the survivors go to list[wave], in list order
-    int n = 0;
-    for (int qd = 0; qd < (cnt + 63) / 64; ++qd) {
+    // the ids of all rounds are loaded first, then the records they name
+    // (one latency each rather than two per round)
+    constexpr int QD = kBatch / 64;
+    uint32_t gid[QD];
+#pragma unroll
+    for (int qd = 0; qd < QD; ++qd) {
       const int idx = qd * 64 + lane;
-      bool hit = false;
-      uint32_t g = 0;
-      if (idx < cnt) {
-        g = vals[base + idx];
-        const float4 r0 = reinterpret_cast<const float4 *>(rec + (size_t)g * RS)[0];
-        const float4 r1 = reinterpret_cast<const float4 *>(rec + (size_t)g * RS)[1];
-        // r0 = (mix, miy, mfx, mfy), r1 = (a, b, c, rx); ry is element 8
-        const float ryv = rec[(size_t)g * RS + R_RY];
-        const float ox = (float)(__float_as_int(r0.x) - X0) + r0.z;
-        const float oy = (float)(__float_as_int(r0.y) - Y0) + r0.w;
-        const float rx = r1.w + 0.01f, ry = ryv + 0.01f;
-        hit = (ox + rx >= 0.f) && (ox - rx <= 7.f) && (oy + ry >= 0.f) && (oy - ry <= 7.f);
+      gid[qd] = idx < cnt ? vals[base + idx] : zero_id;
+    }
+    float4 r0[QD], r1[QD];
+    float ryv[QD];
+#pragma unroll
+    for (int qd = 0; qd < QD; ++qd) {
+      // r0 = (mix, miy, mfx, mfy), r1 = (a, b, c, rx); ry is element 8
+      const float *rg0 = rec + (size_t)gid[qd] * RS;
+      r0[qd] = reinterpret_cast<const float4 *>(rg0)[0];
+      r1[qd] = reinterpret_cast<const float4 *>(rg0)[1];
+      ryv[qd] = rg0[R_RY];
+    }
+    int n = 0;
+#pragma unroll
+    for (int qd = 0; qd < QD; ++qd) {
+      const int idx = qd * 64 + lane;
+      // offsets of the sub-block's pixels from the mean: dx in [ex0, ex0 + 7],
+      // dy in [ey0, ey0 + 7] (the forward's own FP32 expressions at lx = ly = 0)
+      const float ex0 = (float)(X0 - __float_as_int(r0[qd].x)) - r0[qd].z;
+      const float ey0 = (float)(Y0 - __float_as_int(r0[qd].y)) - r0[qd].w;
+      const float rx = r1[qd].w + 0.01f, ry = ryv[qd] + 0.01f;
+      bool hit = idx < cnt && (ex0 <= rx) && (ex0 + 7.f >= -rx) && (ey0 <= ry) &&
+                 (ey0 + 7.f >= -ry);
+      if (hit && thr > -INFINITY) {
+        // the support box touches the sub-block; keep the Gaussian only if the
+        // maximum of the (concave) exponent over the sub-block's rectangle
+        // reaches the threshold (with a margin for rounding)
+        const float a = r1[qd].x, b = r1[qd].y, c = r1[qd].z;
+        const float ex1 = ex0 + 7.f, ey1 = ey0 + 7.f;
+        const bool inside = ex0 <= 0.f && ex1 >= 0.f && ey0 <= 0.f && ey1 >= 0.f;
+        const float ka = -0.5f * b / a, kc = -0.5f * b / c;
+        auto on_x = [&](float e) {  // edge dx = e: maximise over dy
+          const float t = fminf(fmaxf(kc * e, ey0), ey1);
+          return e * (a * e + b * t) + c * t * t;
+        };
+        auto on_y = [&](float f) {  // edge dy = f: maximise over dx
+          const float t = fminf(fmaxf(ka * f, ex0), ex1);
+          return t * (a * t + b * f) + c * f * f;
+        };
+        const float best = fmaxf(fmaxf(on_x(ex0), on_x(ex1)), fmaxf(on_y(ey0), on_y(ey1)));
+        hit = inside || best >= thr - 1e-3f * (1.f - thr);
       }
       const uint64_t m = __ballot(hit);
-      if (hit) list[wave][n + __popcll(m & lt)] = g;
+      if (hit) list[wave][n + __popcll(m & lt)] = gid[qd];
       n += __popcll(m);
     }
     if (lane == 0) list[wave][n] = zero_id;  // pad to even length (zero-amplitude record)
@@ -552,10 +617,22 @@ __global__ __launch_bounds__(64) void k_raster_adj(
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int X0 = tx * kTile, Y0 = ty * kTile;
-  for (int i = lane; i < C * kTile * kTile; i += 64) {
-    const int c = i / (kTile * kTile), p = i % (kTile * kTile);
-    const int x = X0 + (p % kTile), y = Y0 + (p / kTile);
-    sg[p][c] = (x < W && y < H) ? gfield[((size_t)c * H + y) * W + x] : make_float2(0.f, 0.f);
+  {
+    // all C * 4 loads of a lane are issued before the first is stored
+    constexpr int K = C * kTile * kTile / 64;
+    float2 v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = lane + 64 * k, c = i / (kTile * kTile), p = i % (kTile * kTile);
+      const int x = X0 + (p % kTile), y = Y0 + (p / kTile);
+      v[k] = gfield[((size_t)c * H + min(y, H - 1)) * W + min(x, W - 1)];
+      if (x >= W || y >= H) v[k] = make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = lane + 64 * k;
+      sg[i % (kTile * kTile)][i / (kTile * kTile)] = v[k];
+    }
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint2 rg = ranges[tile];
@@ -681,7 +758,8 @@ __global__ __launch_bounds__(64) void k_raster_adj(
           const float dx = (float)(lx & 7) + (lx < 8 ? offx0 : offx1);
           const float p2 = fmaf(dx, fmaf(qa, dx, qb * dy), qc * dy * dy);
           const float G = p2 >= thr ? __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2)) : 0.f;
-          const float2 *gv = sg[ly * kTile + lx];
+          // 24-bit multiply (full rate) for the LDS offset
+          const float2 *gv = &sg[0][0] + __umul24((unsigned)(ly * kTile + lx), (unsigned)C);
           float gp = 0.f;
 #pragma unroll
           for (int c = 0; c < C; ++c) {
@@ -768,21 +846,31 @@ __global__ __launch_bounds__(256) void k_preprocess_adj(
   double S[NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) S[k] = 0.0;
+  const Geom q = geometry(params, n, C, g, W, H);
   const uint64_t off = offsets[g];
   uint64_t end = off + counts[g];
   if ((int64_t)end > cap) end = (uint64_t)cap;
-  for (uint64_t p = off; p < end; ++p) {
-    const float4 *src = reinterpret_cast<const float4 *>(partials + p * PS);
-    float v[PS];
+  // pair partials in slot order, four slots' loads in flight at a time
+  constexpr int U = 4;
+  for (uint64_t p0 = off; p0 < end; p0 += U) {
+    float v[U][PS];
 #pragma unroll
-    for (int k = 0; k < PS / 4; ++k) {
-      const float4 t = src[k];
-      v[4 * k] = t.x; v[4 * k + 1] = t.y; v[4 * k + 2] = t.z; v[4 * k + 3] = t.w;
+    for (int u = 0; u < U; ++u) {
+      const uint64_t p = min(p0 + u, end - 1);
+      const float4 *src = reinterpret_cast<const float4 *>(partials + p * PS);
+#pragma unroll
+      for (int k = 0; k < PS / 4; ++k) {
+        const float4 t = src[k];
+        v[u][4 * k] = t.x; v[u][4 * k + 1] = t.y; v[u][4 * k + 2] = t.z; v[u][4 * k + 3] = t.w;
+      }
     }
 #pragma unroll
-    for (int k = 0; k < NP; ++k) S[k] += (double)v[k];
+    for (int u = 0; u < U; ++u)
+      if (p0 + u < end) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) S[k] += (double)v[u][k];
+      }
   }
-  const Geom q = geometry(params, n, C, g, W, H);
   const float *amp = params + 5 * (size_t)n;
   const float *ph = params + (size_t)(5 + C) * n;
   float *g_mean = grads;

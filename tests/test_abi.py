@@ -38,7 +38,7 @@ def cfg(**kw):
     for i, lam in enumerate(kw.get("lambdas", [515e-9] * min(c.channels, 4))):
         c.wavelength_m[i] = lam
     zs = kw.get("zs", [2e-3])
-    c.num_planes = len(zs)
+    c.num_planes = kw.get("L", len(zs))
     for i, z in enumerate(zs):
         c.z_m[i] = z
     c.support_sigma = kw.get("k", 3.0)
@@ -65,13 +65,28 @@ def test_workspace_size_for_workloads():
     assert big < 2 * 1024 ** 3
 
 
+def test_several_planes_accepted_and_sized():
+    """Planes share the row spectrum; each further plane adds no per-plane
+    spectrum copies beyond the two plane buffers (column output, adjoint sum)."""
+    st1, one = ws(cfg(zs=[2e-3]))
+    st3, three = ws(cfg(zs=[2e-3, 3e-3, -1e-3]))
+    st8, eight = ws(cfg(zs=[1e-3 * (i + 1) for i in range(8)]))
+    assert st1 == st3 == st8 == 0
+    spec = 256 * 512 * 8  # [C][H][Wp] complex64 at C = 1
+    assert three >= one + 2 * spec
+    table = 257 * 257 * 8  # one quarter transfer table (Hp/2 + 1)(Wp/2 + 1) complex64
+    # beyond three planes only the tables and the loss partials grow with L
+    assert eight - three <= 5 * table + 8192
+
+
 @pytest.mark.parametrize("bad, status", [
     (dict(H=0), 1), (dict(W=9000), 1), (dict(C=5), 1), (dict(C=0), 1),
     (dict(Hp=514), 1),            # 514 = 2 * 257 does not factor into 2, 3, 5
     (dict(Hp=200), 1),            # smaller than H
     (dict(pitch=0.0), 1), (dict(lambdas=[-1.0]), 1), (dict(n=-1), 1),
     (dict(flags=1), 1), (dict(pairs=-5), 1),
-    (dict(zs=[1e-3, 2e-3]), 5),   # several planes: not in this build
+    (dict(L=0), 1), (dict(zs=[1e-3] * 8, L=9), 1),   # 1 <= planes <= CGH_MAX_PLANES
+    (dict(zs=[1e-3, float("nan")]), 1),
 ])
 def test_invalid_configs_are_rejected(bad, status):
     st, _ = ws(cfg(**bad))

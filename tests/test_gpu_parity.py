@@ -167,6 +167,47 @@ def test_backward_parity(O, case):
         assert e <= GRAD_TOL, (k, e)
 
 
+@pytest.mark.parametrize("case", [
+    # runtime-plan column pass (Hp = 96: two 48-point chains)
+    dict(H=40, W=56, C=2, n=200, lambdas=[639e-9, 473e-9], zs=[2e-3, -3e-3, 5e-3], Hp=96,
+         Wp=120),
+    # the software-pipelined 2160-row column pass, on a narrow canvas
+    dict(H=1080, W=48, C=1, n=2000, lambdas=[515e-9], zs=[3e-3, 6e-3], Hp=2160, Wp=96),
+])
+def test_multiplane_parity(O, case):
+    """Several propagation distances sharing one row spectrum: u and |u|^2 of
+    every plane, the loss over all planes, dL/dU0 summed over planes and the
+    parameter gradients, against the oracle."""
+    say("multi-plane", case)
+    H, W, C, n = case["H"], case["W"], case["C"], case["n"]
+    zs, L = case["zs"], len(case["zs"])
+    p = synth.params(51, n, H, W, C)
+    T = synth.target(52, C, H, W, L=L)
+    opt = O.Optics(H, W, C, case["Hp"], case["Wp"], 8e-6, case["lambdas"], zs)
+    ctx = binding.Context(H, W, C, 8e-6, case["lambdas"], zs, pad=(case["Hp"], case["Wp"]),
+                          max_gaussians=n)
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    I, u = ctx.propagate(field, intensity=True, field_out=True)
+    u_ref = O.propagate(field.cpu().numpy().astype(np.complex128), opt)
+    assert u.shape == (L, C, H, W)
+    assert rel_l2(u.cpu().numpy(), u_ref) <= FIELD_TOL
+    assert rel_l2(I.cpu().numpy(), np.abs(u_ref) ** 2) <= FIELD_TOL
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss, grad_field=gfield)
+    ref = O.forward_backward(p, T, opt)
+    lg = loss.cpu().numpy()
+    assert abs(lg[0] - ref["loss"]) <= 1e-4 * ref["loss"]
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
+    for k, e in group_errors(grads.cpu().numpy(), ref["grads"], n, C).items():
+        assert e <= GRAD_TOL, (k, e)
+    gI = np.random.default_rng(53).standard_normal((L, C, H, W)).astype(np.float32)
+    g = ctx.propagate_adjoint(field, torch.from_numpy(gI).cuda())
+    g_ref = O.propagate_adjoint(2.0 * gI.astype(np.float64) * u_ref, opt)
+    assert rel_l2(g.cpu().numpy(), g_ref) <= FIELD_TOL
+
+
 def test_gradients_against_finite_differences(O):
     case = dict(H=37, W=53, C=2, n=60, lambdas=[639e-9, 473e-9], zs=[3e-3], Hp=75, Wp=108)
     say("finite differences", case)
@@ -261,6 +302,37 @@ def test_unbounded_support_small(O):
     gg = ctx.backward(gpu_params(p), 12, torch.from_numpy(fg).cuda(), torch.from_numpy(T).cuda())
     ref = O.forward_backward(p, T, opt)
     for k, e in group_errors(gg.cpu().numpy(), ref["grads"], 12, 1).items():
+        assert e <= GRAD_TOL, (k, e)
+
+
+def test_long_tile_lists(O):
+    """3000 Gaussians crowded into a 24 x 24 patch: tile lists of thousands
+    of entries, i.e. long runs of equal sort keys spread over several sort
+    blocks, which the stable sort must keep in Gaussian order.  Field and
+    gradients against the oracle; two runs bitwise equal."""
+    say("long tile lists")
+    H = W = 64
+    n = 3000
+    p = synth.params(41, n, H, W, 1)
+    rng = np.random.default_rng(41)
+    mean = rng.uniform(20.0, 44.0, size=(n, 2))
+    p["mean_pre"] = np.arctanh(2.0 * mean / np.array([W, H]) - 1.0).astype(np.float32)
+    opt = O.Optics(H, W, 1, 2 * H, 2 * W, 8e-6, [515e-9], [2e-3])
+    ctx = binding.Context(H, W, 1, 8e-6, [515e-9], [2e-3], max_gaussians=n)
+    P = gpu_params(p)
+    f1 = ctx.rasterize(P, n).clone()
+    f2 = ctx.rasterize(P, n).clone()
+    assert torch.equal(f1, f2)
+    pairs, ok = ctx.read_status()
+    assert ok and pairs > 3 * 2048
+    fr = O.raster(p, opt)
+    mask, _ = O.ambiguous_mask(p, opt, AMBIGUOUS_BAND)
+    assert mask.mean() < 0.05
+    assert rel_l2(f1.cpu().numpy(), fr, mask) <= FIELD_TOL
+    T = synth.target(42, 1, H, W)
+    gg = ctx.backward(P, n, f1, torch.from_numpy(T).cuda())
+    ref = O.forward_backward(p, T, opt)
+    for k, e in group_errors(gg.cpu().numpy(), ref["grads"], n, 1).items():
         assert e <= GRAD_TOL, (k, e)
 
 
