@@ -915,108 +915,91 @@ __global__ __launch_bounds__(T) void k_col_half_c(ColIO io, int H, int Wp, int W
   }
 }
 
-// Column pass, software-pipelined (even Hp = 2M, H <= M, Wp a multiple of 8):
-// one persistent workgroup per CU walks its tiles.  While it transforms one
-// tile, the next tile it owns streams from HBM into the second LDS buffer
-// through direct global->LDS loads (16 bytes per lane, 1 KiB contiguous per
-// wave), so reading tile i+1 overlaps the FFTs of tile i, and the stores of
-// tile i overlap the start of tile i+1.  With H <= M the odd-chain input is
-// x[n] w^n and the even-chain input is x[n] itself, both read from the LDS
-// copy.  Rows [H, M) of a buffer (the zero upper half of the padded column)
-// are overwritten by the FFTs and cleared again after each tile.
+// Column pass over half a tile (4 columns) per workgroup, two workgroups per
+// CU so that one's LDS traffic overlaps the other's arithmetic.  Blocks come in
+// groups of 16 covering 8 tiles; the two halves of a tile are 8 blocks apart,
+// so they land on the same XCD at about the same time and share its L2 lines.
 template <int M, int T>
-__global__ __launch_bounds__(T) void k_col_pipe(ColIO io, int H, int Wp, int Wt, int ntiles,
-                                                const float2 *__restrict__ twf_m,
-                                                const float2 *__restrict__ twh, int Wq,
-                                                int conj_h, float scale) {
-  __shared__ float2 sbuf[2][8 * M];
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_col_quad(
+    ColIO io, int H, int Wp, int Wt, int ntiles, const float2 *__restrict__ twf_m,
+    const float2 *__restrict__ twh, int Wq, int conj_h, float scale) {
+  constexpr int CB = 4;
+  __shared__ float2 sbuf[CB * M];
   __shared__ float2 tw[M];
   __shared__ TwLds th;
-  constexpr int K = (8 * M + T - 1) / T;
-  constexpr int total = 8 * M;
-  constexpr int Hp = 2 * M;
-  constexpr int NW = T / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tile_bytes = H * 64;  // H rows of 8 complex
-  // The direct loads are issued from inline assembly so that the compiler does
-  // not track them: its own tracking would wait for them before every LDS read
-  // of either buffer.  Completion is awaited explicitly (s_waitcnt vmcnt(0))
-  // before the buffer is published by a barrier.
-  auto prefetch = [&](int tl, int b) {
-    const char *src = reinterpret_cast<const char *>(io.src + (size_t)tl * H * 8);
-    const uint32_t dst = (uint32_t)(uintptr_t)(
-        (__attribute__((address_space(3))) char *)reinterpret_cast<char *>(sbuf[b]));
-    for (int q = wave; q * 1024 < tile_bytes; q += NW) {
-      const int off = q * 1024 + lane * 16;
-      if (off < tile_bytes) {
-        const uint32_t lds = __builtin_amdgcn_readfirstlane(dst + (uint32_t)q * 1024u);
-        uint32_t saved;
-        // M0 holds the wave's LDS destination; its previous value is restored
-        asm volatile(
-            "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\t"
-            "global_load_lds_dwordx4 %1, off\n\ts_nop 0\n\ts_mov_b32 m0, %0"
-            : "=&s"(saved)
-            : "v"(src + off), "s"(lds)
-            : "memory");
-      }
-    }
-  };
+  constexpr int K = (CB * M + T - 1) / T;
+  constexpr int total = CB * M;
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x, within = b & 15;
+  const int h = within >> 3, tl = (b >> 4) * 8 + (within & 7);
+  if (tl >= ntiles) return;
+  const int ch = tl / Wt, t = tl - ch * Wt;
+  const int col0 = t * 8 + h * CB;
+  const size_t off = (size_t)tl * H * 8 + h * CB;
+  const float2 *base = io.src + off;
+  const float2 *hc = io.htab + ch * io.hstride;
   load_table<M, T>(tw, twf_m, tid);
   load_tw<T>(th, twh, tid);
-  for (int i = 8 * H + tid; i < total; i += T) {
-    sbuf[0][i] = make_float2(0.f, 0.f);
-    sbuf[1][i] = make_float2(0.f, 0.f);
+  float2 x[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T, n = i >> 2;
+    x[k] = base[(size_t)min(n, H - 1) * 8 + (i & 3)];
+    if (n >= H || !(total % T == 0 || i < total)) x[k] = make_float2(0.f, 0.f);
   }
-  int tl = blockIdx.x;
-  if (tl < ntiles) prefetch(tl, 0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  for (int b = 0; tl < ntiles; tl += gridDim.x, b ^= 1) {
-    // this tile's loads were waited for by every wave (before the loop, or
-    // before the previous tile's stores); the barrier publishes them
-    lds_sync();
-    float2 *X = sbuf[b];
-    const int ch = tl / Wt, t = tl - ch * Wt;
-    const float2 *hc = io.htab + ch * io.hstride;
-    float2 keep[K];
+  __syncthreads();  // the twiddle tables are read below
+  float2 keep[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = tid + k * T;
-      keep[k] = make_float2(0.f, 0.f);
-      if (total % T == 0 || i < total) keep[k] = cmul(X[i], tw_at(th, i >> 3));
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T;
+    keep[k] = make_float2(0.f, 0.f);
+    if (total % T == 0 || i < total) {
+      sbuf[i] = x[k];
+      keep[k] = cmul(x[k], tw_at(th, i >> 2));
     }
-    for (int parity = 0; parity < 2; ++parity) {
-      cfft<-1, 8, T, M>(X, tw, tid);
-      apply_transfer<M, T>(X, hc, parity, t, Wp, Wq, conj_h, scale, tid);
-      if (parity == 0) {
-        // start streaming the next tile into the other buffer
-        const int nxt = tl + gridDim.x;
-        if (nxt < ntiles) prefetch(nxt, b ^ 1);
-      }
-      lds_sync();
-      cfft<+1, 8, T, M>(X, tw, tid);
-      if (parity == 0) {
+  }
+  __syncthreads();
+  for (int parity = 0; parity < 2; ++parity) {
+    cfft<-1, CB, T, M>(sbuf, tw, tid);
+    {
+      float2 hv[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const int i = tid + k * T;
-          if (total % T == 0 || i < total) {
-            const float2 e = X[i];
-            X[i] = keep[k];
-            keep[k] = e;
-          }
+      for (int k = 0; k < K; ++k) {
+        const int i = tid + k * T;
+        const int kx = col0 + (i & 3), ky = 2 * min(i >> 2, M - 1) + parity;
+        const int qx = min(kx, Wp - kx), qy = min(ky, 2 * M - ky);
+        hv[k] = hc[(uint32_t)(qy * Wq + qx)];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = tid + k * T;
+        if (total % T == 0 || i < total) {
+          float2 hh = hv[k];
+          if (conj_h) hh.y = -hh.y;
+          sbuf[i] = cmul(sbuf[i], cscale(hh, scale));
         }
-        lds_sync();
       }
     }
-    // the next tile must be in LDS before the next iteration; waiting here,
-    // before this tile's stores are issued, does not wait for the stores
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    const size_t off = (size_t)tl * H * 8;
+    __syncthreads();
+    cfft<+1, CB, T, M>(sbuf, tw, tid);
+    if (parity == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = tid + k * T;
-      if (i < 8 * H) col_store(io, off + i, cadd(keep[k], cmul(cconj(tw_at(th, i >> 3)), X[i])));
+      for (int k = 0; k < K; ++k) {
+        const int i = tid + k * T;
+        if (total % T == 0 || i < total) {
+          const float2 e = sbuf[i];
+          sbuf[i] = keep[k];
+          keep[k] = e;
+        }
+      }
+      __syncthreads();
     }
-    for (int i = 8 * H + tid; i < total; i += T) X[i] = make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T, n = i >> 2;
+    if ((total % T == 0 || i < total) && n < H)
+      col_store(io, off + (size_t)n * 8 + (i & 3), cadd(keep[k], cmul(cconj(tw_at(th, n)), sbuf[i])));
   }
 }
 
@@ -1028,8 +1011,8 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
   dim3 grid(c.Wt, c.C);
   if (c.Hp == 2160 && c.H <= 1080 && c.Wp % 8 == 0) {
     const int ntiles = c.Wt * c.C;
-    const int blocks = min(ntiles, c.num_cu);
-    hipLaunchKernelGGL((k_col_pipe<1080, 1024>), dim3(blocks), dim3(1024), 0, s, io, c.H, c.Wp,
+    const int blocks = (ntiles + 7) / 8 * 16;
+    hipLaunchKernelGGL((k_col_quad<1080, 512>), dim3(blocks), dim3(512), 0, s, io, c.H, c.Wp,
                        c.Wt, ntiles, c.twf_m, c.tw_y, c.Wq, conj_h, scale);
   } else if (c.Hp == 2160) {
     hipLaunchKernelGGL((k_col_half_c<1080, 1024>), grid, dim3(1024), 0, s, io, c.H, c.Wp, c.Wt,

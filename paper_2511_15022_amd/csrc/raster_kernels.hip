@@ -423,18 +423,19 @@ hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
 // ----------------------------------------------------------------------------
 // Forward: U_c(p) = sum over the tile's Gaussians with log2 G(p) >= -k^2/2 log2 e
 // of G(p) (alpha c cos phi + j alpha c sin phi).
-// Each wave owns an 8x8 sub-block: it culls the LDS-staged records against its
-// sub-block, writes the survivors' slots to a per-wave list, and walks the list
-// two records at a time (both loaded before use, hiding LDS latency).  Slot
-// kBatch holds a record with zero amplitude that pads the list to even length.
+// Each wave owns an 8x8 sub-block: it culls the tile's Gaussians against its
+// sub-block (one Gaussian per lane), writes the survivors to a per-wave list
+// together with the sub-block origin's offset from their mean, and walks the
+// list two Gaussians at a time.  The list entries and records are wave-uniform,
+// so they come in through scalar registers; per pixel and Gaussian only
+// d = (pixel offset in the sub-block) + (origin offset) is left to compute.
+// Slot kBatch pads the list to even length with the all-zero record.
 // ----------------------------------------------------------------------------
 constexpr int kBatch = 256;
 
 template <int C>
-__device__ __forceinline__ void accumulate(const float *r, int X0, int Y0, float flx, float fly,
-                                           float thr, float *ar, float *ai) {
-  const float offx = (float)(X0 - __float_as_int(r[R_MIX])) - r[R_MFX];
-  const float offy = (float)(Y0 - __float_as_int(r[R_MIY])) - r[R_MFY];
+__device__ __forceinline__ void accumulate(const float *r, float offx, float offy, float flx,
+                                           float fly, float thr, float *ar, float *ai) {
   const float dx = flx + offx, dy = fly + offy;
   const float p2 = fmaf(dx, fmaf(r[R_A], dx, r[R_B] * dy), r[R_C] * dy * dy);
   const float G = p2 >= thr ? __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2)) : 0.f;
@@ -454,7 +455,8 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
                                                     uint32_t zero_id,
                                                     float2 *__restrict__ field) {
   constexpr int RS = rec_stride_c(C);
-  __shared__ uint32_t list[4][kBatch + 2];
+  // (Gaussian id, origin offset x, origin offset y) of the surviving Gaussians
+  __shared__ uint4 list[4][kBatch + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -520,10 +522,12 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
         hit = inside || best >= thr - 1e-3f * (1.f - thr);
       }
       const uint64_t m = __ballot(hit);
-      if (hit) list[wave][n + __popcll(m & lt)] = gid[qd];
+      if (hit)
+        list[wave][n + __popcll(m & lt)] =
+            make_uint4(gid[qd], __float_as_uint(ex0), __float_as_uint(ey0), 0u);
       n += __popcll(m);
     }
-    if (lane == 0) list[wave][n] = zero_id;  // pad to even length (zero-amplitude record)
+    if (lane == 0) list[wave][n] = make_uint4(zero_id, 0u, 0u, 0u);  // pad to even length
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -531,15 +535,20 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
     // the records come in through scalar loads and feed the VALU as scalar
     // operands; both pairs of loads are issued before either is used
     for (int k = 0; k < n; k += 2) {
-      const uint32_t g0 = __builtin_amdgcn_readfirstlane(list[wave][k]);
-      const uint32_t g1 = __builtin_amdgcn_readfirstlane(list[wave][k + 1]);
+      const uint4 e0 = list[wave][k], e1 = list[wave][k + 1];
+      const uint32_t g0 = __builtin_amdgcn_readfirstlane(e0.x);
+      const uint32_t g1 = __builtin_amdgcn_readfirstlane(e1.x);
+      const float ox0 = __uint_as_float(__builtin_amdgcn_readfirstlane(e0.y));
+      const float oy0 = __uint_as_float(__builtin_amdgcn_readfirstlane(e0.z));
+      const float ox1 = __uint_as_float(__builtin_amdgcn_readfirstlane(e1.y));
+      const float oy1 = __uint_as_float(__builtin_amdgcn_readfirstlane(e1.z));
       const float *s0 = rec + (size_t)g0 * RS;
       const float *s1 = rec + (size_t)g1 * RS;
       float r0[R_AMP + 2 * C], r1[R_AMP + 2 * C];
 #pragma unroll
-      for (int i = 0; i < R_AMP + 2 * C; ++i) { r0[i] = s0[i]; r1[i] = s1[i]; }
-      accumulate<C>(r0, X0, Y0, flx, fly, thr, ar, ai);
-      accumulate<C>(r1, X0, Y0, flx, fly, thr, ar, ai);
+      for (int i = R_A; i < R_AMP + 2 * C; ++i) { r0[i] = s0[i]; r1[i] = s1[i]; }
+      accumulate<C>(r0, ox0, oy0, flx, fly, thr, ar, ai);
+      accumulate<C>(r1, ox1, oy1, flx, fly, thr, ar, ai);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -580,20 +589,23 @@ hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
 // with dx, dy = pixel - mean.  The clamped exponent has zero derivative.
 //
 // Work balance.  One wave owns a tile and takes its pair list in batches of
-// 64.  The pixel boxes of a batch are laid end to end (an exclusive scan of the
-// box areas) and the concatenated pixel range is cut into 64 equal contiguous
-// pieces, one per lane, so every lane walks the same number of pixels whatever
-// the mix of box sizes.  A pair that lies inside one lane's piece is written
-// straight to its partial slot.  A pair cut by piece boundaries is finished by
-// the lane where it starts: that lane adds, in lane order, the first part of
-// each following lane the pair reaches (shuffled across the wave).  The cut
-// points depend only on the box areas, so the result is bitwise reproducible.
+// 64.  Each pair's pixel box is cut into segments of 8 pixels (the last one
+// padded), the segments of a batch are laid end to end, and the segment range
+// is cut into 64 equal contiguous pieces, one per lane, so every lane walks
+// the same number of pixels whatever the mix of box sizes.  A lane can move to
+// its next pair only at a segment boundary, so that bookkeeping runs once per
+// 8 pixels.  A pair that lies inside one lane's piece is written straight to
+// its partial slot.  A pair cut by piece boundaries is finished by the lane
+// where it starts: that lane adds, in lane order, the first part of each
+// following lane the pair reaches (shuffled across the wave).  The cut points
+// depend only on the box areas, so the result is bitwise reproducible.
 // ----------------------------------------------------------------------------
 constexpr int kAdjBatch = 64;
+constexpr int kAdjSeg = 8;  // pixels per segment
 
 // per-pair quantities kept in LDS for the walk (floats):
 //   0-3 offx0, offx1, offy0, offy1 (sub-block origin - floor(mean) - frac(mean))
-//   4-6 a, b, c;  7.. amplitude (2C);  then box, start, slot (int bits)
+//   4-6 a, b, c;  7.. amplitude (2C);  then box, first segment, slot (int bits)
 template <int C> struct AdjQ {
   static constexpr int AMP = 7;
   static constexpr int BOX = 7 + 2 * C, START = BOX + 1, SLOT = BOX + 2;
@@ -673,15 +685,16 @@ __global__ __launch_bounds__(64) void k_raster_adj(
         for (int k = 0; k < PS / 4; ++k) dst[k] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
-    // exclusive scan of the areas (lane order); the non-empty pairs are
-    // compacted to the front of the LDS table in the same order
-    int incl = area;
+    // exclusive scan of the segment counts (lane order); the non-empty pairs
+    // are compacted to the front of the LDS table in the same order
+    const int segs = (area + kAdjSeg - 1) / kAdjSeg;
+    int incl = segs;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const int v = __shfl_up(incl, d);
       if (lane >= d) incl += v;
     }
-    const int start = incl - area;
+    const int start = incl - segs;
     const int total = __shfl(incl, 63);
     const uint64_t nem = __ballot(area > 0);
     const int np = __popcll(nem);
@@ -704,17 +717,17 @@ __global__ __launch_bounds__(64) void k_raster_adj(
     }
     __syncthreads();
     if (total > 0) {
-      // ---- walk: this lane owns pixels [f0, f1) of the concatenated boxes --
+      // ---- walk: this lane owns segments [s0, s1) of the concatenated boxes
       const int chunk = (total + 63) / 64;
-      const int f0 = min(total, lane * chunk), f1 = min(total, f0 + chunk);
-      // first pair whose box contains f0: the last j with start_j <= f0
+      const int s0 = min(total, lane * chunk), s1 = min(total, s0 + chunk);
+      // first pair whose segments contain s0: the last j with start_j <= s0
       int j = 0;
       for (int step = 32; step > 0; step >>= 1) {
         const int t = j + step;
-        if (t < np && __float_as_int(sq[t * Q::N + Q::START]) <= f0) j = t;
+        if (t < np && __float_as_int(sq[t * Q::N + Q::START]) <= s0) j = t;
       }
       float offx0, offx1, offy0, offy1, qa, qb, qc, amp[2 * C];
-      int bxa, bxb, rem, lx, ly, sj, span = 0;
+      int bxa, bxb, rem, lx, ly, sj, left, span = 0;
       auto load_pair = [&](int jj) {
         const float *q = sq + jj * Q::N;
         offx0 = q[0]; offx1 = q[1]; offy0 = q[2]; offy1 = q[3];
@@ -726,6 +739,7 @@ __global__ __launch_bounds__(64) void k_raster_adj(
         const int bya = (bx >> 16) & 0xff, byb = (bx >> 24) & 0xff;
         sj = __float_as_int(q[Q::START]);
         rem = (bxb - bxa + 1) * (byb - bya + 1);
+        left = (rem + kAdjSeg - 1) / kAdjSeg;
         lx = bxa; ly = bya;
       };
       auto flush_global = [&](int jj, const float *v) {
@@ -740,44 +754,23 @@ __global__ __launch_bounds__(64) void k_raster_adj(
             dst[k] = make_float4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
         }
       };
-      float S[NS], F[NS];  // running sums; F: the first part when it began before f0
+      float S[NS], F[NS];  // running sums; F: the first part when it began before s0
 #pragma unroll
       for (int k = 0; k < NS; ++k) { S[k] = 0.f; F[k] = 0.f; }
-      if (f0 < f1) {
+      if (s0 < s1) {
         load_pair(j);
-        bool head = sj < f0;
+        bool head = sj < s0;
         {
-          const int o = f0 - sj, wb = bxb - bxa + 1;
+          const int skip = s0 - sj, o = skip * kAdjSeg, wb = bxb - bxa + 1;
           const int oy = o / wb;
           ly += oy;
           lx = bxa + (o - oy * wb);
           rem -= o;
+          left -= skip;
         }
-        for (int f = f0; f < f1; ++f) {
-          const float dy = (float)(ly & 7) + (ly < 8 ? offy0 : offy1);
-          const float dx = (float)(lx & 7) + (lx < 8 ? offx0 : offx1);
-          const float p2 = fmaf(dx, fmaf(qa, dx, qb * dy), qc * dy * dy);
-          const float G = p2 >= thr ? __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2)) : 0.f;
-          // 24-bit multiply (full rate) for the LDS offset
-          const float2 *gv = &sg[0][0] + __umul24((unsigned)(ly * kTile + lx), (unsigned)C);
-          float gp = 0.f;
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            const float2 v = gv[c];
-            gp = fmaf(v.x, amp[2 * c], fmaf(v.y, amp[2 * c + 1], gp));
-            S[2 * c] = fmaf(G, v.x, S[2 * c]);
-            S[2 * c + 1] = fmaf(G, v.y, S[2 * c + 1]);
-          }
-          const float w = p2 > kPowerFloor2 ? gp * G : 0.f;
-          const float wx = w * dx, wy = w * dy;
-          S[2 * C] += wx;
-          S[2 * C + 1] += wy;
-          S[2 * C + 2] = fmaf(wx, dx, S[2 * C + 2]);
-          S[2 * C + 3] = fmaf(wx, dy, S[2 * C + 3]);
-          S[2 * C + 4] = fmaf(wy, dy, S[2 * C + 4]);
-          if (++lx > bxb) { lx = bxa; ++ly; }
-          if (--rem == 0) {
-            // the pair ends inside this lane's piece
+        for (int s = s0; s < s1; ++s) {
+          if (left == 0) {
+            // the previous pair ended with the previous segment
             if (head) {
 #pragma unroll
               for (int k = 0; k < NS; ++k) F[k] = S[k];
@@ -787,22 +780,52 @@ __global__ __launch_bounds__(64) void k_raster_adj(
 #pragma unroll
             for (int k = 0; k < NS; ++k) S[k] = 0.f;
             head = false;
-            if (f + 1 < f1) load_pair(++j);
+            load_pair(++j);
           }
+#pragma unroll
+          for (int u = 0; u < kAdjSeg; ++u) {
+            const bool live = rem > 0;  // the last segment of a pair is padded
+            const float dy = (float)(ly & 7) + (ly < 8 ? offy0 : offy1);
+            const float dx = (float)(lx & 7) + (lx < 8 ? offx0 : offx1);
+            const float p2 = fmaf(dx, fmaf(qa, dx, qb * dy), qc * dy * dy);
+            const float G =
+                (live && p2 >= thr) ? __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2)) : 0.f;
+            // 24-bit multiply (full rate) for the LDS offset
+            const float2 *gv = &sg[0][0] + __umul24((unsigned)(min(ly, kTile - 1) * kTile + lx), (unsigned)C);
+            float gp = 0.f;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+              const float2 v = gv[c];
+              gp = fmaf(v.x, amp[2 * c], fmaf(v.y, amp[2 * c + 1], gp));
+              S[2 * c] = fmaf(G, v.x, S[2 * c]);
+              S[2 * c + 1] = fmaf(G, v.y, S[2 * c + 1]);
+            }
+            const float w = p2 > kPowerFloor2 ? gp * G : 0.f;
+            const float wx = w * dx, wy = w * dy;
+            S[2 * C] += wx;
+            S[2 * C + 1] += wy;
+            S[2 * C + 2] = fmaf(wx, dx, S[2 * C + 2]);
+            S[2 * C + 3] = fmaf(wx, dy, S[2 * C + 3]);
+            S[2 * C + 4] = fmaf(wy, dy, S[2 * C + 4]);
+            --rem;
+            if (++lx > bxb) { lx = bxa; ++ly; }
+          }
+          --left;
         }
-        if (rem != 0) {  // the current pair continues into the next lane's piece
+        if (left == 0) {  // the piece ends exactly where the pair ends
           if (head) {
 #pragma unroll
             for (int k = 0; k < NS; ++k) F[k] = S[k];
           } else {
-            // this lane started the pair and finishes it: it reaches the
-            // lanes lane+1 .. (last pixel of the pair) / chunk
-            const float *q = sq + j * Q::N;
-            const int bx = __float_as_int(q[Q::BOX]);
-            const int a = (((bx >> 8) & 0xff) - (bx & 0xff) + 1) *
-                          (((bx >> 24) & 0xff) - ((bx >> 16) & 0xff) + 1);
-            span = (sj + a - 1) / chunk - lane;
+            flush_global(j, S);
           }
+        } else if (head) {  // a pair that covers this whole piece
+#pragma unroll
+          for (int k = 0; k < NS; ++k) F[k] = S[k];
+        } else {
+          // this lane started the pair and finishes it: it reaches the lanes
+          // lane+1 .. (last segment of the pair) / chunk
+          span = (s1 + left - 1) / chunk - lane;
         }
       }
       // ---- pairs cut by piece boundaries: add the parts in lane order ------
