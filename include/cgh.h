@@ -140,6 +140,19 @@ cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_
                         const float *target, double *loss, cgh_c64 *grad_field, float *grads,
                         void *stream);
 
+/* cgh_backward with the reconstruction loss of Sec. 3.2 (L_recon) in place of
+ * L_MSE: per plane l the sum of ||I_l - T_l||^2, ||I_l M_l - T_l M_l||^2 and
+ * ||I_l T_l - T_l T_l||^2, averaged over planes; as for L_MSE each squared norm
+ * is taken as a mean over its C H W elements, so
+ *   L = (1 / (L C H W)) sum (|u|^2 - target)^2 (1 + mask^2 + target^2).
+ *   mask : [L][H][W] float, the per-plane depth mask M_l (binary in the paper;
+ *          any real weight is accepted), shared by the channels.
+ * Other arguments, outputs and preconditions as cgh_backward; loss[1] is
+ * 10 log10(1 / L).  The SSIM term of the paper's final loss is not included. */
+cgh_status cgh_backward_recon(cgh_ctx *ctx, const float *params, int32_t n,
+                              const cgh_c64 *field, const float *target, const float *mask,
+                              double *loss, cgh_c64 *grad_field, float *grads, void *stream);
+
 /* Adjoint of cgh_propagate's intensity for an arbitrary loss: given
  * grad_intensity = dL/dI ([L][C][H][W]) at I = |u(field)|^2, writes
  * grad_field = dL/dRe(field) + j dL/dIm(field) ([C][H][W]).  Recomputes u. */
@@ -163,6 +176,23 @@ cgh_status cgh_rasterize_adjoint(cgh_ctx *ctx, const float *params, int32_t n,
 cgh_status cgh_step(float *params, const float *grads, float *m, float *v, int64_t count,
                     int32_t t, float lr, float beta1, float beta2, float eps,
                     const float *lr_groups, int32_t channels, void *stream);
+
+/* Adan step (Xie et al., "Adan: Adaptive Nesterov Momentum Algorithm", Algorithm
+ * 1, with bias-corrected moments; the optimiser of Sec. 4) over `count` floats,
+ * in place, in the decay-rate convention (betas close to 1; the Adan paper's
+ * defaults are 0.98, 0.92, 0.99).  With diff = g - prev_grads (0 at t = 1):
+ *   m <- b1 m + (1 - b1) g;  d <- b2 d + (1 - b2) diff;
+ *   s <- b3 s + (1 - b3) (g + b2 diff)^2;
+ *   p <- p (1 - lr wd) - lr (m / (1 - b1^t) + b2 d / (1 - b2^t)) / (sqrt(s / (1 - b3^t)) + eps);
+ *   prev_grads <- g.
+ * m, d, s, prev_grads: caller-owned state of `count` floats (any contents at
+ * t = 1 except that m, d, s must be zero).  lr_groups / channels as cgh_step:
+ * per-block learning rates (e.g. the paper's position / scale / rotation /
+ * amplitude / phase / opacity rates, cosine-annealed by the caller). */
+cgh_status cgh_step_adan(float *params, const float *grads, float *m, float *d, float *s,
+                         float *prev_grads, int64_t count, int32_t t, float lr, float beta1,
+                         float beta2, float beta3, float eps, float weight_decay,
+                         const float *lr_groups, int32_t channels, void *stream);
 
 /* Copies the transfer function of (channel, plane) into `out`, a device array of
  * (Hp/2 + 1) x (Wp/2 + 1) complex: entry [qy][qx] is H at |fy| = qy / (Hp pitch),

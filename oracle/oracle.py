@@ -185,6 +185,24 @@ def mse(u, target):
     return loss, I, grad_u
 
 
+def recon(u, target, mask):
+    """L_recon of Sec. 3.2 with each squared norm a mean over its elements (the
+    reading taken for L_MSE): per plane ||I - T||^2 + ||I M - T M||^2 +
+    ||I T - T T||^2, averaged over planes.  mask [L, H, W] is shared by the
+    channels.  Returns (loss, intensity, grad_u), grad_u = dL/dRe(u) + j dL/dIm(u)."""
+    I = u.real ** 2 + u.imag ** 2
+    T = np.asarray(target, dtype=np.float64).reshape(I.shape)
+    Mk = np.asarray(mask, dtype=np.float64).reshape(I.shape[0], 1, I.shape[2], I.shape[3])
+    n = I.size
+    r = I - T
+    loss = float((np.sum(r * r) + np.sum((I * Mk - T * Mk) ** 2) + np.sum((I * T - T * T) ** 2))
+                 / n)
+    # d/dI of the three squared differences: 2 r (1 + M^2 + T^2)
+    dL_dI = 2.0 * r * (1.0 + Mk * Mk + T * T) / n
+    grad_u = dL_dI * 2.0 * u
+    return loss, I, grad_u
+
+
 def raster_adjoint(params, grad_field, opt):
     """Gradients of the pre-activation parameters from dL/dU0 (suppl. Backward Pass)."""
     p = widen(params)
@@ -202,30 +220,32 @@ def raster_adjoint(params, grad_field, opt):
     return out
 
 
-def forward(params, target, opt, support=None):
-    """Alg. 1 forward: rasterize -> pad -> propagate -> |u|^2 -> L_MSE."""
+def forward(params, target, opt, support=None, mask=None):
+    """Alg. 1 forward: rasterize -> pad -> propagate -> |u|^2 -> L_MSE (or
+    L_recon when a depth mask is given)."""
     field = raster(params, opt, support=support)
     u = propagate(field, opt)
-    loss, I, grad_u = mse(u, target)
+    loss, I, grad_u = mse(u, target) if mask is None else recon(u, target, mask)
     return {"field": field, "u": u, "intensity": I, "loss": loss, "grad_u": grad_u}
 
 
-def forward_backward(params, target, opt):
+def forward_backward(params, target, opt, mask=None):
     """Forward plus the analytic adjoint chain; returns the forward dict with
     ``grad_field`` (dL/dU0) and ``grads`` (pre-activation parameter gradients)."""
-    fwd = forward(params, target, opt)
+    fwd = forward(params, target, opt, mask=mask)
     fwd["grad_field"] = propagate_adjoint(fwd["grad_u"], opt)
     fwd["grads"] = raster_adjoint(params, fwd["grad_field"], opt)
     return fwd
 
 
-def loss_only(params, target, opt, support=None):
-    return forward(params, target, opt, support=support)["loss"]
+def loss_only(params, target, opt, support=None, mask=None):
+    return forward(params, target, opt, support=support, mask=mask)["loss"]
 
 
-def fd_gradient(params, target, opt, key, index, h=None):
-    """Central finite difference of L_MSE w.r.t. one pre-activation parameter
-    entry, in FP64, with the support held at the unperturbed parameters."""
+def fd_gradient(params, target, opt, key, index, h=None, mask=None):
+    """Central finite difference of the loss (L_MSE, or L_recon with a mask)
+    w.r.t. one pre-activation parameter entry, in FP64, with the support held
+    at the unperturbed parameters."""
     base = widen(params)
     flat = base[key].reshape(-1)
     x0 = float(flat[index])
@@ -235,8 +255,8 @@ def fd_gradient(params, target, opt, key, index, h=None):
     minus = {k: v.copy() for k, v in base.items()}
     plus[key].reshape(-1)[index] = x0 + h
     minus[key].reshape(-1)[index] = x0 - h
-    lp = loss_only(plus, target, opt, support=base)
-    lm = loss_only(minus, target, opt, support=base)
+    lp = loss_only(plus, target, opt, support=base, mask=mask)
+    lm = loss_only(minus, target, opt, support=base, mask=mask)
     return (lp - lm) / (2.0 * h)
 
 
@@ -248,6 +268,24 @@ def adam(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
     return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def adan(p, g, m, d, s, g_prev, t, lr, beta1=0.98, beta2=0.92, beta3=0.99, eps=1e-8,
+         weight_decay=0.0):
+    """Adan (Xie et al., Adan: Adaptive Nesterov Momentum Algorithm, Algorithm 1)
+    with bias-corrected moments, decay-rate convention, FP64.  The gradient
+    difference is taken as zero at the first step.  Returns (p, m, d, s, g)."""
+    p, g, m, d, s, g_prev = (np.asarray(a, dtype=np.float64) for a in (p, g, m, d, s, g_prev))
+    diff = np.zeros_like(g) if t == 1 else g - g_prev
+    m = beta1 * m + (1.0 - beta1) * g
+    d = beta2 * d + (1.0 - beta2) * diff
+    nesterov = g + beta2 * diff
+    s = beta3 * s + (1.0 - beta3) * nesterov * nesterov
+    m_hat = m / (1.0 - beta1 ** t)
+    d_hat = d / (1.0 - beta2 ** t)
+    s_hat = s / (1.0 - beta3 ** t)
+    p = p * (1.0 - lr * weight_decay) - lr * (m_hat + beta2 * d_hat) / (np.sqrt(s_hat) + eps)
+    return p, m, d, s, g
 
 
 def psnr(loss):

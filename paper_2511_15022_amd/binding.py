@@ -53,10 +53,16 @@ _SIGS = [
     ("cgh_rasterize", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
     ("cgh_propagate", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("cgh_backward", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("cgh_backward_recon", ctypes.c_int,
+     [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cgh_propagate_adjoint", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("cgh_rasterize_adjoint", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
     ("cgh_step", ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP, ctypes.c_int32, _VP]),
+    ("cgh_step_adan", ctypes.c_int,
+     [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
+      ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP,
+      ctypes.c_int32, _VP]),
     ("cgh_get_transfer", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP]),
     ("cgh_read_status", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_int64)]),
     ("cgh_profile_begin", ctypes.c_int, [_VP, ctypes.c_int32]),
@@ -209,7 +215,9 @@ class Context:
         _check(lib().cgh_propagate(self.handle, _ptr(field), _ptr(I), _ptr(u), _stream(self.device)))
         return I, u
 
-    def backward(self, params, n, field, target, loss=None, grad_field=None, grads=None):
+    def backward(self, params, n, field, target, loss=None, grad_field=None, grads=None,
+                 mask=None):
+        """L_MSE backward; with ``mask`` ([L][H][W]) the L_recon backward."""
         _need(params, torch.float32, param_count(n, self.C), "params", self.device)
         _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)
         _need(target, torch.float32, self.L * self.C * self.H * self.W, "target", self.device)
@@ -219,8 +227,16 @@ class Context:
             _need(loss, torch.float64, 2, "loss", self.device)
         if grad_field is not None:
             _need(grad_field, torch.complex64, self.C * self.H * self.W, "grad_field", self.device)
-        _check(lib().cgh_backward(self.handle, _ptr(params), int(n), _ptr(field), _ptr(target),
-                                  _ptr(loss), _ptr(grad_field), _ptr(grads), _stream(self.device)))
+        if mask is None:
+            _check(lib().cgh_backward(self.handle, _ptr(params), int(n), _ptr(field),
+                                      _ptr(target), _ptr(loss), _ptr(grad_field), _ptr(grads),
+                                      _stream(self.device)))
+        else:
+            _need(mask, torch.float32, self.L * self.H * self.W, "mask", self.device)
+            _check(lib().cgh_backward_recon(self.handle, _ptr(params), int(n), _ptr(field),
+                                            _ptr(target), _ptr(mask), _ptr(loss),
+                                            _ptr(grad_field), _ptr(grads),
+                                            _stream(self.device)))
         return grads
 
     def propagate_adjoint(self, field, grad_intensity, grad_field=None):
@@ -280,3 +296,19 @@ def step(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, lr_groups
                           float(lr), float(beta1), float(beta2), float(eps),
                           ctypes.cast(groups, ctypes.c_void_p) if groups is not None else None,
                           int(channels), _stream(params.device)))
+
+
+def step_adan(params, grads, m, d, s, prev_grads, t, lr, beta1=0.98, beta2=0.92, beta3=0.99,
+              eps=1e-8, weight_decay=0.0, lr_groups=None, channels=1):
+    """cgh_step_adan: in-place Adan over flat tensors of equal size."""
+    for name, x in (("grads", grads), ("m", m), ("d", d), ("s", s), ("prev_grads", prev_grads)):
+        _need(x, torch.float32, params.numel(), name, params.device)
+    _need(params, torch.float32, params.numel(), "params", params.device)
+    groups = None
+    if lr_groups is not None:
+        groups = (ctypes.c_float * 6)(*[float(x) for x in lr_groups])
+    _check(lib().cgh_step_adan(_ptr(params), _ptr(grads), _ptr(m), _ptr(d), _ptr(s),
+                               _ptr(prev_grads), params.numel(), int(t), float(lr), float(beta1),
+                               float(beta2), float(beta3), float(eps), float(weight_decay),
+                               ctypes.cast(groups, ctypes.c_void_p) if groups is not None else None,
+                               int(channels), _stream(params.device)))

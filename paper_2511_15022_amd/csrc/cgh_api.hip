@@ -337,16 +337,19 @@ cgh_status cgh_propagate(cgh_ctx *ctx, const cgh_c64 *field, float *intensity,
     st = plane_spectrum(c, l, s);
     if (st != CGH_OK) return st;
     ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
-    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, l, c.spec_plane, nullptr, nullptr, intensity,
-                                          reinterpret_cast<float2 *>(field_out), 0, s),
+    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, l, c.spec_plane, nullptr, nullptr, nullptr,
+                                          intensity, reinterpret_cast<float2 *>(field_out), 0,
+                                          s),
                      "intensity row pass");
   }
   return CGH_OK;
 }
 
-cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_c64 *field,
-                        const float *target, double *loss, cgh_c64 *grad_field, float *grads,
-                        void *stream) {
+// the fused loss and adjoint of cgh_backward / cgh_backward_recon
+static cgh_status backward_impl(cgh_ctx *ctx, const float *params, int32_t n,
+                                const cgh_c64 *field, const float *target, const float *mask,
+                                double *loss, cgh_c64 *grad_field, float *grads,
+                                void *stream) {
   if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
   Ctx &c = ctx->c;
   cgh_status st = check_n(c, n);
@@ -366,7 +369,7 @@ cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_
     if (st != CGH_OK) return st;
     {
       ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
-      CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, l, c.spec_plane, target, nullptr, nullptr,
+      CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, l, c.spec_plane, target, nullptr, mask, nullptr,
                                             nullptr, 1, s),
                        "loss row pass");
     }
@@ -380,6 +383,19 @@ cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_
   st = adjoint_rows(c, gf, s);
   if (st != CGH_OK) return st;
   return raster_adjoint(c, params, n, gf, grads, s);
+}
+
+cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_c64 *field,
+                        const float *target, double *loss, cgh_c64 *grad_field, float *grads,
+                        void *stream) {
+  return backward_impl(ctx, params, n, field, target, nullptr, loss, grad_field, grads, stream);
+}
+
+cgh_status cgh_backward_recon(cgh_ctx *ctx, const float *params, int32_t n,
+                              const cgh_c64 *field, const float *target, const float *mask,
+                              double *loss, cgh_c64 *grad_field, float *grads, void *stream) {
+  if (!mask) return fail(CGH_ERR_INVALID_ARG, "mask is NULL");
+  return backward_impl(ctx, params, n, field, target, mask, loss, grad_field, grads, stream);
 }
 
 cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
@@ -400,7 +416,7 @@ cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
     {
       ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
       CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, l, c.spec_plane, nullptr, grad_intensity,
-                                            nullptr, nullptr, 1, s),
+                                            nullptr, nullptr, nullptr, 1, s),
                        "adjoint seed row pass");
     }
     st = plane_adjoint(c, l, s);
@@ -422,6 +438,36 @@ cgh_status cgh_rasterize_adjoint(cgh_ctx *ctx, const float *params, int32_t n,
   if (!aligned16(grad_field)) return fail(CGH_ERR_INVALID_ARG, "misaligned grad_field");
   return raster_adjoint(c, params, n, reinterpret_cast<const float2 *>(grad_field), grads,
                         (hipStream_t)stream);
+}
+
+cgh_status cgh_step_adan(float *params, const float *grads, float *m, float *d, float *s,
+                         float *prev_grads, int64_t count, int32_t t, float lr, float beta1,
+                         float beta2, float beta3, float eps, float weight_decay,
+                         const float *lr_groups, int32_t channels, void *stream) {
+  if (count < 0) return fail(CGH_ERR_INVALID_ARG, "count < 0");
+  if (count == 0) return CGH_OK;
+  if (!params || !grads || !m || !d || !s || !prev_grads)
+    return fail(CGH_ERR_INVALID_ARG, "NULL buffer");
+  if (!aligned16(params) || !aligned16(grads) || !aligned16(m) || !aligned16(d) ||
+      !aligned16(s) || !aligned16(prev_grads))
+    return fail(CGH_ERR_INVALID_ARG, "buffers must be 16-byte aligned");
+  if (t < 1) return fail(CGH_ERR_INVALID_ARG, "step number t must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && beta3 >= 0.f &&
+        beta3 < 1.f && eps >= 0.f && weight_decay >= 0.f))
+    return fail(CGH_ERR_INVALID_ARG, "betas must be in [0, 1), eps and weight_decay >= 0");
+  int n = 0;
+  if (lr_groups) {
+    if (channels < 1 || channels > CGH_MAX_CHANNELS)
+      return fail(CGH_ERR_INVALID_ARG, "channels must be in [1, %d]", CGH_MAX_CHANNELS);
+    const int64_t per = 6 + 2 * channels;
+    if (count % per) return fail(CGH_ERR_INVALID_ARG, "count not a multiple of 6 + 2C");
+    n = (int)(count / per);
+  }
+  CGH_CHECK_LAUNCH(cgh::launch_adan(params, grads, m, d, s, prev_grads, count, t, lr, beta1,
+                                    beta2, beta3, eps, weight_decay, lr_groups, n, channels,
+                                    (hipStream_t)stream),
+                   "adan");
+  return CGH_OK;
 }
 
 cgh_status cgh_step(float *params, const float *grads, float *m, float *v, int64_t count,

@@ -110,9 +110,10 @@ hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStrea
 // column pass of plane `plane`: src -> dst (may alias); acc adds into dst
 hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *src, float2 *dst,
                            int acc, hipStream_t s);
+// mask (optional, [L][H][W]): the L_recon weight 1 + mask^2 + target^2
 hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *target,
-                           const float *grad_intensity, float *intensity, float2 *u_out,
-                           int make_grad, hipStream_t s);
+                           const float *grad_intensity, const float *mask, float *intensity,
+                           float2 *u_out, int make_grad, hipStream_t s);
 hipError_t launch_loss_finalize(const Ctx &c, double *loss, hipStream_t s);
 
 hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s);
@@ -123,6 +124,9 @@ hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStre
 hipError_t launch_preprocess_adjoint(const Ctx &c, const float *params, int n, float *grads,
                                      hipStream_t s);
 
+hipError_t launch_adan(float *p, const float *g, float *m, float *d, float *s, float *gprev,
+                       int64_t count, int t, float lr, float b1, float b2, float b3, float eps,
+                       float wd, const float *lr_groups, int n, int C, hipStream_t st);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr,
                        float step_size_scale, float beta1, float beta2, float eps,
                        float inv_sqrt_bc2, const float *lr_groups, int n, int C,

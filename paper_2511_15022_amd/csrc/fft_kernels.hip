@@ -371,8 +371,8 @@ template <int MAXN>
 __global__ __launch_bounds__(kRowThreads) void k_row_loss(
     float2 *__restrict__ S, int H, int W, int Wt, FftPlan p, const float2 *__restrict__ twx,
     const float *__restrict__ target, const float *__restrict__ grad_I,
-    float *__restrict__ intensity, float2 *__restrict__ u_out, double *__restrict__ loss_part,
-    float gscale, int make_grad) {
+    const float *__restrict__ mask, float *__restrict__ intensity, float2 *__restrict__ u_out,
+    double *__restrict__ loss_part, float gscale, int make_grad) {
   extern __shared__ float2 sbuf[];
   __shared__ TwLds tw;
   __shared__ double red[kRowThreads / 64];
@@ -395,9 +395,12 @@ __global__ __launch_bounds__(kRowThreads) void k_row_loss(
       if (u_out) u_out[o] = u;
       float f = 0.f;
       if (target) {
-        const float d = I - target[o];
-        acc += (double)d * (double)d;
-        f = gscale * d;  // 4 (I - T) / M
+        const float t = target[o], d = I - t;
+        // L_recon weight 1 + m^2 + t^2 (plain MSE without a mask)
+        const float w = mask ? 1.f + mask[(size_t)y * W + x] * mask[(size_t)y * W + x] + t * t
+                             : 1.f;
+        acc += (double)d * (double)d * (double)w;
+        f = gscale * d * w;  // 4 w (I - T) / M
       } else if (grad_I) {
         f = 2.0f * grad_I[o];
       }
@@ -533,8 +536,9 @@ template <int N, int ROWS, int T, bool FULL>
 __global__ __launch_bounds__(T) void k_row_loss_c(
     float2 *__restrict__ S, int H, int W, int Wt, const float2 *__restrict__ twf,
     const float2 *__restrict__ tw2, const float *__restrict__ target,
-    const float *__restrict__ grad_I, float *__restrict__ intensity, float2 *__restrict__ u_out,
-    double *__restrict__ loss_part, float gscale, int make_grad) {
+    const float *__restrict__ grad_I, const float *__restrict__ mask,
+    float *__restrict__ intensity, float2 *__restrict__ u_out, double *__restrict__ loss_part,
+    float gscale, int make_grad) {
   __shared__ float2 sbuf[ROWS * N];
   __shared__ RowTw<N, FULL> tw;
   __shared__ double red[T / 64];
@@ -549,12 +553,13 @@ __global__ __launch_bounds__(T) void k_row_loss_c(
   // before the transform (whose barriers do not wait for global loads) so
   // that the loads overlap it
   const float *tsrc = target ? target : grad_I;
-  float tv[KT];
+  float tv[KT], mv[KT];
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     const int i = min(tid + k * T, nw - 1);
-    const int b = row_of<ROWS>(i, W), x = i - b * W;
-    tv[k] = tsrc ? tsrc[((size_t)c * H + min(y0 + b, H - 1)) * W + x] : 0.f;
+    const int b = row_of<ROWS>(i, W), x = i - b * W, y = min(y0 + b, H - 1);
+    tv[k] = tsrc ? tsrc[((size_t)c * H + y) * W + x] : 0.f;
+    mv[k] = mask ? mask[(size_t)y * W + x] : 0.f;
   }
   lds_sync();
   tw.template fft<+1, ROWS, T>(sbuf, tid);
@@ -572,9 +577,10 @@ __global__ __launch_bounds__(T) void k_row_loss_c(
         if (u_out) u_out[o] = u;
         float f = 0.f;
         if (target) {
-          const float d = I - tv[k];
-          acc += (double)d * (double)d;
-          f = gscale * d;  // 4 (I - T) / M
+          // L_recon weight 1 + m^2 + t^2 (plain MSE without a mask)
+          const float d = I - tv[k], w = mask ? 1.f + mv[k] * mv[k] + tv[k] * tv[k] : 1.f;
+          acc += (double)d * (double)d * (double)w;
+          f = gscale * d * w;  // 4 w (I - T) / M
         } else if (grad_I) {
           f = 2.0f * tv[k];
         }
@@ -645,8 +651,8 @@ hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStrea
 }
 
 hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *target,
-                           const float *grad_intensity, float *intensity, float2 *u_out,
-                           int make_grad, hipStream_t s) {
+                           const float *grad_intensity, const float *mask, float *intensity,
+                           float2 *u_out, int make_grad, hipStream_t s) {
   const double M = (double)c.L * c.C * c.H * c.W;
   const float gscale = (float)(4.0 / M);
   // plane l of the [L][C][H][W] arrays; its loss partials after those of planes < l
@@ -655,22 +661,23 @@ hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *ta
   if (grad_intensity) grad_intensity += po;
   if (intensity) intensity += po;
   if (u_out) u_out += po;
+  if (mask) mask += (size_t)plane * c.H * c.W;  // [L][H][W]
   double *lp = c.loss_part + (size_t)plane * row_blocks(c);
   if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_loss_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
-                       buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, intensity,
+                       buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, mask, intensity,
                        u_out, lp, gscale, make_grad);
   else if (c.Wp == 512)
     hipLaunchKernelGGL((k_row_loss_c<512, 4, 256, true>), dim3(row_blocks(c)), dim3(256), 0, s,
-                       buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, intensity,
+                       buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, mask, intensity,
                        u_out, lp, gscale, make_grad);
   else if (c.Wp <= 4096)
     hipLaunchKernelGGL(k_row_loss<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
-                       buf, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity,
+                       buf, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity, mask,
                        intensity, u_out, lp, gscale, make_grad);
   else
     hipLaunchKernelGGL(k_row_loss<8192>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
-                       buf, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity,
+                       buf, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity, mask,
                        intensity, u_out, lp, gscale, make_grad);
   return hipGetLastError();
 }
@@ -915,27 +922,30 @@ __global__ __launch_bounds__(T) void k_col_half_c(ColIO io, int H, int Wp, int W
   }
 }
 
-// Column pass over half a tile (4 columns) per workgroup, two workgroups per
-// CU so that one's LDS traffic overlaps the other's arithmetic.  Blocks come in
-// groups of 16 covering 8 tiles; the two halves of a tile are 8 blocks apart,
-// so they land on the same XCD at about the same time and share its L2 lines.
-template <int M, int T>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_col_quad(
+// Column pass over part of a tile (CB of its 8 columns) per workgroup, with
+// several workgroups per CU so that one's LDS traffic overlaps another's
+// arithmetic.  Blocks come in groups of 8 * (8 / CB) covering 8 tiles; the
+// parts of a tile are 8 blocks apart, so they land on the same XCD at about
+// the same time and share its L2 lines.
+template <int M, int T, int CB>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_col_part(
     ColIO io, int H, int Wp, int Wt, int ntiles, const float2 *__restrict__ twf_m,
     const float2 *__restrict__ twh, int Wq, int conj_h, float scale) {
-  constexpr int CB = 4;
+  static_assert(CB == 2 || CB == 4 || CB == 8, "columns per workgroup");
+  constexpr int SH = CB == 2 ? 1 : (CB == 4 ? 2 : 3);
+  constexpr int P = 8 / CB;
   __shared__ float2 sbuf[CB * M];
   __shared__ float2 tw[M];
   __shared__ TwLds th;
   constexpr int K = (CB * M + T - 1) / T;
   constexpr int total = CB * M;
   const int tid = threadIdx.x;
-  const int b = blockIdx.x, within = b & 15;
-  const int h = within >> 3, tl = (b >> 4) * 8 + (within & 7);
+  const int b = blockIdx.x, within = b % (8 * P);
+  const int part = within >> 3, tl = (b / (8 * P)) * 8 + (within & 7);
   if (tl >= ntiles) return;
   const int ch = tl / Wt, t = tl - ch * Wt;
-  const int col0 = t * 8 + h * CB;
-  const size_t off = (size_t)tl * H * 8 + h * CB;
+  const int col0 = t * 8 + part * CB;
+  const size_t off = (size_t)tl * H * 8 + part * CB;
   const float2 *base = io.src + off;
   const float2 *hc = io.htab + ch * io.hstride;
   load_table<M, T>(tw, twf_m, tid);
@@ -943,8 +953,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_c
   float2 x[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, n = i >> 2;
-    x[k] = base[(size_t)min(n, H - 1) * 8 + (i & 3)];
+    const int i = tid + k * T, n = i >> SH;
+    x[k] = base[(size_t)min(n, H - 1) * 8 + (i & (CB - 1))];
     if (n >= H || !(total % T == 0 || i < total)) x[k] = make_float2(0.f, 0.f);
   }
   __syncthreads();  // the twiddle tables are read below
@@ -955,18 +965,19 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_c
     keep[k] = make_float2(0.f, 0.f);
     if (total % T == 0 || i < total) {
       sbuf[i] = x[k];
-      keep[k] = cmul(x[k], tw_at(th, i >> 2));
+      keep[k] = cmul(x[k], tw_at(th, i >> SH));
     }
   }
   __syncthreads();
   for (int parity = 0; parity < 2; ++parity) {
     cfft<-1, CB, T, M>(sbuf, tw, tid);
     {
+      // all table loads of a thread are issued before the first is used
       float2 hv[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int i = tid + k * T;
-        const int kx = col0 + (i & 3), ky = 2 * min(i >> 2, M - 1) + parity;
+        const int kx = col0 + (i & (CB - 1)), ky = 2 * min(i >> SH, M - 1) + parity;
         const int qx = min(kx, Wp - kx), qy = min(ky, 2 * M - ky);
         hv[k] = hc[(uint32_t)(qy * Wq + qx)];
       }
@@ -997,9 +1008,10 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_c
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, n = i >> 2;
+    const int i = tid + k * T, n = i >> SH;
     if ((total % T == 0 || i < total) && n < H)
-      col_store(io, off + (size_t)n * 8 + (i & 3), cadd(keep[k], cmul(cconj(tw_at(th, n)), sbuf[i])));
+      col_store(io, off + (size_t)n * 8 + (i & (CB - 1)),
+                cadd(keep[k], cmul(cconj(tw_at(th, n)), sbuf[i])));
   }
 }
 
@@ -1010,10 +1022,11 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
   const ColIO io{src, dst, c.htab + (size_t)plane * tab, (size_t)c.L * tab, acc};
   dim3 grid(c.Wt, c.C);
   if (c.Hp == 2160 && c.H <= 1080 && c.Wp % 8 == 0) {
+    constexpr int CB = 4;  // columns per workgroup: two workgroups per tile
     const int ntiles = c.Wt * c.C;
-    const int blocks = (ntiles + 7) / 8 * 16;
-    hipLaunchKernelGGL((k_col_quad<1080, 512>), dim3(blocks), dim3(512), 0, s, io, c.H, c.Wp,
-                       c.Wt, ntiles, c.twf_m, c.tw_y, c.Wq, conj_h, scale);
+    const int blocks = (ntiles + 7) / 8 * 8 * (8 / CB);
+    hipLaunchKernelGGL((k_col_part<1080, 512, CB>), dim3(blocks), dim3(512), 0, s, io, c.H,
+                       c.Wp, c.Wt, ntiles, c.twf_m, c.tw_y, c.Wq, conj_h, scale);
   } else if (c.Hp == 2160) {
     hipLaunchKernelGGL((k_col_half_c<1080, 1024>), grid, dim3(1024), 0, s, io, c.H, c.Wp, c.Wt,
                        c.twf_m, c.tw_y, c.Wq, conj_h, scale);

@@ -165,9 +165,13 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *t
   return off + incl - v;
 }
 
+// per-block exclusive scans of kScanItems elements and the block sums; also
+// clears *zero_word (if given), which lets the binning skip a launch
 __global__ __launch_bounds__(256) void k_scan_local(const uint32_t *__restrict__ in,
                                                     uint32_t *__restrict__ out, int len,
-                                                    uint32_t *__restrict__ block_sums) {
+                                                    uint32_t *__restrict__ block_sums,
+                                                    uint32_t *__restrict__ zero_word) {
+  if (zero_word && blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;
   const int base = blockIdx.x * kScanItems + threadIdx.x * 8;
   uint32_t v[8];
   uint32_t s = 0;
@@ -218,7 +222,7 @@ static hipError_t scan_u32(const uint32_t *in, uint32_t *out, int len, uint32_t 
                            uint32_t *total, uint32_t *total2, hipStream_t s) {
   const int nb = (len + kScanItems - 1) / kScanItems;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, in, out, len, tmp);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, in, out, len, tmp, nullptr);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, tmp, nb, total, total2);
   hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, s, out, len, tmp);
   return hipGetLastError();
@@ -227,8 +231,12 @@ static hipError_t scan_u32(const uint32_t *in, uint32_t *out, int len, uint32_t 
 // ----------------------------------------------------------------------------
 // Binning: emit (tile, gaussian) pairs, stable radix sort, tile ranges.
 // ----------------------------------------------------------------------------
+// Pairs of Gaussian g go to [offset(g), offset(g) + count(g)) in row-major
+// tile order.  offsets[] holds per-chunk exclusive scans and chunk_prefix the
+// scanned chunk sums; the final offset is written back for the adjoint.
 __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict__ counts,
-                                              const uint32_t *__restrict__ offsets,
+                                              uint32_t *__restrict__ offsets,
+                                              const uint32_t *__restrict__ chunk_prefix,
                                               const uint2 *__restrict__ rect, int tiles_x,
                                               int64_t cap, uint32_t *__restrict__ keys,
                                               uint32_t *__restrict__ vals,
@@ -236,11 +244,12 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const uint32_t cnt = counts[g];
+  const uint32_t off32 = offsets[g] + chunk_prefix[g / kScanItems];
+  offsets[g] = off32;
   if (cnt == 0) return;
-  const uint64_t off = offsets[g];
+  const uint64_t off = off32;
   const uint2 rc = rect[g];
   const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
-  const uint32_t w = tx1 - tx0 + 1;
   uint32_t tx = tx0, ty = ty0;
   for (uint32_t t = 0; t < cnt; ++t) {
     const uint64_t pos = off + t;
@@ -252,7 +261,6 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
     vals[pos] = (uint32_t)g;
     if (++tx > tx1) { tx = tx0; ++ty; }
   }
-  (void)w;
 }
 
 __device__ __forceinline__ uint32_t pair_count(const uint32_t *status, int64_t cap) {
@@ -292,14 +300,21 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
 // bits).  The waves of a block then add the counts of earlier waves, and the
 // blocks the exclusive scan of the digit-major histogram: equal keys keep
 // their order.
+// hist_scan holds the digit-major histogram scanned either globally
+// (chunk_sums == nullptr) or per chunk of kScanItems, with the chunk sums in
+// chunk_sums (at most kMaxScanChunks); then each block scans the chunk sums.
+constexpr int kMaxScanChunks = 1024;
+
 __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
     const uint32_t *__restrict__ status, int64_t cap, int shift,
-    const uint32_t *__restrict__ hist_scan, int nblocks) {
+    const uint32_t *__restrict__ hist_scan, int nblocks,
+    const uint32_t *__restrict__ chunk_sums, int nchunks) {
   constexpr int R = kSortItems / 256;  // rounds of 64 keys per wave
   __shared__ uint32_t wcnt[4][256];
   __shared__ uint32_t woff[4][256];
+  __shared__ uint32_t cpre[kMaxScanChunks];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t count = pair_count(status, cap);
   const uint32_t base = blockIdx.x * kSortItems;
@@ -334,9 +349,24 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     // wave's LDS accesses complete in order, so the next round reads it
     if (valid && before == 0) wcnt[wave][d] = prev + (uint32_t)__popcll(m);
   }
+  if (chunk_sums) {
+    // exclusive scan of the chunk sums, four per thread
+    uint32_t c4[4], sum = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = tid * 4 + e;
+      c4[e] = sum;
+      sum += i < nchunks ? chunk_sums[i] : 0u;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(sum, &tot);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) cpre[tid * 4 + e] = ex + c4[e];
+  }
   __syncthreads();
   {
-    uint32_t run = hist_scan[(size_t)tid * nblocks + blockIdx.x];
+    const size_t e = (size_t)tid * nblocks + blockIdx.x;
+    uint32_t run = hist_scan[e] + (chunk_sums ? cpre[e / kScanItems] : 0u);
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
       woff[w][tid] = run;
@@ -357,20 +387,30 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
   }
 }
 
-__global__ void k_fill_ranges(uint2 *__restrict__ ranges, int num_tiles) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < num_tiles) ranges[t] = make_uint2(0u, 0u);
-}
-
+// Tile ranges from the sorted keys; each tile without pairs gets an empty
+// range from the thread at the gap it falls in (every tile is written once).
 __global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ status,
                          int64_t cap, uint2 *__restrict__ ranges, uint32_t num_tiles) {
   const uint32_t count = pair_count(status, cap);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (count == 0) {
+    if (i == 0)
+      for (uint32_t t = 0; t < num_tiles; ++t) ranges[t] = make_uint2(0u, 0u);
+    return;
+  }
   if (i >= count) return;
   const uint32_t k = keys[i];
-  if (k >= num_tiles) return;  // keys are tile ids; guards the write
-  if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
-  if (i + 1 == count || keys[i + 1] != k) ranges[k].y = i + 1;
+  if (k >= num_tiles) return;  // keys are tile ids; guards the writes
+  if (i == 0 || keys[i - 1] != k) {
+    ranges[k].x = i;
+    const uint32_t prev = i == 0 ? 0u : keys[i - 1] + 1u;
+    for (uint32_t t = prev; t < k; ++t) ranges[t] = make_uint2(0u, 0u);
+  }
+  if (i + 1 == count || keys[i + 1] != k) {
+    ranges[k].y = i + 1;
+    if (i + 1 == count)
+      for (uint32_t t = k + 1; t < num_tiles; ++t) ranges[t] = make_uint2(0u, 0u);
+  }
 }
 
 // the record after the last Gaussian slot: all zeros (zero amplitude), used to
@@ -391,29 +431,43 @@ __global__ void k_zero_u32(uint32_t *p, int len) {
 }
 
 hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
-  // status[0] (overflow) and status[1] (pair total) restart at zero
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c.status, 4);
+  // status[0] (overflow) and status[1] (pair total) restart at zero: the
+  // first scan kernel clears the flag and the chunk-sum scan writes the total
   if (n > 0) {
-    hipError_t e = scan_u32(c.counts, c.offsets, n, c.scan_tmp, c.offsets + n, c.status + 1, s);
-    if (e != hipSuccess) return e;
+    const int nb = (n + kScanItems - 1) / kScanItems;
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, c.counts, c.offsets, n,
+                       c.scan_tmp, c.status);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, c.scan_tmp, nb, c.offsets + n,
+                       c.status + 1);
     hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, s, n, c.counts, c.offsets,
-                       c.rect, c.tiles_x, c.pair_cap, c.keys[0], c.vals[0], c.status);
+                       c.scan_tmp, c.rect, c.tiles_x, c.pair_cap, c.keys[0], c.vals[0],
+                       c.status);
+  } else {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c.status, 4);
   }
+  const int hlen = 256 * c.sort_blocks;
+  const int nchunks = (hlen + kScanItems - 1) / kScanItems;
   int cur = 0;
   for (int pass = 0; pass < c.sort_passes; ++pass) {
     const int shift = pass * kSortBits;
     hipLaunchKernelGGL(k_radix_hist, dim3(c.sort_blocks), dim3(256), 0, s, c.keys[cur],
                        c.status, c.pair_cap, shift, c.hist, c.sort_blocks);
-    hipError_t e = scan_u32(c.hist, c.hist, 256 * c.sort_blocks, c.scan_tmp, nullptr, nullptr, s);
-    if (e != hipSuccess) return e;
+    const uint32_t *chunks = nullptr;
+    if (nchunks <= kMaxScanChunks) {
+      // per-chunk scans only; each scatter block scans the chunk sums itself
+      hipLaunchKernelGGL(k_scan_local, dim3(nchunks), dim3(256), 0, s, c.hist, c.hist, hlen,
+                         c.scan_tmp, nullptr);
+      chunks = c.scan_tmp;
+    } else {
+      hipError_t e = scan_u32(c.hist, c.hist, hlen, c.scan_tmp, nullptr, nullptr, s);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_radix_scatter, dim3(c.sort_blocks), dim3(256), 0, s, c.keys[cur],
                        c.vals[cur], c.keys[cur ^ 1], c.vals[cur ^ 1], c.status, c.pair_cap,
-                       shift, c.hist, c.sort_blocks);
+                       shift, c.hist, c.sort_blocks, chunks, nchunks);
     cur ^= 1;
   }
   c.sorted = cur;
-  hipLaunchKernelGGL(k_fill_ranges, dim3((c.num_tiles + 255) / 256), dim3(256), 0, s, c.ranges,
-                     c.num_tiles);
   const int64_t grid = (c.pair_cap + 255) / 256;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, s, c.keys[cur], c.status,
                      c.pair_cap, c.ranges, (uint32_t)c.num_tiles);

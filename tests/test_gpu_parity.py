@@ -391,3 +391,53 @@ def test_rgb_1080p_full_size_parity(O):
     for k, e in group_errors(grads.cpu().numpy(), ref["grads"], n, C).items():
         say("grad", k, e)
         assert e <= GRAD_TOL, (k, e)
+
+
+def test_recon_loss_parity(O):
+    """The L_recon backward (Sec. 3.2; depth masks per plane) against the
+    oracle: loss, dL/dU0 and the parameter gradients, two planes."""
+    say("L_recon backward")
+    H, W, C, n = 48, 80, 3, 500
+    lambdas, zs = [639e-9, 515e-9, 473e-9], [4e-3, 6e-3]
+    p = synth.params(61, n, H, W, C)
+    T = synth.target(62, C, H, W, L=2) * np.float32(0.5)
+    M = (np.random.default_rng(63).uniform(0, 1, (2, H, W)) > 0.5).astype(np.float32)
+    opt = O.Optics(H, W, C, 90, 160, 8e-6, lambdas, zs)
+    ctx = binding.Context(H, W, C, 8e-6, lambdas, zs, pad=(90, 160), max_gaussians=n)
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss, grad_field=gfield,
+                         mask=torch.from_numpy(M).cuda())
+    ref = O.forward_backward(p, T, opt, mask=M)
+    lg = loss.cpu().numpy()
+    assert abs(lg[0] - ref["loss"]) <= 1e-4 * ref["loss"]
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
+    for k, e in group_errors(grads.cpu().numpy(), ref["grads"], n, C).items():
+        assert e <= GRAD_TOL, (k, e)
+
+
+def test_adan_step_matches_oracle(O):
+    """Adan (the paper's optimiser, Sec. 4) over four steps with changing
+    gradients and per-group learning rates, against the FP64 oracle."""
+    say("adan")
+    rng = np.random.default_rng(5)
+    n, C = 37, 3
+    cnt = binding.param_count(n, C)
+    p0 = rng.standard_normal(cnt).astype(np.float32)
+    lrs = [1e-2, 5e-3, 1e-3, 2.5e-3, 2.5e-3, 2.5e-2]
+    P = torch.from_numpy(p0).cuda()
+    Mt, Dt, St, Gt = (torch.zeros(cnt, device="cuda") for _ in range(4))
+    sizes = [2 * n, 2 * n, n, C * n, C * n, n]
+    lr_vec = np.concatenate([np.full(sz, lr) for sz, lr in zip(sizes, lrs)])
+    pp = p0.astype(np.float64)
+    mm = dd = ss = gp = np.zeros(cnt)
+    for t in range(1, 5):
+        g = rng.standard_normal(cnt).astype(np.float32)
+        binding.step_adan(P, torch.from_numpy(g).cuda(), Mt, Dt, St, Gt, t, 0.0,
+                          lr_groups=lrs, channels=C)
+        pp, mm, dd, ss, gp = O.adan(pp, g, mm, dd, ss, gp, t, lr_vec)
+    assert np.max(np.abs(P.cpu().numpy() - pp)) < 1e-5
+    assert np.max(np.abs(Mt.cpu().numpy() - mm)) < 1e-6
+    assert np.max(np.abs(Dt.cpu().numpy() - dd)) < 1e-6
