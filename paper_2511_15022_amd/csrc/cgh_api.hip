@@ -148,6 +148,9 @@ size_t carve(Ctx *c, char *base) {
   c->twf_x = (float2 *)take(sizeof(float2) * c->Wp);
   c->twf_m = (float2 *)take(sizeof(float2) * c->plan_m.n);
   c->htab = (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq);
+  c->htab_t = col_wave(*c) ? (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq)
+                           : nullptr;
+  c->twf_y = col_wave(*c) ? (float2 *)take(sizeof(float2) * c->Hp) : nullptr;
   const size_t spec_len = (size_t)c->C * c->Wt * c->H * 8;
   c->spec = (float2 *)take(sizeof(float2) * spec_len);
   // with several planes the shared row spectrum stays in spec; each plane's
@@ -224,6 +227,7 @@ cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_b
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_m, c.plan_m.n, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_x, c.Wp, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_m, c.plan_m.n, s), "twiddles");
+  if (c.twf_y) CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_y, c.Hp, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, s), "transfer function");
   CGH_CHECK_LAUNCH(cgh::launch_zero_record(c, s), "zero record");
   hipError_t e = hipStreamSynchronize(s);

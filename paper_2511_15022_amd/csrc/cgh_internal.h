@@ -74,6 +74,8 @@ struct Ctx {
   float2 *tw_x, *tw_y, *tw_m;       // two-level twiddle tables for Wp, Hp, Hp/2
   float2 *twf_x, *twf_m;            // full twiddle tables for Wp and Hp/2 (Hp if odd)
   float2 *htab;                     // [C][L][Hq][Wq]
+  float2 *htab_t;                   // [C][L][Wq][Hq] (column-major copy), wave column pass only
+  float2 *twf_y;                    // full twiddle table for Hp, wave column pass only
   float2 *spec;                     // [C][Wt][H][8] column-tiled propagation buffer
   float2 *spec_plane;               // per-plane column-pass output (spec itself when L = 1)
   float2 *spec_acc;                 // adjoint sum over planes (spec itself when L = 1)
@@ -99,6 +101,10 @@ struct Ctx {
 constexpr int kMaxProf = 256;
 
 size_t carve(Ctx *c, char *base);   // returns bytes used (base may be null)
+
+// The column pass runs one wave per column chain (k_col_wave) for Hp = 2160
+// with every column tile full; it reads the column-major transfer table.
+inline bool col_wave(const Ctx &c) { return c.Hp == 2160 && c.H <= 1080 && c.Wp % 8 == 0; }
 
 // ---- launchers (all enqueue on `s`; return hipSuccess or the launch error) ----
 hipError_t launch_build_twiddles(float2 *tw, int n, hipStream_t s);

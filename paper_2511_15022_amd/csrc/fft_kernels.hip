@@ -209,8 +209,9 @@ hipError_t launch_build_twiddles_full(float2 *tw, int n, hipStream_t s) {
 // "Spatial Frequency Computation", "Bandlimit Computation", "Transfer Function
 // Evaluation"), quarter table indexed by |fx| = qx / (Wp dx), |fy| = qy / (Hp dx).
 // L_x, L_y are the extents of the padded grid.  Evanescent frequencies get 0.
-__global__ void k_transfer(float2 *out, int Hq, int Wq, int Hp, int Wp, double pitch,
-                           double lambda, double z) {
+// out_t (optional) receives the same table column-major, [Wq][Hq].
+__global__ void k_transfer(float2 *out, float2 *out_t, int Hq, int Wq, int Hp, int Wp,
+                           double pitch, double lambda, double z) {
   int qx = blockIdx.x * blockDim.x + threadIdx.x;
   int qy = blockIdx.y;
   if (qx >= Wq) return;
@@ -228,15 +229,16 @@ __global__ void k_transfer(float2 *out, int Hq, int Wq, int Hp, int Wp, double p
     h = make_float2((float)cs, (float)sn);
   }
   out[(size_t)qy * Wq + qx] = h;
+  if (out_t) out_t[(size_t)qx * Hq + qy] = h;
 }
 
 hipError_t launch_build_transfer(const Ctx &c, hipStream_t s) {
   for (int ch = 0; ch < c.C; ++ch)
     for (int l = 0; l < c.L; ++l) {
-      float2 *dst = c.htab + ((size_t)ch * c.L + l) * c.Hq * c.Wq;
-      hipLaunchKernelGGL(k_transfer, dim3((c.Wq + 255) / 256, c.Hq), dim3(256), 0, s, dst,
-                         c.Hq, c.Wq, c.Hp, c.Wp, c.cfg.pitch_m, c.cfg.wavelength_m[ch],
-                         c.cfg.z_m[l]);
+      const size_t at = ((size_t)ch * c.L + l) * c.Hq * c.Wq;
+      hipLaunchKernelGGL(k_transfer, dim3((c.Wq + 255) / 256, c.Hq), dim3(256), 0, s,
+                         c.htab + at, c.htab_t ? c.htab_t + at : nullptr, c.Hq, c.Wq, c.Hp,
+                         c.Wp, c.cfg.pitch_m, c.cfg.wavelength_m[ch], c.cfg.z_m[l]);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -922,96 +924,128 @@ __global__ __launch_bounds__(T) void k_col_half_c(ColIO io, int H, int Wp, int W
   }
 }
 
-// Column pass over part of a tile (CB of its 8 columns) per workgroup, with
-// several workgroups per CU so that one's LDS traffic overlaps another's
-// arithmetic.  Blocks come in groups of 8 * (8 / CB) covering 8 tiles; the
-// parts of a tile are 8 blocks apart, so they land on the same XCD at about
-// the same time and share its L2 lines.
-template <int M, int T, int CB>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_col_part(
-    ColIO io, int H, int Wp, int Wt, int ntiles, const float2 *__restrict__ twf_m,
-    const float2 *__restrict__ twh, int Wq, int conj_h, float scale) {
-  static_assert(CB == 2 || CB == 4 || CB == 8, "columns per workgroup");
-  constexpr int SH = CB == 2 ? 1 : (CB == 4 ? 2 : 3);
-  constexpr int P = 8 / CB;
-  __shared__ float2 sbuf[CB * M];
+// ----------------------------------------------------------------------------
+// Column pass with one wave per chain, for M = Hp / 2 = R0 R1 R2 (1080 = 9 6 20).
+// A workgroup takes four columns of a tile; wave 2c + p runs chain p (even,
+// odd) of column c in its own M-element LDS buffer, so the stages of a chain
+// need no workgroup barrier: only loading the columns and combining the two
+// chains of a column are workgroup steps.  The forward plan is R0, R1, R2;
+// its last stage leaves lane j < M / R2 holding spectrum entries j + (M/R2) q
+// (q < R2), which is exactly the input of a first inverse stage of radix R2,
+// so the transfer multiply and that stage run in registers.  The inverse plan
+// is R2, R1, R0.  The transfer table is read column-major ([Wq][Hq]), and the
+// workgroups of a mirror pair of tiles (t, Wt - 1 - t), whose columns need the
+// same table columns, run back to back on one XCD (blocks b, b + 8, b + 16,
+// b + 24 share an XCD).
+// ----------------------------------------------------------------------------
+template <int R0, int R1, int R2>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_col_wave(
+    ColIO io, const float2 *__restrict__ htab_t, int Hq, int H, int Wp, int Wt, int C,
+    const float2 *__restrict__ twf_m, const float2 *__restrict__ twf_y, int conj_h,
+    float scale) {
+  constexpr int M = R0 * R1 * R2;
+  constexpr int NB2 = M / R2;
+  static_assert(NB2 <= 64, "the fused stage takes one butterfly per lane");
+  constexpr int T = 512, K = (4 * M + T - 1) / T, KT = (M + T - 1) / T;
+  __shared__ float2 buf[8 * M];
   __shared__ float2 tw[M];
-  __shared__ TwLds th;
-  constexpr int K = (CB * M + T - 1) / T;
-  constexpr int total = CB * M;
-  const int tid = threadIdx.x;
-  const int b = blockIdx.x, within = b % (8 * P);
-  const int part = within >> 3, tl = (b / (8 * P)) * 8 + (within & 7);
-  if (tl >= ntiles) return;
-  const int ch = tl / Wt, t = tl - ch * Wt;
-  const int col0 = t * 8 + part * CB;
-  const size_t off = (size_t)tl * H * 8 + part * CB;
-  const float2 *base = io.src + off;
-  const float2 *hc = io.htab + ch * io.hstride;
-  load_table<M, T>(tw, twf_m, tid);
-  load_tw<T>(th, twh, tid);
-  float2 x[K];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int b = blockIdx.x;
+  const int slot = (b >> 3) & 3, pi = (b >> 5) * 8 + (b & 7);
+  const int hp = (Wt + 1) >> 1;
+  if (pi >= C * hp) return;
+  const int ch = pi / hp, pp = pi - ch * hp;
+  const int t = slot < 2 ? pp : Wt - 1 - pp;
+  if (slot >= 2 && t == pp) return;  // the middle tile of an odd count has no mirror
+  const int part = slot & 1;
+  const size_t off = ((size_t)ch * Wt + t) * H * 8 + part * 4;
+  const float2 *src = io.src + off;
+  {
+    // every global load of this phase is issued before the first LDS store
+    float2 xv[K], wv[K], tv[KT];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, n = i >> SH;
-    x[k] = base[(size_t)min(n, H - 1) * 8 + (i & (CB - 1))];
-    if (n >= H || !(total % T == 0 || i < total)) x[k] = make_float2(0.f, 0.f);
-  }
-  __syncthreads();  // the twiddle tables are read below
-  float2 keep[K];
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T, n = min(i >> 2, M - 1);
+      xv[k] = src[(uint32_t)(min(n, H - 1) * 8 + (i & 3))];
+      wv[k] = twf_y[n];
+    }
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T;
-    keep[k] = make_float2(0.f, 0.f);
-    if (total % T == 0 || i < total) {
-      sbuf[i] = x[k];
-      keep[k] = cmul(x[k], tw_at(th, i >> SH));
+    for (int k = 0; k < KT; ++k) tv[k] = twf_m[min(tid + k * T, M - 1)];
+#pragma unroll
+    for (int k = 0; k < KT; ++k)
+      if (tid + k * T < M) tw[tid + k * T] = tv[k];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T, n = i >> 2, c = i & 3;
+      if (K * T == 4 * M || i < 4 * M) {
+        const float2 x = n < H ? xv[k] : make_float2(0.f, 0.f);
+        buf[(2 * c) * M + n] = x;
+        buf[(2 * c + 1) * M + n] = cmul(x, wv[k]);  // odd chain input x[n] w^n
+      }
     }
   }
   __syncthreads();
-  for (int parity = 0; parity < 2; ++parity) {
-    cfft<-1, CB, T, M>(sbuf, tw, tid);
+  {
+    const int c = wave >> 1, p = wave & 1;
+    float2 *wb = buf + wave * M;
+    const int kx = t * 8 + part * 4 + c;
+    const int qx = min(kx, Wp - kx);
+    const float2 *hcol = htab_t + (size_t)ch * io.hstride + (size_t)qx * Hq;
+    // transfer values for ky = 2 (j + NB2 q) + p, issued before the forward stages
+    float2 hv[R2];
     {
-      // all table loads of a thread are issued before the first is used
-      float2 hv[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int i = tid + k * T;
-        const int kx = col0 + (i & (CB - 1)), ky = 2 * min(i >> SH, M - 1) + parity;
-        const int qx = min(kx, Wp - kx), qy = min(ky, 2 * M - ky);
-        hv[k] = hc[(uint32_t)(qy * Wq + qx)];
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int i = tid + k * T;
-        if (total % T == 0 || i < total) {
-          float2 hh = hv[k];
-          if (conj_h) hh.y = -hh.y;
-          sbuf[i] = cmul(sbuf[i], cscale(hh, scale));
-        }
-      }
+      const int j = min(lane, NB2 - 1);
+      static_for<0, R2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const int ky = 2 * (j + NB2 * q) + p;
+        hv[q] = hcol[min(ky, 2 * M - ky)];
+      });
     }
-    __syncthreads();
-    cfft<+1, CB, T, M>(sbuf, tw, tid);
-    if (parity == 0) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int i = tid + k * T;
-        if (total % T == 0 || i < total) {
-          const float2 e = sbuf[i];
-          sbuf[i] = keep[k];
-          keep[k] = e;
-        }
-      }
-      __syncthreads();
+    wstage<R0, -1, M, 1>(wb, tw, lane);
+    wstage<R1, -1, M, R0>(wb, tw, lane);
+    float2 v[R2];
+    if (lane < NB2) {
+      static_for<0, R2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        v[q] = wb[lane + q * NB2];
+      });
+      static_for<1, R2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        v[q] = cmul(v[q], tw[q * lane]);  // last forward stage: Ns = NB2, unit twiddle step
+      });
+      RFft<R2, -1>::run(v);
+      static_for<0, R2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        float2 h = hv[q];
+        if (conj_h) h.y = -h.y;
+        v[q] = cmul(v[q], cscale(h, scale));
+      });
+      RFft<R2, +1>::run(v);  // first inverse stage: Ns = 1, no twiddles
     }
+    wave_lds_order();
+    if (lane < NB2) {
+      static_for<0, R2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        wb[lane * R2 + q] = v[q];
+      });
+    }
+    wave_lds_order();
+    wstage<R1, +1, M, R2>(wb, tw, lane);
+    wstage<R0, +1, M, R2 * R1>(wb, tw, lane);
   }
+  {
+    float2 wv[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, n = i >> SH;
-    if ((total % T == 0 || i < total) && n < H)
-      col_store(io, off + (size_t)n * 8 + (i & (CB - 1)),
-                cadd(keep[k], cmul(cconj(tw_at(th, n)), sbuf[i])));
+    for (int k = 0; k < K; ++k) wv[k] = twf_y[min((tid + k * T) >> 2, M - 1)];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T, n = i >> 2, c = i & 3;
+      if ((K * T == 4 * M || i < 4 * M) && n < H) {
+        const float2 e = buf[(2 * c) * M + n], o = buf[(2 * c + 1) * M + n];
+        col_store(io, off + (size_t)n * 8 + c, cadd(e, cmul(cconj(wv[k]), o)));
+      }
+    }
   }
 }
 
@@ -1021,12 +1055,11 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
   const size_t tab = (size_t)c.Hq * c.Wq;
   const ColIO io{src, dst, c.htab + (size_t)plane * tab, (size_t)c.L * tab, acc};
   dim3 grid(c.Wt, c.C);
-  if (c.Hp == 2160 && c.H <= 1080 && c.Wp % 8 == 0) {
-    constexpr int CB = 4;  // columns per workgroup: two workgroups per tile
-    const int ntiles = c.Wt * c.C;
-    const int blocks = (ntiles + 7) / 8 * 8 * (8 / CB);
-    hipLaunchKernelGGL((k_col_part<1080, 512, CB>), dim3(blocks), dim3(512), 0, s, io, c.H,
-                       c.Wp, c.Wt, ntiles, c.twf_m, c.tw_y, c.Wq, conj_h, scale);
+  if (col_wave(c)) {
+    const int pairs = c.C * ((c.Wt + 1) / 2);
+    hipLaunchKernelGGL((k_col_wave<9, 6, 20>), dim3((pairs + 7) / 8 * 32), dim3(512), 0, s, io,
+                       c.htab_t + (size_t)plane * tab, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_m,
+                       c.twf_y, conj_h, scale);
   } else if (c.Hp == 2160) {
     hipLaunchKernelGGL((k_col_half_c<1080, 1024>), grid, dim3(1024), 0, s, io, c.H, c.Wp, c.Wt,
                        c.twf_m, c.tw_y, c.Wq, conj_h, scale);

@@ -439,6 +439,57 @@ __device__ __forceinline__ void cstage2(float2 *__restrict__ buf, const TW &tw, 
   lds_sync();
 }
 
+// Orders this wave's LDS accesses before and after it (compiler barrier only):
+// LDS operations of one wave execute in issue order, so a wave that alone owns
+// a buffer needs no workgroup barrier between the stages of its transform.
+__device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory"); }
+
+// One Stockham stage of a length-N transform owned by a single wave: the
+// buffer buf[0, N) is contiguous in LDS and lane l takes butterflies
+// j = l, l + 64, ...  Same index scheme and twiddles as cstage with B = 1.
+template <int R, int DIR, int N, int NS>
+__device__ __forceinline__ void wstage(float2 *__restrict__ buf, const float2 *__restrict__ tw,
+                                       int lane) {
+  constexpr int NB = N / R;
+  constexpr int IT = (NB + 63) / 64;
+  constexpr int TWS = N / (NS * R);
+  float2 v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int j = lane + 64 * it;
+    if ((it + 1) * 64 <= NB || j < NB) {
+      static_for<0, R>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        v[it][q] = buf[j + q * NB];
+      });
+      if constexpr (NS > 1) {
+        const int e = (j % NS) * TWS;
+        static_for<1, R>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          float2 w = tw[q * e];
+          if constexpr (DIR > 0) w.y = -w.y;
+          v[it][q] = cmul(v[it][q], w);
+        });
+      }
+      RFft<R, DIR>::run(v[it]);
+    }
+  }
+  wave_lds_order();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int j = lane + 64 * it;
+    if ((it + 1) * 64 <= NB || j < NB) {
+      const int k = j % NS;
+      const int base = (j - k) * R + k;
+      static_for<0, R>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        buf[base + q * NS] = v[it][q];
+      });
+    }
+  }
+  wave_lds_order();
+}
+
 template <int DIR, int B, int T, int N, class TW, int S = 0>
 __device__ __forceinline__ void cfft2(float2 *__restrict__ buf, const TW &tw, int tid) {
   if constexpr (S < CPlan<N>::stages()) {

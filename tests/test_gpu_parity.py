@@ -131,6 +131,29 @@ def test_propagation_adjoint_parity(O):
     assert rel_l2(g.cpu().numpy(), g_ref) <= FIELD_TOL
 
 
+def test_propagation_2160_rows(O):
+    """The 2160-row column pass (one wave per column chain) with fewer rows than
+    Hp / 2 and an odd number of column tiles (15: the middle tile has no mirror
+    partner): propagation and its adjoint against the oracle."""
+    w = dict(H=1000, W=56, C=2, Hp=2160, Wp=120, pitch=8e-6, lambdas=[639e-9, 473e-9],
+             zs=[4e-3])
+    say("propagate 2160 rows", w)
+    rng = np.random.default_rng(8)
+    C, H, W = w["C"], w["H"], w["W"]
+    field = (rng.standard_normal((C, H, W)) + 1j * rng.standard_normal((C, H, W))).astype(np.complex64)
+    gI = rng.standard_normal((1, C, H, W)).astype(np.float32)
+    opt = O.Optics(H, W, C, w["Hp"], w["Wp"], w["pitch"], w["lambdas"], w["zs"])
+    ctx = binding.Context(H, W, C, w["pitch"], w["lambdas"], w["zs"], pad=(w["Hp"], w["Wp"]),
+                          max_gaussians=1)
+    F = torch.from_numpy(field).cuda()
+    I, u = ctx.propagate(F, intensity=True, field_out=True)
+    u_ref = O.propagate(field.astype(np.complex128), opt)
+    assert rel_l2(u.cpu().numpy(), u_ref) <= FIELD_TOL
+    g = ctx.propagate_adjoint(F, torch.from_numpy(gI).cuda())
+    g_ref = O.propagate_adjoint(2.0 * gI.astype(np.float64) * u_ref, opt)
+    assert rel_l2(g.cpu().numpy(), g_ref) <= FIELD_TOL
+
+
 def group_errors(g_gpu, g_ref, n, C):
     views = binding.unpack(torch.from_numpy(g_gpu), n, C)
     out = {}
@@ -171,7 +194,7 @@ def test_backward_parity(O, case):
     # runtime-plan column pass (Hp = 96: two 48-point chains)
     dict(H=40, W=56, C=2, n=200, lambdas=[639e-9, 473e-9], zs=[2e-3, -3e-3, 5e-3], Hp=96,
          Wp=120),
-    # the software-pipelined 2160-row column pass, on a narrow canvas
+    # the 2160-row column pass (one wave per column chain), on a narrow canvas
     dict(H=1080, W=48, C=1, n=2000, lambdas=[515e-9], zs=[3e-3, 6e-3], Hp=2160, Wp=96),
 ])
 def test_multiplane_parity(O, case):
