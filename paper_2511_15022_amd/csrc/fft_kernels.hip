@@ -209,9 +209,10 @@ hipError_t launch_build_twiddles_full(float2 *tw, int n, hipStream_t s) {
 // "Spatial Frequency Computation", "Bandlimit Computation", "Transfer Function
 // Evaluation"), quarter table indexed by |fx| = qx / (Wp dx), |fy| = qy / (Hp dx).
 // L_x, L_y are the extents of the padded grid.  Evanescent frequencies get 0.
-// out_t (optional) receives the same table column-major, [Wq][Hq].
-__global__ void k_transfer(float2 *out, float2 *out_t, int Hq, int Wq, int Hp, int Wp,
-                           double pitch, double lambda, double z) {
+// out_t (optional) receives the same table column-major, [Wq][Hq], times
+// t_scale (the 1 / (Hp Wp) of the inverse transform, applied in FP64).
+__global__ void k_transfer(float2 *out, float2 *out_t, double t_scale, int Hq, int Wq, int Hp,
+                           int Wp, double pitch, double lambda, double z) {
   int qx = blockIdx.x * blockDim.x + threadIdx.x;
   int qy = blockIdx.y;
   if (qx >= Wq) return;
@@ -221,15 +222,14 @@ __global__ void k_transfer(float2 *out, float2 *out_t, int Hq, int Wq, int Hp, i
   const double fxmax = 1.0 / (lambda * sqrt(ax * ax + 1.0));
   const double fymax = 1.0 / (lambda * sqrt(ay * ay + 1.0));
   const double arg = 1.0 / (lambda * lambda) - fx * fx - fy * fy;
-  float2 h = make_float2(0.f, 0.f);
+  double sn = 0.0, cs = 0.0;
   if (fx < fxmax && fy < fymax && arg >= 0.0) {
     const double ph = 6.283185307179586476925 * z * sqrt(arg);  // 2 pi z sqrt(arg)
-    double sn, cs;
     sincos(ph, &sn, &cs);
-    h = make_float2((float)cs, (float)sn);
   }
-  out[(size_t)qy * Wq + qx] = h;
-  if (out_t) out_t[(size_t)qx * Hq + qy] = h;
+  out[(size_t)qy * Wq + qx] = make_float2((float)cs, (float)sn);
+  if (out_t)
+    out_t[(size_t)qx * Hq + qy] = make_float2((float)(cs * t_scale), (float)(sn * t_scale));
 }
 
 hipError_t launch_build_transfer(const Ctx &c, hipStream_t s) {
@@ -237,8 +237,9 @@ hipError_t launch_build_transfer(const Ctx &c, hipStream_t s) {
     for (int l = 0; l < c.L; ++l) {
       const size_t at = ((size_t)ch * c.L + l) * c.Hq * c.Wq;
       hipLaunchKernelGGL(k_transfer, dim3((c.Wq + 255) / 256, c.Hq), dim3(256), 0, s,
-                         c.htab + at, c.htab_t ? c.htab_t + at : nullptr, c.Hq, c.Wq, c.Hp,
-                         c.Wp, c.cfg.pitch_m, c.cfg.wavelength_m[ch], c.cfg.z_m[l]);
+                         c.htab + at, c.htab_t ? c.htab_t + at : nullptr,
+                         1.0 / ((double)c.Hp * (double)c.Wp), c.Hq, c.Wq, c.Hp, c.Wp,
+                         c.cfg.pitch_m, c.cfg.wavelength_m[ch], c.cfg.z_m[l]);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -688,6 +689,18 @@ hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *ta
 // Column passes over one 8-column tile of one channel (a contiguous block of
 // H x 8 complex in S), in place.
 // ----------------------------------------------------------------------------
+// Element i of an array at a wave-uniform base, addressed with a 32-bit byte
+// offset (so the access takes the scalar-base form, with no 64-bit address add).
+template <class T>
+__device__ __forceinline__ T &at32(T *base, uint32_t i) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T &at32(const T *base, uint32_t i) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                      i * (uint32_t)sizeof(T));
+}
+
 // Source, destination and transfer table of one column pass.  src and dst
 // may be the same buffer (in place).  acc: add the result to dst instead of
 // overwriting it (the adjoint's sum over planes).  htab points at the table
@@ -925,7 +938,8 @@ __global__ __launch_bounds__(T) void k_col_half_c(ColIO io, int H, int Wp, int W
 }
 
 // ----------------------------------------------------------------------------
-// Column pass with one wave per chain, for M = Hp / 2 = R0 R1 R2 (1080 = 9 6 20).
+// Column pass with one wave per chain, for M = Hp / 2 = R0 R1 R2 (1080 = 9 6 20);
+// CONJ: multiply by conj(H) (the adjoint pass).
 // A workgroup takes four columns of a tile; wave 2c + p runs chain p (even,
 // odd) of column c in its own M-element LDS buffer, so the stages of a chain
 // need no workgroup barrier: only loading the columns and combining the two
@@ -938,18 +952,18 @@ __global__ __launch_bounds__(T) void k_col_half_c(ColIO io, int H, int Wp, int W
 // same table columns, run back to back on one XCD (blocks b, b + 8, b + 16,
 // b + 24 share an XCD).
 // ----------------------------------------------------------------------------
-template <int R0, int R1, int R2>
+template <int R0, int R1, int R2, bool CONJ>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_col_wave(
     ColIO io, const float2 *__restrict__ htab_t, int Hq, int H, int Wp, int Wt, int C,
-    const float2 *__restrict__ twf_m, const float2 *__restrict__ twf_y, int conj_h,
-    float scale) {
+    const float2 *__restrict__ twf_m, const float2 *__restrict__ twf_y) {
   constexpr int M = R0 * R1 * R2;
   constexpr int NB2 = M / R2;
   static_assert(NB2 <= 64, "the fused stage takes one butterfly per lane");
   constexpr int T = 512, K = (4 * M + T - 1) / T, KT = (M + T - 1) / T;
   __shared__ float2 buf[8 * M];
   __shared__ float2 tw[M];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar addressing
   const int b = blockIdx.x;
   const int slot = (b >> 3) & 3, pi = (b >> 5) * 8 + (b & 7);
   const int hp = (Wt + 1) >> 1;
@@ -960,17 +974,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int part = slot & 1;
   const size_t off = ((size_t)ch * Wt + t) * H * 8 + part * 4;
   const float2 *src = io.src + off;
+  float2 *dst = io.dst + off;
   {
     // every global load of this phase is issued before the first LDS store
     float2 xv[K], wv[K], tv[KT];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = tid + k * T, n = min(i >> 2, M - 1);
-      xv[k] = src[(uint32_t)(min(n, H - 1) * 8 + (i & 3))];
-      wv[k] = twf_y[n];
+      xv[k] = at32(src, min(n, H - 1) * 8 + (i & 3));
+      wv[k] = at32(twf_y, n);
     }
 #pragma unroll
-    for (int k = 0; k < KT; ++k) tv[k] = twf_m[min(tid + k * T, M - 1)];
+    for (int k = 0; k < KT; ++k) tv[k] = at32(twf_m, min(tid + k * T, M - 1));
 #pragma unroll
     for (int k = 0; k < KT; ++k)
       if (tid + k * T < M) tw[tid + k * T] = tv[k];
@@ -998,7 +1013,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       static_for<0, R2>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         const int ky = 2 * (j + NB2 * q) + p;
-        hv[q] = hcol[min(ky, 2 * M - ky)];
+        hv[q] = at32(hcol, min(ky, 2 * M - ky));
       });
     }
     wstage<R0, -1, M, 1>(wb, tw, lane);
@@ -1016,9 +1031,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       RFft<R2, -1>::run(v);
       static_for<0, R2>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        float2 h = hv[q];
-        if (conj_h) h.y = -h.y;
-        v[q] = cmul(v[q], cscale(h, scale));
+        v[q] = cmul(v[q], CONJ ? cconj(hv[q]) : hv[q]);  // the table carries 1 / (Hp Wp)
       });
       RFft<R2, +1>::run(v);  // first inverse stage: Ns = 1, no twiddles
     }
@@ -1036,14 +1049,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   {
     float2 wv[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) wv[k] = twf_y[min((tid + k * T) >> 2, M - 1)];
+    for (int k = 0; k < K; ++k) wv[k] = at32(twf_y, min((tid + k * T) >> 2, M - 1));
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = tid + k * T, n = i >> 2, c = i & 3;
       if ((K * T == 4 * M || i < 4 * M) && n < H) {
         const float2 e = buf[(2 * c) * M + n], o = buf[(2 * c + 1) * M + n];
-        col_store(io, off + (size_t)n * 8 + c, cadd(e, cmul(cconj(wv[k]), o)));
+        const float2 y = cadd(e, cmul(cconj(wv[k]), o));
+        float2 &d = at32(dst, n * 8 + c);
+        d = io.acc ? cadd(d, y) : y;
       }
     }
   }
@@ -1057,9 +1072,13 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
   dim3 grid(c.Wt, c.C);
   if (col_wave(c)) {
     const int pairs = c.C * ((c.Wt + 1) / 2);
-    hipLaunchKernelGGL((k_col_wave<9, 6, 20>), dim3((pairs + 7) / 8 * 32), dim3(512), 0, s, io,
-                       c.htab_t + (size_t)plane * tab, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_m,
-                       c.twf_y, conj_h, scale);
+    const float2 *ht = c.htab_t + (size_t)plane * tab;
+    if (conj_h)
+      hipLaunchKernelGGL((k_col_wave<9, 6, 20, true>), dim3((pairs + 7) / 8 * 32), dim3(512), 0,
+                         s, io, ht, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_m, c.twf_y);
+    else
+      hipLaunchKernelGGL((k_col_wave<9, 6, 20, false>), dim3((pairs + 7) / 8 * 32), dim3(512), 0,
+                         s, io, ht, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_m, c.twf_y);
   } else if (c.Hp == 2160) {
     hipLaunchKernelGGL((k_col_half_c<1080, 1024>), grid, dim3(1024), 0, s, io, c.H, c.Wp, c.Wt,
                        c.twf_m, c.tw_y, c.Wq, conj_h, scale);

@@ -487,12 +487,16 @@ hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
 // ----------------------------------------------------------------------------
 constexpr int kBatch = 256;
 
-template <int C>
+// CLAMP: the support threshold lies at or below the exponent clamp (unbounded
+// support), so the clamp has to be applied; otherwise every exponent that
+// passes the threshold is above the clamp already.
+template <int C, bool CLAMP>
 __device__ __forceinline__ void accumulate(const float *r, float offx, float offy, float flx,
                                            float fly, float thr, float *ar, float *ai) {
   const float dx = flx + offx, dy = fly + offy;
   const float p2 = fmaf(dx, fmaf(r[R_A], dx, r[R_B] * dy), r[R_C] * dy * dy);
-  const float G = p2 >= thr ? __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2)) : 0.f;
+  const float G =
+      p2 >= thr ? __builtin_amdgcn_exp2f(CLAMP ? fmaxf(p2, kPowerFloor2) : p2) : 0.f;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     ar[c] = fmaf(G, r[R_AMP + 2 * c], ar[c]);
@@ -501,7 +505,7 @@ __device__ __forceinline__ void accumulate(const float *r, float offx, float off
 }
 
 // zero_id: index of an all-zero record (after the last Gaussian slot)
-template <int C>
+template <int C, bool CLAMP>
 __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ rec,
                                                     const uint32_t *__restrict__ vals,
                                                     const uint2 *__restrict__ ranges, int W,
@@ -587,22 +591,21 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // walk the list two at a time: the record addresses are wave-uniform, so
     // the records come in through scalar loads and feed the VALU as scalar
-    // operands; both pairs of loads are issued before either is used
+    // operands; both pairs of loads are issued before either is used.  The
+    // offsets stay in (uniform) vector registers: the adds take them as they are.
     for (int k = 0; k < n; k += 2) {
       const uint4 e0 = list[wave][k], e1 = list[wave][k + 1];
       const uint32_t g0 = __builtin_amdgcn_readfirstlane(e0.x);
       const uint32_t g1 = __builtin_amdgcn_readfirstlane(e1.x);
-      const float ox0 = __uint_as_float(__builtin_amdgcn_readfirstlane(e0.y));
-      const float oy0 = __uint_as_float(__builtin_amdgcn_readfirstlane(e0.z));
-      const float ox1 = __uint_as_float(__builtin_amdgcn_readfirstlane(e1.y));
-      const float oy1 = __uint_as_float(__builtin_amdgcn_readfirstlane(e1.z));
+      const float ox0 = __uint_as_float(e0.y), oy0 = __uint_as_float(e0.z);
+      const float ox1 = __uint_as_float(e1.y), oy1 = __uint_as_float(e1.z);
       const float *s0 = rec + (size_t)g0 * RS;
       const float *s1 = rec + (size_t)g1 * RS;
       float r0[R_AMP + 2 * C], r1[R_AMP + 2 * C];
 #pragma unroll
       for (int i = R_A; i < R_AMP + 2 * C; ++i) { r0[i] = s0[i]; r1[i] = s1[i]; }
-      accumulate<C>(r0, ox0, oy0, flx, fly, thr, ar, ai);
-      accumulate<C>(r1, ox1, oy1, flx, fly, thr, ar, ai);
+      accumulate<C, CLAMP>(r0, ox0, oy0, flx, fly, thr, ar, ai);
+      accumulate<C, CLAMP>(r1, ox1, oy1, flx, fly, thr, ar, ai);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -624,12 +627,17 @@ hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
   const uint32_t zid = (uint32_t)c.cfg.max_gaussians;  // the zero record
   const uint32_t *vals = c.vals[c.sorted];
   dim3 grid(c.num_tiles), block(256);
+  const bool clamp = !(thr > kPowerFloor2);
+#define CGH_FWD(CC, CL)                                                                  \
+  hipLaunchKernelGGL((k_raster_fwd<CC, CL>), grid, block, 0, s, c.rec, vals, c.ranges, c.W, \
+                     c.H, c.tiles_x, thr, zid, field)
   switch (c.C) {
-    case 1: hipLaunchKernelGGL(k_raster_fwd<1>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, zid, field); break;
-    case 2: hipLaunchKernelGGL(k_raster_fwd<2>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, zid, field); break;
-    case 3: hipLaunchKernelGGL(k_raster_fwd<3>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, zid, field); break;
-    default: hipLaunchKernelGGL(k_raster_fwd<4>, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x, thr, zid, field); break;
+    case 1: if (clamp) CGH_FWD(1, true); else CGH_FWD(1, false); break;
+    case 2: if (clamp) CGH_FWD(2, true); else CGH_FWD(2, false); break;
+    case 3: if (clamp) CGH_FWD(3, true); else CGH_FWD(3, false); break;
+    default: if (clamp) CGH_FWD(4, true); else CGH_FWD(4, false); break;
   }
+#undef CGH_FWD
   return hipGetLastError();
 }
 
@@ -666,7 +674,7 @@ template <int C> struct AdjQ {
   static constexpr int N = ((SLOT + 1) + 3) & ~3;
 };
 
-template <int C>
+template <int C, bool CLAMP>
 __global__ __launch_bounds__(64) void k_raster_adj(
     const float *__restrict__ rec, const uint32_t *__restrict__ vals,
     const uint2 *__restrict__ ranges, const uint2 *__restrict__ rect,
@@ -842,8 +850,9 @@ __global__ __launch_bounds__(64) void k_raster_adj(
             const float dy = (float)(ly & 7) + (ly < 8 ? offy0 : offy1);
             const float dx = (float)(lx & 7) + (lx < 8 ? offx0 : offx1);
             const float p2 = fmaf(dx, fmaf(qa, dx, qb * dy), qc * dy * dy);
-            const float G =
-                (live && p2 >= thr) ? __builtin_amdgcn_exp2f(fmaxf(p2, kPowerFloor2)) : 0.f;
+            const float G = (live && p2 >= thr)
+                                ? __builtin_amdgcn_exp2f(CLAMP ? fmaxf(p2, kPowerFloor2) : p2)
+                                : 0.f;
             // 24-bit multiply (full rate) for the LDS offset
             const float2 *gv = &sg[0][0] + __umul24((unsigned)(min(ly, kTile - 1) * kTile + lx), (unsigned)C);
             float gp = 0.f;
@@ -854,7 +863,8 @@ __global__ __launch_bounds__(64) void k_raster_adj(
               S[2 * c] = fmaf(G, v.x, S[2 * c]);
               S[2 * c + 1] = fmaf(G, v.y, S[2 * c + 1]);
             }
-            const float w = p2 > kPowerFloor2 ? gp * G : 0.f;
+            // without the clamp, G > 0 implies p2 >= thr > the clamp
+            const float w = (!CLAMP || p2 > kPowerFloor2) ? gp * G : 0.f;
             const float wx = w * dx, wy = w * dy;
             S[2 * C] += wx;
             S[2 * C + 1] += wy;
@@ -1009,12 +1019,17 @@ hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStre
   const float thr = support_threshold(c.cfg.support_sigma);
   const uint32_t *vals = c.vals[c.sorted];
   dim3 grid(c.num_tiles), block(64);
+  const bool clamp = !(thr > kPowerFloor2);
+#define CGH_ADJ(CC, CL)                                                                  \
+  hipLaunchKernelGGL((k_raster_adj<CC, CL>), grid, block, 0, s, c.rec, vals, c.ranges, c.rect, \
+                     c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials)
   switch (c.C) {
-    case 1: hipLaunchKernelGGL(k_raster_adj<1>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
-    case 2: hipLaunchKernelGGL(k_raster_adj<2>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
-    case 3: hipLaunchKernelGGL(k_raster_adj<3>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
-    default: hipLaunchKernelGGL(k_raster_adj<4>, grid, block, 0, s, c.rec, vals, c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials); break;
+    case 1: if (clamp) CGH_ADJ(1, true); else CGH_ADJ(1, false); break;
+    case 2: if (clamp) CGH_ADJ(2, true); else CGH_ADJ(2, false); break;
+    case 3: if (clamp) CGH_ADJ(3, true); else CGH_ADJ(3, false); break;
+    default: if (clamp) CGH_ADJ(4, true); else CGH_ADJ(4, false); break;
   }
+#undef CGH_ADJ
   return hipGetLastError();
 }
 
