@@ -44,6 +44,18 @@ struct TwLds {
   float2 lo[64];
 };
 
+// Element i of an array at a wave-uniform base, addressed with a 32-bit byte
+// offset (so the access takes the scalar-base form, with no 64-bit address add).
+template <class T>
+__device__ __forceinline__ T &at32(T *base, uint32_t i) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T &at32(const T *base, uint32_t i) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                      i * (uint32_t)sizeof(T));
+}
+
 __device__ __forceinline__ float2 tw_at(const TwLds &t, int e) {
   return cmul(t.hi[e >> 6], t.lo[e & 63]);
 }
@@ -612,6 +624,225 @@ __global__ __launch_bounds__(T) void k_row_loss_c(
   }
 }
 
+// ----------------------------------------------------------------------------
+// Half-length row passes, for Wp = 2M with W <= M (3840: M = 1920).  As in the
+// column pass, splitting the Wp-point transform of a row by output parity
+// leaves two M-point chains: with the samples x[n] at n < W, bin 2m + p of
+// the forward is FFT_M(x[n] w^{pn})[m], and the inverse cropped to n < W is
+// e[n] + w^{-n} o[n], where e and o are the M-point inverses of the even and
+// odd bins (w = exp(-2 pi i / Wp)).  A 512-thread workgroup takes two rows:
+// four interleaved M-point chains, chain b = 2 r + p at buf[m * 4 + b].  At
+// half length the full M-entry twiddle table fits beside the data (77 KB, two
+// workgroups per CU), so no stage pays for two-level twiddles.
+// ----------------------------------------------------------------------------
+constexpr int kRowHalfThreads = 512;
+
+// full M-entry table exp(-2 pi i e / M) = the even entries of the Wp table
+template <int M, int T>
+__device__ __forceinline__ void load_half_table(float2 *tw, const float2 *__restrict__ twf_x,
+                                                int tid) {
+  constexpr int KT = (M + T - 1) / T;
+  float2 tv[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) tv[k] = at32(twf_x, 2 * min(tid + k * T, M - 1));
+#pragma unroll
+  for (int k = 0; k < KT; ++k)
+    if (KT * T == M || tid + k * T < M) tw[tid + k * T] = tv[k];
+}
+
+// S (column-tiled, channel base Sc) rows y0, y0 + 1 <-> the four chains in LDS:
+// element i of the pair moves S[t][y0 + r][e] with t = i / 16, r = (i / 8) % 2,
+// e = i % 8, i.e. bin x = 8 t + e of chain 2 r + (x & 1) at m = x / 2; sixteen
+// consecutive threads cover one 128-byte line.  Wt = M / 4 tiles.
+template <int M, int T>
+__device__ __forceinline__ void load_row_pair(float2 *buf, const float2 *Sc, int H, int y0,
+                                              int tid) {
+  constexpr int n = M * 4, K = (n + T - 1) / T;
+  const int ylast = H - 1;
+  float2 v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = min(tid + k * T, n - 1), t = i >> 4, r = (i >> 3) & 1, e = i & 7;
+    v[k] = at32(Sc, (t * H + min(y0 + r, ylast)) * 8 + e);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T, t = i >> 4, r = (i >> 3) & 1, e = i & 7, x = 8 * t + e;
+    if (K * T == n || i < n) buf[(x >> 1) * 4 + 2 * r + (x & 1)] = v[k];
+  }
+}
+
+template <int M, int T>
+__device__ __forceinline__ void store_row_pair(const float2 *buf, float2 *Sc, int H, int y0,
+                                               int tid) {
+  constexpr int n = M * 4, K = (n + T - 1) / T;
+  float2 v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = min(tid + k * T, n - 1), t = i >> 4, r = (i >> 3) & 1, e = i & 7;
+    const int x = 8 * t + e;
+    v[k] = buf[(x >> 1) * 4 + 2 * r + (x & 1)];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T, t = i >> 4, r = (i >> 3) & 1, e = i & 7;
+    if ((K * T == n || i < n) && y0 + r < H) at32(Sc, (t * H + y0 + r) * 8 + e) = v[k];
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(kRowHalfThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_row_fwd_h(const float2 *__restrict__ field, int H, int W, const float2 *__restrict__ twf_x,
+            float2 *__restrict__ S) {
+  constexpr int T = kRowHalfThreads, K = (2 * M + T - 1) / T, Wt = M / 4;
+  __shared__ float2 buf[4 * M];
+  __shared__ float2 tw[M];
+  const int tid = threadIdx.x;
+  const int groups = (H + 1) >> 1;
+  const int c = blockIdx.x / groups, y0 = 2 * (blockIdx.x - c * groups);
+  load_half_table<M, T>(tw, twf_x, tid);
+  {
+    // element i: row y0 + i / M, sample n = i % M; all loads issued first
+    const float2 *f0 = field + (size_t)c * H * W;
+    float2 xv[K], wv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = min(tid + k * T, 2 * M - 1), r = i >= M ? 1 : 0, n = i - r * M;
+      xv[k] = at32(f0, min(y0 + r, H - 1) * W + min(n, W - 1));
+      wv[k] = at32(twf_x, n);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T, r = i >= M ? 1 : 0, n = i - r * M;
+      if (K * T == 2 * M || i < 2 * M) {
+        const float2 x = (n < W && y0 + r < H) ? xv[k] : make_float2(0.f, 0.f);
+        buf[n * 4 + 2 * r] = x;
+        buf[n * 4 + 2 * r + 1] = cmul(x, wv[k]);  // odd chain: x[n] w^n
+      }
+    }
+  }
+  __syncthreads();
+  cfft<-1, 4, T, M>(buf, tw, tid);
+  store_row_pair<M, T>(buf, S + (size_t)c * Wt * H * 8, H, y0, tid);
+}
+
+template <int M>
+__global__ __launch_bounds__(kRowHalfThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_row_inv_h(const float2 *__restrict__ S, int H, int W, const float2 *__restrict__ twf_x,
+            float2 *__restrict__ out) {
+  constexpr int T = kRowHalfThreads, K = (2 * M + T - 1) / T, Wt = M / 4;
+  __shared__ float2 buf[4 * M];
+  __shared__ float2 tw[M];
+  const int tid = threadIdx.x;
+  const int groups = (H + 1) >> 1;
+  const int c = blockIdx.x / groups, y0 = 2 * (blockIdx.x - c * groups);
+  load_half_table<M, T>(tw, twf_x, tid);
+  load_row_pair<M, T>(buf, S + (size_t)c * Wt * H * 8, H, y0, tid);
+  // w^n of this thread's output elements (i: row y0 + i / W, n = i % W)
+  float2 wv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = min(tid + k * T, 2 * W - 1), r = i >= W ? 1 : 0;
+    wv[k] = at32(twf_x, i - r * W);
+  }
+  lds_sync();
+  cfft<+1, 4, T, M>(buf, tw, tid);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T, r = i >= W ? 1 : 0, n = i - r * W;
+    if (i < 2 * W && y0 + r < H) {
+      const float2 e = buf[n * 4 + 2 * r], o = buf[n * 4 + 2 * r + 1];
+      out[((size_t)c * H + y0 + r) * W + n] = cadd(e, cmul(cconj(wv[k]), o));
+    }
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(kRowHalfThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_row_loss_h(
+    float2 *__restrict__ S, int H, int W, const float2 *__restrict__ twf_x,
+    const float *__restrict__ target, const float *__restrict__ grad_I,
+    const float *__restrict__ mask, float *__restrict__ intensity, float2 *__restrict__ u_out,
+    double *__restrict__ loss_part, float gscale, int make_grad) {
+  constexpr int T = kRowHalfThreads, K = (2 * M + T - 1) / T, Wt = M / 4;
+  __shared__ float2 buf[4 * M];
+  __shared__ float2 tw[M];
+  __shared__ double red[T / 64];
+  const int tid = threadIdx.x;
+  const int groups = (H + 1) >> 1;
+  const int c = blockIdx.x / groups, y0 = 2 * (blockIdx.x - c * groups);
+  float2 *Sc = S + (size_t)c * Wt * H * 8;
+  load_half_table<M, T>(tw, twf_x, tid);
+  load_row_pair<M, T>(buf, Sc, H, y0, tid);
+  // per-element inputs of this thread (i: row y0 + i / W, n = i % W): target
+  // and mask are fetched before the transform so that their latency overlaps
+  // it; the twiddles w^n (cached in L2) after it, to stay within 128 registers
+  const float *tsrc = target ? target : grad_I;
+  float tv[K], mv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = min(tid + k * T, 2 * W - 1), r = i >= W ? 1 : 0, n = i - r * W;
+    const int y = min(y0 + r, H - 1);
+    tv[k] = tsrc ? tsrc[((size_t)c * H + y) * W + n] : 0.f;
+    mv[k] = mask ? mask[(size_t)y * W + n] : 0.f;
+  }
+  lds_sync();
+  cfft<+1, 4, T, M>(buf, tw, tid);
+  float2 wv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = min(tid + k * T, 2 * W - 1), r = i >= W ? 1 : 0;
+    wv[k] = at32(twf_x, i - r * W);
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T, r = i >= W ? 1 : 0, n = i - r * W;
+    if (i < 2 * W) {
+      const float2 e = buf[n * 4 + 2 * r], o = buf[n * 4 + 2 * r + 1];
+      const float2 u = cadd(e, cmul(cconj(wv[k]), o));
+      float f = 0.f;
+      if (y0 + r < H) {
+        const float I = u.x * u.x + u.y * u.y;
+        const size_t at = ((size_t)c * H + y0 + r) * W + n;
+        if (intensity) intensity[at] = I;
+        if (u_out) u_out[at] = u;
+        if (target) {
+          // L_recon weight 1 + m^2 + t^2 (plain MSE without a mask)
+          const float d = I - tv[k], w = mask ? 1.f + mv[k] * mv[k] + tv[k] * tv[k] : 1.f;
+          acc += (double)d * (double)d * (double)w;
+          f = gscale * d * w;  // 4 w (I - T) / M
+        } else if (grad_I) {
+          f = 2.0f * tv[k];
+        }
+      }
+      if (make_grad) {
+        // inputs of the forward chains, g[n] and g[n] w^n, in the same slots
+        const float2 g = make_float2(f * u.x, f * u.y);
+        buf[n * 4 + 2 * r] = g;
+        buf[n * 4 + 2 * r + 1] = cmul(g, wv[k]);
+      }
+    }
+  }
+  if (make_grad)
+    for (int i = tid; i < 4 * (M - W); i += T) buf[4 * W + i] = make_float2(0.f, 0.f);
+  if (target) {
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < T / 64; ++w) sum += red[w];
+      loss_part[blockIdx.x] = sum;
+    }
+  }
+  if (make_grad) {
+    __syncthreads();
+    cfft<-1, 4, T, M>(buf, tw, tid);
+    store_row_pair<M, T>(buf, Sc, H, y0, tid);
+  }
+}
+
 // rows per row-pass workgroup (specialised lengths use 4, the runtime path 2)
 static bool row_specialised(int Wp) { return Wp == 3840 || Wp == 512; }
 int row_group_rows(const Ctx &c) { return c.Wp == 512 ? 4 : 2; }
@@ -621,8 +852,14 @@ static int row_blocks(const Ctx &c) {
 }
 static size_t row_lds(const Ctx &c) { return (size_t)2 * c.Wp * sizeof(float2); }
 
+// the half-length row passes take Wp = 3840 with W <= Wp / 2
+static bool row_half(const Ctx &c) { return c.Wp == 3840 && c.W <= 1920; }
+
 hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStream_t s) {
-  if (c.Wp == 3840)
+  if (row_half(c))
+    hipLaunchKernelGGL(k_row_fwd_h<1920>, dim3(row_blocks(c)), dim3(kRowHalfThreads), 0, s, field,
+                       c.H, c.W, c.twf_x, dst);
+  else if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_fwd_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
                        field, c.H, c.W, c.Wt, c.twf_x, c.tw_x, dst);
   else if (c.Wp == 512)
@@ -638,7 +875,10 @@ hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStr
 }
 
 hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStream_t s) {
-  if (c.Wp == 3840)
+  if (row_half(c))
+    hipLaunchKernelGGL(k_row_inv_h<1920>, dim3(row_blocks(c)), dim3(kRowHalfThreads), 0, s, src,
+                       c.H, c.W, c.twf_x, out);
+  else if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_inv_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
                        src, c.H, c.W, c.Wt, c.twf_x, c.tw_x, out);
   else if (c.Wp == 512)
@@ -666,7 +906,11 @@ hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *ta
   if (u_out) u_out += po;
   if (mask) mask += (size_t)plane * c.H * c.W;  // [L][H][W]
   double *lp = c.loss_part + (size_t)plane * row_blocks(c);
-  if (c.Wp == 3840)
+  if (row_half(c))
+    hipLaunchKernelGGL(k_row_loss_h<1920>, dim3(row_blocks(c)), dim3(kRowHalfThreads), 0, s, buf,
+                       c.H, c.W, c.twf_x, target, grad_intensity, mask, intensity, u_out, lp,
+                       gscale, make_grad);
+  else if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_loss_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
                        buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, mask, intensity,
                        u_out, lp, gscale, make_grad);
@@ -689,18 +933,6 @@ hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *ta
 // Column passes over one 8-column tile of one channel (a contiguous block of
 // H x 8 complex in S), in place.
 // ----------------------------------------------------------------------------
-// Element i of an array at a wave-uniform base, addressed with a 32-bit byte
-// offset (so the access takes the scalar-base form, with no 64-bit address add).
-template <class T>
-__device__ __forceinline__ T &at32(T *base, uint32_t i) {
-  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (uint32_t)sizeof(T));
-}
-template <class T>
-__device__ __forceinline__ const T &at32(const T *base, uint32_t i) {
-  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
-                                      i * (uint32_t)sizeof(T));
-}
-
 // Source, destination and transfer table of one column pass.  src and dst
 // may be the same buffer (in place).  acc: add the result to dst instead of
 // overwriting it (the adjoint's sum over planes).  htab points at the table

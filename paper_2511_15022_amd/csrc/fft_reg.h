@@ -447,9 +447,11 @@ __device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory")
 // One Stockham stage of a length-N transform owned by a single wave: the
 // buffer buf[0, N) is contiguous in LDS and lane l takes butterflies
 // j = l, l + 64, ...  Same index scheme and twiddles as cstage with B = 1.
-template <int R, int DIR, int N, int NS>
-__device__ __forceinline__ void wstage(float2 *__restrict__ buf, const float2 *__restrict__ tw,
-                                       int lane) {
+// The stage input element i comes from ld(i) (the buffer itself, or global
+// memory for a first stage); the output goes to the buffer.
+template <int R, int DIR, int N, int NS, class LD>
+__device__ __forceinline__ void wstage_ld(float2 *__restrict__ buf, const float2 *__restrict__ tw,
+                                          int lane, LD &&ld) {
   constexpr int NB = N / R;
   constexpr int IT = (NB + 63) / 64;
   constexpr int TWS = N / (NS * R);
@@ -460,7 +462,7 @@ __device__ __forceinline__ void wstage(float2 *__restrict__ buf, const float2 *_
     if ((it + 1) * 64 <= NB || j < NB) {
       static_for<0, R>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        v[it][q] = buf[j + q * NB];
+        v[it][q] = ld(j + q * NB);
       });
       if constexpr (NS > 1) {
         const int e = (j % NS) * TWS;
@@ -488,6 +490,12 @@ __device__ __forceinline__ void wstage(float2 *__restrict__ buf, const float2 *_
     }
   }
   wave_lds_order();
+}
+
+template <int R, int DIR, int N, int NS>
+__device__ __forceinline__ void wstage(float2 *__restrict__ buf, const float2 *__restrict__ tw,
+                                       int lane) {
+  wstage_ld<R, DIR, N, NS>(buf, tw, lane, [&](int i) { return buf[i]; });
 }
 
 template <int DIR, int B, int T, int N, class TW, int S = 0>

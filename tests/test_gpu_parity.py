@@ -441,6 +441,44 @@ def test_recon_loss_parity(O):
         assert e <= GRAD_TOL, (k, e)
 
 
+def test_rows_3840_narrow(O):
+    """The 3840-wide row passes (one wave per half-length chain) with fewer
+    columns than Wp / 2 and an odd number of rows (the last workgroup has a
+    padding row), two planes: propagation, its adjoint, the MSE backward and
+    the L_recon backward against the oracle."""
+    H, W, C, n = 9, 1800, 2, 400
+    lambdas, zs, Hp, Wp = [639e-9, 473e-9], [3e-3, 5e-3], 18, 3840
+    say("rows 3840", H, W, C, n, zs)
+    p = synth.params(71, n, H, W, C)
+    T = synth.target(72, C, H, W, L=2) * np.float32(0.5)
+    Mk = (np.random.default_rng(73).uniform(0, 1, (2, H, W)) > 0.5).astype(np.float32)
+    opt = O.Optics(H, W, C, Hp, Wp, 8e-6, lambdas, zs)
+    ctx = binding.Context(H, W, C, 8e-6, lambdas, zs, pad=(Hp, Wp), max_gaussians=n)
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    I, u = ctx.propagate(field, intensity=True, field_out=True)
+    u_ref = O.propagate(field.cpu().numpy().astype(np.complex128), opt)
+    assert rel_l2(u.cpu().numpy(), u_ref) <= FIELD_TOL
+    assert rel_l2(I.cpu().numpy(), np.abs(u_ref) ** 2) <= FIELD_TOL
+    gI = np.random.default_rng(74).standard_normal((2, C, H, W)).astype(np.float32)
+    g = ctx.propagate_adjoint(field, torch.from_numpy(gI).cuda())
+    g_ref = O.propagate_adjoint(2.0 * gI.astype(np.float64) * u_ref, opt)
+    assert rel_l2(g.cpu().numpy(), g_ref) <= FIELD_TOL
+    for mask in (None, Mk):
+        loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+        gfield = torch.empty_like(field)
+        grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss,
+                             grad_field=gfield,
+                             mask=None if mask is None else torch.from_numpy(mask).cuda())
+        ref = O.forward_backward(p, T, opt, mask=mask)
+        lg = loss.cpu().numpy()
+        say("loss", lg[0], ref["loss"], "mask" if mask is not None else "mse")
+        assert abs(lg[0] - ref["loss"]) <= 1e-4 * ref["loss"]
+        assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
+        for k, e in group_errors(grads.cpu().numpy(), ref["grads"], n, C).items():
+            assert e <= GRAD_TOL, (k, e)
+
+
 def test_adan_step_matches_oracle(O):
     """Adan (the paper's optimiser, Sec. 4) over four steps with changing
     gradients and per-group learning rates, against the FP64 oracle."""
