@@ -172,7 +172,8 @@ size_t carve(Ctx *c, char *base) {
   const size_t scan_len = std::max(N + 1, (size_t)256 * c->sort_blocks);
   c->scan_tmp = (uint32_t *)take(sizeof(uint32_t) * (scan_len / kScanItems + 2));
   c->partials = (float *)take(sizeof(float) * c->part_stride * cap);
-  c->loss_part = (double *)take(sizeof(double) * c->L * c->C * (size_t)((c->H + 1) / 2));
+  const int rg = row_group_rows(*c);  // one loss partial per row-pass workgroup
+  c->loss_part = (double *)take(sizeof(double) * c->L * c->C * (size_t)((c->H + rg - 1) / rg));
   c->status = (uint32_t *)take(sizeof(uint32_t) * 4);
   return (off + 255) & ~(size_t)255;
 }

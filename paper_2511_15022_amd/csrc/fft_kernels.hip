@@ -630,12 +630,12 @@ __global__ __launch_bounds__(T) void k_row_loss_c(
 // leaves two M-point chains: with the samples x[n] at n < W, bin 2m + p of
 // the forward is FFT_M(x[n] w^{pn})[m], and the inverse cropped to n < W is
 // e[n] + w^{-n} o[n], where e and o are the M-point inverses of the even and
-// odd bins (w = exp(-2 pi i / Wp)).  A 512-thread workgroup takes two rows:
-// four interleaved M-point chains, chain b = 2 r + p at buf[m * 4 + b].  At
-// half length the full M-entry twiddle table fits beside the data (77 KB, two
-// workgroups per CU), so no stage pays for two-level twiddles.
+// odd bins (w = exp(-2 pi i / Wp)).  A workgroup of 256 threads per row takes
+// RW rows: 2 RW interleaved M-point chains, chain b = 2 r + p at
+// buf[m * 2 RW + b].  At half length the full M-entry twiddle table fits
+// beside the data, so no stage pays for two-level twiddles.
 // ----------------------------------------------------------------------------
-constexpr int kRowHalfThreads = 512;
+constexpr int kRowHalfRows = 2;  // rows per workgroup: 77 KB of LDS, two workgroups per CU
 
 // full M-entry table exp(-2 pi i e / M) = the even entries of the Wp table
 template <int M, int T>
@@ -650,56 +650,56 @@ __device__ __forceinline__ void load_half_table(float2 *tw, const float2 *__rest
     if (KT * T == M || tid + k * T < M) tw[tid + k * T] = tv[k];
 }
 
-// S (column-tiled, channel base Sc) rows y0, y0 + 1 <-> the four chains in LDS:
-// element i of the pair moves S[t][y0 + r][e] with t = i / 16, r = (i / 8) % 2,
-// e = i % 8, i.e. bin x = 8 t + e of chain 2 r + (x & 1) at m = x / 2; sixteen
-// consecutive threads cover one 128-byte line.  Wt = M / 4 tiles.
-template <int M, int T>
-__device__ __forceinline__ void load_row_pair(float2 *buf, const float2 *Sc, int H, int y0,
-                                              int tid) {
-  constexpr int n = M * 4, K = (n + T - 1) / T;
-  const int ylast = H - 1;
+// S (column-tiled, channel base Sc) rows y0 .. y0 + RW - 1 <-> the chains in
+// LDS: element i moves S[t][y0 + r][e] with t = i / (8 RW), r = (i / 8) % RW,
+// e = i % 8, i.e. bin x = 8 t + e of chain 2 r + (x & 1) at m = x / 2; each
+// tile's rows of the group are contiguous (8 RW consecutive threads, 64 RW
+// bytes).  Wt = M / 4 tiles.
+template <int M, int RW, int T>
+__device__ __forceinline__ void load_row_group(float2 *buf, const float2 *Sc, int H, int y0,
+                                               int tid) {
+  constexpr int n = 2 * M * RW, K = (n + T - 1) / T, B = 2 * RW;  // Wp bins per row
   float2 v[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = min(tid + k * T, n - 1), t = i >> 4, r = (i >> 3) & 1, e = i & 7;
-    v[k] = at32(Sc, (t * H + min(y0 + r, ylast)) * 8 + e);
+    const int i = min(tid + k * T, n - 1), t = i / (8 * RW), r = (i >> 3) % RW, e = i & 7;
+    v[k] = at32(Sc, (t * H + min(y0 + r, H - 1)) * 8 + e);
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, t = i >> 4, r = (i >> 3) & 1, e = i & 7, x = 8 * t + e;
-    if (K * T == n || i < n) buf[(x >> 1) * 4 + 2 * r + (x & 1)] = v[k];
+    const int i = tid + k * T, t = i / (8 * RW), r = (i >> 3) % RW, e = i & 7, x = 8 * t + e;
+    if (K * T == n || i < n) buf[(x >> 1) * B + 2 * r + (x & 1)] = v[k];
   }
 }
 
-template <int M, int T>
-__device__ __forceinline__ void store_row_pair(const float2 *buf, float2 *Sc, int H, int y0,
-                                               int tid) {
-  constexpr int n = M * 4, K = (n + T - 1) / T;
+template <int M, int RW, int T>
+__device__ __forceinline__ void store_row_group(const float2 *buf, float2 *Sc, int H, int y0,
+                                                int tid) {
+  constexpr int n = 2 * M * RW, K = (n + T - 1) / T, B = 2 * RW;  // Wp bins per row
   float2 v[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = min(tid + k * T, n - 1), t = i >> 4, r = (i >> 3) & 1, e = i & 7;
+    const int i = min(tid + k * T, n - 1), t = i / (8 * RW), r = (i >> 3) % RW, e = i & 7;
     const int x = 8 * t + e;
-    v[k] = buf[(x >> 1) * 4 + 2 * r + (x & 1)];
+    v[k] = buf[(x >> 1) * B + 2 * r + (x & 1)];
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, t = i >> 4, r = (i >> 3) & 1, e = i & 7;
+    const int i = tid + k * T, t = i / (8 * RW), r = (i >> 3) % RW, e = i & 7;
     if ((K * T == n || i < n) && y0 + r < H) at32(Sc, (t * H + y0 + r) * 8 + e) = v[k];
   }
 }
 
-template <int M>
-__global__ __launch_bounds__(kRowHalfThreads) __attribute__((amdgpu_waves_per_eu(4))) void
-k_row_fwd_h(const float2 *__restrict__ field, int H, int W, const float2 *__restrict__ twf_x,
-            float2 *__restrict__ S) {
-  constexpr int T = kRowHalfThreads, K = (2 * M + T - 1) / T, Wt = M / 4;
-  __shared__ float2 buf[4 * M];
+template <int M, int RW>
+__global__ __launch_bounds__(256 * RW) __attribute__((amdgpu_waves_per_eu(4))) void k_row_fwd_h(
+    const float2 *__restrict__ field, int H, int W, const float2 *__restrict__ twf_x,
+    float2 *__restrict__ S) {
+  constexpr int T = 256 * RW, B = 2 * RW, K = (RW * M + T - 1) / T, Wt = M / 4;
+  __shared__ float2 buf[B * M];
   __shared__ float2 tw[M];
   const int tid = threadIdx.x;
-  const int groups = (H + 1) >> 1;
-  const int c = blockIdx.x / groups, y0 = 2 * (blockIdx.x - c * groups);
+  const int groups = (H + RW - 1) / RW;
+  const int c = blockIdx.x / groups, y0 = RW * (blockIdx.x - c * groups);
   load_half_table<M, T>(tw, twf_x, tid);
   {
     // element i: row y0 + i / M, sample n = i % M; all loads issued first
@@ -707,73 +707,72 @@ k_row_fwd_h(const float2 *__restrict__ field, int H, int W, const float2 *__rest
     float2 xv[K], wv[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int i = min(tid + k * T, 2 * M - 1), r = i >= M ? 1 : 0, n = i - r * M;
+      const int i = min(tid + k * T, RW * M - 1), r = i / M, n = i - r * M;
       xv[k] = at32(f0, min(y0 + r, H - 1) * W + min(n, W - 1));
       wv[k] = at32(twf_x, n);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int i = tid + k * T, r = i >= M ? 1 : 0, n = i - r * M;
-      if (K * T == 2 * M || i < 2 * M) {
+      const int i = tid + k * T, r = i / M, n = i - r * M;
+      if (K * T == RW * M || i < RW * M) {
         const float2 x = (n < W && y0 + r < H) ? xv[k] : make_float2(0.f, 0.f);
-        buf[n * 4 + 2 * r] = x;
-        buf[n * 4 + 2 * r + 1] = cmul(x, wv[k]);  // odd chain: x[n] w^n
+        buf[n * B + 2 * r] = x;
+        buf[n * B + 2 * r + 1] = cmul(x, wv[k]);  // odd chain: x[n] w^n
       }
     }
   }
   __syncthreads();
-  cfft<-1, 4, T, M>(buf, tw, tid);
-  store_row_pair<M, T>(buf, S + (size_t)c * Wt * H * 8, H, y0, tid);
+  cfft<-1, B, T, M>(buf, tw, tid);
+  store_row_group<M, RW, T>(buf, S + (size_t)c * Wt * H * 8, H, y0, tid);
 }
 
-template <int M>
-__global__ __launch_bounds__(kRowHalfThreads) __attribute__((amdgpu_waves_per_eu(4))) void
-k_row_inv_h(const float2 *__restrict__ S, int H, int W, const float2 *__restrict__ twf_x,
-            float2 *__restrict__ out) {
-  constexpr int T = kRowHalfThreads, K = (2 * M + T - 1) / T, Wt = M / 4;
-  __shared__ float2 buf[4 * M];
+template <int M, int RW>
+__global__ __launch_bounds__(256 * RW) __attribute__((amdgpu_waves_per_eu(4))) void k_row_inv_h(
+    const float2 *__restrict__ S, int H, int W, const float2 *__restrict__ twf_x,
+    float2 *__restrict__ out) {
+  constexpr int T = 256 * RW, B = 2 * RW, K = (RW * M + T - 1) / T, Wt = M / 4;
+  __shared__ float2 buf[B * M];
   __shared__ float2 tw[M];
   const int tid = threadIdx.x;
-  const int groups = (H + 1) >> 1;
-  const int c = blockIdx.x / groups, y0 = 2 * (blockIdx.x - c * groups);
+  const int groups = (H + RW - 1) / RW;
+  const int c = blockIdx.x / groups, y0 = RW * (blockIdx.x - c * groups);
   load_half_table<M, T>(tw, twf_x, tid);
-  load_row_pair<M, T>(buf, S + (size_t)c * Wt * H * 8, H, y0, tid);
+  load_row_group<M, RW, T>(buf, S + (size_t)c * Wt * H * 8, H, y0, tid);
   // w^n of this thread's output elements (i: row y0 + i / W, n = i % W)
   float2 wv[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = min(tid + k * T, 2 * W - 1), r = i >= W ? 1 : 0;
+    const int i = min(tid + k * T, RW * W - 1), r = i / W;
     wv[k] = at32(twf_x, i - r * W);
   }
   lds_sync();
-  cfft<+1, 4, T, M>(buf, tw, tid);
+  cfft<+1, B, T, M>(buf, tw, tid);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, r = i >= W ? 1 : 0, n = i - r * W;
-    if (i < 2 * W && y0 + r < H) {
-      const float2 e = buf[n * 4 + 2 * r], o = buf[n * 4 + 2 * r + 1];
+    const int i = tid + k * T, r = i / W, n = i - r * W;
+    if (i < RW * W && y0 + r < H) {
+      const float2 e = buf[n * B + 2 * r], o = buf[n * B + 2 * r + 1];
       out[((size_t)c * H + y0 + r) * W + n] = cadd(e, cmul(cconj(wv[k]), o));
     }
   }
 }
 
-template <int M>
-__global__ __launch_bounds__(kRowHalfThreads) __attribute__((amdgpu_waves_per_eu(4))) void
-k_row_loss_h(
+template <int M, int RW>
+__global__ __launch_bounds__(256 * RW) __attribute__((amdgpu_waves_per_eu(4))) void k_row_loss_h(
     float2 *__restrict__ S, int H, int W, const float2 *__restrict__ twf_x,
     const float *__restrict__ target, const float *__restrict__ grad_I,
     const float *__restrict__ mask, float *__restrict__ intensity, float2 *__restrict__ u_out,
     double *__restrict__ loss_part, float gscale, int make_grad) {
-  constexpr int T = kRowHalfThreads, K = (2 * M + T - 1) / T, Wt = M / 4;
-  __shared__ float2 buf[4 * M];
+  constexpr int T = 256 * RW, B = 2 * RW, K = (RW * M + T - 1) / T, Wt = M / 4;
+  __shared__ float2 buf[B * M];
   __shared__ float2 tw[M];
   __shared__ double red[T / 64];
   const int tid = threadIdx.x;
-  const int groups = (H + 1) >> 1;
-  const int c = blockIdx.x / groups, y0 = 2 * (blockIdx.x - c * groups);
+  const int groups = (H + RW - 1) / RW;
+  const int c = blockIdx.x / groups, y0 = RW * (blockIdx.x - c * groups);
   float2 *Sc = S + (size_t)c * Wt * H * 8;
   load_half_table<M, T>(tw, twf_x, tid);
-  load_row_pair<M, T>(buf, Sc, H, y0, tid);
+  load_row_group<M, RW, T>(buf, Sc, H, y0, tid);
   // per-element inputs of this thread (i: row y0 + i / W, n = i % W): target
   // and mask are fetched before the transform so that their latency overlaps
   // it; the twiddles w^n (cached in L2) after it, to stay within 128 registers
@@ -781,25 +780,25 @@ k_row_loss_h(
   float tv[K], mv[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = min(tid + k * T, 2 * W - 1), r = i >= W ? 1 : 0, n = i - r * W;
+    const int i = min(tid + k * T, RW * W - 1), r = i / W, n = i - r * W;
     const int y = min(y0 + r, H - 1);
     tv[k] = tsrc ? tsrc[((size_t)c * H + y) * W + n] : 0.f;
     mv[k] = mask ? mask[(size_t)y * W + n] : 0.f;
   }
   lds_sync();
-  cfft<+1, 4, T, M>(buf, tw, tid);
+  cfft<+1, B, T, M>(buf, tw, tid);
   float2 wv[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = min(tid + k * T, 2 * W - 1), r = i >= W ? 1 : 0;
+    const int i = min(tid + k * T, RW * W - 1), r = i / W;
     wv[k] = at32(twf_x, i - r * W);
   }
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, r = i >= W ? 1 : 0, n = i - r * W;
-    if (i < 2 * W) {
-      const float2 e = buf[n * 4 + 2 * r], o = buf[n * 4 + 2 * r + 1];
+    const int i = tid + k * T, r = i / W, n = i - r * W;
+    if (i < RW * W) {
+      const float2 e = buf[n * B + 2 * r], o = buf[n * B + 2 * r + 1];
       const float2 u = cadd(e, cmul(cconj(wv[k]), o));
       float f = 0.f;
       if (y0 + r < H) {
@@ -819,13 +818,13 @@ k_row_loss_h(
       if (make_grad) {
         // inputs of the forward chains, g[n] and g[n] w^n, in the same slots
         const float2 g = make_float2(f * u.x, f * u.y);
-        buf[n * 4 + 2 * r] = g;
-        buf[n * 4 + 2 * r + 1] = cmul(g, wv[k]);
+        buf[n * B + 2 * r] = g;
+        buf[n * B + 2 * r + 1] = cmul(g, wv[k]);
       }
     }
   }
   if (make_grad)
-    for (int i = tid; i < 4 * (M - W); i += T) buf[4 * W + i] = make_float2(0.f, 0.f);
+    for (int i = tid; i < B * (M - W); i += T) buf[B * W + i] = make_float2(0.f, 0.f);
   if (target) {
     for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
     if ((tid & 63) == 0) red[tid >> 6] = acc;
@@ -838,26 +837,26 @@ k_row_loss_h(
   }
   if (make_grad) {
     __syncthreads();
-    cfft<-1, 4, T, M>(buf, tw, tid);
-    store_row_pair<M, T>(buf, Sc, H, y0, tid);
+    cfft<-1, B, T, M>(buf, tw, tid);
+    store_row_group<M, RW, T>(buf, Sc, H, y0, tid);
   }
 }
 
 // rows per row-pass workgroup (specialised lengths use 4, the runtime path 2)
 static bool row_specialised(int Wp) { return Wp == 3840 || Wp == 512; }
-int row_group_rows(const Ctx &c) { return c.Wp == 512 ? 4 : 2; }
+// the half-length row passes take Wp = 3840 with W <= Wp / 2
+static bool row_half(const Ctx &c) { return c.Wp == 3840 && c.W <= 1920; }
+int row_group_rows(const Ctx &c) { return c.Wp == 512 ? 4 : (row_half(c) ? kRowHalfRows : 2); }
 static int row_blocks(const Ctx &c) {
   const int r = row_group_rows(c);
   return c.C * ((c.H + r - 1) / r);
 }
 static size_t row_lds(const Ctx &c) { return (size_t)2 * c.Wp * sizeof(float2); }
 
-// the half-length row passes take Wp = 3840 with W <= Wp / 2
-static bool row_half(const Ctx &c) { return c.Wp == 3840 && c.W <= 1920; }
-
 hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStream_t s) {
   if (row_half(c))
-    hipLaunchKernelGGL(k_row_fwd_h<1920>, dim3(row_blocks(c)), dim3(kRowHalfThreads), 0, s, field,
+    hipLaunchKernelGGL((k_row_fwd_h<1920, kRowHalfRows>), dim3(row_blocks(c)),
+                       dim3(256 * kRowHalfRows), 0, s, field,
                        c.H, c.W, c.twf_x, dst);
   else if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_fwd_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
@@ -876,7 +875,8 @@ hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStr
 
 hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStream_t s) {
   if (row_half(c))
-    hipLaunchKernelGGL(k_row_inv_h<1920>, dim3(row_blocks(c)), dim3(kRowHalfThreads), 0, s, src,
+    hipLaunchKernelGGL((k_row_inv_h<1920, kRowHalfRows>), dim3(row_blocks(c)),
+                       dim3(256 * kRowHalfRows), 0, s, src,
                        c.H, c.W, c.twf_x, out);
   else if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_inv_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
@@ -907,7 +907,8 @@ hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *ta
   if (mask) mask += (size_t)plane * c.H * c.W;  // [L][H][W]
   double *lp = c.loss_part + (size_t)plane * row_blocks(c);
   if (row_half(c))
-    hipLaunchKernelGGL(k_row_loss_h<1920>, dim3(row_blocks(c)), dim3(kRowHalfThreads), 0, s, buf,
+    hipLaunchKernelGGL((k_row_loss_h<1920, kRowHalfRows>), dim3(row_blocks(c)),
+                       dim3(256 * kRowHalfRows), 0, s, buf,
                        c.H, c.W, c.twf_x, target, grad_intensity, mask, intensity, u_out, lp,
                        gscale, make_grad);
   else if (c.Wp == 3840)
