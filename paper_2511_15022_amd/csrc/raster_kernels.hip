@@ -518,9 +518,13 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int X0 = tx * kTile + (wave & 1) * 8, Y0 = ty * kTile + (wave >> 1) * 8;
+  const int Xt = tx * kTile, Yt = ty * kTile;  // tile origin
+  const int sx = (wave & 1) * 8, sy = (wave >> 1) * 8;  // sub-block origin in the tile
+  const int X0 = Xt + sx, Y0 = Yt + sy;
   const int lx = lane & 7, ly = lane >> 3;
-  const float flx = (float)lx, fly = (float)ly;
+  // pixel offsets from the tile origin: d = (x - Xt) + ((Xt - floor(mean)) - frac(mean)),
+  // the same FP32 operations as the adjoint's
+  const float flx = (float)(sx + lx), fly = (float)(sy + ly);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   float ar[C], ai[C];
 #pragma unroll
@@ -553,10 +557,12 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
 #pragma unroll
     for (int qd = 0; qd < QD; ++qd) {
       const int idx = qd * 64 + lane;
-      // offsets of the sub-block's pixels from the mean: dx in [ex0, ex0 + 7],
-      // dy in [ey0, ey0 + 7] (the forward's own FP32 expressions at lx = ly = 0)
-      const float ex0 = (float)(X0 - __float_as_int(r0[qd].x)) - r0[qd].z;
-      const float ey0 = (float)(Y0 - __float_as_int(r0[qd].y)) - r0[qd].w;
+      // offsets of the tile origin from the mean (kept in the list), and of
+      // the sub-block's pixels: dx in [ex0, ex0 + 7], dy in [ey0, ey0 + 7]
+      // (to rounding; the culling test below has a margin)
+      const float ext = (float)(Xt - __float_as_int(r0[qd].x)) - r0[qd].z;
+      const float eyt = (float)(Yt - __float_as_int(r0[qd].y)) - r0[qd].w;
+      const float ex0 = ext + (float)sx, ey0 = eyt + (float)sy;
       const float rx = r1[qd].w + 0.01f, ry = ryv[qd] + 0.01f;
       bool hit = idx < cnt && (ex0 <= rx) && (ex0 + 7.f >= -rx) && (ey0 <= ry) &&
                  (ey0 + 7.f >= -ry);
@@ -582,7 +588,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
       const uint64_t m = __ballot(hit);
       if (hit)
         list[wave][n + __popcll(m & lt)] =
-            make_uint4(gid[qd], __float_as_uint(ex0), __float_as_uint(ey0), 0u);
+            make_uint4(gid[qd], __float_as_uint(ext), __float_as_uint(eyt), 0u);
       n += __popcll(m);
     }
     if (lane == 0) list[wave][n] = make_uint4(zero_id, 0u, 0u, 0u);  // pad to even length
@@ -666,11 +672,11 @@ constexpr int kAdjBatch = 64;
 constexpr int kAdjSeg = 8;  // pixels per segment
 
 // per-pair quantities kept in LDS for the walk (floats):
-//   0-3 offx0, offx1, offy0, offy1 (sub-block origin - floor(mean) - frac(mean))
-//   4-6 a, b, c;  7.. amplitude (2C);  then box, first segment, slot (int bits)
+//   0-1 offx, offy (tile origin - floor(mean) - frac(mean))
+//   2-4 a, b, c;  5.. amplitude (2C);  then box, first segment, slot (int bits)
 template <int C> struct AdjQ {
-  static constexpr int AMP = 7;
-  static constexpr int BOX = 7 + 2 * C, START = BOX + 1, SLOT = BOX + 2;
+  static constexpr int AMP = 5;
+  static constexpr int BOX = 5 + 2 * C, START = BOX + 1, SLOT = BOX + 2;
   static constexpr int N = ((SLOT + 1) + 3) & ~3;
 };
 
@@ -684,7 +690,9 @@ __global__ __launch_bounds__(64) void k_raster_adj(
   constexpr int PS = part_stride_c(C);
   constexpr int NS = 2 * C + 5;
   using Q = AdjQ<C>;
-  __shared__ float2 sg[kTile * kTile][C];
+  // dL/dU0 of the tile, plus one row of zeros (row kTile) that the padding
+  // pixels of a pair's last segment read when they run past the tile's last row
+  __shared__ float2 sg[(kTile + 1) * kTile][C];
   __shared__ float4 sq4[kAdjBatch * Q::N / 4];
   float *sq = reinterpret_cast<float *>(sq4);
   const int lane = threadIdx.x;
@@ -707,6 +715,7 @@ __global__ __launch_bounds__(64) void k_raster_adj(
       const int i = lane + 64 * k;
       sg[i % (kTile * kTile)][i / (kTile * kTile)] = v[k];
     }
+    if (lane < kTile * C) sg[kTile * kTile + lane / C][lane % C] = make_float2(0.f, 0.f);
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint2 rg = ranges[tile];
@@ -764,13 +773,11 @@ __global__ __launch_bounds__(64) void k_raster_adj(
       const int j = __popcll(nem & lt);
       float *q = sq + j * Q::N;
       const int mix = __float_as_int(r[R_MIX]), miy = __float_as_int(r[R_MIY]);
-      // same FP32 operations as the forward: d = (pixel offset in its 8x8
-      // sub-block) + ((sub-block origin - floor(mean)) - frac(mean))
+      // same FP32 operations as the forward: d = (pixel offset in the tile)
+      // + ((tile origin - floor(mean)) - frac(mean))
       q[0] = (float)(X0 - mix) - r[R_MFX];
-      q[1] = (float)(X0 + 8 - mix) - r[R_MFX];
-      q[2] = (float)(Y0 - miy) - r[R_MFY];
-      q[3] = (float)(Y0 + 8 - miy) - r[R_MFY];
-      q[4] = r[R_A]; q[5] = r[R_B]; q[6] = r[R_C];
+      q[1] = (float)(Y0 - miy) - r[R_MFY];
+      q[2] = r[R_A]; q[3] = r[R_B]; q[4] = r[R_C];
 #pragma unroll
       for (int k = 0; k < 2 * C; ++k) q[Q::AMP + k] = r[R_AMP + k];
       q[Q::BOX] = __int_as_float(xa | (xb << 8) | (ya << 16) | (yb << 24));
@@ -788,20 +795,19 @@ __global__ __launch_bounds__(64) void k_raster_adj(
         const int t = j + step;
         if (t < np && __float_as_int(sq[t * Q::N + Q::START]) <= s0) j = t;
       }
-      float offx0, offx1, offy0, offy1, qa, qb, qc, amp[2 * C];
-      int bxa, bxb, rem, lx, ly, sj, left, span = 0;
+      float offx, offy, qa, qb, qc, amp[2 * C];
+      int bxa, bxb, lx, ly, sj, left, span = 0;
       auto load_pair = [&](int jj) {
         const float *q = sq + jj * Q::N;
-        offx0 = q[0]; offx1 = q[1]; offy0 = q[2]; offy1 = q[3];
-        qa = q[4]; qb = q[5]; qc = q[6];
+        offx = q[0]; offy = q[1];
+        qa = q[2]; qb = q[3]; qc = q[4];
 #pragma unroll
         for (int k = 0; k < 2 * C; ++k) amp[k] = q[Q::AMP + k];
         const int bx = __float_as_int(q[Q::BOX]);
         bxa = bx & 0xff; bxb = (bx >> 8) & 0xff;
         const int bya = (bx >> 16) & 0xff, byb = (bx >> 24) & 0xff;
         sj = __float_as_int(q[Q::START]);
-        rem = (bxb - bxa + 1) * (byb - bya + 1);
-        left = (rem + kAdjSeg - 1) / kAdjSeg;
+        left = ((bxb - bxa + 1) * (byb - bya + 1) + kAdjSeg - 1) / kAdjSeg;
         lx = bxa; ly = bya;
       };
       auto flush_global = [&](int jj, const float *v) {
@@ -827,7 +833,6 @@ __global__ __launch_bounds__(64) void k_raster_adj(
           const int oy = o / wb;
           ly += oy;
           lx = bxa + (o - oy * wb);
-          rem -= o;
           left -= skip;
         }
         for (int s = s0; s < s1; ++s) {
@@ -846,15 +851,16 @@ __global__ __launch_bounds__(64) void k_raster_adj(
           }
 #pragma unroll
           for (int u = 0; u < kAdjSeg; ++u) {
-            const bool live = rem > 0;  // the last segment of a pair is padded
-            const float dy = (float)(ly & 7) + (ly < 8 ? offy0 : offy1);
-            const float dx = (float)(lx & 7) + (lx < 8 ? offx0 : offx1);
+            // The last segment of a pair is padded: its padding pixels run on
+            // along the box rows, below the box (outside the support, so G = 0)
+            // or below the tile (the zero row, so every term is 0).
+            const float dy = (float)ly + offy, dx = (float)lx + offx;
             const float p2 = fmaf(dx, fmaf(qa, dx, qb * dy), qc * dy * dy);
-            const float G = (live && p2 >= thr)
-                                ? __builtin_amdgcn_exp2f(CLAMP ? fmaxf(p2, kPowerFloor2) : p2)
-                                : 0.f;
+            const float G =
+                p2 >= thr ? __builtin_amdgcn_exp2f(CLAMP ? fmaxf(p2, kPowerFloor2) : p2) : 0.f;
             // 24-bit multiply (full rate) for the LDS offset
-            const float2 *gv = &sg[0][0] + __umul24((unsigned)(min(ly, kTile - 1) * kTile + lx), (unsigned)C);
+            const float2 *gv =
+                &sg[0][0] + __umul24((unsigned)(min(ly, kTile) * kTile + lx), (unsigned)C);
             float gp = 0.f;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -871,7 +877,6 @@ __global__ __launch_bounds__(64) void k_raster_adj(
             S[2 * C + 2] = fmaf(wx, dx, S[2 * C + 2]);
             S[2 * C + 3] = fmaf(wx, dy, S[2 * C + 3]);
             S[2 * C + 4] = fmaf(wy, dy, S[2 * C + 4]);
-            --rem;
             if (++lx > bxb) { lx = bxa; ++ly; }
           }
           --left;
