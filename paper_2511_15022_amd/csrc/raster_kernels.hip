@@ -674,10 +674,13 @@ constexpr int kAdjSeg = 8;  // pixels per segment
 // per-pair quantities kept in LDS for the walk (floats):
 //   0-1 offx, offy (tile origin - floor(mean) - frac(mean))
 //   2-4 a, b, c;  5.. amplitude (2C);  then box, first segment, slot (int bits)
+// The stride N is a multiple of 4 floats (16-byte reads) with N / 4 odd: lanes
+// reading different pairs then spread their 16-byte reads over all LDS banks.
 template <int C> struct AdjQ {
   static constexpr int AMP = 5;
   static constexpr int BOX = 5 + 2 * C, START = BOX + 1, SLOT = BOX + 2;
-  static constexpr int N = ((SLOT + 1) + 3) & ~3;
+  static constexpr int N4 = ((SLOT + 1) + 3) & ~3;
+  static constexpr int N = (N4 / 4) % 2 ? N4 : N4 + 4;
 };
 
 template <int C, bool CLAMP>
