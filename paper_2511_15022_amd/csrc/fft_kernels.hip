@@ -844,8 +844,8 @@ __global__ __launch_bounds__(256 * RW) __attribute__((amdgpu_waves_per_eu(4))) v
 
 // rows per row-pass workgroup (specialised lengths use 4, the runtime path 2)
 static bool row_specialised(int Wp) { return Wp == 3840 || Wp == 512; }
-// the half-length row passes take Wp = 3840 with W <= Wp / 2
-static bool row_half(const Ctx &c) { return c.Wp == 3840 && c.W <= 1920; }
+// the half-length row passes take Wp = 3840 (1080p) and 7680 (4K) with W <= Wp / 2
+static bool row_half(const Ctx &c) { return (c.Wp == 3840 || c.Wp == 7680) && 2 * c.W <= c.Wp; }
 int row_group_rows(const Ctx &c) { return c.Wp == 512 ? 4 : (row_half(c) ? kRowHalfRows : 2); }
 static int row_blocks(const Ctx &c) {
   const int r = row_group_rows(c);
@@ -854,7 +854,10 @@ static int row_blocks(const Ctx &c) {
 static size_t row_lds(const Ctx &c) { return (size_t)2 * c.Wp * sizeof(float2); }
 
 hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStream_t s) {
-  if (row_half(c))
+  if (row_half(c) && c.Wp == 7680)
+    hipLaunchKernelGGL((k_row_fwd_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
+                       dim3(256 * kRowHalfRows), 0, s, field, c.H, c.W, c.twf_x, dst);
+  else if (row_half(c))
     hipLaunchKernelGGL((k_row_fwd_h<1920, kRowHalfRows>), dim3(row_blocks(c)),
                        dim3(256 * kRowHalfRows), 0, s, field,
                        c.H, c.W, c.twf_x, dst);
@@ -874,7 +877,10 @@ hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStr
 }
 
 hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStream_t s) {
-  if (row_half(c))
+  if (row_half(c) && c.Wp == 7680)
+    hipLaunchKernelGGL((k_row_inv_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
+                       dim3(256 * kRowHalfRows), 0, s, src, c.H, c.W, c.twf_x, out);
+  else if (row_half(c))
     hipLaunchKernelGGL((k_row_inv_h<1920, kRowHalfRows>), dim3(row_blocks(c)),
                        dim3(256 * kRowHalfRows), 0, s, src,
                        c.H, c.W, c.twf_x, out);
@@ -906,7 +912,11 @@ hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *ta
   if (u_out) u_out += po;
   if (mask) mask += (size_t)plane * c.H * c.W;  // [L][H][W]
   double *lp = c.loss_part + (size_t)plane * row_blocks(c);
-  if (row_half(c))
+  if (row_half(c) && c.Wp == 7680)
+    hipLaunchKernelGGL((k_row_loss_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
+                       dim3(256 * kRowHalfRows), 0, s, buf, c.H, c.W, c.twf_x, target,
+                       grad_intensity, mask, intensity, u_out, lp, gscale, make_grad);
+  else if (row_half(c))
     hipLaunchKernelGGL((k_row_loss_h<1920, kRowHalfRows>), dim3(row_blocks(c)),
                        dim3(256 * kRowHalfRows), 0, s, buf,
                        c.H, c.W, c.twf_x, target, grad_intensity, mask, intensity, u_out, lp,
@@ -1171,6 +1181,89 @@ __global__ __launch_bounds__(T) void k_col_half_c(ColIO io, int H, int Wp, int W
 }
 
 // ----------------------------------------------------------------------------
+// Even/odd column pass for long columns (M = Hp / 2 = 2160 at 4K): a workgroup
+// takes half a tile (4 columns) and keeps both chains of each column in LDS,
+// eight interleaved M-point transforms (chain b = 2 c + p at buf[m * 8 + b]),
+// so no chain result has to wait in registers.  Blocks 2 t and 2 t + 1 take
+// the two halves of tile t.  Needs Wp % 8 == 0 and H <= M.
+// ----------------------------------------------------------------------------
+template <int M, int T>
+__global__ __launch_bounds__(T) void k_col_both(ColIO io, int H, int Wp, int Wt,
+                                                const float2 *__restrict__ twf_m,
+                                                const float2 *__restrict__ twh, int Wq,
+                                                int conj_h, float scale) {
+  __shared__ float2 buf[8 * M];
+  __shared__ float2 tw[M];
+  __shared__ TwLds th;
+  constexpr int NE = 4 * M, K = (NE + T - 1) / T, NB = 8 * M, KB = (NB + T - 1) / T;
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x >> 1, part = blockIdx.x & 1, ch = blockIdx.y;
+  const size_t off = ((size_t)ch * Wt + t) * H * 8 + part * 4;
+  const float2 *src = io.src + off;
+  float2 *dst = io.dst + off;
+  const float2 *hc = io.htab + ch * io.hstride;
+  load_table<M, T>(tw, twf_m, tid);
+  load_tw<T>(th, twh, tid);
+  {
+    // element i: row n = i / 4 of column c = i % 4
+    float2 xv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = min(tid + k * T, NE - 1), n = i >> 2;
+      xv[k] = at32(src, min(n, H - 1) * 8 + (i & 3));
+    }
+    __syncthreads();  // the twiddle tables are read below
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T, n = i >> 2, c = i & 3;
+      if (K * T == NE || i < NE) {
+        const float2 x = n < H ? xv[k] : make_float2(0.f, 0.f);
+        buf[n * 8 + 2 * c] = x;
+        buf[n * 8 + 2 * c + 1] = cmul(x, tw_at(th, n));  // odd chain: x[n] w^n
+      }
+    }
+  }
+  __syncthreads();
+  cfft<-1, 8, T, M>(buf, tw, tid);
+  {
+    // x H(ky = 2 m + p, kx): the table loads of a group are issued before the
+    // first is used
+    constexpr int G = 4;
+    const int kx0 = t * 8 + part * 4;
+#pragma unroll
+    for (int k0 = 0; k0 < KB; k0 += G) {
+      float2 hv[G];
+#pragma unroll
+      for (int k = k0; k < k0 + G && k < KB; ++k) {
+        const int i = min(tid + k * T, NB - 1), m = i >> 3, b = i & 7;
+        const int kx = kx0 + (b >> 1), ky = 2 * m + (b & 1);
+        hv[k - k0] = at32(hc, min(ky, 2 * M - ky) * Wq + min(kx, Wp - kx));
+      }
+#pragma unroll
+      for (int k = k0; k < k0 + G && k < KB; ++k) {
+        const int i = tid + k * T;
+        if (KB * T == NB || i < NB) {
+          float2 h = hv[k - k0];
+          if (conj_h) h.y = -h.y;
+          buf[i] = cmul(buf[i], cscale(h, scale));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  cfft<+1, 8, T, M>(buf, tw, tid);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * T, n = i >> 2, c = i & 3;
+    if ((K * T == NE || i < NE) && n < H) {
+      const float2 y = cadd(buf[n * 8 + 2 * c], cmul(cconj(tw_at(th, n)), buf[n * 8 + 2 * c + 1]));
+      float2 &d = at32(dst, n * 8 + c);
+      d = io.acc ? cadd(d, y) : y;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Column pass with one wave per chain, for M = Hp / 2 = R0 R1 R2 (1080 = 9 6 20);
 // CONJ: multiply by conj(H) (the adjoint pass).
 // A workgroup takes four columns of a tile; wave 2c + p runs chain p (even,
@@ -1312,6 +1405,9 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
     else
       hipLaunchKernelGGL((k_col_wave<9, 6, 20, false>), dim3((pairs + 7) / 8 * 32), dim3(512), 0,
                          s, io, ht, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_m, c.twf_y);
+  } else if (c.Hp == 4320 && c.H <= 2160 && c.Wp % 8 == 0) {
+    hipLaunchKernelGGL((k_col_both<2160, 512>), dim3(2 * c.Wt, c.C), dim3(512), 0, s, io, c.H,
+                       c.Wp, c.Wt, c.twf_m, c.tw_y, c.Wq, conj_h, scale);
   } else if (c.Hp == 2160) {
     hipLaunchKernelGGL((k_col_half_c<1080, 1024>), grid, dim3(1024), 0, s, io, c.H, c.Wp, c.Wt,
                        c.twf_m, c.tw_y, c.Wq, conj_h, scale);

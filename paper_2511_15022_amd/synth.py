@@ -82,7 +82,23 @@ def target(seed, C, H, W, L=1):
     return out
 
 
-# Named workloads: (H, W, C, Hp, Wp, pitch_m, wavelengths_m, z_m, N, params seed, target seed)
+def focal_masks(seed, L, H, W):
+    """[L, H, W] float32 one-hot focal masks: a smooth random depth map
+    (band-limited noise as in target(), radial |f| <= 1/64 cycles/px) split
+    at its quantiles into L depth bins of equal area; mask l is 1 where the
+    depth falls in bin l."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fy = np.fft.fftfreq(H)[:, None]
+    fx = np.fft.fftfreq(W)[None, :]
+    keep = (fx * fx + fy * fy) <= (1.0 / 64.0) ** 2
+    d = np.real(np.fft.ifft2(np.fft.fft2(rng.standard_normal((H, W))) * keep))
+    edges = np.quantile(d, [l / L for l in range(1, L)])
+    b = np.searchsorted(edges, d, side="right")
+    return np.stack([(b == l) for l in range(L)]).astype(np.float32)
+
+
+# Named workloads: (H, W, C, Hp, Wp, pitch_m, wavelengths_m, z_m, N, params seed, target seed);
+# masks: per-depth targets trained with focal masks (the reconstruction loss)
 WORKLOADS = {
     "tiny_256": dict(H=256, W=256, C=1, Hp=512, Wp=512, pitch=8e-6, lambdas=[515e-9],
                      zs=[2e-3], n=4096, pseed=0, tseed=1),
@@ -92,4 +108,7 @@ WORKLOADS = {
                              zs=[300e-3], n=4096, pseed=4, tseed=5),
     "rgb_4k": dict(H=2160, W=3840, C=3, Hp=4320, Wp=7680, pitch=3.74e-6,
                    lambdas=[639e-9, 515e-9, 473e-9], zs=[5e-3], n=1658880, pseed=6, tseed=7),
+    "rgb_4k_3z": dict(H=2160, W=3840, C=3, Hp=4320, Wp=7680, pitch=3.74e-6,
+                      lambdas=[639e-9, 515e-9, 473e-9], zs=[3e-3, 5e-3, 7e-3], n=1658880,
+                      pseed=6, tseed=7, masks=True),
 }

@@ -479,6 +479,41 @@ def test_rows_3840_narrow(O):
             assert e <= GRAD_TOL, (k, e)
 
 
+@pytest.mark.parametrize("case", [
+    # 4K column length: 2160 rows padded to 4320 (runtime-plan column pass, M = 2160)
+    dict(H=2160, W=40, Hp=4320, Wp=80),
+    # 4K row length: 3840 columns padded to 7680 (runtime-plan row passes)
+    dict(H=5, W=3840, Hp=10, Wp=7680),
+])
+def test_4k_pads_narrow(O, case):
+    """The padded lengths of the 4K workload, each on a narrow canvas:
+    propagation, its adjoint and the MSE backward against the oracle."""
+    H, W, Hp, Wp, C, n = case["H"], case["W"], case["Hp"], case["Wp"], 2, 300
+    lambdas, zs = [639e-9, 473e-9], [5e-3]
+    say("4k pads", case)
+    p = synth.params(81, n, H, W, C)
+    T = synth.target(82, C, H, W) * np.float32(0.5)
+    opt = O.Optics(H, W, C, Hp, Wp, 3.74e-6, lambdas, zs)
+    ctx = binding.Context(H, W, C, 3.74e-6, lambdas, zs, pad=(Hp, Wp), max_gaussians=n)
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    I, u = ctx.propagate(field, intensity=True, field_out=True)
+    u_ref = O.propagate(field.cpu().numpy().astype(np.complex128), opt)
+    assert rel_l2(u.cpu().numpy(), u_ref) <= FIELD_TOL
+    gI = np.random.default_rng(83).standard_normal((1, C, H, W)).astype(np.float32)
+    g = ctx.propagate_adjoint(field, torch.from_numpy(gI).cuda())
+    g_ref = O.propagate_adjoint(2.0 * gI.astype(np.float64) * u_ref, opt)
+    assert rel_l2(g.cpu().numpy(), g_ref) <= FIELD_TOL
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss, grad_field=gfield)
+    ref = O.forward_backward(p, T, opt)
+    assert abs(loss.cpu().numpy()[0] - ref["loss"]) <= 1e-4 * ref["loss"]
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
+    for k, e in group_errors(grads.cpu().numpy(), ref["grads"], n, C).items():
+        assert e <= GRAD_TOL, (k, e)
+
+
 def test_adan_step_matches_oracle(O):
     """Adan (the paper's optimiser, Sec. 4) over four steps with changing
     gradients and per-group learning rates, against the FP64 oracle."""
