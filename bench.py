@@ -373,27 +373,44 @@ def main():
         # field [C][H][W] one way, [C][H][Wp] the other
         "row_fft": C * H * (W + Wp) * 8,
     }
+    # per-pair and per-Gaussian byte counts of the record layouts (C channels)
+    rec_stride = ((9 + 2 * C) + 3) & ~3
+    part_stride = ((2 * C + 5) + 3) & ~3
+    nparam = 6 + 2 * C
+    hbm_bytes["preprocess"] = n * (nparam * 4 + rec_stride * 4 + 8 + 4)
+    hbm_bytes["preprocess_adjoint"] = n * (2 * nparam * 4 + 8) + pairs * part_stride * 4
+    npairs_cache = []
+
+    def class_roofline(cls):
+        t_launch = kernels[cls]["ms_per_launch"] * 1e-3
+        if cls in hbm_bytes:
+            achieved = hbm_bytes[cls] / t_launch / 1e9
+            return {"kernel": cls, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": measured_traffic(cls),
+                    "algorithmic_bytes_per_launch": hbm_bytes[cls]}
+        if cls in ("raster", "raster_adjoint"):
+            if not npairs_cache:
+                npairs_cache.append(in_support_pairs(p, H, W, 3.0))
+            npairs = npairs_cache[0]
+            per_pair = (10 + 4 * C) if cls == "raster" else (21 + 8 * C)
+            achieved = npairs * per_pair / t_launch / 1e12
+            return {"kernel": cls, "bound": "alu", "achieved": achieved,
+                    "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": measured_traffic(cls),
+                    "in_support_pairs": npairs, "flop_per_pair": per_pair}
+        label = {"binning": "latency (integer sort, ten short launches)",
+                 "loss": "latency (one-block FP64 reduction)"}.get(cls, "latency")
+        return {"kernel": cls, "bound": label}
+
     roofline = None
+    rooflines = {}
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-        t_launch = kernels[dom]["ms_per_launch"] * 1e-3
-        if dom in hbm_bytes:
-            achieved = hbm_bytes[dom] / t_launch / 1e9
-            roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved,
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": measured_traffic(dom),
-                        "algorithmic_bytes_per_launch": hbm_bytes[dom]}
-        elif dom in ("raster", "raster_adjoint"):
-            npairs = in_support_pairs(p, H, W, 3.0)
-            per_pair = (10 + 4 * C) if dom == "raster" else (21 + 8 * C)
-            achieved = npairs * per_pair / t_launch / 1e12
-            roofline = {"kernel": dom, "bound": "alu", "achieved": achieved,
-                        "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": achieved / FP32_VALU_PEAK_TFLOPS,
-                        "traffic": measured_traffic(dom),
-                        "in_support_pairs": npairs, "flop_per_pair": per_pair}
-        else:
-            roofline = {"kernel": dom, "bound": "unknown"}
+        roofline = class_roofline(dom)
+        for cls in kernels:
+            r = class_roofline(cls)
+            rooflines[cls] = {k: r[k] for k in ("bound", "achieved", "unit", "frac") if k in r}
 
     conv = None
     if args.convergence_steps > 0 and L == 1 and Mk is None:
@@ -455,6 +472,7 @@ def main():
                    "loss": "L_recon with focal masks" if Mk is not None else "MSE",
                    "parallelism": "single-gpu"},
         "roofline": roofline,
+        "rooflines": rooflines,
         "cpu_baseline": cpu,
         "convergence": conv,
         "autodiff": autodiff,

@@ -14,7 +14,7 @@ constexpr int kTile = 16;          // rasterizer tile edge, pixels
 constexpr int kMaxStages = 16;     // radix stages per FFT length
 constexpr int kMaxFft = 8192;      // longest supported FFT
 constexpr int kSortBits = 8;       // bits per radix-sort pass
-constexpr int kSortItems = 4096;   // keys per radix-sort block (256 threads x 16)
+constexpr int kSortItems = 2048;   // keys per radix-sort block (256 threads x 8)
 constexpr int kScanItems = 2048;   // elements per scan block (256 threads x 8)
 
 // Mixed-radix (2, 3, 4, 5, 8) Stockham plan for one transform length.

@@ -293,11 +293,11 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
   hist[(size_t)tid * nblocks + blockIdx.x] = h[tid];
 }
 
-// Stable scatter of one 8-bit digit.  Wave w of block b owns the 1024 keys
-// [4096 b + 1024 w, +1024), taken in index order 64 at a time; a key's rank
-// among equal digits of its wave is (the wave's running count of the digit) +
-// (earlier lanes of its round with that digit, from ballots over the digit
-// bits).  The waves of a block then add the counts of earlier waves, and the
+// Stable scatter of one 8-bit digit.  Wave w of block b owns the kSortItems / 4
+// keys from kSortItems b + (kSortItems / 4) w, taken in index order 64 at a
+// time; a key's rank among equal digits of its wave is (the wave's running
+// count of the digit) + (earlier lanes of its round with that digit, from
+// ballots over the digit bits).  The waves of a block then add the counts of earlier waves, and the
 // blocks the exclusive scan of the digit-major histogram: equal keys keep
 // their order.
 // hist_scan holds the digit-major histogram scanned either globally
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
   if (base >= count) return;  // the whole block is past the end (uniform)
 #pragma unroll
   for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
-  const uint32_t first = base + 1024u * wave + lane;
+  const uint32_t first = base + (uint32_t)(kSortItems / 4) * wave + lane;
   uint32_t key[R], val[R], rank[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
