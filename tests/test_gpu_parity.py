@@ -514,6 +514,53 @@ def test_4k_pads_narrow(O, case):
         assert e <= GRAD_TOL, (k, e)
 
 
+def test_graph_capture_replays_match_eager(O):
+    """The step's calls are stream-ordered with no host synchronisation or
+    allocation, so rasterize + backward can be captured into a HIP graph.
+    Replay it several times with the parameters changed eagerly between
+    replays (and eager work and synchronisations in between), and check every
+    replay bitwise against the eager calls on the same parameters."""
+    say("graph capture")
+    H, W, C, n = 48, 80, 3, 500
+    lambdas, zs = [639e-9, 515e-9, 473e-9], [4e-3, 6e-3]
+    p = synth.params(101, n, H, W, C)
+    T = torch.from_numpy(synth.target(102, C, H, W, L=2)).cuda()
+    ctx = binding.Context(H, W, C, 8e-6, lambdas, zs, pad=(90, 160), max_gaussians=n)
+    P = gpu_params(p)
+    field = torch.empty(ctx.field_shape(), dtype=torch.complex64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = torch.empty_like(P)
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    def run(f, gf, g, lo):
+        ctx.rasterize(P, n, f)
+        ctx.backward(P, n, f, T, loss=lo, grad_field=gf, grads=g)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run(field, gfield, grads, loss)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run(field, gfield, grads, loss)
+    torch.cuda.synchronize()
+    f_e, gf_e, g_e = torch.empty_like(field), torch.empty_like(gfield), torch.empty_like(grads)
+    lo_e = torch.zeros_like(loss)
+    gen = torch.Generator(device="cuda").manual_seed(103)
+    for rep in range(4):
+        P.add_(1e-3 * torch.randn(P.shape, device="cuda", generator=gen))  # eager work
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        run(f_e, gf_e, g_e, lo_e)
+        torch.cuda.synchronize()
+        say("replay", rep, "loss", loss[0].item(), lo_e[0].item())
+        assert torch.equal(field, f_e) and torch.equal(gfield, gf_e)
+        assert torch.equal(grads, g_e) and torch.equal(loss, lo_e)
+
+
 def test_adan_step_matches_oracle(O):
     """Adan (the paper's optimiser, Sec. 4) over four steps with changing
     gradients and per-group learning rates, against the FP64 oracle."""
