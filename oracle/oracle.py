@@ -203,6 +203,101 @@ def recon(u, target, mask):
     return loss, I, grad_u
 
 
+# SSIM (Wang, Bovik, Sheikh and Simoncelli 2004, "Image quality assessment:
+# from error visibility to structural similarity"), the L_SSIM term of the
+# paper's final loss (Sec. 3.2).  Reading: 11 x 11 Gaussian window of standard
+# deviation 1.5 normalised to sum 1, C1 = (0.01 R)^2 and C2 = (0.03 R)^2 with
+# R = 1 (intensities in [0, 1]), windows fully inside the image.
+SSIM_WIN = 11
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window():
+    """1-D weights w_i (i = 0..10), exp(-(i - 5)^2 / (2 1.5^2)) normalised; the
+    2-D window is w_i w_j."""
+    i = np.arange(SSIM_WIN) - SSIM_WIN // 2
+    w = np.exp(-(i * i) / (2.0 * 1.5 ** 2))
+    return w / w.sum()
+
+
+def _windows(a):
+    """[H, W] -> [H - 10, W - 10, 11, 11]: the window at every valid position."""
+    return np.lib.stride_tricks.sliding_window_view(a, (SSIM_WIN, SSIM_WIN))
+
+
+def ssim_parts(x, y):
+    """Window moments and SSIM at every valid position of two [H, W] images:
+    mu_x, mu_y, sigma_x^2, sigma_y^2, sigma_xy (weighted by the window) and
+    SSIM = (2 mu_x mu_y + C1)(2 sigma_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(sigma_x^2 + sigma_y^2 + C2))."""
+    w = ssim_window()
+    w2 = np.outer(w, w)
+    X, Y = _windows(np.asarray(x, np.float64)), _windows(np.asarray(y, np.float64))
+    mx = np.einsum("abij,ij->ab", X, w2)
+    my = np.einsum("abij,ij->ab", Y, w2)
+    sxx = np.einsum("abij,ij->ab", X * X, w2) - mx * mx
+    syy = np.einsum("abij,ij->ab", Y * Y, w2) - my * my
+    sxy = np.einsum("abij,ij->ab", X * Y, w2) - mx * my
+    n1, n2 = 2 * mx * my + SSIM_C1, 2 * sxy + SSIM_C2
+    d1, d2 = mx * mx + my * my + SSIM_C1, sxx + syy + SSIM_C2
+    return {"mu_x": mx, "mu_y": my, "s_xx": sxx, "s_yy": syy, "s_xy": sxy,
+            "ssim": n1 * n2 / (d1 * d2), "n1": n1, "n2": n2, "d1": d1, "d2": d2}
+
+
+def ssim_grad(x, y, coef):
+    """d(sum_p coef(p) SSIM(p)) / dx for one image pair.  With the window sums
+    mu_x = sum w x, e_xx = sum w x^2, e_xy = sum w x y, SSIM(p) depends on x(q)
+    through w(q - p) [dS/dmu_x + 2 x(q) dS/de_xx + y(q) dS/de_xy], where
+    dS/de_xx = dS/dsigma_x^2, dS/de_xy = dS/dsigma_xy and
+    dS/dmu_x = (partial at fixed sigmas) - 2 mu_x dS/dsigma_x^2 - mu_y dS/dsigma_xy."""
+    q = ssim_parts(x, y)
+    S, mx, my = q["ssim"], q["mu_x"], q["mu_y"]
+    den = q["d1"] * q["d2"]
+    dS_dmx = 2 * my * q["n2"] / den - 2 * mx * S / q["d1"]
+    dS_dsxx = -S / q["d2"]
+    dS_dsxy = 2 * q["n1"] / den
+    A = coef * (dS_dmx - 2 * mx * dS_dsxx - my * dS_dsxy)
+    B = coef * dS_dsxx
+    Cc = coef * dS_dsxy
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    w = ssim_window()
+    g = np.zeros_like(x)
+    Hv, Wv = S.shape
+    for i in range(SSIM_WIN):
+        for j in range(SSIM_WIN):
+            xs, ys = x[i:i + Hv, j:j + Wv], y[i:i + Hv, j:j + Wv]
+            g[i:i + Hv, j:j + Wv] += w[i] * w[j] * (A + 2 * xs * B + ys * Cc)
+    return g
+
+
+def ssim_loss(I, target):
+    """L_SSIM = 1 - mean SSIM over every plane, channel and valid window
+    position of I [L, C, H, W] against the target.  Returns (loss, dL/dI)."""
+    I = np.asarray(I, np.float64)
+    T = np.asarray(target, np.float64).reshape(I.shape)
+    L, C, H, W = I.shape
+    npos = L * C * (H - SSIM_WIN + 1) * (W - SSIM_WIN + 1)
+    total = 0.0
+    g = np.zeros_like(I)
+    for l in range(L):
+        for c in range(C):
+            total += ssim_parts(I[l, c], T[l, c])["ssim"].sum()
+            g[l, c] = -ssim_grad(I[l, c], T[l, c], 1.0 / npos)
+    return 1.0 - total / npos, g
+
+
+def full_loss(u, target, mask, ssim_weight):
+    """The paper's final training loss (Sec. 3.2): L_recon (L_MSE without a
+    mask) + ssim_weight L_SSIM.  Returns (loss, intensity, grad_u, psnr of the
+    plain MSE)."""
+    loss, I, grad_u = mse(u, target) if mask is None else recon(u, target, mask)
+    ls, gI = ssim_loss(I, target)
+    T = np.asarray(target, np.float64).reshape(I.shape)
+    m = float(np.mean((I - T) ** 2))
+    return loss + ssim_weight * ls, I, grad_u + ssim_weight * 2.0 * gI * u, 10.0 * np.log10(1.0 / m)
+
+
 def raster_adjoint(params, grad_field, opt):
     """Gradients of the pre-activation parameters from dL/dU0 (suppl. Backward Pass)."""
     p = widen(params)
@@ -220,19 +315,25 @@ def raster_adjoint(params, grad_field, opt):
     return out
 
 
-def forward(params, target, opt, support=None, mask=None):
+def forward(params, target, opt, support=None, mask=None, ssim_weight=0.0):
     """Alg. 1 forward: rasterize -> pad -> propagate -> |u|^2 -> L_MSE (or
-    L_recon when a depth mask is given)."""
+    L_recon when a depth mask is given), plus ssim_weight L_SSIM if nonzero."""
     field = raster(params, opt, support=support)
     u = propagate(field, opt)
-    loss, I, grad_u = mse(u, target) if mask is None else recon(u, target, mask)
-    return {"field": field, "u": u, "intensity": I, "loss": loss, "grad_u": grad_u}
+    out = {"field": field, "u": u}
+    if ssim_weight:
+        loss, I, grad_u, psnr = full_loss(u, target, mask, ssim_weight)
+        out["psnr"] = psnr
+    else:
+        loss, I, grad_u = mse(u, target) if mask is None else recon(u, target, mask)
+    out.update({"intensity": I, "loss": loss, "grad_u": grad_u})
+    return out
 
 
-def forward_backward(params, target, opt, mask=None):
+def forward_backward(params, target, opt, mask=None, ssim_weight=0.0):
     """Forward plus the analytic adjoint chain; returns the forward dict with
     ``grad_field`` (dL/dU0) and ``grads`` (pre-activation parameter gradients)."""
-    fwd = forward(params, target, opt, mask=mask)
+    fwd = forward(params, target, opt, mask=mask, ssim_weight=ssim_weight)
     fwd["grad_field"] = propagate_adjoint(fwd["grad_u"], opt)
     fwd["grads"] = raster_adjoint(params, fwd["grad_field"], opt)
     return fwd

@@ -2,8 +2,8 @@
 through the activations of Sec. 3.1) to automatic differentiation: the forward
 is restated here from the paper's formulas with torch operations in FP64
 (brute force over every pixel and Gaussian, FFT-based propagation with the
-band-limited transfer function, L_MSE or L_recon), and torch.autograd
-differentiates it.  The support indicator q <= k^2 is piecewise constant, so
+band-limited transfer function, L_MSE or L_recon, optionally + L_SSIM), and
+torch.autograd differentiates it.  The support indicator q <= k^2 is piecewise constant, so
 both sides differentiate the same function; agreement is to rounding."""
 import numpy as np
 import pytest
@@ -14,7 +14,27 @@ from paper_2511_15022_amd import synth
 KEYS = ("mean_pre", "log_scale", "rotation", "amplitude", "phase", "opacity_pre")
 
 
-def torch_loss(P, T, opt, Hs, k, mask=None):
+def torch_ssim(I, T):
+    """1 - mean SSIM (11 x 11 Gaussian window, sigma 1.5; C1 = 0.01^2,
+    C2 = 0.03^2; windows inside the image) with separable conv2d filtering."""
+    i = torch.arange(11, dtype=torch.float64) - 5
+    w = torch.exp(-(i * i) / (2 * 1.5 ** 2))
+    w = w / w.sum()
+    L, C, H, W = I.shape
+    x, y = I.reshape(L * C, 1, H, W), T.reshape(L * C, 1, H, W)
+
+    def f(a):
+        a = torch.nn.functional.conv2d(a, w.view(1, 1, 1, 11))
+        return torch.nn.functional.conv2d(a, w.view(1, 1, 11, 1))
+
+    mx, my = f(x), f(y)
+    sxx, syy, sxy = f(x * x) - mx * mx, f(y * y) - my * my, f(x * y) - mx * my
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    s = (2 * mx * my + c1) * (2 * sxy + c2) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
+    return 1 - s.mean()
+
+
+def torch_loss(P, T, opt, Hs, k, mask=None, ssim_weight=0.0):
     """P: dict of FP64 leaf tensors (pre-activation), T [L, C, H, W]."""
     H, W, C = opt.H, opt.W, opt.C
     mx = 0.5 * (torch.tanh(P["mean_pre"][:, 0]) + 1.0) * W
@@ -46,16 +66,20 @@ def torch_loss(P, T, opt, Hs, k, mask=None):
     I = u.real ** 2 + u.imag ** 2
     r = I - T
     n = I.numel()
+    extra = ssim_weight * torch_ssim(I, T) if ssim_weight else 0.0
     if mask is None:
-        return torch.sum(r * r) / n
+        return torch.sum(r * r) / n + extra
     Mk = mask[:, None]                                               # [L, 1, H, W]
-    return (torch.sum(r * r) + torch.sum((I * Mk - T * Mk) ** 2) + torch.sum((I * T - T * T) ** 2)) / n
+    return (torch.sum(r * r) + torch.sum((I * Mk - T * Mk) ** 2)
+            + torch.sum((I * T - T * T) ** 2)) / n + extra
 
 
 @pytest.mark.parametrize("case", [
     dict(C=2, zs=[3e-3], k=3.0, mask=False),
     dict(C=1, zs=[2e-3, -4e-3], k=3.0, mask=True),
     dict(C=1, zs=[3e-3], k=0.0, mask=False),  # unbounded support: the exponent clamp binds
+    # the paper's final loss: L_recon + 0.005 L_SSIM
+    dict(C=2, zs=[2e-3, 5e-3], k=3.0, mask=True, ssim=0.005),
 ])
 def test_adjoint_matches_autodiff(O, case):
     H, W, n = 20, 28, 30
@@ -68,13 +92,15 @@ def test_adjoint_matches_autodiff(O, case):
     mask = (np.random.default_rng(93).uniform(0, 1, (L, H, W)) > 0.5).astype(np.float32) \
         if case["mask"] else None
     opt = O.Optics(H, W, C, Hp, Wp, 8e-6, lambdas, zs, k=k)
-    ref = O.forward_backward(p, T, opt, mask=mask)
+    ssim = case.get("ssim", 0.0)
+    ref = O.forward_backward(p, T, opt, mask=mask, ssim_weight=ssim)
     Hs = torch.from_numpy(np.stack([np.stack([O.transfer(Hp, Wp, 8e-6, lam, z) for lam in lambdas])
                                     for z in zs]))                   # [L, C, Hp, Wp]
     P = {key: torch.tensor(np.asarray(p[key], dtype=np.float64), requires_grad=True)
          for key in KEYS}
     loss = torch_loss(P, torch.from_numpy(T.astype(np.float64)), opt, Hs, k,
-                      None if mask is None else torch.from_numpy(mask.astype(np.float64)))
+                      None if mask is None else torch.from_numpy(mask.astype(np.float64)),
+                      ssim_weight=ssim)
     assert abs(loss.item() - ref["loss"]) <= 1e-12 * ref["loss"]
     loss.backward()
     for key in KEYS:
