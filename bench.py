@@ -259,6 +259,52 @@ def run_autodiff(ctx, binding, P0, T, n, C, H, W, Hp, Wp, dev, reps=3):
     return out
 
 
+def run_paper_loss(binding, w, p, T, Mk, n, steps, dev, weight=0.005):
+    """The same step with the paper's final loss, L_recon (L_MSE without masks)
+    + weight L_SSIM, on a context that holds the SSIM workspace; times `steps`
+    steps after 3 warmup steps, and the SSIM kernels (loss class) alone."""
+    import torch
+    H, W, C = w["H"], w["W"], w["C"]
+    ctx = binding.Context(H, W, C, w["pitch"], w["lambdas"], w["zs"], pad=(w["Hp"], w["Wp"]),
+                          max_gaussians=n, full_loss=True, device=dev)
+    P = binding.pack(p, device=dev)
+    field = torch.empty(ctx.field_shape(), dtype=torch.complex64, device=dev)
+    G = torch.empty_like(P)
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    loss = torch.zeros(2, dtype=torch.float64, device=dev)
+    t = [0]
+
+    def step():
+        t[0] += 1
+        ctx.rasterize(P, n, field)
+        ctx.backward(P, n, field, T, loss=loss, grads=G, mask=Mk, ssim_weight=weight)
+        binding.step(P, G, M, V, t[0], 1e-3)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize(dev)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize(dev)
+    ms = a.elapsed_time(b) / steps
+    ctx.profile_begin("loss")
+    for _ in range(3):
+        step()
+    ms_loss, _ = ctx.profile_end()
+    out = {"ms_per_step": ms, "value": 1000.0 / ms, "unit": "it/s", "steps": steps,
+           "ssim_weight": weight, "loss": "L_recon + 0.005 L_SSIM" if Mk is not None
+           else "L_MSE + 0.005 L_SSIM", "final_loss": loss[0].item(),
+           "psnr_db": loss[1].item(), "ssim_us_per_step": ms_loss / 3 * 1e3,
+           "workspace_bytes": ctx.workspace_bytes}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,6 +318,8 @@ def main():
                     help="optimiser steps of the PSNR-vs-time run from plain init (0: skip)")
     ap.add_argument("--no-autodiff", action="store_true",
                     help="skip the fused-vs-autodiff comparison")
+    ap.add_argument("--paper-loss-steps", type=int, default=20,
+                    help="timed steps with the paper's final loss, L + 0.005 L_SSIM (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -412,6 +460,17 @@ def main():
             r = class_roofline(cls)
             rooflines[cls] = {k: r[k] for k in ("bound", "achieved", "unit", "frac") if k in r}
 
+    paper_loss = None
+    if args.paper_loss_steps > 0:
+        log(f"[bench] paper's final loss (+ 0.005 L_SSIM): {args.paper_loss_steps} steps")
+        try:
+            paper_loss = run_paper_loss(binding, w, p, T, Mk, n, args.paper_loss_steps, dev)
+            log(f"[bench]   {paper_loss['ms_per_step']:.4f} ms/step; "
+                f"ssim kernels {paper_loss['ssim_us_per_step']:.1f} us/step")
+        except Exception as e:
+            paper_loss = {"error": f"{type(e).__name__}: {e}"[:300]}
+        torch.cuda.empty_cache()
+
     conv = None
     if args.convergence_steps > 0 and L == 1 and Mk is None:
         log(f"[bench] convergence from plain init: {args.convergence_steps} Adam steps")
@@ -476,6 +535,7 @@ def main():
         "cpu_baseline": cpu,
         "convergence": conv,
         "autodiff": autodiff,
+        "paper_loss": paper_loss,
         "kernels_us_per_step": {k: round(v["ms_per_step"] * 1e3, 2) for k, v in kernels.items()},
         "tile_pairs": pairs,
         "peak_vram_gb": peak_vram / 1e9,

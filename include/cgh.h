@@ -85,8 +85,13 @@ typedef struct {
   int32_t max_gaussians;         /* capacity for n                                        */
   int64_t max_pairs;             /* capacity of the (tile, Gaussian) list (0: default     */
                                  /* 8 * max_gaussians + 65536)                            */
-  int32_t flags;                 /* reserved, must be 0                                   */
+  int32_t flags;                 /* 0 or CGH_FULL_LOSS                                    */
 } cgh_config;
+
+/* cgh_config.flags: reserve the workspace of cgh_backward_full (the SSIM term:
+ * intensity, propagated field and three coefficient maps per plane and
+ * channel, about 24 bytes per element of [L][C][H][W]); needs H, W >= 11. */
+#define CGH_FULL_LOSS 1
 
 typedef struct cgh_ctx cgh_ctx;
 
@@ -148,10 +153,30 @@ cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_
  *   mask : [L][H][W] float, the per-plane depth mask M_l (binary in the paper;
  *          any real weight is accepted), shared by the channels.
  * Other arguments, outputs and preconditions as cgh_backward; loss[1] is
- * 10 log10(1 / L).  The SSIM term of the paper's final loss is not included. */
+ * 10 log10(1 / L).  The SSIM term of the paper's final loss is in
+ * cgh_backward_full. */
 cgh_status cgh_backward_recon(cgh_ctx *ctx, const float *params, int32_t n,
                               const cgh_c64 *field, const float *target, const float *mask,
                               double *loss, cgh_c64 *grad_field, float *grads, void *stream);
+
+/* The paper's final training loss (Sec. 3.2, L = L_recon + lambda_1 L_SSIM, the
+ * paper uses lambda_1 = 0.005) and its adjoint: L_recon as cgh_backward_recon
+ * (L_MSE when mask is NULL) plus ssim_weight * L_SSIM, with
+ * L_SSIM = 1 - (mean SSIM over planes, channels and window positions).  SSIM
+ * is the structural similarity of Wang, Bovik, Sheikh and Simoncelli (2004)
+ * between I_l and the target of the same plane and channel: an 11 x 11
+ * Gaussian window (standard deviation 1.5, normalised to sum 1) at every
+ * position fully inside the H x W image, C1 = 0.01^2, C2 = 0.03^2 (intensities
+ * in [0, 1]).  loss[0] = L; loss[1] = 10 log10(1 / MSE) with the plain MSE
+ * between I and the target (the reported PSNR).
+ * Needs a context created with CGH_FULL_LOSS (else CGH_ERR_STATE) and
+ * ssim_weight >= 0 and finite (else CGH_ERR_INVALID_ARG).  Other arguments,
+ * outputs and preconditions as cgh_backward_recon, except that mask may be
+ * NULL. */
+cgh_status cgh_backward_full(cgh_ctx *ctx, const float *params, int32_t n,
+                             const cgh_c64 *field, const float *target, const float *mask,
+                             float ssim_weight, double *loss, cgh_c64 *grad_field,
+                             float *grads, void *stream);
 
 /* Adjoint of cgh_propagate's intensity for an arbitrary loss: given
  * grad_intensity = dL/dI ([L][C][H][W]) at I = |u(field)|^2, writes

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libcgh.so")
 
 MAX_CHANNELS = 4
 MAX_PLANES = 8
+CGH_FULL_LOSS = 1  # cgh_config.flags bit: workspace for cgh_backward_full
 PARAM_KEYS = ("mean_pre", "log_scale", "rotation", "amplitude", "phase", "opacity_pre")
 
 KERNEL_CLASSES = {"preprocess": 1, "binning": 2, "raster": 3, "row_fft": 4, "col_pass": 5,
@@ -55,6 +56,8 @@ _SIGS = [
     ("cgh_backward", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cgh_backward_recon", ctypes.c_int,
      [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("cgh_backward_full", ctypes.c_int,
+     [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_float, _VP, _VP, _VP, _VP]),
     ("cgh_propagate_adjoint", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("cgh_rasterize_adjoint", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
     ("cgh_step", ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
@@ -139,7 +142,8 @@ class Context:
     device workspace is a torch tensor owned by this object."""
 
     def __init__(self, height, width, channels, pitch, wavelengths, zs, pad=None,
-                 support_sigma=3.0, max_gaussians=0, max_pairs=0, device="cuda"):
+                 support_sigma=3.0, max_gaussians=0, max_pairs=0, full_loss=False,
+                 device="cuda"):
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -161,7 +165,7 @@ class Context:
         cfg.support_sigma = float(support_sigma)
         cfg.max_gaussians = int(max_gaussians)
         cfg.max_pairs = int(max_pairs)
-        cfg.flags = 0
+        cfg.flags = CGH_FULL_LOSS if full_loss else 0
         self.cfg = cfg
         self.L = len(zs)
         self.Hp = cfg.pad_height or 2 * self.H
@@ -216,8 +220,10 @@ class Context:
         return I, u
 
     def backward(self, params, n, field, target, loss=None, grad_field=None, grads=None,
-                 mask=None):
-        """L_MSE backward; with ``mask`` ([L][H][W]) the L_recon backward."""
+                 mask=None, ssim_weight=None):
+        """L_MSE backward; with ``mask`` ([L][H][W]) the L_recon backward; with
+        ``ssim_weight`` (a context made with ``full_loss=True``) the final loss
+        L_recon (or L_MSE) + ssim_weight L_SSIM."""
         _need(params, torch.float32, param_count(n, self.C), "params", self.device)
         _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)
         _need(target, torch.float32, self.L * self.C * self.H * self.W, "target", self.device)
@@ -227,12 +233,18 @@ class Context:
             _need(loss, torch.float64, 2, "loss", self.device)
         if grad_field is not None:
             _need(grad_field, torch.complex64, self.C * self.H * self.W, "grad_field", self.device)
-        if mask is None:
+        if mask is not None:
+            _need(mask, torch.float32, self.L * self.H * self.W, "mask", self.device)
+        if ssim_weight is not None:
+            _check(lib().cgh_backward_full(self.handle, _ptr(params), int(n), _ptr(field),
+                                           _ptr(target), _ptr(mask), float(ssim_weight),
+                                           _ptr(loss), _ptr(grad_field), _ptr(grads),
+                                           _stream(self.device)))
+        elif mask is None:
             _check(lib().cgh_backward(self.handle, _ptr(params), int(n), _ptr(field),
                                       _ptr(target), _ptr(loss), _ptr(grad_field), _ptr(grads),
                                       _stream(self.device)))
         else:
-            _need(mask, torch.float32, self.L * self.H * self.W, "mask", self.device)
             _check(lib().cgh_backward_recon(self.handle, _ptr(params), int(n), _ptr(field),
                                             _ptr(target), _ptr(mask), _ptr(loss),
                                             _ptr(grad_field), _ptr(grads),

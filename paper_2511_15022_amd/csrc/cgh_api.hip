@@ -73,7 +73,10 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
     return fail(CGH_ERR_INVALID_ARG, "max_gaussians must be in [0, 2^28]");
   if (f.max_pairs < 0 || f.max_pairs > 0x7fffffffLL)
     return fail(CGH_ERR_INVALID_ARG, "max_pairs must be in [0, 2^31)");
-  if (f.flags != 0) return fail(CGH_ERR_INVALID_ARG, "flags must be 0 in this build");
+  if (f.flags & ~CGH_FULL_LOSS)
+    return fail(CGH_ERR_INVALID_ARG, "flags: unknown bits 0x%x", f.flags & ~CGH_FULL_LOSS);
+  if ((f.flags & CGH_FULL_LOSS) && (f.height < 11 || f.width < 11))
+    return fail(CGH_ERR_INVALID_ARG, "CGH_FULL_LOSS needs height, width >= 11 (the SSIM window)");
 
   c->cfg = f;
   c->cfg.pad_height = Hp;
@@ -175,6 +178,20 @@ size_t carve(Ctx *c, char *base) {
   const int rg = row_group_rows(*c);  // one loss partial per row-pass workgroup
   c->loss_part = (double *)take(sizeof(double) * c->L * c->C * (size_t)((c->H + rg - 1) / rg));
   c->status = (uint32_t *)take(sizeof(uint32_t) * 4);
+  c->ssim_I = nullptr;
+  c->ssim_u = nullptr;
+  c->ssim_abc = nullptr;
+  c->ssim_part = nullptr;
+  c->mse_part = nullptr;
+  if (c->cfg.flags & CGH_FULL_LOSS) {
+    const size_t LC = (size_t)c->L * c->C;
+    const size_t valid = (size_t)(c->H - 10) * (c->W - 10);
+    c->ssim_I = (float *)take(sizeof(float) * LC * HW);
+    c->ssim_u = (float2 *)take(sizeof(float2) * LC * HW);
+    c->ssim_abc = (float *)take(sizeof(float) * 3 * LC * valid);
+    c->ssim_part = (double *)take(sizeof(double) * LC * ssim_pos_tiles(*c));
+    c->mse_part = (double *)take(sizeof(double) * LC * ssim_pix_tiles(*c));
+  }
   return (off + 255) & ~(size_t)255;
 }
 
@@ -401,6 +418,60 @@ cgh_status cgh_backward_recon(cgh_ctx *ctx, const float *params, int32_t n,
                               double *loss, cgh_c64 *grad_field, float *grads, void *stream) {
   if (!mask) return fail(CGH_ERR_INVALID_ARG, "mask is NULL");
   return backward_impl(ctx, params, n, field, target, mask, loss, grad_field, grads, stream);
+}
+
+cgh_status cgh_backward_full(cgh_ctx *ctx, const float *params, int32_t n,
+                             const cgh_c64 *field, const float *target, const float *mask,
+                             float ssim_weight, double *loss, cgh_c64 *grad_field,
+                             float *grads, void *stream) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  Ctx &c = ctx->c;
+  if (!(c.cfg.flags & CGH_FULL_LOSS))
+    return fail(CGH_ERR_STATE, "cgh_backward_full needs a context created with CGH_FULL_LOSS");
+  if (!(ssim_weight >= 0.f) || !std::isfinite(ssim_weight))
+    return fail(CGH_ERR_INVALID_ARG, "ssim_weight must be >= 0 and finite");
+  cgh_status st = check_n(c, n);
+  if (st != CGH_OK) return st;
+  if (n != c.last_n)
+    return fail(CGH_ERR_STATE, "backward with n = %d after rasterize with n = %d", n, c.last_n);
+  if (!field || !target || (n > 0 && (!params || !grads)))
+    return fail(CGH_ERR_INVALID_ARG, "field/target/params/grads is NULL");
+  if (!aligned16(field) || !aligned16(grad_field) || ((uintptr_t)loss & 7u))
+    return fail(CGH_ERR_INVALID_ARG, "misaligned buffer");
+  hipStream_t s = (hipStream_t)stream;
+  float2 *gf = grad_field ? reinterpret_cast<float2 *>(grad_field) : c.gfield_tmp;
+  // forward: every plane's intensity, field and L_recon partials
+  st = row_spectrum(c, field, s);
+  if (st != CGH_OK) return st;
+  for (int l = 0; l < c.L; ++l) {
+    st = plane_spectrum(c, l, s);
+    if (st != CGH_OK) return st;
+    ProfScope p(c, CGH_KERNEL_ROW_LOSS, s);
+    CGH_CHECK_LAUNCH(cgh::launch_row_loss(c, l, c.spec_plane, target, nullptr, mask, c.ssim_I,
+                                          c.ssim_u, 0, s),
+                     "loss row pass");
+  }
+  // SSIM and dL/dI over all planes; ssim_u becomes 2 (dL/dI) u
+  {
+    ProfScope p(c, CGH_KERNEL_LOSS, s);
+    CGH_CHECK_LAUNCH(cgh::launch_ssim_fwd(c, target, s), "ssim");
+    CGH_CHECK_LAUNCH(cgh::launch_ssim_bwd(c, target, mask, ssim_weight, s), "ssim adjoint");
+    if (loss) CGH_CHECK_LAUNCH(cgh::launch_full_loss_finalize(c, ssim_weight, loss, s), "loss");
+  }
+  // adjoint of the propagation from the intensity gradient, plane by plane
+  for (int l = 0; l < c.L; ++l) {
+    {
+      ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
+      CGH_CHECK_LAUNCH(cgh::launch_row_fwd(c, c.ssim_u + (size_t)l * c.C * c.H * c.W,
+                                           c.spec_plane, s),
+                       "adjoint seed row fft");
+    }
+    st = plane_adjoint(c, l, s);
+    if (st != CGH_OK) return st;
+  }
+  st = adjoint_rows(c, gf, s);
+  if (st != CGH_OK) return st;
+  return raster_adjoint(c, params, n, gf, grads, s);
 }
 
 cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,

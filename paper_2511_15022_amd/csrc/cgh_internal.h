@@ -91,6 +91,12 @@ struct Ctx {
   uint32_t *scan_tmp;               // partial sums for scans
   float *partials;                  // [pair_cap][part_stride] raster-adjoint partials
   double *loss_part;                // [L][row-pass workgroups] FP64 loss partials
+  // cgh_backward_full only (CGH_FULL_LOSS), else null
+  float *ssim_I;                    // [L][C][H][W] intensity
+  float2 *ssim_u;                   // [L][C][H][W] propagated field, then 2 dL/dI u
+  float *ssim_abc;                  // [3][L][C][H - 10][W - 10] SSIM gradient coefficients
+  double *ssim_part;                // [L][C][position tiles] sums of SSIM
+  double *mse_part;                 // [L][C][pixel tiles] sums of (I - T)^2
   uint32_t *status;                 // [0] overflow flag, [1] pair total
   int sorted;                       // which ping-pong buffer holds the sorted pairs
   // kernel-class timing (cgh_profile_begin / _end)
@@ -121,6 +127,16 @@ hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *ta
                            const float *grad_intensity, const float *mask, float *intensity,
                            float2 *u_out, int make_grad, hipStream_t s);
 hipError_t launch_loss_finalize(const Ctx &c, double *loss, hipStream_t s);
+
+// SSIM term of the full loss over the [L][C] images in c.ssim_I against target
+int ssim_pos_tiles(const Ctx &c);   // position tiles per image (k_ssim_fwd)
+int ssim_pix_tiles(const Ctx &c);   // pixel tiles per image (k_ssim_bwd)
+hipError_t launch_ssim_fwd(const Ctx &c, const float *target, hipStream_t s);
+// c.ssim_u <- 2 (dL_recon/dI + ssim_weight dL_SSIM/dI) u, and the MSE partials
+hipError_t launch_ssim_bwd(const Ctx &c, const float *target, const float *mask,
+                           float ssim_weight, hipStream_t s);
+hipError_t launch_full_loss_finalize(const Ctx &c, float ssim_weight, double *loss,
+                                     hipStream_t s);
 
 hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s);
 hipError_t launch_zero_record(const Ctx &c, hipStream_t s);

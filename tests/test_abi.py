@@ -79,12 +79,26 @@ def test_several_planes_accepted_and_sized():
     assert eight - three <= 5 * table + 8192
 
 
+def test_full_loss_flag_reserves_the_ssim_buffers():
+    """CGH_FULL_LOSS adds, per element of [L][C][H][W], the intensity (4 B) and
+    the propagated field (8 B), three FP32 coefficient maps over the valid
+    window positions, and the per-tile sums; nothing else changes."""
+    kw = dict(H=200, W=120, C=3, lambdas=[639e-9, 515e-9, 473e-9], zs=[2e-3, 4e-3])
+    st0, base = ws(cfg(**kw))
+    st1, full = ws(cfg(flags=binding.CGH_FULL_LOSS, **kw))
+    assert st0 == st1 == 0
+    LC = 2 * 3
+    need = LC * 200 * 120 * 12 + 3 * LC * 190 * 110 * 4
+    assert need <= full - base <= need + 5 * 256 + 8 * LC * 2 * 7 * 4
+
+
 @pytest.mark.parametrize("bad, status", [
     (dict(H=0), 1), (dict(W=9000), 1), (dict(C=5), 1), (dict(C=0), 1),
     (dict(Hp=514), 1),            # 514 = 2 * 257 does not factor into 2, 3, 5
     (dict(Hp=200), 1),            # smaller than H
     (dict(pitch=0.0), 1), (dict(lambdas=[-1.0]), 1), (dict(n=-1), 1),
-    (dict(flags=1), 1), (dict(pairs=-5), 1),
+    (dict(flags=2), 1), (dict(pairs=-5), 1),
+    (dict(flags=1, H=10), 1), (dict(flags=1, W=10, Wp=20), 1),   # SSIM window is 11 x 11
     (dict(L=0), 1), (dict(zs=[1e-3] * 8, L=9), 1),   # 1 <= planes <= CGH_MAX_PLANES
     (dict(zs=[1e-3, float("nan")]), 1),
 ])
@@ -99,6 +113,8 @@ def test_null_arguments_are_rejected_without_device_work():
     assert L.cgh_workspace_size(None, None) == 1
     assert L.cgh_rasterize(None, None, 0, None, None) == 1
     assert L.cgh_backward(None, None, 0, None, None, None, None, None, None) == 1
+    assert L.cgh_backward_full(None, None, 0, None, None, None, 0.005, None, None, None,
+                               None) == 1
     assert L.cgh_step(None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None, 1, None) == 0
     assert L.cgh_step(None, None, None, None, 10, 1, 1e-3, 0.9, 0.999, 1e-8, None, 1, None) == 1
     c = cfg()

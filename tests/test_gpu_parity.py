@@ -441,6 +441,82 @@ def test_recon_loss_parity(O):
         assert e <= GRAD_TOL, (k, e)
 
 
+@pytest.mark.parametrize("case", [
+    # the paper's weight, depth masks, two planes; 38 x 70 window positions
+    # (2 x 3 position tiles, both ragged) and 2 x 3 pixel tiles
+    dict(H=48, W=80, C=3, zs=[4e-3, 6e-3], Hp=90, Wp=160, mask=True, w=0.005),
+    # SSIM-dominated gradient, plain MSE, one plane; 90 x 125 positions
+    dict(H=100, W=135, C=2, zs=[3e-3], Hp=200, Wp=270, mask=False, w=5.0),
+    # the smallest image the window fits: one position per image
+    dict(H=11, W=11, C=1, zs=[2e-3], Hp=80, Wp=80, mask=False, w=1.0),
+])
+def test_full_loss_parity(O, case):
+    """The final loss L_recon (or L_MSE) + w L_SSIM (Sec. 3.2) and its adjoint
+    against the oracle: loss, PSNR of the plain MSE, dL/dU0 and the parameter
+    gradients; with w = 0 the result equals cgh_backward's."""
+    say("full loss", case)
+    H, W, C, zs = case["H"], case["W"], case["C"], case["zs"]
+    # the paper's density, one Gaussian per 5 pixels: denser canvases make the
+    # FP32/FP64 support-boundary decisions (not the loss) dominate the error
+    L, n = len(zs), max(24, H * W // 5)
+    lambdas = [639e-9, 515e-9, 473e-9][:C]
+    p = synth.params(91, n, H, W, C)
+    T = synth.target(92, C, H, W, L=L) * np.float32(0.5)
+    M = ((np.random.default_rng(93).uniform(0, 1, (L, H, W)) > 0.5).astype(np.float32)
+         if case["mask"] else None)
+    opt = O.Optics(H, W, C, case["Hp"], case["Wp"], 8e-6, lambdas, zs)
+    ctx = binding.Context(H, W, C, 8e-6, lambdas, zs, pad=(case["Hp"], case["Wp"]),
+                          max_gaussians=n, full_loss=True)
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    Tg = torch.from_numpy(T).cuda()
+    Mg = None if M is None else torch.from_numpy(M).cuda()
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = ctx.backward(P, n, field, Tg, loss=loss, grad_field=gfield, mask=Mg,
+                         ssim_weight=case["w"])
+    torch.cuda.synchronize()
+    ref = O.forward_backward(p, T, opt, mask=M, ssim_weight=case["w"])
+    lg = loss.cpu().numpy()
+    say("loss gpu", lg, "oracle", ref["loss"], ref["psnr"])
+    assert abs(lg[0] - ref["loss"]) <= 1e-4 * abs(ref["loss"])
+    assert abs(lg[1] - ref["psnr"]) < 1e-3
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
+    errs = group_errors(grads.cpu().numpy(), ref["grads"], n, C)
+    say("grad rel-L2 per group", errs)
+    for k, e in errs.items():
+        assert e <= GRAD_TOL, (k, e)
+    # w = 0 reduces to the L_recon / L_MSE backward (same kernels up to the seed)
+    loss0 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    g0 = ctx.backward(P, n, field, Tg, loss=loss0, mask=Mg, ssim_weight=0.0)
+    loss1 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    g1 = ctx.backward(P, n, field, Tg, loss=loss1, mask=Mg)
+    torch.cuda.synchronize()
+    assert abs(loss0[0].item() - loss1[0].item()) <= 1e-12 * abs(loss1[0].item())
+    assert rel_l2(g0.cpu().numpy(), g1.cpu().numpy()) <= 1e-5
+
+
+def test_full_loss_rejections(O):
+    """A context without CGH_FULL_LOSS refuses cgh_backward_full (state error);
+    a negative or non-finite weight is an argument error."""
+    p, T, opt, ctx = tiny(O)
+    n = WORK["tiny_256"]["n"]
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    with pytest.raises(binding.CghError) as e:
+        ctx.backward(P, n, field, torch.from_numpy(T).cuda(), ssim_weight=0.005)
+    assert e.value.status == 6
+    w = WORK["tiny_256"]
+    ctx2 = binding.Context(w["H"], w["W"], w["C"], w["pitch"], w["lambdas"], w["zs"],
+                           pad=(w["Hp"], w["Wp"]), max_gaussians=n, full_loss=True)
+    field = ctx2.rasterize(P, n)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(binding.CghError) as e:
+            ctx2.backward(P, n, field, torch.from_numpy(T).cuda(), ssim_weight=bad)
+        assert e.value.status == 1
+    torch.cuda.synchronize()
+
+
 def test_rows_3840_narrow(O):
     """The 3840-wide row passes (one wave per half-length chain) with fewer
     columns than Wp / 2 and an odd number of rows (the last workgroup has a
