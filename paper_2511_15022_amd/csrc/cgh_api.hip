@@ -151,9 +151,10 @@ size_t carve(Ctx *c, char *base) {
   c->twf_x = (float2 *)take(sizeof(float2) * c->Wp);
   c->twf_m = (float2 *)take(sizeof(float2) * c->plan_m.n);
   c->htab = (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq);
-  c->htab_t = col_wave(*c) ? (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq)
-                           : nullptr;
-  c->twf_y = col_wave(*c) ? (float2 *)take(sizeof(float2) * c->Hp) : nullptr;
+  const bool wave_cols = col_wave(*c) || col_wave4(*c);
+  c->htab_t = wave_cols ? (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq)
+                        : nullptr;
+  c->twf_y = wave_cols ? (float2 *)take(sizeof(float2) * c->Hp) : nullptr;
   const size_t spec_len = (size_t)c->C * c->Wt * c->H * 8;
   c->spec = (float2 *)take(sizeof(float2) * spec_len);
   // with several planes the shared row spectrum stays in spec; each plane's

@@ -111,6 +111,8 @@ size_t carve(Ctx *c, char *base);   // returns bytes used (base may be null)
 // The column pass runs one wave per column chain (k_col_wave) for Hp = 2160
 // with every column tile full; it reads the column-major transfer table.
 inline bool col_wave(const Ctx &c) { return c.Hp == 2160 && c.H <= 1080 && c.Wp % 8 == 0; }
+// ... and four chains per column (k_col_wave4) for Hp = 4320 with H <= 2160
+inline bool col_wave4(const Ctx &c) { return c.Hp == 4320 && c.H <= 2160 && c.Wp % 8 == 0; }
 
 // ---- launchers (all enqueue on `s`; return hipSuccess or the launch error) ----
 hipError_t launch_build_twiddles(float2 *tw, int n, hipStream_t s);

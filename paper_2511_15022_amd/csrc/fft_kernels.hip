@@ -1390,6 +1390,148 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
+// ----------------------------------------------------------------------------
+// Column pass for Hp = 4 M (4320 = 4 x 1080) with H <= 2 M, one wave per chain.
+// Output bin 4 m + p of the padded column is bin m of the M-point transform
+// of w^{p n} (x[n] + (-i)^p x[n + M]) (n < M; w = e^{-2 pi i / Hp}), so a
+// column is four M-point chains; the inverse gives u[n + M j] = sum_p
+// w^{-p n} i^{p j} z_p[n] for j = 0, 1.  A workgroup takes two columns of a
+// quarter tile; wave 4 c + p runs chain p of column c with the same
+// per-wave stages, fused transfer multiply and mirror-tile launch order as
+// k_col_wave (eight quarter tiles of a mirror pair, blocks b + 8 s).
+// ----------------------------------------------------------------------------
+template <int R0, int R1, int R2, bool CONJ>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_col_wave4(
+    ColIO io, const float2 *__restrict__ htab_t, int Hq, int H, int Wp, int Wt, int C,
+    const float2 *__restrict__ twf_y) {
+  constexpr int M = R0 * R1 * R2;
+  constexpr int NB2 = M / R2;
+  static_assert(NB2 <= 64, "the fused stage takes one butterfly per lane");
+  constexpr int T = 512, NI = 2 * M, K = (NI + T - 1) / T, KT = (M + T - 1) / T;
+  __shared__ float2 buf[8 * M];
+  __shared__ float2 tw[M];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar addressing
+  const int b = blockIdx.x;
+  const int slot = (b >> 3) & 7, pi = (b >> 6) * 8 + (b & 7);
+  const int hp = (Wt + 1) >> 1;
+  if (pi >= C * hp) return;
+  const int ch = pi / hp, pp = pi - ch * hp;
+  const int t = slot < 4 ? pp : Wt - 1 - pp;
+  if (slot >= 4 && t == pp) return;  // the middle tile of an odd count has no mirror
+  const int part = slot & 3;
+  const size_t off = ((size_t)ch * Wt + t) * H * 8 + part * 2;
+  const float2 *src = io.src + off;
+  float2 *dst = io.dst + off;
+  {
+    // item i: row n = i / 2 of column c = i % 2; every global load of this
+    // phase is issued before the first LDS store
+    float2 av[K], bv[K], w1[K], tv[KT];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T, n = min(i >> 1, M - 1), c = i & 1;
+      av[k] = at32(src, min(n, H - 1) * 8 + c);
+      bv[k] = at32(src, min(n + M, H - 1) * 8 + c);
+      w1[k] = at32(twf_y, n);
+    }
+#pragma unroll
+    for (int k = 0; k < KT; ++k) tv[k] = at32(twf_y, 4 * min(tid + k * T, M - 1));  // w_M^k
+#pragma unroll
+    for (int k = 0; k < KT; ++k)
+      if (tid + k * T < M) tw[tid + k * T] = tv[k];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T, n = i >> 1, c = i & 1;
+      if (K * T == NI || i < NI) {
+        const float2 a = n < H ? av[k] : make_float2(0.f, 0.f);
+        const float2 bb = n + M < H ? bv[k] : make_float2(0.f, 0.f);
+        const float2 s0 = cadd(a, bb), s2 = csub(a, bb);
+        const float2 s1 = make_float2(a.x + bb.y, a.y - bb.x);  // a - i b
+        const float2 s3 = make_float2(a.x - bb.y, a.y + bb.x);  // a + i b
+        const float2 w2 = cmul(w1[k], w1[k]), w3 = cmul(w2, w1[k]);  // w^{2n}, w^{3n}
+        buf[(4 * c) * M + n] = s0;
+        buf[(4 * c + 1) * M + n] = cmul(s1, w1[k]);
+        buf[(4 * c + 2) * M + n] = cmul(s2, w2);
+        buf[(4 * c + 3) * M + n] = cmul(s3, w3);
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int c = wave >> 2, p = wave & 3;
+    float2 *wb = buf + wave * M;
+    const int kx = t * 8 + part * 2 + c;
+    const int qx = min(kx, Wp - kx);
+    const float2 *hcol = htab_t + (size_t)ch * io.hstride + (size_t)qx * Hq;
+    // transfer values for ky = 4 (j + NB2 q) + p, issued before the forward stages
+    float2 hv[R2];
+    {
+      const int j = min(lane, NB2 - 1);
+      static_for<0, R2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const int ky = 4 * (j + NB2 * q) + p;
+        hv[q] = at32(hcol, min(ky, 4 * M - ky));
+      });
+    }
+    wstage<R0, -1, M, 1>(wb, tw, lane);
+    wstage<R1, -1, M, R0>(wb, tw, lane);
+    float2 v[R2];
+    if (lane < NB2) {
+      static_for<0, R2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        v[q] = wb[lane + q * NB2];
+      });
+      static_for<1, R2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        v[q] = cmul(v[q], tw[q * lane]);  // last forward stage: Ns = NB2, unit twiddle step
+      });
+      RFft<R2, -1>::run(v);
+      static_for<0, R2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        v[q] = cmul(v[q], CONJ ? cconj(hv[q]) : hv[q]);  // the table carries 1 / (Hp Wp)
+      });
+      RFft<R2, +1>::run(v);  // first inverse stage: Ns = 1, no twiddles
+    }
+    wave_lds_order();
+    if (lane < NB2) {
+      static_for<0, R2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        wb[lane * R2 + q] = v[q];
+      });
+    }
+    wave_lds_order();
+    wstage<R1, +1, M, R2>(wb, tw, lane);
+    wstage<R0, +1, M, R2 * R1>(wb, tw, lane);
+  }
+  {
+    float2 w1[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) w1[k] = at32(twf_y, min((tid + k * T) >> 1, M - 1));
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T, n = i >> 1, c = i & 1;
+      if ((K * T == NI || i < NI) && n < H) {
+        const float2 w2 = cmul(w1[k], w1[k]), w3 = cmul(w2, w1[k]);
+        const float2 z0 = buf[(4 * c) * M + n];
+        const float2 z1 = cmul(cconj(w1[k]), buf[(4 * c + 1) * M + n]);
+        const float2 z2 = cmul(cconj(w2), buf[(4 * c + 2) * M + n]);
+        const float2 z3 = cmul(cconj(w3), buf[(4 * c + 3) * M + n]);
+        const float2 y0 = cadd(cadd(z0, z1), cadd(z2, z3));
+        float2 &d0 = at32(dst, n * 8 + c);
+        d0 = io.acc ? cadd(d0, y0) : y0;
+        if (n + M < H) {
+          // z0 + i z1 - z2 - i z3
+          const float2 e = csub(z0, z2), o = csub(z1, z3);
+          const float2 y1 = make_float2(e.x - o.y, e.y + o.x);
+          float2 &d1 = at32(dst, (n + M) * 8 + c);
+          d1 = io.acc ? cadd(d1, y1) : y1;
+        }
+      }
+    }
+  }
+}
+
 hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *src, float2 *dst,
                            int acc, hipStream_t s) {
   const float scale = (float)(1.0 / ((double)c.Hp * (double)c.Wp));
@@ -1405,6 +1547,15 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
     else
       hipLaunchKernelGGL((k_col_wave<9, 6, 20, false>), dim3((pairs + 7) / 8 * 32), dim3(512), 0,
                          s, io, ht, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_m, c.twf_y);
+  } else if (col_wave4(c)) {
+    const int pairs = c.C * ((c.Wt + 1) / 2);
+    const float2 *ht = c.htab_t + (size_t)plane * tab;
+    if (conj_h)
+      hipLaunchKernelGGL((k_col_wave4<9, 6, 20, true>), dim3((pairs + 7) / 8 * 64), dim3(512),
+                         0, s, io, ht, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_y);
+    else
+      hipLaunchKernelGGL((k_col_wave4<9, 6, 20, false>), dim3((pairs + 7) / 8 * 64), dim3(512),
+                         0, s, io, ht, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_y);
   } else if (c.Hp == 4320 && c.H <= 2160 && c.Wp % 8 == 0) {
     hipLaunchKernelGGL((k_col_both<2160, 512>), dim3(2 * c.Wt, c.C), dim3(512), 0, s, io, c.H,
                        c.Wp, c.Wt, c.twf_m, c.tw_y, c.Wq, conj_h, scale);

@@ -196,6 +196,9 @@ def test_backward_parity(O, case):
          Wp=120),
     # the 2160-row column pass (one wave per column chain), on a narrow canvas
     dict(H=1080, W=48, C=1, n=2000, lambdas=[515e-9], zs=[3e-3, 6e-3], Hp=2160, Wp=96),
+    # the 4320-row column pass (four chains per column), adjoint summed over planes
+    dict(H=2160, W=24, C=2, n=1500, lambdas=[639e-9, 473e-9], zs=[3e-3, 7e-3], Hp=4320,
+         Wp=48),
 ])
 def test_multiplane_parity(O, case):
     """Several propagation distances sharing one row spectrum: u and |u|^2 of
@@ -556,10 +559,13 @@ def test_rows_3840_narrow(O):
 
 
 @pytest.mark.parametrize("case", [
-    # 4K column length: 2160 rows padded to 4320 (runtime-plan column pass, M = 2160)
+    # 4K column length: 2160 rows padded to 4320 (four 1080-point chains per column)
     dict(H=2160, W=40, Hp=4320, Wp=80),
     # 4K row length: 3840 columns padded to 7680 (runtime-plan row passes)
     dict(H=5, W=3840, Hp=10, Wp=7680),
+    # 4320 rows with H < 2160 (the second output half is cut short) and an odd
+    # number of column tiles (the middle tile has no mirror)
+    dict(H=1500, W=20, Hp=4320, Wp=40),
 ])
 def test_4k_pads_narrow(O, case):
     """The padded lengths of the 4K workload, each on a narrow canvas:
