@@ -842,11 +842,240 @@ __global__ __launch_bounds__(256 * RW) __attribute__((amdgpu_waves_per_eu(4))) v
   }
 }
 
+// ----------------------------------------------------------------------------
+// Quarter-length row passes, for Wp = 4M with W <= 2M (7680: M = 1920).  With
+// the samples at n < 2M, bin 4m + p of the forward is FFT_M of
+// w^{pn}(x[n] + (-i)^p x[n + M]) (n < M), and the inverse cropped to n < 2M is
+// u[n + M j] = sum_p w^{-pn} i^{pj} z_p[n] for j = 0, 1, with z_p the M-point
+// inverse of bins p mod 4 (w = exp(-2 pi i / Wp)).  A 512-thread workgroup
+// takes one row: four interleaved M-point chains, chain p at buf[4 m + p],
+// which is the row in natural bin order.  Blocks b and b + 8, which run on one
+// XCD, take rows 2k and 2k + 1, so the two halves of each 128-byte line of the
+// column-tiled spectrum meet in one L2.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int quarter_row(int b, int rows) {
+  if (b >= (rows & ~15)) return b;
+  return (b & ~15) + 2 * (b & 7) + ((b >> 3) & 1);
+}
+
+// M-entry table exp(-2 pi i e / M) = every fourth entry of the Wp table
+template <int M, int T>
+__device__ __forceinline__ void load_quarter_table(float2 *tw, const float2 *__restrict__ twf_x,
+                                                   int tid) {
+  constexpr int KT = (M + T - 1) / T;
+  float2 tv[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) tv[k] = at32(twf_x, 4 * min(tid + k * T, M - 1));
+#pragma unroll
+  for (int k = 0; k < KT; ++k)
+    if (KT * T == M || tid + k * T < M) tw[tid + k * T] = tv[k];
+}
+
+// one row y of channel base Sc (column-tiled [Wp / 8][H][8]) <-> buf in natural order
+template <int M, int T>
+__device__ __forceinline__ void load_quarter_row(float2 *buf, const float2 *Sc, int H, int y,
+                                                 int tid) {
+  constexpr int n = 4 * M, K = (n + T - 1) / T;
+  float2 v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int x = min(tid + k * T, n - 1);
+    v[k] = at32(Sc, ((x >> 3) * H + y) * 8 + (x & 7));
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (K * T == n || tid + k * T < n) buf[tid + k * T] = v[k];
+}
+
+template <int M, int T>
+__device__ __forceinline__ void store_quarter_row(const float2 *buf, float2 *Sc, int H, int y,
+                                                  int tid) {
+  constexpr int n = 4 * M, K = (n + T - 1) / T;
+  float2 v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = buf[min(tid + k * T, n - 1)];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int x = tid + k * T;
+    if (K * T == n || x < n) at32(Sc, ((x >> 3) * H + y) * 8 + (x & 7)) = v[k];
+  }
+}
+
+// the four chain inputs at m = n from the samples a = x[n], b = x[n + M]
+__device__ __forceinline__ void quarter_inputs(float2 *buf, int n, float2 a, float2 b,
+                                               float2 w1) {
+  const float2 w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+  buf[4 * n] = cadd(a, b);
+  buf[4 * n + 1] = cmul(make_float2(a.x + b.y, a.y - b.x), w1);  // (a - i b) w^n
+  buf[4 * n + 2] = cmul(csub(a, b), w2);                         // (a - b) w^{2n}
+  buf[4 * n + 3] = cmul(make_float2(a.x - b.y, a.y + b.x), w3);  // (a + i b) w^{3n}
+}
+
+// u[n] and u[n + M] from the four chain outputs at m = n
+__device__ __forceinline__ void quarter_outputs(const float2 *buf, int n, float2 w1, float2 &u0,
+                                                float2 &u1) {
+  const float2 w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+  const float2 z0 = buf[4 * n];
+  const float2 z1 = cmul(cconj(w1), buf[4 * n + 1]);
+  const float2 z2 = cmul(cconj(w2), buf[4 * n + 2]);
+  const float2 z3 = cmul(cconj(w3), buf[4 * n + 3]);
+  u0 = cadd(cadd(z0, z1), cadd(z2, z3));
+  const float2 e = csub(z0, z2), o = csub(z1, z3);
+  u1 = make_float2(e.x - o.y, e.y + o.x);  // z0 + i z1 - z2 - i z3
+}
+
+template <int M>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_row_fwd_q(
+    const float2 *__restrict__ field, int H, int W, int rows, const float2 *__restrict__ twf_x,
+    float2 *__restrict__ S) {
+  constexpr int T = 512, K = (M + T - 1) / T, Wt = M / 2;
+  __shared__ float2 buf[4 * M];
+  __shared__ float2 tw[M];
+  const int tid = threadIdx.x;
+  const int R = quarter_row(blockIdx.x, rows), c = R / H, y = R - c * H;
+  load_quarter_table<M, T>(tw, twf_x, tid);
+  {
+    const float2 *f = field + ((size_t)c * H + y) * W;
+    float2 av[K], bv[K], wv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int n = min(tid + k * T, M - 1);
+      av[k] = at32(f, min(n, W - 1));
+      bv[k] = at32(f, min(n + M, W - 1));
+      wv[k] = at32(twf_x, n);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int n = tid + k * T;
+      if (K * T == M || n < M) {
+        const float2 a = n < W ? av[k] : make_float2(0.f, 0.f);
+        const float2 b = n + M < W ? bv[k] : make_float2(0.f, 0.f);
+        quarter_inputs(buf, n, a, b, wv[k]);
+      }
+    }
+  }
+  __syncthreads();
+  cfft<-1, 4, T, M>(buf, tw, tid);
+  store_quarter_row<M, T>(buf, S + (size_t)c * Wt * H * 8, H, y, tid);
+}
+
+template <int M>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_row_inv_q(
+    const float2 *__restrict__ S, int H, int W, int rows, const float2 *__restrict__ twf_x,
+    float2 *__restrict__ out) {
+  constexpr int T = 512, K = (M + T - 1) / T, Wt = M / 2;
+  __shared__ float2 buf[4 * M];
+  __shared__ float2 tw[M];
+  const int tid = threadIdx.x;
+  const int R = quarter_row(blockIdx.x, rows), c = R / H, y = R - c * H;
+  load_quarter_table<M, T>(tw, twf_x, tid);
+  load_quarter_row<M, T>(buf, S + (size_t)c * Wt * H * 8, H, y, tid);
+  float2 wv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) wv[k] = at32(twf_x, min(tid + k * T, M - 1));
+  lds_sync();
+  cfft<+1, 4, T, M>(buf, tw, tid);
+  float2 *o = out + ((size_t)c * H + y) * W;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int n = tid + k * T;
+    if ((K * T == M || n < M) && n < W) {
+      float2 u0, u1;
+      quarter_outputs(buf, n, wv[k], u0, u1);
+      o[n] = u0;
+      if (n + M < W) o[n + M] = u1;
+    }
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_row_loss_q(
+    float2 *__restrict__ S, int H, int W, int rows, const float2 *__restrict__ twf_x,
+    const float *__restrict__ target, const float *__restrict__ grad_I,
+    const float *__restrict__ mask, float *__restrict__ intensity, float2 *__restrict__ u_out,
+    double *__restrict__ loss_part, float gscale, int make_grad) {
+  constexpr int T = 512, K = (M + T - 1) / T, Wt = M / 2;
+  __shared__ float2 buf[4 * M];
+  __shared__ float2 tw[M];
+  __shared__ double red[T / 64];
+  const int tid = threadIdx.x;
+  const int R = quarter_row(blockIdx.x, rows), c = R / H, y = R - c * H;
+  float2 *Sc = S + (size_t)c * Wt * H * 8;
+  load_quarter_table<M, T>(tw, twf_x, tid);
+  load_quarter_row<M, T>(buf, Sc, H, y, tid);
+  // per-element inputs at n and n + M, fetched before the transform so that
+  // their latency overlaps it
+  const float *tsrc = target ? target : grad_I;
+  const size_t row = ((size_t)c * H + y) * W;
+  float tv0[K], tv1[K], mv0[K], mv1[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int n = min(tid + k * T, M - 1);
+    const int n0 = min(n, W - 1), n1 = min(n + M, W - 1);
+    tv0[k] = tsrc ? tsrc[row + n0] : 0.f;
+    tv1[k] = tsrc ? tsrc[row + n1] : 0.f;
+    mv0[k] = mask ? mask[(size_t)y * W + n0] : 0.f;
+    mv1[k] = mask ? mask[(size_t)y * W + n1] : 0.f;
+  }
+  lds_sync();
+  cfft<+1, 4, T, M>(buf, tw, tid);
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int n = tid + k * T;
+    if (K * T == M || n < M) {
+      const float2 w1 = at32(twf_x, n);
+      float2 u[2];
+      quarter_outputs(buf, n, w1, u[0], u[1]);
+      float f[2] = {0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int x = n + j * M;
+        if (x >= W) continue;
+        const float t = j ? tv1[k] : tv0[k], m = j ? mv1[k] : mv0[k];
+        const float I = u[j].x * u[j].x + u[j].y * u[j].y;
+        if (intensity) intensity[row + x] = I;
+        if (u_out) u_out[row + x] = u[j];
+        if (target) {
+          // L_recon weight 1 + m^2 + t^2 (plain MSE without a mask)
+          const float d = I - t, w = mask ? 1.f + m * m + t * t : 1.f;
+          acc += (double)d * (double)d * (double)w;
+          f[j] = gscale * d * w;  // 4 w (I - T) / M
+        } else if (grad_I) {
+          f[j] = 2.0f * t;
+        }
+      }
+      if (make_grad)
+        quarter_inputs(buf, n, make_float2(f[0] * u[0].x, f[0] * u[0].y),
+                       make_float2(f[1] * u[1].x, f[1] * u[1].y), w1);
+    }
+  }
+  if (target) {
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < T / 64; ++w) sum += red[w];
+      loss_part[R] = sum;
+    }
+  }
+  if (make_grad) {
+    __syncthreads();
+    cfft<-1, 4, T, M>(buf, tw, tid);
+    store_quarter_row<M, T>(buf, Sc, H, y, tid);
+  }
+}
+
 // rows per row-pass workgroup (specialised lengths use 4, the runtime path 2)
 static bool row_specialised(int Wp) { return Wp == 3840 || Wp == 512; }
 // the half-length row passes take Wp = 3840 (1080p) and 7680 (4K) with W <= Wp / 2
+// the quarter-length row passes take Wp = 7680 (4K) with W <= Wp / 2, one row per workgroup
+static bool row_quarter(const Ctx &c) { return c.Wp == 7680 && 2 * c.W <= c.Wp; }
 static bool row_half(const Ctx &c) { return (c.Wp == 3840 || c.Wp == 7680) && 2 * c.W <= c.Wp; }
-int row_group_rows(const Ctx &c) { return c.Wp == 512 ? 4 : (row_half(c) ? kRowHalfRows : 2); }
+int row_group_rows(const Ctx &c) {
+  return c.Wp == 512 ? 4 : (row_quarter(c) ? 1 : (row_half(c) ? kRowHalfRows : 2));
+}
 static int row_blocks(const Ctx &c) {
   const int r = row_group_rows(c);
   return c.C * ((c.H + r - 1) / r);
@@ -854,7 +1083,10 @@ static int row_blocks(const Ctx &c) {
 static size_t row_lds(const Ctx &c) { return (size_t)2 * c.Wp * sizeof(float2); }
 
 hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStream_t s) {
-  if (row_half(c) && c.Wp == 7680)
+  if (row_quarter(c))
+    hipLaunchKernelGGL(k_row_fwd_q<1920>, dim3(row_blocks(c)), dim3(512), 0, s, field, c.H, c.W,
+                       row_blocks(c), c.twf_x, dst);
+  else if (row_half(c) && c.Wp == 7680)
     hipLaunchKernelGGL((k_row_fwd_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
                        dim3(256 * kRowHalfRows), 0, s, field, c.H, c.W, c.twf_x, dst);
   else if (row_half(c))
@@ -877,7 +1109,10 @@ hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStr
 }
 
 hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStream_t s) {
-  if (row_half(c) && c.Wp == 7680)
+  if (row_quarter(c))
+    hipLaunchKernelGGL(k_row_inv_q<1920>, dim3(row_blocks(c)), dim3(512), 0, s, src, c.H, c.W,
+                       row_blocks(c), c.twf_x, out);
+  else if (row_half(c) && c.Wp == 7680)
     hipLaunchKernelGGL((k_row_inv_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
                        dim3(256 * kRowHalfRows), 0, s, src, c.H, c.W, c.twf_x, out);
   else if (row_half(c))
@@ -912,7 +1147,11 @@ hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *ta
   if (u_out) u_out += po;
   if (mask) mask += (size_t)plane * c.H * c.W;  // [L][H][W]
   double *lp = c.loss_part + (size_t)plane * row_blocks(c);
-  if (row_half(c) && c.Wp == 7680)
+  if (row_quarter(c))
+    hipLaunchKernelGGL(k_row_loss_q<1920>, dim3(row_blocks(c)), dim3(512), 0, s, buf, c.H, c.W,
+                       row_blocks(c), c.twf_x, target, grad_intensity, mask, intensity, u_out, lp,
+                       gscale, make_grad);
+  else if (row_half(c) && c.Wp == 7680)
     hipLaunchKernelGGL((k_row_loss_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
                        dim3(256 * kRowHalfRows), 0, s, buf, c.H, c.W, c.twf_x, target,
                        grad_intensity, mask, intensity, u_out, lp, gscale, make_grad);

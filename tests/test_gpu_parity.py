@@ -520,19 +520,28 @@ def test_full_loss_rejections(O):
     torch.cuda.synchronize()
 
 
-def test_rows_3840_narrow(O):
-    """The 3840-wide row passes (one wave per half-length chain) with fewer
-    columns than Wp / 2 and an odd number of rows (the last workgroup has a
-    padding row), two planes: propagation, its adjoint, the MSE backward and
-    the L_recon backward against the oracle."""
-    H, W, C, n = 9, 1800, 2, 400
-    lambdas, zs, Hp, Wp = [639e-9, 473e-9], [3e-3, 5e-3], 18, 3840
-    say("rows 3840", H, W, C, n, zs)
+@pytest.mark.parametrize("case", [
+    # 3840-wide rows (two half-length chains), an odd row count: the last
+    # workgroup has a padding row
+    dict(H=15, W=1800, Hp=30, Wp=3840),
+    # 7680-wide rows (four quarter-length chains) with W < Wp / 2, so the
+    # second output half of each chain is cut short; 17 rows x 2 channels is
+    # not a multiple of the 16-block row pairing
+    dict(H=17, W=2500, Hp=36, Wp=7680),
+])
+def test_rows_narrow(O, case):
+    """The specialised row passes with fewer columns than Wp / 2, two planes:
+    propagation, its adjoint, the MSE backward, the L_recon backward and the
+    final loss with the SSIM term against the oracle."""
+    H, W, Hp, Wp, C, n = case["H"], case["W"], case["Hp"], case["Wp"], 2, 400
+    lambdas, zs = [639e-9, 473e-9], [3e-3, 5e-3]
+    say("rows narrow", H, W, Hp, Wp, C, n, zs)
     p = synth.params(71, n, H, W, C)
     T = synth.target(72, C, H, W, L=2) * np.float32(0.5)
     Mk = (np.random.default_rng(73).uniform(0, 1, (2, H, W)) > 0.5).astype(np.float32)
     opt = O.Optics(H, W, C, Hp, Wp, 8e-6, lambdas, zs)
-    ctx = binding.Context(H, W, C, 8e-6, lambdas, zs, pad=(Hp, Wp), max_gaussians=n)
+    ctx = binding.Context(H, W, C, 8e-6, lambdas, zs, pad=(Hp, Wp), max_gaussians=n,
+                          full_loss=True)
     P = gpu_params(p)
     field = ctx.rasterize(P, n)
     I, u = ctx.propagate(field, intensity=True, field_out=True)
@@ -556,12 +565,24 @@ def test_rows_3840_narrow(O):
         assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
         for k, e in group_errors(grads.cpu().numpy(), ref["grads"], n, C).items():
             assert e <= GRAD_TOL, (k, e)
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss, grad_field=gfield,
+                         mask=torch.from_numpy(Mk).cuda(), ssim_weight=0.005)
+    ref = O.forward_backward(p, T, opt, mask=Mk, ssim_weight=0.005)
+    lg = loss.cpu().numpy()
+    say("full loss", lg, ref["loss"], ref["psnr"])
+    assert abs(lg[0] - ref["loss"]) <= 1e-4 * ref["loss"]
+    assert abs(lg[1] - ref["psnr"]) < 1e-3
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
+    for k, e in group_errors(grads.cpu().numpy(), ref["grads"], n, C).items():
+        assert e <= GRAD_TOL, (k, e)
 
 
 @pytest.mark.parametrize("case", [
     # 4K column length: 2160 rows padded to 4320 (four 1080-point chains per column)
     dict(H=2160, W=40, Hp=4320, Wp=80),
-    # 4K row length: 3840 columns padded to 7680 (runtime-plan row passes)
+    # 4K row length: 3840 columns padded to 7680 (four 1920-point chains per row)
     dict(H=5, W=3840, Hp=10, Wp=7680),
     # 4320 rows with H < 2160 (the second output half is cut short) and an odd
     # number of column tiles (the middle tile has no mirror)
