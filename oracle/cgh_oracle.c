@@ -230,11 +230,15 @@ void orc_raster(int n, int C, int W, int H, double k, int flags, const double *m
 
 /* Pairs whose Mahalanobis distance lies within a relative band of the
  * support boundary k^2: their in/out decision depends on rounding, so the
- * parity tests exclude the pixels they touch.  Writes 1 into mask[j*W+i]
- * for every such pixel and returns the number of such pairs. */
-long orc_ambiguous_pixels(int n, int W, int H, double k, double rel_band, const double *mean_pre,
-                          const double *log_scale, const double *rotation,
-                          const double *opacity_pre, unsigned char *mask) {
+ * parity tests exclude the pixels they touch.  With FLAG_PAPER_ALPHA the
+ * Alg. 2 skip (alpha G < 1/255, i.e. q > 2 ln(255 alpha)) is a second such
+ * boundary, with a jump of c/255 in the contribution, and pairs within the
+ * same band of it count too.  Writes 1 into mask[j*W+i] for every such pixel
+ * and returns the number of such pairs. */
+long orc_ambiguous_pixels(int n, int W, int H, double k, double rel_band, int flags,
+                          const double *mean_pre, const double *log_scale,
+                          const double *rotation, const double *opacity_pre,
+                          unsigned char *mask) {
   if (k <= 0.0) return 0;
   geom_t *g = (geom_t *)malloc(sizeof(geom_t) * (size_t)(n > 0 ? n : 1));
   geometry(n, W, H, mean_pre, log_scale, rotation, opacity_pre, g);
@@ -247,7 +251,10 @@ long orc_ambiguous_pixels(int n, int W, int H, double k, double rel_band, const 
     for (int j = j0; j <= j1; ++j)
       for (int i = i0; i <= i1; ++i) {
         double q = mahal(&g[m], (double)i - g[m].mx, (double)j - g[m].my);
-        if (fabs(q - k2) <= rel_band * k2) {
+        int near = fabs(q - k2) <= rel_band * k2;
+        if ((flags & FLAG_PAPER_ALPHA) && q <= k2)
+          near |= fabs(q - 2.0 * log(255.0 * g[m].alpha)) <= rel_band * k2;
+        if (near) {
           mask[(size_t)j * W + i] = 1;
           ++count;
         }

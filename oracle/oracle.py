@@ -37,7 +37,7 @@ def lib():
         L.orc_geometry.argtypes = [i, i, i, d, d, d, d, d]
         L.orc_raster_brute.argtypes = [i, i, i, i, f, i, d, d, d, d, d, d, d, d]
         L.orc_raster.argtypes = [i, i, i, i, f, i, d, d, d, d, d, d, d, d, d, d, d]
-        L.orc_ambiguous_pixels.argtypes = [i, i, i, f, f, d, d, d, d, u8]
+        L.orc_ambiguous_pixels.argtypes = [i, i, i, f, f, i, d, d, d, d, u8]
         L.orc_ambiguous_pixels.restype = ctypes.c_long
         L.orc_fft1.argtypes = [i, d, i]
         L.orc_fft2.argtypes = [i, i, d, i]
@@ -119,12 +119,14 @@ def raster(params, opt, brute=False, support=None):
 
 def ambiguous_mask(params, opt, rel_band=1e-4):
     """Pixels touched by a (Gaussian, pixel) pair whose Mahalanobis distance lies
-    within ``rel_band * k^2`` of the support boundary.  Returns (mask [H, W] bool,
-    number of such pairs)."""
+    within ``rel_band * k^2`` of the support boundary (or, with the Alg. 2
+    weight, of its 1/255 skip boundary).  Returns (mask [H, W] bool, number of
+    such pairs)."""
     p = widen(params)
     n = p["rotation"].shape[0]
     mask = np.zeros((opt.H, opt.W), dtype=np.uint8)
-    cnt = lib().orc_ambiguous_pixels(n, opt.W, opt.H, opt.k, rel_band, _p(p["mean_pre"]),
+    cnt = lib().orc_ambiguous_pixels(n, opt.W, opt.H, opt.k, rel_band, opt.flags,
+                                     _p(p["mean_pre"]),
                                      _p(p["log_scale"]), _p(p["rotation"]),
                                      _p(p["opacity_pre"]),
                                      mask.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))

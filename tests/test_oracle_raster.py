@@ -189,3 +189,23 @@ def test_paper_alpha_flag(O):
     assert np.all(f[~kept] == 0.0)
     assert np.allclose(f[kept].real, 0.5 * np.minimum(0.99, w[kept]), rtol=0, atol=1e-15)
     assert alpha > 0.99
+
+
+def test_ambiguous_pixels_of_the_paper_alpha_skip(O):
+    """With the Alg. 2 weight the 1/255 skip is a second decision boundary: an
+    isotropic Gaussian (s = exp(ln 0.9) + 0.1 = 1, so Sigma = 1.1 I) at the canvas centre whose
+    alpha puts alpha G = 1/255 exactly at distance 2 (q = 4 / 1.1) has the four
+    pixels at that distance marked, and no pixel without the flag."""
+    q = 4.0 / 1.1
+    alpha = math.exp(q / 2.0) / 255.0
+    p = one((0.0, 0.0), (math.log(0.9),) * 2, 0.0, (1.0,), (0.0,),
+            math.log(alpha / (1.0 - alpha)))
+    geo = O.geometry(p, 16, 16)[0]
+    assert geo[0] == 8.0 and geo[1] == 8.0 and abs(geo[11] - alpha) < 1e-7
+    m_pa, n_pa = O.ambiguous_mask(p, opt(O, 16, 16, flags=O.FLAG_PAPER_ALPHA), 1e-5)
+    m_plain, n_plain = O.ambiguous_mask(p, opt(O, 16, 16), 1e-5)
+    # alpha and s pass through FP32 pre-activations: the boundary moves by
+    # ~1e-6 in q, well inside the band of 9e-5
+    assert n_plain == 0 and not m_plain.any()
+    assert n_pa == 4
+    assert sorted(zip(*np.nonzero(m_pa))) == [(6, 8), (8, 6), (8, 10), (10, 8)]
