@@ -85,13 +85,20 @@ typedef struct {
   int32_t max_gaussians;         /* capacity for n                                        */
   int64_t max_pairs;             /* capacity of the (tile, Gaussian) list (0: default     */
                                  /* 8 * max_gaussians + 65536)                            */
-  int32_t flags;                 /* 0 or CGH_FULL_LOSS                                    */
+  int32_t flags;                 /* 0, or CGH_FULL_LOSS and/or CGH_PAPER_ALPHA            */
 } cgh_config;
 
 /* cgh_config.flags: reserve the workspace of cgh_backward_full (the SSIM term:
  * intensity, propagated field and three coefficient maps per plane and
  * channel, about 24 bytes per element of [L][C][H][W]); needs H, W >= 11. */
 #define CGH_FULL_LOSS 1
+/* cgh_config.flags: the weight of Alg. 2 instead of the coherent-sum equations
+ * of Sec. 3.1 and the supplementary rendering: a Gaussian contributes
+ * c_{n,c} w exp(j phi_{n,c}) with w = min(0.99, alpha_n G_n), and nothing where
+ * alpha_n G_n < 1/255 (on top of the k-sigma support).  Forward and every
+ * adjoint follow it (w does not depend on alpha or the geometry where the
+ * 0.99 clamp is active).  Costs 8 bytes per Gaussian of workspace. */
+#define CGH_PAPER_ALPHA 2
 
 typedef struct cgh_ctx cgh_ctx;
 
@@ -114,7 +121,8 @@ cgh_status cgh_destroy(cgh_ctx *ctx);
 /* ComplexRasterize2D (Alg. 2; Sec. 3.1 coherent sum; supplementary Forward
  * Pass): field[c][j][i] = sum_n alpha_n c_{n,c} G_n(i, j) exp(j phi_{n,c}) over
  * the Gaussians whose k-sigma ellipse contains (i, j), with
- * G = exp(max(-q/2, -50)).  params: n * (6 + 2C) floats (layout above),
+ * G = exp(max(-q/2, -50)) (alpha_n G_n replaced as documented at
+ * CGH_PAPER_ALPHA when that flag is set).  params: n * (6 + 2C) floats (layout above),
  * 0 <= n <= max_gaussians.  field: [C][H][W] complex, overwritten.
  * Keeps the per-tile Gaussian lists in the workspace for the adjoint. */
 cgh_status cgh_rasterize(cgh_ctx *ctx, const float *params, int32_t n, cgh_c64 *field,

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libcgh.so")
 MAX_CHANNELS = 4
 MAX_PLANES = 8
 CGH_FULL_LOSS = 1  # cgh_config.flags bit: workspace for cgh_backward_full
+CGH_PAPER_ALPHA = 2  # cgh_config.flags bit: the Alg. 2 weight min(0.99, alpha G), skip < 1/255
 PARAM_KEYS = ("mean_pre", "log_scale", "rotation", "amplitude", "phase", "opacity_pre")
 
 KERNEL_CLASSES = {"preprocess": 1, "binning": 2, "raster": 3, "row_fft": 4, "col_pass": 5,
@@ -143,7 +144,7 @@ class Context:
 
     def __init__(self, height, width, channels, pitch, wavelengths, zs, pad=None,
                  support_sigma=3.0, max_gaussians=0, max_pairs=0, full_loss=False,
-                 device="cuda"):
+                 paper_alpha=False, device="cuda"):
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -165,7 +166,7 @@ class Context:
         cfg.support_sigma = float(support_sigma)
         cfg.max_gaussians = int(max_gaussians)
         cfg.max_pairs = int(max_pairs)
-        cfg.flags = CGH_FULL_LOSS if full_loss else 0
+        cfg.flags = (CGH_FULL_LOSS if full_loss else 0) | (CGH_PAPER_ALPHA if paper_alpha else 0)
         self.cfg = cfg
         self.L = len(zs)
         self.Hp = cfg.pad_height or 2 * self.H

@@ -73,8 +73,9 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
     return fail(CGH_ERR_INVALID_ARG, "max_gaussians must be in [0, 2^28]");
   if (f.max_pairs < 0 || f.max_pairs > 0x7fffffffLL)
     return fail(CGH_ERR_INVALID_ARG, "max_pairs must be in [0, 2^31)");
-  if (f.flags & ~CGH_FULL_LOSS)
-    return fail(CGH_ERR_INVALID_ARG, "flags: unknown bits 0x%x", f.flags & ~CGH_FULL_LOSS);
+  const int32_t known = CGH_FULL_LOSS | CGH_PAPER_ALPHA;
+  if (f.flags & ~known)
+    return fail(CGH_ERR_INVALID_ARG, "flags: unknown bits 0x%x", f.flags & ~known);
   if ((f.flags & CGH_FULL_LOSS) && (f.height < 11 || f.width < 11))
     return fail(CGH_ERR_INVALID_ARG, "CGH_FULL_LOSS needs height, width >= 11 (the SSIM window)");
 
@@ -164,6 +165,7 @@ size_t carve(Ctx *c, char *base) {
   c->field_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
   c->gfield_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
   c->rec = (float *)take(sizeof(float) * c->rec_stride * (N + 1));
+  c->alim = (c->cfg.flags & CGH_PAPER_ALPHA) ? (float2 *)take(sizeof(float2) * (N + 1)) : nullptr;
   c->rect = (uint2 *)take(sizeof(uint2) * (N ? N : 1));
   c->counts = (uint32_t *)take(sizeof(uint32_t) * (N ? N : 1));
   c->offsets = (uint32_t *)take(sizeof(uint32_t) * (N + 1));

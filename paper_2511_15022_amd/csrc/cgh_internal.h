@@ -82,6 +82,9 @@ struct Ctx {
   float2 *field_tmp;                // [C][H][W]
   float2 *gfield_tmp;               // [C][H][W]
   float *rec;                       // [max_gaussians + 1][rec_stride]; the last is all zeros
+  float2 *alim;                     // CGH_PAPER_ALPHA only, else null: [max_gaussians + 1]
+                                    // (lo, hi) exponent limits, log2 G in [lo, .) kept,
+                                    // clamped at hi (the last entry (0, 0))
   uint2 *rect;                      // [max_gaussians] tile rectangles (x0|x1<<16, y0|y1<<16)
   uint32_t *counts;                 // [max_gaussians]
   uint32_t *offsets;                // [max_gaussians + 1]

@@ -65,7 +65,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ pa
                                                     int W, int H, float k, int tiles_x,
                                                     float *__restrict__ rec,
                                                     uint2 *__restrict__ rect,
-                                                    uint32_t *__restrict__ counts) {
+                                                    uint32_t *__restrict__ counts, float thr,
+                                                    float2 *__restrict__ alim) {
   constexpr int RS = rec_stride_c(C);
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
@@ -120,18 +121,31 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ pa
   for (int i = 0; i < RS / 4; ++i) dst[i] = make_float4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
   counts[g] = cnt;
   rect[g] = rc;
+  if (alim) {
+    // Alg. 2 weight w = min(0.99, alpha G), kept where alpha G >= 1/255: in the
+    // exponent p = log2 G, kept for p >= max(support threshold, log2(1/(255 alpha)))
+    // and clamped at log2(0.99 / alpha)
+    const double lo = log2(1.0 / (255.0 * q.alpha)), hi = log2(0.99 / q.alpha);
+    alim[g] = make_float2(fmaxf(thr, (float)lo), (float)hi);
+  }
   (void)tiles_x;
+}
+
+static float support_threshold(float k) {
+  // log2 G >= -k^2/2 log2(e)  <=>  q <= k^2 ; k <= 0: everything
+  if (k <= 0.f) return -INFINITY;
+  return (float)(-0.5 * (double)k * (double)k * kLog2e);
 }
 
 hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   dim3 grid((n + 255) / 256), block(256);
-  const float k = c.cfg.support_sigma;
+  const float k = c.cfg.support_sigma, thr = support_threshold(k);
   switch (c.C) {
-    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts); break;
-    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts); break;
-    case 3: hipLaunchKernelGGL(k_preprocess<3>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts); break;
-    default: hipLaunchKernelGGL(k_preprocess<4>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts, thr, c.alim); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts, thr, c.alim); break;
+    case 3: hipLaunchKernelGGL(k_preprocess<3>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts, thr, c.alim); break;
+    default: hipLaunchKernelGGL(k_preprocess<4>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts, thr, c.alim); break;
   }
   return hipGetLastError();
 }
@@ -415,13 +429,14 @@ __global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__re
 
 // the record after the last Gaussian slot: all zeros (zero amplitude), used to
 // pad per-wave lists in the forward rasterizer
-__global__ void k_zero_record(float *rec, int slot, int rs) {
+__global__ void k_zero_record(float *rec, int slot, int rs, float2 *alim) {
   if ((int)threadIdx.x < rs) rec[(size_t)slot * rs + threadIdx.x] = 0.f;
+  if (alim && threadIdx.x == 0) alim[slot] = make_float2(0.f, 0.f);  // G = 1 times amplitude 0
 }
 
 hipError_t launch_zero_record(const Ctx &c, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_record, dim3(1), dim3(64), 0, s, c.rec, c.cfg.max_gaussians,
-                     c.rec_stride);
+                     c.rec_stride, c.alim);
   return hipGetLastError();
 }
 
@@ -490,13 +505,18 @@ constexpr int kBatch = 256;
 // CLAMP: the support threshold lies at or below the exponent clamp (unbounded
 // support), so the clamp has to be applied; otherwise every exponent that
 // passes the threshold is above the clamp already.
-template <int C, bool CLAMP>
+// PA: the Alg. 2 weight (CGH_PAPER_ALPHA): G = 2^min(p, hi) where p >= lo, else 0
+template <int C, bool CLAMP, bool PA>
 __device__ __forceinline__ void accumulate(const float *r, float offx, float offy, float flx,
-                                           float fly, float thr, float *ar, float *ai) {
+                                           float fly, float thr, float lo, float hi, float *ar,
+                                           float *ai) {
   const float dx = flx + offx, dy = fly + offy;
   const float p2 = fmaf(dx, fmaf(r[R_A], dx, r[R_B] * dy), r[R_C] * dy * dy);
-  const float G =
-      p2 >= thr ? __builtin_amdgcn_exp2f(CLAMP ? fmaxf(p2, kPowerFloor2) : p2) : 0.f;
+  float G;
+  if (PA)
+    G = p2 >= lo ? __builtin_amdgcn_exp2f(fminf(p2, hi)) : 0.f;
+  else
+    G = p2 >= thr ? __builtin_amdgcn_exp2f(CLAMP ? fmaxf(p2, kPowerFloor2) : p2) : 0.f;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     ar[c] = fmaf(G, r[R_AMP + 2 * c], ar[c]);
@@ -505,12 +525,13 @@ __device__ __forceinline__ void accumulate(const float *r, float offx, float off
 }
 
 // zero_id: index of an all-zero record (after the last Gaussian slot)
-template <int C, bool CLAMP>
+template <int C, bool CLAMP, bool PA>
 __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ rec,
                                                     const uint32_t *__restrict__ vals,
                                                     const uint2 *__restrict__ ranges, int W,
                                                     int H, int tiles_x, float thr,
                                                     uint32_t zero_id,
+                                                    const float2 *__restrict__ alim,
                                                     float2 *__restrict__ field) {
   constexpr int RS = rec_stride_c(C);
   // (Gaussian id, origin offset x, origin offset y) of the surviving Gaussians
@@ -610,8 +631,10 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
       float r0[R_AMP + 2 * C], r1[R_AMP + 2 * C];
 #pragma unroll
       for (int i = R_A; i < R_AMP + 2 * C; ++i) { r0[i] = s0[i]; r1[i] = s1[i]; }
-      accumulate<C, CLAMP>(r0, ox0, oy0, flx, fly, thr, ar, ai);
-      accumulate<C, CLAMP>(r1, ox1, oy1, flx, fly, thr, ar, ai);
+      float2 l0 = make_float2(0.f, 0.f), l1 = make_float2(0.f, 0.f);
+      if (PA) { l0 = alim[g0]; l1 = alim[g1]; }
+      accumulate<C, CLAMP, PA>(r0, ox0, oy0, flx, fly, thr, l0.x, l0.y, ar, ai);
+      accumulate<C, CLAMP, PA>(r1, ox1, oy1, flx, fly, thr, l1.x, l1.y, ar, ai);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -622,21 +645,22 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
   }
 }
 
-static float support_threshold(float k) {
-  // log2 G >= -k^2/2 log2(e)  <=>  q <= k^2 ; k <= 0: everything
-  if (k <= 0.f) return -INFINITY;
-  return (float)(-0.5 * (double)k * (double)k * kLog2e);
-}
-
 hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
   const float thr = support_threshold(c.cfg.support_sigma);
   const uint32_t zid = (uint32_t)c.cfg.max_gaussians;  // the zero record
   const uint32_t *vals = c.vals[c.sorted];
   dim3 grid(c.num_tiles), block(256);
   const bool clamp = !(thr > kPowerFloor2);
-#define CGH_FWD(CC, CL)                                                                  \
-  hipLaunchKernelGGL((k_raster_fwd<CC, CL>), grid, block, 0, s, c.rec, vals, c.ranges, c.W, \
-                     c.H, c.tiles_x, thr, zid, field)
+  const bool pa = c.alim != nullptr;  // the clamp of the exponent never binds there
+#define CGH_FWD(CC, CL)                                                                      \
+  do {                                                                                       \
+    if (pa)                                                                                  \
+      hipLaunchKernelGGL((k_raster_fwd<CC, false, true>), grid, block, 0, s, c.rec, vals,    \
+                         c.ranges, c.W, c.H, c.tiles_x, thr, zid, c.alim, field);            \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_raster_fwd<CC, CL, false>), grid, block, 0, s, c.rec, vals,      \
+                         c.ranges, c.W, c.H, c.tiles_x, thr, zid, c.alim, field);            \
+  } while (0)
   switch (c.C) {
     case 1: if (clamp) CGH_FWD(1, true); else CGH_FWD(1, false); break;
     case 2: if (clamp) CGH_FWD(2, true); else CGH_FWD(2, false); break;
@@ -676,23 +700,30 @@ constexpr int kAdjSeg = 8;  // pixels per segment
 //   2-4 a, b, c;  5.. amplitude (2C);  then box, first segment, slot (int bits)
 // The stride N is a multiple of 4 floats (16-byte reads) with N / 4 odd: lanes
 // reading different pairs then spread their 16-byte reads over all LDS banks.
-template <int C> struct AdjQ {
+// PA (CGH_PAPER_ALPHA) adds the exponent limits (lo, hi) of the pair's Gaussian
+template <int C, bool PA> struct AdjQ {
   static constexpr int AMP = 5;
   static constexpr int BOX = 5 + 2 * C, START = BOX + 1, SLOT = BOX + 2;
-  static constexpr int N4 = ((SLOT + 1) + 3) & ~3;
+  static constexpr int LO = SLOT + 1, HI = SLOT + 2;
+  static constexpr int N4 = ((SLOT + 1 + (PA ? 2 : 0)) + 3) & ~3;
   static constexpr int N = (N4 / 4) % 2 ? N4 : N4 + 4;
 };
 
-template <int C, bool CLAMP>
+// Pair partials: dP_c, dQ_c (2C), sum w d (2), sum w d d^T (3); with PA one more,
+// the sum of G gp over the pixels where the 0.99 clamp is active (their
+// weight does not depend on alpha), in the slot that the stride leaves spare.
+template <int C, bool CLAMP, bool PA>
 __global__ __launch_bounds__(64) void k_raster_adj(
     const float *__restrict__ rec, const uint32_t *__restrict__ vals,
     const uint2 *__restrict__ ranges, const uint2 *__restrict__ rect,
     const uint32_t *__restrict__ offsets, int W, int H, int tiles_x, float thr,
-    const float2 *__restrict__ gfield, int64_t cap, float *__restrict__ partials) {
+    const float2 *__restrict__ alim, const float2 *__restrict__ gfield, int64_t cap,
+    float *__restrict__ partials) {
   constexpr int RS = rec_stride_c(C);
   constexpr int PS = part_stride_c(C);
-  constexpr int NS = 2 * C + 5;
-  using Q = AdjQ<C>;
+  constexpr int NS = 2 * C + 5 + (PA ? 1 : 0);
+  static_assert(NS <= PS, "the clamped-pixel sum needs a spare partial slot");
+  using Q = AdjQ<C, PA>;
   // dL/dU0 of the tile, plus one row of zeros (row kTile) that the padding
   // pixels of a pair's last segment read when they run past the tile's last row
   __shared__ float2 sg[(kTile + 1) * kTile][C];
@@ -786,6 +817,11 @@ __global__ __launch_bounds__(64) void k_raster_adj(
       q[Q::BOX] = __int_as_float(xa | (xb << 8) | (ya << 16) | (yb << 24));
       q[Q::START] = __int_as_float(start);
       q[Q::SLOT] = __uint_as_float(slot);
+      if (PA) {
+        const float2 l = alim[vals[base + lane]];
+        q[Q::LO] = l.x;
+        q[Q::HI] = l.y;
+      }
     }
     __syncthreads();
     if (total > 0) {
@@ -798,12 +834,13 @@ __global__ __launch_bounds__(64) void k_raster_adj(
         const int t = j + step;
         if (t < np && __float_as_int(sq[t * Q::N + Q::START]) <= s0) j = t;
       }
-      float offx, offy, qa, qb, qc, amp[2 * C];
+      float offx, offy, qa, qb, qc, amp[2 * C], plo = 0.f, phi = 0.f;
       int bxa, bxb, lx, ly, sj, left, span = 0;
       auto load_pair = [&](int jj) {
         const float *q = sq + jj * Q::N;
         offx = q[0]; offy = q[1];
         qa = q[2]; qb = q[3]; qc = q[4];
+        if (PA) { plo = q[Q::LO]; phi = q[Q::HI]; }
 #pragma unroll
         for (int k = 0; k < 2 * C; ++k) amp[k] = q[Q::AMP + k];
         const int bx = __float_as_int(q[Q::BOX]);
@@ -859,8 +896,12 @@ __global__ __launch_bounds__(64) void k_raster_adj(
             // or below the tile (the zero row, so every term is 0).
             const float dy = (float)ly + offy, dx = (float)lx + offx;
             const float p2 = fmaf(dx, fmaf(qa, dx, qb * dy), qc * dy * dy);
-            const float G =
-                p2 >= thr ? __builtin_amdgcn_exp2f(CLAMP ? fmaxf(p2, kPowerFloor2) : p2) : 0.f;
+            float G;
+            if (PA)
+              G = p2 >= plo ? __builtin_amdgcn_exp2f(fminf(p2, phi)) : 0.f;
+            else
+              G = p2 >= thr ? __builtin_amdgcn_exp2f(CLAMP ? fmaxf(p2, kPowerFloor2) : p2)
+                            : 0.f;
             // 24-bit multiply (full rate) for the LDS offset
             const float2 *gv =
                 &sg[0][0] + __umul24((unsigned)(min(ly, kTile) * kTile + lx), (unsigned)C);
@@ -872,8 +913,16 @@ __global__ __launch_bounds__(64) void k_raster_adj(
               S[2 * c] = fmaf(G, v.x, S[2 * c]);
               S[2 * c + 1] = fmaf(G, v.y, S[2 * c + 1]);
             }
-            // without the clamp, G > 0 implies p2 >= thr > the clamp
-            const float w = (!CLAMP || p2 > kPowerFloor2) ? gp * G : 0.f;
+            // without the clamp, G > 0 implies p2 >= thr > the clamp; with PA the
+            // weight is constant (0.99) where p2 > hi, so only alpha's sum sees it
+            float w;
+            if constexpr (PA) {
+              const bool clamped = p2 > phi;
+              w = clamped ? 0.f : gp * G;
+              S[2 * C + 5] += clamped ? gp * G : 0.f;
+            } else {
+              w = (!CLAMP || p2 > kPowerFloor2) ? gp * G : 0.f;
+            }
             const float wx = w * dx, wy = w * dy;
             S[2 * C] += wx;
             S[2 * C + 1] += wy;
@@ -921,7 +970,9 @@ __global__ __launch_bounds__(64) void k_raster_adj(
 // Pass items 1-7):
 //   dL/dc_c   = alpha (cos phi dP_c + sin phi dQ_c)
 //   dL/dphi_c = alpha c (-sin phi dP_c + cos phi dQ_c)
-//   dL/dalpha = sum_c c (cos phi dP_c + sin phi dQ_c);  dalpha/dalpha~ = alpha (1 - alpha)
+//   dL/dalpha = sum_c c (cos phi dP_c + sin phi dQ_c) (minus, with CGH_PAPER_ALPHA, the
+//               part of the pixels where the 0.99 clamp is active);
+//               dalpha/dalpha~ = alpha (1 - alpha)
 //   dL/dmean  = Sigma^{-1} (sum w d);  dmean/dx~ = [W, H]/2 (1 - tanh^2 x~)
 //   dL/dSigma^{-1} entries (inv00, inv01 stored once, inv11) = -(1/2, 1, 1/2) sum w d d
 //   dL/dSigma = -Sigma^{-1} G Sigma^{-1} (G the symmetric gradient matrix), off-
@@ -929,13 +980,15 @@ __global__ __launch_bounds__(64) void k_raster_adj(
 //   inv = adj(Sigma) / eps_d
 //   Sigma -> (s_x, s_y, theta) and s = exp(s~) + eps_s.
 // ----------------------------------------------------------------------------
-template <int C>
+template <int C, bool PA>
 __global__ __launch_bounds__(256) void k_preprocess_adj(
     const float *__restrict__ params, int n, int W, int H,
     const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets, int64_t cap,
     const float *__restrict__ partials, float *__restrict__ grads) {
   constexpr int PS = part_stride_c(C);
-  constexpr int NP = 2 * C + 5;
+  // the 2C + 5 partial sums, plus the clamped-pixel sum with CGH_PAPER_ALPHA
+  constexpr int NP = 2 * C + 5 + (PA ? 1 : 0);
+  static_assert(NP <= PS, "spare partial slot");
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   double S[NP];
@@ -986,6 +1039,9 @@ __global__ __launch_bounds__(256) void k_preprocess_adj(
     g_ph[(size_t)g * C + c] = (float)(q.alpha * cc * (-sn * dP + cs * dQ));
     dalpha += cc * proj;
   }
+  // pixels where the Alg. 2 clamp is active contribute 0.99 c e^{j phi}, which
+  // does not depend on alpha: their part of the amplitude sums comes off here
+  if constexpr (PA) dalpha -= S[2 * C + 5] / q.alpha;
   g_op[g] = (float)(dalpha * q.alpha * (1.0 - q.alpha));
   const double W1 = S[2 * C], W2 = S[2 * C + 1], W3 = S[2 * C + 2], W4 = S[2 * C + 3],
                W5 = S[2 * C + 4];
@@ -1028,9 +1084,18 @@ hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStre
   const uint32_t *vals = c.vals[c.sorted];
   dim3 grid(c.num_tiles), block(64);
   const bool clamp = !(thr > kPowerFloor2);
-#define CGH_ADJ(CC, CL)                                                                  \
-  hipLaunchKernelGGL((k_raster_adj<CC, CL>), grid, block, 0, s, c.rec, vals, c.ranges, c.rect, \
-                     c.offsets, c.W, c.H, c.tiles_x, thr, grad_field, c.pair_cap, c.partials)
+  const bool pa = c.alim != nullptr;
+#define CGH_ADJ(CC, CL)                                                                       \
+  do {                                                                                        \
+    if (pa)                                                                                   \
+      hipLaunchKernelGGL((k_raster_adj<CC, false, true>), grid, block, 0, s, c.rec, vals,     \
+                         c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, c.alim,       \
+                         grad_field, c.pair_cap, c.partials);                                 \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_raster_adj<CC, CL, false>), grid, block, 0, s, c.rec, vals,       \
+                         c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, c.alim,       \
+                         grad_field, c.pair_cap, c.partials);                                 \
+  } while (0)
   switch (c.C) {
     case 1: if (clamp) CGH_ADJ(1, true); else CGH_ADJ(1, false); break;
     case 2: if (clamp) CGH_ADJ(2, true); else CGH_ADJ(2, false); break;
@@ -1045,12 +1110,17 @@ hipError_t launch_preprocess_adjoint(const Ctx &c, const float *params, int n, f
                                      hipStream_t s) {
   if (n <= 0) return hipSuccess;
   dim3 g2((n + 255) / 256), block(256);
+  const bool pa = c.alim != nullptr;
+#define CGH_PADJ(CC, PA)                                                                  \
+  hipLaunchKernelGGL((k_preprocess_adj<CC, PA>), g2, block, 0, s, params, n, c.W, c.H,    \
+                     c.counts, c.offsets, c.pair_cap, c.partials, grads)
   switch (c.C) {
-    case 1: hipLaunchKernelGGL(k_preprocess_adj<1>, g2, block, 0, s, params, n, c.W, c.H, c.counts, c.offsets, c.pair_cap, c.partials, grads); break;
-    case 2: hipLaunchKernelGGL(k_preprocess_adj<2>, g2, block, 0, s, params, n, c.W, c.H, c.counts, c.offsets, c.pair_cap, c.partials, grads); break;
-    case 3: hipLaunchKernelGGL(k_preprocess_adj<3>, g2, block, 0, s, params, n, c.W, c.H, c.counts, c.offsets, c.pair_cap, c.partials, grads); break;
-    default: hipLaunchKernelGGL(k_preprocess_adj<4>, g2, block, 0, s, params, n, c.W, c.H, c.counts, c.offsets, c.pair_cap, c.partials, grads); break;
+    case 1: if (pa) CGH_PADJ(1, true); else CGH_PADJ(1, false); break;
+    case 2: if (pa) CGH_PADJ(2, true); else CGH_PADJ(2, false); break;
+    case 3: if (pa) CGH_PADJ(3, true); else CGH_PADJ(3, false); break;
+    default: if (pa) CGH_PADJ(4, true); else CGH_PADJ(4, false); break;
   }
+#undef CGH_PADJ
   return hipGetLastError();
 }
 

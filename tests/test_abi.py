@@ -92,12 +92,20 @@ def test_full_loss_flag_reserves_the_ssim_buffers():
     assert need <= full - base <= need + 5 * 256 + 8 * LC * 2 * 7 * 4
 
 
+def test_paper_alpha_flag_reserves_the_exponent_limits():
+    """CGH_PAPER_ALPHA adds one (lo, hi) float pair per Gaussian slot (n + 1)."""
+    st0, base = ws(cfg(n=5000))
+    st1, pa = ws(cfg(n=5000, flags=binding.CGH_PAPER_ALPHA))
+    assert st0 == st1 == 0
+    assert 8 * 5001 <= pa - base <= 8 * 5001 + 256
+
+
 @pytest.mark.parametrize("bad, status", [
     (dict(H=0), 1), (dict(W=9000), 1), (dict(C=5), 1), (dict(C=0), 1),
     (dict(Hp=514), 1),            # 514 = 2 * 257 does not factor into 2, 3, 5
     (dict(Hp=200), 1),            # smaller than H
     (dict(pitch=0.0), 1), (dict(lambdas=[-1.0]), 1), (dict(n=-1), 1),
-    (dict(flags=2), 1), (dict(pairs=-5), 1),
+    (dict(flags=4), 1), (dict(pairs=-5), 1),
     (dict(flags=1, H=10), 1), (dict(flags=1, W=10, Wp=20), 1),   # SSIM window is 11 x 11
     (dict(L=0), 1), (dict(zs=[1e-3] * 8, L=9), 1),   # 1 <= planes <= CGH_MAX_PLANES
     (dict(zs=[1e-3, float("nan")]), 1),

@@ -444,6 +444,57 @@ def test_recon_loss_parity(O):
         assert e <= GRAD_TOL, (k, e)
 
 
+def test_paper_alpha_parity(O):
+    """The Alg. 2 weight (CGH_PAPER_ALPHA: min(0.99, alpha G), skipped below
+    1/255) against the oracle with the same flag: field, loss, dL/dU0 and the
+    parameter gradients, with opacities spread so that both the clamp and the
+    skip occur.  Pixels touched by a pair within the rounding band of the
+    support or skip boundary are left out of the field comparison."""
+    H, W, C, n = 48, 80, 3, 700
+    lambdas, zs = [639e-9, 515e-9, 473e-9], [4e-3]
+    say("paper alpha", H, W, C, n)
+    p = synth.params(111, n, H, W, C)
+    p["opacity_pre"] = np.random.default_rng(112).uniform(-4.0, 7.0, n).astype(np.float32)
+    # 200 nearly opaque, wide Gaussians: alpha G > 0.99 within ~0.12 sigma of
+    # their means, so the 0.99 clamp is active at the pixels nearest to them
+    p["opacity_pre"][:200] = 6.0
+    p["log_scale"][:200] = np.float32(math.log(6.0))
+    T = synth.target(113, C, H, W) * np.float32(0.5)
+    opt = O.Optics(H, W, C, 90, 160, 8e-6, lambdas, zs, flags=O.FLAG_PAPER_ALPHA)
+    ctx = binding.Context(H, W, C, 8e-6, lambdas, zs, pad=(90, 160), max_gaussians=n,
+                          paper_alpha=True)
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    ref = O.forward_backward(p, T, opt)
+    plain = O.raster(p, O.Optics(H, W, C, 90, 160, 8e-6, lambdas, zs))
+    # the flag matters here: clamped and skipped pairs change the field well
+    # beyond the tolerance, and the clamp is active at some Gaussians' nearest pixel
+    geo = O.geometry(p, W, H)
+    d = np.stack([np.round(geo[:, 0]) - geo[:, 0], np.round(geo[:, 1]) - geo[:, 1]], 1)
+    qn = geo[:, 8] * d[:, 0] ** 2 + 2 * geo[:, 9] * d[:, 0] * d[:, 1] + geo[:, 10] * d[:, 1] ** 2
+    clamped = int(np.sum(geo[:, 11] * np.exp(-qn / 2) > 0.99))
+    say("field change from the flag", rel_l2(ref["field"], plain), "clamped Gaussians", clamped)
+    assert rel_l2(ref["field"], plain) > 10 * FIELD_TOL
+    assert clamped >= 20
+    mask, amb = O.ambiguous_mask(p, opt, AMBIGUOUS_BAND)
+    err = rel_l2(field.cpu().numpy(), ref["field"], mask)
+    say("field rel-L2", err, "ambiguous pairs", amb, "masked pixels", int(mask.sum()))
+    # two rounding-sensitive boundaries here (support and skip): at most 0.5 %
+    # of the pixels are left out
+    assert mask.sum() <= 5e-3 * mask.size
+    assert err <= FIELD_TOL
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss, grad_field=gfield)
+    torch.cuda.synchronize()
+    assert abs(loss.cpu().numpy()[0] - ref["loss"]) <= 1e-4 * ref["loss"]
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
+    errs = group_errors(grads.cpu().numpy(), ref["grads"], n, C)
+    say("grad rel-L2 per group", errs)
+    for k, e in errs.items():
+        assert e <= GRAD_TOL, (k, e)
+
+
 @pytest.mark.parametrize("case", [
     # the paper's weight, depth masks, two planes; 38 x 70 window positions
     # (2 x 3 position tiles, both ragged) and 2 x 3 pixel tiles
