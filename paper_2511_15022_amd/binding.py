@@ -75,7 +75,25 @@ _SIGS = [
     ("cgh_last_error", ctypes.c_char_p, []),
     ("cgh_abi_version", ctypes.c_int32, []),
 ]
+# entry points of include/cgh_net.h (the learned initialiser's network)
+_I32, _I64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_NET_SIGS = [
+    ("cgh_net_conv3x3", ctypes.c_int,
+     [_VP, _I32, _I32, _VP, _I32, _I32, _I32, _VP, _VP, _I32, _I32, _VP, _VP, _VP]),
+    ("cgh_net_flip_weights", ctypes.c_int, [_VP, _I32, _I32, _VP, _VP]),
+    ("cgh_net_wgrad_workspace", ctypes.c_size_t, [_I32, _I32, _I32, _I32]),
+    ("cgh_net_conv3x3_wgrad", ctypes.c_int,
+     [_VP, _I32, _I32, _VP, _I32, _I32, _I32, _VP, _I32, _VP, _VP, _VP, _SZ, _VP]),
+    ("cgh_net_cast_bf16", ctypes.c_int, [_VP, _I64, _VP, _VP]),
+    ("cgh_net_relu_grad", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP]),
+    ("cgh_net_pool2", ctypes.c_int, [_VP, _I32, _I32, _I32, _VP, _VP]),
+    ("cgh_net_up_adjoint", ctypes.c_int, [_VP, _I32, _I32, _I32, _I32, _VP, _VP]),
+    ("cgh_net_grad_combine", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _I32, _I32, _VP, _VP]),
+    ("cgh_net_lattice_gather", ctypes.c_int, [_VP, _I32, _I32, _I32, _I32, _VP, _VP]),
+    ("cgh_net_lattice_scatter", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP]),
+]
 EXPORTS = tuple(name for name, _, _ in _SIGS)
+NET_EXPORTS = tuple(name for name, _, _ in _NET_SIGS)
 
 _lib = None
 
@@ -88,7 +106,7 @@ def lib():
             raise RuntimeError(f"libcgh.so not found at {LIB_PATH}; build it with "
                                "paper_2511_15022_amd/build.py (no CPU fallback exists)")
         L = ctypes.CDLL(LIB_PATH)
-        for name, res, args in _SIGS:
+        for name, res, args in _SIGS + _NET_SIGS:
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args

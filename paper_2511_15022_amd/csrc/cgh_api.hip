@@ -27,6 +27,19 @@ cgh_status device_fail(hipError_t e, const char *where) {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+}  // namespace
+
+// the error channel of cgh_last_error() for the other source files of the library
+cgh_status cgh::report(cgh_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+namespace {
+
 #define CGH_CHECK_LAUNCH(expr, where)              \
   do {                                             \
     hipError_t e_ = (expr);                        \

@@ -110,6 +110,7 @@ struct Ctx {
 constexpr int kMaxProf = 256;
 
 size_t carve(Ctx *c, char *base);   // returns bytes used (base may be null)
+cgh_status report(cgh_status st, const char *fmt, ...);  // sets cgh_last_error()
 
 // The column pass runs one wave per column chain (k_col_wave) for Hp = 2160
 // with every column tile full; it reads the column-major transfer table.

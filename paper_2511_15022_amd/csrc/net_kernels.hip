@@ -1,0 +1,475 @@
+// Kernels of the learned initialiser's U-Net (include/cgh_net.h): 3x3
+// convolutions as implicit GEMMs on the matrix cores (BF16 inputs, FP32
+// sums), their weight gradients, and the pooling, upsampling, ReLU and
+// lattice glue around them.
+//
+// Matrix instruction: v_mfma_f32_32x32x8 bf16 (one wave, D = A B + D with A
+// 32 x 8, B 8 x 32).  Lane l supplies A[l % 32][4 (l / 32) + i] and
+// B[4 (l / 32) + i][l % 32] (i < 4) and holds D[8 (v / 4) + 4 (l / 32) +
+// v % 4][l % 32] in accumulator v < 16.
+#include <algorithm>
+#include <cmath>
+
+#include "cgh_internal.h"
+#include "cgh_net.h"
+
+namespace cgh {
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);  // nearest, ties to even
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// four consecutive channels (8 bytes) of the convolution input at (y, x),
+// channel c0 (a multiple of 4) of [up(x1), x2]; zero outside the image
+__device__ __forceinline__ v4s conv_in4(const uint16_t *__restrict__ x1, int c1, int up,
+                                        const uint16_t *__restrict__ x2, int c2, int H, int W,
+                                        int y, int x, int c0) {
+  v4s r = {0, 0, 0, 0};
+  if (y < 0 || y >= H || x < 0 || x >= W) return r;
+  const uint16_t *src;
+  if (c0 < c1) {
+    src = up ? x1 + ((size_t)(y >> 1) * (W >> 1) + (x >> 1)) * c1 + c0
+             : x1 + ((size_t)y * W + x) * c1 + c0;
+  } else {
+    src = x2 + ((size_t)y * W + x) * c2 + (c0 - c1);
+  }
+  return *reinterpret_cast<const v4s *>(src);
+}
+
+// ----------------------------------------------------------------------------
+// Convolution: a workgroup of 4 waves takes 128 consecutive pixels (in row-major
+// order) and 32 NB output channels; wave w computes pixels 32 w .. 32 w + 31
+// against the NB blocks of 32 channels, stepping through the 9 taps and the
+// input channels 8 at a time.
+// ----------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1, int c1, int up,
+                                                 const uint16_t *__restrict__ x2, int c2, int H,
+                                                 int W, const uint16_t *__restrict__ w,
+                                                 const float *__restrict__ bias, int cout,
+                                                 int relu, float *__restrict__ out32,
+                                                 uint16_t *__restrict__ out16) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int P = H * W, cin = c1 + c2;
+  const int p = blockIdx.x * 128 + wave * 32 + (lane & 31);  // this lane's A row
+  const int kq = 4 * (lane >> 5);                            // its k offset in a block of 8
+  const int co0 = blockIdx.y * 32 * NB;
+  const int py = p / W, px = p - py * W;
+  v16f acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
+  for (int t = 0; t < 9; ++t) {
+    const int ky = t / 3, kx = t - 3 * ky;
+    const int sy = py + ky - 1, sx = px + kx - 1;
+    const bool valid = p < P;
+    for (int ci = 0; ci < cin; ci += 8) {
+      const v4s a = valid ? conv_in4(x1, c1, up, x2, c2, H, W, sy, sx, ci + kq) : v4s{0, 0, 0, 0};
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int co = co0 + 32 * b + (lane & 31);
+        const v4s bb = *reinterpret_cast<const v4s *>(w + ((size_t)co * 9 + t) * cin + ci + kq);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc[b], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int co = co0 + 32 * b + (lane & 31);
+    const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int q = blockIdx.x * 128 + wave * 32 + 8 * (v >> 2) + kq + (v & 3);
+      if (q < P) {
+        const float s = acc[b][v] + bv;
+        if (out32) out32[(size_t)q * cout + co] = s;
+        if (out16) out16[(size_t)q * cout + co] = to_bf16(relu ? fmaxf(s, 0.f) : s);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Weight gradient: gw[co][n] (n = t cin + ci, tap t = 3 ky + kx) = sum_p gy[p][co]
+// in[p + k(t) - 1][ci] as a GEMM over pixels.  One wave per (32 n, 32 co, split):
+// A = gy^T (co x 8 pixels), B = the shifted input (8 pixels x n); FP32 partials
+// per split; the bias gradient rides along in the n-block 0 waves.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_conv3x3_wgrad(
+    const uint16_t *__restrict__ x1, int c1, int up, const uint16_t *__restrict__ x2, int c2,
+    int H, int W, const uint16_t *__restrict__ gy, int cout, int chunk,
+    float *__restrict__ part, float *__restrict__ part_b) {
+  const int lane = threadIdx.x;
+  const int P = H * W, cin = c1 + c2, N = 9 * cin;
+  const int nb = blockIdx.x, cb = blockIdx.y, s = blockIdx.z;
+  const int kq = 4 * (lane >> 5);
+  const int co = cb * 32 + (lane & 31);
+  const int n = nb * 32 + (lane & 31);
+  const bool nv = n < N;
+  const int t = nv ? n / cin : 0, ci = nv ? n - t * cin : 0;
+  const int ky = t / 3, kx = t - 3 * ky;
+  // B reads one channel at a time; pick x1 or x2 once
+  const bool from1 = ci < c1;
+  const int p0 = s * chunk, p1 = min(P, p0 + chunk);
+  v16f acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  float bsum = 0.f;
+  for (int pb = p0; pb < p1; pb += 8) {
+    v4s a, bb;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = pb + kq + i;
+      uint16_t av = 0, bv = 0;
+      if (p < p1) {
+        av = gy[(size_t)p * cout + co];
+        const int py = p / W, px = p - py * W;
+        const int sy = py + ky - 1, sx = px + kx - 1;
+        if (nv && sy >= 0 && sy < H && sx >= 0 && sx < W) {
+          if (from1)
+            bv = up ? x1[((size_t)(sy >> 1) * (W >> 1) + (sx >> 1)) * c1 + ci]
+                    : x1[((size_t)sy * W + sx) * c1 + ci];
+          else
+            bv = x2[((size_t)sy * W + sx) * c2 + (ci - c1)];
+        }
+      }
+      a[i] = (short)av;
+      bb[i] = (short)bv;
+      bsum += from_bf16(av);
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc, 0, 0, 0);
+  }
+  // D[row = co][col = n]
+  float *dst = part + (size_t)s * cout * N;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int r = cb * 32 + 8 * (v >> 2) + kq + (v & 3);
+    if (nv) dst[(size_t)r * N + n] = acc[v];
+  }
+  if (nb == 0) {
+    // lanes l and l + 32 hold the two halves of the pixels of channel co
+    bsum += __shfl_down(bsum, 32, 64);
+    if (lane < 32) part_b[(size_t)s * cout + co] = bsum;
+  }
+}
+
+// fixed-order sum over the splits
+__global__ void k_wgrad_reduce(const float *__restrict__ part, const float *__restrict__ part_b,
+                               int splits, int64_t len, int cout, float *__restrict__ gw,
+                               float *__restrict__ gb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) {
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part[(size_t)k * len + i];
+    gw[i] = s;
+  }
+  if (gb && i < cout) {
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part_b[(size_t)k * cout + i];
+    gb[i] = s;
+  }
+}
+
+__global__ void k_flip(const uint16_t *__restrict__ w, int cout, int cin,
+                       uint16_t *__restrict__ wt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over wt: [cin][9][cout]
+  if (i >= cout * 9 * cin) return;
+  const int co = i % cout, t = (i / cout) % 9, ci = i / (9 * cout);
+  wt[i] = w[((size_t)co * 9 + (8 - t)) * cin + ci];  // (ky, kx) -> (2 - ky, 2 - kx)
+}
+
+__global__ void k_cast(const float *__restrict__ x, int64_t n, uint16_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = to_bf16(x[i]);
+}
+
+__global__ void k_relu_grad(const float *__restrict__ g, const uint16_t *__restrict__ a,
+                            int64_t n, uint16_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = to_bf16((a == nullptr || from_bf16(a[i]) > 0.f) ? g[i] : 0.f);
+}
+
+__global__ void k_pool2(const uint16_t *__restrict__ x, int H, int W, int C,
+                        uint16_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int Ho = H / 2, Wo = W / 2;
+  if (i >= (int64_t)Ho * Wo * C) return;
+  const int c = (int)(i % C);
+  const int64_t q = i / C;
+  const int y = (int)(q / Wo), xo = (int)(q - (int64_t)y * Wo);
+  const uint16_t *s = x + ((size_t)(2 * y) * W + 2 * xo) * C + c;
+  const float v = (from_bf16(s[0]) + from_bf16(s[C])) +
+                  (from_bf16(s[(size_t)W * C]) + from_bf16(s[(size_t)W * C + C]));
+  out[i] = to_bf16(0.25f * v);
+}
+
+__global__ void k_up_adjoint(const float *__restrict__ g, int H, int W, int stride, int C,
+                             float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int Ho = H / 2, Wo = W / 2;
+  if (i >= (int64_t)Ho * Wo * C) return;
+  const int c = (int)(i % C);
+  const int64_t q = i / C;
+  const int y = (int)(q / Wo), x = (int)(q - (int64_t)y * Wo);
+  const float *s = g + ((size_t)(2 * y) * W + 2 * x) * stride + c;
+  out[i] = (s[0] + s[stride]) + (s[(size_t)W * stride] + s[(size_t)W * stride + stride]);
+}
+
+__global__ void k_grad_combine(const float *__restrict__ gp, const float *__restrict__ gs,
+                               int stride, int off, int H, int W, int C,
+                               float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)H * W * C) return;
+  const int c = (int)(i % C);
+  const int64_t q = i / C;
+  const int y = (int)(q / W), x = (int)(q - (int64_t)y * W);
+  float v = 0.f;
+  if (gp) v = 0.25f * gp[((size_t)(y >> 1) * (W >> 1) + (x >> 1)) * C + c];
+  if (gs) v += gs[(size_t)q * stride + off + c];
+  out[i] = v;
+}
+
+// lattice point k = i gx + j: centre in FP64, its pixel
+__device__ __forceinline__ void lattice_point(int k, int H, int W, int gy, int gx, double &cy,
+                                              double &cx, int &iy, int &ix) {
+  const int i = k / gx, j = k - i * gx;
+  cy = (i + 0.5) * (double)H / gy;
+  cx = (j + 0.5) * (double)W / gx;
+  iy = (int)floor(cy);
+  ix = (int)floor(cx);
+}
+
+constexpr double kLogScale0 = 0.69314718055994530942;  // ln 2
+constexpr double kAmp0 = 0.5, kOpacity0 = -0.5;
+
+__global__ void k_lattice_gather(const float *__restrict__ net, int H, int W, int gy, int gx,
+                                 float *__restrict__ params) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = gy * gx;
+  if (k >= n) return;
+  double cy, cx;
+  int iy, ix;
+  lattice_point(k, H, W, gy, gx, cy, cx, iy, ix);
+  const float *o = net + ((size_t)iy * W + ix) * 8;
+  const double mx = fmin(fmax(cx + (double)o[0], 1e-3), W - 1e-3);
+  const double my = fmin(fmax(cy + (double)o[1], 1e-3), H - 1e-3);
+  // flat layout: mean_pre [n][2], log_scale [n][2], rotation [n], amplitude [n],
+  // phase [n], opacity_pre [n] (C = 1)
+  params[2 * k] = (float)atanh(2.0 * mx / W - 1.0);
+  params[2 * k + 1] = (float)atanh(2.0 * my / H - 1.0);
+  params[2 * (size_t)n + 2 * k] = (float)((double)o[2] + kLogScale0);
+  params[2 * (size_t)n + 2 * k + 1] = (float)((double)o[3] + kLogScale0);
+  params[4 * (size_t)n + k] = o[4];
+  params[5 * (size_t)n + k] = (float)((double)o[5] + kAmp0);
+  params[6 * (size_t)n + k] = o[6];
+  params[7 * (size_t)n + k] = (float)((double)o[7] + kOpacity0);
+}
+
+__global__ void k_fill0(float *__restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.f;
+}
+
+__global__ void k_lattice_scatter(const float *__restrict__ net, const float *__restrict__ g,
+                                  int H, int W, int gy, int gx, float *__restrict__ gnet) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = gy * gx;
+  if (k >= n) return;
+  double cy, cx;
+  int iy, ix;
+  lattice_point(k, H, W, gy, gx, cy, cx, iy, ix);
+  const float *o = net + ((size_t)iy * W + ix) * 8;
+  float *d = gnet + ((size_t)iy * W + ix) * 8;
+  const double mx = cx + (double)o[0], my = cy + (double)o[1];
+  const double ux = 2.0 * mx / W - 1.0, uy = 2.0 * my / H - 1.0;
+  // d atanh(2m / S - 1) / dm = (2 / S) / (1 - u^2); zero where the clip is active
+  d[0] = (mx > 1e-3 && mx < W - 1e-3) ? (float)((double)g[2 * k] * (2.0 / W) / (1.0 - ux * ux)) : 0.f;
+  d[1] = (my > 1e-3 && my < H - 1e-3) ? (float)((double)g[2 * k + 1] * (2.0 / H) / (1.0 - uy * uy)) : 0.f;
+  d[2] = g[2 * (size_t)n + 2 * k];
+  d[3] = g[2 * (size_t)n + 2 * k + 1];
+  d[4] = g[4 * (size_t)n + k];
+  d[5] = g[5 * (size_t)n + k];
+  d[6] = g[6 * (size_t)n + k];
+  d[7] = g[7 * (size_t)n + k];
+}
+
+unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+int wgrad_chunk(int P) {
+  // about 1024 pixels per split, a multiple of 8
+  const int splits = std::max(1, P / 1024);
+  return ((P + splits - 1) / splits + 7) & ~7;
+}
+
+}  // namespace
+}  // namespace cgh
+
+using namespace cgh;
+
+#define NET_CHECK(cond, ...) \
+  do {                       \
+    if (!(cond)) return report(CGH_ERR_INVALID_ARG, __VA_ARGS__); \
+  } while (0)
+#define NET_LAUNCHED(where)                                                           \
+  do {                                                                                \
+    const hipError_t e_ = hipGetLastError();                                          \
+    if (e_ != hipSuccess) return report(CGH_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e_)); \
+  } while (0)
+
+static cgh_status check_conv_shape(const cgh_bf16 *x1, int32_t c1, int32_t up,
+                                   const cgh_bf16 *x2, int32_t c2, int32_t H, int32_t W) {
+  NET_CHECK(x1 && c1 > 0 && c1 % 8 == 0, "x1 NULL or c1 = %d not a positive multiple of 8", c1);
+  NET_CHECK((x2 == nullptr) == (c2 == 0) && c2 >= 0 && c2 % 8 == 0,
+            "x2 / c2 = %d: both absent, or c2 a positive multiple of 8", c2);
+  NET_CHECK(H >= 1 && W >= 1 && (int64_t)H * W < (1LL << 31), "bad size %d x %d", H, W);
+  NET_CHECK(!up || (H % 2 == 0 && W % 2 == 0), "upsampled input needs even H, W");
+  NET_CHECK(al16(x1) && al16(x2), "inputs must be 16-byte aligned");
+  return CGH_OK;
+}
+
+extern "C" {
+
+cgh_status cgh_net_conv3x3(const cgh_bf16 *x1, int32_t c1, int32_t up, const cgh_bf16 *x2,
+                           int32_t c2, int32_t H, int32_t W, const cgh_bf16 *w,
+                           const float *bias, int32_t cout, int32_t relu, float *out32,
+                           cgh_bf16 *out16, void *stream) {
+  const cgh_status st = check_conv_shape(x1, c1, up, x2, c2, H, W);
+  if (st != CGH_OK) return st;
+  NET_CHECK(w && cout > 0 && cout % 32 == 0, "w NULL or cout = %d not a multiple of 32", cout);
+  NET_CHECK(out32 || out16, "no output");
+  NET_CHECK(al16(w), "w must be 16-byte aligned");
+  const int nb = cout % 128 == 0 ? 4 : (cout % 64 == 0 ? 2 : 1);
+  const dim3 grid(blocks_of((int64_t)H * W, 128), cout / (32 * nb));
+  hipStream_t s = (hipStream_t)stream;
+#define NET_CONV(NB)                                                                       \
+  hipLaunchKernelGGL(k_conv3x3<NB>, grid, dim3(256), 0, s, x1, c1, up, x2, c2, H, W, w, bias, \
+                     cout, relu, out32, out16)
+  if (nb == 4) NET_CONV(4);
+  else if (nb == 2) NET_CONV(2);
+  else NET_CONV(1);
+#undef NET_CONV
+  NET_LAUNCHED("conv3x3");
+  return CGH_OK;
+}
+
+cgh_status cgh_net_flip_weights(const cgh_bf16 *w, int32_t cout, int32_t cin, cgh_bf16 *w_t,
+                                void *stream) {
+  NET_CHECK(w && w_t && cout > 0 && cin > 0, "bad arguments");
+  hipLaunchKernelGGL(k_flip, dim3(blocks_of((int64_t)cout * 9 * cin, 256)), dim3(256), 0,
+                     (hipStream_t)stream, w, cout, cin, w_t);
+  NET_LAUNCHED("flip_weights");
+  return CGH_OK;
+}
+
+size_t cgh_net_wgrad_workspace(int32_t H, int32_t W, int32_t cin, int32_t cout) {
+  if (H < 1 || W < 1 || cin < 1 || cout < 1) return 0;
+  const int P = H * W, chunk = wgrad_chunk(P), splits = (P + chunk - 1) / chunk;
+  return (size_t)splits * ((size_t)cout * 9 * cin + cout) * sizeof(float);
+}
+
+cgh_status cgh_net_conv3x3_wgrad(const cgh_bf16 *x1, int32_t c1, int32_t up, const cgh_bf16 *x2,
+                                 int32_t c2, int32_t H, int32_t W, const cgh_bf16 *gy,
+                                 int32_t cout, float *gw, float *gb, void *workspace,
+                                 size_t workspace_bytes, void *stream) {
+  const cgh_status st = check_conv_shape(x1, c1, up, x2, c2, H, W);
+  if (st != CGH_OK) return st;
+  NET_CHECK(gy && gw && cout > 0 && cout % 32 == 0, "gy/gw NULL or cout = %d not a multiple of 32",
+            cout);
+  const int cin = c1 + c2, P = H * W, chunk = wgrad_chunk(P), splits = (P + chunk - 1) / chunk;
+  const size_t need = cgh_net_wgrad_workspace(H, W, cin, cout);
+  if (!workspace || workspace_bytes < need)
+    return report(CGH_ERR_WORKSPACE, "wgrad workspace has %zu bytes, needs %zu", workspace_bytes,
+                  need);
+  const int64_t len = (int64_t)cout * 9 * cin;
+  float *part = (float *)workspace, *part_b = part + (size_t)splits * len;
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid((9 * cin + 31) / 32, cout / 32, splits);
+  hipLaunchKernelGGL(k_conv3x3_wgrad, grid, dim3(64), 0, s, x1, c1, up, x2, c2, H, W, gy, cout,
+                     chunk, part, part_b);
+  NET_LAUNCHED("conv3x3_wgrad");
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_of(std::max<int64_t>(len, cout), 256)),
+                     dim3(256), 0, s, part, part_b, splits, len, cout, gw, gb);
+  NET_LAUNCHED("wgrad_reduce");
+  return CGH_OK;
+}
+
+cgh_status cgh_net_cast_bf16(const float *x, int64_t count, cgh_bf16 *out, void *stream) {
+  NET_CHECK(count >= 0 && (count == 0 || (x && out)), "bad arguments");
+  if (count == 0) return CGH_OK;
+  hipLaunchKernelGGL(k_cast, dim3(blocks_of(count, 256)), dim3(256), 0, (hipStream_t)stream, x,
+                     count, out);
+  NET_LAUNCHED("cast_bf16");
+  return CGH_OK;
+}
+
+cgh_status cgh_net_relu_grad(const float *g, const cgh_bf16 *a, int64_t count, cgh_bf16 *out,
+                             void *stream) {
+  NET_CHECK(count >= 0 && (count == 0 || (g && out)), "bad arguments");
+  if (count == 0) return CGH_OK;
+  hipLaunchKernelGGL(k_relu_grad, dim3(blocks_of(count, 256)), dim3(256), 0,
+                     (hipStream_t)stream, g, a, count, out);
+  NET_LAUNCHED("relu_grad");
+  return CGH_OK;
+}
+
+cgh_status cgh_net_pool2(const cgh_bf16 *x, int32_t H, int32_t W, int32_t C, cgh_bf16 *out,
+                         void *stream) {
+  NET_CHECK(x && out && H >= 2 && W >= 2 && H % 2 == 0 && W % 2 == 0 && C > 0, "bad arguments");
+  hipLaunchKernelGGL(k_pool2, dim3(blocks_of((int64_t)(H / 2) * (W / 2) * C, 256)), dim3(256), 0,
+                     (hipStream_t)stream, x, H, W, C, out);
+  NET_LAUNCHED("pool2");
+  return CGH_OK;
+}
+
+cgh_status cgh_net_up_adjoint(const float *g, int32_t H, int32_t W, int32_t stride, int32_t C,
+                              float *out, void *stream) {
+  NET_CHECK(g && out && H % 2 == 0 && W % 2 == 0 && H >= 2 && W >= 2 && C > 0 && stride >= C,
+            "bad arguments");
+  hipLaunchKernelGGL(k_up_adjoint, dim3(blocks_of((int64_t)(H / 2) * (W / 2) * C, 256)),
+                     dim3(256), 0, (hipStream_t)stream, g, H, W, stride, C, out);
+  NET_LAUNCHED("up_adjoint");
+  return CGH_OK;
+}
+
+cgh_status cgh_net_grad_combine(const float *gp, const float *gs, int32_t stride, int32_t off,
+                                int32_t H, int32_t W, int32_t C, float *out, void *stream) {
+  NET_CHECK(out && H >= 1 && W >= 1 && C > 0, "bad arguments");
+  NET_CHECK(!gp || (H % 2 == 0 && W % 2 == 0), "pooled gradient needs even H, W");
+  NET_CHECK(!gs || (off >= 0 && off + C <= stride), "skip slice outside its rows");
+  hipLaunchKernelGGL(k_grad_combine, dim3(blocks_of((int64_t)H * W * C, 256)), dim3(256), 0,
+                     (hipStream_t)stream, gp, gs, stride, off, H, W, C, out);
+  NET_LAUNCHED("grad_combine");
+  return CGH_OK;
+}
+
+cgh_status cgh_net_lattice_gather(const float *net, int32_t H, int32_t W, int32_t gy,
+                                  int32_t gx, float *params, void *stream) {
+  NET_CHECK(net && params && gy >= 1 && gx >= 1 && gy <= H && gx <= W, "bad arguments");
+  hipLaunchKernelGGL(k_lattice_gather, dim3(blocks_of((int64_t)gy * gx, 256)), dim3(256), 0,
+                     (hipStream_t)stream, net, H, W, gy, gx, params);
+  NET_LAUNCHED("lattice_gather");
+  return CGH_OK;
+}
+
+cgh_status cgh_net_lattice_scatter(const float *net, const float *grads, int32_t H, int32_t W,
+                                   int32_t gy, int32_t gx, float *g_net, void *stream) {
+  NET_CHECK(net && grads && g_net && gy >= 1 && gx >= 1 && gy <= H && gx <= W, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_fill0, dim3(blocks_of((int64_t)H * W * 8, 256)), dim3(256), 0, s, g_net,
+                     (int64_t)H * W * 8);
+  hipLaunchKernelGGL(k_lattice_scatter, dim3(blocks_of((int64_t)gy * gx, 256)), dim3(256), 0, s,
+                     net, grads, H, W, gy, gx, g_net);
+  NET_LAUNCHED("lattice_scatter");
+  return CGH_OK;
+}
+
+}  // extern "C"

@@ -13,19 +13,23 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "cgh.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+NET_HEADER = os.path.join(ROOT, "include", "cgh_net.h")
+
+
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(cgh_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(cgh_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
     assert declared_functions() == sorted(binding.EXPORTS)
+    assert declared_functions(NET_HEADER) == sorted(binding.NET_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
     L = binding.lib()
-    for name in declared_functions():
+    for name in declared_functions() + declared_functions(NET_HEADER):
         assert hasattr(L, name), name
     assert L.cgh_abi_version() == 1
 
@@ -128,6 +132,26 @@ def test_null_arguments_are_rejected_without_device_work():
     c = cfg()
     out = ctypes.c_void_p()
     assert L.cgh_create(ctypes.byref(c), None, 0, None, ctypes.byref(out)) == 1
+
+
+def test_net_argument_checks_and_workspace_sizes():
+    """Host-side checks of the network entry points; no device work."""
+    L = binding.lib()
+    # 512 x 512, 32 -> 32: about 1024 pixels per split
+    ws = L.cgh_net_wgrad_workspace(512, 512, 32, 32)
+    assert ws == 256 * (32 * 9 * 32 + 32) * 4
+    assert L.cgh_net_wgrad_workspace(0, 5, 8, 32) == 0
+    # c1 not a multiple of 8, cout not a multiple of 32, missing outputs
+    assert L.cgh_net_conv3x3(16, 6, 0, None, 0, 4, 4, 16, None, 32, 0, 16, None, None) == 1
+    assert L.cgh_net_conv3x3(16, 8, 0, None, 0, 4, 4, 16, None, 48, 0, 16, None, None) == 1
+    assert L.cgh_net_conv3x3(16, 8, 0, None, 0, 4, 4, 16, None, 32, 0, None, None, None) == 1
+    # upsampled input with odd size; x2 given without channels
+    assert L.cgh_net_conv3x3(16, 8, 1, None, 0, 5, 4, 16, None, 32, 0, 16, None, None) == 1
+    assert L.cgh_net_conv3x3(16, 8, 0, 32, 0, 4, 4, 16, None, 32, 0, 16, None, None) == 1
+    # workspace too small
+    assert L.cgh_net_conv3x3_wgrad(16, 8, 0, None, 0, 64, 64, 16, 32, 16, None, 16, 8,
+                                   None) == 2
+    assert L.cgh_net_lattice_gather(16, 10, 10, 11, 3, 16, None) == 1
 
 
 def test_pack_unpack_layout_roundtrip():

@@ -1,0 +1,193 @@
+"""GPU parity of the learned initialiser's network kernels (include/cgh_net.h)
+against the FP64 oracle (oracle/unet.py), through the C ABI.  Inputs are BF16
+on both sides, so the two differ only by FP32 against FP64 sums: the bar is
+a relative L2 error of 1e-5 per output (FP32 accumulation over up to
+9 x 384 terms), except where a sum is itself rounded to BF16 (one BF16 ulp,
+2^-8 relative, at the elements where the two roundings differ)."""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import unet as U
+from paper_2511_15022_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def bf(shape, rng, scale=1.0):
+    """A BF16 device tensor and its exact FP64 copy."""
+    t = torch.from_numpy((rng.standard_normal(shape) * scale).astype(np.float32))
+    t = t.to(torch.bfloat16)
+    return t.cuda(), t.to(torch.float64).numpy()
+
+
+def P(t):
+    return None if t is None else t.data_ptr()
+
+
+def stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def check(st):
+    assert st == 0, binding.lib().cgh_last_error().decode()
+
+
+@pytest.mark.parametrize("case", [
+    dict(H=19, W=23, c1=8, c2=0, up=False, cout=32, relu=True),     # ragged tiles
+    dict(H=16, W=20, c1=32, c2=16, up=True, cout=64, relu=False),   # [up(x1), x2]
+    dict(H=7, W=9, c1=64, c2=0, up=False, cout=128, relu=True),     # 4 blocks of 32
+    dict(H=12, W=8, c1=256, c2=128, up=True, cout=128, relu=True),  # widest decoder input
+])
+def test_conv_forward_and_adjoints(case):
+    say("conv", case)
+    rng = np.random.default_rng(zlib.crc32(str(sorted(case.items())).encode()))
+    H, W, c1, c2, up, cout = case["H"], case["W"], case["c1"], case["c2"], case["up"], case["cout"]
+    h1, w1 = (H // 2, W // 2) if up else (H, W)
+    x1, x1n = bf((h1, w1, c1), rng)
+    x2, x2n = bf((H, W, c2), rng) if c2 else (None, None)
+    cin = c1 + c2
+    w, wn = bf((cout, 3, 3, cin), rng, 1.0 / np.sqrt(9 * cin))
+    b = torch.from_numpy(rng.standard_normal(cout).astype(np.float32)).cuda()
+    out32 = torch.empty((H, W, cout), dtype=torch.float32, device="cuda")
+    out16 = torch.empty((H, W, cout), dtype=torch.bfloat16, device="cuda")
+    L = binding.lib()
+    check(L.cgh_net_conv3x3(P(x1), c1, int(up), P(x2), c2, H, W, P(w), P(b), cout,
+                            int(case["relu"]), P(out32), P(out16), stream()))
+    xin = U.conv_input(x1n, x2n, up)
+    ref = U.conv3x3(xin, wn, b.cpu().numpy())
+    torch.cuda.synchronize()
+    e = rel(out32.cpu().numpy(), ref)
+    say("forward rel", e)
+    assert e <= TOL
+    r16 = U.bf16(U.relu(ref) if case["relu"] else ref)
+    g16 = out16.to(torch.float64).cpu().numpy()
+    # BF16 of the FP32 sum equals BF16 of the FP64 sum except at near-ties
+    assert np.mean(g16 != r16) < 1e-3
+    assert np.all(np.abs(g16 - r16) <= 2.0 ** -7 * np.abs(r16) + 1e-5 * np.abs(ref).max())
+    # input adjoint through the flipped weights (the convolution needs cin % 32 == 0)
+    gy, gyn = bf((H, W, cout), rng)
+    gx_ref, gw_ref, gb_ref = U.conv3x3_backward(xin, wn, gyn)
+    if cin % 32 == 0:
+        wt = torch.empty((cin, 3, 3, cout), dtype=torch.bfloat16, device="cuda")
+        check(L.cgh_net_flip_weights(P(w), cout, cin, P(wt), stream()))
+        gx = torch.empty((H, W, cin), dtype=torch.float32, device="cuda")
+        check(L.cgh_net_conv3x3(P(gy), cout, 0, None, 0, H, W, P(wt), None, cin, 0, P(gx), None,
+                                stream()))
+        torch.cuda.synchronize()
+        e = rel(gx.cpu().numpy(), gx_ref)
+        say("input adjoint rel", e)
+        assert e <= TOL
+        if up:
+            # the upsampled part goes back to half resolution, the skip part stays
+            g1 = torch.empty((h1, w1, c1), dtype=torch.float32, device="cuda")
+            check(L.cgh_net_up_adjoint(P(gx), H, W, cin, c1, P(g1), stream()))
+            torch.cuda.synchronize()
+            assert rel(g1.cpu().numpy(), U.up2_adjoint(gx_ref[:, :, :c1])) <= TOL
+    # weight and bias gradients
+    ws = L.cgh_net_wgrad_workspace(H, W, cin, cout)
+    scratch = torch.empty(ws // 4 + 4, dtype=torch.float32, device="cuda")
+    gw = torch.empty((cout, 3, 3, cin), dtype=torch.float32, device="cuda")
+    gb = torch.empty(cout, dtype=torch.float32, device="cuda")
+    check(L.cgh_net_conv3x3_wgrad(P(x1), c1, int(up), P(x2), c2, H, W, P(gy), cout, P(gw), P(gb),
+                                  P(scratch), ws, stream()))
+    torch.cuda.synchronize()
+    ew, eb = rel(gw.cpu().numpy(), gw_ref), rel(gb.cpu().numpy(), gb_ref)
+    say("weight / bias gradient rel", ew, eb)
+    assert ew <= TOL and eb <= TOL
+
+
+def test_wgrad_many_splits_is_deterministic():
+    """128 x 96 pixels: twelve splits of the pixel range; two runs bitwise equal."""
+    rng = np.random.default_rng(3)
+    H, W, c1, cout = 128, 96, 32, 64
+    x1, x1n = bf((H, W, c1), rng)
+    gy, gyn = bf((H, W, cout), rng)
+    L = binding.lib()
+    ws = L.cgh_net_wgrad_workspace(H, W, c1, cout)
+    scratch = torch.empty(ws // 4 + 4, dtype=torch.float32, device="cuda")
+    outs = []
+    for _ in range(2):
+        gw = torch.empty((cout, 3, 3, c1), dtype=torch.float32, device="cuda")
+        gb = torch.empty(cout, dtype=torch.float32, device="cuda")
+        check(L.cgh_net_conv3x3_wgrad(P(x1), c1, 0, None, 0, H, W, P(gy), cout, P(gw), P(gb),
+                                      P(scratch), ws, stream()))
+        torch.cuda.synchronize()
+        outs.append((gw.cpu().numpy(), gb.cpu().numpy()))
+    _, gw_ref, gb_ref = U.conv3x3_backward(x1n, np.zeros((cout, 3, 3, c1)), gyn)
+    assert rel(outs[0][0], gw_ref) <= TOL and rel(outs[0][1], gb_ref) <= TOL
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_glue_kernels():
+    rng = np.random.default_rng(4)
+    L = binding.lib()
+    H, W, C = 10, 14, 24
+    x, xn = bf((H, W, C), rng)
+    p = torch.empty((H // 2, W // 2, C), dtype=torch.bfloat16, device="cuda")
+    check(L.cgh_net_pool2(P(x), H, W, C, P(p), stream()))
+    g = torch.from_numpy(rng.standard_normal((H, W, 40)).astype(np.float32)).cuda()
+    up = torch.empty((H // 2, W // 2, C), dtype=torch.float32, device="cuda")
+    check(L.cgh_net_up_adjoint(P(g), H, W, 40, C, P(up), stream()))
+    gp = torch.from_numpy(rng.standard_normal((H // 2, W // 2, C)).astype(np.float32)).cuda()
+    comb = torch.empty((H, W, C), dtype=torch.float32, device="cuda")
+    check(L.cgh_net_grad_combine(P(gp), P(g), 40, 16, H, W, C, P(comb), stream()))
+    a, an = bf((H, W, C), rng)
+    gf = torch.from_numpy(rng.standard_normal((H, W, C)).astype(np.float32)).cuda()
+    rg = torch.empty((H, W, C), dtype=torch.bfloat16, device="cuda")
+    check(L.cgh_net_relu_grad(P(gf), P(a), H * W * C, P(rg), stream()))
+    cast = torch.empty((H, W, C), dtype=torch.bfloat16, device="cuda")
+    check(L.cgh_net_cast_bf16(P(gf), H * W * C, P(cast), stream()))
+    torch.cuda.synchronize()
+    # BF16 of an FP32 four-term sum against BF16 of the exact mean: equal but
+    # for rare near-ties, and then one BF16 ulp apart
+    pg, pr = p.to(torch.float64).cpu().numpy(), U.bf16(U.pool2(xn))
+    assert np.mean(pg != pr) < 1e-3
+    assert np.all(np.abs(pg - pr) <= 2.0 ** -7 * np.abs(pr) + 1e-30)
+    gn = g.cpu().numpy().astype(np.float64)
+    assert rel(up.cpu().numpy(), U.up2_adjoint(gn[:, :, :C])) <= 1e-7
+    assert rel(comb.cpu().numpy(), U.pool2_adjoint(gp.cpu().numpy().astype(np.float64))
+               + gn[:, :, 16:16 + C]) <= 1e-7
+    gfn = gf.cpu().numpy().astype(np.float64)
+    assert np.array_equal(rg.to(torch.float64).cpu().numpy(), U.bf16(gfn * (an > 0)))
+    assert np.array_equal(cast.to(torch.float64).cpu().numpy(), U.bf16(gfn))
+    # torch's own round to nearest even agrees on the cast
+    assert torch.equal(cast.cpu(), gf.cpu().to(torch.bfloat16))
+
+
+def test_lattice_gather_and_scatter():
+    rng = np.random.default_rng(5)
+    H, W, gy, gx = 64, 96, 29, 43
+    out = (0.4 * rng.standard_normal((H, W, 8))).astype(np.float32)
+    out[::7, ::5, 0] = 200.0   # some means pushed past the canvas: the clip
+    n = gy * gx
+    L = binding.lib()
+    net = torch.from_numpy(out).cuda()
+    params = torch.empty(8 * n, dtype=torch.float32, device="cuda")
+    check(L.cgh_net_lattice_gather(P(net), H, W, gy, gx, P(params), stream()))
+    g = torch.from_numpy(rng.standard_normal(8 * n).astype(np.float32)).cuda()
+    gnet = torch.full((H, W, 8), 7.0, dtype=torch.float32, device="cuda")
+    check(L.cgh_net_lattice_scatter(P(net), P(g), H, W, gy, gx, P(gnet), stream()))
+    torch.cuda.synchronize()
+    ref = U.gather(out, H, W, gy, gx)
+    got = binding.unpack(params.cpu(), n, 1)
+    for k in binding.PARAM_KEYS:
+        assert rel(got[k].numpy(), ref[k].reshape(got[k].shape)) <= 1e-7, k
+    gd = binding.unpack(g.cpu(), n, 1)
+    gref = U.gather_adjoint({k: gd[k].numpy().astype(np.float64) for k in gd}, out, H, W, gy, gx)
+    assert rel(gnet.cpu().numpy(), gref) <= 1e-7
