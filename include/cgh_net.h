@@ -34,7 +34,7 @@ typedef uint16_t cgh_bf16; /* the upper 16 bits of an IEEE binary32 */
 /* 3x3 convolution of in = [up(x1) if up else x1, x2] (channels concatenated,
  * x1 first; up repeats each pixel of x1, which is then H/2 x W/2, over a 2x2
  * block).  x1: c1 channels, x2: c2 channels (x2 may be NULL with c2 = 0);
- * c1, c2 multiples of 8; cout a multiple of 32; H, W >= 1 (even when up).
+ * c1, c2 multiples of 8; cout a multiple of 8; H, W >= 1 (even when up).
  * w: [cout][3][3][c1 + c2] BF16; bias: [cout] FP32 or NULL.
  * out32 (FP32 [H][W][cout], may be NULL) receives the sum plus bias; out16
  * (BF16, may be NULL) receives the same, after ReLU when relu != 0.  With
@@ -89,7 +89,7 @@ cgh_status cgh_net_up_adjoint(const float *g, int32_t H, int32_t W, int32_t stri
 cgh_status cgh_net_grad_combine(const float *gp, const float *gs, int32_t stride, int32_t off,
                                 int32_t H, int32_t W, int32_t C, float *out, void *stream);
 
-/* Lattice of gy x gx Gaussians on an H x W canvas (C = 1): Gaussian i gy + ...
+/* Lattice of gy x gx Gaussians on an H x W canvas (C = 1): Gaussian k = i gx + j
  * sits at ((j + 1/2) W / gx, (i + 1/2) H / gy) and reads the network output
  * `net` (FP32 [H][W][8]) at the pixel containing that point: channels 0, 1 move
  * the mean (pixels, clipped to (1e-3, size - 1e-3)), 2, 3 are log-scales minus
@@ -104,6 +104,14 @@ cgh_status cgh_net_lattice_gather(const float *net, int32_t H, int32_t W, int32_
  * zero where no Gaussian reads) from dL/dparams (flat layout). */
 cgh_status cgh_net_lattice_scatter(const float *net, const float *grads, int32_t H, int32_t W,
                                    int32_t gy, int32_t gx, float *g_net, void *stream);
+
+/* The network's input.  cgh_net_sqrt_field: field[i] = sqrt(max(T[i], 0)) + 0 j
+ * (complex64, count = H W), the amplitude whose propagation by -z (cgh_propagate
+ * on a context with that distance) gives `back`.  cgh_net_features: out (BF16
+ * [H][W][8]) = [T, sqrt(T), Re back, Im back, |back|, 0, 0, 0] per pixel. */
+cgh_status cgh_net_sqrt_field(const float *target, int64_t count, cgh_c64 *field, void *stream);
+cgh_status cgh_net_features(const float *target, const cgh_c64 *back, int64_t count,
+                            cgh_bf16 *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -76,8 +76,10 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1
       const v4s a = valid ? conv_in4(x1, c1, up, x2, c2, H, W, sy, sx, ci + kq) : v4s{0, 0, 0, 0};
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const int co = co0 + 32 * b + (lane & 31);
-        const v4s bb = *reinterpret_cast<const v4s *>(w + ((size_t)co * 9 + t) * cin + ci + kq);
+        const int co = co0 + 32 * b + (lane & 31);  // channels past cout: zero weights
+        const v4s bb = co < cout
+                           ? *reinterpret_cast<const v4s *>(w + ((size_t)co * 9 + t) * cin + ci + kq)
+                           : v4s{0, 0, 0, 0};
         acc[b] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc[b], 0, 0, 0);
       }
     }
@@ -85,11 +87,11 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int co = co0 + 32 * b + (lane & 31);
-    const float bv = bias ? bias[co] : 0.f;
+    const float bv = (bias && co < cout) ? bias[co] : 0.f;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int q = blockIdx.x * 128 + wave * 32 + 8 * (v >> 2) + kq + (v & 3);
-      if (q < P) {
+      if (q < P && co < cout) {
         const float s = acc[b][v] + bv;
         if (out32) out32[(size_t)q * cout + co] = s;
         if (out16) out16[(size_t)q * cout + co] = to_bf16(relu ? fmaxf(s, 0.f) : s);
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(
       const int p = pb + kq + i;
       uint16_t av = 0, bv = 0;
       if (p < p1) {
-        av = gy[(size_t)p * cout + co];
+        av = co < cout ? gy[(size_t)p * cout + co] : (uint16_t)0;
         const int py = p / W, px = p - py * W;
         const int sy = py + ky - 1, sx = px + kx - 1;
         if (nv && sy >= 0 && sy < H && sx >= 0 && sx < W) {
@@ -153,12 +155,12 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int r = cb * 32 + 8 * (v >> 2) + kq + (v & 3);
-    if (nv) dst[(size_t)r * N + n] = acc[v];
+    if (nv && r < cout) dst[(size_t)r * N + n] = acc[v];
   }
   if (nb == 0) {
     // lanes l and l + 32 hold the two halves of the pixels of channel co
     bsum += __shfl_down(bsum, 32, 64);
-    if (lane < 32) part_b[(size_t)s * cout + co] = bsum;
+    if (lane < 32 && co < cout) part_b[(size_t)s * cout + co] = bsum;
   }
 }
 
@@ -302,6 +304,26 @@ __global__ void k_lattice_scatter(const float *__restrict__ net, const float *__
   d[7] = g[7 * (size_t)n + k];
 }
 
+__global__ void k_sqrt_field(const float *__restrict__ t, int64_t n, float2 *__restrict__ f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = make_float2(sqrtf(fmaxf(t[i], 0.f)), 0.f);
+}
+
+__global__ void k_features(const float *__restrict__ t, const float2 *__restrict__ b, int64_t n,
+                           uint16_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float v = t[i];
+  const float2 u = b[i];
+  uint16_t *o = out + i * 8;
+  o[0] = to_bf16(v);
+  o[1] = to_bf16(sqrtf(fmaxf(v, 0.f)));
+  o[2] = to_bf16(u.x);
+  o[3] = to_bf16(u.y);
+  o[4] = to_bf16(sqrtf(u.x * u.x + u.y * u.y));
+  o[5] = o[6] = o[7] = 0;
+}
+
 unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 int wgrad_chunk(int P) {
@@ -344,11 +366,11 @@ cgh_status cgh_net_conv3x3(const cgh_bf16 *x1, int32_t c1, int32_t up, const cgh
                            cgh_bf16 *out16, void *stream) {
   const cgh_status st = check_conv_shape(x1, c1, up, x2, c2, H, W);
   if (st != CGH_OK) return st;
-  NET_CHECK(w && cout > 0 && cout % 32 == 0, "w NULL or cout = %d not a multiple of 32", cout);
+  NET_CHECK(w && cout > 0 && cout % 8 == 0, "w NULL or cout = %d not a multiple of 8", cout);
   NET_CHECK(out32 || out16, "no output");
   NET_CHECK(al16(w), "w must be 16-byte aligned");
   const int nb = cout % 128 == 0 ? 4 : (cout % 64 == 0 ? 2 : 1);
-  const dim3 grid(blocks_of((int64_t)H * W, 128), cout / (32 * nb));
+  const dim3 grid(blocks_of((int64_t)H * W, 128), (cout + 32 * nb - 1) / (32 * nb));
   hipStream_t s = (hipStream_t)stream;
 #define NET_CONV(NB)                                                                       \
   hipLaunchKernelGGL(k_conv3x3<NB>, grid, dim3(256), 0, s, x1, c1, up, x2, c2, H, W, w, bias, \
@@ -382,7 +404,7 @@ cgh_status cgh_net_conv3x3_wgrad(const cgh_bf16 *x1, int32_t c1, int32_t up, con
                                  size_t workspace_bytes, void *stream) {
   const cgh_status st = check_conv_shape(x1, c1, up, x2, c2, H, W);
   if (st != CGH_OK) return st;
-  NET_CHECK(gy && gw && cout > 0 && cout % 32 == 0, "gy/gw NULL or cout = %d not a multiple of 32",
+  NET_CHECK(gy && gw && cout > 0 && cout % 8 == 0, "gy/gw NULL or cout = %d not a multiple of 8",
             cout);
   const int cin = c1 + c2, P = H * W, chunk = wgrad_chunk(P), splits = (P + chunk - 1) / chunk;
   const size_t need = cgh_net_wgrad_workspace(H, W, cin, cout);
@@ -392,7 +414,7 @@ cgh_status cgh_net_conv3x3_wgrad(const cgh_bf16 *x1, int32_t c1, int32_t up, con
   const int64_t len = (int64_t)cout * 9 * cin;
   float *part = (float *)workspace, *part_b = part + (size_t)splits * len;
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid((9 * cin + 31) / 32, cout / 32, splits);
+  const dim3 grid((9 * cin + 31) / 32, (cout + 31) / 32, splits);
   hipLaunchKernelGGL(k_conv3x3_wgrad, grid, dim3(64), 0, s, x1, c1, up, x2, c2, H, W, gy, cout,
                      chunk, part, part_b);
   NET_LAUNCHED("conv3x3_wgrad");
@@ -469,6 +491,24 @@ cgh_status cgh_net_lattice_scatter(const float *net, const float *grads, int32_t
   hipLaunchKernelGGL(k_lattice_scatter, dim3(blocks_of((int64_t)gy * gx, 256)), dim3(256), 0, s,
                      net, grads, H, W, gy, gx, g_net);
   NET_LAUNCHED("lattice_scatter");
+  return CGH_OK;
+}
+
+cgh_status cgh_net_sqrt_field(const float *target, int64_t count, cgh_c64 *field,
+                              void *stream) {
+  NET_CHECK(target && field && count > 0, "bad arguments");
+  hipLaunchKernelGGL(k_sqrt_field, dim3(blocks_of(count, 256)), dim3(256), 0,
+                     (hipStream_t)stream, target, count, reinterpret_cast<float2 *>(field));
+  NET_LAUNCHED("sqrt_field");
+  return CGH_OK;
+}
+
+cgh_status cgh_net_features(const float *target, const cgh_c64 *back, int64_t count,
+                            cgh_bf16 *out, void *stream) {
+  NET_CHECK(target && back && out && count > 0, "bad arguments");
+  hipLaunchKernelGGL(k_features, dim3(blocks_of(count, 256)), dim3(256), 0, (hipStream_t)stream,
+                     target, reinterpret_cast<const float2 *>(back), count, out);
+  NET_LAUNCHED("features");
   return CGH_OK;
 }
 

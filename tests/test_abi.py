@@ -141,9 +141,9 @@ def test_net_argument_checks_and_workspace_sizes():
     ws = L.cgh_net_wgrad_workspace(512, 512, 32, 32)
     assert ws == 256 * (32 * 9 * 32 + 32) * 4
     assert L.cgh_net_wgrad_workspace(0, 5, 8, 32) == 0
-    # c1 not a multiple of 8, cout not a multiple of 32, missing outputs
+    # c1 not a multiple of 8, cout not a multiple of 8, missing outputs
     assert L.cgh_net_conv3x3(16, 6, 0, None, 0, 4, 4, 16, None, 32, 0, 16, None, None) == 1
-    assert L.cgh_net_conv3x3(16, 8, 0, None, 0, 4, 4, 16, None, 48, 0, 16, None, None) == 1
+    assert L.cgh_net_conv3x3(16, 8, 0, None, 0, 4, 4, 16, None, 12, 0, 16, None, None) == 1
     assert L.cgh_net_conv3x3(16, 8, 0, None, 0, 4, 4, 16, None, 32, 0, None, None, None) == 1
     # upsampled input with odd size; x2 given without channels
     assert L.cgh_net_conv3x3(16, 8, 1, None, 0, 5, 4, 16, None, 32, 0, 16, None, None) == 1

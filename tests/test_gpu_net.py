@@ -53,6 +53,7 @@ def check(st):
     dict(H=16, W=20, c1=32, c2=16, up=True, cout=64, relu=False),   # [up(x1), x2]
     dict(H=7, W=9, c1=64, c2=0, up=False, cout=128, relu=True),     # 4 blocks of 32
     dict(H=12, W=8, c1=256, c2=128, up=True, cout=128, relu=True),  # widest decoder input
+    dict(H=9, W=13, c1=32, c2=0, up=False, cout=8, relu=False),     # the head: 8 of 32 channels
 ])
 def test_conv_forward_and_adjoints(case):
     say("conv", case)
@@ -191,3 +192,146 @@ def test_lattice_gather_and_scatter():
     gd = binding.unpack(g.cpu(), n, 1)
     gref = U.gather_adjoint({k: gd[k].numpy().astype(np.float64) for k in gd}, out, H, W, gy, gx)
     assert rel(gnet.cpu().numpy(), gref) <= 1e-7
+
+
+# ---------------------------------------------------------------------------
+# The whole network and the learned initialiser against the oracle.  Every
+# activation is stored in BF16, and where an FP32 sum and the FP64 sum of the
+# same terms fall on either side of a BF16 rounding tie the two stored values
+# differ by one BF16 ulp (2^-7 relative); that happens to ~0.1 % of the
+# elements of a layer and compounds over the 15 layers.  So the wiring is
+# checked layer by layer on the GPU's own inputs (exact up to those flips),
+# the weight gradients on the GPU's own activations, and the end-to-end output
+# against the fully independent oracle run at a bar that allows the
+# compounding (2e-2 relative L2).
+# ---------------------------------------------------------------------------
+LAYER_FLIPS = 2e-3
+GRAD_TOL_NET = 5e-3
+E2E_TOL = 2e-2
+
+
+def gpu_cache(net, x16):
+    """The oracle's cache built from the GPU's stored activations: the exact
+    inputs each GPU convolution read, and its stored output for the ReLU test."""
+    A = {k: v.to(torch.float64).cpu().numpy() for k, v in net.act.items()}
+    Pl = {k: v.to(torch.float64).cpu().numpy() for k, v in net.pooled.items()}
+    x = x16.to(torch.float64).cpu().numpy()
+    nl = len(net.widths)
+    cache = {"in": {}, "pre": {}}
+    for l in range(nl):
+        cache["in"][f"enc{l}a"] = (x if l == 0 else Pl[l - 1], None, False)
+        cache["in"][f"enc{l}b"] = (A[f"enc{l}a"], None, False)
+    for l in range(nl - 2, -1, -1):
+        below = A[f"dec{l + 1}b"] if l + 1 < nl - 1 else A[f"enc{nl - 1}b"]
+        cache["in"][f"dec{l}a"] = (below, A[f"enc{l}b"], True)
+        cache["in"][f"dec{l}b"] = (A[f"dec{l}a"], None, False)
+    cache["in"]["head"] = (A["dec0b"], None, False)
+    for k, v in A.items():
+        cache["pre"][k] = v
+    return cache, A, Pl
+
+
+def test_unet_forward_backward_matches_oracle():
+    from paper_2511_15022_amd import learned_init as LI
+    H, W = 32, 48
+    say("unet", H, W)
+    rng = np.random.default_rng(21)
+    net = LI.UNet(H, W, seed=22)
+    wd = net.get_weights()
+    for k in wd:  # nonzero biases exercise the bias path
+        if k.endswith(".b"):
+            wd[k] = (0.05 * rng.standard_normal(wd[k].shape)).astype(np.float32)
+    net.set_weights(wd)
+    x16, xn = bf((H, W, 8), rng)
+    out = net.forward(x16).clone()
+    g = (rng.standard_normal((H, W, 8))).astype(np.float32)
+    net.backward(torch.from_numpy(g).cuda(), x16)
+    torch.cuda.synchronize()
+    cache, A, Pl = gpu_cache(net, x16)
+    # 1. layer by layer on the GPU's own inputs
+    for name, cu, cs, co, relu in net.layers:
+        h, skip, up = cache["in"][name]
+        z = U.conv3x3(U.conv_input(h, skip, up), U.bf16(wd[name]), wd[name + ".b"])
+        if name == "head":
+            e = rel(out.cpu().numpy(), z)
+            assert e <= TOL, (name, e)
+            continue
+        ref16, got = U.bf16(U.relu(z)), A[name]
+        frac = np.mean(ref16 != got)
+        assert frac <= LAYER_FLIPS, (name, frac)
+        assert np.all(np.abs(ref16 - got) <= 2.0 ** -7 * np.abs(ref16) + 1e-6 * np.abs(z).max()), name
+    for l, p in Pl.items():
+        src = A[f"enc{l}b"]
+        pr = U.bf16(U.pool2(src))
+        assert np.mean(pr != p) <= LAYER_FLIPS
+    # 2. weight gradients on the GPU's activations
+    arch = U.architecture()
+    grads = U.backward(arch, wd, cache, g.astype(np.float64))
+    host = net.grad.cpu().numpy()
+    worst = (0.0, "")
+    for name, cu, cs, co, _ in net.layers:
+        o, n = net.off[name]
+        worst = max(worst, (rel(host[o:o + n].reshape(co, 3, 3, cu + cs), grads[name]), name))
+        o, n = net.off[name + ".b"]
+        worst = max(worst, (rel(host[o:o + n], grads[name + ".b"]), name + ".b"))
+    say("worst gradient rel (GPU activations)", worst)
+    assert worst[0] <= GRAD_TOL_NET
+    # 3. end to end against the independent oracle run
+    ref, _ = U.forward(arch, wd, xn)
+    e = rel(out.cpu().numpy(), ref)
+    say("end-to-end output rel", e)
+    assert e <= E2E_TOL
+
+
+def test_initializer_prediction_and_training_gradients():
+    """Features (the library's back-propagation of sqrt(T)), network, lattice
+    gather, rendering, MSE backward, scatter and network backward, against the
+    oracle's composition of the same steps."""
+    from oracle import oracle as O
+    from paper_2511_15022_amd import learned_init as LI, synth
+    H, W, pitch, lam, z = 32, 48, 8e-6, 515e-9, 2e-3
+    init = LI.Initializer(H, W, pitch, lam, z, pad=(64, 96), seed=31)
+    T = synth.target(32, 1, H, W)[0, 0]
+    Tg = torch.from_numpy(T).cuda()
+    params = init.predict(Tg).clone()
+    x16 = init.x16.clone()
+    torch.cuda.synchronize()
+    # the oracle's features: sqrt(T) propagated by -z, rounded to BF16
+    back = O.propagate(np.sqrt(np.maximum(T, 0)).astype(np.complex128)[None],
+                       O.Optics(H, W, 1, 64, 96, pitch, [lam], [-z]))[0, 0]
+    feats = np.zeros((H, W, 8))
+    feats[..., 0], feats[..., 1] = T, np.sqrt(np.maximum(T, 0))
+    feats[..., 2], feats[..., 3], feats[..., 4] = back.real, back.imag, np.abs(back)
+    fr = U.bf16(feats)
+    fg = x16.to(torch.float64).cpu().numpy()
+    # BF16 of the FP32 and FP64 back-propagations: equal but for near-ties
+    assert np.mean(fg != fr) < 2e-3 and rel(fg, fr) < 2e-3
+    wd = init.net.get_weights()
+    arch = U.architecture()
+    out = init.net.out.cpu().numpy().astype(np.float64)
+    cache, _, _ = gpu_cache(init.net, x16)
+    # the lattice gather of the GPU's network output is exact up to FP32 rounding
+    ref = U.gather(out, H, W, init.gy, init.gx)
+    ref = U.gather(out, H, W, init.gy, init.gx)
+    got = binding.unpack(params.cpu(), init.n, 1)
+    for k in binding.PARAM_KEYS:
+        e = rel(got[k].numpy(), np.asarray(ref[k]).reshape(got[k].shape))
+        assert e <= 1e-6, (k, e)
+    # one training step: gradients of the network's weights
+    init.train_step(Tg, lr=0.0)
+    torch.cuda.synchronize()
+    opt = O.Optics(H, W, 1, 64, 96, pitch, [lam], [z])
+    p32 = {k: np.asarray(got[k].numpy(), np.float32) for k in got}
+    fb = O.forward_backward(p32, T[None, None], opt)
+    g_out = U.gather_adjoint({k: np.asarray(v, np.float64) for k, v in fb["grads"].items()},
+                             out, H, W, init.gy, init.gx)
+    grads = U.backward(arch, wd, cache, g_out)
+    host = init.net.grad.cpu().numpy()
+    worst = 0.0
+    for name, cu, cs, co, _ in init.net.layers:
+        o, n = init.net.off[name]
+        worst = max(worst, rel(host[o:o + n].reshape(co, 3, 3, cu + cs), grads[name]))
+    say("initializer: worst weight-gradient rel", worst, "loss", init.loss.cpu().numpy(),
+        fb["loss"])
+    assert abs(init.loss.cpu().numpy()[0] - fb["loss"]) <= 1e-4 * fb["loss"]
+    assert worst <= GRAD_TOL_NET
