@@ -223,11 +223,13 @@ def backward(arch, W, cache, g_out, q=bf16):
 
 # ---------------------------------------------------------------------------
 # Gaussian lattice: Gaussian (i, j) of a G_y x G_x lattice sits at
-# ((j + 1/2) W / G_x, (i + 1/2) H / G_y) and reads the network output at the
-# pixel containing that point.  Output channels: 0, 1 offset of the mean
-# (pixels), 2, 3 log-scale minus ln 2, 4 rotation, 5 amplitude minus 1/2,
-# 6 phase, 7 opacity logit plus 1/2 (so that zero outputs give the plain
-# initialisation's scale, amplitude and opacity).
+# ((j + 1/2) W / G_x, (i + 1/2) H / G_y) and reads the network output (8 C
+# channels, one block of 8 per colour channel) at the pixel containing that
+# point.  Block 0 carries the shared geometry: 0, 1 offset of the mean
+# (pixels), 2, 3 log-scale minus ln 2, 4 rotation, 7 opacity logit plus 1/2;
+# block c carries colour c: 8 c + 5 amplitude minus 1/2, 8 c + 6 phase (so
+# that zero outputs give the plain initialisation's scale, amplitude and
+# opacity).
 # ---------------------------------------------------------------------------
 LOG_SCALE0, AMP0, OPACITY0 = np.log(2.0), 0.5, -0.5
 
@@ -238,27 +240,27 @@ def lattice(H, W, gy, gx):
     return np.meshgrid(cy, cx, indexing="ij")
 
 
-def gather(out, H, W, gy, gx):
-    """Network output [H][W][8] -> the library's parameter dict (C = 1)."""
+def gather(out, H, W, gy, gx, C=1):
+    """Network output [H][W][8 C] -> the library's parameter dict."""
     cy, cx = lattice(H, W, gy, gx)
     iy, ix = np.floor(cy).astype(int), np.floor(cx).astype(int)
-    o = np.asarray(out, np.float64)[iy, ix].reshape(-1, 8)
+    o = np.asarray(out, np.float64)[iy, ix].reshape(-1, 8 * C)
     mx = np.clip(cx.reshape(-1) + o[:, 0], 1e-3, W - 1e-3)
     my = np.clip(cy.reshape(-1) + o[:, 1], 1e-3, H - 1e-3)
     return {"mean_pre": np.stack([np.arctanh(2 * mx / W - 1), np.arctanh(2 * my / H - 1)], 1),
             "log_scale": o[:, 2:4] + LOG_SCALE0, "rotation": o[:, 4],
-            "amplitude": (o[:, 5] + AMP0)[:, None], "phase": o[:, 6][:, None],
+            "amplitude": o[:, 5::8] + AMP0, "phase": o[:, 6::8],
             "opacity_pre": o[:, 7] + OPACITY0}
 
 
-def gather_adjoint(grads, out, H, W, gy, gx):
-    """dL/d(network output) [H][W][8] from dL/d(parameters)."""
+def gather_adjoint(grads, out, H, W, gy, gx, C=1):
+    """dL/d(network output) [H][W][8 C] from dL/d(parameters)."""
     cy, cx = lattice(H, W, gy, gx)
     iy, ix = np.floor(cy).astype(int).reshape(-1), np.floor(cx).astype(int).reshape(-1)
     o = np.asarray(out, np.float64)[iy, ix]
     mx = cx.reshape(-1) + o[:, 0]
     my = cy.reshape(-1) + o[:, 1]
-    g = np.zeros((H, W, 8))
+    g = np.zeros((H, W, 8 * C))
     inx = (mx > 1e-3) & (mx < W - 1e-3)
     iny = (my > 1e-3) & (my < H - 1e-3)
     # d atanh(2m/W - 1)/dm = (2/W) / (1 - (2m/W - 1)^2)
@@ -268,7 +270,10 @@ def gather_adjoint(grads, out, H, W, gy, gx):
     g[iy, ix, 1] = np.where(iny, gm[:, 1] * (2.0 / H) / (1 - uy * uy), 0.0)
     g[iy, ix, 2:4] = grads["log_scale"]
     g[iy, ix, 4] = grads["rotation"]
-    g[iy, ix, 5] = np.asarray(grads["amplitude"]).reshape(-1)
-    g[iy, ix, 6] = np.asarray(grads["phase"]).reshape(-1)
     g[iy, ix, 7] = grads["opacity_pre"]
+    amp = np.asarray(grads["amplitude"]).reshape(-1, C)
+    ph = np.asarray(grads["phase"]).reshape(-1, C)
+    for c in range(C):
+        g[iy, ix, 8 * c + 5] = amp[:, c]
+        g[iy, ix, 8 * c + 6] = ph[:, c]
     return g

@@ -110,17 +110,18 @@ def test_network_backward_matches_finite_differences():
     assert checked == 27
 
 
-def test_gather_adjoint_matches_finite_differences():
+@pytest.mark.parametrize("C", [1, 3])
+def test_gather_adjoint_matches_finite_differences(C):
     H, W, gy, gx = 20, 30, 9, 13
     rng = np.random.default_rng(8)
-    out = 0.3 * rng.standard_normal((H, W, 8))
+    out = 0.3 * rng.standard_normal((H, W, 8 * C))
     gp = {"mean_pre": rng.standard_normal((gy * gx, 2)), "log_scale": rng.standard_normal((gy * gx, 2)),
-          "rotation": rng.standard_normal(gy * gx), "amplitude": rng.standard_normal((gy * gx, 1)),
-          "phase": rng.standard_normal((gy * gx, 1)), "opacity_pre": rng.standard_normal(gy * gx)}
-    g = U.gather_adjoint(gp, out, H, W, gy, gx)
+          "rotation": rng.standard_normal(gy * gx), "amplitude": rng.standard_normal((gy * gx, C)),
+          "phase": rng.standard_normal((gy * gx, C)), "opacity_pre": rng.standard_normal(gy * gx)}
+    g = U.gather_adjoint(gp, out, H, W, gy, gx, C)
 
     def f(o):
-        p = U.gather(o, H, W, gy, gx)
+        p = U.gather(o, H, W, gy, gx, C)
         return sum(np.sum(np.asarray(p[k]) * gp[k]) for k in gp)
 
     cy, cx = U.lattice(H, W, gy, gx)
@@ -128,13 +129,22 @@ def test_gather_adjoint_matches_finite_differences():
     # every lattice point reads its own pixel, and no two share one
     assert len(set(zip(iy, ix))) == gy * gx
     for t in rng.choice(gy * gx, 6, replace=False):
-        for ch in range(8):
+        for ch in range(8 * C):
             o1, o2 = out.copy(), out.copy()
             o1[iy[t], ix[t], ch] += 1e-6
             o2[iy[t], ix[t], ch] -= 1e-6
             fd = (f(o1) - f(o2)) / 2e-6
             assert abs(fd - g[iy[t], ix[t], ch]) < 1e-5 * max(1.0, abs(fd))
-    # pixels no lattice point reads get no gradient
+    # pixels no lattice point reads get no gradient, nor do the unused
+    # channels of the colour blocks after the first
     mask = np.ones((H, W), bool)
     mask[iy, ix] = False
     assert np.all(g[mask] == 0)
+    for c in range(1, C):
+        for k in (0, 1, 2, 3, 4, 7):
+            assert np.all(g[:, :, 8 * c + k] == 0)
+    # C = 1 reads channels 5 and 6 as the amplitude and phase
+    p1 = U.gather(out, H, W, gy, gx, C)
+    assert np.allclose(np.asarray(p1["amplitude"])[:, C - 1],
+                       out[np.floor(cy).astype(int), np.floor(cx).astype(int)][..., 8 * (C - 1) + 5]
+                       .reshape(-1) + 0.5)
