@@ -89,28 +89,32 @@ cgh_status cgh_net_up_adjoint(const float *g, int32_t H, int32_t W, int32_t stri
 cgh_status cgh_net_grad_combine(const float *gp, const float *gs, int32_t stride, int32_t off,
                                 int32_t H, int32_t W, int32_t C, float *out, void *stream);
 
-/* Lattice of gy x gx Gaussians on an H x W canvas (C = 1): Gaussian k = i gx + j
- * sits at ((j + 1/2) W / gx, (i + 1/2) H / gy) and reads the network output
- * `net` (FP32 [H][W][8]) at the pixel containing that point: channels 0, 1 move
- * the mean (pixels, clipped to (1e-3, size - 1e-3)), 2, 3 are log-scales minus
- * ln 2, 4 the rotation, 5 the amplitude minus 1/2, 6 the phase, 7 the opacity
- * logit plus 1/2.  params: the library's flat layout (cgh.h) for n = gy gx,
- * C = 1.  Computed in FP64.  Requires gy <= H and gx <= W (one pixel per
- * Gaussian). */
+/* Lattice of gy x gx Gaussians on an H x W canvas with C colour channels:
+ * Gaussian k = i gx + j sits at ((j + 1/2) W / gx, (i + 1/2) H / gy) and reads
+ * the network output `net` (FP32 [H][W][8 C], one block of 8 per colour) at
+ * the pixel containing that point.  Block 0 holds the shared geometry:
+ * channels 0, 1 move the mean (pixels, clipped to (1e-3, size - 1e-3)), 2, 3
+ * are log-scales minus ln 2, 4 the rotation, 7 the opacity logit plus 1/2;
+ * block c holds colour c: 8 c + 5 the amplitude minus 1/2, 8 c + 6 the phase.
+ * params: the library's flat layout (cgh.h) for n = gy gx.  Computed in FP64.
+ * Requires gy <= H and gx <= W (one pixel per Gaussian), 1 <= C <= 4. */
 cgh_status cgh_net_lattice_gather(const float *net, int32_t H, int32_t W, int32_t gy,
-                                  int32_t gx, float *params, void *stream);
+                                  int32_t gx, int32_t C, float *params, void *stream);
 
-/* Adjoint of cgh_net_lattice_gather: g_net (FP32 [H][W][8], overwritten,
+/* Adjoint of cgh_net_lattice_gather: g_net (FP32 [H][W][8 C], overwritten,
  * zero where no Gaussian reads) from dL/dparams (flat layout). */
 cgh_status cgh_net_lattice_scatter(const float *net, const float *grads, int32_t H, int32_t W,
-                                   int32_t gy, int32_t gx, float *g_net, void *stream);
+                                   int32_t gy, int32_t gx, int32_t C, float *g_net,
+                                   void *stream);
 
 /* The network's input.  cgh_net_sqrt_field: field[i] = sqrt(max(T[i], 0)) + 0 j
- * (complex64, count = H W), the amplitude whose propagation by -z (cgh_propagate
- * on a context with that distance) gives `back`.  cgh_net_features: out (BF16
- * [H][W][8]) = [T, sqrt(T), Re back, Im back, |back|, 0, 0, 0] per pixel. */
+ * (complex64, `count` elements), the amplitude whose propagation by -z
+ * (cgh_propagate on a context with that distance) gives `back`.
+ * cgh_net_features: target and back planar [C][count] (count = H W); out (BF16
+ * [H][W][8 C]) holds, in block c of each pixel, [T, sqrt(T), Re back, Im back,
+ * |back|, 0, 0, 0] of colour c. */
 cgh_status cgh_net_sqrt_field(const float *target, int64_t count, cgh_c64 *field, void *stream);
-cgh_status cgh_net_features(const float *target, const cgh_c64 *back, int64_t count,
+cgh_status cgh_net_features(const float *target, const cgh_c64 *back, int64_t count, int32_t C,
                             cgh_bf16 *out, void *stream);
 
 #ifdef __cplusplus

@@ -89,10 +89,11 @@ _NET_SIGS = [
     ("cgh_net_pool2", ctypes.c_int, [_VP, _I32, _I32, _I32, _VP, _VP]),
     ("cgh_net_up_adjoint", ctypes.c_int, [_VP, _I32, _I32, _I32, _I32, _VP, _VP]),
     ("cgh_net_grad_combine", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _I32, _I32, _VP, _VP]),
-    ("cgh_net_lattice_gather", ctypes.c_int, [_VP, _I32, _I32, _I32, _I32, _VP, _VP]),
-    ("cgh_net_lattice_scatter", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP]),
+    ("cgh_net_lattice_gather", ctypes.c_int, [_VP, _I32, _I32, _I32, _I32, _I32, _VP, _VP]),
+    ("cgh_net_lattice_scatter", ctypes.c_int,
+     [_VP, _VP, _I32, _I32, _I32, _I32, _I32, _VP, _VP]),
     ("cgh_net_sqrt_field", ctypes.c_int, [_VP, _I64, _VP, _VP]),
-    ("cgh_net_features", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP]),
+    ("cgh_net_features", ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _VP]),
 ]
 EXPORTS = tuple(name for name, _, _ in _SIGS)
 NET_EXPORTS = tuple(name for name, _, _ in _NET_SIGS)

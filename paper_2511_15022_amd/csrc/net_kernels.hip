@@ -254,26 +254,28 @@ constexpr double kLogScale0 = 0.69314718055994530942;  // ln 2
 constexpr double kAmp0 = 0.5, kOpacity0 = -0.5;
 
 __global__ void k_lattice_gather(const float *__restrict__ net, int H, int W, int gy, int gx,
-                                 float *__restrict__ params) {
+                                 int C, float *__restrict__ params) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = gy * gx;
   if (k >= n) return;
   double cy, cx;
   int iy, ix;
   lattice_point(k, H, W, gy, gx, cy, cx, iy, ix);
-  const float *o = net + ((size_t)iy * W + ix) * 8;
+  const float *o = net + ((size_t)iy * W + ix) * 8 * C;
   const double mx = fmin(fmax(cx + (double)o[0], 1e-3), W - 1e-3);
   const double my = fmin(fmax(cy + (double)o[1], 1e-3), H - 1e-3);
-  // flat layout: mean_pre [n][2], log_scale [n][2], rotation [n], amplitude [n],
-  // phase [n], opacity_pre [n] (C = 1)
+  // flat layout: mean_pre [n][2], log_scale [n][2], rotation [n], amplitude [n][C],
+  // phase [n][C], opacity_pre [n]; colour c from output block c
   params[2 * k] = (float)atanh(2.0 * mx / W - 1.0);
   params[2 * k + 1] = (float)atanh(2.0 * my / H - 1.0);
   params[2 * (size_t)n + 2 * k] = (float)((double)o[2] + kLogScale0);
   params[2 * (size_t)n + 2 * k + 1] = (float)((double)o[3] + kLogScale0);
   params[4 * (size_t)n + k] = o[4];
-  params[5 * (size_t)n + k] = (float)((double)o[5] + kAmp0);
-  params[6 * (size_t)n + k] = o[6];
-  params[7 * (size_t)n + k] = (float)((double)o[7] + kOpacity0);
+  for (int c = 0; c < C; ++c) {
+    params[5 * (size_t)n + (size_t)k * C + c] = (float)((double)o[8 * c + 5] + kAmp0);
+    params[(size_t)(5 + C) * n + (size_t)k * C + c] = o[8 * c + 6];
+  }
+  params[(size_t)(5 + 2 * C) * n + k] = (float)((double)o[7] + kOpacity0);
 }
 
 __global__ void k_fill0(float *__restrict__ x, int64_t n) {
@@ -282,15 +284,16 @@ __global__ void k_fill0(float *__restrict__ x, int64_t n) {
 }
 
 __global__ void k_lattice_scatter(const float *__restrict__ net, const float *__restrict__ g,
-                                  int H, int W, int gy, int gx, float *__restrict__ gnet) {
+                                  int H, int W, int gy, int gx, int C,
+                                  float *__restrict__ gnet) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = gy * gx;
   if (k >= n) return;
   double cy, cx;
   int iy, ix;
   lattice_point(k, H, W, gy, gx, cy, cx, iy, ix);
-  const float *o = net + ((size_t)iy * W + ix) * 8;
-  float *d = gnet + ((size_t)iy * W + ix) * 8;
+  const float *o = net + ((size_t)iy * W + ix) * 8 * C;
+  float *d = gnet + ((size_t)iy * W + ix) * 8 * C;
   const double mx = cx + (double)o[0], my = cy + (double)o[1];
   const double ux = 2.0 * mx / W - 1.0, uy = 2.0 * my / H - 1.0;
   // d atanh(2m / S - 1) / dm = (2 / S) / (1 - u^2); zero where the clip is active
@@ -299,9 +302,11 @@ __global__ void k_lattice_scatter(const float *__restrict__ net, const float *__
   d[2] = g[2 * (size_t)n + 2 * k];
   d[3] = g[2 * (size_t)n + 2 * k + 1];
   d[4] = g[4 * (size_t)n + k];
-  d[5] = g[5 * (size_t)n + k];
-  d[6] = g[6 * (size_t)n + k];
-  d[7] = g[7 * (size_t)n + k];
+  for (int c = 0; c < C; ++c) {
+    d[8 * c + 5] = g[5 * (size_t)n + (size_t)k * C + c];
+    d[8 * c + 6] = g[(size_t)(5 + C) * n + (size_t)k * C + c];
+  }
+  d[7] = g[(size_t)(5 + 2 * C) * n + k];
 }
 
 __global__ void k_sqrt_field(const float *__restrict__ t, int64_t n, float2 *__restrict__ f) {
@@ -309,13 +314,16 @@ __global__ void k_sqrt_field(const float *__restrict__ t, int64_t n, float2 *__r
   if (i < n) f[i] = make_float2(sqrtf(fmaxf(t[i], 0.f)), 0.f);
 }
 
+// planar [C][n] inputs -> [n][8 C]: block c of pixel i from colour c
 __global__ void k_features(const float *__restrict__ t, const float2 *__restrict__ b, int64_t n,
-                           uint16_t *__restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float v = t[i];
-  const float2 u = b[i];
-  uint16_t *o = out + i * 8;
+                           int C, uint16_t *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n * C) return;
+  const int c = (int)(j / n);
+  const int64_t i = j - (int64_t)c * n;
+  const float v = t[j];
+  const float2 u = b[j];
+  uint16_t *o = out + (i * C + c) * 8;
   o[0] = to_bf16(v);
   o[1] = to_bf16(sqrtf(fmaxf(v, 0.f)));
   o[2] = to_bf16(u.x);
@@ -474,22 +482,25 @@ cgh_status cgh_net_grad_combine(const float *gp, const float *gs, int32_t stride
 }
 
 cgh_status cgh_net_lattice_gather(const float *net, int32_t H, int32_t W, int32_t gy,
-                                  int32_t gx, float *params, void *stream) {
-  NET_CHECK(net && params && gy >= 1 && gx >= 1 && gy <= H && gx <= W, "bad arguments");
+                                  int32_t gx, int32_t C, float *params, void *stream) {
+  NET_CHECK(net && params && gy >= 1 && gx >= 1 && gy <= H && gx <= W && C >= 1 &&
+                C <= CGH_MAX_CHANNELS, "bad arguments");
   hipLaunchKernelGGL(k_lattice_gather, dim3(blocks_of((int64_t)gy * gx, 256)), dim3(256), 0,
-                     (hipStream_t)stream, net, H, W, gy, gx, params);
+                     (hipStream_t)stream, net, H, W, gy, gx, C, params);
   NET_LAUNCHED("lattice_gather");
   return CGH_OK;
 }
 
 cgh_status cgh_net_lattice_scatter(const float *net, const float *grads, int32_t H, int32_t W,
-                                   int32_t gy, int32_t gx, float *g_net, void *stream) {
-  NET_CHECK(net && grads && g_net && gy >= 1 && gx >= 1 && gy <= H && gx <= W, "bad arguments");
+                                   int32_t gy, int32_t gx, int32_t C, float *g_net,
+                                   void *stream) {
+  NET_CHECK(net && grads && g_net && gy >= 1 && gx >= 1 && gy <= H && gx <= W && C >= 1 &&
+                C <= CGH_MAX_CHANNELS, "bad arguments");
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_fill0, dim3(blocks_of((int64_t)H * W * 8, 256)), dim3(256), 0, s, g_net,
-                     (int64_t)H * W * 8);
+  hipLaunchKernelGGL(k_fill0, dim3(blocks_of((int64_t)H * W * 8 * C, 256)), dim3(256), 0, s,
+                     g_net, (int64_t)H * W * 8 * C);
   hipLaunchKernelGGL(k_lattice_scatter, dim3(blocks_of((int64_t)gy * gx, 256)), dim3(256), 0, s,
-                     net, grads, H, W, gy, gx, g_net);
+                     net, grads, H, W, gy, gx, C, g_net);
   NET_LAUNCHED("lattice_scatter");
   return CGH_OK;
 }
@@ -503,11 +514,13 @@ cgh_status cgh_net_sqrt_field(const float *target, int64_t count, cgh_c64 *field
   return CGH_OK;
 }
 
-cgh_status cgh_net_features(const float *target, const cgh_c64 *back, int64_t count,
+cgh_status cgh_net_features(const float *target, const cgh_c64 *back, int64_t count, int32_t C,
                             cgh_bf16 *out, void *stream) {
-  NET_CHECK(target && back && out && count > 0, "bad arguments");
-  hipLaunchKernelGGL(k_features, dim3(blocks_of(count, 256)), dim3(256), 0, (hipStream_t)stream,
-                     target, reinterpret_cast<const float2 *>(back), count, out);
+  NET_CHECK(target && back && out && count > 0 && C >= 1 && C <= CGH_MAX_CHANNELS,
+            "bad arguments");
+  hipLaunchKernelGGL(k_features, dim3(blocks_of(count * C, 256)), dim3(256), 0,
+                     (hipStream_t)stream, target, reinterpret_cast<const float2 *>(back), count, C,
+                     out);
   NET_LAUNCHED("features");
   return CGH_OK;
 }

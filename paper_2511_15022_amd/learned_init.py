@@ -255,28 +255,31 @@ class UNet:
 
 
 class Initializer:
-    """Target intensity -> Gaussian parameters for one hologram geometry
-    (C = 1): a gy x gx lattice (one Gaussian per ``pixels_per_gaussian``
-    pixels), the U-Net, and the contexts of the forward (z) and back (-z)
-    propagations."""
+    """Target intensity -> Gaussian parameters for one hologram geometry with
+    C = len(wavelengths) colour channels sharing the Gaussians' geometry: a
+    gy x gx lattice (one Gaussian per ``pixels_per_gaussian`` pixels), the
+    U-Net (8 C input and output channels), and the contexts of the forward
+    (z) and back (-z) propagations."""
 
-    def __init__(self, H, W, pitch, wavelength, z, pad=None, pixels_per_gaussian=5.0, seed=0,
-                 device="cuda", widths=(32, 64, 128, 256)):
+    def __init__(self, H, W, pitch, wavelengths, z, pad=None, pixels_per_gaussian=5.0, seed=0,
+                 device="cuda", widths=(32, 64, 128, 256), max_pairs=0):
         self.H, self.W, self.dev = H, W, torch.device(device)
+        lams = list(wavelengths) if np.ndim(wavelengths) else [wavelengths]
+        self.C = C = len(lams)
         g = np.sqrt(H * W / pixels_per_gaussian)
         self.gy = int(round(g * np.sqrt(H / W)))
         self.gx = int(round(H * W / pixels_per_gaussian / self.gy))
         self.n = self.gy * self.gx
-        self.net = UNet(H, W, widths=widths, seed=seed, device=device)
-        self.back = binding.Context(H, W, 1, pitch, [wavelength], [-z], pad=pad, max_gaussians=1,
+        self.net = UNet(H, W, widths=widths, c_in=8 * C, c_out=8 * C, seed=seed, device=device)
+        self.back = binding.Context(H, W, C, pitch, lams, [-z], pad=pad, max_gaussians=1,
                                     device=device)
-        self.ctx = binding.Context(H, W, 1, pitch, [wavelength], [z], pad=pad,
-                                   max_gaussians=self.n, device=device)
-        self.x16 = torch.empty((H, W, 8), dtype=torch.bfloat16, device=self.dev)
-        self.field = torch.empty((1, H, W), dtype=torch.complex64, device=self.dev)
-        self.params = torch.empty(self.n * 8, dtype=torch.float32, device=self.dev)
+        self.ctx = binding.Context(H, W, C, pitch, lams, [z], pad=pad, max_gaussians=self.n,
+                                   max_pairs=max_pairs, device=device)
+        self.x16 = torch.empty((H, W, 8 * C), dtype=torch.bfloat16, device=self.dev)
+        self.field = torch.empty((C, H, W), dtype=torch.complex64, device=self.dev)
+        self.params = torch.empty(self.n * (6 + 2 * C), dtype=torch.float32, device=self.dev)
         self.gparams = torch.empty_like(self.params)
-        self.gnet = torch.empty((H, W, 8), dtype=torch.float32, device=self.dev)
+        self.gnet = torch.empty((H, W, 8 * C), dtype=torch.float32, device=self.dev)
         self.loss = torch.zeros(2, dtype=torch.float64, device=self.dev)
         self.L = binding.lib()
 
@@ -284,20 +287,29 @@ class Initializer:
         return ctypes.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
 
     def features(self, target):
-        """target: FP32 [H][W] (device) -> the network input self.x16."""
+        """target: FP32 [C][H][W] (device) -> the network input self.x16."""
         hw = self.H * self.W
-        sq = torch.empty((1, self.H, self.W), dtype=torch.complex64, device=self.dev)
-        binding._check(self.L.cgh_net_sqrt_field(_p(target), hw, _p(sq), self._s()))
+        sq = torch.empty((self.C, self.H, self.W), dtype=torch.complex64, device=self.dev)
+        binding._check(self.L.cgh_net_sqrt_field(_p(target), hw * self.C, _p(sq), self._s()))
         _, back = self.back.propagate(sq, intensity=False, field_out=True)
-        binding._check(self.L.cgh_net_features(_p(target), _p(back), hw, _p(self.x16), self._s()))
+        binding._check(self.L.cgh_net_features(_p(target), _p(back), hw, self.C, _p(self.x16),
+                                               self._s()))
         return self.x16
 
     def predict(self, target):
-        """Gaussian parameters (library flat layout, C = 1) for a target."""
+        """Gaussian parameters (library flat layout) for a target [C][H][W]."""
         self.net.forward(self.features(target))
         binding._check(self.L.cgh_net_lattice_gather(_p(self.net.out), self.H, self.W, self.gy,
-                                                     self.gx, _p(self.params), self._s()))
+                                                     self.gx, self.C, _p(self.params), self._s()))
         return self.params
+
+    def grid(self):
+        """The plain lattice ("grid") initialisation: zero network output."""
+        zero = torch.zeros((self.H, self.W, 8 * self.C), dtype=torch.float32, device=self.dev)
+        out = torch.empty_like(self.params)
+        binding._check(self.L.cgh_net_lattice_gather(_p(zero), self.H, self.W, self.gy, self.gx,
+                                                     self.C, _p(out), self._s()))
+        return out
 
     def train_step(self, target, lr):
         """One step of end-to-end training: the network's parameters are
@@ -307,11 +319,62 @@ class Initializer:
         Returns the device loss [L_MSE, PSNR] of this step's prediction."""
         params = self.predict(target)
         self.ctx.rasterize(params, self.n, self.field)
-        self.ctx.backward(params, self.n, self.field, target.reshape(1, 1, self.H, self.W),
+        self.ctx.backward(params, self.n, self.field, target.reshape(1, self.C, self.H, self.W),
                           loss=self.loss, grads=self.gparams)
         binding._check(self.L.cgh_net_lattice_scatter(_p(self.net.out), _p(self.gparams), self.H,
-                                                      self.W, self.gy, self.gx, _p(self.gnet),
-                                                      self._s()))
+                                                      self.W, self.gy, self.gx, self.C,
+                                                      _p(self.gnet), self._s()))
         self.net.backward(self.gnet, self.x16)
         self.net.step(lr)
         return self.loss
+
+
+def scale_head(init, factor):
+    """Multiply the head's weights (not its bias) by `factor`: with a small
+    factor the untrained network's output is near zero, which is the plain
+    lattice ("grid") initialisation."""
+    wd = init.net.get_weights()
+    wd["head"] = (wd["head"] * np.float32(factor)).astype(np.float32)
+    init.net.set_weights(wd)
+
+
+def train(init, targets, steps, lr, order_seed=0):
+    """End-to-end training over a pool of device targets (FP32 [H][W] each),
+    visited in a seeded random order.  Returns (per-step [L_MSE, PSNR] on the
+    host, seconds)."""
+    rng = np.random.default_rng(order_seed)
+    order = rng.integers(0, len(targets), steps)
+    log = torch.zeros((steps, 2), dtype=torch.float64, device=init.dev)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(init.dev)
+    start.record()
+    for i in range(steps):
+        loss = init.train_step(targets[order[i]], lr)
+        log[i].copy_(loss)
+    stop.record()
+    torch.cuda.synchronize(init.dev)
+    return log.cpu().numpy(), start.elapsed_time(stop) / 1e3
+
+
+def optimise(ctx, params, n, target, steps, lr=1e-3):
+    """Adam (the plain optimiser) from `params` for `steps` steps on one
+    target; returns (PSNR before each step, seconds at the end of each)."""
+    P = params.clone()
+    field = torch.empty(ctx.field_shape(), dtype=torch.complex64, device=P.device)
+    G = torch.empty_like(P)
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    log = torch.zeros((steps, 2), dtype=torch.float64, device=P.device)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    T = target.reshape(1, -1, *target.shape[-2:])
+    torch.cuda.synchronize(P.device)
+    ev[0].record()
+    for i in range(steps):
+        ctx.rasterize(P, n, field)
+        ctx.backward(P, n, field, T, loss=log[i], grads=G)
+        binding.step(P, G, M, V, i + 1, lr)
+        ev[i + 1].record()
+    torch.cuda.synchronize(P.device)
+    t = np.array([ev[0].elapsed_time(ev[i + 1]) for i in range(steps)]) / 1e3
+    return log[:, 1].cpu().numpy(), t

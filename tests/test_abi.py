@@ -151,7 +151,8 @@ def test_net_argument_checks_and_workspace_sizes():
     # workspace too small
     assert L.cgh_net_conv3x3_wgrad(16, 8, 0, None, 0, 64, 64, 16, 32, 16, None, 16, 8,
                                    None) == 2
-    assert L.cgh_net_lattice_gather(16, 10, 10, 11, 3, 16, None) == 1
+    assert L.cgh_net_lattice_gather(16, 10, 10, 11, 3, 1, 16, None) == 1
+    assert L.cgh_net_lattice_gather(16, 10, 10, 5, 3, 5, 16, None) == 1   # C > 4
 
 
 def test_pack_unpack_layout_roundtrip():

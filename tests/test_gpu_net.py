@@ -171,26 +171,28 @@ def test_glue_kernels():
     assert torch.equal(cast.cpu(), gf.cpu().to(torch.bfloat16))
 
 
-def test_lattice_gather_and_scatter():
+@pytest.mark.parametrize("C", [1, 3])
+def test_lattice_gather_and_scatter(C):
     rng = np.random.default_rng(5)
     H, W, gy, gx = 64, 96, 29, 43
-    out = (0.4 * rng.standard_normal((H, W, 8))).astype(np.float32)
+    out = (0.4 * rng.standard_normal((H, W, 8 * C))).astype(np.float32)
     out[::7, ::5, 0] = 200.0   # some means pushed past the canvas: the clip
     n = gy * gx
     L = binding.lib()
     net = torch.from_numpy(out).cuda()
-    params = torch.empty(8 * n, dtype=torch.float32, device="cuda")
-    check(L.cgh_net_lattice_gather(P(net), H, W, gy, gx, P(params), stream()))
-    g = torch.from_numpy(rng.standard_normal(8 * n).astype(np.float32)).cuda()
-    gnet = torch.full((H, W, 8), 7.0, dtype=torch.float32, device="cuda")
-    check(L.cgh_net_lattice_scatter(P(net), P(g), H, W, gy, gx, P(gnet), stream()))
+    params = torch.empty((6 + 2 * C) * n, dtype=torch.float32, device="cuda")
+    check(L.cgh_net_lattice_gather(P(net), H, W, gy, gx, C, P(params), stream()))
+    g = torch.from_numpy(rng.standard_normal((6 + 2 * C) * n).astype(np.float32)).cuda()
+    gnet = torch.full((H, W, 8 * C), 7.0, dtype=torch.float32, device="cuda")
+    check(L.cgh_net_lattice_scatter(P(net), P(g), H, W, gy, gx, C, P(gnet), stream()))
     torch.cuda.synchronize()
-    ref = U.gather(out, H, W, gy, gx)
-    got = binding.unpack(params.cpu(), n, 1)
+    ref = U.gather(out, H, W, gy, gx, C)
+    got = binding.unpack(params.cpu(), n, C)
     for k in binding.PARAM_KEYS:
-        assert rel(got[k].numpy(), ref[k].reshape(got[k].shape)) <= 1e-7, k
-    gd = binding.unpack(g.cpu(), n, 1)
-    gref = U.gather_adjoint({k: gd[k].numpy().astype(np.float64) for k in gd}, out, H, W, gy, gx)
+        assert rel(got[k].numpy(), np.asarray(ref[k]).reshape(got[k].shape)) <= 1e-7, k
+    gd = binding.unpack(g.cpu(), n, C)
+    gref = U.gather_adjoint({k: gd[k].numpy().astype(np.float64) for k in gd}, out, H, W, gy, gx,
+                            C)
     assert rel(gnet.cpu().numpy(), gref) <= 1e-7
 
 
@@ -283,48 +285,52 @@ def test_unet_forward_backward_matches_oracle():
     assert e <= E2E_TOL
 
 
-def test_initializer_prediction_and_training_gradients():
+@pytest.mark.parametrize("lams", [[515e-9], [639e-9, 515e-9, 473e-9]])
+def test_initializer_prediction_and_training_gradients(lams):
     """Features (the library's back-propagation of sqrt(T)), network, lattice
     gather, rendering, MSE backward, scatter and network backward, against the
-    oracle's composition of the same steps."""
+    oracle's composition of the same steps; one and three colour channels."""
     from oracle import oracle as O
     from paper_2511_15022_amd import learned_init as LI, synth
-    H, W, pitch, lam, z = 32, 48, 8e-6, 515e-9, 2e-3
-    init = LI.Initializer(H, W, pitch, lam, z, pad=(64, 96), seed=31)
-    T = synth.target(32, 1, H, W)[0, 0]
+    H, W, pitch, z = 32, 48, 8e-6, 2e-3
+    C = len(lams)
+    say("initializer", C)
+    init = LI.Initializer(H, W, pitch, lams, z, pad=(64, 96), seed=31)
+    T = synth.target(32, C, H, W)[0]
     Tg = torch.from_numpy(T).cuda()
     params = init.predict(Tg).clone()
     x16 = init.x16.clone()
     torch.cuda.synchronize()
     # the oracle's features: sqrt(T) propagated by -z, rounded to BF16
-    back = O.propagate(np.sqrt(np.maximum(T, 0)).astype(np.complex128)[None],
-                       O.Optics(H, W, 1, 64, 96, pitch, [lam], [-z]))[0, 0]
-    feats = np.zeros((H, W, 8))
-    feats[..., 0], feats[..., 1] = T, np.sqrt(np.maximum(T, 0))
-    feats[..., 2], feats[..., 3], feats[..., 4] = back.real, back.imag, np.abs(back)
+    back = O.propagate(np.sqrt(np.maximum(T, 0)).astype(np.complex128),
+                       O.Optics(H, W, C, 64, 96, pitch, lams, [-z]))[0]
+    feats = np.zeros((H, W, 8 * C))
+    for c in range(C):
+        feats[..., 8 * c], feats[..., 8 * c + 1] = T[c], np.sqrt(np.maximum(T[c], 0))
+        feats[..., 8 * c + 2], feats[..., 8 * c + 3] = back[c].real, back[c].imag
+        feats[..., 8 * c + 4] = np.abs(back[c])
     fr = U.bf16(feats)
     fg = x16.to(torch.float64).cpu().numpy()
     # BF16 of the FP32 and FP64 back-propagations: equal but for near-ties
     assert np.mean(fg != fr) < 2e-3 and rel(fg, fr) < 2e-3
     wd = init.net.get_weights()
-    arch = U.architecture()
+    arch = U.architecture(c_in=8 * C, c_out=8 * C)
     out = init.net.out.cpu().numpy().astype(np.float64)
     cache, _, _ = gpu_cache(init.net, x16)
     # the lattice gather of the GPU's network output is exact up to FP32 rounding
-    ref = U.gather(out, H, W, init.gy, init.gx)
-    ref = U.gather(out, H, W, init.gy, init.gx)
-    got = binding.unpack(params.cpu(), init.n, 1)
+    ref = U.gather(out, H, W, init.gy, init.gx, C)
+    got = binding.unpack(params.cpu(), init.n, C)
     for k in binding.PARAM_KEYS:
         e = rel(got[k].numpy(), np.asarray(ref[k]).reshape(got[k].shape))
         assert e <= 1e-6, (k, e)
     # one training step: gradients of the network's weights
     init.train_step(Tg, lr=0.0)
     torch.cuda.synchronize()
-    opt = O.Optics(H, W, 1, 64, 96, pitch, [lam], [z])
+    opt = O.Optics(H, W, C, 64, 96, pitch, lams, [z])
     p32 = {k: np.asarray(got[k].numpy(), np.float32) for k in got}
-    fb = O.forward_backward(p32, T[None, None], opt)
+    fb = O.forward_backward(p32, T[None], opt)
     g_out = U.gather_adjoint({k: np.asarray(v, np.float64) for k, v in fb["grads"].items()},
-                             out, H, W, init.gy, init.gx)
+                             out, H, W, init.gy, init.gx, C)
     grads = U.backward(arch, wd, cache, g_out)
     host = init.net.grad.cpu().numpy()
     worst = 0.0
