@@ -186,6 +186,81 @@ def run_convergence_paper(binding, w, p, T, n, steps, dev, target_db=30.0, weigh
     }
 
 
+# Learned initialiser (the metric's "vs plain init" half): train the U-Net of
+# paper_2511_15022_amd.learned_init end to end through this library on seeded
+# 512 x 512 targets of the workload's geometry, move its weights to a network
+# of the workload's size, and optimise from its prediction with the same Adam
+# recipe as the plain-init run.  Seconds to the target PSNR count the
+# network's inference (features, U-Net, lattice gather) plus the optimiser
+# steps until the PSNR first reaches it.
+def unet_flops(layers, H, W):
+    f = 0
+    for name, cu, cs, co, _ in layers:
+        lev = 0 if name == "head" else int(name[3])
+        f += 2 * (H >> lev) * (W >> lev) * 9 * (cu + cs) * co
+    return f
+
+
+def run_learned_init(binding, w, T, n_plain, dev, train_steps, opt_steps, target_db=30.0,
+                     lr_train=3e-4, lr=1e-3, train_size=512, pool=32):
+    import numpy as np
+    import torch
+    from paper_2511_15022_amd import learned_init as LI, synth
+    H, W, C = w["H"], w["W"], w["C"]
+    z = w["zs"][0]
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    small = LI.Initializer(train_size, train_size, w["pitch"], w["lambdas"], z, seed=0, device=dev)
+    LI.scale_head(small, 0.01)
+    targets = [torch.from_numpy(synth.target(1000 + i, C, train_size, train_size)[0]).to(dev)
+               for i in range(pool)]
+    log, secs = LI.train(small, targets, train_steps, lr_train)
+    big = LI.Initializer(H, W, w["pitch"], w["lambdas"], z, seed=0, device=dev)
+    big.net.set_weights(small.net.get_weights())
+    Tt = T.reshape(C, H, W)
+    big.predict(Tt)  # warm-up
+    a, b = ev(), ev()
+    torch.cuda.synchronize(dev)
+    a.record()
+    learned = big.predict(Tt).clone()
+    b.record()
+    torch.cuda.synchronize(dev)
+    infer = a.elapsed_time(b) / 1e3
+    a2, b2 = ev(), ev()
+    x = big.features(Tt)
+    a2.record()
+    big.net.forward(x)
+    b2.record()
+    torch.cuda.synchronize(dev)
+    fwd = a2.elapsed_time(b2) / 1e3
+    flops = unet_flops(big.net.layers, H, W)
+    out = {"train": {"size": [train_size, train_size], "targets": pool, "steps": train_steps,
+                     "seconds": secs, "ms_per_step": 1e3 * secs / train_steps, "lr": lr_train,
+                     "psnr_db_first10": float(log[:10, 1].mean()),
+                     "psnr_db_last20": float(log[-20:, 1].mean())},
+           "network": {"params": big.net.n_params, "forward_ms": 1e3 * fwd,
+                       "forward_tflops": flops / fwd / 1e12,
+                       "mfma_bf16_peak_tflops": 2500.0,
+                       "frac": flops / fwd / 1e12 / 2500.0},
+           "gaussians": big.n, "inference_ms": 1e3 * infer, "target_psnr_db": target_db,
+           "optimiser": f"Adam lr {lr:g} (0.9, 0.999, 1e-8)", "loss": "MSE"}
+    for name, p0 in (("learned", learned), ("grid", big.grid())):
+        psnr, t = LI.optimise(big.ctx, p0, big.n, Tt, opt_steps, lr)
+        hit = np.nonzero(psnr >= target_db)[0]
+        # PSNR i is that of the parameters before step i; reaching it at i
+        # costs the i steps before it
+        t0 = np.concatenate([[0.0], t])
+        sec = None
+        if len(hit):
+            sec = float(t0[hit[0]]) + (infer if name == "learned" else 0.0)
+        marks = sorted({min(opt_steps, k) for k in (1, 10, 50, 100, 200, 500)})
+        out[name] = {"psnr_db_at_step": {str(k - 1): round(float(psnr[k - 1]), 3) for k in marks},
+                     "best_psnr_db": float(psnr.max()), "seconds_to_target": sec,
+                     "steps_to_target": int(hit[0]) if len(hit) else None}
+    pairs, ok = big.ctx.read_status(raise_on_overflow=False)
+    out["pair_capacity_ok"] = bool(ok)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Autodiff comparators: the same forward written with plain PyTorch ops and
 # differentiated by torch.autograd, on the same GPU and inputs.
@@ -381,6 +456,8 @@ def main():
     ap.add_argument("--paper-convergence-steps", type=int, default=2000,
                     help="steps of the run with the paper's optimiser recipe and final loss "
                          "from plain init (0: skip)")
+    ap.add_argument("--learned-init-steps", type=int, default=600,
+                    help="training steps of the learned initialiser (0: skip)")
     ap.add_argument("--paper-loss-steps", type=int, default=20,
                     help="timed steps with the paper's final loss, L + 0.005 L_SSIM (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -556,6 +633,22 @@ def main():
         except Exception as e:
             conv_paper = {"error": f"{type(e).__name__}: {e}"[:300]}
         torch.cuda.empty_cache()
+    learned = None
+    if args.learned_init_steps > 0 and L == 1 and Mk is None:
+        log(f"[bench] learned initialiser: {args.learned_init_steps} training steps at 512 x 512")
+        try:
+            learned = run_learned_init(binding, w, T, n, dev, args.learned_init_steps,
+                                       max(args.convergence_steps, 200))
+            log(f"[bench]   train {learned['train']['seconds']:.2f} s "
+                f"({learned['train']['ms_per_step']:.2f} ms/step); inference "
+                f"{learned['inference_ms']:.2f} ms; U-Net forward "
+                f"{learned['network']['forward_ms']:.2f} ms "
+                f"({learned['network']['forward_tflops']:.1f} TFLOP/s)")
+            for k in ("learned", "grid"):
+                log(f"[bench]   {k}: {learned[k]}")
+        except Exception as e:
+            learned = {"error": f"{type(e).__name__}: {e}"[:300]}
+        torch.cuda.empty_cache()
     autodiff = None
     if not args.no_autodiff and L == 1 and Mk is None:
         log("[bench] fused adjoint vs autodiff (same GPU, same inputs)")
@@ -611,6 +704,7 @@ def main():
         "cpu_baseline": cpu,
         "convergence": conv,
         "convergence_paper_recipe": conv_paper,
+        "learned_init": learned,
         "autodiff": autodiff,
         "paper_loss": paper_loss,
         "kernels_us_per_step": {k: round(v["ms_per_step"] * 1e3, 2) for k, v in kernels.items()},

@@ -341,3 +341,28 @@ def test_initializer_prediction_and_training_gradients(lams):
         fb["loss"])
     assert abs(init.loss.cpu().numpy()[0] - fb["loss"]) <= 1e-4 * fb["loss"]
     assert worst <= GRAD_TOL_NET
+
+
+def test_trained_initializer_beats_the_grid_initialisation():
+    """What the trained network gains over the method without it: after a
+    short training (200 steps on 16 seeded 64 x 64 RGB targets), its prediction
+    for held-out targets renders far closer to them than the plain lattice
+    (zero network output) does, and stays ahead after 50 optimiser steps."""
+    from paper_2511_15022_amd import learned_init as LI, synth
+    H = W = 64
+    lams, z = [639e-9, 515e-9, 473e-9], 5e-3
+    init = LI.Initializer(H, W, 8e-6, lams, z, seed=0)
+    LI.scale_head(init, 0.01)
+    pool = [torch.from_numpy(synth.target(1000 + i, 3, H, W)[0]).cuda() for i in range(16)]
+    log, secs = LI.train(init, pool, 200, 3e-4)
+    say("training psnr first/last", log[:10, 1].mean(), log[-10:, 1].mean(), "seconds", secs)
+    gains0, gains50 = [], []
+    for i in range(3):
+        T = torch.from_numpy(synth.target(9000 + i, 3, H, W)[0]).cuda()
+        pl, tl = LI.optimise(init.ctx, init.predict(T).clone(), init.n, T, 51)
+        pg, tg = LI.optimise(init.ctx, init.grid(), init.n, T, 51)
+        gains0.append(pl[0] - pg[0])
+        gains50.append(pl[50] - pg[50])
+    say("PSNR gain over the grid init at step 0 / 50:", gains0, gains50)
+    assert min(gains0) > 10.0
+    assert min(gains50) > 3.0
