@@ -193,6 +193,14 @@ cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
                                  const float *grad_intensity, cgh_c64 *grad_field,
                                  void *stream);
 
+/* Adjoint of cgh_propagate's field output for an arbitrary seed: given
+ * grad_u = dL/dRe(u) + j dL/dIm(u) ([L][C][H][W]), writes grad_field =
+ * sum_l P_l^H grad_u[l] ([C][H][W]), the conjugate transfer function with the
+ * same band limit (supplementary BLASM Backward Pass).  Used where the loss is
+ * not a function of the intensity alone (the Random POH's L_extract). */
+cgh_status cgh_propagate_field_adjoint(cgh_ctx *ctx, const cgh_c64 *grad_u, cgh_c64 *grad_field,
+                                       void *stream);
+
 /* Adjoint of cgh_rasterize (supplementary rasterizer Backward Pass, items 1-7):
  * grads <- dL/dparams from grad_field = dL/dRe(U0) + j dL/dIm(U0) ([C][H][W]).
  * Same precondition as cgh_backward. */

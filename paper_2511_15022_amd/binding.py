@@ -60,6 +60,7 @@ _SIGS = [
     ("cgh_backward_full", ctypes.c_int,
      [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_float, _VP, _VP, _VP, _VP]),
     ("cgh_propagate_adjoint", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    ("cgh_propagate_field_adjoint", ctypes.c_int, [_VP, _VP, _VP, _VP]),
     ("cgh_rasterize_adjoint", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
     ("cgh_step", ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP, ctypes.c_int32, _VP]),
@@ -95,7 +96,18 @@ _NET_SIGS = [
     ("cgh_net_sqrt_field", ctypes.c_int, [_VP, _I64, _VP, _VP]),
     ("cgh_net_features", ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _VP]),
 ]
+# entry points of include/cgh_poh.h (phase-only hologram conversion)
+_POH_SIGS = [
+    ("cgh_poh_dpac", ctypes.c_int, [_VP, _I32, _I32, _I32, _VP, _VP, _VP]),
+    ("cgh_poh_field", ctypes.c_int, [_VP, _I64, _VP, _VP]),
+    ("cgh_poh_phase_grad", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP]),
+    ("cgh_poh_extract_partials", ctypes.c_int64, [_I64]),
+    ("cgh_poh_extract_seed", ctypes.c_int,
+     [_VP, _VP, _VP, _VP, _I32, _I32, _I32, _I32, ctypes.c_float, ctypes.c_float, _VP, _VP, _VP,
+      _VP, _VP]),
+]
 EXPORTS = tuple(name for name, _, _ in _SIGS)
+POH_EXPORTS = tuple(name for name, _, _ in _POH_SIGS)
 NET_EXPORTS = tuple(name for name, _, _ in _NET_SIGS)
 
 _lib = None
@@ -109,7 +121,7 @@ def lib():
             raise RuntimeError(f"libcgh.so not found at {LIB_PATH}; build it with "
                                "paper_2511_15022_amd/build.py (no CPU fallback exists)")
         L = ctypes.CDLL(LIB_PATH)
-        for name, res, args in _SIGS + _NET_SIGS:
+        for name, res, args in _SIGS + _NET_SIGS + _POH_SIGS:
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
@@ -272,6 +284,16 @@ class Context:
                                             _ptr(grad_field), _ptr(grads),
                                             _stream(self.device)))
         return grads
+
+    def propagate_field_adjoint(self, grad_u, grad_field=None):
+        """cgh_propagate_field_adjoint: sum over planes of P^H grad_u."""
+        _need(grad_u, torch.complex64, self.L * self.C * self.H * self.W, "grad_u", self.device)
+        if grad_field is None:
+            grad_field = torch.empty(self.field_shape(), dtype=torch.complex64, device=self.device)
+        _need(grad_field, torch.complex64, self.C * self.H * self.W, "grad_field", self.device)
+        _check(lib().cgh_propagate_field_adjoint(self.handle, _ptr(grad_u), _ptr(grad_field),
+                                                 _stream(self.device)))
+        return grad_field
 
     def propagate_adjoint(self, field, grad_intensity, grad_field=None):
         _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)

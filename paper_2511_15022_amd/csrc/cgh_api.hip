@@ -490,6 +490,27 @@ cgh_status cgh_backward_full(cgh_ctx *ctx, const float *params, int32_t n,
   return raster_adjoint(c, params, n, gf, grads, s);
 }
 
+cgh_status cgh_propagate_field_adjoint(cgh_ctx *ctx, const cgh_c64 *grad_u, cgh_c64 *grad_field,
+                                       void *stream) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  Ctx &c = ctx->c;
+  if (!grad_u || !grad_field) return fail(CGH_ERR_INVALID_ARG, "grad_u/grad_field is NULL");
+  if (!aligned16(grad_u) || !aligned16(grad_field))
+    return fail(CGH_ERR_INVALID_ARG, "buffers must be 16-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const float2 *g = reinterpret_cast<const float2 *>(grad_u);
+  for (int l = 0; l < c.L; ++l) {
+    {
+      ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
+      CGH_CHECK_LAUNCH(cgh::launch_row_fwd(c, g + (size_t)l * c.C * c.H * c.W, c.spec_plane, s),
+                       "adjoint seed row fft");
+    }
+    cgh_status st = plane_adjoint(c, l, s);
+    if (st != CGH_OK) return st;
+  }
+  return adjoint_rows(c, reinterpret_cast<float2 *>(grad_field), s);
+}
+
 cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
                                  const float *grad_intensity, cgh_c64 *grad_field,
                                  void *stream) {

@@ -14,6 +14,7 @@ HEADER = os.path.join(ROOT, "include", "cgh.h")
 
 
 NET_HEADER = os.path.join(ROOT, "include", "cgh_net.h")
+POH_HEADER = os.path.join(ROOT, "include", "cgh_poh.h")
 
 
 def declared_functions(header=HEADER):
@@ -25,11 +26,13 @@ def declared_functions(header=HEADER):
 def test_header_and_binding_agree():
     assert declared_functions() == sorted(binding.EXPORTS)
     assert declared_functions(NET_HEADER) == sorted(binding.NET_EXPORTS)
+    assert declared_functions(POH_HEADER) == sorted(binding.POH_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
     L = binding.lib()
-    for name in declared_functions() + declared_functions(NET_HEADER):
+    for name in (declared_functions() + declared_functions(NET_HEADER) +
+                 declared_functions(POH_HEADER)):
         assert hasattr(L, name), name
     assert L.cgh_abi_version() == 1
 
