@@ -347,11 +347,14 @@ void orc_fft2(int ny, int nx, double *data, int inverse) {
 /* supplementary "Spatial Frequency Computation", "Bandlimit Computation",  */
 /* "Transfer Function Evaluation").  Laid out in natural FFT order: index k */
 /* carries the frequency ((k + N/2) mod N - N/2) / (N dx), i.e. the         */
-/* paper's centred grid without the shift.                                  */
+/* paper's centred grid without the shift.  aperture > 0: the circular     */
+/* aperture of Alg. 3, read as centred on the zero frequency: bins with     */
+/* kx^2 + ky^2 >= aperture^2 (signed bin indices) are zeroed.               */
 /* ------------------------------------------------------------------------- */
 static double signed_index(int k, int n) { return (double)(((k + n / 2) % n) - n / 2); }
 
-void orc_transfer(int ny, int nx, double pitch, double lambda, double z, double *out) {
+void orc_transfer(int ny, int nx, double pitch, double lambda, double z, double aperture,
+                  double *out) {
   double Lx = nx * pitch, Ly = ny * pitch;
   double fxmax = 1.0 / (lambda * sqrt((2.0 * z / Lx) * (2.0 * z / Lx) + 1.0));
   double fymax = 1.0 / (lambda * sqrt((2.0 * z / Ly) * (2.0 * z / Ly) + 1.0));
@@ -362,7 +365,9 @@ void orc_transfer(int ny, int nx, double pitch, double lambda, double z, double 
       double fy = signed_index(ky, ny) / Ly;
       double arg = 1.0 / (lambda * lambda) - fx * fx - fy * fy;
       cplx v = 0.0;
-      if (fabs(fx) < fxmax && fabs(fy) < fymax && arg >= 0.0) {
+      double ix = signed_index(kx, nx), iy = signed_index(ky, ny);
+      int open = aperture <= 0.0 || ix * ix + iy * iy < aperture * aperture;
+      if (fabs(fx) < fxmax && fabs(fy) < fymax && arg >= 0.0 && open) {
         double ph = TWO_PI * z * sqrt(arg);
         v = cos(ph) + sin(ph) * I;
       }
@@ -378,14 +383,14 @@ void orc_transfer(int ny, int nx, double pitch, double lambda, double z, double 
 /* "Backward Pass" of BLASM) and sums over planes into a [C][H][W] result.  */
 /* ------------------------------------------------------------------------- */
 static void propagate_one(int H, int W, int Hp, int Wp, double pitch, double lambda, double z,
-                          int conj_h, const cplx *in, cplx *out) {
+                          double aperture, int conj_h, const cplx *in, cplx *out) {
   int oy = (Hp - H) / 2, ox = (Wp - W) / 2;
   cplx *P = (cplx *)calloc((size_t)Hp * Wp, sizeof(cplx));
   cplx *Ht = (cplx *)malloc(sizeof(cplx) * (size_t)Hp * Wp);
   for (int j = 0; j < H; ++j)
     for (int i = 0; i < W; ++i) P[(size_t)(j + oy) * Wp + (i + ox)] = in[(size_t)j * W + i];
   orc_fft2(Hp, Wp, (double *)P, 0);
-  orc_transfer(Hp, Wp, pitch, lambda, z, (double *)Ht);
+  orc_transfer(Hp, Wp, pitch, lambda, z, aperture, (double *)Ht);
   for (size_t t = 0; t < (size_t)Hp * Wp; ++t) P[t] *= conj_h ? conj(Ht[t]) : Ht[t];
   orc_fft2(Hp, Wp, (double *)P, 1);
   for (int j = 0; j < H; ++j)
@@ -396,24 +401,24 @@ static void propagate_one(int H, int W, int Hp, int Wp, double pitch, double lam
 
 /* field: [C][H][W] complex -> out: [L][C][H][W] complex */
 void orc_propagate(int C, int H, int W, int Hp, int Wp, double pitch, const double *lambdas,
-                   int L, const double *zs, const double *field, double *out) {
+                   int L, const double *zs, double aperture, const double *field, double *out) {
   for (int l = 0; l < L; ++l)
     for (int c = 0; c < C; ++c)
-      propagate_one(H, W, Hp, Wp, pitch, lambdas[c], zs[l], 0,
+      propagate_one(H, W, Hp, Wp, pitch, lambdas[c], zs[l], aperture, 0,
                     (const cplx *)field + (size_t)c * H * W,
                     (cplx *)out + ((size_t)l * C + c) * H * W);
 }
 
 /* grad_u: [L][C][H][W] complex -> grad_field: [C][H][W] complex (sum over l) */
 void orc_propagate_adjoint(int C, int H, int W, int Hp, int Wp, double pitch,
-                           const double *lambdas, int L, const double *zs, const double *grad_u,
-                           double *grad_field) {
+                           const double *lambdas, int L, const double *zs, double aperture,
+                           const double *grad_u, double *grad_field) {
   cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)H * W);
   cplx *gf = (cplx *)grad_field;
   memset(gf, 0, sizeof(cplx) * (size_t)C * H * W);
   for (int l = 0; l < L; ++l)
     for (int c = 0; c < C; ++c) {
-      propagate_one(H, W, Hp, Wp, pitch, lambdas[c], zs[l], 1,
+      propagate_one(H, W, Hp, Wp, pitch, lambdas[c], zs[l], aperture, 1,
                     (const cplx *)grad_u + ((size_t)l * C + c) * H * W, tmp);
       for (size_t t = 0; t < (size_t)H * W; ++t) gf[(size_t)c * H * W + t] += tmp[t];
     }

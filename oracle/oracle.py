@@ -41,9 +41,9 @@ def lib():
         L.orc_ambiguous_pixels.restype = ctypes.c_long
         L.orc_fft1.argtypes = [i, d, i]
         L.orc_fft2.argtypes = [i, i, d, i]
-        L.orc_transfer.argtypes = [i, i, f, f, f, d]
-        L.orc_propagate.argtypes = [i, i, i, i, i, f, d, i, d, d, d]
-        L.orc_propagate_adjoint.argtypes = [i, i, i, i, i, f, d, i, d, d, d]
+        L.orc_transfer.argtypes = [i, i, f, f, f, f, d]
+        L.orc_propagate.argtypes = [i, i, i, i, i, f, d, i, d, f, d, d]
+        L.orc_propagate_adjoint.argtypes = [i, i, i, i, i, f, d, i, d, f, d, d]
         L.orc_raster_adjoint.argtypes = [i, i, i, i, f, i, d, d, d, d, d, d, d, d, d, d, d, d, d]
         _LIB = L
     return _LIB
@@ -60,15 +60,18 @@ def _f64(a):
 class Optics:
     """Problem geometry: canvas H x W, C channels, padded grid Hp x Wp,
     pixel pitch, one wavelength per channel, L propagation distances, support
-    radius k (in standard deviations; k <= 0 means unbounded)."""
+    radius k (in standard deviations; k <= 0 means unbounded), and the optional
+    circular aperture of Alg. 3 (radius in frequency bins of the padded grid,
+    centred on the zero frequency; 0: none)."""
 
-    def __init__(self, H, W, C, Hp, Wp, pitch, lambdas, zs, k=3.0, flags=0):
+    def __init__(self, H, W, C, Hp, Wp, pitch, lambdas, zs, k=3.0, flags=0, aperture=0.0):
         self.H, self.W, self.C, self.Hp, self.Wp = int(H), int(W), int(C), int(Hp), int(Wp)
         self.pitch = float(pitch)
         self.lambdas = _f64(lambdas).reshape(-1)
         self.zs = _f64(zs).reshape(-1)
         self.k = float(k)
         self.flags = int(flags)
+        self.aperture = float(aperture)
         assert self.lambdas.size == self.C
 
     @property
@@ -146,11 +149,12 @@ def fft2(x, inverse=False):
     return a
 
 
-def transfer(Hp, Wp, pitch, lam, z):
+def transfer(Hp, Wp, pitch, lam, z, aperture=0.0):
     """Band-limited angular-spectrum transfer function on the natural-order
     [Hp, Wp] frequency grid (Sec. 2; suppl. BLASM section)."""
     h = np.zeros((Hp, Wp), dtype=np.complex128)
-    lib().orc_transfer(Hp, Wp, float(pitch), float(lam), float(z), _p(h.view(np.float64)))
+    lib().orc_transfer(Hp, Wp, float(pitch), float(lam), float(z), float(aperture),
+                       _p(h.view(np.float64)))
     return h
 
 
@@ -159,7 +163,8 @@ def propagate(field, opt):
     f = np.ascontiguousarray(field, dtype=np.complex128)
     out = np.zeros((opt.L, opt.C, opt.H, opt.W), dtype=np.complex128)
     lib().orc_propagate(opt.C, opt.H, opt.W, opt.Hp, opt.Wp, opt.pitch, _p(opt.lambdas), opt.L,
-                        _p(opt.zs), _p(f.view(np.float64)), _p(out.view(np.float64)))
+                        _p(opt.zs), opt.aperture, _p(f.view(np.float64)),
+                        _p(out.view(np.float64)))
     return out
 
 
@@ -169,7 +174,8 @@ def propagate_adjoint(grad_u, opt):
     g = np.ascontiguousarray(grad_u, dtype=np.complex128)
     out = np.zeros((opt.C, opt.H, opt.W), dtype=np.complex128)
     lib().orc_propagate_adjoint(opt.C, opt.H, opt.W, opt.Hp, opt.Wp, opt.pitch,
-                                _p(opt.lambdas), opt.L, _p(opt.zs), _p(g.view(np.float64)),
+                                _p(opt.lambdas), opt.L, _p(opt.zs), opt.aperture,
+                                _p(g.view(np.float64)),
                                 _p(out.view(np.float64)))
     return out
 

@@ -81,3 +81,18 @@ def test_band_limit_inactive_at_workload_geometries(O):
         assert np.all(np.abs(H) > 0)
     H = O.transfer(512, 512, 8e-6, 515e-9, 2e-3)
     assert np.all(np.abs(H) > 0)
+
+
+def test_aperture_keeps_the_lattice_points_inside_the_circle(O):
+    """Alg. 3's circular aperture, centred on the zero frequency: radius 10 bins
+    keeps the 305 lattice points with i^2 + j^2 < 100 (the 317 of the closed
+    disk less the 12 on its rim: (+-10, 0), (0, +-10), (+-6, +-8), (+-8, +-6)),
+    and inside it H is the unfiltered transfer function."""
+    import numpy as np
+    h0 = O.transfer(64, 64, 8e-6, 515e-9, 1e-3)
+    h = O.transfer(64, 64, 8e-6, 515e-9, 1e-3, aperture=10.0)
+    assert np.count_nonzero(h0) == 64 * 64           # the band limit does not bind here
+    assert np.count_nonzero(h) == 305
+    kept = h != 0
+    assert np.array_equal(h[kept], h0[kept])
+    assert h[0, 10] == 0 and h[0, 9] != 0 and h[6, 8] == 0 and h[63, 63] != 0
