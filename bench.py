@@ -258,7 +258,82 @@ def run_learned_init(binding, w, T, n_plain, dev, train_steps, opt_steps, target
                      "steps_to_target": int(hit[0]) if len(hit) else None}
     pairs, ok = big.ctx.read_status(raise_on_overflow=False)
     out["pair_capacity_ok"] = bool(ok)
+    out["_ctx"], out["_learned"] = big.ctx, learned  # for the POH leg; removed before printing
+    out["_n"] = big.n
     return out
+
+
+def psnr_of(u, T):
+    """PSNR (dB) of |u|^2 against T, after the least-squares intensity scale
+    (phase-only holograms have no amplitude freedom), on the host."""
+    import numpy as np
+    I = (u.real ** 2 + u.imag ** 2).double().cpu().numpy().reshape(-1)
+    t = T.double().cpu().numpy().reshape(-1)
+    s = float(I @ t / max(I @ I, 1e-300))
+    return float(10 * np.log10(1.0 / np.mean((s * I - t) ** 2))), s
+
+
+def run_poh(binding, ctx, params, n, T, steps, dev, opt_steps=200, lr=1e-3, lr_phase=0.1):
+    """POH conversion (Sec. 3.3) at the workload's size: the Gaussians are first
+    optimised from `params` (Adam, `opt_steps`); the Smooth POH is the
+    double-phase coding of their field; the Random POH is optimised jointly
+    with them under L_extract for `steps` steps from a seeded random phase."""
+    import torch
+    from paper_2511_15022_amd import learned_init as LI, poh
+    C, H, W = ctx.C, ctx.H, ctx.W
+    Tt = T.reshape(1, C, H, W)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    # the complex hologram after the plain optimiser
+    P = params.clone()
+    field = torch.empty((C, H, W), dtype=torch.complex64, device=dev)
+    G, M, V = torch.empty_like(P), torch.zeros_like(P), torch.zeros_like(P)
+    for i in range(opt_steps):
+        ctx.rasterize(P, n, field)
+        ctx.backward(P, n, field, Tt, grads=G)
+        binding.step(P, G, M, V, i + 1, lr)
+    ctx.rasterize(P, n, field)
+    _, u = ctx.propagate(field, intensity=False, field_out=True)
+    complex_db, _ = psnr_of(u, Tt)
+    a, b = ev(), ev()
+    torch.cuda.synchronize(dev)
+    a.record()
+    _, hs = poh.smooth(field)
+    b.record()
+    torch.cuda.synchronize(dev)
+    # displayed through the circular aperture of Alg. 3 (half the Nyquist radius
+    # of the longer padded side), which removes the double-phase carrier's
+    # replica at the corner of the spectrum
+    Hp, Wp = ctx.Hp, ctx.Wp
+    apert = max(Hp, Wp) / 4.0
+    actx = binding.Context(H, W, C, ctx.cfg.pitch_m, list(ctx.cfg.wavelength_m)[:C],
+                           [ctx.cfg.z_m[0]], pad=(Hp, Wp), max_gaussians=1, aperture=apert,
+                           device=dev)
+    _, us = actx.propagate(hs, intensity=False, field_out=True)
+    smooth_db, smooth_scale = psnr_of(us, Tt)
+    _, us0 = ctx.propagate(hs, intensity=False, field_out=True)
+    smooth_open_db, _ = psnr_of(us0, Tt)
+    actx.close()
+    rp = poh.RandomPOH(ctx, P, n, Tt, seed=7, lr_phase=lr_phase)
+    a2, b2 = ev(), ev()
+    torch.cuda.synchronize(dev)
+    a2.record()
+    for _ in range(steps):
+        rp.step()
+    b2.record()
+    torch.cuda.synchronize(dev)
+    u_g, u_r = rp.gradients()
+    rand_db, rand_scale = psnr_of(u_r, Tt)
+    return {"complex_hologram": {"optimiser_steps": opt_steps, "psnr_db": complex_db},
+            "smooth_poh": {"method": "double-phase coding", "ms": a.elapsed_time(b),
+                           "aperture_bins": apert, "psnr_db": smooth_db,
+                           "intensity_scale": smooth_scale,
+                           "psnr_db_without_aperture": smooth_open_db},
+            "random_poh": {"steps": steps, "ms_per_step": a2.elapsed_time(b2) / steps,
+                           "psnr_db": rand_db, "intensity_scale": rand_scale,
+                           "gaussians_psnr_db": psnr_of(u_g, Tt)[0],
+                           "loss": f"L_extract, l_comp 0.1, l_field 0.01, Adam lr {lr:g} "
+                                   f"(Gaussians), {lr_phase:g} (phase)"},
+            "psnr_note": "PSNR of the propagated intensity after the least-squares intensity scale"}
 
 
 # ---------------------------------------------------------------------------
@@ -456,6 +531,8 @@ def main():
     ap.add_argument("--paper-convergence-steps", type=int, default=2000,
                     help="steps of the run with the paper's optimiser recipe and final loss "
                          "from plain init (0: skip)")
+    ap.add_argument("--poh-steps", type=int, default=200,
+                    help="Random POH steps after the learned initialiser leg (0: skip)")
     ap.add_argument("--learned-init-steps", type=int, default=600,
                     help="training steps of the learned initialiser (0: skip)")
     ap.add_argument("--paper-loss-steps", type=int, default=20,
@@ -646,8 +723,19 @@ def main():
                 f"({learned['network']['forward_tflops']:.1f} TFLOP/s)")
             for k in ("learned", "grid"):
                 log(f"[bench]   {k}: {learned[k]}")
+            if args.poh_steps > 0:
+                log(f"[bench] POH conversion: {args.poh_steps} Random POH steps")
+                try:
+                    learned["poh"] = run_poh(binding, learned["_ctx"], learned["_learned"],
+                                             learned["_n"], T, args.poh_steps, dev)
+                    log(f"[bench]   {learned['poh']}")
+                except Exception as e:
+                    learned["poh"] = {"error": f"{type(e).__name__}: {e}"[:300]}
         except Exception as e:
             learned = {"error": f"{type(e).__name__}: {e}"[:300]}
+        if isinstance(learned, dict):
+            for k in ("_ctx", "_learned", "_n"):
+                learned.pop(k, None)
         torch.cuda.empty_cache()
     autodiff = None
     if not args.no_autodiff and L == 1 and Mk is None:

@@ -86,6 +86,10 @@ typedef struct {
   int64_t max_pairs;             /* capacity of the (tile, Gaussian) list (0: default     */
                                  /* 8 * max_gaussians + 65536)                            */
   int32_t flags;                 /* 0, or CGH_FULL_LOSS and/or CGH_PAPER_ALPHA            */
+  double aperture;               /* circular aperture of Alg. 3 in the frequency plane:   */
+                                 /* keep the bins of the padded grid with                 */
+                                 /* kx^2 + ky^2 < aperture^2 (signed bin indices, centred */
+                                 /* on the zero frequency); 0: none                       */
 } cgh_config;
 
 /* cgh_config.flags: reserve the workspace of cgh_backward_full (the SSIM term:
@@ -271,7 +275,7 @@ cgh_status cgh_profile_end(cgh_ctx *ctx, void *stream, double *total_ms, int32_t
 const char *cgh_last_error(void);
 
 /* ABI version of this header (CGH_ABI_VERSION). */
-#define CGH_ABI_VERSION 1
+#define CGH_ABI_VERSION 2
 int32_t cgh_abi_version(void);
 
 #ifdef __cplusplus

@@ -43,6 +43,7 @@ class cgh_config(ctypes.Structure):
         ("max_gaussians", ctypes.c_int32),
         ("max_pairs", ctypes.c_int64),
         ("flags", ctypes.c_int32),
+        ("aperture", ctypes.c_double),
     ]
 
 
@@ -177,7 +178,7 @@ class Context:
 
     def __init__(self, height, width, channels, pitch, wavelengths, zs, pad=None,
                  support_sigma=3.0, max_gaussians=0, max_pairs=0, full_loss=False,
-                 paper_alpha=False, device="cuda"):
+                 paper_alpha=False, aperture=0.0, device="cuda"):
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -200,6 +201,7 @@ class Context:
         cfg.max_gaussians = int(max_gaussians)
         cfg.max_pairs = int(max_pairs)
         cfg.flags = (CGH_FULL_LOSS if full_loss else 0) | (CGH_PAPER_ALPHA if paper_alpha else 0)
+        cfg.aperture = float(aperture)
         self.cfg = cfg
         self.L = len(zs)
         self.Hp = cfg.pad_height or 2 * self.H

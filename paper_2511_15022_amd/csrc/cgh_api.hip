@@ -80,6 +80,8 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
       return fail(CGH_ERR_INVALID_ARG, "wavelength of channel %d must be positive", ch);
   for (int l = 0; l < f.num_planes; ++l)
     if (!std::isfinite(f.z_m[l])) return fail(CGH_ERR_INVALID_ARG, "z of plane %d not finite", l);
+  if (!(f.aperture >= 0.0) || !std::isfinite(f.aperture))
+    return fail(CGH_ERR_INVALID_ARG, "aperture must be >= 0 and finite");
   if (!std::isfinite(f.support_sigma))
     return fail(CGH_ERR_INVALID_ARG, "support_sigma must be finite");
   if (f.max_gaussians < 0 || f.max_gaussians > (1 << 28))

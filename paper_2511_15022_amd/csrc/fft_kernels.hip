@@ -223,8 +223,10 @@ hipError_t launch_build_twiddles_full(float2 *tw, int n, hipStream_t s) {
 // L_x, L_y are the extents of the padded grid.  Evanescent frequencies get 0.
 // out_t (optional) receives the same table column-major, [Wq][Hq], times
 // t_scale (the 1 / (Hp Wp) of the inverse transform, applied in FP64).
+// aperture > 0: the circular aperture of Alg. 3, centred on the zero frequency
+// (bins with qx^2 + qy^2 >= aperture^2 are zeroed).
 __global__ void k_transfer(float2 *out, float2 *out_t, double t_scale, int Hq, int Wq, int Hp,
-                           int Wp, double pitch, double lambda, double z) {
+                           int Wp, double pitch, double lambda, double z, double aperture) {
   int qx = blockIdx.x * blockDim.x + threadIdx.x;
   int qy = blockIdx.y;
   if (qx >= Wq) return;
@@ -235,7 +237,8 @@ __global__ void k_transfer(float2 *out, float2 *out_t, double t_scale, int Hq, i
   const double fymax = 1.0 / (lambda * sqrt(ay * ay + 1.0));
   const double arg = 1.0 / (lambda * lambda) - fx * fx - fy * fy;
   double sn = 0.0, cs = 0.0;
-  if (fx < fxmax && fy < fymax && arg >= 0.0) {
+  const bool open = aperture <= 0.0 || (double)qx * qx + (double)qy * qy < aperture * aperture;
+  if (fx < fxmax && fy < fymax && arg >= 0.0 && open) {
     const double ph = 6.283185307179586476925 * z * sqrt(arg);  // 2 pi z sqrt(arg)
     sincos(ph, &sn, &cs);
   }
@@ -251,7 +254,8 @@ hipError_t launch_build_transfer(const Ctx &c, hipStream_t s) {
       hipLaunchKernelGGL(k_transfer, dim3((c.Wq + 255) / 256, c.Hq), dim3(256), 0, s,
                          c.htab + at, c.htab_t ? c.htab_t + at : nullptr,
                          1.0 / ((double)c.Hp * (double)c.Wp), c.Hq, c.Wq, c.Hp, c.Wp,
-                         c.cfg.pitch_m, c.cfg.wavelength_m[ch], c.cfg.z_m[l]);
+                         c.cfg.pitch_m, c.cfg.wavelength_m[ch], c.cfg.z_m[l],
+                         c.cfg.aperture);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }

@@ -47,7 +47,7 @@ class RandomPOH:
     context ``ctx``) and a random POH phase [C][H][W] under L_extract against
     ``target`` ([L][C][H][W]) with optional focal masks ([L][H][W])."""
 
-    def __init__(self, ctx, params, n, target, mask=None, seed=0, lr=1e-3, lr_phase=2e-2,
+    def __init__(self, ctx, params, n, target, mask=None, seed=0, lr=1e-3, lr_phase=0.1,
                  l_comp=LAMBDA_COMP, l_field=LAMBDA_FIELD):
         self.ctx, self.n = ctx, n
         self.dev = params.device

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     for name in (declared_functions() + declared_functions(NET_HEADER) +
                  declared_functions(POH_HEADER)):
         assert hasattr(L, name), name
-    assert L.cgh_abi_version() == 1
+    assert L.cgh_abi_version() == 2
 
 
 def cfg(**kw):
@@ -52,6 +52,7 @@ def cfg(**kw):
     c.max_gaussians = kw.get("n", 4096)
     c.max_pairs = kw.get("pairs", 0)
     c.flags = kw.get("flags", 0)
+    c.aperture = kw.get("aperture", 0.0)
     return c
 
 
@@ -116,6 +117,7 @@ def test_paper_alpha_flag_reserves_the_exponent_limits():
     (dict(flags=1, H=10), 1), (dict(flags=1, W=10, Wp=20), 1),   # SSIM window is 11 x 11
     (dict(L=0), 1), (dict(zs=[1e-3] * 8, L=9), 1),   # 1 <= planes <= CGH_MAX_PLANES
     (dict(zs=[1e-3, float("nan")]), 1),
+    (dict(aperture=-1.0), 1), (dict(aperture=float("inf")), 1),
 ])
 def test_invalid_configs_are_rejected(bad, status):
     st, _ = ws(cfg(**bad))

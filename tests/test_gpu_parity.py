@@ -64,6 +64,27 @@ def tiny(O, **kw):
 
 
 # ---------------------------------------------------------------------------
+def test_aperture_matches_oracle(O):
+    """The circular aperture of Alg. 3 in the library's transfer table and in
+    propagation: a radius of 30 bins on a 96 x 120 padded grid, two planes."""
+    H, W, C, lams, zs = 48, 60, 2, [639e-9, 473e-9], [2e-3, -3e-3]
+    ctx = binding.Context(H, W, C, 8e-6, lams, zs, pad=(96, 120), max_gaussians=1, aperture=30.0)
+    opt = O.Optics(H, W, C, 96, 120, 8e-6, lams, zs, aperture=30.0)
+    for ch in range(C):
+        for l in range(2):
+            h = ctx.get_transfer(ch, l).cpu().numpy()
+            full = O.transfer(96, 120, 8e-6, lams[ch], zs[l], aperture=30.0)
+            assert np.count_nonzero(full[:49, :61]) == np.count_nonzero(h)
+            assert rel_l2(h, full[:49, :61]) <= 1e-7
+    rng = np.random.default_rng(9)
+    f = (rng.standard_normal((C, H, W)) + 1j * rng.standard_normal((C, H, W))).astype(np.complex64)
+    _, u = ctx.propagate(torch.from_numpy(f).cuda(), intensity=False, field_out=True)
+    u_ref = O.propagate(f.astype(np.complex128), opt)
+    assert rel_l2(u.cpu().numpy(), u_ref) <= FIELD_TOL
+    assert rel_l2(u_ref, O.propagate(f.astype(np.complex128),
+                                     O.Optics(H, W, C, 96, 120, 8e-6, lams, zs))) > 0.05
+
+
 def test_transfer_table_matches_oracle(O):
     for name in ("tiny_256", "bandlimit_stress"):
         w = WORK[name]
