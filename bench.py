@@ -469,6 +469,64 @@ def run_autodiff(ctx, binding, P0, T, n, C, H, W, Hp, Wp, dev, reps=3):
     return out
 
 
+def run_serving(binding, dev, holograms, steps, seed=300, candidates=(1, 2, 4)):
+    """The serving batch: ``holograms`` seeded requests of sizes drawn from
+    the five classes (512^2 .. 2048^2, one colour, n = pixels / 5, random
+    wavelength of three and z in [2, 10] mm), each a ``steps``-step Adam solve
+    captured as one HIP graph, scheduled over concurrent streams.  The stream
+    count is autotuned (each candidate: one warm-up run, one timed run); the
+    reported batch is the timed run of the best.  The same batch solved by
+    eager per-kernel calls on one stream is timed beside it."""
+    import torch
+    from paper_2511_15022_amd import serve
+    reqs = serve.make_requests(holograms, seed=seed, device=dev)
+    server = serve.Server(steps, max_streams=max(candidates), device=dev)
+    costs = server.measure_class_costs(reqs)
+    rates, runs = {}, {}
+    for k in candidates:
+        server.run(reqs, streams=k)
+        runs[k] = server.run(reqs, streams=k)
+        rates[k] = len(reqs) / runs[k]["wall_s"]
+        log(f"[bench]   serving: {k} stream(s): {rates[k]:.2f} holograms/s")
+    best = max(rates, key=lambda k: (rates[k], -k))
+    out = serve.summary(reqs, runs[best])
+    classes = {}
+    for r in reqs:
+        classes.setdefault(f"{r.H}x{r.W}", 0)
+        classes[f"{r.H}x{r.W}"] += 1
+    # eager comparator: the same solves, one host call per kernel group, one stream
+    ctxs = {key: server.slot(0, *key, key[0] * key[1] // 5).ctx for key in costs}
+    bufs = {key: torch.empty_like(next(r.params for r in reqs if (r.H, r.W) == key))
+            for key in costs}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        ctx = ctxs[(r.H, r.W)]
+        P = bufs[(r.H, r.W)]
+        P.copy_(r.params)
+        ctx.set_optics([r.wavelength], [r.z])
+        serve.solve_eager(ctx, P, r.n, r.target, steps)
+    torch.cuda.synchronize()
+    eager_s = time.perf_counter() - t0
+    final_psnr = [float(r.out_loss[-1, 1].item()) for r in reqs]
+    first_psnr = [float(r.out_loss[0, 1].item()) for r in reqs]
+    out.update({
+        "steps_per_solve": steps,
+        "streams": best,
+        "autotune_holograms_per_s": {str(k): v for k, v in rates.items()},
+        "class_counts": classes,
+        "class_solve_ms": {f"{h}x{w}": v for (h, w), v in costs.items()},
+        "class_step_us": {f"{h}x{w}": 1e3 * v / steps for (h, w), v in costs.items()},
+        "eager_one_stream_holograms_per_s": len(reqs) / eager_s,
+        "graph_speedup_vs_eager": (len(reqs) / runs[best]["wall_s"]) / (len(reqs) / eager_s),
+        "psnr_db_first_step_median": float(np.median(first_psnr)),
+        "psnr_db_last_step_median": float(np.median(final_psnr)),
+        "data": "synthetic, seeded (see DESIGN.md input recipe)",
+    })
+    del server, reqs
+    return out
+
+
 def run_paper_loss(binding, w, p, T, Mk, n, steps, dev, weight=0.005):
     """The same step with the paper's final loss, L_recon (L_MSE without masks)
     + weight L_SSIM, on a context that holds the SSIM workspace; times `steps`
@@ -537,6 +595,10 @@ def main():
                     help="training steps of the learned initialiser (0: skip)")
     ap.add_argument("--paper-loss-steps", type=int, default=20,
                     help="timed steps with the paper's final loss, L + 0.005 L_SSIM (0: skip)")
+    ap.add_argument("--serving-holograms", type=int, default=64,
+                    help="holograms in the serving batch (0: skip)")
+    ap.add_argument("--serving-steps", type=int, default=300,
+                    help="Adam steps per hologram solve in the serving batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -751,6 +813,20 @@ def main():
             autodiff = {"error": f"{type(e).__name__}: {e}"[:300]}
         torch.cuda.empty_cache()
 
+    serving = None
+    if args.serving_holograms > 0 and args.workload == "rgb_1080p":
+        log(f"[bench] serving batch: {args.serving_holograms} holograms x "
+            f"{args.serving_steps} steps")
+        try:
+            serving = run_serving(binding, dev, args.serving_holograms, args.serving_steps)
+            log(f"[bench]   {serving['holograms_per_s']:.2f} holograms/s on "
+                f"{serving['streams']} stream(s); latency p50 {serving['latency_p50_ms']:.1f} ms "
+                f"p99 {serving['latency_p99_ms']:.1f} ms; eager "
+                f"{serving['eager_one_stream_holograms_per_s']:.2f} holograms/s")
+        except Exception as e:
+            serving = {"error": f"{type(e).__name__}: {e}"[:300]}
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -795,6 +871,7 @@ def main():
         "learned_init": learned,
         "autodiff": autodiff,
         "paper_loss": paper_loss,
+        "serving_batch": serving,
         "kernels_us_per_step": {k: round(v["ms_per_step"] * 1e3, 2) for k, v in kernels.items()},
         "tile_pairs": pairs,
         "peak_vram_gb": peak_vram / 1e9,

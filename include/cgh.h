@@ -271,11 +271,52 @@ cgh_status cgh_read_status(cgh_ctx *ctx, void *stream, int64_t *pairs);
 cgh_status cgh_profile_begin(cgh_ctx *ctx, int32_t kernel_class);
 cgh_status cgh_profile_end(cgh_ctx *ctx, void *stream, double *total_ms, int32_t *launches);
 
+/* Replaces the wavelengths and propagation distances of an existing context
+ * and rebuilds its transfer functions H(fx, fy; lambda_c, z_l) in FP64 on
+ * `stream`, the same tables cgh_create builds, so that one context and its
+ * workspace serve holograms of one size under different optics.
+ *   wavelength_m: HOST array of C values (> 0, finite), metres;
+ *   z_m         : HOST array of L values (finite), metres.
+ * Stream-ordered: work enqueued earlier on `stream` still reads the old
+ * tables; work on other streams must be ordered against this call by the
+ * caller.  Argument errors leave the context unchanged.  Does not wait. */
+cgh_status cgh_set_optics(cgh_ctx *ctx, const double *wavelength_m, const double *z_m,
+                          void *stream);
+
+/* A plain-optimiser solve (Alg. 1 with L_MSE and Adam) captured once as a HIP
+ * graph, so that one launch replaces the host's per-kernel launches of every
+ * step.  Each launch of the graph first zeroes m and v, then, for
+ * t = 1 .. steps, runs exactly the kernels of
+ *   cgh_rasterize(ctx, params, n, field);
+ *   cgh_backward(ctx, params, n, field, target, loss_log + 2 (t - 1), NULL, grads);
+ *   cgh_step(params, grads, m, v, count, t, lr, beta1, beta2, eps, NULL, C)
+ * (count = n (6 + 2C)), with the same results bit for bit.  The graph binds
+ * the pointers given here: a launch optimises from whatever params and target
+ * hold when it starts and leaves the optimised parameters in params;
+ * loss_log (device double[2 steps]) receives {L, 10 log10(1 / L)} before each
+ * step.  Buffers and their layouts as in those calls; grads, m and v hold
+ * count floats.  steps: 1 .. 10000.  stream must not be NULL (the legacy
+ * stream cannot be captured); cgh_solve_create records the graph without
+ * running it and returns CGH_ERR_STATE while kernel timing
+ * (cgh_profile_begin) is active on ctx.  The context, its workspace and the
+ * bound buffers must outlive the solve, and nothing else may use the context
+ * while a launch runs (launches on one stream are ordered; across streams the
+ * caller orders them). */
+typedef struct cgh_solve cgh_solve;
+cgh_status cgh_solve_create(cgh_ctx *ctx, float *params, int32_t n, const float *target,
+                            cgh_c64 *field, float *grads, float *m, float *v, double *loss_log,
+                            int32_t steps, float lr, float beta1, float beta2, float eps,
+                            void *stream, cgh_solve **out);
+/* Enqueues one launch of the solve's graph on `stream` (not NULL). */
+cgh_status cgh_solve_launch(cgh_solve *solve, void *stream);
+/* Releases the graph (the buffers stay the caller's). */
+cgh_status cgh_solve_destroy(cgh_solve *solve);
+
 /* Message for the last non-OK status returned on this thread. */
 const char *cgh_last_error(void);
 
 /* ABI version of this header (CGH_ABI_VERSION). */
-#define CGH_ABI_VERSION 2
+#define CGH_ABI_VERSION 3
 int32_t cgh_abi_version(void);
 
 #ifdef __cplusplus

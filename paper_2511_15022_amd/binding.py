@@ -74,6 +74,12 @@ _SIGS = [
     ("cgh_profile_begin", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("cgh_profile_end", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int32)]),
+    ("cgh_set_optics", ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    ("cgh_solve_create", ctypes.c_int,
+     [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_float,
+      ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP, ctypes.POINTER(_VP)]),
+    ("cgh_solve_launch", ctypes.c_int, [_VP, _VP]),
+    ("cgh_solve_destroy", ctypes.c_int, [_VP]),
     ("cgh_last_error", ctypes.c_char_p, []),
     ("cgh_abi_version", ctypes.c_int32, []),
 ]
@@ -323,6 +329,18 @@ class Context:
                                       _stream(self.device)))
         return out
 
+    def set_optics(self, wavelengths, zs, stream=None):
+        """cgh_set_optics: new wavelengths ([C]) and distances ([L]) for this
+        context; the transfer tables are rebuilt on ``stream`` (default: the
+        current stream)."""
+        if len(wavelengths) != self.C or len(zs) != self.L:
+            raise ValueError(f"need {self.C} wavelengths and {self.L} distances")
+        lam = (ctypes.c_double * self.C)(*[float(x) for x in wavelengths])
+        zz = (ctypes.c_double * self.L)(*[float(x) for x in zs])
+        st = _stream(self.device) if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(lib().cgh_set_optics(self.handle, ctypes.cast(lam, ctypes.c_void_p),
+                                    ctypes.cast(zz, ctypes.c_void_p), st))
+
     def profile_begin(self, kernel_class):
         _check(lib().cgh_profile_begin(self.handle, int(KERNEL_CLASSES[kernel_class])))
 
@@ -339,6 +357,52 @@ class Context:
         if st != 0 and (raise_on_overflow or st != 3):
             _check(st)
         return pairs.value, st == 0
+
+
+class Solve:
+    """cgh_solve_*: ``steps`` Adam steps of L_MSE on ``ctx`` captured once as a
+    HIP graph over the given buffers (params and target are read when a launch
+    starts; params holds the result).  The solve owns its field, gradient,
+    moment and loss-log buffers (``self.loss_log``: [steps][2] doubles)."""
+
+    def __init__(self, ctx, params, n, target, steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 stream=None):
+        dev = ctx.device
+        _need(params, torch.float32, param_count(n, ctx.C), "params", dev)
+        _need(target, torch.float32, ctx.L * ctx.C * ctx.H * ctx.W, "target", dev)
+        self.ctx, self.n, self.steps = ctx, n, steps
+        self.params, self.target = params, target
+        self.field = torch.empty(ctx.field_shape(), dtype=torch.complex64, device=dev)
+        self.grads = torch.empty_like(params)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.loss_log = torch.zeros((steps, 2), dtype=torch.float64, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        handle = ctypes.c_void_p()
+        _check(lib().cgh_solve_create(ctx.handle, _ptr(params), int(n), _ptr(target),
+                                      _ptr(self.field), _ptr(self.grads), _ptr(self.m),
+                                      _ptr(self.v), _ptr(self.loss_log), int(steps), float(lr),
+                                      float(beta1), float(beta2), float(eps),
+                                      ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(handle)))
+        self.handle = handle
+        ctx.last_n = n
+
+    def launch(self, stream=None):
+        """Enqueues one solve on ``stream`` (default: the stream it was made on)."""
+        s = self.stream if stream is None else stream
+        _check(lib().cgh_solve_launch(self.handle, ctypes.c_void_p(s.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cgh_solve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def step(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, lr_groups=None,

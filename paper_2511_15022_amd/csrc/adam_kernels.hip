@@ -2,6 +2,7 @@
 // Adam (Kingma & Ba, Algorithm 1) and Adan (Xie et al., Adan: adaptive
 // Nesterov momentum, Algorithm 1, with bias-corrected moments), the
 // optimiser the paper trains with (Sec. 4).
+#include <algorithm>
 #include <cmath>
 
 #include "cgh_internal.h"
@@ -184,6 +185,23 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t cou
   const int64_t threads = (count + 3) / 4;
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, p, g, m,
                      v, count, lr * step_size_scale, beta1, beta2, eps, inv_sqrt_bc2, gr, use);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_zero_pair(float *__restrict__ a, float *__restrict__ b,
+                                                   int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += stride) {
+    a[i] = 0.f;
+    b[i] = 0.f;
+  }
+}
+
+// a[0 .. count) = b[0 .. count) = 0 by a kernel (no memset node when captured)
+hipError_t launch_zero_pair(float *a, float *b, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero_pair, dim3((unsigned)blocks), dim3(256), 0, s, a, b, count);
   return hipGetLastError();
 }
 

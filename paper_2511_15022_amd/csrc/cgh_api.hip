@@ -669,6 +669,116 @@ cgh_status cgh_profile_end(cgh_ctx *ctx, void *stream, double *total_ms, int32_t
   return CGH_OK;
 }
 
+cgh_status cgh_set_optics(cgh_ctx *ctx, const double *wavelength_m, const double *z_m,
+                          void *stream) {
+  if (!ctx || !wavelength_m || !z_m) return fail(CGH_ERR_INVALID_ARG, "ctx/wavelength/z is NULL");
+  Ctx &c = ctx->c;
+  for (int ch = 0; ch < c.C; ++ch)
+    if (!(wavelength_m[ch] > 0.0) || !std::isfinite(wavelength_m[ch]))
+      return fail(CGH_ERR_INVALID_ARG, "wavelength of channel %d must be positive", ch);
+  for (int l = 0; l < c.L; ++l)
+    if (!std::isfinite(z_m[l])) return fail(CGH_ERR_INVALID_ARG, "z of plane %d not finite", l);
+  for (int ch = 0; ch < c.C; ++ch) c.cfg.wavelength_m[ch] = wavelength_m[ch];
+  for (int l = 0; l < c.L; ++l) c.cfg.z_m[l] = z_m[l];
+  CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, (hipStream_t)stream), "transfer function");
+  return CGH_OK;
+}
+
+}  // extern "C"
+
+struct cgh_solve {
+  hipGraphExec_t exec;
+};
+
+namespace {
+
+// The kernels of one solve, enqueued on s (which is capturing).
+cgh_status record_solve(cgh_ctx *ctx, float *params, int32_t n, const float *target,
+                        cgh_c64 *field, float *grads, float *m, float *v, double *loss_log,
+                        int32_t steps, float lr, float beta1, float beta2, float eps,
+                        hipStream_t s) {
+  const int64_t count = (int64_t)n * (6 + 2 * ctx->c.C);
+  CGH_CHECK_LAUNCH(cgh::launch_zero_pair(m, v, count, s), "solve: zero moments");
+  for (int32_t t = 1; t <= steps; ++t) {
+    cgh_status st = cgh_rasterize(ctx, params, n, field, s);
+    if (st == CGH_OK)
+      st = cgh_backward(ctx, params, n, field, target, loss_log + 2 * (int64_t)(t - 1), nullptr,
+                        grads, s);
+    if (st == CGH_OK)
+      st = cgh_step(params, grads, m, v, count, t, lr, beta1, beta2, eps, nullptr, ctx->c.C, s);
+    if (st != CGH_OK) return st;
+  }
+  return CGH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cgh_status cgh_solve_create(cgh_ctx *ctx, float *params, int32_t n, const float *target,
+                            cgh_c64 *field, float *grads, float *m, float *v, double *loss_log,
+                            int32_t steps, float lr, float beta1, float beta2, float eps,
+                            void *stream, cgh_solve **out) {
+  if (!out) return fail(CGH_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  if (!stream) return fail(CGH_ERR_INVALID_ARG, "the NULL stream cannot be captured");
+  cgh_status st = check_n(ctx->c, n);
+  if (st != CGH_OK) return st;
+  if (n < 1) return fail(CGH_ERR_INVALID_ARG, "a solve needs n >= 1");
+  if (steps < 1 || steps > 10000) return fail(CGH_ERR_INVALID_ARG, "steps must be in [1, 10000]");
+  if (!params || !target || !field || !grads || !m || !v || !loss_log)
+    return fail(CGH_ERR_INVALID_ARG, "NULL buffer");
+  if (!aligned16(params) || !aligned16(grads) || !aligned16(m) || !aligned16(v) ||
+      !aligned16(field) || ((uintptr_t)loss_log & 7u))
+    return fail(CGH_ERR_INVALID_ARG, "misaligned buffer");
+  if (!(lr >= 0.f) || !std::isfinite(lr) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+    return fail(CGH_ERR_INVALID_ARG, "lr must be >= 0, betas in [0, 1), eps >= 0");
+  if (ctx->c.prof_class)
+    return fail(CGH_ERR_STATE, "kernel timing is active on this context");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return device_fail(e, "cgh_solve_create: begin capture");
+  st = record_solve(ctx, params, n, target, field, grads, m, v, loss_log, steps, lr, beta1, beta2,
+                    eps, s);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(s, &graph);
+  if (st != CGH_OK) {
+    if (graph) (void)hipGraphDestroy(graph);  // the recorded error is the one to report
+    return st;
+  }
+  if (e != hipSuccess) return device_fail(e, "cgh_solve_create: end capture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);  // the executable graph no longer needs it
+  if (e != hipSuccess) return device_fail(e, "cgh_solve_create: instantiate");
+  cgh_solve *h = new (std::nothrow) cgh_solve;
+  if (!h) {
+    (void)hipGraphExecDestroy(exec);
+    return fail(CGH_ERR_INVALID_ARG, "host allocation failed");
+  }
+  h->exec = exec;
+  *out = h;
+  return CGH_OK;
+}
+
+cgh_status cgh_solve_launch(cgh_solve *solve, void *stream) {
+  if (!solve) return fail(CGH_ERR_INVALID_ARG, "solve is NULL");
+  if (!stream) return fail(CGH_ERR_INVALID_ARG, "stream is NULL");
+  hipError_t e = hipGraphLaunch(solve->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "cgh_solve_launch");
+  return CGH_OK;
+}
+
+cgh_status cgh_solve_destroy(cgh_solve *solve) {
+  if (!solve) return CGH_OK;
+  hipError_t e = hipGraphExecDestroy(solve->exec);
+  delete solve;
+  if (e != hipSuccess) return device_fail(e, "cgh_solve_destroy");
+  return CGH_OK;
+}
+
 cgh_status cgh_read_status(cgh_ctx *ctx, void *stream, int64_t *pairs) {
   if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
   Ctx &c = ctx->c;

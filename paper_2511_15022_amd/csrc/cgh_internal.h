@@ -155,6 +155,7 @@ hipError_t launch_preprocess_adjoint(const Ctx &c, const float *params, int n, f
 hipError_t launch_adan(float *p, const float *g, float *m, float *d, float *s, float *gprev,
                        int64_t count, int t, float lr, float b1, float b2, float b3, float eps,
                        float wd, const float *lr_groups, int n, int C, hipStream_t st);
+hipError_t launch_zero_pair(float *a, float *b, int64_t count, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr,
                        float step_size_scale, float beta1, float beta2, float eps,
                        float inv_sqrt_bc2, const float *lr_groups, int n, int C,

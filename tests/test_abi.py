@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     for name in (declared_functions() + declared_functions(NET_HEADER) +
                  declared_functions(POH_HEADER)):
         assert hasattr(L, name), name
-    assert L.cgh_abi_version() == 2
+    assert L.cgh_abi_version() == 3
 
 
 def cfg(**kw):
@@ -137,6 +137,15 @@ def test_null_arguments_are_rejected_without_device_work():
     c = cfg()
     out = ctypes.c_void_p()
     assert L.cgh_create(ctypes.byref(c), None, 0, None, ctypes.byref(out)) == 1
+    lam = (ctypes.c_double * 1)(515e-9)
+    assert L.cgh_set_optics(None, ctypes.cast(lam, ctypes.c_void_p),
+                            ctypes.cast(lam, ctypes.c_void_p), None) == 1
+    assert L.cgh_solve_create(None, None, 1, None, None, None, None, None, None, 10, 1e-3, 0.9,
+                              0.999, 1e-8, None, ctypes.byref(out)) == 1
+    assert L.cgh_solve_create(None, None, 1, None, None, None, None, None, None, 10, 1e-3, 0.9,
+                              0.999, 1e-8, None, None) == 1
+    assert L.cgh_solve_launch(None, None) == 1
+    assert L.cgh_solve_destroy(None) == 0
 
 
 def test_net_argument_checks_and_workspace_sizes():
