@@ -26,6 +26,8 @@
 // which halves the LDS footprint of a column block.
 #include <cmath>
 
+#include <type_traits>
+
 #include "cgh_internal.h"
 #include "fft_reg.h"
 
@@ -1074,8 +1076,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 // rows per row-pass workgroup (specialised lengths use 4, the runtime path 2)
 static bool row_specialised(int Wp) { return Wp == 3840 || Wp == 512; }
 // the half-length row passes take Wp = 3840 (1080p) and 7680 (4K) with W <= Wp / 2
-// the quarter-length row passes take Wp = 7680 (4K) with W <= Wp / 2, one row per workgroup
-static bool row_quarter(const Ctx &c) { return c.Wp == 7680 && 2 * c.W <= c.Wp; }
+// the quarter-length row passes take Wp = 4 M with W <= Wp / 2, one row per workgroup,
+// for the chain lengths they are built for (4K: 1920; 1024 .. 4096 pads: 256, 512, 1024);
+// quarter_m returns M, or 0 where they do not apply
+static int quarter_m(const Ctx &c) {
+  if (c.Wp % 4 != 0 || 2 * c.W > c.Wp) return 0;
+  const int M = c.Wp / 4;
+  return (M == 1920 || M == 1024 || M == 512 || M == 256) ? M : 0;
+}
+static bool row_quarter(const Ctx &c) { return quarter_m(c) != 0; }
+// calls f(std::integral_constant<int, M>) for the quarter length of c
+template <class F>
+static void with_quarter(const Ctx &c, F &&f) {
+  switch (quarter_m(c)) {
+    case 1920: f(std::integral_constant<int, 1920>{}); break;
+    case 1024: f(std::integral_constant<int, 1024>{}); break;
+    case 512: f(std::integral_constant<int, 512>{}); break;
+    default: f(std::integral_constant<int, 256>{}); break;
+  }
+}
 static bool row_half(const Ctx &c) { return (c.Wp == 3840 || c.Wp == 7680) && 2 * c.W <= c.Wp; }
 int row_group_rows(const Ctx &c) {
   return c.Wp == 512 ? 4 : (row_quarter(c) ? 1 : (row_half(c) ? kRowHalfRows : 2));
@@ -1088,8 +1107,10 @@ static size_t row_lds(const Ctx &c) { return (size_t)2 * c.Wp * sizeof(float2); 
 
 hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStream_t s) {
   if (row_quarter(c))
-    hipLaunchKernelGGL(k_row_fwd_q<1920>, dim3(row_blocks(c)), dim3(512), 0, s, field, c.H, c.W,
-                       row_blocks(c), c.twf_x, dst);
+    with_quarter(c, [&](auto mc) {
+      hipLaunchKernelGGL(k_row_fwd_q<decltype(mc)::value>, dim3(row_blocks(c)), dim3(512), 0, s,
+                         field, c.H, c.W, row_blocks(c), c.twf_x, dst);
+    });
   else if (row_half(c) && c.Wp == 7680)
     hipLaunchKernelGGL((k_row_fwd_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
                        dim3(256 * kRowHalfRows), 0, s, field, c.H, c.W, c.twf_x, dst);
@@ -1114,8 +1135,10 @@ hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStr
 
 hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStream_t s) {
   if (row_quarter(c))
-    hipLaunchKernelGGL(k_row_inv_q<1920>, dim3(row_blocks(c)), dim3(512), 0, s, src, c.H, c.W,
-                       row_blocks(c), c.twf_x, out);
+    with_quarter(c, [&](auto mc) {
+      hipLaunchKernelGGL(k_row_inv_q<decltype(mc)::value>, dim3(row_blocks(c)), dim3(512), 0, s,
+                         src, c.H, c.W, row_blocks(c), c.twf_x, out);
+    });
   else if (row_half(c) && c.Wp == 7680)
     hipLaunchKernelGGL((k_row_inv_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
                        dim3(256 * kRowHalfRows), 0, s, src, c.H, c.W, c.twf_x, out);
@@ -1152,9 +1175,11 @@ hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *ta
   if (mask) mask += (size_t)plane * c.H * c.W;  // [L][H][W]
   double *lp = c.loss_part + (size_t)plane * row_blocks(c);
   if (row_quarter(c))
-    hipLaunchKernelGGL(k_row_loss_q<1920>, dim3(row_blocks(c)), dim3(512), 0, s, buf, c.H, c.W,
-                       row_blocks(c), c.twf_x, target, grad_intensity, mask, intensity, u_out, lp,
-                       gscale, make_grad);
+    with_quarter(c, [&](auto mc) {
+      hipLaunchKernelGGL(k_row_loss_q<decltype(mc)::value>, dim3(row_blocks(c)), dim3(512), 0, s,
+                         buf, c.H, c.W, row_blocks(c), c.twf_x, target, grad_intensity, mask,
+                         intensity, u_out, lp, gscale, make_grad);
+    });
   else if (row_half(c) && c.Wp == 7680)
     hipLaunchKernelGGL((k_row_loss_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
                        dim3(256 * kRowHalfRows), 0, s, buf, c.H, c.W, c.twf_x, target,
@@ -1793,12 +1818,25 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
   } else if (col_wave4(c)) {
     const int pairs = c.C * ((c.Wt + 1) / 2);
     const float2 *ht = c.htab_t + (size_t)plane * tab;
-    if (conj_h)
-      hipLaunchKernelGGL((k_col_wave4<9, 6, 20, true>), dim3((pairs + 7) / 8 * 64), dim3(512),
-                         0, s, io, ht, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_y);
-    else
-      hipLaunchKernelGGL((k_col_wave4<9, 6, 20, false>), dim3((pairs + 7) / 8 * 64), dim3(512),
-                         0, s, io, ht, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_y);
+    const dim3 grid4((pairs + 7) / 8 * 64);
+    // M = R0 R1 R2 with M / R2 <= 64 (one fused butterfly per lane)
+    auto go = [&](auto r0, auto r1, auto r2) {
+      constexpr int R0 = decltype(r0)::value, R1 = decltype(r1)::value, R2 = decltype(r2)::value;
+      if (conj_h)
+        hipLaunchKernelGGL((k_col_wave4<R0, R1, R2, true>), grid4, dim3(512), 0, s, io, ht, c.Hq,
+                           c.H, c.Wp, c.Wt, c.C, c.twf_y);
+      else
+        hipLaunchKernelGGL((k_col_wave4<R0, R1, R2, false>), grid4, dim3(512), 0, s, io, ht,
+                           c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_y);
+    };
+    using std::integral_constant;
+    switch (col_wave4_m(c)) {
+      case 1080: go(integral_constant<int, 9>{}, integral_constant<int, 6>{}, integral_constant<int, 20>{}); break;
+      case 1024: go(integral_constant<int, 8>{}, integral_constant<int, 8>{}, integral_constant<int, 16>{}); break;
+      case 512: go(integral_constant<int, 8>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
+      case 384: go(integral_constant<int, 6>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
+      default: go(integral_constant<int, 4>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
+    }
   } else if (c.Hp == 4320 && c.H <= 2160 && c.Wp % 8 == 0) {
     hipLaunchKernelGGL((k_col_both<2160, 512>), dim3(2 * c.Wt, c.C), dim3(512), 0, s, io, c.H,
                        c.Wp, c.Wt, c.twf_m, c.tw_y, c.Wq, conj_h, scale);

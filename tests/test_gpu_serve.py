@@ -194,3 +194,51 @@ def test_serving_sizes_propagation_match_oracle(O, H, W):
     # dL/dI = g  =>  dL/du = 2 g u, then the adjoint propagation
     gf_ref = O.propagate_adjoint(2.0 * g.astype(np.float64) * u_ref, opt)
     assert rel_l2(gf.cpu().numpy(), gf_ref) <= FIELD_TOL
+
+
+@pytest.mark.parametrize("case", [
+    # quarter rows M = 512 (W < 2M), four-chain columns M = 384 (H < 2M), 2 colours x 2 planes
+    dict(H=700, W=900, Hp=1536, Wp=2048, C=2, zs=[3e-3, -6e-3]),
+    # quarter rows M = 256, four-chain columns M = 256
+    dict(H=300, W=500, Hp=1024, Wp=1024, C=1, zs=[4e-3]),
+    # four-chain columns M = 256 with an odd number of column tiles (15), runtime rows
+    dict(H=400, W=60, Hp=1024, Wp=120, C=2, zs=[2e-3]),
+])
+def test_four_chain_pads_ragged_match_oracle(O, case):
+    """The quarter-length row passes and four-chain column passes at the
+    serving pads with ragged H, W (fewer rows/columns than half the pad),
+    several colours and planes: propagation, its adjoint and a fused
+    forward + backward with Gaussians against the oracle."""
+    say("four-chain pads", case)
+    H, W, Hp, Wp, C, zs = (case[k] for k in ("H", "W", "Hp", "Wp", "C", "zs"))
+    lams = [639e-9, 473e-9][:C]
+    L = len(zs)
+    rng = np.random.default_rng(161)
+    f = (rng.standard_normal((C, H, W)) + 1j * rng.standard_normal((C, H, W))).astype(np.complex64)
+    gI = rng.standard_normal((L, C, H, W)).astype(np.float32)
+    n = 600
+    ctx = binding.Context(H, W, C, 8e-6, lams, zs, pad=(Hp, Wp), max_gaussians=n)
+    opt = O.Optics(H, W, C, Hp, Wp, 8e-6, lams, zs)
+    tf = torch.from_numpy(f).cuda()
+    _, u = ctx.propagate(tf, intensity=False, field_out=True)
+    g = ctx.propagate_adjoint(tf, torch.from_numpy(gI).cuda())
+    torch.cuda.synchronize()
+    u_ref = O.propagate(f.astype(np.complex128), opt)
+    assert rel_l2(u.cpu().numpy(), u_ref) <= FIELD_TOL
+    g_ref = O.propagate_adjoint(2.0 * gI.astype(np.float64) * u_ref, opt)
+    assert rel_l2(g.cpu().numpy(), g_ref) <= FIELD_TOL
+    p = synth.params(162, n, H, W, C)
+    T = synth.target(163, C, H, W, L=L)
+    P = binding.pack(p, device="cuda")
+    field = ctx.rasterize(P, n)
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss, grad_field=gfield)
+    torch.cuda.synchronize()
+    ref = O.forward_backward(p, T, opt)
+    assert abs(loss[0].item() - ref["loss"]) <= 1e-4 * ref["loss"]
+    assert rel_l2(gfield.cpu().numpy(), ref["grad_field"]) <= GRAD_TOL
+    views = binding.unpack(grads.cpu(), n, C)
+    for k in binding.PARAM_KEYS:
+        e = rel_l2(views[k].numpy(), ref["grads"][k])
+        assert e <= GRAD_TOL, (k, e)
