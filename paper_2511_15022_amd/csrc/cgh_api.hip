@@ -167,7 +167,7 @@ size_t carve(Ctx *c, char *base) {
   c->twf_x = (float2 *)take(sizeof(float2) * c->Wp);
   c->twf_m = (float2 *)take(sizeof(float2) * c->plan_m.n);
   c->htab = (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq);
-  const bool wave_cols = col_wave(*c) || col_wave4(*c);
+  const bool wave_cols = col_wave4(*c);
   c->htab_t = wave_cols ? (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq)
                         : nullptr;
   c->twf_y = wave_cols ? (float2 *)take(sizeof(float2) * c->Hp) : nullptr;

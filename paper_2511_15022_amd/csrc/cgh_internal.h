@@ -112,16 +112,15 @@ constexpr int kMaxProf = 256;
 size_t carve(Ctx *c, char *base);   // returns bytes used (base may be null)
 cgh_status report(cgh_status st, const char *fmt, ...);  // sets cgh_last_error()
 
-// The column pass runs one wave per column chain (k_col_wave) for Hp = 2160
-// with every column tile full; it reads the column-major transfer table.
-inline bool col_wave(const Ctx &c) { return c.Hp == 2160 && c.H <= 1080 && c.Wp % 8 == 0; }
-// ... and four chains per column (k_col_wave4) for Hp = 4 M with H <= 2 M and M
-// one of the chain lengths it is built for (4K: 1080; 1024^2 .. 4096^2 pads:
-// 256, 384, 512, 1024); returns M, or 0 where it does not apply
+// The column pass runs one wave per column chain, four chains per column
+// (k_col_wave4), for Hp = 4 M with H <= 2 M and M one of the chain lengths it is
+// built for (4K: 1080; 1080p: 540; 1024^2 .. 4096^2 pads: 256, 384, 512, 1024); it
+// reads the column-major transfer table.  col_wave4_m returns M, or 0 where it does
+// not apply.
 inline int col_wave4_m(const Ctx &c) {
   if (c.Hp % 4 != 0 || 2 * c.H > c.Hp || c.Wp % 8 != 0) return 0;
   const int M = c.Hp / 4;
-  return (M == 1080 || M == 1024 || M == 512 || M == 384 || M == 256) ? M : 0;
+  return (M == 1080 || M == 1024 || M == 540 || M == 512 || M == 384 || M == 256) ? M : 0;
 }
 inline bool col_wave4(const Ctx &c) { return col_wave4_m(c) != 0; }
 

@@ -631,224 +631,6 @@ __global__ __launch_bounds__(T) void k_row_loss_c(
 }
 
 // ----------------------------------------------------------------------------
-// Half-length row passes, for Wp = 2M with W <= M (3840: M = 1920).  As in the
-// column pass, splitting the Wp-point transform of a row by output parity
-// leaves two M-point chains: with the samples x[n] at n < W, bin 2m + p of
-// the forward is FFT_M(x[n] w^{pn})[m], and the inverse cropped to n < W is
-// e[n] + w^{-n} o[n], where e and o are the M-point inverses of the even and
-// odd bins (w = exp(-2 pi i / Wp)).  A workgroup of 256 threads per row takes
-// RW rows: 2 RW interleaved M-point chains, chain b = 2 r + p at
-// buf[m * 2 RW + b].  At half length the full M-entry twiddle table fits
-// beside the data, so no stage pays for two-level twiddles.
-// ----------------------------------------------------------------------------
-constexpr int kRowHalfRows = 2;  // rows per workgroup: 77 KB of LDS, two workgroups per CU
-
-// full M-entry table exp(-2 pi i e / M) = the even entries of the Wp table
-template <int M, int T>
-__device__ __forceinline__ void load_half_table(float2 *tw, const float2 *__restrict__ twf_x,
-                                                int tid) {
-  constexpr int KT = (M + T - 1) / T;
-  float2 tv[KT];
-#pragma unroll
-  for (int k = 0; k < KT; ++k) tv[k] = at32(twf_x, 2 * min(tid + k * T, M - 1));
-#pragma unroll
-  for (int k = 0; k < KT; ++k)
-    if (KT * T == M || tid + k * T < M) tw[tid + k * T] = tv[k];
-}
-
-// S (column-tiled, channel base Sc) rows y0 .. y0 + RW - 1 <-> the chains in
-// LDS: element i moves S[t][y0 + r][e] with t = i / (8 RW), r = (i / 8) % RW,
-// e = i % 8, i.e. bin x = 8 t + e of chain 2 r + (x & 1) at m = x / 2; each
-// tile's rows of the group are contiguous (8 RW consecutive threads, 64 RW
-// bytes).  Wt = M / 4 tiles.
-template <int M, int RW, int T>
-__device__ __forceinline__ void load_row_group(float2 *buf, const float2 *Sc, int H, int y0,
-                                               int tid) {
-  constexpr int n = 2 * M * RW, K = (n + T - 1) / T, B = 2 * RW;  // Wp bins per row
-  float2 v[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = min(tid + k * T, n - 1), t = i / (8 * RW), r = (i >> 3) % RW, e = i & 7;
-    v[k] = at32(Sc, (t * H + min(y0 + r, H - 1)) * 8 + e);
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, t = i / (8 * RW), r = (i >> 3) % RW, e = i & 7, x = 8 * t + e;
-    if (K * T == n || i < n) buf[(x >> 1) * B + 2 * r + (x & 1)] = v[k];
-  }
-}
-
-template <int M, int RW, int T>
-__device__ __forceinline__ void store_row_group(const float2 *buf, float2 *Sc, int H, int y0,
-                                                int tid) {
-  constexpr int n = 2 * M * RW, K = (n + T - 1) / T, B = 2 * RW;  // Wp bins per row
-  float2 v[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = min(tid + k * T, n - 1), t = i / (8 * RW), r = (i >> 3) % RW, e = i & 7;
-    const int x = 8 * t + e;
-    v[k] = buf[(x >> 1) * B + 2 * r + (x & 1)];
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, t = i / (8 * RW), r = (i >> 3) % RW, e = i & 7;
-    if ((K * T == n || i < n) && y0 + r < H) at32(Sc, (t * H + y0 + r) * 8 + e) = v[k];
-  }
-}
-
-template <int M, int RW>
-__global__ __launch_bounds__(256 * RW) __attribute__((amdgpu_waves_per_eu(4))) void k_row_fwd_h(
-    const float2 *__restrict__ field, int H, int W, const float2 *__restrict__ twf_x,
-    float2 *__restrict__ S) {
-  constexpr int T = 256 * RW, B = 2 * RW, K = (RW * M + T - 1) / T, Wt = M / 4;
-  __shared__ float2 buf[B * M];
-  __shared__ float2 tw[M];
-  const int tid = threadIdx.x;
-  const int groups = (H + RW - 1) / RW;
-  const int c = blockIdx.x / groups, y0 = RW * (blockIdx.x - c * groups);
-  load_half_table<M, T>(tw, twf_x, tid);
-  {
-    // element i: row y0 + i / M, sample n = i % M; all loads issued first
-    const float2 *f0 = field + (size_t)c * H * W;
-    float2 xv[K], wv[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = min(tid + k * T, RW * M - 1), r = i / M, n = i - r * M;
-      xv[k] = at32(f0, min(y0 + r, H - 1) * W + min(n, W - 1));
-      wv[k] = at32(twf_x, n);
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = tid + k * T, r = i / M, n = i - r * M;
-      if (K * T == RW * M || i < RW * M) {
-        const float2 x = (n < W && y0 + r < H) ? xv[k] : make_float2(0.f, 0.f);
-        buf[n * B + 2 * r] = x;
-        buf[n * B + 2 * r + 1] = cmul(x, wv[k]);  // odd chain: x[n] w^n
-      }
-    }
-  }
-  __syncthreads();
-  cfft<-1, B, T, M>(buf, tw, tid);
-  store_row_group<M, RW, T>(buf, S + (size_t)c * Wt * H * 8, H, y0, tid);
-}
-
-template <int M, int RW>
-__global__ __launch_bounds__(256 * RW) __attribute__((amdgpu_waves_per_eu(4))) void k_row_inv_h(
-    const float2 *__restrict__ S, int H, int W, const float2 *__restrict__ twf_x,
-    float2 *__restrict__ out) {
-  constexpr int T = 256 * RW, B = 2 * RW, K = (RW * M + T - 1) / T, Wt = M / 4;
-  __shared__ float2 buf[B * M];
-  __shared__ float2 tw[M];
-  const int tid = threadIdx.x;
-  const int groups = (H + RW - 1) / RW;
-  const int c = blockIdx.x / groups, y0 = RW * (blockIdx.x - c * groups);
-  load_half_table<M, T>(tw, twf_x, tid);
-  load_row_group<M, RW, T>(buf, S + (size_t)c * Wt * H * 8, H, y0, tid);
-  // w^n of this thread's output elements (i: row y0 + i / W, n = i % W)
-  float2 wv[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = min(tid + k * T, RW * W - 1), r = i / W;
-    wv[k] = at32(twf_x, i - r * W);
-  }
-  lds_sync();
-  cfft<+1, B, T, M>(buf, tw, tid);
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, r = i / W, n = i - r * W;
-    if (i < RW * W && y0 + r < H) {
-      const float2 e = buf[n * B + 2 * r], o = buf[n * B + 2 * r + 1];
-      out[((size_t)c * H + y0 + r) * W + n] = cadd(e, cmul(cconj(wv[k]), o));
-    }
-  }
-}
-
-template <int M, int RW>
-__global__ __launch_bounds__(256 * RW) __attribute__((amdgpu_waves_per_eu(4))) void k_row_loss_h(
-    float2 *__restrict__ S, int H, int W, const float2 *__restrict__ twf_x,
-    const float *__restrict__ target, const float *__restrict__ grad_I,
-    const float *__restrict__ mask, float *__restrict__ intensity, float2 *__restrict__ u_out,
-    double *__restrict__ loss_part, float gscale, int make_grad) {
-  constexpr int T = 256 * RW, B = 2 * RW, K = (RW * M + T - 1) / T, Wt = M / 4;
-  __shared__ float2 buf[B * M];
-  __shared__ float2 tw[M];
-  __shared__ double red[T / 64];
-  const int tid = threadIdx.x;
-  const int groups = (H + RW - 1) / RW;
-  const int c = blockIdx.x / groups, y0 = RW * (blockIdx.x - c * groups);
-  float2 *Sc = S + (size_t)c * Wt * H * 8;
-  load_half_table<M, T>(tw, twf_x, tid);
-  load_row_group<M, RW, T>(buf, Sc, H, y0, tid);
-  // per-element inputs of this thread (i: row y0 + i / W, n = i % W): target
-  // and mask are fetched before the transform so that their latency overlaps
-  // it; the twiddles w^n (cached in L2) after it, to stay within 128 registers
-  const float *tsrc = target ? target : grad_I;
-  float tv[K], mv[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = min(tid + k * T, RW * W - 1), r = i / W, n = i - r * W;
-    const int y = min(y0 + r, H - 1);
-    tv[k] = tsrc ? tsrc[((size_t)c * H + y) * W + n] : 0.f;
-    mv[k] = mask ? mask[(size_t)y * W + n] : 0.f;
-  }
-  lds_sync();
-  cfft<+1, B, T, M>(buf, tw, tid);
-  float2 wv[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = min(tid + k * T, RW * W - 1), r = i / W;
-    wv[k] = at32(twf_x, i - r * W);
-  }
-  double acc = 0.0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, r = i / W, n = i - r * W;
-    if (i < RW * W) {
-      const float2 e = buf[n * B + 2 * r], o = buf[n * B + 2 * r + 1];
-      const float2 u = cadd(e, cmul(cconj(wv[k]), o));
-      float f = 0.f;
-      if (y0 + r < H) {
-        const float I = u.x * u.x + u.y * u.y;
-        const size_t at = ((size_t)c * H + y0 + r) * W + n;
-        if (intensity) intensity[at] = I;
-        if (u_out) u_out[at] = u;
-        if (target) {
-          // L_recon weight 1 + m^2 + t^2 (plain MSE without a mask)
-          const float d = I - tv[k], w = mask ? 1.f + mv[k] * mv[k] + tv[k] * tv[k] : 1.f;
-          acc += (double)d * (double)d * (double)w;
-          f = gscale * d * w;  // 4 w (I - T) / M
-        } else if (grad_I) {
-          f = 2.0f * tv[k];
-        }
-      }
-      if (make_grad) {
-        // inputs of the forward chains, g[n] and g[n] w^n, in the same slots
-        const float2 g = make_float2(f * u.x, f * u.y);
-        buf[n * B + 2 * r] = g;
-        buf[n * B + 2 * r + 1] = cmul(g, wv[k]);
-      }
-    }
-  }
-  if (make_grad)
-    for (int i = tid; i < B * (M - W); i += T) buf[B * W + i] = make_float2(0.f, 0.f);
-  if (target) {
-    for (int d = 32; d > 0; d >>= 1) acc += __shfl_down(acc, d, 64);
-    if ((tid & 63) == 0) red[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) {
-      double sum = 0.0;
-      for (int w = 0; w < T / 64; ++w) sum += red[w];
-      loss_part[blockIdx.x] = sum;
-    }
-  }
-  if (make_grad) {
-    __syncthreads();
-    cfft<-1, B, T, M>(buf, tw, tid);
-    store_row_group<M, RW, T>(buf, Sc, H, y0, tid);
-  }
-}
-
-// ----------------------------------------------------------------------------
 // Quarter-length row passes, for Wp = 4M with W <= 2M (7680: M = 1920).  With
 // the samples at n < 2M, bin 4m + p of the forward is FFT_M of
 // w^{pn}(x[n] + (-i)^p x[n + M]) (n < M), and the inverse cropped to n < 2M is
@@ -1077,12 +859,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 static bool row_specialised(int Wp) { return Wp == 3840 || Wp == 512; }
 // the half-length row passes take Wp = 3840 (1080p) and 7680 (4K) with W <= Wp / 2
 // the quarter-length row passes take Wp = 4 M with W <= Wp / 2, one row per workgroup,
-// for the chain lengths they are built for (4K: 1920; 1024 .. 4096 pads: 256, 512, 1024);
+// for the chain lengths they are built for (4K: 1920; 1080p: 960; 1024 .. 4096 pads:
+// 256, 512, 1024);
 // quarter_m returns M, or 0 where they do not apply
 static int quarter_m(const Ctx &c) {
   if (c.Wp % 4 != 0 || 2 * c.W > c.Wp) return 0;
   const int M = c.Wp / 4;
-  return (M == 1920 || M == 1024 || M == 512 || M == 256) ? M : 0;
+  return (M == 1920 || M == 1024 || M == 960 || M == 512 || M == 256) ? M : 0;
 }
 static bool row_quarter(const Ctx &c) { return quarter_m(c) != 0; }
 // calls f(std::integral_constant<int, M>) for the quarter length of c
@@ -1091,13 +874,13 @@ static void with_quarter(const Ctx &c, F &&f) {
   switch (quarter_m(c)) {
     case 1920: f(std::integral_constant<int, 1920>{}); break;
     case 1024: f(std::integral_constant<int, 1024>{}); break;
+    case 960: f(std::integral_constant<int, 960>{}); break;
     case 512: f(std::integral_constant<int, 512>{}); break;
     default: f(std::integral_constant<int, 256>{}); break;
   }
 }
-static bool row_half(const Ctx &c) { return (c.Wp == 3840 || c.Wp == 7680) && 2 * c.W <= c.Wp; }
 int row_group_rows(const Ctx &c) {
-  return c.Wp == 512 ? 4 : (row_quarter(c) ? 1 : (row_half(c) ? kRowHalfRows : 2));
+  return c.Wp == 512 ? 4 : (row_quarter(c) ? 1 : 2);
 }
 static int row_blocks(const Ctx &c) {
   const int r = row_group_rows(c);
@@ -1111,13 +894,6 @@ hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStr
       hipLaunchKernelGGL(k_row_fwd_q<decltype(mc)::value>, dim3(row_blocks(c)), dim3(512), 0, s,
                          field, c.H, c.W, row_blocks(c), c.twf_x, dst);
     });
-  else if (row_half(c) && c.Wp == 7680)
-    hipLaunchKernelGGL((k_row_fwd_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
-                       dim3(256 * kRowHalfRows), 0, s, field, c.H, c.W, c.twf_x, dst);
-  else if (row_half(c))
-    hipLaunchKernelGGL((k_row_fwd_h<1920, kRowHalfRows>), dim3(row_blocks(c)),
-                       dim3(256 * kRowHalfRows), 0, s, field,
-                       c.H, c.W, c.twf_x, dst);
   else if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_fwd_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
                        field, c.H, c.W, c.Wt, c.twf_x, c.tw_x, dst);
@@ -1139,13 +915,6 @@ hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStrea
       hipLaunchKernelGGL(k_row_inv_q<decltype(mc)::value>, dim3(row_blocks(c)), dim3(512), 0, s,
                          src, c.H, c.W, row_blocks(c), c.twf_x, out);
     });
-  else if (row_half(c) && c.Wp == 7680)
-    hipLaunchKernelGGL((k_row_inv_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
-                       dim3(256 * kRowHalfRows), 0, s, src, c.H, c.W, c.twf_x, out);
-  else if (row_half(c))
-    hipLaunchKernelGGL((k_row_inv_h<1920, kRowHalfRows>), dim3(row_blocks(c)),
-                       dim3(256 * kRowHalfRows), 0, s, src,
-                       c.H, c.W, c.twf_x, out);
   else if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_inv_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
                        src, c.H, c.W, c.Wt, c.twf_x, c.tw_x, out);
@@ -1180,15 +949,6 @@ hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *ta
                          buf, c.H, c.W, row_blocks(c), c.twf_x, target, grad_intensity, mask,
                          intensity, u_out, lp, gscale, make_grad);
     });
-  else if (row_half(c) && c.Wp == 7680)
-    hipLaunchKernelGGL((k_row_loss_h<3840, kRowHalfRows>), dim3(row_blocks(c)),
-                       dim3(256 * kRowHalfRows), 0, s, buf, c.H, c.W, c.twf_x, target,
-                       grad_intensity, mask, intensity, u_out, lp, gscale, make_grad);
-  else if (row_half(c))
-    hipLaunchKernelGGL((k_row_loss_h<1920, kRowHalfRows>), dim3(row_blocks(c)),
-                       dim3(256 * kRowHalfRows), 0, s, buf,
-                       c.H, c.W, c.twf_x, target, grad_intensity, mask, intensity, u_out, lp,
-                       gscale, make_grad);
   else if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_loss_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
                        buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, mask, intensity,
@@ -1532,141 +1292,23 @@ __global__ __launch_bounds__(T) void k_col_both(ColIO io, int H, int Wp, int Wt,
 }
 
 // ----------------------------------------------------------------------------
-// Column pass with one wave per chain, for M = Hp / 2 = R0 R1 R2 (1080 = 9 6 20);
-// CONJ: multiply by conj(H) (the adjoint pass).
-// A workgroup takes four columns of a tile; wave 2c + p runs chain p (even,
-// odd) of column c in its own M-element LDS buffer, so the stages of a chain
-// need no workgroup barrier: only loading the columns and combining the two
-// chains of a column are workgroup steps.  The forward plan is R0, R1, R2;
-// its last stage leaves lane j < M / R2 holding spectrum entries j + (M/R2) q
-// (q < R2), which is exactly the input of a first inverse stage of radix R2,
-// so the transfer multiply and that stage run in registers.  The inverse plan
-// is R2, R1, R0.  The transfer table is read column-major ([Wq][Hq]), and the
-// workgroups of a mirror pair of tiles (t, Wt - 1 - t), whose columns need the
-// same table columns, run back to back on one XCD (blocks b, b + 8, b + 16,
-// b + 24 share an XCD).
-// ----------------------------------------------------------------------------
-template <int R0, int R1, int R2, bool CONJ>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_col_wave(
-    ColIO io, const float2 *__restrict__ htab_t, int Hq, int H, int Wp, int Wt, int C,
-    const float2 *__restrict__ twf_m, const float2 *__restrict__ twf_y) {
-  constexpr int M = R0 * R1 * R2;
-  constexpr int NB2 = M / R2;
-  static_assert(NB2 <= 64, "the fused stage takes one butterfly per lane");
-  constexpr int T = 512, K = (4 * M + T - 1) / T, KT = (M + T - 1) / T;
-  __shared__ float2 buf[8 * M];
-  __shared__ float2 tw[M];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar addressing
-  const int b = blockIdx.x;
-  const int slot = (b >> 3) & 3, pi = (b >> 5) * 8 + (b & 7);
-  const int hp = (Wt + 1) >> 1;
-  if (pi >= C * hp) return;
-  const int ch = pi / hp, pp = pi - ch * hp;
-  const int t = slot < 2 ? pp : Wt - 1 - pp;
-  if (slot >= 2 && t == pp) return;  // the middle tile of an odd count has no mirror
-  const int part = slot & 1;
-  const size_t off = ((size_t)ch * Wt + t) * H * 8 + part * 4;
-  const float2 *src = io.src + off;
-  float2 *dst = io.dst + off;
-  {
-    // every global load of this phase is issued before the first LDS store
-    float2 xv[K], wv[K], tv[KT];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = tid + k * T, n = min(i >> 2, M - 1);
-      xv[k] = at32(src, min(n, H - 1) * 8 + (i & 3));
-      wv[k] = at32(twf_y, n);
-    }
-#pragma unroll
-    for (int k = 0; k < KT; ++k) tv[k] = at32(twf_m, min(tid + k * T, M - 1));
-#pragma unroll
-    for (int k = 0; k < KT; ++k)
-      if (tid + k * T < M) tw[tid + k * T] = tv[k];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = tid + k * T, n = i >> 2, c = i & 3;
-      if (K * T == 4 * M || i < 4 * M) {
-        const float2 x = n < H ? xv[k] : make_float2(0.f, 0.f);
-        buf[(2 * c) * M + n] = x;
-        buf[(2 * c + 1) * M + n] = cmul(x, wv[k]);  // odd chain input x[n] w^n
-      }
-    }
-  }
-  __syncthreads();
-  {
-    const int c = wave >> 1, p = wave & 1;
-    float2 *wb = buf + wave * M;
-    const int kx = t * 8 + part * 4 + c;
-    const int qx = min(kx, Wp - kx);
-    const float2 *hcol = htab_t + (size_t)ch * io.hstride + (size_t)qx * Hq;
-    // transfer values for ky = 2 (j + NB2 q) + p, issued before the forward stages
-    float2 hv[R2];
-    {
-      const int j = min(lane, NB2 - 1);
-      static_for<0, R2>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        const int ky = 2 * (j + NB2 * q) + p;
-        hv[q] = at32(hcol, min(ky, 2 * M - ky));
-      });
-    }
-    wstage<R0, -1, M, 1>(wb, tw, lane);
-    wstage<R1, -1, M, R0>(wb, tw, lane);
-    float2 v[R2];
-    if (lane < NB2) {
-      static_for<0, R2>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        v[q] = wb[lane + q * NB2];
-      });
-      static_for<1, R2>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        v[q] = cmul(v[q], tw[q * lane]);  // last forward stage: Ns = NB2, unit twiddle step
-      });
-      RFft<R2, -1>::run(v);
-      static_for<0, R2>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        v[q] = cmul(v[q], CONJ ? cconj(hv[q]) : hv[q]);  // the table carries 1 / (Hp Wp)
-      });
-      RFft<R2, +1>::run(v);  // first inverse stage: Ns = 1, no twiddles
-    }
-    wave_lds_order();
-    if (lane < NB2) {
-      static_for<0, R2>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        wb[lane * R2 + q] = v[q];
-      });
-    }
-    wave_lds_order();
-    wstage<R1, +1, M, R2>(wb, tw, lane);
-    wstage<R0, +1, M, R2 * R1>(wb, tw, lane);
-  }
-  {
-    float2 wv[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) wv[k] = at32(twf_y, min((tid + k * T) >> 2, M - 1));
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = tid + k * T, n = i >> 2, c = i & 3;
-      if ((K * T == 4 * M || i < 4 * M) && n < H) {
-        const float2 e = buf[(2 * c) * M + n], o = buf[(2 * c + 1) * M + n];
-        const float2 y = cadd(e, cmul(cconj(wv[k]), o));
-        float2 &d = at32(dst, n * 8 + c);
-        d = io.acc ? cadd(d, y) : y;
-      }
-    }
-  }
-}
-
-// ----------------------------------------------------------------------------
-// Column pass for Hp = 4 M (4320 = 4 x 1080) with H <= 2 M, one wave per chain.
+// Column pass for Hp = 4 M with H <= 2 M, one wave per chain, M = R0 R1 R2
+// (1080 = 9 6 20 at 4K, 540 = 9 6 10 at 1080p); CONJ: multiply by conj(H)
+// (the adjoint pass).
 // Output bin 4 m + p of the padded column is bin m of the M-point transform
 // of w^{p n} (x[n] + (-i)^p x[n + M]) (n < M; w = e^{-2 pi i / Hp}), so a
 // column is four M-point chains; the inverse gives u[n + M j] = sum_p
 // w^{-p n} i^{p j} z_p[n] for j = 0, 1.  A workgroup takes two columns of a
-// quarter tile; wave 4 c + p runs chain p of column c with the same
-// per-wave stages, fused transfer multiply and mirror-tile launch order as
-// k_col_wave (eight quarter tiles of a mirror pair, blocks b + 8 s).
+// quarter tile; wave 4 c + p runs chain p of column c in its own M-element
+// LDS buffer, so the stages of a chain need no workgroup barrier: only
+// loading the columns and combining the chains are workgroup steps.  The
+// forward plan is R0, R1, R2; its last stage leaves lane j < M / R2 holding
+// spectrum entries j + (M / R2) q (q < R2), exactly the input of a first
+// inverse stage of radix R2, so the transfer multiply and that stage run in
+// registers; the inverse plan is R2, R1, R0.  The transfer table is read
+// column-major ([Wq][Hq]); the eight quarter tiles of a mirror pair of tiles
+// (t, Wt - 1 - t), whose columns need the same table columns, are blocks
+// b + 8 s (s < 8), which share an XCD.
 // ----------------------------------------------------------------------------
 template <int R0, int R1, int R2, bool CONJ>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_col_wave4(
@@ -1806,16 +1448,7 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
   const size_t tab = (size_t)c.Hq * c.Wq;
   const ColIO io{src, dst, c.htab + (size_t)plane * tab, (size_t)c.L * tab, acc};
   dim3 grid(c.Wt, c.C);
-  if (col_wave(c)) {
-    const int pairs = c.C * ((c.Wt + 1) / 2);
-    const float2 *ht = c.htab_t + (size_t)plane * tab;
-    if (conj_h)
-      hipLaunchKernelGGL((k_col_wave<9, 6, 20, true>), dim3((pairs + 7) / 8 * 32), dim3(512), 0,
-                         s, io, ht, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_m, c.twf_y);
-    else
-      hipLaunchKernelGGL((k_col_wave<9, 6, 20, false>), dim3((pairs + 7) / 8 * 32), dim3(512), 0,
-                         s, io, ht, c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_m, c.twf_y);
-  } else if (col_wave4(c)) {
+  if (col_wave4(c)) {
     const int pairs = c.C * ((c.Wt + 1) / 2);
     const float2 *ht = c.htab_t + (size_t)plane * tab;
     const dim3 grid4((pairs + 7) / 8 * 64);
@@ -1833,6 +1466,7 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
     switch (col_wave4_m(c)) {
       case 1080: go(integral_constant<int, 9>{}, integral_constant<int, 6>{}, integral_constant<int, 20>{}); break;
       case 1024: go(integral_constant<int, 8>{}, integral_constant<int, 8>{}, integral_constant<int, 16>{}); break;
+      case 540: go(integral_constant<int, 9>{}, integral_constant<int, 6>{}, integral_constant<int, 10>{}); break;
       case 512: go(integral_constant<int, 8>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
       case 384: go(integral_constant<int, 6>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
       default: go(integral_constant<int, 4>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;

@@ -153,9 +153,10 @@ def test_propagation_adjoint_parity(O):
 
 
 def test_propagation_2160_rows(O):
-    """The 2160-row column pass (one wave per column chain) with fewer rows than
-    Hp / 2 and an odd number of column tiles (15: the middle tile has no mirror
-    partner): propagation and its adjoint against the oracle."""
+    """The 2160-row column pass (four 540-point chains per column, one wave
+    each) with fewer rows than Hp / 2 and an odd number of column tiles (15:
+    the middle tile has no mirror partner): propagation and its adjoint
+    against the oracle."""
     w = dict(H=1000, W=56, C=2, Hp=2160, Wp=120, pitch=8e-6, lambdas=[639e-9, 473e-9],
              zs=[4e-3])
     say("propagate 2160 rows", w)
@@ -215,7 +216,7 @@ def test_backward_parity(O, case):
     # runtime-plan column pass (Hp = 96: two 48-point chains)
     dict(H=40, W=56, C=2, n=200, lambdas=[639e-9, 473e-9], zs=[2e-3, -3e-3, 5e-3], Hp=96,
          Wp=120),
-    # the 2160-row column pass (one wave per column chain), on a narrow canvas
+    # the 2160-row column pass (four 540-point chains per column), on a narrow canvas
     dict(H=1080, W=48, C=1, n=2000, lambdas=[515e-9], zs=[3e-3, 6e-3], Hp=2160, Wp=96),
     # the 4320-row column pass (four chains per column), adjoint summed over planes
     dict(H=2160, W=24, C=2, n=1500, lambdas=[639e-9, 473e-9], zs=[3e-3, 7e-3], Hp=4320,
@@ -593,8 +594,8 @@ def test_full_loss_rejections(O):
 
 
 @pytest.mark.parametrize("case", [
-    # 3840-wide rows (two half-length chains), an odd row count: the last
-    # workgroup has a padding row
+    # 3840-wide rows (four 960-point chains) with W < Wp / 2, so the second
+    # output half of each chain is cut short; an odd row count
     dict(H=15, W=1800, Hp=30, Wp=3840),
     # 7680-wide rows (four quarter-length chains) with W < Wp / 2, so the
     # second output half of each chain is cut short; 17 rows x 2 channels is
