@@ -3,10 +3,12 @@
 // sums), their weight gradients, and the pooling, upsampling, ReLU and
 // lattice glue around them.
 //
-// Matrix instruction: v_mfma_f32_32x32x8 bf16 (one wave, D = A B + D with A
-// 32 x 8, B 8 x 32).  Lane l supplies A[l % 32][4 (l / 32) + i] and
-// B[4 (l / 32) + i][l % 32] (i < 4) and holds D[8 (v / 4) + 4 (l / 32) +
-// v % 4][l % 32] in accumulator v < 16.
+// Matrix instructions (one wave, D = A B + D, D 32 x 32 FP32): in
+// v_mfma_f32_32x32x8 bf16 (A 32 x 8, B 8 x 32) lane l supplies
+// A[l % 32][4 (l / 32) + i] and B[4 (l / 32) + i][l % 32] (i < 4); in
+// v_mfma_f32_32x32x16 bf16 (A 32 x 16, B 16 x 32) it supplies
+// A[l % 32][8 (l / 32) + i] and B[8 (l / 32) + i][l % 32] (i < 8).  Both leave
+// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32] in accumulator v < 16.
 #include <algorithm>
 #include <cmath>
 
@@ -17,6 +19,8 @@ namespace cgh {
 namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -27,13 +31,14 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 
 bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-// four consecutive channels (8 bytes) of the convolution input at (y, x),
-// channel c0 (a multiple of 4) of [up(x1), x2]; zero outside the image
-__device__ __forceinline__ v4s conv_in4(const uint16_t *__restrict__ x1, int c1, int up,
+// eight consecutive channels (16 bytes) of the convolution input at (y, x),
+// channel c0 (a multiple of 8) of [up(x1), x2]; zero outside the image and at
+// c0 >= c1 + c2 (the upper half of a last, half-filled block of 16)
+__device__ __forceinline__ v8s conv_in8(const uint16_t *__restrict__ x1, int c1, int up,
                                         const uint16_t *__restrict__ x2, int c2, int H, int W,
                                         int y, int x, int c0) {
-  v4s r = {0, 0, 0, 0};
-  if (y < 0 || y >= H || x < 0 || x >= W) return r;
+  v8s r = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (y < 0 || y >= H || x < 0 || x >= W || c0 >= c1 + c2) return r;
   const uint16_t *src;
   if (c0 < c1) {
     src = up ? x1 + ((size_t)(y >> 1) * (W >> 1) + (x >> 1)) * c1 + c0
@@ -41,14 +46,15 @@ __device__ __forceinline__ v4s conv_in4(const uint16_t *__restrict__ x1, int c1,
   } else {
     src = x2 + ((size_t)y * W + x) * c2 + (c0 - c1);
   }
-  return *reinterpret_cast<const v4s *>(src);
+  return *reinterpret_cast<const v8s *>(src);
 }
 
 // ----------------------------------------------------------------------------
 // Convolution: a workgroup of 4 waves takes 128 consecutive pixels (in row-major
 // order) and 32 NB output channels; wave w computes pixels 32 w .. 32 w + 31
 // against the NB blocks of 32 channels, stepping through the 9 taps and the
-// input channels 8 at a time.
+// input channels 16 at a time (a last block of 8 is zero-filled above), with
+// the loads of the next step issued before the products of this one.
 // ----------------------------------------------------------------------------
 template <int NB>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1, int c1, int up,
@@ -60,29 +66,53 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int P = H * W, cin = c1 + c2;
   const int p = blockIdx.x * 128 + wave * 32 + (lane & 31);  // this lane's A row
-  const int kq = 4 * (lane >> 5);                            // its k offset in a block of 8
+  const int kq = 8 * (lane >> 5);                            // its k offset in a block of 16
   const int co0 = blockIdx.y * 32 * NB;
   const int py = p / W, px = p - py * W;
+  const bool valid = p < P;
+  const int nk = (cin + 15) / 16;  // k blocks per tap
   v16f acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
-  for (int t = 0; t < 9; ++t) {
+  // the operands of tap t, k block kb: channels past cout get zero weights
+  auto fetch = [&](int t, int kb, v8s &a, v8s (&bb)[NB]) {
     const int ky = t / 3, kx = t - 3 * ky;
-    const int sy = py + ky - 1, sx = px + kx - 1;
-    const bool valid = p < P;
-    for (int ci = 0; ci < cin; ci += 8) {
-      const v4s a = valid ? conv_in4(x1, c1, up, x2, c2, H, W, sy, sx, ci + kq) : v4s{0, 0, 0, 0};
+    const int c0 = kb * 16 + kq;
+    const v8s z = {0, 0, 0, 0, 0, 0, 0, 0};
+    a = valid ? conv_in8(x1, c1, up, x2, c2, H, W, py + ky - 1, px + kx - 1, c0) : z;
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int co = co0 + 32 * b + (lane & 31);  // channels past cout: zero weights
-        const v4s bb = co < cout
-                           ? *reinterpret_cast<const v4s *>(w + ((size_t)co * 9 + t) * cin + ci + kq)
-                           : v4s{0, 0, 0, 0};
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc[b], 0, 0, 0);
-      }
+    for (int b = 0; b < NB; ++b) {
+      const int co = co0 + 32 * b + (lane & 31);
+      bb[b] = (co < cout && c0 < cin)
+                  ? *reinterpret_cast<const v8s *>(w + ((size_t)co * 9 + t) * cin + c0)
+                  : z;
     }
+  };
+  v8s a, bb[NB];
+  fetch(0, 0, a, bb);
+  int t = 0, kb = 0;
+  for (int step = 0, steps = 9 * nk; step < steps; ++step) {
+    int tn = t, kn = kb + 1;
+    if (kn == nk) {
+      kn = 0;
+      ++tn;
+    }
+    v8s an = a, bn[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bn[b] = bb[b];
+    if (tn < 9) fetch(tn, kn, an, bn);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a),
+                                                       __builtin_bit_cast(v8bf, bb[b]), acc[b],
+                                                       0, 0, 0);
+    a = an;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bb[b] = bn[b];
+    t = tn;
+    kb = kn;
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -90,7 +120,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1
     const float bv = (bias && co < cout) ? bias[co] : 0.f;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int q = blockIdx.x * 128 + wave * 32 + 8 * (v >> 2) + kq + (v & 3);
+      const int q = blockIdx.x * 128 + wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
       if (q < P && co < cout) {
         const float s = acc[b][v] + bv;
         if (out32) out32[(size_t)q * cout + co] = s;
