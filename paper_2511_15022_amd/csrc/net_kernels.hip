@@ -50,12 +50,18 @@ __device__ __forceinline__ v8s conv_in8(const uint16_t *__restrict__ x1, int c1,
 }
 
 // ----------------------------------------------------------------------------
-// Convolution: a workgroup of 4 waves takes 128 consecutive pixels (in row-major
-// order) and 32 NB output channels; wave w computes pixels 32 w .. 32 w + 31
-// against the NB blocks of 32 channels, stepping through the 9 taps and the
-// input channels 16 at a time (a last block of 8 is zero-filled above), with
-// the loads of the next step issued before the products of this one.
+// Convolution: a workgroup of 4 waves takes 128 consecutive pixels (row-major)
+// p0 .. p0 + 127 and 32 NB output channels.  For each block of 16 input
+// channels it stages in LDS the three input row segments that the 3 x 3 taps
+// of its pixels read (pixels p0 + (ky - 1) W - 1 .. p0 + (ky - 1) W + 128,
+// ky < 3, zero outside the image) and the weights of its output channels for
+// the 9 taps; wave w then takes its 32 pixels x 32 NB channels through the 9
+// taps from LDS.  A tap that leaves the image (a pixel in the first or last
+// column or row) reads zero.  Each block's global loads are issued before the
+// workgroup waits for the previous block's products.
 // ----------------------------------------------------------------------------
+constexpr int kSeg = 130;  // pixels per staged row segment: 128 + one on each side
+
 template <int NB>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1, int c1, int up,
                                                  const uint16_t *__restrict__ x2, int c2, int H,
@@ -63,56 +69,75 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1
                                                  const float *__restrict__ bias, int cout,
                                                  int relu, float *__restrict__ out32,
                                                  uint16_t *__restrict__ out16) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int CO = 32 * NB;
+  constexpr int NA = 3 * kSeg * 2, NW = 9 * CO * 2;  // 16-byte items: [ky][pixel][half], [t][co][half]
+  constexpr int KA = (NA + 255) / 256, KW = (NW + 255) / 256;
+  __shared__ v8s sa[NA];
+  __shared__ v8s sw[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int P = H * W, cin = c1 + c2;
-  const int p = blockIdx.x * 128 + wave * 32 + (lane & 31);  // this lane's A row
-  const int kq = 8 * (lane >> 5);                            // its k offset in a block of 16
-  const int co0 = blockIdx.y * 32 * NB;
+  const int p0 = blockIdx.x * 128;
+  const int i = wave * 32 + (lane & 31);  // this lane's A row: pixel p0 + i
+  const int half = lane >> 5;             // its 8 channels of a block of 16
+  const int p = p0 + i;
+  const int co0 = blockIdx.y * CO;
   const int py = p / W, px = p - py * W;
   const bool valid = p < P;
-  const int nk = (cin + 15) / 16;  // k blocks per tap
+  const int nk = (cin + 15) / 16;  // channel blocks (a last block of 8 is zero-filled)
+  const v8s z = {0, 0, 0, 0, 0, 0, 0, 0};
   v16f acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
-  // the operands of tap t, k block kb: channels past cout get zero weights
-  auto fetch = [&](int t, int kb, v8s &a, v8s (&bb)[NB]) {
-    const int ky = t / 3, kx = t - 3 * ky;
-    const int c0 = kb * 16 + kq;
-    const v8s z = {0, 0, 0, 0, 0, 0, 0, 0};
-    a = valid ? conv_in8(x1, c1, up, x2, c2, H, W, py + ky - 1, px + kx - 1, c0) : z;
+  for (int kb = 0; kb < nk; ++kb) {
+    v8s ra[KA], rw[KW];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int co = co0 + 32 * b + (lane & 31);
-      bb[b] = (co < cout && c0 < cin)
-                  ? *reinterpret_cast<const v8s *>(w + ((size_t)co * 9 + t) * cin + c0)
-                  : z;
+    for (int k = 0; k < KA; ++k) {
+      const int item = tid + 256 * k;
+      ra[k] = z;
+      if (KA * 256 == NA || item < NA) {
+        const int seg = item / (2 * kSeg), rem = item - seg * (2 * kSeg);
+        const int q = p0 + (seg - 1) * W - 1 + (rem >> 1);
+        if (q >= 0 && q < P) {
+          const int qy = q / W;
+          ra[k] = conv_in8(x1, c1, up, x2, c2, H, W, qy, q - qy * W, kb * 16 + 8 * (rem & 1));
+        }
+      }
     }
-  };
-  v8s a, bb[NB];
-  fetch(0, 0, a, bb);
-  int t = 0, kb = 0;
-  for (int step = 0, steps = 9 * nk; step < steps; ++step) {
-    int tn = t, kn = kb + 1;
-    if (kn == nk) {
-      kn = 0;
-      ++tn;
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      const int item = tid + 256 * k;
+      rw[k] = z;
+      if (KW * 256 == NW || item < NW) {
+        const int t = item / (2 * CO), rem = item - t * (2 * CO);
+        const int co = co0 + (rem >> 1), c0 = kb * 16 + 8 * (rem & 1);
+        if (co < cout && c0 < cin)
+          rw[k] = *reinterpret_cast<const v8s *>(w + ((size_t)co * 9 + t) * cin + c0);
+      }
     }
-    v8s an = a, bn[NB];
+    if (kb > 0) __syncthreads();  // every wave is done with the previous block
 #pragma unroll
-    for (int b = 0; b < NB; ++b) bn[b] = bb[b];
-    if (tn < 9) fetch(tn, kn, an, bn);
+    for (int k = 0; k < KA; ++k)
+      if (KA * 256 == NA || tid + 256 * k < NA) sa[tid + 256 * k] = ra[k];
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-      acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a),
-                                                       __builtin_bit_cast(v8bf, bb[b]), acc[b],
-                                                       0, 0, 0);
-    a = an;
+    for (int k = 0; k < KW; ++k)
+      if (KW * 256 == NW || tid + 256 * k < NW) sw[tid + 256 * k] = rw[k];
+    __syncthreads();
 #pragma unroll
-    for (int b = 0; b < NB; ++b) bb[b] = bn[b];
-    t = tn;
-    kb = kn;
+    for (int t = 0; t < 9; ++t) {
+      const int ky = t / 3, kx = t - 3 * ky;
+      const int sy = py + ky - 1, sx = px + kx - 1;
+      const bool in = valid && sy >= 0 && sy < H && sx >= 0 && sx < W;
+      const v8s a = in ? sa[(ky * kSeg + i + kx) * 2 + half] : z;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const v8s bb = sw[(t * CO + 32 * b + (lane & 31)) * 2 + half];
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a),
+                                                         __builtin_bit_cast(v8bf, bb), acc[b],
+                                                         0, 0, 0);
+      }
+    }
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
