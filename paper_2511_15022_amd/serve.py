@@ -185,6 +185,10 @@ class Server:
             main.wait_stream(self.streams[si])
         torch.cuda.synchronize()
         wall = time.perf_counter() - host0
+        # pair-list capacity: each slot reports its last rasterize (the last
+        # step of the last solve it ran); raises CghError on an overflow
+        for key in {(si, r.H, r.W) for si, q in enumerate(queues) for r in q}:
+            self.slots[key].ctx.read_status()
         latency = {i: e0.elapsed_time(e1) for i, (e0, e1, _) in marks.items()}
         turnaround = {i: t0.elapsed_time(e1) for i, (_, e1, _) in marks.items()}
         return {"wall_s": wall, "latency_ms": latency, "turnaround_ms": turnaround,
