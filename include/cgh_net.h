@@ -50,15 +50,18 @@ cgh_status cgh_net_conv3x3(const cgh_bf16 *x1, int32_t c1, int32_t up, const cgh
 cgh_status cgh_net_flip_weights(const cgh_bf16 *w, int32_t cout, int32_t cin, cgh_bf16 *w_t,
                                 void *stream);
 
-/* Bytes of scratch cgh_net_conv3x3_wgrad needs for this shape. */
+/* Bytes of scratch cgh_net_conv3x3_wgrad needs for this shape: FP32 partial
+ * sums over pixel ranges, and channel-major BF16 copies of dL/dout and of the
+ * input (three column-shifted, zero-padded copies). */
 size_t cgh_net_wgrad_workspace(int32_t H, int32_t W, int32_t cin, int32_t cout);
 
 /* Weight and bias gradients of the convolution above for dL/dout = gy
  * (BF16 [H][W][cout]): gw[co][ky][kx][ci] = sum_p gy[p][co] in[p + k - 1][ci]
  * and gb[co] = sum_p gy[p][co] (FP32; gb may be NULL), in = [up(x1), x2] as in
  * cgh_net_conv3x3 (same restrictions).  Partial sums over pixel ranges go to
- * `workspace` (>= cgh_net_wgrad_workspace bytes, else CGH_ERR_WORKSPACE) and
- * are added in a fixed order, so the result is deterministic. */
+ * `workspace` (>= cgh_net_wgrad_workspace bytes, else CGH_ERR_WORKSPACE;
+ * 16-byte aligned, as gy must be) and are added in a fixed order, so the
+ * result is deterministic. */
 cgh_status cgh_net_conv3x3_wgrad(const cgh_bf16 *x1, int32_t c1, int32_t up, const cgh_bf16 *x2,
                                  int32_t c2, int32_t H, int32_t W, const cgh_bf16 *gy,
                                  int32_t cout, float *gw, float *gb, void *workspace,

@@ -156,83 +156,163 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1
 }
 
 // ----------------------------------------------------------------------------
-// Weight gradient: gw[co][n] (n = t cin + ci, tap t = 3 ky + kx) = sum_p gy[p][co]
-// in[p + k(t) - 1][ci] as a GEMM over pixels.  One wave per (32 n, 32 co, split):
-// A = gy^T (co x 8 pixels), B = the shifted input (8 pixels x n); FP32 partials
-// per split; the bias gradient rides along in the n-block 0 waves.
+// Weight gradient: gw[co][t][ci] (tap t = 3 ky + kx) = sum_p gy[p][co]
+// in[p + k(t) - 1][ci], a GEMM whose reduction runs over pixels.  Both operands
+// are first copied channel-major, so that a lane's eight consecutive pixels of
+// one channel are one aligned 16-byte load (Wr = W rounded up to 16):
+//   gyT[co][y][x]      = gy[y][x][co]                (x < Wr; zero for x >= W)
+//   ink[kx][ci][yy][x] = in[yy - 1][x + kx - 1][ci]  (yy < H + 2; zero outside)
+// Tap (ky, kx) of output pixel (y, x) then reads ink[kx][ci][y + ky][x] with no
+// border test.  One wave takes 32 output channels x 32 input channels, all nine
+// taps, over a range of 16-pixel row chunks (v_mfma_f32_32x32x16 bf16, K = the
+// chunk's pixels), and writes FP32 partials for its range; the bias gradient
+// rides along in the waves of the first input-channel block.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_conv3x3_wgrad(
-    const uint16_t *__restrict__ x1, int c1, int up, const uint16_t *__restrict__ x2, int c2,
-    int H, int W, const uint16_t *__restrict__ gy, int cout, int chunk,
-    float *__restrict__ part, float *__restrict__ part_b) {
-  const int lane = threadIdx.x;
-  const int P = H * W, cin = c1 + c2, N = 9 * cin;
-  const int nb = blockIdx.x, cb = blockIdx.y, s = blockIdx.z;
-  const int kq = 4 * (lane >> 5);
-  const int co = cb * 32 + (lane & 31);
-  const int n = nb * 32 + (lane & 31);
-  const bool nv = n < N;
-  const int t = nv ? n / cin : 0, ci = nv ? n - t * cin : 0;
-  const int ky = t / 3, kx = t - 3 * ky;
-  // B reads one channel at a time; pick x1 or x2 once
-  const bool from1 = ci < c1;
-  const int p0 = s * chunk, p1 = min(P, p0 + chunk);
-  v16f acc;
+
+// gyT: a workgroup transposes one row y, 64 columns and 32 channels through LDS
+__global__ __launch_bounds__(256) void k_wg_gyT(const uint16_t *__restrict__ gy, int H, int W,
+                                                int Wr, int cout, uint16_t *__restrict__ gyT) {
+  __shared__ uint16_t tile[64][33];
+  const int tid = threadIdx.x;
+  const int y = blockIdx.y, x0 = blockIdx.x * 64, co0 = blockIdx.z * 32;
+  {
+    const int px = tid >> 2, g = tid & 3, x = x0 + px, co = co0 + 8 * g;
+    v8s v = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (x < W && co < cout) v = *reinterpret_cast<const v8s *>(gy + ((size_t)y * W + x) * cout + co);
 #pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-  float bsum = 0.f;
-  for (int pb = p0; pb < p1; pb += 8) {
-    v4s a, bb;
+    for (int i = 0; i < 8; ++i) tile[px][8 * g + i] = (uint16_t)v[i];
+  }
+  __syncthreads();
+  {
+    const int co = tid >> 3, seg = tid & 7, x = x0 + 8 * seg;
+    if (co0 + co < cout && x < Wr) {
+      v8s v;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int p = pb + kq + i;
-      uint16_t av = 0, bv = 0;
-      if (p < p1) {
-        av = co < cout ? gy[(size_t)p * cout + co] : (uint16_t)0;
-        const int py = p / W, px = p - py * W;
-        const int sy = py + ky - 1, sx = px + kx - 1;
-        if (nv && sy >= 0 && sy < H && sx >= 0 && sx < W) {
-          if (from1)
-            bv = up ? x1[((size_t)(sy >> 1) * (W >> 1) + (sx >> 1)) * c1 + ci]
-                    : x1[((size_t)sy * W + sx) * c1 + ci];
-          else
-            bv = x2[((size_t)sy * W + sx) * c2 + (ci - c1)];
-        }
-      }
-      a[i] = (short)av;
-      bb[i] = (short)bv;
-      bsum += from_bf16(av);
+      for (int i = 0; i < 8; ++i) v[i] = (short)tile[8 * seg + i][co];
+      *reinterpret_cast<v8s *>(gyT + ((size_t)(co0 + co) * H + y) * Wr + x) = v;
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc, 0, 0, 0);
-  }
-  // D[row = co][col = n]
-  float *dst = part + (size_t)s * cout * N;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int r = cb * 32 + 8 * (v >> 2) + kq + (v & 3);
-    if (nv && r < cout) dst[(size_t)r * N + n] = acc[v];
-  }
-  if (nb == 0) {
-    // lanes l and l + 32 hold the two halves of the pixels of channel co
-    bsum += __shfl_down(bsum, 32, 64);
-    if (lane < 32 && co < cout) part_b[(size_t)s * cout + co] = bsum;
   }
 }
 
-// fixed-order sum over the splits
-__global__ void k_wgrad_reduce(const float *__restrict__ part, const float *__restrict__ part_b,
-                               int splits, int64_t len, int cout, float *__restrict__ gw,
-                               float *__restrict__ gb) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < len) {
-    float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part[(size_t)k * len + i];
-    gw[i] = s;
+// ink: a workgroup builds row yy (< H + 2) of the three shifted copies for 64
+// columns and 32 channels from source columns x0 - 1 .. x0 + 64 staged in LDS
+__global__ __launch_bounds__(256) void k_wg_ink(const uint16_t *__restrict__ x1, int c1, int up,
+                                                const uint16_t *__restrict__ x2, int c2, int H,
+                                                int W, int Wr, uint16_t *__restrict__ ink) {
+  __shared__ uint16_t tile[66][33];
+  const int tid = threadIdx.x;
+  const int yy = blockIdx.y, x0 = blockIdx.x * 64, ci0 = blockIdx.z * 32;
+  const int cin = c1 + c2;
+  for (int item = tid; item < 66 * 4; item += 256) {
+    const int col = item >> 2, g = item & 3;
+    // conv_in8 is zero outside the image and past the last channel
+    const v8s v = conv_in8(x1, c1, up, x2, c2, H, W, yy - 1, x0 - 1 + col, ci0 + 8 * g);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tile[col][8 * g + i] = (uint16_t)v[i];
   }
-  if (gb && i < cout) {
-    float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part_b[(size_t)k * cout + i];
-    gb[i] = s;
+  __syncthreads();
+  for (int item = tid; item < 3 * 256; item += 256) {
+    const int kx = item >> 8, r = item & 255, ci = r >> 3, seg = r & 7, x = x0 + 8 * seg;
+    if (ci0 + ci < cin && x < Wr) {
+      v8s v;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = (short)tile[8 * seg + i + kx][ci];  // column x + i + kx - 1
+      *reinterpret_cast<v8s *>(ink + (((size_t)kx * cin + ci0 + ci) * (H + 2) + yy) * Wr + x) = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_conv3x3_wgrad(const uint16_t *__restrict__ gyT,
+                                                      const uint16_t *__restrict__ ink, int H,
+                                                      int Wr, int cin, int cout, int cps,
+                                                      int nchunks, float *__restrict__ part,
+                                                      float *__restrict__ part_b) {
+  const int lane = threadIdx.x, half = lane >> 5;
+  const int cib = blockIdx.x, cob = blockIdx.y, s = blockIdx.z;
+  const int N = 9 * cin, cw = Wr / 16;
+  const int co = cob * 32 + (lane & 31), ci = cib * 32 + (lane & 31);
+  const bool cov = co < cout, civ = ci < cin;
+  const uint16_t *arow = gyT + (size_t)(cov ? co : 0) * H * Wr;
+  const uint16_t *brow = ink + (size_t)(civ ? ci : 0) * (H + 2) * Wr;
+  const size_t kstride = (size_t)cin * (H + 2) * Wr;  // between the kx copies
+  const v8s z = {0, 0, 0, 0, 0, 0, 0, 0};
+  v16f acc[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
+  float bsum = 0.f;
+  const int cbeg = s * cps, cend = min(nchunks, cbeg + cps);
+  for (int c = cbeg; c < cend; ++c) {
+    const int y = c / cw, x = (c - y * cw) * 16 + 8 * half;
+    const v8s a = cov ? *reinterpret_cast<const v8s *>(arow + (size_t)y * Wr + x) : z;
+    v8s b[9];
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx)
+        b[3 * ky + kx] =
+            civ ? *reinterpret_cast<const v8s *>(brow + kx * kstride + (size_t)(y + ky) * Wr + x)
+                : z;
+    if (cib == 0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) bsum += from_bf16((uint16_t)a[i]);
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a),
+                                                       __builtin_bit_cast(v8bf, b[t]), acc[t], 0,
+                                                       0, 0);
+  }
+  // D[row = co][col = ci] of tap t
+  float *dst = part + (size_t)s * cout * N;
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int r = cob * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+      if (civ && r < cout) dst[(size_t)r * N + t * cin + ci] = acc[t][v];
+    }
+  if (cib == 0) {
+    // lanes l and l + 32 hold the two halves of the pixels of channel co
+    bsum += __shfl_down(bsum, 32, 64);
+    if (lane < 32 && cov) part_b[(size_t)s * cout + co] = bsum;
+  }
+}
+
+// fixed-order sum over the splits: a workgroup takes 16 outputs with 16 lanes
+// each; lane g of an output adds splits g, g + 16, ... in order, then one lane
+// adds the 16 lane sums in order.  Outputs i < len are the weight gradients;
+// the workgroups with i < cout also sum the bias partials the same way.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ part,
+                                                      const float *__restrict__ part_b,
+                                                      int splits, int64_t len, int cout,
+                                                      float *__restrict__ gw,
+                                                      float *__restrict__ gb) {
+  __shared__ float red[16][17];
+  const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + o;
+  float s = 0.f;
+  if (i < len)
+    for (int k = g; k < splits; k += 16) s += part[(size_t)k * len + i];
+  red[g][o] = s;
+  __syncthreads();
+  if (g == 0 && i < len) {
+    float t = 0.f;
+    for (int q = 0; q < 16; ++q) t += red[q][o];
+    gw[i] = t;
+  }
+  if (gb == nullptr || (int64_t)blockIdx.x * 16 >= cout) return;  // uniform per workgroup
+  __syncthreads();
+  s = 0.f;
+  if (i < cout)
+    for (int k = g; k < splits; k += 16) s += part_b[(size_t)k * cout + i];
+  red[g][o] = s;
+  __syncthreads();
+  if (g == 0 && i < cout) {
+    float t = 0.f;
+    for (int q = 0; q < 16; ++q) t += red[q][o];
+    gb[i] = t;
   }
 }
 
@@ -389,10 +469,28 @@ __global__ void k_features(const float *__restrict__ t, const float2 *__restrict
 
 unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-int wgrad_chunk(int P) {
-  // about 1024 pixels per split, a multiple of 8
-  const int splits = std::max(1, P / 1024);
-  return ((P + splits - 1) / splits + 7) & ~7;
+// the split of the weight-gradient GEMM: about 512 waves over the 16-pixel
+// row chunks of a Wr-wide image, and the byte offsets of its workspace parts
+struct WgPlan {
+  int Wr, nchunks, cps, splits;
+  size_t part, part_b, gyT, ink, bytes;
+};
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+WgPlan wgrad_plan(int H, int W, int cin, int cout) {
+  WgPlan p;
+  p.Wr = (W + 15) & ~15;
+  p.nchunks = H * (p.Wr / 16);
+  const int pairs = ((cin + 31) / 32) * ((cout + 31) / 32);
+  const int want = std::max(1, std::min(p.nchunks, (512 + pairs - 1) / pairs));
+  p.cps = (p.nchunks + want - 1) / want;
+  p.splits = (p.nchunks + p.cps - 1) / p.cps;
+  const size_t len = (size_t)cout * 9 * cin;
+  p.part = 0;
+  p.part_b = round256(p.splits * len * sizeof(float));
+  p.gyT = p.part_b + round256((size_t)p.splits * cout * sizeof(float));
+  p.ink = p.gyT + round256((size_t)cout * H * p.Wr * sizeof(uint16_t));
+  p.bytes = p.ink + round256((size_t)3 * cin * (H + 2) * p.Wr * sizeof(uint16_t));
+  return p;
 }
 
 }  // namespace
@@ -457,8 +555,7 @@ cgh_status cgh_net_flip_weights(const cgh_bf16 *w, int32_t cout, int32_t cin, cg
 
 size_t cgh_net_wgrad_workspace(int32_t H, int32_t W, int32_t cin, int32_t cout) {
   if (H < 1 || W < 1 || cin < 1 || cout < 1) return 0;
-  const int P = H * W, chunk = wgrad_chunk(P), splits = (P + chunk - 1) / chunk;
-  return (size_t)splits * ((size_t)cout * 9 * cin + cout) * sizeof(float);
+  return wgrad_plan(H, W, cin, cout).bytes;
 }
 
 cgh_status cgh_net_conv3x3_wgrad(const cgh_bf16 *x1, int32_t c1, int32_t up, const cgh_bf16 *x2,
@@ -469,20 +566,28 @@ cgh_status cgh_net_conv3x3_wgrad(const cgh_bf16 *x1, int32_t c1, int32_t up, con
   if (st != CGH_OK) return st;
   NET_CHECK(gy && gw && cout > 0 && cout % 8 == 0, "gy/gw NULL or cout = %d not a multiple of 8",
             cout);
-  const int cin = c1 + c2, P = H * W, chunk = wgrad_chunk(P), splits = (P + chunk - 1) / chunk;
-  const size_t need = cgh_net_wgrad_workspace(H, W, cin, cout);
-  if (!workspace || workspace_bytes < need)
+  const int cin = c1 + c2;
+  const WgPlan pl = wgrad_plan(H, W, cin, cout);
+  if (!workspace || workspace_bytes < pl.bytes)
     return report(CGH_ERR_WORKSPACE, "wgrad workspace has %zu bytes, needs %zu", workspace_bytes,
-                  need);
+                  pl.bytes);
+  NET_CHECK(al16(workspace) && al16(gy), "workspace and gy must be 16-byte aligned");
   const int64_t len = (int64_t)cout * 9 * cin;
-  float *part = (float *)workspace, *part_b = part + (size_t)splits * len;
+  char *base = (char *)workspace;
+  float *part = (float *)(base + pl.part), *part_b = (float *)(base + pl.part_b);
+  uint16_t *gyT = (uint16_t *)(base + pl.gyT), *ink = (uint16_t *)(base + pl.ink);
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid((9 * cin + 31) / 32, (cout + 31) / 32, splits);
-  hipLaunchKernelGGL(k_conv3x3_wgrad, grid, dim3(64), 0, s, x1, c1, up, x2, c2, H, W, gy, cout,
-                     chunk, part, part_b);
+  hipLaunchKernelGGL(k_wg_gyT, dim3((pl.Wr + 63) / 64, H, (cout + 31) / 32), dim3(256), 0, s,
+                     reinterpret_cast<const uint16_t *>(gy), H, W, pl.Wr, cout, gyT);
+  hipLaunchKernelGGL(k_wg_ink, dim3((pl.Wr + 63) / 64, H + 2, (cin + 31) / 32), dim3(256), 0, s,
+                     reinterpret_cast<const uint16_t *>(x1), c1, up,
+                     reinterpret_cast<const uint16_t *>(x2), c2, H, W, pl.Wr, ink);
+  NET_LAUNCHED("conv3x3_wgrad staging");
+  hipLaunchKernelGGL(k_conv3x3_wgrad, dim3((cin + 31) / 32, (cout + 31) / 32, pl.splits), dim3(64),
+                     0, s, gyT, ink, H, pl.Wr, cin, cout, pl.cps, pl.nchunks, part, part_b);
   NET_LAUNCHED("conv3x3_wgrad");
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_of(std::max<int64_t>(len, cout), 256)),
-                     dim3(256), 0, s, part, part_b, splits, len, cout, gw, gb);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_of(std::max<int64_t>(len, cout), 16)),
+                     dim3(256), 0, s, part, part_b, pl.splits, len, cout, gw, gb);
   NET_LAUNCHED("wgrad_reduce");
   return CGH_OK;
 }

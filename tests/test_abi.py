@@ -151,9 +151,12 @@ def test_null_arguments_are_rejected_without_device_work():
 def test_net_argument_checks_and_workspace_sizes():
     """Host-side checks of the network entry points; no device work."""
     L = binding.lib()
-    # 512 x 512, 32 -> 32: about 1024 pixels per split
+    # 512 x 512, 32 -> 32: 16384 row chunks of 16 pixels in 512 splits; FP32
+    # partials (512 x 9216) and bias partials (512 x 32), the channel-major
+    # dL/dy (32 x 512 x 512 BF16) and the three shifted, padded input copies
+    # (3 x 32 x 514 x 512 BF16), each part rounded up to 256 bytes
     ws = L.cgh_net_wgrad_workspace(512, 512, 32, 32)
-    assert ws == 256 * (32 * 9 * 32 + 32) * 4
+    assert ws == 512 * 9216 * 4 + 512 * 32 * 4 + 32 * 512 * 512 * 2 + 3 * 32 * 514 * 512 * 2
     assert L.cgh_net_wgrad_workspace(0, 5, 8, 32) == 0
     # c1 not a multiple of 8, cout not a multiple of 8, missing outputs
     assert L.cgh_net_conv3x3(16, 6, 0, None, 0, 4, 4, 16, None, 32, 0, 16, None, None) == 1

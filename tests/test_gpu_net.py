@@ -114,7 +114,8 @@ def test_conv_forward_and_adjoints(case):
 
 
 def test_wgrad_many_splits_is_deterministic():
-    """128 x 96 pixels: twelve splits of the pixel range; two runs bitwise equal."""
+    """128 x 96 pixels: many splits of the pixel range (256 ranges of three
+    16-pixel row chunks); two runs bitwise equal."""
     rng = np.random.default_rng(3)
     H, W, c1, cout = 128, 96, 32, 64
     x1, x1n = bf((H, W, c1), rng)
