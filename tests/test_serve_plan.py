@@ -42,3 +42,28 @@ def test_single_stream_holds_everything_in_cost_order():
     reqs = [R(i, c) for i, c in enumerate([5.0, 1.0, 3.0, 3.0])]
     (q,) = serve.plan(reqs, 1, lambda r: r.c)
     assert [r.index for r in q] == [1, 2, 3, 0]
+
+
+def test_requests_are_seeded_and_follow_the_recipe():
+    """The synthetic serving batch (CPU tensors): same seed, same batch; sizes,
+    wavelengths and distances from the stated sets and ranges; n = HW // 5;
+    each target is its class's target circularly shifted."""
+    from paper_2511_15022_amd import synth
+    sizes = ((16, 24), (32, 16))
+    a = serve.make_requests(12, seed=7, sizes=sizes, device="cpu")
+    b = serve.make_requests(12, seed=7, sizes=sizes, device="cpu")
+    for r, q in zip(a, b):
+        assert (r.H, r.W, r.wavelength, r.z) == (q.H, q.W, q.wavelength, q.z)
+        assert np.array_equal(r.params.numpy(), q.params.numpy())
+        assert np.array_equal(r.target.numpy(), q.target.numpy())
+    assert {(r.H, r.W) for r in a} == set(sizes)
+    for r in a:
+        assert r.wavelength in serve.WAVELENGTHS and 2e-3 <= r.z <= 10e-3
+        assert r.n == r.H * r.W // 5 and r.params.numel() == r.n * 8
+        k = sizes.index((r.H, r.W))
+        base = synth.target(7 + 1 + k, 1, r.H, r.W).reshape(r.H, r.W)
+        t = r.target.numpy().reshape(r.H, r.W)
+        # some circular shift of the class target
+        assert any(np.array_equal(np.roll(base, (dy, dx), axis=(0, 1)), t)
+                   for dy in range(r.H) for dx in range(r.W))
+    assert len({r.wavelength for r in a}) > 1 and len({round(r.z, 6) for r in a}) == 12
