@@ -25,8 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-# FP32 vector FMA issue rate without packed-FP32 instructions (this build never
-# emits them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+# FP32 vector FMA issue rate without packed-FP32 instructions (the library is
+# compiled without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
@@ -521,7 +521,7 @@ def run_serving(binding, dev, holograms, steps, seed=300, candidates=(1, 2, 4)):
         "graph_speedup_vs_eager": (len(reqs) / runs[best]["wall_s"]) / (len(reqs) / eager_s),
         "psnr_db_first_step_median": float(np.median(first_psnr)),
         "psnr_db_last_step_median": float(np.median(final_psnr)),
-        "data": "synthetic, seeded (see DESIGN.md input recipe)",
+        "data": "synthetic, seeded (serve.make_requests, seed 300)",
     })
     del server, reqs
     return out
@@ -604,8 +604,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs the hot path on one GPU only; multi-GPU runs are not "
-              "part of it (see the sharding note in DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        print("bench.py: the hot path runs on one GPU; runs over several GPUs are not "
+              "implemented. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -63,7 +63,7 @@ typedef enum {
   CGH_ERR_WORKSPACE = 2,   /* workspace smaller than cgh_workspace_size            */
   CGH_ERR_CAPACITY = 3,    /* pair list overflowed (see cgh_read_status)            */
   CGH_ERR_DEVICE = 4,      /* HIP runtime error                                     */
-  CGH_ERR_UNSUPPORTED = 5, /* valid request this build does not implement           */
+  CGH_ERR_UNSUPPORTED = 5, /* valid request the library does not implement          */
   CGH_ERR_STATE = 6        /* call order violated (e.g. adjoint before rasterize)   */
 } cgh_status;
 

@@ -71,7 +71,7 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
                 kMaxFft);
   if (!col_supported(Hp))
     return fail(CGH_ERR_UNSUPPORTED,
-                "padded height %d: this build supports even values up to %d and odd values "
+                "padded height %d: the library supports even values up to %d and odd values "
                 "up to %d", Hp, 2 * kColHalfMax, kColFullMax);
   if (!(f.pitch_m > 0.0) || !std::isfinite(f.pitch_m))
     return fail(CGH_ERR_INVALID_ARG, "pitch must be positive and finite");
