@@ -248,7 +248,9 @@ cgh_status cgh_get_transfer(cgh_ctx *ctx, int32_t channel, int32_t plane, cgh_c6
 /* Waits for `stream`, then reports the device-side status of the last
  * rasterize: *pairs <- number of (tile, Gaussian) pairs it needed (may be NULL).
  * Returns CGH_ERR_CAPACITY if that exceeded max_pairs (the field and gradients of
- * that call are then incomplete), CGH_OK otherwise. */
+ * that call are then incomplete), or if any rasterize since the previous
+ * cgh_read_status on this context did (a solve graph runs many; this part is
+ * reported once and then cleared), CGH_OK otherwise. */
 cgh_status cgh_read_status(cgh_ctx *ctx, void *stream, int64_t *pairs);
 
 /* Kernel classes for cgh_profile_begin. */

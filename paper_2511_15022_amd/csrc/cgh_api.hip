@@ -266,6 +266,7 @@ cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_b
   if (c.twf_y) CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_y, c.Hp, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, s), "transfer function");
   CGH_CHECK_LAUNCH(cgh::launch_zero_record(c, s), "zero record");
+  CGH_CHECK_LAUNCH(cgh::launch_zero_status(c, s), "zero status");
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return device_fail(e, "cgh_create");
   cgh_ctx *h = new (std::nothrow) cgh_ctx;
@@ -784,13 +785,23 @@ cgh_status cgh_read_status(cgh_ctx *ctx, void *stream, int64_t *pairs) {
   Ctx &c = ctx->c;
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return device_fail(e, "cgh_read_status");
-  uint32_t st[2] = {0, 0};
+  uint32_t st[3] = {0, 0, 0};
   e = hipMemcpy(st, c.status, sizeof(st), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return device_fail(e, "cgh_read_status");
   if (pairs) *pairs = (int64_t)st[1];
+  if (st[2]) {
+    // an overflow since the last read: report it once
+    const uint32_t zero = 0u;
+    e = hipMemcpy(c.status + 2, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return device_fail(e, "cgh_read_status");
+  }
   if (st[0])
     return fail(CGH_ERR_CAPACITY, "pair list needed %u entries, capacity is %lld", st[1],
                 (long long)c.pair_cap);
+  if (st[2])
+    return fail(CGH_ERR_CAPACITY,
+                "a rasterize since the last status read overflowed the pair list (capacity "
+                "%lld; the last one needed %u entries)", (long long)c.pair_cap, st[1]);
   return CGH_OK;
 }
 

@@ -100,7 +100,7 @@ struct Ctx {
   float *ssim_abc;                  // [3][L][C][H - 10][W - 10] SSIM gradient coefficients
   double *ssim_part;                // [L][C][position tiles] sums of SSIM
   double *mse_part;                 // [L][C][pixel tiles] sums of (I - T)^2
-  uint32_t *status;                 // [0] overflow flag, [1] pair total
+  uint32_t *status;                 // [0] overflow flag, [1] pair total, [2] sticky overflow
   int sorted;                       // which ping-pong buffer holds the sorted pairs
   // kernel-class timing (cgh_profile_begin / _end)
   int prof_class;                   // 0: off
@@ -152,6 +152,7 @@ hipError_t launch_full_loss_finalize(const Ctx &c, float ssim_weight, double *lo
 
 hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s);
 hipError_t launch_zero_record(const Ctx &c, hipStream_t s);
+hipError_t launch_zero_status(const Ctx &c, hipStream_t s);
 hipError_t launch_binning(Ctx &c, int n, hipStream_t s);  // sets c.sorted
 hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s);
 hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStream_t s);

@@ -268,7 +268,8 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
   for (uint32_t t = 0; t < cnt; ++t) {
     const uint64_t pos = off + t;
     if ((int64_t)pos >= cap) {
-      atomicOr(&status[0], 1u);
+      atomicOr(&status[0], 1u);  // this rasterize
+      atomicOr(&status[2], 1u);  // sticky until the next status read
       break;
     }
     keys[pos] = ty * (uint32_t)tiles_x + tx;
@@ -440,9 +441,17 @@ hipError_t launch_zero_record(const Ctx &c, hipStream_t s) {
   return hipGetLastError();
 }
 
+
 __global__ void k_zero_u32(uint32_t *p, int len) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) p[i] = 0u;
+}
+
+// the status words: overflow of the last rasterize, its pair total, and the
+// overflow flag that stays set until cgh_read_status reads it
+hipError_t launch_zero_status(const Ctx &c, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c.status, 4);
+  return hipGetLastError();
 }
 
 hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
@@ -458,7 +467,7 @@ hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
                        c.scan_tmp, c.rect, c.tiles_x, c.pair_cap, c.keys[0], c.vals[0],
                        c.status);
   } else {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c.status, 4);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c.status, 2);
   }
   const int hlen = 256 * c.sort_blocks;
   const int nchunks = (hlen + kScanItems - 1) / kScanItems;

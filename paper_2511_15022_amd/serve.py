@@ -185,8 +185,8 @@ class Server:
             main.wait_stream(self.streams[si])
         torch.cuda.synchronize()
         wall = time.perf_counter() - host0
-        # pair-list capacity: each slot reports its last rasterize (the last
-        # step of the last solve it ran); raises CghError on an overflow
+        # pair-list capacity: each slot reports an overflow in any step of any
+        # solve it ran since its previous status read; raises CghError
         for key in {(si, r.H, r.W) for si, q in enumerate(queues) for r in q}:
             self.slots[key].ctx.read_status()
         latency = {i: e0.elapsed_time(e1) for i, (e0, e1, _) in marks.items()}

@@ -395,6 +395,23 @@ def test_capacity_overflow_is_reported(O):
         ctx.read_status()
 
 
+def test_capacity_overflow_of_an_earlier_rasterize_is_reported_once(O):
+    """An overflowing rasterize followed by one that fits: the next status
+    read still reports the overflow (as a graph-captured solve needs), the
+    read after it does not."""
+    say("sticky capacity overflow")
+    p = synth.params(0, 500, 64, 64, 1)
+    ctx = binding.Context(64, 64, 1, 8e-6, [515e-9], [2e-3], max_gaussians=500, max_pairs=100)
+    P = gpu_params(p)
+    ctx.rasterize(P, 500)
+    few = binding.pack(synth.params(1, 5, 64, 64, 1), device="cuda")
+    ctx.rasterize(few, 5)
+    pairs, ok = ctx.read_status(raise_on_overflow=False)
+    assert not ok and pairs <= 100
+    pairs, ok = ctx.read_status(raise_on_overflow=False)
+    assert ok and pairs <= 100
+
+
 def test_adam_step_matches_oracle(O):
     say("adam")
     rng = np.random.default_rng(0)
