@@ -1,0 +1,64 @@
+"""Writes tests/golden/rgb_4k_3z_samples.npz, the FP64 oracle's values at
+seeded samples of the 4K three-depth workload (2160 x 3840 RGB, 1,658,880
+Gaussians, padded 4320 x 7680, pitch 3.74 um, z = 3, 5, 7 mm, focal masks,
+the L_recon loss): the loss; the SLM field and dL/dU0 at 512 pixels that no
+(Gaussian, pixel) pair near the support boundary touches; and the parameter
+gradients of 1024 Gaussians none of whose pairs lies near that boundary.
+It calls only the oracle and the seeded input generators (about four
+minutes on eight cores):  python tests/golden/make_rgb_4k_3z_samples.py"""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import oracle as O  # noqa: E402
+from paper_2511_15022_amd import synth  # noqa: E402
+
+BAND = 1e-5  # relative half-width of the support-boundary band (as the parity tests)
+
+
+def main():
+    w = synth.WORKLOADS["rgb_4k_3z"]
+    H, W, C, n, L = w["H"], w["W"], w["C"], w["n"], len(w["zs"])
+    p = synth.params(w["pseed"], n, H, W, C)
+    T = synth.target(w["tseed"], C, H, W, L=L)
+    Mk = synth.focal_masks(w["tseed"] + 1, L, H, W)
+    opt = O.Optics(H, W, C, w["Hp"], w["Wp"], w["pitch"], w["lambdas"], w["zs"])
+    ref = O.forward_backward(p, T, opt, mask=Mk)
+    amb, _ = O.ambiguous_mask(p, opt, BAND)
+    rng = np.random.default_rng(4321)
+    clear = np.flatnonzero(~amb.ravel())
+    pix = np.sort(rng.choice(clear, 512, replace=False))
+    # Gaussians with no pair in the band: test every pixel of the k-sigma box
+    g = O.geometry(p, W, H)
+    k2 = opt.k * opt.k
+    cand = rng.permutation(n)
+    keep = []
+    for i in cand:
+        mx, my, sx, sy, s00, s01, s11 = g[i, :7]
+        i00, i01, i11 = g[i, 8:11]
+        rx, ry = opt.k * np.sqrt(s00), opt.k * np.sqrt(s11)
+        xs = np.arange(max(0, int(np.floor(mx - rx)) - 1), min(W, int(np.ceil(mx + rx)) + 2))
+        ys = np.arange(max(0, int(np.floor(my - ry)) - 1), min(H, int(np.ceil(my + ry)) + 2))
+        dx, dy = np.meshgrid(xs - mx, ys - my)
+        q = i00 * dx * dx + 2 * i01 * dx * dy + i11 * dy * dy
+        if not np.any(np.abs(q - k2) < BAND * k2):
+            keep.append(i)
+        if len(keep) == 1024:
+            break
+    gid = np.sort(np.array(keep))
+    grads = np.concatenate([ref["grads"][k].reshape(n, -1)[gid] for k in
+                            ("mean_pre", "log_scale", "rotation", "amplitude", "phase",
+                             "opacity_pre")], axis=1)
+    field = ref["field"].reshape(C, -1)[:, pix]
+    gfield = ref["grad_field"].reshape(C, -1)[:, pix]
+    np.savez_compressed(os.path.join(HERE, "rgb_4k_3z_samples.npz"), loss=np.float64(ref["loss"]),
+                        pixels=pix, field=field, grad_field=gfield, gaussians=gid, grads=grads)
+    print("loss", ref["loss"], "pixels", pix.size, "gaussians", gid.size)
+
+
+if __name__ == "__main__":
+    main()

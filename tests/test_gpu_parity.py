@@ -458,6 +458,54 @@ def test_rgb_1080p_full_size_parity(O):
         assert e <= GRAD_TOL, (k, e)
 
 
+def test_rgb_4k_3z_full_size_sampled_parity():
+    """The 4K three-depth workload at full size (2160 x 3840 RGB, 1,658,880
+    Gaussians, padded 4320 x 7680, z = 3, 5, 7 mm, focal masks, L_recon) in the
+    launch configuration of its benchmark line, against FP64 oracle values
+    stored by tests/golden/make_rgb_4k_3z_samples.py (the full oracle takes
+    minutes): the loss, the field and dL/dU0 at 512 seeded pixels, and the
+    parameter gradients of 1024 seeded Gaussians, per group."""
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "rgb_4k_3z_samples.npz"))
+    w = WORK["rgb_4k_3z"]
+    H, W, C, n, L = w["H"], w["W"], w["C"], w["n"], len(w["zs"])
+    say("rgb_4k_3z full size: inputs")
+    p = synth.params(w["pseed"], n, H, W, C)
+    T = synth.target(w["tseed"], C, H, W, L=L)
+    Mk = synth.focal_masks(w["tseed"] + 1, L, H, W)
+    ctx = binding.Context(H, W, C, w["pitch"], w["lambdas"], w["zs"], pad=(w["Hp"], w["Wp"]),
+                          max_gaussians=n)
+    say("rgb_4k_3z full size: gpu")
+    P = gpu_params(p)
+    field = ctx.rasterize(P, n)
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+    gfield = torch.empty_like(field)
+    grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss, grad_field=gfield,
+                         mask=torch.from_numpy(Mk).cuda())
+    _, ok = ctx.read_status()
+    assert ok
+    pix, gid = gold["pixels"], gold["gaussians"]
+    say("loss", loss[0].item(), float(gold["loss"]))
+    assert abs(loss[0].item() - float(gold["loss"])) <= 1e-4 * float(gold["loss"])
+    e = rel_l2(field.cpu().numpy().reshape(C, -1)[:, pix], gold["field"])
+    say("sampled field rel", e)
+    assert e <= FIELD_TOL
+    e = rel_l2(gfield.cpu().numpy().reshape(C, -1)[:, pix], gold["grad_field"])
+    say("sampled dL/dU0 rel", e)
+    assert e <= GRAD_TOL
+    views = binding.unpack(grads.cpu(), n, C)
+    got = np.concatenate([views[k].numpy().reshape(n, -1)[gid] for k in binding.PARAM_KEYS],
+                         axis=1)
+    ref = gold["grads"]
+    col = 0
+    for k in binding.PARAM_KEYS:
+        width = views[k].numpy().reshape(n, -1).shape[1]
+        e = rel_l2(got[:, col:col + width], ref[:, col:col + width])
+        say("sampled grad", k, e)
+        assert e <= GRAD_TOL, (k, e)
+        col += width
+
+
 def test_recon_loss_parity(O):
     """The L_recon backward (Sec. 3.2; depth masks per plane) against the
     oracle: loss, dL/dU0 and the parameter gradients, two planes."""
