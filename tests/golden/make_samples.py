@@ -1,11 +1,15 @@
-"""Writes tests/golden/rgb_4k_3z_samples.npz, the FP64 oracle's values at
-seeded samples of the 4K three-depth workload (2160 x 3840 RGB, 1,658,880
-Gaussians, padded 4320 x 7680, pitch 3.74 um, z = 3, 5, 7 mm, focal masks,
-the L_recon loss): the loss; the SLM field and dL/dU0 at 512 pixels that no
-(Gaussian, pixel) pair near the support boundary touches; and the parameter
-gradients of 1024 Gaussians none of whose pairs lies near that boundary.
-It calls only the oracle and the seeded input generators (about four
-minutes on eight cores):  python tests/golden/make_rgb_4k_3z_samples.py"""
+"""Writes the FP64 oracle's values at seeded samples of a full-size workload:
+the loss; the SLM field and dL/dU0 at 512 pixels that no (Gaussian, pixel)
+pair near the support boundary touches; and the parameter gradients of 1024
+Gaussians none of whose pairs lies near that boundary.  It calls only the
+oracle and the seeded input generators.
+  python tests/golden/make_samples.py            -> rgb_4k_3z_samples.npz
+      the 4K three-depth workload (2160 x 3840 RGB, 1,658,880 Gaussians, padded
+      4320 x 7680, pitch 3.74 um, z = 3, 5, 7 mm, focal masks, L_recon; about
+      four minutes on eight cores)
+  python tests/golden/make_samples.py serving_2048 -> serving_2048_samples.npz
+      the largest serving class at full size (2048 x 2048, one colour, 838,860
+      Gaussians, padded 4096 x 4096, pitch 8 um, 473 nm, z = 6.1 mm, L_MSE)"""
 import os
 import sys
 
@@ -20,12 +24,17 @@ from paper_2511_15022_amd import synth  # noqa: E402
 BAND = 1e-5  # relative half-width of the support-boundary band (as the parity tests)
 
 
-def main():
-    w = synth.WORKLOADS["rgb_4k_3z"]
+# the largest serving class: seeds 500 / 501 (parameters / target)
+SERVING_2048 = dict(H=2048, W=2048, C=1, n=2048 * 2048 // 5, Hp=4096, Wp=4096, pitch=8e-6,
+                    lambdas=[473e-9], zs=[6.1e-3], pseed=500, tseed=501, masks=False)
+
+
+def main(name="rgb_4k_3z"):
+    w = SERVING_2048 if name == "serving_2048" else synth.WORKLOADS[name]
     H, W, C, n, L = w["H"], w["W"], w["C"], w["n"], len(w["zs"])
     p = synth.params(w["pseed"], n, H, W, C)
     T = synth.target(w["tseed"], C, H, W, L=L)
-    Mk = synth.focal_masks(w["tseed"] + 1, L, H, W)
+    Mk = synth.focal_masks(w["tseed"] + 1, L, H, W) if w.get("masks") else None
     opt = O.Optics(H, W, C, w["Hp"], w["Wp"], w["pitch"], w["lambdas"], w["zs"])
     ref = O.forward_backward(p, T, opt, mask=Mk)
     amb, _ = O.ambiguous_mask(p, opt, BAND)
@@ -55,10 +64,10 @@ def main():
                              "opacity_pre")], axis=1)
     field = ref["field"].reshape(C, -1)[:, pix]
     gfield = ref["grad_field"].reshape(C, -1)[:, pix]
-    np.savez_compressed(os.path.join(HERE, "rgb_4k_3z_samples.npz"), loss=np.float64(ref["loss"]),
+    np.savez_compressed(os.path.join(HERE, f"{name}_samples.npz"), loss=np.float64(ref["loss"]),
                         pixels=pix, field=field, grad_field=gfield, gaussians=gid, grads=grads)
     print("loss", ref["loss"], "pixels", pix.size, "gaussians", gid.size)
 
 
 if __name__ == "__main__":
-    main()
+    main(*sys.argv[1:2])

@@ -458,30 +458,37 @@ def test_rgb_1080p_full_size_parity(O):
         assert e <= GRAD_TOL, (k, e)
 
 
-def test_rgb_4k_3z_full_size_sampled_parity():
-    """The 4K three-depth workload at full size (2160 x 3840 RGB, 1,658,880
-    Gaussians, padded 4320 x 7680, z = 3, 5, 7 mm, focal masks, L_recon) in the
-    launch configuration of its benchmark line, against FP64 oracle values
-    stored by tests/golden/make_rgb_4k_3z_samples.py (the full oracle takes
-    minutes): the loss, the field and dL/dU0 at 512 seeded pixels, and the
-    parameter gradients of 1024 seeded Gaussians, per group."""
+# the largest serving class at full size (as in tests/golden/make_samples.py)
+SERVING_2048 = dict(H=2048, W=2048, C=1, n=2048 * 2048 // 5, Hp=4096, Wp=4096, pitch=8e-6,
+                    lambdas=[473e-9], zs=[6.1e-3], pseed=500, tseed=501, masks=False)
+
+
+@pytest.mark.parametrize("name", ["rgb_4k_3z", "serving_2048"])
+def test_full_size_sampled_parity(name):
+    """Full-size workloads whose full oracle takes minutes, in the launch
+    configuration of their benchmark lines, against FP64 oracle values stored
+    by tests/golden/make_samples.py: the loss, the field and dL/dU0 at 512
+    seeded pixels, and the parameter gradients of 1024 seeded Gaussians, per
+    group.  rgb_4k_3z: 2160 x 3840 RGB, 1,658,880 Gaussians, padded 4320 x 7680,
+    z = 3, 5, 7 mm, focal masks, L_recon.  serving_2048: 2048 x 2048, one
+    colour, 838,860 Gaussians, padded 4096 x 4096, L_MSE."""
     import os
-    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "rgb_4k_3z_samples.npz"))
-    w = WORK["rgb_4k_3z"]
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", f"{name}_samples.npz"))
+    w = SERVING_2048 if name == "serving_2048" else WORK[name]
     H, W, C, n, L = w["H"], w["W"], w["C"], w["n"], len(w["zs"])
-    say("rgb_4k_3z full size: inputs")
+    say(name, "full size: inputs")
     p = synth.params(w["pseed"], n, H, W, C)
     T = synth.target(w["tseed"], C, H, W, L=L)
-    Mk = synth.focal_masks(w["tseed"] + 1, L, H, W)
+    Mk = synth.focal_masks(w["tseed"] + 1, L, H, W) if w.get("masks") else None
     ctx = binding.Context(H, W, C, w["pitch"], w["lambdas"], w["zs"], pad=(w["Hp"], w["Wp"]),
                           max_gaussians=n)
-    say("rgb_4k_3z full size: gpu")
+    say(name, "full size: gpu")
     P = gpu_params(p)
     field = ctx.rasterize(P, n)
     loss = torch.zeros(2, dtype=torch.float64, device="cuda")
     gfield = torch.empty_like(field)
     grads = ctx.backward(P, n, field, torch.from_numpy(T).cuda(), loss=loss, grad_field=gfield,
-                         mask=torch.from_numpy(Mk).cuda())
+                         mask=None if Mk is None else torch.from_numpy(Mk).cuda())
     _, ok = ctx.read_status()
     assert ok
     pix, gid = gold["pixels"], gold["gaussians"]
