@@ -726,7 +726,7 @@ def main():
                     "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": measured_traffic(cls),
                     "in_support_pairs": npairs, "flop_per_pair": per_pair}
-        label = {"binning": "latency (integer sort, ten short launches)",
+        label = {"binning": "latency (integer sort, nine short launches)",
                  "loss": "latency (one-block FP64 reduction)"}.get(cls, "latency")
         return {"kernel": cls, "bound": label}
 

@@ -246,19 +246,33 @@ static hipError_t scan_u32(const uint32_t *in, uint32_t *out, int len, uint32_t 
 // Binning: emit (tile, gaussian) pairs, stable radix sort, tile ranges.
 // ----------------------------------------------------------------------------
 // Pairs of Gaussian g go to [offset(g), offset(g) + count(g)) in row-major
-// tile order.  offsets[] holds per-chunk exclusive scans and chunk_prefix the
-// scanned chunk sums; the final offset is written back for the adjoint.
+// tile order.  offsets[] holds per-chunk exclusive scans and chunk_sums the
+// (unscanned) chunk totals: each workgroup adds the totals of the chunks before
+// its own, and workgroup 0 writes the grand total to offsets[n] and to the
+// pair total status[1]; the final offset is written back for the adjoint.
 __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict__ counts,
                                               uint32_t *__restrict__ offsets,
-                                              const uint32_t *__restrict__ chunk_prefix,
-                                              const uint2 *__restrict__ rect, int tiles_x,
-                                              int64_t cap, uint32_t *__restrict__ keys,
+                                              const uint32_t *__restrict__ chunk_sums,
+                                              int nchunks, const uint2 *__restrict__ rect,
+                                              int tiles_x, int64_t cap,
+                                              uint32_t *__restrict__ keys,
                                               uint32_t *__restrict__ vals,
                                               uint32_t *__restrict__ status) {
+  static_assert(kScanItems % 256 == 0, "a workgroup lies in one scan chunk");
+  const int upto = blockIdx.x == 0 ? nchunks : (int)(blockIdx.x * 256 / kScanItems);
+  uint32_t part = 0;
+  for (int k = threadIdx.x; k < upto; k += 256) part += chunk_sums[k];
+  uint32_t total;
+  block_exclusive_scan(part, &total);  // every thread of the workgroup takes part
+  const uint32_t prefix = blockIdx.x == 0 ? 0u : total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    offsets[n] = total;
+    status[1] = total;
+  }
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const uint32_t cnt = counts[g];
-  const uint32_t off32 = offsets[g] + chunk_prefix[g / kScanItems];
+  const uint32_t off32 = offsets[g] + prefix;
   offsets[g] = off32;
   if (cnt == 0) return;
   const uint64_t off = off32;
@@ -455,16 +469,14 @@ hipError_t launch_zero_status(const Ctx &c, hipStream_t s) {
 }
 
 hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
-  // status[0] (overflow) and status[1] (pair total) restart at zero: the
-  // first scan kernel clears the flag and the chunk-sum scan writes the total
+  // status[0] (overflow) and status[1] (pair total) restart: the first scan
+  // kernel clears the flag and the emit kernel writes the total
   if (n > 0) {
     const int nb = (n + kScanItems - 1) / kScanItems;
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, c.counts, c.offsets, n,
                        c.scan_tmp, c.status);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, c.scan_tmp, nb, c.offsets + n,
-                       c.status + 1);
     hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, s, n, c.counts, c.offsets,
-                       c.scan_tmp, c.rect, c.tiles_x, c.pair_cap, c.keys[0], c.vals[0],
+                       c.scan_tmp, nb, c.rect, c.tiles_x, c.pair_cap, c.keys[0], c.vals[0],
                        c.status);
   } else {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c.status, 2);
