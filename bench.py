@@ -482,13 +482,9 @@ def run_serving(binding, dev, holograms, steps, seed=300, candidates=(1, 2, 4)):
     reqs = serve.make_requests(holograms, seed=seed, device=dev)
     server = serve.Server(steps, max_streams=max(candidates), device=dev)
     costs = server.measure_class_costs(reqs)
-    rates, runs = {}, {}
-    for k in candidates:
-        server.run(reqs, streams=k)
-        runs[k] = server.run(reqs, streams=k)
-        rates[k] = len(reqs) / runs[k]["wall_s"]
-        log(f"[bench]   serving: {k} stream(s): {rates[k]:.2f} holograms/s")
-    best = max(rates, key=lambda k: (rates[k], -k))
+    best, rates, runs = serve.autotune(server, reqs, candidates)
+    for k, r in rates.items():
+        log(f"[bench]   serving: {k} stream(s): {r:.2f} holograms/s")
     out = serve.summary(reqs, runs[best])
     classes = {}
     for r in reqs:

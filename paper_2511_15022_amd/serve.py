@@ -221,17 +221,18 @@ def summary(requests, res):
 
 
 def autotune(server, requests, candidates=(1, 2, 4)):
-    """Runs the batch at each candidate stream count (the first run of each
-    also serves as its warm-up) and returns (best count, {count: holograms/s})."""
-    rates = {}
+    """Runs the batch at each candidate stream count (a warm-up run: slots,
+    graphs and caches; then a timed run) and returns (best count,
+    {count: holograms/s}, {count: the timed run's result from ``run``})."""
+    rates, runs = {}, {}
     for k in candidates:
         if k > len(server.streams):
             continue
-        server.run(requests, streams=k)  # warm-up: slots, graphs, caches
-        res = server.run(requests, streams=k)
-        rates[k] = len(requests) / res["wall_s"]
+        server.run(requests, streams=k)
+        runs[k] = server.run(requests, streams=k)
+        rates[k] = len(requests) / runs[k]["wall_s"]
     best = max(rates, key=lambda k: (rates[k], -k))
-    return best, rates
+    return best, rates, runs
 
 
 def solve_eager(ctx, params, n, target, steps, lr=1e-3):
