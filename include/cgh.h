@@ -25,6 +25,14 @@
  *    Pair-list overflow is detected on the device and reported by
  *    cgh_read_status.  No C++ exception crosses this interface.
  *  - Threads: a context may be used by one host thread at a time.
+ *  - Batches: a context may hold B = cgh_config.batch holograms of one size
+ *    (each with its own Gaussians, target and optics; every kernel then runs
+ *    over all of them in one launch).  With B > 1 the arrays below gain a
+ *    hologram dimension: parameters and gradients [B][n (6 + 2C)] (each
+ *    hologram's block in the layout below), field [B][C][H][W], and every
+ *    per-plane array [L][B][C][H][W] (for each plane, the holograms act as
+ *    further channels of the propagation); masks [L][B][H][W]; loss [B][2].
+ *    B = 1 is the single-hologram layout.
  *
  * Layouts
  *  - Complex values are interleaved float pairs (re, im), cgh_c64 below --
@@ -64,11 +72,13 @@ typedef enum {
   CGH_ERR_CAPACITY = 3,    /* pair list overflowed (see cgh_read_status)            */
   CGH_ERR_DEVICE = 4,      /* HIP runtime error                                     */
   CGH_ERR_UNSUPPORTED = 5, /* valid request the library does not implement          */
-  CGH_ERR_STATE = 6        /* call order violated (e.g. adjoint before rasterize)   */
+  CGH_ERR_STATE = 6,       /* call order violated (e.g. adjoint before rasterize)   */
+  CGH_ERR_NONFINITE = 7    /* NaN or Inf met by a CGH_CHECK_FINITE context          */
 } cgh_status;
 
 #define CGH_MAX_CHANNELS 4
 #define CGH_MAX_PLANES 8
+#define CGH_MAX_BATCH 64
 
 /* Geometry and optics of one hologram problem. */
 typedef struct {
@@ -82,14 +92,23 @@ typedef struct {
   double z_m[CGH_MAX_PLANES];    /* propagation distance per plane, metres (any sign)     */
   float support_sigma;           /* k: a Gaussian covers the pixels with Mahalanobis      */
                                  /* distance q <= k^2 (k <= 0: every pixel)               */
-  int32_t max_gaussians;         /* capacity for n                                        */
+  int32_t max_gaussians;         /* capacity for n (per hologram)                         */
   int64_t max_pairs;             /* capacity of the (tile, Gaussian) list (0: default     */
-                                 /* 8 * max_gaussians + 65536)                            */
-  int32_t flags;                 /* 0, or CGH_FULL_LOSS and/or CGH_PAPER_ALPHA            */
+                                 /* K B max_gaussians + 65536, K = 16 for 8 x 8 tiles,    */
+                                 /* else 8)                                               */
+  int32_t flags;                 /* 0, or CGH_FULL_LOSS, CGH_PAPER_ALPHA, CGH_CHECK_FINITE */
   double aperture;               /* circular aperture of Alg. 3 in the frequency plane:   */
                                  /* keep the bins of the padded grid with                 */
                                  /* kx^2 + ky^2 < aperture^2 (signed bin indices, centred */
                                  /* on the zero frequency); 0: none                       */
+  int32_t tile_w, tile_h;        /* rasterizer tile in pixels: 16 x 16, 32 x 8, 16 x 8 or */
+                                 /* 8 x 8 (0, 0: 16 x 16).  Results do not depend on it   */
+                                 /* beyond FP32 rounding of the adjoint's partial sums    */
+                                 /* (the forward is bitwise the same for every shape)     */
+  int32_t batch;                 /* B: holograms of this size in the context, 1 .. 64     */
+                                 /* (0: 1); wavelength_m and z_m give every hologram's    */
+                                 /* optics at creation (cgh_set_hologram_optics changes   */
+                                 /* one); needs flags without CGH_FULL_LOSS when B > 1    */
 } cgh_config;
 
 /* cgh_config.flags: reserve the workspace of cgh_backward_full (the SSIM term:
@@ -103,11 +122,22 @@ typedef struct {
  * adjoint follow it (w does not depend on alpha or the geometry where the
  * 0.99 clamp is active).  Costs 8 bytes per Gaussian of workspace. */
 #define CGH_PAPER_ALPHA 2
+/* cgh_config.flags: check for NaN and Inf on the device: the parameters read by
+ * cgh_rasterize and cgh_rasterize_lists, the gradients written by every
+ * backward and rasterizer adjoint, and the loss.  A non-finite value sets a
+ * sticky device word that cgh_read_status reports as CGH_ERR_NONFINITE (and
+ * then clears).  Costs one compare per value and no extra launch. */
+#define CGH_CHECK_FINITE 4
 
 typedef struct cgh_ctx cgh_ctx;
 
-/* Bytes of device workspace a context with this configuration needs.
- * Host-only; validates the configuration (CGH_ERR_INVALID_ARG on a bad one). */
+/* Bytes of device workspace a context with this configuration needs: the FFT
+ * twiddle tables, the FP64-built transfer functions (Sec. 2 equation for H;
+ * Alg. 3), the column-tiled propagation buffers of the padded grid (Alg. 1
+ * ZeroPad), the Gaussian records and (tile, Gaussian) lists of Alg. 2, and the
+ * rasterizer adjoint's per-pair partial sums.  Host-only; validates the
+ * configuration (CGH_ERR_INVALID_ARG on a bad one, CGH_ERR_UNSUPPORTED on a
+ * valid one this library does not implement). */
 cgh_status cgh_workspace_size(const cgh_config *cfg, size_t *bytes);
 
 /* Creates a context over a caller-owned device workspace (>= cgh_workspace_size
@@ -127,8 +157,10 @@ cgh_status cgh_destroy(cgh_ctx *ctx);
  * the Gaussians whose k-sigma ellipse contains (i, j), with
  * G = exp(max(-q/2, -50)) (alpha_n G_n replaced as documented at
  * CGH_PAPER_ALPHA when that flag is set).  params: n * (6 + 2C) floats (layout above),
- * 0 <= n <= max_gaussians.  field: [C][H][W] complex, overwritten.
- * Keeps the per-tile Gaussian lists in the workspace for the adjoint. */
+ * 0 <= n <= max_gaussians (per hologram; B blocks with a batch).  field:
+ * [C][H][W] complex ([B][C][H][W]), overwritten.
+ * Keeps the per-tile Gaussian lists in the workspace for the adjoint and
+ * advances the context's list generation (cgh_generation). */
 cgh_status cgh_rasterize(cgh_ctx *ctx, const float *params, int32_t n, cgh_c64 *field,
                          void *stream);
 
@@ -190,9 +222,12 @@ cgh_status cgh_backward_full(cgh_ctx *ctx, const float *params, int32_t n,
                              float ssim_weight, double *loss, cgh_c64 *grad_field,
                              float *grads, void *stream);
 
-/* Adjoint of cgh_propagate's intensity for an arbitrary loss: given
+/* Adjoint of cgh_propagate's intensity for an arbitrary loss (supplementary
+ * BLASM Backward Pass: the same zero padding, FFT and band limit with the
+ * conjugate transfer function, then the crop's adjoint): given
  * grad_intensity = dL/dI ([L][C][H][W]) at I = |u(field)|^2, writes
- * grad_field = dL/dRe(field) + j dL/dIm(field) ([C][H][W]).  Recomputes u. */
+ * grad_field = dL/dRe(field) + j dL/dIm(field) = sum_l P_l^H (2 dL/dI_l u_l)
+ * ([C][H][W]).  Recomputes u from field instead of storing it. */
 cgh_status cgh_propagate_adjoint(cgh_ctx *ctx, const cgh_c64 *field,
                                  const float *grad_intensity, cgh_c64 *grad_field,
                                  void *stream);
@@ -207,9 +242,26 @@ cgh_status cgh_propagate_field_adjoint(cgh_ctx *ctx, const cgh_c64 *grad_u, cgh_
 
 /* Adjoint of cgh_rasterize (supplementary rasterizer Backward Pass, items 1-7):
  * grads <- dL/dparams from grad_field = dL/dRe(U0) + j dL/dIm(U0) ([C][H][W]).
- * Same precondition as cgh_backward. */
+ * Recomputes every pixel's Gaussian response from the tile lists instead of
+ * storing it.  Same precondition as cgh_backward: the lists must be those of
+ * these params (a caller that cannot guarantee it compares cgh_generation
+ * with the value after its own rasterize, and on a mismatch rebuilds them
+ * with cgh_rasterize_lists first). */
 cgh_status cgh_rasterize_adjoint(cgh_ctx *ctx, const float *params, int32_t n,
                                  const cgh_c64 *grad_field, float *grads, void *stream);
+
+/* The list-building part of ComplexRasterize2D (Alg. 2: preprocess, duplicate
+ * each Gaussian to the tiles its support box touches, sort by tile) without
+ * the per-pixel sum: rebuilds the context's tile lists for `params` so that a
+ * rasterizer adjoint can follow, and advances the generation.  The
+ * recomputation step of a deferred adjoint (e.g. after other rasterize calls
+ * on the same context).  Arguments as cgh_rasterize. */
+cgh_status cgh_rasterize_lists(cgh_ctx *ctx, const float *params, int32_t n, void *stream);
+
+/* *generation <- the number of cgh_rasterize / cgh_rasterize_lists calls made
+ * on ctx so far (host counter; no device work).  The tile lists in the
+ * workspace are those of the call that set the current value. */
+cgh_status cgh_generation(cgh_ctx *ctx, int64_t *generation);
 
 /* Adam step (Kingma & Ba, Algorithm 1) over `count` floats, in place:
  *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
@@ -239,7 +291,8 @@ cgh_status cgh_step_adan(float *params, const float *grads, float *m, float *d, 
                          float beta2, float beta3, float eps, float weight_decay,
                          const float *lr_groups, int32_t channels, void *stream);
 
-/* Copies the transfer function of (channel, plane) into `out`, a device array of
+/* Copies the transfer function of (channel, plane) into `out` (with a batch,
+ * channel b C + c is colour c of hologram b), a device array of
  * (Hp/2 + 1) x (Wp/2 + 1) complex: entry [qy][qx] is H at |fy| = qy / (Hp pitch),
  * |fx| = qx / (Wp pitch) (H depends on the frequency only through |fx|, |fy|). */
 cgh_status cgh_get_transfer(cgh_ctx *ctx, int32_t channel, int32_t plane, cgh_c64 *out,
@@ -250,7 +303,10 @@ cgh_status cgh_get_transfer(cgh_ctx *ctx, int32_t channel, int32_t plane, cgh_c6
  * Returns CGH_ERR_CAPACITY if that exceeded max_pairs (the field and gradients of
  * that call are then incomplete), or if any rasterize since the previous
  * cgh_read_status on this context did (a solve graph runs many; this part is
- * reported once and then cleared), CGH_OK otherwise. */
+ * reported once and then cleared); else CGH_ERR_NONFINITE if a
+ * CGH_CHECK_FINITE context met a NaN or Inf since the previous read (the
+ * message says where: parameters, gradients or loss; reported once, then
+ * cleared); CGH_OK otherwise. */
 cgh_status cgh_read_status(cgh_ctx *ctx, void *stream, int64_t *pairs);
 
 /* Kernel classes for cgh_profile_begin. */
@@ -285,6 +341,12 @@ cgh_status cgh_profile_end(cgh_ctx *ctx, void *stream, double *total_ms, int32_t
 cgh_status cgh_set_optics(cgh_ctx *ctx, const double *wavelength_m, const double *z_m,
                           void *stream);
 
+/* cgh_set_optics for hologram `hologram` (0 .. B - 1) of a batched context
+ * only: its C wavelengths and L distances (HOST arrays), its transfer tables
+ * rebuilt in FP64 on `stream`.  cgh_set_optics sets every hologram's. */
+cgh_status cgh_set_hologram_optics(cgh_ctx *ctx, int32_t hologram, const double *wavelength_m,
+                                   const double *z_m, void *stream);
+
 /* A plain-optimiser solve (Alg. 1 with L_MSE and Adam) captured once as a HIP
  * graph, so that one launch replaces the host's per-kernel launches of every
  * step.  Each launch of the graph first zeroes m and v, then, for
@@ -318,7 +380,7 @@ cgh_status cgh_solve_destroy(cgh_solve *solve);
 const char *cgh_last_error(void);
 
 /* ABI version of this header (CGH_ABI_VERSION). */
-#define CGH_ABI_VERSION 3
+#define CGH_ABI_VERSION 4
 int32_t cgh_abi_version(void);
 
 #ifdef __cplusplus

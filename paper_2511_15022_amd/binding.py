@@ -16,13 +16,17 @@ MAX_CHANNELS = 4
 MAX_PLANES = 8
 CGH_FULL_LOSS = 1  # cgh_config.flags bit: workspace for cgh_backward_full
 CGH_PAPER_ALPHA = 2  # cgh_config.flags bit: the Alg. 2 weight min(0.99, alpha G), skip < 1/255
+CGH_CHECK_FINITE = 4  # cgh_config.flags bit: device check for NaN / Inf (cgh_read_status)
+MAX_BATCH = 64
+TILE_SHAPES = ((16, 16), (32, 8), (16, 8), (8, 8))  # rasterizer tiles (width, height)
 PARAM_KEYS = ("mean_pre", "log_scale", "rotation", "amplitude", "phase", "opacity_pre")
 
 KERNEL_CLASSES = {"preprocess": 1, "binning": 2, "raster": 3, "row_fft": 4, "col_pass": 5,
                   "row_loss": 6, "loss": 7, "raster_adjoint": 8, "preprocess_adjoint": 9}
 
 STATUS = {0: "CGH_OK", 1: "CGH_ERR_INVALID_ARG", 2: "CGH_ERR_WORKSPACE", 3: "CGH_ERR_CAPACITY",
-          4: "CGH_ERR_DEVICE", 5: "CGH_ERR_UNSUPPORTED", 6: "CGH_ERR_STATE"}
+          4: "CGH_ERR_DEVICE", 5: "CGH_ERR_UNSUPPORTED", 6: "CGH_ERR_STATE",
+          7: "CGH_ERR_NONFINITE"}
 
 
 class CghError(RuntimeError):
@@ -44,6 +48,9 @@ class cgh_config(ctypes.Structure):
         ("max_pairs", ctypes.c_int64),
         ("flags", ctypes.c_int32),
         ("aperture", ctypes.c_double),
+        ("tile_w", ctypes.c_int32),
+        ("tile_h", ctypes.c_int32),
+        ("batch", ctypes.c_int32),
     ]
 
 
@@ -63,6 +70,8 @@ _SIGS = [
     ("cgh_propagate_adjoint", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("cgh_propagate_field_adjoint", ctypes.c_int, [_VP, _VP, _VP, _VP]),
     ("cgh_rasterize_adjoint", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
+    ("cgh_rasterize_lists", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP]),
+    ("cgh_generation", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
     ("cgh_step", ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP, ctypes.c_int32, _VP]),
     ("cgh_step_adan", ctypes.c_int,
@@ -75,6 +84,7 @@ _SIGS = [
     ("cgh_profile_end", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int32)]),
     ("cgh_set_optics", ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    ("cgh_set_hologram_optics", ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     ("cgh_solve_create", ctypes.c_int,
      [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_float,
       ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP, ctypes.POINTER(_VP)]),
@@ -179,12 +189,15 @@ def unpack(flat, n, C):
 
 
 class Context:
-    """One hologram problem on one device (cgh_create / cgh_destroy).  The
-    device workspace is a torch tensor owned by this object."""
+    """One hologram problem, or a batch of ``batch`` holograms of one size, on
+    one device (cgh_create / cgh_destroy).  The device workspace is a torch
+    tensor owned by this object.  ``tile`` is the rasterizer tile (width,
+    height), one of TILE_SHAPES (None: 16 x 16)."""
 
     def __init__(self, height, width, channels, pitch, wavelengths, zs, pad=None,
                  support_sigma=3.0, max_gaussians=0, max_pairs=0, full_loss=False,
-                 paper_alpha=False, aperture=0.0, device="cuda"):
+                 paper_alpha=False, aperture=0.0, device="cuda", tile=None, batch=1,
+                 check_finite=False):
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -206,8 +219,14 @@ class Context:
         cfg.support_sigma = float(support_sigma)
         cfg.max_gaussians = int(max_gaussians)
         cfg.max_pairs = int(max_pairs)
-        cfg.flags = (CGH_FULL_LOSS if full_loss else 0) | (CGH_PAPER_ALPHA if paper_alpha else 0)
+        cfg.flags = ((CGH_FULL_LOSS if full_loss else 0) | (CGH_PAPER_ALPHA if paper_alpha else 0)
+                     | (CGH_CHECK_FINITE if check_finite else 0))
         cfg.aperture = float(aperture)
+        tw, th = tile if tile is not None else (0, 0)
+        cfg.tile_w, cfg.tile_h = int(tw), int(th)
+        cfg.batch = int(batch)
+        self.B = int(batch)
+        self.tile = (int(tw) or 16, int(th) or 16)
         self.cfg = cfg
         self.L = len(zs)
         self.Hp = cfg.pad_height or 2 * self.H
@@ -238,24 +257,53 @@ class Context:
 
     # -- shapes -------------------------------------------------------------
     def field_shape(self):
-        return (self.C, self.H, self.W)
+        """[C][H][W], or [B][C][H][W] for a batch."""
+        return (self.C, self.H, self.W) if self.B == 1 else (self.B, self.C, self.H, self.W)
 
     def plane_shape(self):
-        return (self.L, self.C, self.H, self.W)
+        """[L][C][H][W], or [L][B][C][H][W] for a batch."""
+        if self.B == 1:
+            return (self.L, self.C, self.H, self.W)
+        return (self.L, self.B, self.C, self.H, self.W)
+
+    def mask_shape(self):
+        return (self.L, self.H, self.W) if self.B == 1 else (self.L, self.B, self.H, self.W)
+
+    def param_count(self, n):
+        """Floats of the parameter (or gradient) array of n Gaussians per hologram."""
+        return self.B * param_count(n, self.C)
+
+    def _field_numel(self):
+        return self.B * self.C * self.H * self.W
+
+    def _plane_numel(self):
+        return self.L * self._field_numel()
 
     # -- entry points -------------------------------------------------------
     def rasterize(self, params, n, field=None):
-        _need(params, torch.float32, param_count(n, self.C), "params", self.device)
+        _need(params, torch.float32, self.param_count(n), "params", self.device)
         if field is None:
             field = torch.empty(self.field_shape(), dtype=torch.complex64, device=self.device)
-        _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)
+        _need(field, torch.complex64, self._field_numel(), "field", self.device)
         _check(lib().cgh_rasterize(self.handle, _ptr(params), int(n), _ptr(field),
                                    _stream(self.device)))
         self.last_n = n
         return field
 
+    def rasterize_lists(self, params, n):
+        """cgh_rasterize_lists: rebuild the tile lists of ``params`` (no field)."""
+        _need(params, torch.float32, self.param_count(n), "params", self.device)
+        _check(lib().cgh_rasterize_lists(self.handle, _ptr(params), int(n), _stream(self.device)))
+        self.last_n = n
+
+    def generation(self):
+        """cgh_generation: rasterize / rasterize_lists calls made so far."""
+        g = ctypes.c_int64(0)
+        _check(lib().cgh_generation(self.handle, ctypes.byref(g)))
+        return g.value
+
     def propagate(self, field, intensity=True, field_out=False):
-        _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)
+        _need(field, torch.complex64, self._field_numel(), "field", self.device)
         I = torch.empty(self.plane_shape(), dtype=torch.float32, device=self.device) if intensity else None
         u = torch.empty(self.plane_shape(), dtype=torch.complex64, device=self.device) if field_out else None
         _check(lib().cgh_propagate(self.handle, _ptr(field), _ptr(I), _ptr(u), _stream(self.device)))
@@ -266,17 +314,17 @@ class Context:
         """L_MSE backward; with ``mask`` ([L][H][W]) the L_recon backward; with
         ``ssim_weight`` (a context made with ``full_loss=True``) the final loss
         L_recon (or L_MSE) + ssim_weight L_SSIM."""
-        _need(params, torch.float32, param_count(n, self.C), "params", self.device)
-        _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)
-        _need(target, torch.float32, self.L * self.C * self.H * self.W, "target", self.device)
+        _need(params, torch.float32, self.param_count(n), "params", self.device)
+        _need(field, torch.complex64, self._field_numel(), "field", self.device)
+        _need(target, torch.float32, self._plane_numel(), "target", self.device)
         if grads is None:
             grads = torch.empty_like(params)
         if loss is not None:
-            _need(loss, torch.float64, 2, "loss", self.device)
+            _need(loss, torch.float64, 2 * self.B, "loss", self.device)
         if grad_field is not None:
-            _need(grad_field, torch.complex64, self.C * self.H * self.W, "grad_field", self.device)
+            _need(grad_field, torch.complex64, self._field_numel(), "grad_field", self.device)
         if mask is not None:
-            _need(mask, torch.float32, self.L * self.H * self.W, "mask", self.device)
+            _need(mask, torch.float32, self.L * self.B * self.H * self.W, "mask", self.device)
         if ssim_weight is not None:
             _check(lib().cgh_backward_full(self.handle, _ptr(params), int(n), _ptr(field),
                                            _ptr(target), _ptr(mask), float(ssim_weight),
@@ -295,18 +343,17 @@ class Context:
 
     def propagate_field_adjoint(self, grad_u, grad_field=None):
         """cgh_propagate_field_adjoint: sum over planes of P^H grad_u."""
-        _need(grad_u, torch.complex64, self.L * self.C * self.H * self.W, "grad_u", self.device)
+        _need(grad_u, torch.complex64, self._plane_numel(), "grad_u", self.device)
         if grad_field is None:
             grad_field = torch.empty(self.field_shape(), dtype=torch.complex64, device=self.device)
-        _need(grad_field, torch.complex64, self.C * self.H * self.W, "grad_field", self.device)
+        _need(grad_field, torch.complex64, self._field_numel(), "grad_field", self.device)
         _check(lib().cgh_propagate_field_adjoint(self.handle, _ptr(grad_u), _ptr(grad_field),
                                                  _stream(self.device)))
         return grad_field
 
     def propagate_adjoint(self, field, grad_intensity, grad_field=None):
-        _need(field, torch.complex64, self.C * self.H * self.W, "field", self.device)
-        _need(grad_intensity, torch.float32, self.L * self.C * self.H * self.W, "grad_intensity",
-              self.device)
+        _need(field, torch.complex64, self._field_numel(), "field", self.device)
+        _need(grad_intensity, torch.float32, self._plane_numel(), "grad_intensity", self.device)
         if grad_field is None:
             grad_field = torch.empty(self.field_shape(), dtype=torch.complex64, device=self.device)
         _check(lib().cgh_propagate_adjoint(self.handle, _ptr(field), _ptr(grad_intensity),
@@ -314,13 +361,24 @@ class Context:
         return grad_field
 
     def rasterize_adjoint(self, params, n, grad_field, grads=None):
-        _need(params, torch.float32, param_count(n, self.C), "params", self.device)
-        _need(grad_field, torch.complex64, self.C * self.H * self.W, "grad_field", self.device)
+        _need(params, torch.float32, self.param_count(n), "params", self.device)
+        _need(grad_field, torch.complex64, self._field_numel(), "grad_field", self.device)
         if grads is None:
             grads = torch.empty_like(params)
         _check(lib().cgh_rasterize_adjoint(self.handle, _ptr(params), int(n), _ptr(grad_field),
                                            _ptr(grads), _stream(self.device)))
         return grads
+
+    def set_hologram_optics(self, hologram, wavelengths, zs, stream=None):
+        """cgh_set_hologram_optics: new optics for one hologram of a batch."""
+        if len(wavelengths) != self.C or len(zs) != self.L:
+            raise ValueError(f"need {self.C} wavelengths and {self.L} distances")
+        lam = (ctypes.c_double * self.C)(*[float(x) for x in wavelengths])
+        zz = (ctypes.c_double * self.L)(*[float(x) for x in zs])
+        st = _stream(self.device) if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(lib().cgh_set_hologram_optics(self.handle, int(hologram),
+                                             ctypes.cast(lam, ctypes.c_void_p),
+                                             ctypes.cast(zz, ctypes.c_void_p), st))
 
     def get_transfer(self, channel=0, plane=0):
         out = torch.empty((self.Hp // 2 + 1, self.Wp // 2 + 1), dtype=torch.complex64,
@@ -363,20 +421,22 @@ class Solve:
     """cgh_solve_*: ``steps`` Adam steps of L_MSE on ``ctx`` captured once as a
     HIP graph over the given buffers (params and target are read when a launch
     starts; params holds the result).  The solve owns its field, gradient,
-    moment and loss-log buffers (``self.loss_log``: [steps][2] doubles)."""
+    moment and loss-log buffers (``self.loss_log``: [steps][2] doubles, or
+    [steps][B][2] for a batch)."""
 
     def __init__(self, ctx, params, n, target, steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
                  stream=None):
         dev = ctx.device
-        _need(params, torch.float32, param_count(n, ctx.C), "params", dev)
-        _need(target, torch.float32, ctx.L * ctx.C * ctx.H * ctx.W, "target", dev)
+        _need(params, torch.float32, ctx.param_count(n), "params", dev)
+        _need(target, torch.float32, ctx._plane_numel(), "target", dev)
         self.ctx, self.n, self.steps = ctx, n, steps
         self.params, self.target = params, target
         self.field = torch.empty(ctx.field_shape(), dtype=torch.complex64, device=dev)
         self.grads = torch.empty_like(params)
         self.m = torch.zeros_like(params)
         self.v = torch.zeros_like(params)
-        self.loss_log = torch.zeros((steps, 2), dtype=torch.float64, device=dev)
+        shape = (steps, 2) if ctx.B == 1 else (steps, ctx.B, 2)
+        self.loss_log = torch.zeros(shape, dtype=torch.float64, device=dev)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
         handle = ctypes.c_void_p()
         _check(lib().cgh_solve_create(ctx.handle, _ptr(params), int(n), _ptr(target),

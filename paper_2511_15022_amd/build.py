@@ -1,4 +1,5 @@
 """Build libcgh.so (all HIP sources, gfx950) in-tree, next to this file."""
+import concurrent.futures
 import glob
 import os
 import subprocess
@@ -21,19 +22,40 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc] + HIPCC_FLAGS + SOURCES + ["-o", LIB + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     # the host pass does not know the device feature flag; drop that one warning
     noise = "'-packed-fp32-ops' is not a recognized feature"
     msgs = [l for l in (res.stdout + res.stderr).splitlines() if noise not in l]
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
-    if verbose and msgs:
-        print("\n".join(msgs))
+    return res.returncode, msgs
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles every source to an object in parallel, then links libcgh.so."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.basename(src)[:-4] + ".o")
+        jobs.append((src, obj, [hipcc] + compile_flags + ["-c", src, "-o", obj]))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        results = list(ex.map(lambda j: (j, _run(j[2])), jobs))
+    for (src, _, cmd), (rc, msgs) in results:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        if rc != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n" + "\n".join(msgs))
+        if verbose and msgs:
+            print("\n".join(msgs))
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for _, o, _ in jobs] + [
+        "-o", LIB + ".tmp"]
+    if verbose:
+        print(" ".join(link), flush=True)
+    rc, msgs = _run(link)
+    if rc != 0:
+        raise RuntimeError("link failed:\n" + "\n".join(msgs))
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

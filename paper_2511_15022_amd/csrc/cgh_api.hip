@@ -88,11 +88,25 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
     return fail(CGH_ERR_INVALID_ARG, "max_gaussians must be in [0, 2^28]");
   if (f.max_pairs < 0 || f.max_pairs > 0x7fffffffLL)
     return fail(CGH_ERR_INVALID_ARG, "max_pairs must be in [0, 2^31)");
-  const int32_t known = CGH_FULL_LOSS | CGH_PAPER_ALPHA;
+  const int32_t known = CGH_FULL_LOSS | CGH_PAPER_ALPHA | CGH_CHECK_FINITE;
   if (f.flags & ~known)
     return fail(CGH_ERR_INVALID_ARG, "flags: unknown bits 0x%x", f.flags & ~known);
   if ((f.flags & CGH_FULL_LOSS) && (f.height < 11 || f.width < 11))
     return fail(CGH_ERR_INVALID_ARG, "CGH_FULL_LOSS needs height, width >= 11 (the SSIM window)");
+  const int tw = f.tile_w ? f.tile_w : kTile, th = f.tile_h ? f.tile_h : kTile;
+  if ((f.tile_w == 0) != (f.tile_h == 0))
+    return fail(CGH_ERR_INVALID_ARG, "tile_w and tile_h must both be 0 or both be set");
+  if (!((tw == 16 && th == 16) || (tw == 32 && th == 8) || (tw == 16 && th == 8) ||
+        (tw == 8 && th == 8)))
+    return fail(CGH_ERR_UNSUPPORTED,
+                "tile %d x %d: the rasterizer supports 16 x 16, 32 x 8, 16 x 8 and 8 x 8", tw, th);
+  const int B = f.batch ? f.batch : 1;
+  if (B < 1 || B > CGH_MAX_BATCH)
+    return fail(CGH_ERR_INVALID_ARG, "batch must be in [1, %d] (got %d)", CGH_MAX_BATCH, f.batch);
+  if (B > 1 && (f.flags & CGH_FULL_LOSS))
+    return fail(CGH_ERR_UNSUPPORTED, "CGH_FULL_LOSS needs a context of one hologram");
+  if ((int64_t)B * f.max_gaussians > (1 << 28))
+    return fail(CGH_ERR_INVALID_ARG, "batch * max_gaussians must be <= 2^28");
 
   c->cfg = f;
   c->cfg.pad_height = Hp;
@@ -105,20 +119,37 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
   c->Wp = Wp;
   c->Hq = Hp / 2 + 1;
   c->Wq = Wp / 2 + 1;
+  c->cfg.tile_w = tw;
+  c->cfg.tile_h = th;
+  c->cfg.batch = B;
+  c->B = B;
+  c->CF = B * f.channels;
   c->Wt = (Wp + 7) / 8;
-  c->tiles_x = (f.width + kTile - 1) / kTile;
-  c->tiles_y = (f.height + kTile - 1) / kTile;
-  c->num_tiles = c->tiles_x * c->tiles_y;
+  c->tile_w = tw;
+  c->tile_h = th;
+  c->tiles_x = (f.width + tw - 1) / tw;
+  c->tiles_y = (f.height + th - 1) / th;
+  c->tiles_per = c->tiles_x * c->tiles_y;
+  if ((int64_t)B * c->tiles_per > (1LL << 30))
+    return fail(CGH_ERR_INVALID_ARG, "too many tiles (%lld)", (long long)B * c->tiles_per);
+  c->num_tiles = B * c->tiles_per;
   int bits = 0;
   while ((1 << bits) < c->num_tiles) ++bits;
   c->sort_passes = (bits + kSortBits - 1) / kSortBits;
-  int64_t cap = f.max_pairs ? f.max_pairs : 8LL * f.max_gaussians + 65536;
+  // about 3 (16 x 16) to 7 (8 x 8) tiles per Gaussian at the synthetic scales
+  const int64_t per = tw * th <= 64 ? 16 : 8;
+  int64_t cap = f.max_pairs ? f.max_pairs : per * B * f.max_gaussians + 65536;
   if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
   c->pair_cap = cap;
   c->sort_blocks = (int)((cap + kSortItems - 1) / kSortItems);
   c->rec_stride = rec_stride(c->C);
   c->part_stride = partial_stride(c->C);
   c->last_n = -1;
+  c->gen = 0;
+  for (int b = 0; b < B; ++b) {
+    for (int ch = 0; ch < f.channels; ++ch) c->lam[b][ch] = f.wavelength_m[ch];
+    for (int l = 0; l < f.num_planes; ++l) c->zd[b][l] = f.z_m[l];
+  }
   c->sorted = 0;
   c->num_cu = 1;
   c->prof_class = 0;
@@ -158,7 +189,7 @@ size_t carve(Ctx *c, char *base) {
     off += bytes;
     return p;
   };
-  const size_t N = (size_t)c->cfg.max_gaussians;
+  const size_t N = (size_t)c->B * c->cfg.max_gaussians;  // Gaussians of all holograms
   const size_t cap = (size_t)c->pair_cap;
   const size_t HW = (size_t)c->H * c->W;
   c->tw_x = (float2 *)take(sizeof(float2) * kTwTable);
@@ -166,19 +197,19 @@ size_t carve(Ctx *c, char *base) {
   c->tw_m = (float2 *)take(sizeof(float2) * kTwTable);
   c->twf_x = (float2 *)take(sizeof(float2) * c->Wp);
   c->twf_m = (float2 *)take(sizeof(float2) * c->plan_m.n);
-  c->htab = (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq);
+  c->htab = (float2 *)take(sizeof(float2) * c->CF * c->L * (size_t)c->Hq * c->Wq);
   const bool wave_cols = col_wave4(*c);
-  c->htab_t = wave_cols ? (float2 *)take(sizeof(float2) * c->C * c->L * (size_t)c->Hq * c->Wq)
+  c->htab_t = wave_cols ? (float2 *)take(sizeof(float2) * c->CF * c->L * (size_t)c->Hq * c->Wq)
                         : nullptr;
   c->twf_y = wave_cols ? (float2 *)take(sizeof(float2) * c->Hp) : nullptr;
-  const size_t spec_len = (size_t)c->C * c->Wt * c->H * 8;
+  const size_t spec_len = (size_t)c->CF * c->Wt * c->H * 8;
   c->spec = (float2 *)take(sizeof(float2) * spec_len);
   // with several planes the shared row spectrum stays in spec; each plane's
   // column pass writes spec_plane, and the adjoint sums the planes in spec_acc
   c->spec_plane = c->L > 1 ? (float2 *)take(sizeof(float2) * spec_len) : c->spec;
   c->spec_acc = c->L > 1 ? (float2 *)take(sizeof(float2) * spec_len) : c->spec;
-  c->field_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
-  c->gfield_tmp = (float2 *)take(sizeof(float2) * c->C * HW);
+  c->field_tmp = (float2 *)take(sizeof(float2) * c->CF * HW);
+  c->gfield_tmp = (float2 *)take(sizeof(float2) * c->CF * HW);
   c->rec = (float *)take(sizeof(float) * c->rec_stride * (N + 1));
   c->alim = (c->cfg.flags & CGH_PAPER_ALPHA) ? (float2 *)take(sizeof(float2) * (N + 1)) : nullptr;
   c->rect = (uint2 *)take(sizeof(uint2) * (N ? N : 1));
@@ -194,8 +225,9 @@ size_t carve(Ctx *c, char *base) {
   c->scan_tmp = (uint32_t *)take(sizeof(uint32_t) * (scan_len / kScanItems + 2));
   c->partials = (float *)take(sizeof(float) * c->part_stride * cap);
   const int rg = row_group_rows(*c);  // one loss partial per row-pass workgroup
-  c->loss_part = (double *)take(sizeof(double) * c->L * c->C * (size_t)((c->H + rg - 1) / rg));
+  c->loss_part = (double *)take(sizeof(double) * c->L * c->CF * (size_t)((c->H + rg - 1) / rg));
   c->status = (uint32_t *)take(sizeof(uint32_t) * 4);
+  c->finite_flag = (c->cfg.flags & CGH_CHECK_FINITE) && c->status ? c->status + 3 : nullptr;
   c->ssim_I = nullptr;
   c->ssim_u = nullptr;
   c->ssim_abc = nullptr;
@@ -264,7 +296,7 @@ cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_b
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_x, c.Wp, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_m, c.plan_m.n, s), "twiddles");
   if (c.twf_y) CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_y, c.Hp, s), "twiddles");
-  CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, s), "transfer function");
+  CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, 0, c.B, s), "transfer function");
   CGH_CHECK_LAUNCH(cgh::launch_zero_record(c, s), "zero record");
   CGH_CHECK_LAUNCH(cgh::launch_zero_status(c, s), "zero status");
   hipError_t e = hipStreamSynchronize(s);
@@ -293,6 +325,21 @@ static cgh_status check_n(const Ctx &c, int32_t n) {
   return CGH_OK;
 }
 
+// preprocess and binning of Alg. 2: the tile lists of params, a new generation
+static cgh_status build_lists(Ctx &c, const float *params, int32_t n, hipStream_t s) {
+  {
+    ProfScope p(c, CGH_KERNEL_PREPROCESS, s);
+    CGH_CHECK_LAUNCH(cgh::launch_preprocess(c, params, n, s), "preprocess");
+  }
+  {
+    ProfScope p(c, CGH_KERNEL_BINNING, s);
+    CGH_CHECK_LAUNCH(cgh::launch_binning(c, n, s), "binning");
+  }
+  c.last_n = n;
+  ++c.gen;
+  return CGH_OK;
+}
+
 cgh_status cgh_rasterize(cgh_ctx *ctx, const float *params, int32_t n, cgh_c64 *field,
                          void *stream) {
   if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
@@ -302,19 +349,25 @@ cgh_status cgh_rasterize(cgh_ctx *ctx, const float *params, int32_t n, cgh_c64 *
   if ((n > 0 && !params) || !field) return fail(CGH_ERR_INVALID_ARG, "params/field is NULL");
   if (!aligned16(field)) return fail(CGH_ERR_INVALID_ARG, "field must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  {
-    ProfScope p(c, CGH_KERNEL_PREPROCESS, s);
-    CGH_CHECK_LAUNCH(cgh::launch_preprocess(c, params, n, s), "preprocess");
-  }
-  {
-    ProfScope p(c, CGH_KERNEL_BINNING, s);
-    CGH_CHECK_LAUNCH(cgh::launch_binning(c, n, s), "binning");
-  }
-  {
-    ProfScope p(c, CGH_KERNEL_RASTER, s);
-    CGH_CHECK_LAUNCH(cgh::launch_raster_fwd(c, reinterpret_cast<float2 *>(field), s), "raster");
-  }
-  c.last_n = n;
+  st = build_lists(c, params, n, s);
+  if (st != CGH_OK) return st;
+  ProfScope p(c, CGH_KERNEL_RASTER, s);
+  CGH_CHECK_LAUNCH(cgh::launch_raster_fwd(c, reinterpret_cast<float2 *>(field), s), "raster");
+  return CGH_OK;
+}
+
+cgh_status cgh_rasterize_lists(cgh_ctx *ctx, const float *params, int32_t n, void *stream) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  Ctx &c = ctx->c;
+  cgh_status st = check_n(c, n);
+  if (st != CGH_OK) return st;
+  if (n > 0 && !params) return fail(CGH_ERR_INVALID_ARG, "params is NULL");
+  return build_lists(c, params, n, (hipStream_t)stream);
+}
+
+cgh_status cgh_generation(cgh_ctx *ctx, int64_t *generation) {
+  if (!ctx || !generation) return fail(CGH_ERR_INVALID_ARG, "ctx/generation is NULL");
+  *generation = ctx->c.gen;
   return CGH_OK;
 }
 
@@ -505,7 +558,7 @@ cgh_status cgh_propagate_field_adjoint(cgh_ctx *ctx, const cgh_c64 *grad_u, cgh_
   for (int l = 0; l < c.L; ++l) {
     {
       ProfScope p(c, CGH_KERNEL_ROW_FFT, s);
-      CGH_CHECK_LAUNCH(cgh::launch_row_fwd(c, g + (size_t)l * c.C * c.H * c.W, c.spec_plane, s),
+      CGH_CHECK_LAUNCH(cgh::launch_row_fwd(c, g + (size_t)l * c.CF * c.H * c.W, c.spec_plane, s),
                        "adjoint seed row fft");
     }
     cgh_status st = plane_adjoint(c, l, s);
@@ -618,7 +671,7 @@ cgh_status cgh_get_transfer(cgh_ctx *ctx, int32_t channel, int32_t plane, cgh_c6
                             void *stream) {
   if (!ctx || !out) return fail(CGH_ERR_INVALID_ARG, "ctx/out is NULL");
   Ctx &c = ctx->c;
-  if (channel < 0 || channel >= c.C || plane < 0 || plane >= c.L)
+  if (channel < 0 || channel >= c.CF || plane < 0 || plane >= c.L)
     return fail(CGH_ERR_INVALID_ARG, "channel/plane out of range");
   const size_t elems = (size_t)c.Hq * c.Wq;
   hipError_t e = hipMemcpyAsync(out, c.htab + ((size_t)channel * c.L + plane) * elems,
@@ -670,8 +723,9 @@ cgh_status cgh_profile_end(cgh_ctx *ctx, void *stream, double *total_ms, int32_t
   return CGH_OK;
 }
 
-cgh_status cgh_set_optics(cgh_ctx *ctx, const double *wavelength_m, const double *z_m,
-                          void *stream) {
+// new optics for holograms [b0, b1) of ctx; validated before anything changes
+static cgh_status set_optics_range(cgh_ctx *ctx, int b0, int b1, const double *wavelength_m,
+                                   const double *z_m, void *stream) {
   if (!ctx || !wavelength_m || !z_m) return fail(CGH_ERR_INVALID_ARG, "ctx/wavelength/z is NULL");
   Ctx &c = ctx->c;
   for (int ch = 0; ch < c.C; ++ch)
@@ -679,10 +733,30 @@ cgh_status cgh_set_optics(cgh_ctx *ctx, const double *wavelength_m, const double
       return fail(CGH_ERR_INVALID_ARG, "wavelength of channel %d must be positive", ch);
   for (int l = 0; l < c.L; ++l)
     if (!std::isfinite(z_m[l])) return fail(CGH_ERR_INVALID_ARG, "z of plane %d not finite", l);
-  for (int ch = 0; ch < c.C; ++ch) c.cfg.wavelength_m[ch] = wavelength_m[ch];
-  for (int l = 0; l < c.L; ++l) c.cfg.z_m[l] = z_m[l];
-  CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, (hipStream_t)stream), "transfer function");
+  for (int b = b0; b < b1; ++b) {
+    for (int ch = 0; ch < c.C; ++ch) c.lam[b][ch] = wavelength_m[ch];
+    for (int l = 0; l < c.L; ++l) c.zd[b][l] = z_m[l];
+  }
+  if (b0 == 0 && b1 == c.B) {
+    for (int ch = 0; ch < c.C; ++ch) c.cfg.wavelength_m[ch] = wavelength_m[ch];
+    for (int l = 0; l < c.L; ++l) c.cfg.z_m[l] = z_m[l];
+  }
+  CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, b0, b1, (hipStream_t)stream),
+                   "transfer function");
   return CGH_OK;
+}
+
+cgh_status cgh_set_optics(cgh_ctx *ctx, const double *wavelength_m, const double *z_m,
+                          void *stream) {
+  return set_optics_range(ctx, 0, ctx ? ctx->c.B : 0, wavelength_m, z_m, stream);
+}
+
+cgh_status cgh_set_hologram_optics(cgh_ctx *ctx, int32_t hologram, const double *wavelength_m,
+                                   const double *z_m, void *stream) {
+  if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
+  if (hologram < 0 || hologram >= ctx->c.B)
+    return fail(CGH_ERR_INVALID_ARG, "hologram %d outside [0, %d)", hologram, ctx->c.B);
+  return set_optics_range(ctx, hologram, hologram + 1, wavelength_m, z_m, stream);
 }
 
 }  // extern "C"
@@ -698,13 +772,13 @@ cgh_status record_solve(cgh_ctx *ctx, float *params, int32_t n, const float *tar
                         cgh_c64 *field, float *grads, float *m, float *v, double *loss_log,
                         int32_t steps, float lr, float beta1, float beta2, float eps,
                         hipStream_t s) {
-  const int64_t count = (int64_t)n * (6 + 2 * ctx->c.C);
+  const int64_t count = cgh::total_gaussians(ctx->c, n) * (6 + 2 * ctx->c.C);
   CGH_CHECK_LAUNCH(cgh::launch_zero_pair(m, v, count, s), "solve: zero moments");
   for (int32_t t = 1; t <= steps; ++t) {
     cgh_status st = cgh_rasterize(ctx, params, n, field, s);
     if (st == CGH_OK)
-      st = cgh_backward(ctx, params, n, field, target, loss_log + 2 * (int64_t)(t - 1), nullptr,
-                        grads, s);
+      st = cgh_backward(ctx, params, n, field, target,
+                        loss_log + 2 * (int64_t)ctx->c.B * (t - 1), nullptr, grads, s);
     if (st == CGH_OK)
       st = cgh_step(params, grads, m, v, count, t, lr, beta1, beta2, eps, nullptr, ctx->c.C, s);
     if (st != CGH_OK) return st;
@@ -785,14 +859,14 @@ cgh_status cgh_read_status(cgh_ctx *ctx, void *stream, int64_t *pairs) {
   Ctx &c = ctx->c;
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return device_fail(e, "cgh_read_status");
-  uint32_t st[3] = {0, 0, 0};
+  uint32_t st[4] = {0, 0, 0, 0};
   e = hipMemcpy(st, c.status, sizeof(st), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return device_fail(e, "cgh_read_status");
   if (pairs) *pairs = (int64_t)st[1];
-  if (st[2]) {
-    // an overflow since the last read: report it once
-    const uint32_t zero = 0u;
-    e = hipMemcpy(c.status + 2, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  if (st[2] || st[3]) {
+    // an overflow or a non-finite value since the last read: report it once
+    const uint32_t zero[2] = {0u, 0u};
+    e = hipMemcpy(c.status + 2, zero, sizeof(zero), hipMemcpyHostToDevice);
     if (e != hipSuccess) return device_fail(e, "cgh_read_status");
   }
   if (st[0])
@@ -802,6 +876,11 @@ cgh_status cgh_read_status(cgh_ctx *ctx, void *stream, int64_t *pairs) {
     return fail(CGH_ERR_CAPACITY,
                 "a rasterize since the last status read overflowed the pair list (capacity "
                 "%lld; the last one needed %u entries)", (long long)c.pair_cap, st[1]);
+  if (st[3])
+    return fail(CGH_ERR_NONFINITE, "non-finite values since the last status read in:%s%s%s",
+                (st[3] & cgh::kNonFiniteParams) ? " parameters" : "",
+                (st[3] & cgh::kNonFiniteGrads) ? " gradients" : "",
+                (st[3] & cgh::kNonFiniteLoss) ? " loss" : "");
   return CGH_OK;
 }
 

@@ -10,7 +10,8 @@
 
 namespace cgh {
 
-constexpr int kTile = 16;          // rasterizer tile edge, pixels
+constexpr int kTile = 16;          // default rasterizer tile edge, pixels
+constexpr int kMaxBatch = CGH_MAX_BATCH;
 constexpr int kMaxStages = 16;     // radix stages per FFT length
 constexpr int kMaxFft = 8192;      // longest supported FFT
 constexpr int kSortBits = 8;       // bits per radix-sort pass
@@ -59,11 +60,22 @@ enum RecField {
 inline int rec_stride(int C) { return ((R_AMP + 2 * C) + 3) & ~3; }
 inline int partial_stride(int C) { return ((2 * C + 5) + 3) & ~3; }
 
+// Bits of the sticky non-finite word (status[3]) of a CGH_CHECK_FINITE context.
+constexpr uint32_t kNonFiniteParams = 1u, kNonFiniteGrads = 2u, kNonFiniteLoss = 4u;
+
 struct Ctx {
   cgh_config cfg;
   int H, W, C, L, Hp, Wp, Hq, Wq;   // Hq, Wq: quarter-table extents Hp/2+1, Wp/2+1
+  int B;                            // holograms in the context
+  int CF;                           // B C: channels of the propagation (hologram-major)
   int Wt;                           // column tiles of 8 in the propagation buffer
-  int tiles_x, tiles_y, num_tiles, sort_passes;
+  int tile_w, tile_h;               // rasterizer tile, pixels
+  int tiles_x, tiles_y;             // tiles of one hologram per row / column
+  int tiles_per;                    // tiles_x tiles_y
+  int num_tiles, sort_passes;       // num_tiles = B tiles_per (sort keys b tiles_per + tile)
+  int64_t gen;                      // rasterize / rasterize_lists calls so far
+  double lam[kMaxBatch][CGH_MAX_CHANNELS];  // wavelength of (hologram, colour)
+  double zd[kMaxBatch][CGH_MAX_PLANES];     // distance of (hologram, plane)
   int64_t pair_cap;
   int sort_blocks;                  // radix-sort grid (covers pair_cap)
   int rec_stride, part_stride;
@@ -73,34 +85,37 @@ struct Ctx {
   // workspace carve (device pointers)
   float2 *tw_x, *tw_y, *tw_m;       // two-level twiddle tables for Wp, Hp, Hp/2
   float2 *twf_x, *twf_m;            // full twiddle tables for Wp and Hp/2 (Hp if odd)
-  float2 *htab;                     // [C][L][Hq][Wq]
-  float2 *htab_t;                   // [C][L][Wq][Hq] (column-major copy), wave column pass only
+  float2 *htab;                     // [B C][L][Hq][Wq]
+  float2 *htab_t;                   // [B C][L][Wq][Hq] (column-major copy), wave column pass only
   float2 *twf_y;                    // full twiddle table for Hp, wave column pass only
-  float2 *spec;                     // [C][Wt][H][8] column-tiled propagation buffer
+  float2 *spec;                     // [B C][Wt][H][8] column-tiled propagation buffer
   float2 *spec_plane;               // per-plane column-pass output (spec itself when L = 1)
   float2 *spec_acc;                 // adjoint sum over planes (spec itself when L = 1)
-  float2 *field_tmp;                // [C][H][W]
-  float2 *gfield_tmp;               // [C][H][W]
-  float *rec;                       // [max_gaussians + 1][rec_stride]; the last is all zeros
-  float2 *alim;                     // CGH_PAPER_ALPHA only, else null: [max_gaussians + 1]
+  float2 *field_tmp;                // [B C][H][W]
+  float2 *gfield_tmp;               // [B C][H][W]
+  float *rec;                       // [B max_gaussians + 1][rec_stride]; the last is all zeros
+  float2 *alim;                     // CGH_PAPER_ALPHA only, else null: [B max_gaussians + 1]
                                     // (lo, hi) exponent limits, log2 G in [lo, .) kept,
                                     // clamped at hi (the last entry (0, 0))
-  uint2 *rect;                      // [max_gaussians] tile rectangles (x0|x1<<16, y0|y1<<16)
-  uint32_t *counts;                 // [max_gaussians]
-  uint32_t *offsets;                // [max_gaussians + 1]
+  uint2 *rect;                      // [B max_gaussians] tile rectangles (x0|x1<<16, y0|y1<<16)
+  uint32_t *counts;                 // [B max_gaussians]
+  uint32_t *offsets;                // [B max_gaussians + 1]
   uint32_t *keys[2], *vals[2];      // [pair_cap] ping-pong (tile id, Gaussian id)
   uint2 *ranges;                    // [num_tiles] [start, end) into the sorted list
   uint32_t *hist;                   // [256 * sort_blocks] digit-major block histograms
   uint32_t *scan_tmp;               // partial sums for scans
   float *partials;                  // [pair_cap][part_stride] raster-adjoint partials
-  double *loss_part;                // [L][row-pass workgroups] FP64 loss partials
+  double *loss_part;                // [L][row-pass workgroups] FP64 loss partials (the
+                                    // workgroups of hologram b contiguous in each plane)
   // cgh_backward_full only (CGH_FULL_LOSS), else null
   float *ssim_I;                    // [L][C][H][W] intensity
   float2 *ssim_u;                   // [L][C][H][W] propagated field, then 2 dL/dI u
   float *ssim_abc;                  // [3][L][C][H - 10][W - 10] SSIM gradient coefficients
   double *ssim_part;                // [L][C][position tiles] sums of SSIM
   double *mse_part;                 // [L][C][pixel tiles] sums of (I - T)^2
-  uint32_t *status;                 // [0] overflow flag, [1] pair total, [2] sticky overflow
+  uint32_t *status;                 // [0] overflow flag, [1] pair total, [2] sticky overflow,
+                                    // [3] sticky non-finite bits (kNonFinite*)
+  uint32_t *finite_flag;            // status + 3 with CGH_CHECK_FINITE, else null
   int sorted;                       // which ping-pong buffer holds the sorted pairs
   // kernel-class timing (cgh_profile_begin / _end)
   int prof_class;                   // 0: off
@@ -128,7 +143,8 @@ inline bool col_wave4(const Ctx &c) { return col_wave4_m(c) != 0; }
 hipError_t launch_build_twiddles(float2 *tw, int n, hipStream_t s);
 hipError_t launch_build_twiddles_full(float2 *tw, int n, hipStream_t s);
 int row_group_rows(const Ctx &c);   // rows per row-pass workgroup
-hipError_t launch_build_transfer(const Ctx &c, hipStream_t s);
+// transfer tables of holograms [b0, b1) from c.lam, c.zd
+hipError_t launch_build_transfer(const Ctx &c, int b0, int b1, hipStream_t s);
 hipError_t launch_row_fwd(const Ctx &c, const float2 *field, float2 *dst, hipStream_t s);
 hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStream_t s);
 // column pass of plane `plane`: src -> dst (may alias); acc adds into dst
@@ -150,6 +166,8 @@ hipError_t launch_ssim_bwd(const Ctx &c, const float *target, const float *mask,
 hipError_t launch_full_loss_finalize(const Ctx &c, float ssim_weight, double *loss,
                                      hipStream_t s);
 
+// the number of Gaussians of all holograms: B n
+inline int64_t total_gaussians(const Ctx &c, int n) { return (int64_t)c.B * n; }
 hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s);
 hipError_t launch_zero_record(const Ctx &c, hipStream_t s);
 hipError_t launch_zero_status(const Ctx &c, hipStream_t s);

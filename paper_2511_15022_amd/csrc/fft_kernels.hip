@@ -249,18 +249,19 @@ __global__ void k_transfer(float2 *out, float2 *out_t, double t_scale, int Hq, i
     out_t[(size_t)qx * Hq + qy] = make_float2((float)(cs * t_scale), (float)(sn * t_scale));
 }
 
-hipError_t launch_build_transfer(const Ctx &c, hipStream_t s) {
-  for (int ch = 0; ch < c.C; ++ch)
-    for (int l = 0; l < c.L; ++l) {
-      const size_t at = ((size_t)ch * c.L + l) * c.Hq * c.Wq;
-      hipLaunchKernelGGL(k_transfer, dim3((c.Wq + 255) / 256, c.Hq), dim3(256), 0, s,
-                         c.htab + at, c.htab_t ? c.htab_t + at : nullptr,
-                         1.0 / ((double)c.Hp * (double)c.Wp), c.Hq, c.Wq, c.Hp, c.Wp,
-                         c.cfg.pitch_m, c.cfg.wavelength_m[ch], c.cfg.z_m[l],
-                         c.cfg.aperture);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
+hipError_t launch_build_transfer(const Ctx &c, int b0, int b1, hipStream_t s) {
+  for (int b = b0; b < b1; ++b)
+    for (int ch = 0; ch < c.C; ++ch)
+      for (int l = 0; l < c.L; ++l) {
+        // propagation channel b C + ch: colour ch of hologram b
+        const size_t at = (((size_t)b * c.C + ch) * c.L + l) * c.Hq * c.Wq;
+        hipLaunchKernelGGL(k_transfer, dim3((c.Wq + 255) / 256, c.Hq), dim3(256), 0, s,
+                           c.htab + at, c.htab_t ? c.htab_t + at : nullptr,
+                           1.0 / ((double)c.Hp * (double)c.Wp), c.Hq, c.Wq, c.Hp, c.Wp,
+                           c.cfg.pitch_m, c.lam[b][ch], c.zd[b][l], c.cfg.aperture);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
   return hipSuccess;
 }
 
@@ -392,7 +393,7 @@ template <int MAXN>
 __global__ __launch_bounds__(kRowThreads) void k_row_loss(
     float2 *__restrict__ S, int H, int W, int Wt, FftPlan p, const float2 *__restrict__ twx,
     const float *__restrict__ target, const float *__restrict__ grad_I,
-    const float *__restrict__ mask, float *__restrict__ intensity, float2 *__restrict__ u_out,
+    const float *__restrict__ mask, int mcg, float *__restrict__ intensity, float2 *__restrict__ u_out,
     double *__restrict__ loss_part, float gscale, int make_grad) {
   extern __shared__ float2 sbuf[];
   __shared__ TwLds tw;
@@ -401,6 +402,7 @@ __global__ __launch_bounds__(kRowThreads) void k_row_loss(
   const int pairs = (H + 1) >> 1;
   const int c = blockIdx.x / pairs, y0 = 2 * (blockIdx.x % pairs);
   load_tw<kRowThreads>(tw, twx, tid);
+  if (mask) mask += (size_t)(c / mcg) * H * W;
   load_rows_tiled(sbuf, S, c, y0, H, n, Wt, tid);
   __syncthreads();
   fft_lds<+1, 2, kRowThreads, MAXN>(sbuf, p, tw, tid);
@@ -557,7 +559,7 @@ template <int N, int ROWS, int T, bool FULL>
 __global__ __launch_bounds__(T) void k_row_loss_c(
     float2 *__restrict__ S, int H, int W, int Wt, const float2 *__restrict__ twf,
     const float2 *__restrict__ tw2, const float *__restrict__ target,
-    const float *__restrict__ grad_I, const float *__restrict__ mask,
+    const float *__restrict__ grad_I, const float *__restrict__ mask, int mcg,
     float *__restrict__ intensity, float2 *__restrict__ u_out, double *__restrict__ loss_part,
     float gscale, int make_grad) {
   __shared__ float2 sbuf[ROWS * N];
@@ -568,6 +570,7 @@ __global__ __launch_bounds__(T) void k_row_loss_c(
   const int groups = (H + ROWS - 1) / ROWS;
   const int c = blockIdx.x / groups, y0 = ROWS * (blockIdx.x % groups);
   const int nw = ROWS * W;  // element i: row y0 + i / W, column i % W
+  if (mask) mask += (size_t)(c / mcg) * H * W;
   tw.template load<T>(twf, tw2, tid);
   load_rows_c<N, ROWS, T>(sbuf, S, c, y0, H, Wt, tid);
   // the target (or the caller's dL/dI) of this thread's elements, fetched
@@ -780,7 +783,7 @@ template <int M>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_row_loss_q(
     float2 *__restrict__ S, int H, int W, int rows, const float2 *__restrict__ twf_x,
     const float *__restrict__ target, const float *__restrict__ grad_I,
-    const float *__restrict__ mask, float *__restrict__ intensity, float2 *__restrict__ u_out,
+    const float *__restrict__ mask, int mcg, float *__restrict__ intensity, float2 *__restrict__ u_out,
     double *__restrict__ loss_part, float gscale, int make_grad) {
   constexpr int T = 512, K = (M + T - 1) / T, Wt = M / 2;
   __shared__ float2 buf[4 * M];
@@ -791,6 +794,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   float2 *Sc = S + (size_t)c * Wt * H * 8;
   load_quarter_table<M, T>(tw, twf_x, tid);
   load_quarter_row<M, T>(buf, Sc, H, y, tid);
+  if (mask) mask += (size_t)(c / mcg) * H * W;
   // per-element inputs at n and n + M, fetched before the transform so that
   // their latency overlaps it
   const float *tsrc = target ? target : grad_I;
@@ -884,7 +888,7 @@ int row_group_rows(const Ctx &c) {
 }
 static int row_blocks(const Ctx &c) {
   const int r = row_group_rows(c);
-  return c.C * ((c.H + r - 1) / r);
+  return c.CF * ((c.H + r - 1) / r);
 }
 static size_t row_lds(const Ctx &c) { return (size_t)2 * c.Wp * sizeof(float2); }
 
@@ -933,37 +937,40 @@ hipError_t launch_row_inv(const Ctx &c, const float2 *src, float2 *out, hipStrea
 hipError_t launch_row_loss(const Ctx &c, int plane, float2 *buf, const float *target,
                            const float *grad_intensity, const float *mask, float *intensity,
                            float2 *u_out, int make_grad, hipStream_t s) {
+  // the loss of each hologram is its own mean over L C H W
   const double M = (double)c.L * c.C * c.H * c.W;
   const float gscale = (float)(4.0 / M);
-  // plane l of the [L][C][H][W] arrays; its loss partials after those of planes < l
-  const size_t po = (size_t)plane * c.C * c.H * c.W;
+  // plane l of the [L][B C][H][W] arrays; its loss partials after those of planes < l
+  const size_t po = (size_t)plane * c.CF * c.H * c.W;
   if (target) target += po;
   if (grad_intensity) grad_intensity += po;
   if (intensity) intensity += po;
   if (u_out) u_out += po;
-  if (mask) mask += (size_t)plane * c.H * c.W;  // [L][H][W]
+  // [L][B][H][W]: propagation channel ch reads the mask of hologram ch / C
+  if (mask) mask += (size_t)plane * c.B * c.H * c.W;
+  const int mcg = c.C;
   double *lp = c.loss_part + (size_t)plane * row_blocks(c);
   if (row_quarter(c))
     with_quarter(c, [&](auto mc) {
       hipLaunchKernelGGL(k_row_loss_q<decltype(mc)::value>, dim3(row_blocks(c)), dim3(512), 0, s,
-                         buf, c.H, c.W, row_blocks(c), c.twf_x, target, grad_intensity, mask,
+                         buf, c.H, c.W, row_blocks(c), c.twf_x, target, grad_intensity, mask, mcg,
                          intensity, u_out, lp, gscale, make_grad);
     });
   else if (c.Wp == 3840)
     hipLaunchKernelGGL((k_row_loss_c<3840, 2, 512, false>), dim3(row_blocks(c)), dim3(512), 0, s,
-                       buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, mask, intensity,
+                       buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, mask, mcg, intensity,
                        u_out, lp, gscale, make_grad);
   else if (c.Wp == 512)
     hipLaunchKernelGGL((k_row_loss_c<512, 4, 256, true>), dim3(row_blocks(c)), dim3(256), 0, s,
-                       buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, mask, intensity,
+                       buf, c.H, c.W, c.Wt, c.twf_x, c.tw_x, target, grad_intensity, mask, mcg, intensity,
                        u_out, lp, gscale, make_grad);
   else if (c.Wp <= 4096)
     hipLaunchKernelGGL(k_row_loss<4096>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
-                       buf, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity, mask,
+                       buf, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity, mask, mcg,
                        intensity, u_out, lp, gscale, make_grad);
   else
     hipLaunchKernelGGL(k_row_loss<8192>, dim3(row_blocks(c)), dim3(kRowThreads), row_lds(c), s,
-                       buf, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity, mask,
+                       buf, c.H, c.W, c.Wt, c.plan_x, c.tw_x, target, grad_intensity, mask, mcg,
                        intensity, u_out, lp, gscale, make_grad);
   return hipGetLastError();
 }
@@ -1209,89 +1216,6 @@ __global__ __launch_bounds__(T) void k_col_half_c(ColIO io, int H, int Wp, int W
 }
 
 // ----------------------------------------------------------------------------
-// Even/odd column pass for long columns (M = Hp / 2 = 2160 at 4K): a workgroup
-// takes half a tile (4 columns) and keeps both chains of each column in LDS,
-// eight interleaved M-point transforms (chain b = 2 c + p at buf[m * 8 + b]),
-// so no chain result has to wait in registers.  Blocks 2 t and 2 t + 1 take
-// the two halves of tile t.  Needs Wp % 8 == 0 and H <= M.
-// ----------------------------------------------------------------------------
-template <int M, int T>
-__global__ __launch_bounds__(T) void k_col_both(ColIO io, int H, int Wp, int Wt,
-                                                const float2 *__restrict__ twf_m,
-                                                const float2 *__restrict__ twh, int Wq,
-                                                int conj_h, float scale) {
-  __shared__ float2 buf[8 * M];
-  __shared__ float2 tw[M];
-  __shared__ TwLds th;
-  constexpr int NE = 4 * M, K = (NE + T - 1) / T, NB = 8 * M, KB = (NB + T - 1) / T;
-  const int tid = threadIdx.x;
-  const int t = blockIdx.x >> 1, part = blockIdx.x & 1, ch = blockIdx.y;
-  const size_t off = ((size_t)ch * Wt + t) * H * 8 + part * 4;
-  const float2 *src = io.src + off;
-  float2 *dst = io.dst + off;
-  const float2 *hc = io.htab + ch * io.hstride;
-  load_table<M, T>(tw, twf_m, tid);
-  load_tw<T>(th, twh, tid);
-  {
-    // element i: row n = i / 4 of column c = i % 4
-    float2 xv[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = min(tid + k * T, NE - 1), n = i >> 2;
-      xv[k] = at32(src, min(n, H - 1) * 8 + (i & 3));
-    }
-    __syncthreads();  // the twiddle tables are read below
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = tid + k * T, n = i >> 2, c = i & 3;
-      if (K * T == NE || i < NE) {
-        const float2 x = n < H ? xv[k] : make_float2(0.f, 0.f);
-        buf[n * 8 + 2 * c] = x;
-        buf[n * 8 + 2 * c + 1] = cmul(x, tw_at(th, n));  // odd chain: x[n] w^n
-      }
-    }
-  }
-  __syncthreads();
-  cfft<-1, 8, T, M>(buf, tw, tid);
-  {
-    // x H(ky = 2 m + p, kx): the table loads of a group are issued before the
-    // first is used
-    constexpr int G = 4;
-    const int kx0 = t * 8 + part * 4;
-#pragma unroll
-    for (int k0 = 0; k0 < KB; k0 += G) {
-      float2 hv[G];
-#pragma unroll
-      for (int k = k0; k < k0 + G && k < KB; ++k) {
-        const int i = min(tid + k * T, NB - 1), m = i >> 3, b = i & 7;
-        const int kx = kx0 + (b >> 1), ky = 2 * m + (b & 1);
-        hv[k - k0] = at32(hc, min(ky, 2 * M - ky) * Wq + min(kx, Wp - kx));
-      }
-#pragma unroll
-      for (int k = k0; k < k0 + G && k < KB; ++k) {
-        const int i = tid + k * T;
-        if (KB * T == NB || i < NB) {
-          float2 h = hv[k - k0];
-          if (conj_h) h.y = -h.y;
-          buf[i] = cmul(buf[i], cscale(h, scale));
-        }
-      }
-    }
-  }
-  __syncthreads();
-  cfft<+1, 8, T, M>(buf, tw, tid);
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = tid + k * T, n = i >> 2, c = i & 3;
-    if ((K * T == NE || i < NE) && n < H) {
-      const float2 y = cadd(buf[n * 8 + 2 * c], cmul(cconj(tw_at(th, n)), buf[n * 8 + 2 * c + 1]));
-      float2 &d = at32(dst, n * 8 + c);
-      d = io.acc ? cadd(d, y) : y;
-    }
-  }
-}
-
-// ----------------------------------------------------------------------------
 // Column pass for Hp = 4 M with H <= 2 M, one wave per chain, M = R0 R1 R2
 // (1080 = 9 6 20 at 4K, 540 = 9 6 10 at 1080p); CONJ: multiply by conj(H)
 // (the adjoint pass).
@@ -1447,9 +1371,9 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
   const float scale = (float)(1.0 / ((double)c.Hp * (double)c.Wp));
   const size_t tab = (size_t)c.Hq * c.Wq;
   const ColIO io{src, dst, c.htab + (size_t)plane * tab, (size_t)c.L * tab, acc};
-  dim3 grid(c.Wt, c.C);
+  dim3 grid(c.Wt, c.CF);
   if (col_wave4(c)) {
-    const int pairs = c.C * ((c.Wt + 1) / 2);
+    const int pairs = c.CF * ((c.Wt + 1) / 2);
     const float2 *ht = c.htab_t + (size_t)plane * tab;
     const dim3 grid4((pairs + 7) / 8 * 64);
     // M = R0 R1 R2 with M / R2 <= 64 (one fused butterfly per lane)
@@ -1457,10 +1381,10 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
       constexpr int R0 = decltype(r0)::value, R1 = decltype(r1)::value, R2 = decltype(r2)::value;
       if (conj_h)
         hipLaunchKernelGGL((k_col_wave4<R0, R1, R2, true>), grid4, dim3(512), 0, s, io, ht, c.Hq,
-                           c.H, c.Wp, c.Wt, c.C, c.twf_y);
+                           c.H, c.Wp, c.Wt, c.CF, c.twf_y);
       else
         hipLaunchKernelGGL((k_col_wave4<R0, R1, R2, false>), grid4, dim3(512), 0, s, io, ht,
-                           c.Hq, c.H, c.Wp, c.Wt, c.C, c.twf_y);
+                           c.Hq, c.H, c.Wp, c.Wt, c.CF, c.twf_y);
     };
     using std::integral_constant;
     switch (col_wave4_m(c)) {
@@ -1471,9 +1395,6 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
       case 384: go(integral_constant<int, 6>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
       default: go(integral_constant<int, 4>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
     }
-  } else if (c.Hp == 4320 && c.H <= 2160 && c.Wp % 8 == 0) {
-    hipLaunchKernelGGL((k_col_both<2160, 512>), dim3(2 * c.Wt, c.C), dim3(512), 0, s, io, c.H,
-                       c.Wp, c.Wt, c.twf_m, c.tw_y, c.Wq, conj_h, scale);
   } else if (c.Hp == 2160) {
     hipLaunchKernelGGL((k_col_half_c<1080, 1024>), grid, dim3(1024), 0, s, io, c.H, c.Wp, c.Wt,
                        c.twf_m, c.tw_y, c.Wq, conj_h, scale);
@@ -1495,13 +1416,20 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
   return hipGetLastError();
 }
 
-// loss = sum(loss_part) / M, psnr = 10 log10(1 / loss): one block, fixed order.
+// Per hologram b: loss = sum of its loss partials / M, psnr = 10 log10(1 / loss);
+// one block per hologram, fixed order.  The partials of plane l are
+// part[l * rows_per_plane + r]; hologram b owns r in [b span, (b + 1) span).
 __global__ __launch_bounds__(256) void k_loss_finalize(const double *__restrict__ part,
-                                                       int rows, double inv_m,
-                                                       double *__restrict__ out) {
+                                                       int planes, int rows_per_plane, int span,
+                                                       double inv_m, double *__restrict__ out,
+                                                       uint32_t *__restrict__ finite_flag) {
   __shared__ double red[256];
+  const int b = blockIdx.x;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < rows; i += 256) acc += part[i];
+  for (int l = 0; l < planes; ++l) {
+    const double *p = part + (size_t)l * rows_per_plane + (size_t)b * span;
+    for (int i = threadIdx.x; i < span; i += 256) acc += p[i];
+  }
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -1510,15 +1438,17 @@ __global__ __launch_bounds__(256) void k_loss_finalize(const double *__restrict_
   }
   if (threadIdx.x == 0) {
     const double loss = red[0] * inv_m;
-    out[0] = loss;
-    out[1] = 10.0 * log10(1.0 / loss);
+    out[2 * b] = loss;
+    out[2 * b + 1] = 10.0 * log10(1.0 / loss);
+    if (finite_flag && !isfinite(loss)) atomicOr(finite_flag, kNonFiniteLoss);
   }
 }
 
 hipError_t launch_loss_finalize(const Ctx &c, double *loss, hipStream_t s) {
   const double inv_m = 1.0 / ((double)c.L * c.C * c.H * c.W);
-  hipLaunchKernelGGL(k_loss_finalize, dim3(1), dim3(256), 0, s, c.loss_part,
-                     c.L * row_blocks(c), inv_m, loss);
+  const int rows = row_blocks(c);
+  hipLaunchKernelGGL(k_loss_finalize, dim3(c.B), dim3(256), 0, s, c.loss_part, c.L, rows,
+                     rows / c.B, inv_m, loss, c.finite_flag);
   return hipGetLastError();
 }
 

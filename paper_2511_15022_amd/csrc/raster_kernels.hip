@@ -7,15 +7,21 @@
 //                      pairs in Gaussian order -> stable LSD radix sort on the
 //                      tile id -> [start, end) per tile.  Deterministic: each
 //                      tile lists its Gaussians in increasing index.
-//   forward            one 16x16 tile per workgroup, one 8x8 sub-block per
-//                      wavefront; Gaussian records staged in LDS, culled per
-//                      sub-block with a ballot, summed per pixel in FP32
+//   forward            one tile (16x16, 32x8, 16x8 or 8x8 pixels) per
+//                      workgroup, one 8x8 sub-block per wavefront; Gaussians
+//                      culled per sub-block with a ballot, summed per pixel in
+//                      FP32 in list order (the same order for every tile shape)
 //   adjoint            per tile, the tile's dL/dU0 staged in LDS; one lane per
 //                      (tile, Gaussian) pair walks the pair's pixels and keeps
 //                      its 2C + 5 partial sums in registers (no per-pixel
 //                      storage, no atomics); the per-pair partials are summed in
 //                      a fixed order per Gaussian by the FP64 preprocess adjoint
+// A context may hold B holograms of one size: Gaussian g belongs to hologram
+// g / n (its parameters are that hologram's block of the [B][n (6 + 2C)]
+// array), and tile t to hologram t / tiles_per, so one launch of each kernel
+// covers all of them.
 #include <cmath>
+#include <type_traits>
 
 #include "cgh_internal.h"
 
@@ -60,19 +66,53 @@ __device__ __forceinline__ Geom geometry(const float *__restrict__ params, int n
   return q;
 }
 
+// true if the 6 + 2C parameters of Gaussian g (of n) are all finite
 template <int C>
-__global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ params, int n,
-                                                    int W, int H, float k, int tiles_x,
-                                                    float *__restrict__ rec,
+__device__ __forceinline__ bool params_finite(const float *__restrict__ params, int n, int g) {
+  bool ok = isfinite(params[2 * g]) && isfinite(params[2 * g + 1]) &&
+            isfinite(params[2 * (size_t)n + 2 * g]) &&
+            isfinite(params[2 * (size_t)n + 2 * g + 1]) && isfinite(params[4 * (size_t)n + g]) &&
+            isfinite(params[(size_t)(5 + 2 * C) * n + g]);
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+    ok = ok && isfinite(params[5 * (size_t)n + (size_t)g * C + c]) &&
+         isfinite(params[(size_t)(5 + C) * n + (size_t)g * C + c]);
+  return ok;
+}
+
+// Gaussian g of all B n: hologram b = g / n, index gl within it, and the base
+// of that hologram's parameter (or gradient) block
+struct GaussIdx {
+  int b, gl;
+  size_t base;
+};
+template <int C>
+__device__ __forceinline__ GaussIdx gauss_idx(int g, int n) {
+  GaussIdx r;
+  r.b = g / n;
+  r.gl = g - r.b * n;
+  r.base = (size_t)r.b * n * (6 + 2 * C);
+  return r;
+}
+
+// tile shape: (1 << tlx) x (1 << tly) pixels
+template <int C>
+__global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ params_all, int n,
+                                                    int total, int W, int H, float k, int tlx,
+                                                    int tly, float *__restrict__ rec,
                                                     uint2 *__restrict__ rect,
                                                     uint32_t *__restrict__ counts, float thr,
-                                                    float2 *__restrict__ alim) {
+                                                    float2 *__restrict__ alim,
+                                                    uint32_t *__restrict__ finite_flag) {
   constexpr int RS = rec_stride_c(C);
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const Geom q = geometry(params, n, C, g, W, H);
-  const float *amp = params + 5 * (size_t)n;
-  const float *ph = params + (size_t)(5 + C) * n;
+  if (g >= total) return;
+  const GaussIdx gi = gauss_idx<C>(g, n);
+  const float *params = params_all + gi.base;
+  if (finite_flag && !params_finite<C>(params, n, gi.gl)) atomicOr(finite_flag, kNonFiniteParams);
+  const Geom q = geometry(params, n, C, gi.gl, W, H);
+  const float *amp = params + 5 * (size_t)n + (size_t)gi.gl * C;
+  const float *ph = params + (size_t)(5 + C) * n + (size_t)gi.gl * C;
   float r[RS];
 #pragma unroll
   for (int i = 0; i < RS; ++i) r[i] = 0.f;
@@ -87,8 +127,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ pa
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     double s, co;
-    sincos((double)ph[(size_t)g * C + c], &s, &co);
-    const double a = q.alpha * (double)amp[(size_t)g * C + c];
+    sincos((double)ph[c], &s, &co);
+    const double a = q.alpha * (double)amp[c];
     r[R_AMP + 2 * c] = (float)(a * co);
     r[R_AMP + 2 * c + 1] = (float)(a * s);
   }
@@ -111,8 +151,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ pa
     i0 = 0; i1 = W - 1; j0 = 0; j1 = H - 1;
   }
   if (i0 <= i1 && j0 <= j1) {
-    const uint32_t tx0 = (uint32_t)i0 / kTile, tx1 = (uint32_t)i1 / kTile;
-    const uint32_t ty0 = (uint32_t)j0 / kTile, ty1 = (uint32_t)j1 / kTile;
+    const uint32_t tx0 = (uint32_t)i0 >> tlx, tx1 = (uint32_t)i1 >> tlx;
+    const uint32_t ty0 = (uint32_t)j0 >> tly, ty1 = (uint32_t)j1 >> tly;
     cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
     rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
   }
@@ -128,7 +168,6 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ pa
     const double lo = log2(1.0 / (255.0 * q.alpha)), hi = log2(0.99 / q.alpha);
     alim[g] = make_float2(fmaxf(thr, (float)lo), (float)hi);
   }
-  (void)tiles_x;
 }
 
 static float support_threshold(float k) {
@@ -137,16 +176,28 @@ static float support_threshold(float k) {
   return (float)(-0.5 * (double)k * (double)k * kLog2e);
 }
 
+static int log2i(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
 hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  dim3 grid((n + 255) / 256), block(256);
+  const int total = (int)total_gaussians(c, n);
+  if (total <= 0) return hipSuccess;
+  dim3 grid((total + 255) / 256), block(256);
   const float k = c.cfg.support_sigma, thr = support_threshold(k);
+  const int tlx = log2i(c.tile_w), tly = log2i(c.tile_h);
+#define CGH_PRE(CC)                                                                           \
+  hipLaunchKernelGGL(k_preprocess<CC>, grid, block, 0, s, params, n, total, c.W, c.H, k, tlx, \
+                     tly, c.rec, c.rect, c.counts, thr, c.alim, c.finite_flag)
   switch (c.C) {
-    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts, thr, c.alim); break;
-    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts, thr, c.alim); break;
-    case 3: hipLaunchKernelGGL(k_preprocess<3>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts, thr, c.alim); break;
-    default: hipLaunchKernelGGL(k_preprocess<4>, grid, block, 0, s, params, n, c.W, c.H, k, c.tiles_x, c.rec, c.rect, c.counts, thr, c.alim); break;
+    case 1: CGH_PRE(1); break;
+    case 2: CGH_PRE(2); break;
+    case 3: CGH_PRE(3); break;
+    default: CGH_PRE(4); break;
   }
+#undef CGH_PRE
   return hipGetLastError();
 }
 
@@ -246,11 +297,14 @@ static hipError_t scan_u32(const uint32_t *in, uint32_t *out, int len, uint32_t 
 // Binning: emit (tile, gaussian) pairs, stable radix sort, tile ranges.
 // ----------------------------------------------------------------------------
 // Pairs of Gaussian g go to [offset(g), offset(g) + count(g)) in row-major
-// tile order.  offsets[] holds per-chunk exclusive scans and chunk_sums the
-// (unscanned) chunk totals: each workgroup adds the totals of the chunks before
-// its own, and workgroup 0 writes the grand total to offsets[n] and to the
-// pair total status[1]; the final offset is written back for the adjoint.
-__global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict__ counts,
+// tile order; the key of tile (tx, ty) of hologram b = g / n_per is
+// b tiles_per + ty tiles_x + tx.  offsets[] holds per-chunk exclusive scans and
+// chunk_sums the (unscanned) chunk totals: each workgroup adds the totals of
+// the chunks before its own, and workgroup 0 writes the grand total to
+// offsets[n] and to the pair total status[1]; the final offset is written
+// back for the adjoint.
+__global__ __launch_bounds__(256) void k_emit(int n, int n_per, int tiles_per,
+                                              const uint32_t *__restrict__ counts,
                                               uint32_t *__restrict__ offsets,
                                               const uint32_t *__restrict__ chunk_sums,
                                               int nchunks, const uint2 *__restrict__ rect,
@@ -278,6 +332,7 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
   const uint64_t off = off32;
   const uint2 rc = rect[g];
   const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
+  const uint32_t kb = (uint32_t)(g / n_per) * (uint32_t)tiles_per;
   uint32_t tx = tx0, ty = ty0;
   for (uint32_t t = 0; t < cnt; ++t) {
     const uint64_t pos = off + t;
@@ -286,7 +341,7 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t *__restrict_
       atomicOr(&status[2], 1u);  // sticky until the next status read
       break;
     }
-    keys[pos] = ty * (uint32_t)tiles_x + tx;
+    keys[pos] = kb + ty * (uint32_t)tiles_x + tx;
     vals[pos] = (uint32_t)g;
     if (++tx > tx1) { tx = tx0; ++ty; }
   }
@@ -450,8 +505,8 @@ __global__ void k_zero_record(float *rec, int slot, int rs, float2 *alim) {
 }
 
 hipError_t launch_zero_record(const Ctx &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_record, dim3(1), dim3(64), 0, s, c.rec, c.cfg.max_gaussians,
-                     c.rec_stride, c.alim);
+  hipLaunchKernelGGL(k_zero_record, dim3(1), dim3(64), 0, s, c.rec,
+                     (int)total_gaussians(c, c.cfg.max_gaussians), c.rec_stride, c.alim);
   return hipGetLastError();
 }
 
@@ -471,13 +526,14 @@ hipError_t launch_zero_status(const Ctx &c, hipStream_t s) {
 hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
   // status[0] (overflow) and status[1] (pair total) restart: the first scan
   // kernel clears the flag and the emit kernel writes the total
-  if (n > 0) {
-    const int nb = (n + kScanItems - 1) / kScanItems;
-    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, c.counts, c.offsets, n,
+  const int total = (int)total_gaussians(c, n);
+  if (total > 0) {
+    const int nb = (total + kScanItems - 1) / kScanItems;
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, c.counts, c.offsets, total,
                        c.scan_tmp, c.status);
-    hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, s, n, c.counts, c.offsets,
-                       c.scan_tmp, nb, c.rect, c.tiles_x, c.pair_cap, c.keys[0], c.vals[0],
-                       c.status);
+    hipLaunchKernelGGL(k_emit, dim3((total + 255) / 256), dim3(256), 0, s, total, n, c.tiles_per,
+                       c.counts, c.offsets, c.scan_tmp, nb, c.rect, c.tiles_x, c.pair_cap,
+                       c.keys[0], c.vals[0], c.status);
   } else {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c.status, 2);
   }
@@ -545,23 +601,24 @@ __device__ __forceinline__ void accumulate(const float *r, float offx, float off
   }
 }
 
-// zero_id: index of an all-zero record (after the last Gaussian slot)
-template <int C, bool CLAMP, bool PA>
-__global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ rec,
-                                                    const uint32_t *__restrict__ vals,
-                                                    const uint2 *__restrict__ ranges, int W,
-                                                    int H, int tiles_x, float thr,
-                                                    uint32_t zero_id,
-                                                    const float2 *__restrict__ alim,
-                                                    float2 *__restrict__ field) {
+// zero_id: index of an all-zero record (after the last Gaussian slot).
+// The tile is SBX x SBY sub-blocks of 8 x 8 pixels, one wave each.
+template <int C, bool CLAMP, bool PA, int SBX, int SBY>
+__global__ __launch_bounds__(64 * SBX * SBY) void k_raster_fwd(
+    const float *__restrict__ rec, const uint32_t *__restrict__ vals,
+    const uint2 *__restrict__ ranges, int W, int H, int tiles_x, int tiles_per, float thr,
+    uint32_t zero_id, const float2 *__restrict__ alim, float2 *__restrict__ field_all) {
   constexpr int RS = rec_stride_c(C);
+  constexpr int NW = SBX * SBY;
   // (Gaussian id, origin offset x, origin offset y) of the surviving Gaussians
-  __shared__ uint4 list[4][kBatch + 2];
+  __shared__ uint4 list[NW][kBatch + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tile = blockIdx.x;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int Xt = tx * kTile, Yt = ty * kTile;  // tile origin
-  const int sx = (wave & 1) * 8, sy = (wave >> 1) * 8;  // sub-block origin in the tile
+  const int hb = tile / tiles_per, ltile = tile - hb * tiles_per;  // hologram, its tile
+  float2 *field = field_all + (size_t)hb * C * H * W;
+  const int tx = ltile % tiles_x, ty = ltile / tiles_x;
+  const int Xt = tx * (8 * SBX), Yt = ty * (8 * SBY);  // tile origin
+  const int sx = (wave % SBX) * 8, sy = (wave / SBX) * 8;  // sub-block origin in the tile
   const int X0 = Xt + sx, Y0 = Yt + sy;
   const int lx = lane & 7, ly = lane >> 3;
   // pixel offsets from the tile origin: d = (x - Xt) + ((Xt - floor(mean)) - frac(mean)),
@@ -666,29 +723,48 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float *__restrict__ re
   }
 }
 
+// calls f(integral_constant<TW>, integral_constant<TH>) for the context's tile
+template <class F>
+static void with_tile(const Ctx &c, F &&f) {
+  using std::integral_constant;
+  if (c.tile_w == 32 && c.tile_h == 8) f(integral_constant<int, 32>{}, integral_constant<int, 8>{});
+  else if (c.tile_w == 16 && c.tile_h == 8) f(integral_constant<int, 16>{}, integral_constant<int, 8>{});
+  else if (c.tile_w == 8 && c.tile_h == 8) f(integral_constant<int, 8>{}, integral_constant<int, 8>{});
+  else f(integral_constant<int, 16>{}, integral_constant<int, 16>{});
+}
+
+template <class F>
+static void with_channels(int C, F &&f) {
+  using std::integral_constant;
+  switch (C) {
+    case 1: f(integral_constant<int, 1>{}); break;
+    case 2: f(integral_constant<int, 2>{}); break;
+    case 3: f(integral_constant<int, 3>{}); break;
+    default: f(integral_constant<int, 4>{}); break;
+  }
+}
+
 hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
   const float thr = support_threshold(c.cfg.support_sigma);
-  const uint32_t zid = (uint32_t)c.cfg.max_gaussians;  // the zero record
+  // the zero record, after the last Gaussian slot of every hologram
+  const uint32_t zid = (uint32_t)((int64_t)c.B * c.cfg.max_gaussians);
   const uint32_t *vals = c.vals[c.sorted];
-  dim3 grid(c.num_tiles), block(256);
   const bool clamp = !(thr > kPowerFloor2);
   const bool pa = c.alim != nullptr;  // the clamp of the exponent never binds there
-#define CGH_FWD(CC, CL)                                                                      \
-  do {                                                                                       \
-    if (pa)                                                                                  \
-      hipLaunchKernelGGL((k_raster_fwd<CC, false, true>), grid, block, 0, s, c.rec, vals,    \
-                         c.ranges, c.W, c.H, c.tiles_x, thr, zid, c.alim, field);            \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_raster_fwd<CC, CL, false>), grid, block, 0, s, c.rec, vals,      \
-                         c.ranges, c.W, c.H, c.tiles_x, thr, zid, c.alim, field);            \
-  } while (0)
-  switch (c.C) {
-    case 1: if (clamp) CGH_FWD(1, true); else CGH_FWD(1, false); break;
-    case 2: if (clamp) CGH_FWD(2, true); else CGH_FWD(2, false); break;
-    case 3: if (clamp) CGH_FWD(3, true); else CGH_FWD(3, false); break;
-    default: if (clamp) CGH_FWD(4, true); else CGH_FWD(4, false); break;
-  }
-#undef CGH_FWD
+  with_tile(c, [&](auto tw, auto th) {
+    constexpr int SBX = decltype(tw)::value / 8, SBY = decltype(th)::value / 8;
+    with_channels(c.C, [&](auto cc) {
+      constexpr int CC = decltype(cc)::value;
+      dim3 grid(c.num_tiles), block(64 * SBX * SBY);
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x,
+                           c.tiles_per, thr, zid, c.alim, field);
+      };
+      if (pa) go(k_raster_fwd<CC, false, true, SBX, SBY>);
+      else if (clamp) go(k_raster_fwd<CC, true, false, SBX, SBY>);
+      else go(k_raster_fwd<CC, false, false, SBX, SBY>);
+    });
+  });
   return hipGetLastError();
 }
 
@@ -733,44 +809,48 @@ template <int C, bool PA> struct AdjQ {
 // Pair partials: dP_c, dQ_c (2C), sum w d (2), sum w d d^T (3); with PA one more,
 // the sum of G gp over the pixels where the 0.99 clamp is active (their
 // weight does not depend on alpha), in the slot that the stride leaves spare.
-template <int C, bool CLAMP, bool PA>
+template <int C, bool CLAMP, bool PA, int TW, int TH>
 __global__ __launch_bounds__(64) void k_raster_adj(
     const float *__restrict__ rec, const uint32_t *__restrict__ vals,
     const uint2 *__restrict__ ranges, const uint2 *__restrict__ rect,
-    const uint32_t *__restrict__ offsets, int W, int H, int tiles_x, float thr,
-    const float2 *__restrict__ alim, const float2 *__restrict__ gfield, int64_t cap,
+    const uint32_t *__restrict__ offsets, int W, int H, int tiles_x, int tiles_per, float thr,
+    const float2 *__restrict__ alim, const float2 *__restrict__ gfield_all, int64_t cap,
     float *__restrict__ partials) {
   constexpr int RS = rec_stride_c(C);
   constexpr int PS = part_stride_c(C);
   constexpr int NS = 2 * C + 5 + (PA ? 1 : 0);
   static_assert(NS <= PS, "the clamped-pixel sum needs a spare partial slot");
   using Q = AdjQ<C, PA>;
-  // dL/dU0 of the tile, plus one row of zeros (row kTile) that the padding
+  constexpr int TP = TW * TH;  // pixels of the tile
+  static_assert(TP % 64 == 0 && TW * C <= 64 * 4, "tile shape");
+  // dL/dU0 of the tile, plus one row of zeros (row TH) that the padding
   // pixels of a pair's last segment read when they run past the tile's last row
-  __shared__ float2 sg[(kTile + 1) * kTile][C];
+  __shared__ float2 sg[(TH + 1) * TW][C];
   __shared__ float4 sq4[kAdjBatch * Q::N / 4];
   float *sq = reinterpret_cast<float *>(sq4);
   const int lane = threadIdx.x;
   const int tile = blockIdx.x;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int X0 = tx * kTile, Y0 = ty * kTile;
+  const int hb = tile / tiles_per, ltile = tile - hb * tiles_per;  // hologram, its tile
+  const float2 *gfield = gfield_all + (size_t)hb * C * H * W;
+  const int tx = ltile % tiles_x, ty = ltile / tiles_x;
+  const int X0 = tx * TW, Y0 = ty * TH;
   {
-    // all C * 4 loads of a lane are issued before the first is stored
-    constexpr int K = C * kTile * kTile / 64;
+    // all C TP / 64 loads of a lane are issued before the first is stored
+    constexpr int K = C * TP / 64;
     float2 v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int i = lane + 64 * k, c = i / (kTile * kTile), p = i % (kTile * kTile);
-      const int x = X0 + (p % kTile), y = Y0 + (p / kTile);
+      const int i = lane + 64 * k, c = i / TP, p = i % TP;
+      const int x = X0 + (p % TW), y = Y0 + (p / TW);
       v[k] = gfield[((size_t)c * H + min(y, H - 1)) * W + min(x, W - 1)];
       if (x >= W || y >= H) v[k] = make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = lane + 64 * k;
-      sg[i % (kTile * kTile)][i / (kTile * kTile)] = v[k];
+      sg[i % TP][i / TP] = v[k];
     }
-    if (lane < kTile * C) sg[kTile * kTile + lane / C][lane % C] = make_float2(0.f, 0.f);
+    for (int i = lane; i < TW * C; i += 64) sg[TP + i / C][i % C] = make_float2(0.f, 0.f);
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint2 rg = ranges[tile];
@@ -792,13 +872,13 @@ __global__ __launch_bounds__(64) void k_raster_adj(
         r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
       }
       const int mix = __float_as_int(r[R_MIX]), miy = __float_as_int(r[R_MIY]);
-      // pixel box of the support inside this tile (local coordinates 0..15)
+      // pixel box of the support inside this tile (local coordinates)
       const float rx = fminf(r[R_RX], 1e6f) + 0.01f, ry = fminf(r[R_RY], 1e6f) + 0.01f;
       const float cx = (float)(mix - X0) + r[R_MFX], cy = (float)(miy - Y0) + r[R_MFY];
       xa = max(0, (int)ceilf(fmaxf(cx - rx, -1.f)));
-      xb = min(kTile - 1, (int)floorf(fminf(cx + rx, (float)kTile)));
+      xb = min(TW - 1, (int)floorf(fminf(cx + rx, (float)TW)));
       ya = max(0, (int)ceilf(fmaxf(cy - ry, -1.f)));
-      yb = min(kTile - 1, (int)floorf(fminf(cy + ry, (float)kTile)));
+      yb = min(TH - 1, (int)floorf(fminf(cy + ry, (float)TH)));
       if (xb >= xa && yb >= ya) area = (xb - xa + 1) * (yb - ya + 1);
       const uint2 rc = rect[g];
       const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
@@ -925,7 +1005,7 @@ __global__ __launch_bounds__(64) void k_raster_adj(
                             : 0.f;
             // 24-bit multiply (full rate) for the LDS offset
             const float2 *gv =
-                &sg[0][0] + __umul24((unsigned)(min(ly, kTile) * kTile + lx), (unsigned)C);
+                &sg[0][0] + __umul24((unsigned)(min(ly, TH) * TW + lx), (unsigned)C);
             float gp = 0.f;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -1003,21 +1083,28 @@ __global__ __launch_bounds__(64) void k_raster_adj(
 // ----------------------------------------------------------------------------
 template <int C, bool PA>
 __global__ __launch_bounds__(256) void k_preprocess_adj(
-    const float *__restrict__ params, int n, int W, int H,
+    const float *__restrict__ params_all, int n, int total, int W, int H,
     const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets, int64_t cap,
-    const float *__restrict__ partials, float *__restrict__ grads) {
+    const float *__restrict__ partials, float *__restrict__ grads_all,
+    uint32_t *__restrict__ finite_flag) {
   constexpr int PS = part_stride_c(C);
   // the 2C + 5 partial sums, plus the clamped-pixel sum with CGH_PAPER_ALPHA
   constexpr int NP = 2 * C + 5 + (PA ? 1 : 0);
   static_assert(NP <= PS, "spare partial slot");
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
+  const int gg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gg >= total) return;
+  // partial slots are indexed by the Gaussian's index among all B n; its
+  // parameters and gradients by its index g in its hologram's block
+  const GaussIdx gi = gauss_idx<C>(gg, n);
+  const float *params = params_all + gi.base;
+  float *grads = grads_all + gi.base;
+  const int g = gi.gl;
   double S[NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) S[k] = 0.0;
   const Geom q = geometry(params, n, C, g, W, H);
-  const uint64_t off = offsets[g];
-  uint64_t end = off + counts[g];
+  const uint64_t off = offsets[gg];
+  uint64_t end = off + counts[gg];
   if ((int64_t)end > cap) end = (uint64_t)cap;
   // pair partials in slot order, four slots' loads in flight at a time
   constexpr int U = 4;
@@ -1098,50 +1185,46 @@ __global__ __launch_bounds__(256) void k_preprocess_adj(
   g_ls[2 * g] = (float)(dsx * (sx - 0.1));      // d s / d s~ = exp(s~)
   g_ls[2 * g + 1] = (float)(dsy * (sy - 0.1));
   g_rot[g] = (float)dth;
+  if (finite_flag && !params_finite<C>(grads, n, g)) atomicOr(finite_flag, kNonFiniteGrads);
 }
 
 hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStream_t s) {
   const float thr = support_threshold(c.cfg.support_sigma);
   const uint32_t *vals = c.vals[c.sorted];
-  dim3 grid(c.num_tiles), block(64);
   const bool clamp = !(thr > kPowerFloor2);
   const bool pa = c.alim != nullptr;
-#define CGH_ADJ(CC, CL)                                                                       \
-  do {                                                                                        \
-    if (pa)                                                                                   \
-      hipLaunchKernelGGL((k_raster_adj<CC, false, true>), grid, block, 0, s, c.rec, vals,     \
-                         c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, c.alim,       \
-                         grad_field, c.pair_cap, c.partials);                                 \
-    else                                                                                      \
-      hipLaunchKernelGGL((k_raster_adj<CC, CL, false>), grid, block, 0, s, c.rec, vals,       \
-                         c.ranges, c.rect, c.offsets, c.W, c.H, c.tiles_x, thr, c.alim,       \
-                         grad_field, c.pair_cap, c.partials);                                 \
-  } while (0)
-  switch (c.C) {
-    case 1: if (clamp) CGH_ADJ(1, true); else CGH_ADJ(1, false); break;
-    case 2: if (clamp) CGH_ADJ(2, true); else CGH_ADJ(2, false); break;
-    case 3: if (clamp) CGH_ADJ(3, true); else CGH_ADJ(3, false); break;
-    default: if (clamp) CGH_ADJ(4, true); else CGH_ADJ(4, false); break;
-  }
-#undef CGH_ADJ
+  with_tile(c, [&](auto tw, auto th) {
+    constexpr int TW = decltype(tw)::value, TH = decltype(th)::value;
+    with_channels(c.C, [&](auto cc) {
+      constexpr int CC = decltype(cc)::value;
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(c.num_tiles), dim3(64), 0, s, c.rec, vals, c.ranges,
+                           c.rect, c.offsets, c.W, c.H, c.tiles_x, c.tiles_per, thr, c.alim,
+                           grad_field, c.pair_cap, c.partials);
+      };
+      if (pa) go(k_raster_adj<CC, false, true, TW, TH>);
+      else if (clamp) go(k_raster_adj<CC, true, false, TW, TH>);
+      else go(k_raster_adj<CC, false, false, TW, TH>);
+    });
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_preprocess_adjoint(const Ctx &c, const float *params, int n, float *grads,
                                      hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  dim3 g2((n + 255) / 256), block(256);
+  const int total = (int)total_gaussians(c, n);
+  if (total <= 0) return hipSuccess;
+  dim3 g2((total + 255) / 256), block(256);
   const bool pa = c.alim != nullptr;
-#define CGH_PADJ(CC, PA)                                                                  \
-  hipLaunchKernelGGL((k_preprocess_adj<CC, PA>), g2, block, 0, s, params, n, c.W, c.H,    \
-                     c.counts, c.offsets, c.pair_cap, c.partials, grads)
-  switch (c.C) {
-    case 1: if (pa) CGH_PADJ(1, true); else CGH_PADJ(1, false); break;
-    case 2: if (pa) CGH_PADJ(2, true); else CGH_PADJ(2, false); break;
-    case 3: if (pa) CGH_PADJ(3, true); else CGH_PADJ(3, false); break;
-    default: if (pa) CGH_PADJ(4, true); else CGH_PADJ(4, false); break;
-  }
-#undef CGH_PADJ
+  with_channels(c.C, [&](auto cc) {
+    constexpr int CC = decltype(cc)::value;
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, g2, block, 0, s, params, n, total, c.W, c.H, c.counts, c.offsets,
+                         c.pair_cap, c.partials, grads, c.finite_flag);
+    };
+    if (pa) go(k_preprocess_adj<CC, true>);
+    else go(k_preprocess_adj<CC, false>);
+  });
   return hipGetLastError();
 }
 

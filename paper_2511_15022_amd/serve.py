@@ -21,6 +21,17 @@ A solve is a fixed number of Adam steps of L_MSE (Alg. 1).
 * ``autotune`` times the batch at each candidate stream count and keeps the
   fastest.
 
+``BatchServer`` instead solves all requests of a size class together: one
+batched context (cgh_config.batch = B) holds B holograms of the class, each
+with its own Gaussians, target, wavelength and distance, so every kernel of
+a step covers the whole class in one launch (the hologram index is part of
+the grid) and small classes fill the chip.  A class with more than
+``max_batch`` requests is cut into batches.  ``tune_tiles`` chooses the
+rasterizer tile shape of each class by timing a short captured solve of the
+class batch at every supported shape; ``autotune_batched`` then picks the
+stream count.  Results equal the single-hologram solves bit for bit (the
+same kernels over the same tile lists; tested).
+
 All device work is the library's kernels; this module only owns buffers,
 streams and the order of the calls.
 """
@@ -248,3 +259,210 @@ def solve_eager(ctx, params, n, target, steps, lr=1e-3):
         ctx.backward(params, n, field, target, loss=log[t - 1], grads=grads)
         binding.step(params, grads, m, v, t, lr)
     return log
+
+
+# ---------------------------------------------------------------------------
+# Batched serving: one context and one graph launch per batch of a size class
+# ---------------------------------------------------------------------------
+class BatchSlot:
+    """A batched context of B holograms of one class on one stream, with its
+    captured solve; ``enqueue`` loads up to B requests and launches it."""
+
+    def __init__(self, H, W, n, B, steps, lr, stream, pitch, device, tile):
+        self.H, self.W, self.n, self.B, self.tile = H, W, n, B, tile
+        self.stream = stream
+        self.per = binding.param_count(n, 1)
+        self.ctx = binding.Context(H, W, 1, pitch, [WAVELENGTHS[1]], [5e-3], max_gaussians=n,
+                                   batch=B, tile=tile, device=device)
+        self.params = torch.zeros(B * self.per, dtype=torch.float32, device=device)
+        self.target = torch.zeros((1, B, 1, H, W), dtype=torch.float32, device=device)
+        self.solve = binding.Solve(self.ctx, self.params, n, self.target, steps, lr=lr,
+                                   stream=stream)
+
+    def enqueue(self, reqs):
+        """Everything for one batch of requests on this slot's stream (no host
+        wait).  Fewer than B requests leave the other holograms' inputs as
+        they were; their results are not read."""
+        s = self.stream
+        with torch.cuda.stream(s):
+            for b, r in enumerate(reqs):
+                self.params[b * self.per:(b + 1) * self.per].copy_(r.params, non_blocking=True)
+                self.target[0, b, 0].copy_(r.target.view(self.H, self.W), non_blocking=True)
+                self.ctx.set_hologram_optics(b, [r.wavelength], [r.z], stream=s)
+            self.solve.launch(s)
+            for b, r in enumerate(reqs):
+                r.out_params.copy_(self.params[b * self.per:(b + 1) * self.per],
+                                   non_blocking=True)
+                r.out_loss.copy_(self.solve.loss_log[:, b], non_blocking=True)
+
+
+def batches_of(requests, max_batch):
+    """Requests grouped by size class (in order of first appearance), each
+    class cut into batches of at most ``max_batch`` (in request order)."""
+    classes = {}
+    for r in requests:
+        classes.setdefault((r.H, r.W), []).append(r)
+    out = []
+    for key, rs in classes.items():
+        for i in range(0, len(rs), max_batch):
+            out.append(rs[i:i + max_batch])
+    return out
+
+
+class BatchServer:
+    """Serves a batch of requests as one batched solve per size-class batch,
+    the batches spread over up to ``max_streams`` streams (longest first)."""
+
+    def __init__(self, steps, lr=1e-3, max_streams=2, max_batch=binding.MAX_BATCH, pitch=PITCH,
+                 device="cuda"):
+        self.steps, self.lr, self.pitch, self.device = steps, lr, pitch, device
+        self.max_batch = max_batch
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(max_streams)]
+        self.slots = {}
+        self.tiles = {}        # (H, W) -> tile shape (width, height)
+        self.batch_ms = {}     # (H, W, B) -> measured solve time of a batch, ms
+
+    def tile_of(self, H, W):
+        return self.tiles.get((H, W), (16, 16))
+
+    def slot(self, si, H, W, n, B):
+        tile = self.tile_of(H, W)
+        key = (si, H, W, B, tile)
+        if key not in self.slots:
+            self.slots[key] = BatchSlot(H, W, n, B, self.steps, self.lr, self.streams[si],
+                                        self.pitch, self.device, tile)
+        s = self.slots[key]
+        if s.n != n:
+            raise ValueError(f"class {H}x{W} holds n = {s.n}, request has n = {n}")
+        return s
+
+    def cost(self, batch):
+        r = batch[0]
+        return self.batch_ms.get((r.H, r.W, len(batch)), float(r.pixels * len(batch)))
+
+    def prepare(self, requests, streams):
+        for si, q in enumerate(plan_batches(batches_of(requests, self.max_batch), streams,
+                                            self.cost)):
+            for bt in q:
+                self.slot(si, bt[0].H, bt[0].W, bt[0].n, len(bt))
+        for r in requests:
+            if r.out_params is None:
+                r.out_params = torch.empty_like(r.params)
+                r.out_loss = torch.empty((self.steps, 2), dtype=torch.float64,
+                                         device=self.device)
+        torch.cuda.synchronize()
+
+    def run(self, requests, streams=None):
+        """Serves ``requests``; returns the batch wall time (s) and per request
+        the solve latency (its batch's span on its stream, ms) and turnaround
+        (from the batch start, ms), from HIP events."""
+        streams = len(self.streams) if streams is None else streams
+        queues = plan_batches(batches_of(requests, self.max_batch), streams, self.cost)
+        self.prepare(requests, streams)
+        main = torch.cuda.current_stream(self.device)
+        t0 = torch.cuda.Event(enable_timing=True)
+        marks, spans = {}, []
+        host0 = time.perf_counter()
+        t0.record(main)
+        for si in range(streams):
+            self.streams[si].wait_event(t0)
+        depth = max((len(q) for q in queues), default=0)
+        for k in range(depth):
+            for si, q in enumerate(queues):
+                if k >= len(q):
+                    continue
+                bt = q[k]
+                slot = self.slot(si, bt[0].H, bt[0].W, bt[0].n, len(bt))
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(slot.stream)
+                slot.enqueue(bt)
+                e1.record(slot.stream)
+                spans.append((bt, e0, e1))
+                for r in bt:
+                    marks[r.index] = (e0, e1, si)
+        for si in range(streams):
+            main.wait_stream(self.streams[si])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - host0
+        for slot in {self.slot(si, bt[0].H, bt[0].W, bt[0].n, len(bt))
+                     for si, q in enumerate(queues) for bt in q}:
+            slot.ctx.read_status()
+        for bt, e0, e1 in spans:
+            self.batch_ms[(bt[0].H, bt[0].W, len(bt))] = e0.elapsed_time(e1)
+        latency = {i: e0.elapsed_time(e1) for i, (e0, e1, _) in marks.items()}
+        turnaround = {i: t0.elapsed_time(e1) for i, (_, e1, _) in marks.items()}
+        return {"wall_s": wall, "latency_ms": latency, "turnaround_ms": turnaround,
+                "stream_of": {i: si for i, (_, _, si) in marks.items()},
+                "batches": [(bt[0].H, bt[0].W, len(bt)) for _, q in enumerate(queues)
+                            for bt in q]}
+
+    def tune_tiles(self, requests, probe_steps=20, tiles=binding.TILE_SHAPES):
+        """The project's tile-shape autotuner: for each size class, times a
+        ``probe_steps``-step captured solve of the class's first batch at every
+        tile shape (one warm-up launch, then one timed launch) and keeps the
+        fastest shape.  Returns {(H, W): {tile: ms}}."""
+        timings = {}
+        for bt in batches_of(requests, self.max_batch):
+            key = (bt[0].H, bt[0].W)
+            if key in timings:
+                continue
+            timings[key] = {}
+            for tile in tiles:
+                ctx = binding.Context(key[0], key[1], 1, self.pitch, [WAVELENGTHS[1]], [5e-3],
+                                      max_gaussians=bt[0].n, batch=len(bt), tile=tile,
+                                      device=self.device)
+                per = binding.param_count(bt[0].n, 1)
+                P = torch.cat([r.params for r in bt])
+                T = torch.stack([r.target.view(key) for r in bt]).view(1, len(bt), 1, *key)
+                for b, r in enumerate(bt):
+                    ctx.set_hologram_optics(b, [r.wavelength], [r.z])
+                stream = self.streams[0]
+                solve = binding.Solve(ctx, P.clone(), bt[0].n, T.contiguous(), probe_steps,
+                                      lr=self.lr, stream=stream)
+                solve.launch(stream)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                solve.launch(stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ctx.read_status()
+                timings[key][tile] = e0.elapsed_time(e1)
+                solve.close()
+                ctx.close()
+                del P, T, per
+            self.tiles[key] = min(timings[key], key=lambda t: (timings[key][t], t != (16, 16)))
+        torch.cuda.empty_cache()
+        return timings
+
+
+def plan_batches(batches, streams, cost):
+    """Longest-processing-time-first assignment of batches to stream queues
+    (as ``plan``), each queue then shortest first."""
+    load = [0.0] * streams
+    queues = [[] for _ in range(streams)]
+    order = sorted(range(len(batches)), key=lambda i: (-cost(batches[i]), i))
+    for i in order:
+        si = min(range(streams), key=lambda k: (load[k], k))
+        load[si] += cost(batches[i])
+        queues[si].append(batches[i])
+    for q in queues:
+        q.sort(key=lambda bt: (cost(bt), bt[0].index))
+    return queues
+
+
+def autotune_batched(server, requests, candidates=(1, 2), probe_steps=20):
+    """Tile shape per class (``BatchServer.tune_tiles``), then the stream
+    count: each candidate gets a warm-up run and a timed run.  Returns
+    (best stream count, {count: holograms/s}, {count: timed run}, tile timings)."""
+    tile_ms = server.tune_tiles(requests, probe_steps=probe_steps)
+    rates, runs = {}, {}
+    for k in candidates:
+        if k > len(server.streams):
+            continue
+        server.run(requests, streams=k)
+        runs[k] = server.run(requests, streams=k)
+        rates[k] = len(requests) / runs[k]["wall_s"]
+    best = max(rates, key=lambda k: (rates[k], -k))
+    return best, rates, runs, tile_ms

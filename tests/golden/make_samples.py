@@ -1,8 +1,9 @@
 """Writes the FP64 oracle's values at seeded samples of a full-size workload:
 the loss; the SLM field and dL/dU0 at 512 pixels that no (Gaussian, pixel)
 pair near the support boundary touches; and the parameter gradients of 1024
-Gaussians none of whose pairs lies near that boundary.  It calls only the
-oracle and the seeded input generators.
+Gaussians none of whose pairs lies near that boundary.  It also records how
+many pixels that band excludes, and how many Gaussians were examined to find
+the 1024.  It calls only the oracle and the seeded input generators.
   python tests/golden/make_samples.py            -> rgb_4k_3z_samples.npz
       the 4K three-depth workload (2160 x 3840 RGB, 1,658,880 Gaussians, padded
       4320 x 7680, pitch 3.74 um, z = 3, 5, 7 mm, focal masks, L_recon; about
@@ -64,9 +65,15 @@ def main(name="rgb_4k_3z"):
                              "opacity_pre")], axis=1)
     field = ref["field"].reshape(C, -1)[:, pix]
     gfield = ref["grad_field"].reshape(C, -1)[:, pix]
+    # how many pixels the band leaves out of the sampling (the parity tests
+    # bound their share)
     np.savez_compressed(os.path.join(HERE, f"{name}_samples.npz"), loss=np.float64(ref["loss"]),
-                        pixels=pix, field=field, grad_field=gfield, gaussians=gid, grads=grads)
-    print("loss", ref["loss"], "pixels", pix.size, "gaussians", gid.size)
+                        pixels=pix, field=field, grad_field=gfield, gaussians=gid, grads=grads,
+                        ambiguous_pixels=np.int64(amb.sum()), canvas_pixels=np.int64(H * W),
+                        gaussians_examined=np.int64(len(keep) and (np.flatnonzero(
+                            cand == keep[-1])[0] + 1)))
+    print("loss", ref["loss"], "pixels", pix.size, "gaussians", gid.size,
+          "ambiguous pixels", int(amb.sum()), "of", H * W)
 
 
 if __name__ == "__main__":

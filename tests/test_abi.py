@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     for name in (declared_functions() + declared_functions(NET_HEADER) +
                  declared_functions(POH_HEADER)):
         assert hasattr(L, name), name
-    assert L.cgh_abi_version() == 3
+    assert L.cgh_abi_version() == 4
 
 
 def cfg(**kw):
@@ -53,6 +53,8 @@ def cfg(**kw):
     c.max_pairs = kw.get("pairs", 0)
     c.flags = kw.get("flags", 0)
     c.aperture = kw.get("aperture", 0.0)
+    c.tile_w, c.tile_h = kw.get("tile", (0, 0))
+    c.batch = kw.get("B", 0)
     return c
 
 
@@ -113,16 +115,50 @@ def test_paper_alpha_flag_reserves_the_exponent_limits():
     (dict(Hp=514), 1),            # 514 = 2 * 257 does not factor into 2, 3, 5
     (dict(Hp=200), 1),            # smaller than H
     (dict(pitch=0.0), 1), (dict(lambdas=[-1.0]), 1), (dict(n=-1), 1),
-    (dict(flags=4), 1), (dict(pairs=-5), 1),
+    (dict(flags=8), 1), (dict(pairs=-5), 1),
     (dict(flags=1, H=10), 1), (dict(flags=1, W=10, Wp=20), 1),   # SSIM window is 11 x 11
     (dict(L=0), 1), (dict(zs=[1e-3] * 8, L=9), 1),   # 1 <= planes <= CGH_MAX_PLANES
     (dict(zs=[1e-3, float("nan")]), 1),
     (dict(aperture=-1.0), 1), (dict(aperture=float("inf")), 1),
+    (dict(tile=(16, 0)), 1), (dict(tile=(0, 8)), 1),             # both or neither
+    (dict(tile=(16, 32)), 5), (dict(tile=(64, 4)), 5), (dict(tile=(12, 12)), 5),
+    (dict(B=65), 1), (dict(B=-1), 1),
+    (dict(B=2, flags=1), 5),                                     # SSIM term: one hologram
 ])
 def test_invalid_configs_are_rejected(bad, status):
     st, _ = ws(cfg(**bad))
     assert st == status
     assert binding.lib().cgh_last_error()
+
+
+def test_check_finite_flag_reserves_nothing():
+    st0, base = ws(cfg())
+    st1, chk = ws(cfg(flags=binding.CGH_CHECK_FINITE))
+    assert st0 == st1 == 0 and chk == base
+
+
+def test_tile_shapes_and_batch_sizes():
+    """Every supported tile shape is accepted; 8 x 8 tiles double the default
+    pair capacity (16 n + 65536 pairs: keys and values twice, one partial
+    record each).  A batch of B holograms multiplies the per-hologram
+    buffers; only the twiddle tables are shared."""
+    sizes = {}
+    for t in binding.TILE_SHAPES:
+        st, sizes[t] = ws(cfg(tile=t))
+        assert st == 0, t
+    assert sizes[(16, 16)] == ws(cfg())[1]
+    # 8 x 8: 8 n more pairs (16 B of keys / values, 32 B of partials at C = 1),
+    # about 4x the tile ranges
+    extra = sizes[(8, 8)] - sizes[(16, 16)]
+    assert 8 * 4096 * 48 <= extra <= 8 * 4096 * 48 + 4 * 1024 * 8 + 64 * 1024
+    st1, one = ws(cfg(H=96, W=160, n=3000))
+    st4, four = ws(cfg(H=96, W=160, n=3000, B=4))
+    assert st1 == st4 == 0
+    # shared: the 65536 spare pairs (keys, values, partials: 48 B each at
+    # C = 1) and the twiddle tables; everything else is per hologram
+    shared = 65536 * 48
+    per = one - shared
+    assert 2.9 * per < four - one < 3 * per + 64 * 1024
 
 
 def test_null_arguments_are_rejected_without_device_work():
@@ -146,6 +182,10 @@ def test_null_arguments_are_rejected_without_device_work():
                               0.999, 1e-8, None, None) == 1
     assert L.cgh_solve_launch(None, None) == 1
     assert L.cgh_solve_destroy(None) == 0
+    assert L.cgh_rasterize_lists(None, None, 0, None) == 1
+    assert L.cgh_generation(None, None) == 1
+    assert L.cgh_set_hologram_optics(None, 0, ctypes.cast(lam, ctypes.c_void_p),
+                                     ctypes.cast(lam, ctypes.c_void_p), None) == 1
 
 
 def test_net_argument_checks_and_workspace_sizes():

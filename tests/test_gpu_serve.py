@@ -145,6 +145,34 @@ def test_server_matches_standalone_solves():
         assert torch.equal(r.out_params, f)
 
 
+def test_batch_server_matches_standalone_solves():
+    """Nine requests of three sizes served as batched solves (at most two
+    holograms per batch, so a class spans several batches and batch sizes),
+    after the tile-shape autotuner has chosen each class's tile: every result
+    equals the eager solve of that request alone on a context with its optics
+    and the chosen tile, bit for bit."""
+    sizes = ((40, 60), (48, 64), (32, 32))
+    reqs = serve.make_requests(9, seed=151, sizes=sizes)
+    steps, lr = 5, 1e-3
+    server = serve.BatchServer(steps, lr=lr, max_streams=2, max_batch=2)
+    timings = server.tune_tiles(reqs, probe_steps=3)
+    assert set(timings) == {(r.H, r.W) for r in reqs}
+    for key, t in timings.items():
+        say("tile timings", key, t, "chosen", server.tile_of(*key))
+        assert set(t) == set(binding.TILE_SHAPES) and server.tile_of(*key) in t
+    res = server.run(reqs, streams=2)
+    assert len(res["latency_ms"]) == 9
+    assert max(b for _, _, b in res["batches"]) == 2
+    for r in reqs:
+        ctx = binding.Context(r.H, r.W, 1, serve.PITCH, [r.wavelength], [r.z], max_gaussians=r.n,
+                              tile=server.tile_of(r.H, r.W))
+        P = r.params.clone()
+        log = _eager(ctx, P, r.n, r.target, steps, lr)
+        say("batched request", r.index, r.H, r.W)
+        assert torch.equal(r.out_params, P)
+        assert torch.equal(r.out_loss, log)
+
+
 @pytest.mark.parametrize("H,W", [(512, 512), (768, 1024)])
 def test_serving_sizes_forward_backward_match_oracle(O, H, W):
     """Full-size serving classes (pads 1024^2 and 1536 x 2048, the runtime

@@ -67,3 +67,20 @@ def test_requests_are_seeded_and_follow_the_recipe():
         assert any(np.array_equal(np.roll(base, (dy, dx), axis=(0, 1)), t)
                    for dy in range(r.H) for dx in range(r.W))
     assert len({r.wavelength for r in a}) > 1 and len({round(r.z, 6) for r in a}) == 12
+
+
+def test_batches_group_classes_and_respect_the_limit():
+    class R:
+        def __init__(self, i, H, W):
+            self.index, self.H, self.W = i, H, W
+    reqs = [R(i, *((8, 8) if i % 3 else (4, 4))) for i in range(10)]
+    bts = serve.batches_of(reqs, 3)
+    assert all(len(b) <= 3 for b in bts)
+    assert all(len({(r.H, r.W) for r in b}) == 1 for b in bts)
+    assert sorted(r.index for b in bts for r in b) == list(range(10))
+    # classes in order of first appearance, requests in order within a class
+    assert [r.index for r in bts[0]] == [0, 3, 6] and [r.index for r in bts[1]] == [9]
+    queues = serve.plan_batches(bts, 2, lambda b: float(len(b)))
+    assert sorted(id(b) for q in queues for b in q) == sorted(id(b) for b in bts)
+    loads = [sum(len(b) for b in q) for q in queues]
+    assert max(loads) - min(loads) <= 3
