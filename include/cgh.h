@@ -103,8 +103,8 @@ typedef struct {
                                  /* on the zero frequency); 0: none                       */
   int32_t tile_w, tile_h;        /* rasterizer tile in pixels: 16 x 16, 32 x 8, 16 x 8 or */
                                  /* 8 x 8 (0, 0: 16 x 16).  Results do not depend on it   */
-                                 /* beyond FP32 rounding of the adjoint's partial sums    */
-                                 /* (the forward is bitwise the same for every shape)     */
+                                 /* beyond FP32 rounding (pixel offsets are formed from   */
+                                 /* the tile origin; the adjoint's partial sums per tile) */
   int32_t batch;                 /* B: holograms of this size in the context, 1 .. 64     */
                                  /* (0: 1); wavelength_m and z_m give every hologram's    */
                                  /* optics at creation (cgh_set_hologram_optics changes   */

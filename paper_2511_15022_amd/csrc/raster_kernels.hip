@@ -10,7 +10,7 @@
 //   forward            one tile (16x16, 32x8, 16x8 or 8x8 pixels) per
 //                      workgroup, one 8x8 sub-block per wavefront; Gaussians
 //                      culled per sub-block with a ballot, summed per pixel in
-//                      FP32 in list order (the same order for every tile shape)
+//                      FP32 in list order
 //   adjoint            per tile, the tile's dL/dU0 staged in LDS; one lane per
 //                      (tile, Gaussian) pair walks the pair's pixels and keeps
 //                      its 2C + 5 partial sums in registers (no per-pixel

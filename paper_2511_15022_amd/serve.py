@@ -293,7 +293,7 @@ class BatchSlot:
             for b, r in enumerate(reqs):
                 r.out_params.copy_(self.params[b * self.per:(b + 1) * self.per],
                                    non_blocking=True)
-                r.out_loss.copy_(self.solve.loss_log[:, b], non_blocking=True)
+                r.out_loss.copy_(self.solve.loss_log.view(-1, self.B, 2)[:, b], non_blocking=True)
 
 
 def batches_of(requests, max_batch):

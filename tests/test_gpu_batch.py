@@ -2,11 +2,13 @@
 size in every launch), the non-finite check and the solve graph over a batch,
 all through the C ABI.
 
-* Tile shapes (16 x 16, 32 x 8, 16 x 8, 8 x 8): the forward sums each pixel's
-  Gaussians in the same order whatever the tile, so the field is bitwise the
-  same for every shape; each shape matches the FP64 oracle (field 1e-4,
-  gradients 1e-3 per group) and the shapes' gradients agree with each other
-  to FP32 rounding of the per-tile partial sums.
+* Tile shapes (16 x 16, 32 x 8, 16 x 8, 8 x 8): each shape matches the FP64
+  oracle (field 1e-4, gradients 1e-3 per group), and the shapes agree with
+  each other to FP32 rounding: the pixel offsets from a Gaussian's mean are
+  formed from the tile origin (as in the adjoint, so that forward and adjoint
+  take the same support decisions), which changes their last bits with the
+  tile shape; pixels of pairs within the rounding band of the support
+  boundary are left out of the field comparison.
 * Batches: hologram b of a batched context gives, bit for bit, what a single
   context with that hologram's parameters, target and optics gives (the same
   kernels over the same tile lists), and one hologram is checked against the
@@ -76,7 +78,9 @@ def test_tile_shapes_match_oracle_and_each_other(O, case):
         if base_field is None:
             base_field, base_grads = field, grads
         else:
-            assert torch.equal(field, base_field), tile
+            e = rel_l2(field.cpu().numpy(), base_field.cpu().numpy(), mask)
+            say("field vs 16 x 16", e)
+            assert e <= 1e-6, (tile, e)
             g = binding.unpack(grads.cpu(), n, C)
             b = binding.unpack(base_grads.cpu(), n, C)
             for k in binding.PARAM_KEYS:
@@ -150,7 +154,7 @@ def test_batch_matches_single_contexts(O, tile):
 def test_batch_recon_masks_and_adjoints(O):
     """L_recon with per-hologram masks ([L][B][H][W]) and the split adjoints
     over a batch, against single contexts."""
-    B, H, W, C, n, L = 2, 40, 56, 1, 200, 2
+    B, H, W, C, n, L = 2, 40, 60, 1, 200, 2
     lams, zs, ps, Ts = batch_case(B, H, W, C, n, L, 400)
     Ms = [(np.random.default_rng(410 + b).uniform(0, 1, (L, H, W)) > 0.5).astype(np.float32)
           for b in range(B)]
@@ -195,7 +199,7 @@ def test_batched_solve_graph_matches_eager(O):
     """A captured solve over a batch of three holograms: two launches (the
     second from new parameters) equal the eager calls bit for bit, and each
     hologram's first logged loss matches the oracle."""
-    B, H, W, C, n, steps = 3, 40, 56, 1, 250, 6
+    B, H, W, C, n, steps = 3, 40, 60, 1, 250, 6
     lams, zs, ps, Ts = batch_case(B, H, W, C, n, 1, 500)
     ctx = binding.Context(H, W, C, 8e-6, lams[0], zs[0], max_gaussians=n, batch=B)
     for b in range(B):

@@ -548,10 +548,14 @@ def test_adam_step_matches_oracle(O):
     v0 = np.zeros(n, np.float32)
     P, M, V = (torch.from_numpy(a).cuda() for a in (p0, m0, v0))
     pp, mm, vv = p0.astype(np.float64), m0.astype(np.float64), v0.astype(np.float64)
+    # the oracle takes the kernel's inputs widened exactly: the FP32 roundings
+    # of lr and the betas (0.999 in FP32 moves 1 - beta2 by 1.3e-5 relative)
+    f32 = lambda x: float(np.float32(x))
     for t in range(1, 4):
         g = rng.standard_normal(n).astype(np.float32)
         binding.step(P, torch.from_numpy(g).cuda(), M, V, t, 1e-3)
-        pp, mm, vv = O.adam(pp, g, mm, vv, t, 1e-3)
+        pp, mm, vv = O.adam(pp, g, mm, vv, t, f32(1e-3), beta1=f32(0.9), beta2=f32(0.999),
+                            eps=f32(1e-8))
     assert np.max(np.abs(P.cpu().numpy() - pp)) < 1e-6
     assert np.max(np.abs(M.cpu().numpy() - mm)) < 1e-6
     # second moments: relative, since v ~ g^2 spans several decades
