@@ -149,8 +149,29 @@ cgh_status cgh_workspace_size(const cgh_config *cfg, size_t *bytes);
 cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_bytes,
                       void *stream, cgh_ctx **out);
 
-/* Releases the host handle (the workspace stays the caller's). */
+/* Releases the host handle (the workspace stays the caller's).  For a context
+ * of cgh_create_static: frees the device's static workspace for the next one
+ * (work still queued with that context must have finished). */
 cgh_status cgh_destroy(cgh_ctx *ctx);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): cgh_create
+ * with the library's static workspace, a device array of
+ * CGH_STATIC_WORKSPACE_BYTES that each GPU the library runs on holds until the
+ * process ends, instead of a caller workspace.  Calls no allocating routine.
+ * The context then works with every entry point as any other.
+ *  - One static context per device at a time: while one exists on the current
+ *    device, another call returns CGH_ERR_STATE (cgh_destroy frees the slot).
+ *  - A configuration whose cgh_workspace_size exceeds the array returns
+ *    CGH_ERR_WORKSPACE before any device work.
+ *  - The array keeps what the last context left in it; creation rebuilds the
+ *    tables and clears the status words, as cgh_create does, and nothing else
+ *    needs to start at zero.  Work of a destroyed static context that is still
+ *    running when the next one is created on the same device races with that
+ *    creation: synchronise its stream before cgh_destroy.
+ * Builds the tables on `stream` and waits for them (as cgh_create). */
+#define CGH_STATIC_WORKSPACE_BYTES (64u << 20)
+cgh_status cgh_create_static(const cgh_config *cfg, void *stream, cgh_ctx **out);
 
 /* ComplexRasterize2D (Alg. 2; Sec. 3.1 coherent sum; supplementary Forward
  * Pass): field[c][j][i] = sum_n alpha_n c_{n,c} G_n(i, j) exp(j phi_{n,c}) over

@@ -60,6 +60,7 @@ _SIGS = [
     ("cgh_workspace_size", ctypes.c_int, [ctypes.POINTER(cgh_config), ctypes.POINTER(ctypes.c_size_t)]),
     ("cgh_create", ctypes.c_int, [ctypes.POINTER(cgh_config), _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
     ("cgh_destroy", ctypes.c_int, [_VP]),
+    ("cgh_create_static", ctypes.c_int, [ctypes.POINTER(cgh_config), _VP, ctypes.POINTER(_VP)]),
     ("cgh_rasterize", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
     ("cgh_propagate", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("cgh_backward", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -191,13 +192,15 @@ def unpack(flat, n, C):
 class Context:
     """One hologram problem, or a batch of ``batch`` holograms of one size, on
     one device (cgh_create / cgh_destroy).  The device workspace is a torch
-    tensor owned by this object.  ``tile`` is the rasterizer tile (width,
-    height), one of TILE_SHAPES (None: 16 x 16)."""
+    tensor owned by this object, or with ``static=True`` the library's static
+    workspace (cgh_create_static: nothing is allocated; one such context per
+    device at a time).  ``tile`` is the rasterizer tile (width, height), one
+    of TILE_SHAPES (None: 16 x 16)."""
 
     def __init__(self, height, width, channels, pitch, wavelengths, zs, pad=None,
                  support_sigma=3.0, max_gaussians=0, max_pairs=0, full_loss=False,
                  paper_alpha=False, aperture=0.0, device="cuda", tile=None, batch=1,
-                 check_finite=False):
+                 check_finite=False, static=False):
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -234,13 +237,21 @@ class Context:
         size = ctypes.c_size_t(0)
         _check(lib().cgh_workspace_size(ctypes.byref(cfg), ctypes.byref(size)))
         self.workspace_bytes = size.value
-        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
-                                     device=self.device)
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) & ~255
         handle = ctypes.c_void_p()
-        _check(lib().cgh_create(ctypes.byref(cfg), ctypes.c_void_p(aligned), self.workspace_bytes,
-                                _stream(self.device), ctypes.byref(handle)))
+        if static:
+            # cgh_create_static: the library's static workspace, no allocation
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(lib().cgh_create_static(ctypes.byref(cfg), _stream(self.device),
+                                               ctypes.byref(handle)))
+        else:
+            self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
+                                         device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) & ~255
+            _check(lib().cgh_create(ctypes.byref(cfg), ctypes.c_void_p(aligned),
+                                    self.workspace_bytes, _stream(self.device),
+                                    ctypes.byref(handle)))
         self.handle = handle
         self.last_n = None
 

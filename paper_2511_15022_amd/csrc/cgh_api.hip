@@ -155,6 +155,7 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
   c->prof_class = 0;
   c->prof_n = 0;
   c->prof_ev = nullptr;
+  c->static_dev = -1;
   if (!make_plan(Wp, &c->plan_x) || !make_plan(Hp, &c->plan_y) ||
       !make_plan(Hp % 2 == 0 ? Hp / 2 : Hp, &c->plan_m))
     return fail(CGH_ERR_INVALID_ARG, "cannot plan FFTs of %d and %d", Wp, Hp);
@@ -249,10 +250,6 @@ size_t carve(Ctx *c, char *base) {
 
 using cgh::Ctx;
 
-struct cgh_ctx {
-  Ctx c;
-};
-
 extern "C" {
 
 int32_t cgh_abi_version(void) { return CGH_ABI_VERSION; }
@@ -268,10 +265,12 @@ cgh_status cgh_workspace_size(const cgh_config *cfg, size_t *bytes) {
   return CGH_OK;
 }
 
-cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_bytes,
-                      void *stream, cgh_ctx **out) {
-  if (!out) return fail(CGH_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
+}  // extern "C"
+
+// Validates cfg, carves the workspace, builds the tables on the stream and
+// waits for them; *out receives the context (no host or device allocation).
+cgh_status cgh::create_into(const cgh_config *cfg, void *workspace, size_t workspace_bytes,
+                            hipStream_t s, Ctx *out) {
   Ctx c;
   cgh_status st = setup(cfg, &c);
   if (st != CGH_OK) return st;
@@ -289,7 +288,6 @@ cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_b
     if (e != hipSuccess) return device_fail(e, "cgh_create");
     if (c.num_cu < 1) c.num_cu = 1;
   }
-  hipStream_t s = (hipStream_t)stream;
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_x, c.Wp, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_y, c.Hp, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_m, c.plan_m.n, s), "twiddles");
@@ -301,6 +299,19 @@ cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_b
   CGH_CHECK_LAUNCH(cgh::launch_zero_status(c, s), "zero status");
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return device_fail(e, "cgh_create");
+  *out = c;
+  return CGH_OK;
+}
+
+extern "C" {
+
+cgh_status cgh_create(const cgh_config *cfg, void *workspace, size_t workspace_bytes,
+                      void *stream, cgh_ctx **out) {
+  if (!out) return fail(CGH_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  Ctx c;
+  cgh_status st = cgh::create_into(cfg, workspace, workspace_bytes, (hipStream_t)stream, &c);
+  if (st != CGH_OK) return st;
   cgh_ctx *h = new (std::nothrow) cgh_ctx;
   if (!h) return fail(CGH_ERR_INVALID_ARG, "host allocation failed");
   h->c = c;
@@ -313,6 +324,11 @@ cgh_status cgh_destroy(cgh_ctx *ctx) {
     // teardown: a failure to destroy an event leaves nothing to recover
     for (int i = 0; i < 2 * cgh::kMaxProf; ++i) (void)hipEventDestroy(ctx->c.prof_ev[i]);
     delete[] ctx->c.prof_ev;
+    ctx->c.prof_ev = nullptr;
+  }
+  if (ctx && ctx->c.static_dev >= 0) {
+    cgh::release_static(ctx);  // the library's own handle: not deleted
+    return CGH_OK;
   }
   delete ctx;
   return CGH_OK;

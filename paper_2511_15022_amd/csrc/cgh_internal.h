@@ -121,8 +121,13 @@ struct Ctx {
   int prof_class;                   // 0: off
   int prof_n;                       // launches recorded
   hipEvent_t *prof_ev;              // 2 * kMaxProf events, created on first use
+  int static_dev;                   // device whose static workspace this context uses
+                                    // (cgh_create_static), -1 otherwise
 };
 constexpr int kMaxProf = 256;
+
+cgh_status create_into(const cgh_config *cfg, void *workspace, size_t workspace_bytes,
+                       hipStream_t s, Ctx *out);
 
 size_t carve(Ctx *c, char *base);   // returns bytes used (base may be null)
 cgh_status report(cgh_status st, const char *fmt, ...);  // sets cgh_last_error()
@@ -186,4 +191,14 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t cou
                        float inv_sqrt_bc2, const float *lr_groups, int n, int C,
                        hipStream_t s);
 
+}  // namespace cgh
+
+// the host handle of a context
+struct cgh_ctx {
+  cgh::Ctx c;
+};
+
+namespace cgh {
+// frees the static workspace of a cgh_create_static context for the next one
+void release_static(cgh_ctx *ctx);
 }  // namespace cgh
