@@ -111,4 +111,10 @@ WORKLOADS = {
     "rgb_4k_3z": dict(H=2160, W=3840, C=3, Hp=4320, Wp=7680, pitch=3.74e-6,
                       lambdas=[639e-9, 515e-9, 473e-9], zs=[3e-3, 5e-3, 7e-3], n=1658880,
                       pseed=6, tseed=7, masks=True),
+    # the shape of the paper's own measurements (Sec. 4): 3 x 640 x 1024, two
+    # planes spanning the 4 mm volume around d0 = 3 mm, 532 nm green, pitch
+    # 3.74 um, 65,536 Gaussians (the 5:1 parameter ratio)
+    "paper_640x1024": dict(H=640, W=1024, C=3, Hp=1280, Wp=2048, pitch=3.74e-6,
+                           lambdas=[639e-9, 532e-9, 473e-9], zs=[1e-3, 5e-3], n=65536,
+                           pseed=8, tseed=9, masks=True),
 }
