@@ -57,7 +57,15 @@ enum RecField {
   R_RY = 8,    // k sqrt(Sigma11)
   R_AMP = 9    // then alpha c_c cos(phi_c), alpha c_c sin(phi_c) for c < C
 };
-inline int rec_stride(int C) { return ((R_AMP + 2 * C) + 3) & ~3; }
+// After the amplitudes (padded to 4 floats) four more: the exponent along a pixel
+// row, log2 G = kappa dy^2 - (ra (dx - s dy))^2, with
+enum RecExt {
+  RX_S = 0,      // s = Sigma01 / Sigma11 (x offset of the row maximum per unit dy)
+  RX_KAPPA = 1,  // kappa = -log2(e) / (2 Sigma11)
+  RX_RA = 2      // ra = sqrt(log2(e) inv00 / 2)  (a = -ra^2)
+};
+inline int rec_ext(int C) { return ((R_AMP + 2 * C) + 3) & ~3; }
+inline int rec_stride(int C) { return rec_ext(C) + 4; }
 inline int partial_stride(int C) { return ((2 * C + 5) + 3) & ~3; }
 
 // Bits of the sticky non-finite word (status[3]) of a CGH_CHECK_FINITE context.

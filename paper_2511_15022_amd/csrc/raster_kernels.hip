@@ -20,6 +20,7 @@
 // g / n (its parameters are that hologram's block of the [B][n (6 + 2C)]
 // array), and tile t to hologram t / tiles_per, so one launch of each kernel
 // covers all of them.
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -30,7 +31,8 @@ namespace cgh {
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr float kPowerFloor2 = -50.0f * 1.4426950408889634f;  // clamp of the exponent, base 2
 
-constexpr int rec_stride_c(int C) { return ((R_AMP + 2 * C) + 3) & ~3; }
+constexpr int rec_ext_c(int C) { return ((R_AMP + 2 * C) + 3) & ~3; }
+constexpr int rec_stride_c(int C) { return rec_ext_c(C) + 4; }
 constexpr int part_stride_c(int C) { return ((2 * C + 5) + 3) & ~3; }
 
 // ----------------------------------------------------------------------------
@@ -156,6 +158,11 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ pa
     cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
     rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
   }
+  // row form of the exponent (completing the square in dx):
+  //   i00 dx^2 + 2 i01 dx dy + i11 dy^2 = i00 (dx - s dy)^2 + (i11 - i01^2 / i00) dy^2
+  r[rec_ext_c(C) + RX_S] = (float)(-q.i01 / q.i00);
+  r[rec_ext_c(C) + RX_KAPPA] = (float)(-0.5 * kLog2e * (q.i11 - q.i01 * q.i01 / q.i00));
+  r[rec_ext_c(C) + RX_RA] = (float)sqrt(0.5 * kLog2e * q.i00);
   float4 *dst = reinterpret_cast<float4 *>(rec + (size_t)g * RS);
 #pragma unroll
   for (int i = 0; i < RS / 4; ++i) dst[i] = make_float4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
@@ -381,9 +388,12 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
 // keys from kSortItems b + (kSortItems / 4) w, taken in index order 64 at a
 // time; a key's rank among equal digits of its wave is (the wave's running
 // count of the digit) + (earlier lanes of its round with that digit, from
-// ballots over the digit bits).  The waves of a block then add the counts of earlier waves, and the
-// blocks the exclusive scan of the digit-major histogram: equal keys keep
-// their order.
+// ballots over the digit bits).  The block then orders its keys by digit in
+// LDS (digit, then wave, then rank) and writes them out in that order, so
+// consecutive threads store consecutive positions of one digit's run and the
+// stores coalesce.  The global position of the key at local index i with
+// digit d is (exclusive scan of the digit-major histogram at (d, b)) +
+// (i - the block's first local index of d): equal keys keep their order.
 // hist_scan holds the digit-major histogram scanned either globally
 // (chunk_sums == nullptr) or per chunk of kScanItems, with the chunk sums in
 // chunk_sums (at most kMaxScanChunks); then each block scans the chunk sums.
@@ -396,13 +406,15 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint32_t *__restrict__ hist_scan, int nblocks,
     const uint32_t *__restrict__ chunk_sums, int nchunks) {
   constexpr int R = kSortItems / 256;  // rounds of 64 keys per wave
-  __shared__ uint32_t wcnt[4][256];
-  __shared__ uint32_t woff[4][256];
+  __shared__ uint32_t wcnt[4][256];    // per-wave digit counts, then local offsets
+  __shared__ uint32_t gofs[256];       // global position of local index 0 of each digit
   __shared__ uint32_t cpre[kMaxScanChunks];
+  __shared__ uint32_t skey[kSortItems], sval[kSortItems];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t count = pair_count(status, cap);
   const uint32_t base = blockIdx.x * kSortItems;
   if (base >= count) return;  // the whole block is past the end (uniform)
+  const uint32_t nvalid = min((uint32_t)kSortItems, count - base);
 #pragma unroll
   for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
   const uint32_t first = base + (uint32_t)(kSortItems / 4) * wave + lane;
@@ -449,23 +461,44 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
   }
   __syncthreads();
   {
-    const size_t e = (size_t)tid * nblocks + blockIdx.x;
-    uint32_t run = hist_scan[e] + (chunk_sums ? cpre[e / kScanItems] : 0u);
+    // thread tid = digit d: the block's local offsets of d per wave, and the
+    // global position of d's local index 0
+    uint32_t c[4], tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) { c[w] = wcnt[w][tid]; tot += c[w]; }
+    uint32_t all;
+    const uint32_t lbase = block_exclusive_scan(tot, &all);
+    uint32_t run = lbase;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      woff[w][tid] = run;
-      run += wcnt[w][tid];
+      wcnt[w][tid] = run;
+      run += c[w];
     }
+    const size_t e = (size_t)tid * nblocks + blockIdx.x;
+    gofs[tid] = hist_scan[e] + (chunk_sums ? cpre[e / kScanItems] : 0u) - lbase;
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (first + 64u * r < count) {
       const uint32_t d = (key[r] >> shift) & 255u;
-      const uint32_t pos = woff[wave][d] + rank[r];
+      const uint32_t lp = wcnt[wave][d] + rank[r];
+      if (lp < (uint32_t)kSortItems) {  // always true for consistent counts; guards the write
+        skey[lp] = key[r];
+        sval[lp] = val[r];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = (uint32_t)tid + 256u * r;
+    if (i < nvalid) {
+      const uint32_t k = skey[i];
+      const uint32_t pos = gofs[(k >> shift) & 255u] + i;
       if (pos < count) {  // always true for a consistent histogram; guards the write
-        kout[pos] = key[r];
-        vout[pos] = val[r];
+        kout[pos] = k;
+        vout[pos] = sval[i];
       }
     }
   }
@@ -473,27 +506,30 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
 
 // Tile ranges from the sorted keys; each tile without pairs gets an empty
 // range from the thread at the gap it falls in (every tile is written once).
+// A grid-stride loop: the grid is sized for the pair capacity's worth of
+// blocks at most, far fewer than one thread per pair.
 __global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ status,
                          int64_t cap, uint2 *__restrict__ ranges, uint32_t num_tiles) {
   const uint32_t count = pair_count(status, cap);
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
   if (count == 0) {
-    if (i == 0)
+    if (i0 == 0)
       for (uint32_t t = 0; t < num_tiles; ++t) ranges[t] = make_uint2(0u, 0u);
     return;
   }
-  if (i >= count) return;
-  const uint32_t k = keys[i];
-  if (k >= num_tiles) return;  // keys are tile ids; guards the writes
-  if (i == 0 || keys[i - 1] != k) {
-    ranges[k].x = i;
-    const uint32_t prev = i == 0 ? 0u : keys[i - 1] + 1u;
-    for (uint32_t t = prev; t < k; ++t) ranges[t] = make_uint2(0u, 0u);
-  }
-  if (i + 1 == count || keys[i + 1] != k) {
-    ranges[k].y = i + 1;
-    if (i + 1 == count)
-      for (uint32_t t = k + 1; t < num_tiles; ++t) ranges[t] = make_uint2(0u, 0u);
+  for (uint32_t i = i0; i < count; i += gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    if (k >= num_tiles) continue;  // keys are tile ids; guards the writes
+    if (i == 0 || keys[i - 1] != k) {
+      ranges[k].x = i;
+      const uint32_t prev = i == 0 ? 0u : keys[i - 1] + 1u;
+      for (uint32_t t = prev; t < k; ++t) ranges[t] = make_uint2(0u, 0u);
+    }
+    if (i + 1 == count || keys[i + 1] != k) {
+      ranges[k].y = i + 1;
+      if (i + 1 == count)
+        for (uint32_t t = k + 1; t < num_tiles; ++t) ranges[t] = make_uint2(0u, 0u);
+    }
   }
 }
 
@@ -560,7 +596,7 @@ hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
     cur ^= 1;
   }
   c.sorted = cur;
-  const int64_t grid = (c.pair_cap + 255) / 256;
+  const int64_t grid = std::min<int64_t>((c.pair_cap + 255) / 256, (int64_t)c.num_cu * 8);
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, s, c.keys[cur], c.status,
                      c.pair_cap, c.ranges, (uint32_t)c.num_tiles);
   return hipGetLastError();
@@ -723,6 +759,245 @@ __global__ __launch_bounds__(64 * SBX * SBY) void k_raster_fwd(
   }
 }
 
+// ----------------------------------------------------------------------------
+// Forward, row-segment form (tiles 16 or 32 pixels wide, without the Alg. 2
+// weight).  The tile is cut into segments of 16 pixels of one row, and a wave
+// owns four segments, one per DPP row of 16 lanes: lane i of row g is pixel i
+// of segment 4 wave + g.  Along a pixel row the exponent is
+//   log2 G = kappa dy^2 - (ra (dx - s dy))^2          (dx, dy = pixel - mean)
+// (the record's row form), so with u = x - (segment centre) in [-7.5, 7.5]
+//   w = ra u + m,   log2 G = qmax - w^2,
+//   m = ra ((segment centre - mean_x) - s dy),   qmax = kappa dy^2
+// per (Gaussian, segment).  The largest exponent over the segment is
+// qmax - max(0, |m| - 7.5 ra)^2, and a Gaussian is listed for the segment only
+// where that reaches the support threshold, so no pixel row outside the
+// support is walked.  The walk takes sixteen listed Gaussians per row at a
+// time, one per lane (m, qmax, ra from the list, amplitudes from the record),
+// and broadcasts them across the row one after another with DPP row_newbcast:
+// the four rows of a wave step through four different lists in one
+// instruction stream, and each listed Gaussian costs 7 + 2C instructions per
+// 16 pixels.  Lists keep the tile-list order, so the sums are reproducible.
+// ----------------------------------------------------------------------------
+constexpr int kSegBatch = 128;  // Gaussians culled per batch (two per lane of each wave)
+
+#define CGH_NB(j) " row_newbcast:" #j " row_mask:0xf bank_mask:0xf\n"
+// two steps (lanes ja, jb of each row): exponents into pa, pb
+#define CGH_P2(ja, jb)                                  \
+  "v_mov_b32_dpp %[wa], %[m]" CGH_NB(ja)                \
+  "v_mov_b32_dpp %[wb], %[m]" CGH_NB(jb)                \
+  "v_fmac_f32_dpp %[wa], %[ra], %[u]" CGH_NB(ja)        \
+  "v_fmac_f32_dpp %[wb], %[ra], %[u]" CGH_NB(jb)        \
+  "v_mul_f32_e32 %[wa], %[wa], %[wa]\n"                 \
+  "v_mul_f32_e32 %[wb], %[wb], %[wb]\n"                 \
+  "v_sub_f32_dpp %[pa], %[qm], %[wa]" CGH_NB(ja)        \
+  "v_sub_f32_dpp %[pb], %[qm], %[wb]" CGH_NB(jb)
+// G = 2^p where p >= thr, else 0 (into wa, wb).  The comparisons are issued
+// first: a lane mask written by a VALU compare needs two wait states before
+// v_cndmask reads it, and a v_exp result one.
+#define CGH_G                                           \
+  "v_cmp_le_f32_e32 vcc, %[thr], %[pa]\n"               \
+  "v_cmp_le_f32_e64 %[sb], %[thr], %[pb]\n"             \
+  "v_exp_f32_e32 %[wa], %[pa]\n"                        \
+  "v_exp_f32_e32 %[wb], %[pb]\n"                        \
+  "v_cndmask_b32_e32 %[wa], 0, %[wa], vcc\n"            \
+  "v_cndmask_b32_e64 %[wb], 0, %[wb], %[sb]\n"
+// the same with the exponent clamped at fl from below (unbounded support)
+#define CGH_G_CLAMP                                     \
+  "v_cmp_le_f32_e32 vcc, %[thr], %[pa]\n"               \
+  "v_cmp_le_f32_e64 %[sb], %[thr], %[pb]\n"             \
+  "v_max_f32_e32 %[pa], %[fl], %[pa]\n"                 \
+  "v_max_f32_e32 %[pb], %[fl], %[pb]\n"                 \
+  "v_exp_f32_e32 %[wa], %[pa]\n"                        \
+  "v_exp_f32_e32 %[wb], %[pb]\n"                        \
+  "v_cndmask_b32_e32 %[wa], 0, %[wa], vcc\n"            \
+  "v_cndmask_b32_e64 %[wb], 0, %[wb], %[sb]\n"
+#define CGH_ACC(j, g, k) "v_fmac_f32_dpp %[a" #k "], %[c" #k "], %[" g "]" CGH_NB(j)
+#define CGH_ACC1(j, g) CGH_ACC(j, g, 0) CGH_ACC(j, g, 1)
+#define CGH_ACC2(j, g) CGH_ACC1(j, g) CGH_ACC(j, g, 2) CGH_ACC(j, g, 3)
+#define CGH_ACC3(j, g) CGH_ACC2(j, g) CGH_ACC(j, g, 4) CGH_ACC(j, g, 5)
+#define CGH_ACC4(j, g) CGH_ACC3(j, g) CGH_ACC(j, g, 6) CGH_ACC(j, g, 7)
+// four steps, lanes j0..j3.  The s_nop gives the two wait states a DPP source
+// needs after a VALU write (the sources are not written inside the block).
+#define CGH_STEP4(ACC, GEXP, j0, j1, j2, j3)                                       \
+  "s_nop 1\n" CGH_P2(j0, j1) GEXP ACC(j0, "wa") ACC(j1, "wb") CGH_P2(j2, j3) GEXP \
+      ACC(j2, "wa") ACC(j3, "wb")
+
+// accumulators a[2C] (re, im per channel), amplitudes c[2C] of the lane's
+// listed Gaussian; runs steps 4 q .. 4 q + 3
+#define CGH_OPS_COMMON                                                          \
+  [wa] "=&v"(wa), [wb] "=&v"(wb), [pa] "=&v"(pa), [pb] "=&v"(pb), [sb] "=&s"(sb)
+template <int C, bool CLAMP, int Q>
+__device__ __forceinline__ void seg_steps(float (&a)[2 * C], const float (&cv)[2 * C], float m,
+                                          float ra, float qm, float u, float thr, float fl) {
+  float wa, wb, pa, pb;
+  uint64_t sb;
+#define CGH_IN [m] "v"(m), [ra] "v"(ra), [qm] "v"(qm), [u] "v"(u), [thr] "s"(thr), [fl] "s"(fl)
+#define CGH_RUN(N, GEXP, j0, j1, j2, j3)                                           \
+  asm volatile(CGH_STEP4(CGH_ACC##N, GEXP, j0, j1, j2, j3)                           \
+               : CGH_OPS_COMMON, CGH_O##N                                           \
+               : CGH_IN, CGH_I##N                                                   \
+               : "vcc")
+#define CGH_O1 [a0] "+v"(a[0]), [a1] "+v"(a[1])
+#define CGH_O2 CGH_O1, [a2] "+v"(a[2]), [a3] "+v"(a[3])
+#define CGH_O3 CGH_O2, [a4] "+v"(a[4]), [a5] "+v"(a[5])
+#define CGH_O4 CGH_O3, [a6] "+v"(a[6]), [a7] "+v"(a[7])
+#define CGH_I1 [c0] "v"(cv[0]), [c1] "v"(cv[1])
+#define CGH_I2 CGH_I1, [c2] "v"(cv[2]), [c3] "v"(cv[3])
+#define CGH_I3 CGH_I2, [c4] "v"(cv[4]), [c5] "v"(cv[5])
+#define CGH_I4 CGH_I3, [c6] "v"(cv[6]), [c7] "v"(cv[7])
+#define CGH_BY_Q(N, GEXP)                                     \
+  if constexpr (Q == 0) CGH_RUN(N, GEXP, 0, 1, 2, 3);         \
+  else if constexpr (Q == 1) CGH_RUN(N, GEXP, 4, 5, 6, 7);    \
+  else if constexpr (Q == 2) CGH_RUN(N, GEXP, 8, 9, 10, 11);  \
+  else CGH_RUN(N, GEXP, 12, 13, 14, 15)
+#define CGH_BY_G(N)                                             \
+  if constexpr (CLAMP) { CGH_BY_Q(N, CGH_G_CLAMP); } else { CGH_BY_Q(N, CGH_G); }
+  if constexpr (C == 1) { CGH_BY_G(1); }
+  else if constexpr (C == 2) { CGH_BY_G(2); }
+  else if constexpr (C == 3) { CGH_BY_G(3); }
+  else { CGH_BY_G(4); }
+#undef CGH_IN
+#undef CGH_RUN
+#undef CGH_O1
+#undef CGH_O2
+#undef CGH_O3
+#undef CGH_O4
+#undef CGH_I1
+#undef CGH_I2
+#undef CGH_I3
+#undef CGH_I4
+#undef CGH_BY_Q
+#undef CGH_BY_G
+}
+
+template <int C, bool CLAMP, int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_raster_seg(
+    const float *__restrict__ rec, const uint32_t *__restrict__ vals,
+    const uint2 *__restrict__ ranges, int W, int H, int tiles_x, int tiles_per, float thr,
+    uint32_t zero_id, float2 *__restrict__ field_all) {
+  constexpr int RS = rec_stride_c(C), RX = rec_ext_c(C);
+  constexpr int SPR = TW / 16;  // segments per pixel row
+  constexpr int NW = SPR * TH / 4;
+  static_assert(TW % 16 == 0 && (SPR * TH) % 4 == 0, "tile shape");
+  // (Gaussian id bits, m, qmax, ra) of the listed Gaussians of each segment
+  __shared__ float4 list[NW][4][kSegBatch];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = blockIdx.x;
+  const int hb = tile / tiles_per, ltile = tile - hb * tiles_per;  // hologram, its tile
+  float2 *field = field_all + (size_t)hb * C * H * W;
+  const int tx = ltile % tiles_x, ty = ltile / tiles_x;
+  const int Xt = tx * TW, Yt = ty * TH;  // tile origin
+  // this lane's pixel: row rg = lane / 16 of the wave, pixel lane % 16 of segment
+  // 4 wave + rg
+  const int rg = lane >> 4, seg = 4 * wave + rg;
+  const int sr = seg / SPR, sc = seg % SPR;
+  const int px = Xt + 16 * sc + (lane & 15), py = Yt + sr;
+  const float u = (float)(lane & 15) - 7.5f;
+  const float fl = kPowerFloor2;
+  const float cull = thr - 1e-3f * (1.f - thr);  // margin for rounding
+  float acc[2 * C];
+#pragma unroll
+  for (int k = 0; k < 2 * C; ++k) acc[k] = 0.f;
+  const uint2 rng = ranges[tile];
+  for (uint32_t base = rng.x; base < rng.y; base += kSegBatch) {
+    const int cnt = (int)min((uint32_t)kSegBatch, rng.y - base);
+    // ---- cull: each lane takes one Gaussian per round against the wave's
+    // four segments; survivors are appended to the segment lists in order
+    constexpr int QD = kSegBatch / 64;
+    uint32_t gid[QD];
+    float4 r0[QD], rx[QD];
+#pragma unroll
+    for (int qd = 0; qd < QD; ++qd) {
+      const int idx = qd * 64 + lane;
+      gid[qd] = idx < cnt ? vals[base + idx] : zero_id;
+    }
+#pragma unroll
+    for (int qd = 0; qd < QD; ++qd) {
+      const float *g0 = rec + (size_t)gid[qd] * RS;
+      r0[qd] = reinterpret_cast<const float4 *>(g0)[0];       // mix, miy, mfx, mfy
+      rx[qd] = reinterpret_cast<const float4 *>(g0 + RX)[0];  // s, kappa, ra
+    }
+    int nl[4] = {0, 0, 0, 0};  // list lengths (wave-uniform)
+#pragma unroll
+    for (int qd = 0; qd < QD; ++qd) {
+      if (qd * 64 >= cnt) break;  // uniform
+      const bool valid = qd * 64 + lane < cnt;
+      const float oxt = (float)(Xt - __float_as_int(r0[qd].x)) - r0[qd].z;
+      const float eyt = (float)(Yt - __float_as_int(r0[qd].y)) - r0[qd].w;
+      const float s = rx[qd].x, kap = rx[qd].y, ra = rx[qd].z;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int sg = 4 * wave + g;
+        const float dy = eyt + (float)(sg / SPR);
+        const float oxc = oxt + (float)(16 * (sg % SPR)) + 7.5f;
+        const float qm = kap * dy * dy;
+        const float m = ra * fmaf(-s, dy, oxc);
+        const float d = fmaxf(fmaf(-7.5f, ra, fabsf(m)), 0.f);
+        const bool hit = valid && fmaf(-d, d, qm) >= cull;
+        const uint64_t bm = __builtin_amdgcn_ballot_w64(hit);
+        if (hit) {
+          const int pos = nl[g] + (int)__builtin_amdgcn_mbcnt_hi(
+                                      (uint32_t)(bm >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+          list[wave][g][pos] = make_float4(__uint_as_float(gid[qd]), m, qm, ra);
+        }
+        nl[g] += __popcll(bm);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // ---- walk: sixteen entries of each row's list per round; the entries
+    // and amplitudes of the next round are loaded while this one runs
+    const int nmax = max(max(nl[0], nl[1]), max(nl[2], nl[3]));
+    const int nmine = rg == 0 ? nl[0] : rg == 1 ? nl[1] : rg == 2 ? nl[2] : nl[3];
+    auto fetch = [&](int b0, float4 &e, float (&cv)[2 * C]) {
+      const int j = b0 + (lane & 15);
+      e = list[wave][rg][min(j, kSegBatch - 1)];
+      if (j >= nmine) e = make_float4(__uint_as_float(zero_id), 0.f, 0.f, 0.f);
+      const float *amp = rec + (size_t)__float_as_uint(e.x) * RS + R_AMP;
+#pragma unroll
+      for (int k = 0; k < 2 * C; ++k) cv[k] = amp[k];
+    };
+    float4 e;
+    float cv[2 * C];
+    if (nmax > 0) fetch(0, e, cv);
+    for (int b0 = 0; b0 < nmax; b0 += 16) {
+      // issued on every round (past the end it reads zero entries), so the
+      // wait before the steps covers only this round's loads
+      float4 en;
+      float cvn[2 * C];
+      fetch(b0 + 16, en, cvn);
+      const int left = nmax - b0;
+      seg_steps<C, CLAMP, 0>(acc, cv, e.y, e.w, e.z, u, thr, fl);
+      if (left > 4) seg_steps<C, CLAMP, 1>(acc, cv, e.y, e.w, e.z, u, thr, fl);
+      if (left > 8) seg_steps<C, CLAMP, 2>(acc, cv, e.y, e.w, e.z, u, thr, fl);
+      if (left > 12) seg_steps<C, CLAMP, 3>(acc, cv, e.y, e.w, e.z, u, thr, fl);
+      e = en;
+#pragma unroll
+      for (int k = 0; k < 2 * C; ++k) cv[k] = cvn[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (px < W && py < H) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      field[((size_t)c * H + py) * W + px] = make_float2(acc[2 * c], acc[2 * c + 1]);
+  }
+}
+#undef CGH_NB
+#undef CGH_P2
+#undef CGH_G
+#undef CGH_G_CLAMP
+#undef CGH_ACC
+#undef CGH_ACC1
+#undef CGH_ACC2
+#undef CGH_ACC3
+#undef CGH_ACC4
+#undef CGH_STEP4
+#undef CGH_OPS_COMMON
+
 // calls f(integral_constant<TW>, integral_constant<TH>) for the context's tile
 template <class F>
 static void with_tile(const Ctx &c, F &&f) {
@@ -760,8 +1035,16 @@ hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
         hipLaunchKernelGGL(kern, grid, block, 0, s, c.rec, vals, c.ranges, c.W, c.H, c.tiles_x,
                            c.tiles_per, thr, zid, c.alim, field);
       };
+      constexpr int TW = decltype(tw)::value, TH = decltype(th)::value;
+      auto go_seg = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(TW * TH), 0, s, c.rec, vals, c.ranges, c.W,
+                           c.H, c.tiles_x, c.tiles_per, thr, zid, field);
+      };
       if (pa) go(k_raster_fwd<CC, false, true, SBX, SBY>);
-      else if (clamp) go(k_raster_fwd<CC, true, false, SBX, SBY>);
+      else if constexpr (TW >= 16) {
+        if (clamp) go_seg(k_raster_seg<CC, true, TW, TH>);
+        else go_seg(k_raster_seg<CC, false, TW, TH>);
+      } else if (clamp) go(k_raster_fwd<CC, true, false, SBX, SBY>);
       else go(k_raster_fwd<CC, false, false, SBX, SBY>);
     });
   });
@@ -816,7 +1099,7 @@ __global__ __launch_bounds__(64) void k_raster_adj(
     const uint32_t *__restrict__ offsets, int W, int H, int tiles_x, int tiles_per, float thr,
     const float2 *__restrict__ alim, const float2 *__restrict__ gfield_all, int64_t cap,
     float *__restrict__ partials) {
-  constexpr int RS = rec_stride_c(C);
+  constexpr int RS = rec_stride_c(C), RX = rec_ext_c(C);
   constexpr int PS = part_stride_c(C);
   constexpr int NS = 2 * C + 5 + (PA ? 1 : 0);
   static_assert(NS <= PS, "the clamped-pixel sum needs a spare partial slot");
@@ -860,14 +1143,14 @@ __global__ __launch_bounds__(64) void k_raster_adj(
     int area = 0;
     int xa = 0, xb = -1, ya = 0, yb = -1;
     uint32_t slot = 0xffffffffu;
-    float r[RS];
+    float r[RX];
 #pragma unroll
-    for (int k = 0; k < RS; ++k) r[k] = 0.f;
+    for (int k = 0; k < RX; ++k) r[k] = 0.f;
     if (lane < cnt) {
       const uint32_t g = vals[base + lane];
       const float4 *src = reinterpret_cast<const float4 *>(rec + (size_t)g * RS);
 #pragma unroll
-      for (int k = 0; k < RS / 4; ++k) {
+      for (int k = 0; k < RX / 4; ++k) {
         const float4 v = src[k];
         r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
       }
