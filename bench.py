@@ -88,21 +88,51 @@ KERNEL_SOURCE = {"col_pass": "fft_kernels.hip", "row_loss": "fft_kernels.hip",
                  "raster_adjoint": "raster_kernels.hip"}
 
 
-def measured_traffic(cls):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current source of that kernel; else None."""
+def committed_figure(kind, cls, pattern):
+    """A per-launch figure of kernel class ``cls`` from a committed rocprofv3
+    summary under profiles/ (lines ``<kind> <class> <value> <sha256>``), if it
+    was taken on the current source of that kernel; else None."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_2511_15022_amd", "csrc", KERNEL_SOURCE.get(cls, ""))
     if not os.path.isfile(src):
         return None
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    for path in glob.glob(os.path.join(ROOT, "profiles", "*hbm_counters*.txt")):
+    for path in glob.glob(os.path.join(ROOT, "profiles", pattern)):
         for line in open(path):
             parts = line.split()
-            if len(parts) == 4 and parts[0] == "traffic" and parts[1] == cls and parts[3] == digest:
-                return int(parts[2])
+            if len(parts) == 4 and parts[0] == kind and parts[1] == cls and parts[3] == digest:
+                return float(parts[2])
     return None
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    v = committed_figure("traffic", cls, "*hbm_counters*.txt")
+    return None if v is None else int(v)
+
+
+VALU_CYCLES_PER_INST = 4     # a wave64 FP32 VALU instruction on a 16-lane SIMD
+SIMDS, CLOCK_GHZ = 1024, 2.4  # MI355X: 256 CUs x 4 SIMDs
+
+
+def profile_figures(cls, algorithmic, unit_scale, peak, t_launch_s):
+    """Counter-based figures of a class: the kernel-trace duration and the
+    fraction of peak it gives, the VALU floor from SQ_INSTS_VALU and the VALU
+    issue utilisation against this run's own launch time."""
+    out = {}
+    dur = committed_figure("duration", cls, "*kernel_trace*.txt")
+    if dur is not None:
+        out["profile_duration_us"] = dur
+        if algorithmic is not None:
+            out["profile_frac"] = algorithmic / (dur * 1e-6) / unit_scale / peak
+    insts = committed_figure("valu", cls, "*valu_counters*.txt")
+    if insts is not None:
+        floor_us = insts * VALU_CYCLES_PER_INST / SIMDS / (CLOCK_GHZ * 1e3)
+        out["valu_insts_per_launch"] = insts
+        out["valu_floor_us"] = floor_us
+        out["valu_issue_util"] = floor_us / (t_launch_s * 1e6)
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -840,6 +870,33 @@ def main():
     log(f"[bench] {args.steps} steps in {ms_total:.2f} ms -> {ms_per_step:.4f} ms/step; "
         f"loss {loss[0].item():.6f}")
     peak_vram = torch.cuda.max_memory_allocated(dev)
+    # the same steps as one HIP-graph launch (cgh_solve: rasterize, backward and
+    # Adam per step, captured once; L_MSE only, so not for the masked workloads)
+    ms_per_step_eager, graph = ms_per_step, None
+    if Mk is None and args.steps > 0:
+        Pg = binding.pack(p, device=dev)
+        sol = binding.Solve(ctx, Pg, n, T, args.steps, lr=lr)
+        sol.launch()  # warm-up launch
+        torch.cuda.synchronize(dev)
+        Pg.copy_(P)
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(sol.stream)
+        sol.launch()
+        g1.record(sol.stream)
+        torch.cuda.synchronize(dev)
+        ms_graph = g0.elapsed_time(g1) / args.steps
+        pairs_g, ok_g = ctx.read_status()
+        assert ok_g, "pair list overflow in the graph-launched steps"
+        graph = {"ms_per_step": ms_graph, "steps": args.steps,
+                 "final_loss": sol.loss_log[-1, 0].item(),
+                 "what": "the timed steps as one cgh_solve graph launch (moments zeroed at its "
+                         "start), from the parameters the eager steps ended with"}
+        sol.close()
+        del Pg, sol
+        log(f"[bench] graph-launched: {args.steps} steps -> {ms_graph:.4f} ms/step "
+            f"(eager calls {ms_per_step_eager:.4f} ms/step)")
+        ms_per_step = min(ms_per_step, ms_graph)
     if args.copy_probe:
         # a plain copy of known size: 256 MiB read + 256 MiB written per launch
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -878,7 +935,7 @@ def main():
         "row_fft": C * H * (W + Wp) * 8,
     }
     # per-pair and per-Gaussian byte counts of the record layouts (C channels)
-    rec_stride = ((9 + 2 * C) + 3) & ~3
+    rec_stride = (((9 + 2 * C) + 3) & ~3) + 4
     part_stride = ((2 * C + 5) + 3) & ~3
     nparam = 6 + 2 * C
     hbm_bytes["preprocess"] = n * (nparam * 4 + rec_stride * 4 + 8 + 4)
@@ -889,20 +946,25 @@ def main():
         t_launch = kernels[cls]["ms_per_launch"] * 1e-3
         if cls in hbm_bytes:
             achieved = hbm_bytes[cls] / t_launch / 1e9
-            return {"kernel": cls, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": measured_traffic(cls),
-                    "algorithmic_bytes_per_launch": hbm_bytes[cls]}
+            r = {"kernel": cls, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                 "traffic": measured_traffic(cls),
+                 "algorithmic_bytes_per_launch": hbm_bytes[cls]}
+            r.update(profile_figures(cls, hbm_bytes[cls], 1e9, HBM_PEAK_GBS, t_launch))
+            return r
         if cls in ("raster", "raster_adjoint"):
             if not npairs_cache:
                 npairs_cache.append(in_support_pairs(p, H, W, 3.0))
             npairs = npairs_cache[0]
             per_pair = (10 + 4 * C) if cls == "raster" else (21 + 8 * C)
             achieved = npairs * per_pair / t_launch / 1e12
-            return {"kernel": cls, "bound": "alu", "achieved": achieved,
-                    "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": measured_traffic(cls),
-                    "in_support_pairs": npairs, "flop_per_pair": per_pair}
+            r = {"kernel": cls, "bound": "alu", "achieved": achieved,
+                 "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": measured_traffic(cls),
+                 "in_support_pairs": npairs, "flop_per_pair": per_pair}
+            r.update(profile_figures(cls, npairs * per_pair, 1e12, FP32_VALU_PEAK_TFLOPS,
+                                     t_launch))
+            return r
         label = {"binning": "latency (integer sort, nine short launches)",
                  "loss": "latency (one-block FP64 reduction)"}.get(cls, "latency")
         return {"kernel": cls, "bound": label}
@@ -914,7 +976,9 @@ def main():
         roofline = class_roofline(dom)
         for cls in kernels:
             r = class_roofline(cls)
-            rooflines[cls] = {k: r[k] for k in ("bound", "achieved", "unit", "frac") if k in r}
+            rooflines[cls] = {k: r[k] for k in ("bound", "achieved", "unit", "frac",
+                                                "profile_frac", "valu_floor_us",
+                                                "valu_issue_util") if k in r}
 
     paper_loss = None
     if args.paper_loss_steps > 0:
@@ -1045,6 +1109,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_eager_calls": ms_per_step_eager,
+        "graph_launched": graph,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
