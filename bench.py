@@ -845,8 +845,13 @@ def main():
     def step():
         t_step[0] += 1
         ctx.rasterize(P, n, field)
-        ctx.backward(P, n, field, T, loss=loss, grad_field=gfield, grads=G, mask=Mk)
-        binding.step(P, G, M, V, t_step[0], lr)
+        if Mk is None:
+            # the L_MSE backward with the Adam update fused into its last kernel
+            ctx.backward_step(P, n, field, T, M, V, t_step[0], lr, loss=loss,
+                              grad_field=gfield)
+        else:
+            ctx.backward(P, n, field, T, loss=loss, grad_field=gfield, grads=G, mask=Mk)
+            binding.step(P, G, M, V, t_step[0], lr)
 
     for _ in range(args.warmup):
         step()

@@ -210,6 +210,24 @@ cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_
                         const float *target, double *loss, cgh_c64 *grad_field, float *grads,
                         void *stream);
 
+/* One whole optimisation step after cgh_rasterize: cgh_backward followed by the
+ * Adam update of cgh_step (uniform learning rate), fused: the per-Gaussian
+ * stage of the rasterizer adjoint applies Adam (Kingma & Ba, Algorithm 1) to
+ * each Gaussian's 6 + 2C parameters as it produces their gradients, so the
+ * gradients make no round trip through memory before the update.  The results
+ * (params, m, v, loss, grad_field and grads) are bitwise those of cgh_backward
+ * and then cgh_step with lr_groups = NULL.
+ *   params : n * (6 + 2C) floats, updated in place (read first, as cgh_backward).
+ *   grads  : dL/dparams as cgh_backward, or NULL (not stored).
+ *   m, v   : the Adam moments, same layout, updated in place (zero before t = 1).
+ *   t, lr, beta1, beta2, eps: as cgh_step.
+ * Other arguments, outputs and preconditions as cgh_backward; the Adam
+ * arguments are checked as in cgh_step (CGH_ERR_INVALID_ARG). */
+cgh_status cgh_backward_step(cgh_ctx *ctx, float *params, int32_t n, const cgh_c64 *field,
+                             const float *target, double *loss, cgh_c64 *grad_field,
+                             float *grads, float *m, float *v, int32_t t, float lr, float beta1,
+                             float beta2, float eps, void *stream);
+
 /* cgh_backward with the reconstruction loss of Sec. 3.2 (L_recon) in place of
  * L_MSE: per plane l the sum of ||I_l - T_l||^2, ||I_l M_l - T_l M_l||^2 and
  * ||I_l T_l - T_l T_l||^2, averaged over planes; as for L_MSE each squared norm
@@ -373,9 +391,11 @@ cgh_status cgh_set_hologram_optics(cgh_ctx *ctx, int32_t hologram, const double 
  * step.  Each launch of the graph first zeroes m and v, then, for
  * t = 1 .. steps, runs exactly the kernels of
  *   cgh_rasterize(ctx, params, n, field);
- *   cgh_backward(ctx, params, n, field, target, loss_log + 2 (t - 1), NULL, grads);
- *   cgh_step(params, grads, m, v, count, t, lr, beta1, beta2, eps, NULL, C)
- * (count = n (6 + 2C)), with the same results bit for bit.  The graph binds
+ *   cgh_backward_step(ctx, params, n, field, target, loss_log + 2 (t - 1), NULL, grads,
+ *                     m, v, t, lr, beta1, beta2, eps)
+ * which give bit for bit the results of cgh_backward and then
+ * cgh_step(params, grads, m, v, count, t, lr, beta1, beta2, eps, NULL, C)
+ * (count = n (6 + 2C)); grads receives the last step's gradients only.  The graph binds
  * the pointers given here: a launch optimises from whatever params and target
  * hold when it starts and leaves the optimised parameters in params;
  * loss_log (device double[2 steps]) receives {L, 10 log10(1 / L)} before each

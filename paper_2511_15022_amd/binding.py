@@ -64,6 +64,9 @@ _SIGS = [
     ("cgh_rasterize", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
     ("cgh_propagate", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("cgh_backward", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("cgh_backward_step", ctypes.c_int,
+     [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32,
+      ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP]),
     ("cgh_backward_recon", ctypes.c_int,
      [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cgh_backward_full", ctypes.c_int,
@@ -351,6 +354,27 @@ class Context:
                                             _ptr(grad_field), _ptr(grads),
                                             _stream(self.device)))
         return grads
+
+    def backward_step(self, params, n, field, target, m, v, t, lr, beta1=0.9, beta2=0.999,
+                      eps=1e-8, loss=None, grad_field=None, grads=None):
+        """cgh_backward_step: the L_MSE backward and the Adam update of ``params``
+        (in place, with moments ``m``, ``v``) in one pass of the per-Gaussian
+        adjoint stage.  ``grads`` (optional) receives dL/dparams."""
+        _need(params, torch.float32, self.param_count(n), "params", self.device)
+        _need(m, torch.float32, self.param_count(n), "m", self.device)
+        _need(v, torch.float32, self.param_count(n), "v", self.device)
+        _need(field, torch.complex64, self._field_numel(), "field", self.device)
+        _need(target, torch.float32, self._plane_numel(), "target", self.device)
+        if grads is not None:
+            _need(grads, torch.float32, self.param_count(n), "grads", self.device)
+        if loss is not None:
+            _need(loss, torch.float64, 2 * self.B, "loss", self.device)
+        if grad_field is not None:
+            _need(grad_field, torch.complex64, self._field_numel(), "grad_field", self.device)
+        _check(lib().cgh_backward_step(self.handle, _ptr(params), int(n), _ptr(field),
+                                       _ptr(target), _ptr(loss), _ptr(grad_field), _ptr(grads),
+                                       _ptr(m), _ptr(v), int(t), float(lr), float(beta1),
+                                       float(beta2), float(eps), _stream(self.device)))
 
     def propagate_field_adjoint(self, grad_u, grad_field=None):
         """cgh_propagate_field_adjoint: sum over planes of P^H grad_u."""

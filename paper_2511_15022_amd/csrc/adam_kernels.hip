@@ -9,14 +9,6 @@
 
 namespace cgh {
 
-__device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, float lr_scaled,
-                                         float b1, float b2, float eps, float inv_sqrt_bc2) {
-  m = fmaf(b1, m, (1.0f - b1) * g);
-  v = fmaf(b2, v, (1.0f - b2) * g * g);
-  const float denom = sqrtf(v) * inv_sqrt_bc2 + eps;
-  p -= lr_scaled * m / denom;
-}
-
 // lr_scaled = lr / (1 - b1^t) (uniform), or per parameter block when
 // group_lr != nullptr (six blocks of the layout mean, scale, rotation,
 // amplitude, phase, opacity with sizes 2n, 2n, n, Cn, Cn, n).

@@ -196,13 +196,16 @@ size_t carve(Ctx *c, char *base) {
   c->tw_x = (float2 *)take(sizeof(float2) * kTwTable);
   c->tw_y = (float2 *)take(sizeof(float2) * kTwTable);
   c->tw_m = (float2 *)take(sizeof(float2) * kTwTable);
-  c->twf_x = (float2 *)take(sizeof(float2) * c->Wp);
+  // full tables of Wp and Hp entries, each followed (when its length is a
+  // multiple of 4) by the contiguous table of the quarter length, the twiddles
+  // of the four-chain row and column passes
+  c->twf_x = (float2 *)take(sizeof(float2) * (c->Wp + (c->Wp % 4 ? 0 : c->Wp / 4)));
   c->twf_m = (float2 *)take(sizeof(float2) * c->plan_m.n);
   c->htab = (float2 *)take(sizeof(float2) * c->CF * c->L * (size_t)c->Hq * c->Wq);
   const bool wave_cols = col_wave4(*c);
   c->htab_t = wave_cols ? (float2 *)take(sizeof(float2) * c->CF * c->L * (size_t)c->Hq * c->Wq)
                         : nullptr;
-  c->twf_y = wave_cols ? (float2 *)take(sizeof(float2) * c->Hp) : nullptr;
+  c->twf_y = wave_cols ? (float2 *)take(sizeof(float2) * (c->Hp + c->Hp / 4)) : nullptr;
   const size_t spec_len = (size_t)c->CF * c->Wt * c->H * 8;
   c->spec = (float2 *)take(sizeof(float2) * spec_len);
   // with several planes the shared row spectrum stays in spec; each plane's
@@ -223,7 +226,9 @@ size_t carve(Ctx *c, char *base) {
   c->ranges = (uint2 *)take(sizeof(uint2) * c->num_tiles);
   c->hist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)c->sort_blocks);
   const size_t scan_len = std::max(N + 1, (size_t)256 * c->sort_blocks);
-  c->scan_tmp = (uint32_t *)take(sizeof(uint32_t) * (scan_len / kScanItems + 2));
+  // chunk sums: per kScanItems of a scan, or per preprocess workgroup (256 Gaussians)
+  c->scan_tmp = (uint32_t *)take(sizeof(uint32_t) *
+                                 std::max(scan_len / kScanItems + 2, (N + 255) / 256 + 2));
   c->partials = (float *)take(sizeof(float) * c->part_stride * cap);
   const int rg = row_group_rows(*c);  // one loss partial per row-pass workgroup
   c->loss_part = (double *)take(sizeof(double) * c->L * c->CF * (size_t)((c->H + rg - 1) / rg));
@@ -292,8 +297,13 @@ cgh_status cgh::create_into(const cgh_config *cfg, void *workspace, size_t works
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_y, c.Hp, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles(c.tw_m, c.plan_m.n, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_x, c.Wp, s), "twiddles");
+  if (c.Wp % 4 == 0)
+    CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_x + c.Wp, c.Wp / 4, s), "twiddles");
   CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_m, c.plan_m.n, s), "twiddles");
-  if (c.twf_y) CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_y, c.Hp, s), "twiddles");
+  if (c.twf_y) {
+    CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_y, c.Hp, s), "twiddles");
+    CGH_CHECK_LAUNCH(cgh::launch_build_twiddles_full(c.twf_y + c.Hp, c.Hp / 4, s), "twiddles");
+  }
   CGH_CHECK_LAUNCH(cgh::launch_build_transfer(c, 0, c.B, s), "transfer function");
   CGH_CHECK_LAUNCH(cgh::launch_zero_record(c, s), "zero record");
   CGH_CHECK_LAUNCH(cgh::launch_zero_status(c, s), "zero status");
@@ -413,14 +423,15 @@ static cgh_status plane_adjoint(Ctx &c, int l, hipStream_t s) {
 
 // rasterizer adjoint: tile stage, then the FP64 per-Gaussian stage
 static cgh_status raster_adjoint(Ctx &c, const float *params, int n, const float2 *gf,
-                                 float *grads, hipStream_t s) {
+                                 float *grads, hipStream_t s,
+                                 const cgh::AdamFuse *adam = nullptr) {
   {
     ProfScope p(c, CGH_KERNEL_RASTER_ADJOINT, s);
     CGH_CHECK_LAUNCH(cgh::launch_raster_adjoint(c, gf, s), "raster adjoint");
   }
   {
     ProfScope p(c, CGH_KERNEL_PREPROCESS_ADJOINT, s);
-    CGH_CHECK_LAUNCH(cgh::launch_preprocess_adjoint(c, params, n, grads, s),
+    CGH_CHECK_LAUNCH(cgh::launch_preprocess_adjoint(c, params, n, grads, s, adam),
                      "preprocess adjoint");
   }
   return CGH_OK;
@@ -459,14 +470,14 @@ cgh_status cgh_propagate(cgh_ctx *ctx, const cgh_c64 *field, float *intensity,
 static cgh_status backward_impl(cgh_ctx *ctx, const float *params, int32_t n,
                                 const cgh_c64 *field, const float *target, const float *mask,
                                 double *loss, cgh_c64 *grad_field, float *grads,
-                                void *stream) {
+                                void *stream, const cgh::AdamFuse *adam = nullptr) {
   if (!ctx) return fail(CGH_ERR_INVALID_ARG, "ctx is NULL");
   Ctx &c = ctx->c;
   cgh_status st = check_n(c, n);
   if (st != CGH_OK) return st;
   if (n != c.last_n)
     return fail(CGH_ERR_STATE, "backward with n = %d after rasterize with n = %d", n, c.last_n);
-  if (!field || !target || (n > 0 && (!params || !grads)))
+  if (!field || !target || (n > 0 && (!params || (!grads && !adam))))
     return fail(CGH_ERR_INVALID_ARG, "field/target/params/grads is NULL");
   if (!aligned16(field) || !aligned16(grad_field) || ((uintptr_t)loss & 7u))
     return fail(CGH_ERR_INVALID_ARG, "misaligned buffer");
@@ -492,13 +503,43 @@ static cgh_status backward_impl(cgh_ctx *ctx, const float *params, int32_t n,
   }
   st = adjoint_rows(c, gf, s);
   if (st != CGH_OK) return st;
-  return raster_adjoint(c, params, n, gf, grads, s);
+  return raster_adjoint(c, params, n, gf, grads, s, adam);
+}
+
+// checks of the Adam arguments shared by cgh_step and cgh_backward_step; fills
+// the step's scalars
+static cgh_status adam_scalars(int32_t t, float lr, float beta1, float beta2, float eps,
+                               float *lr_scaled, float *inv_sqrt_bc2) {
+  if (t < 1) return fail(CGH_ERR_INVALID_ARG, "step number t must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+    return fail(CGH_ERR_INVALID_ARG, "betas must be in [0, 1) and eps >= 0");
+  const double bc1 = 1.0 - std::pow((double)beta1, (double)t);
+  const double bc2 = 1.0 - std::pow((double)beta2, (double)t);
+  *lr_scaled = (float)(1.0 / bc1);
+  *inv_sqrt_bc2 = (float)(1.0 / std::sqrt(bc2));
+  return CGH_OK;
 }
 
 cgh_status cgh_backward(cgh_ctx *ctx, const float *params, int32_t n, const cgh_c64 *field,
                         const float *target, double *loss, cgh_c64 *grad_field, float *grads,
                         void *stream) {
   return backward_impl(ctx, params, n, field, target, nullptr, loss, grad_field, grads, stream);
+}
+
+cgh_status cgh_backward_step(cgh_ctx *ctx, float *params, int32_t n, const cgh_c64 *field,
+                             const float *target, double *loss, cgh_c64 *grad_field,
+                             float *grads, float *m, float *v, int32_t t, float lr, float beta1,
+                             float beta2, float eps, void *stream) {
+  if (n > 0 && (!m || !v)) return fail(CGH_ERR_INVALID_ARG, "m/v is NULL");
+  if (!aligned16(params) || !aligned16(grads) || !aligned16(m) || !aligned16(v))
+    return fail(CGH_ERR_INVALID_ARG, "buffers must be 16-byte aligned");
+  float scale = 0.f, isb = 0.f;
+  cgh_status st = adam_scalars(t, lr, beta1, beta2, eps, &scale, &isb);
+  if (st != CGH_OK) return st;
+  // the same FP32 scalars as cgh_step: lr_scaled = lr * (1 / (1 - b1^t))
+  const cgh::AdamFuse adam{params, m, v, lr * scale, beta1, beta2, eps, isb};
+  return backward_impl(ctx, params, n, field, target, nullptr, loss, grad_field, grads, stream,
+                       &adam);
 }
 
 cgh_status cgh_backward_recon(cgh_ctx *ctx, const float *params, int32_t n,
@@ -663,9 +704,9 @@ cgh_status cgh_step(float *params, const float *grads, float *m, float *v, int64
   if (!params || !grads || !m || !v) return fail(CGH_ERR_INVALID_ARG, "NULL buffer");
   if (!aligned16(params) || !aligned16(grads) || !aligned16(m) || !aligned16(v))
     return fail(CGH_ERR_INVALID_ARG, "buffers must be 16-byte aligned");
-  if (t < 1) return fail(CGH_ERR_INVALID_ARG, "step number t must be >= 1");
-  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
-    return fail(CGH_ERR_INVALID_ARG, "betas must be in [0, 1) and eps >= 0");
+  float scale = 0.f, isb = 0.f;
+  cgh_status st = adam_scalars(t, lr, beta1, beta2, eps, &scale, &isb);
+  if (st != CGH_OK) return st;
   int n = 0;
   if (lr_groups) {
     if (channels < 1 || channels > CGH_MAX_CHANNELS)
@@ -674,11 +715,8 @@ cgh_status cgh_step(float *params, const float *grads, float *m, float *v, int64
     if (count % per) return fail(CGH_ERR_INVALID_ARG, "count not a multiple of 6 + 2C");
     n = (int)(count / per);
   }
-  const double bc1 = 1.0 - std::pow((double)beta1, (double)t);
-  const double bc2 = 1.0 - std::pow((double)beta2, (double)t);
-  CGH_CHECK_LAUNCH(cgh::launch_adam(params, grads, m, v, count, lr, (float)(1.0 / bc1), beta1,
-                                    beta2, eps, (float)(1.0 / std::sqrt(bc2)), lr_groups, n,
-                                    channels, (hipStream_t)stream),
+  CGH_CHECK_LAUNCH(cgh::launch_adam(params, grads, m, v, count, lr, scale, beta1, beta2, eps,
+                                    isb, lr_groups, n, channels, (hipStream_t)stream),
                    "adam");
   return CGH_OK;
 }
@@ -793,10 +831,9 @@ cgh_status record_solve(cgh_ctx *ctx, float *params, int32_t n, const float *tar
   for (int32_t t = 1; t <= steps; ++t) {
     cgh_status st = cgh_rasterize(ctx, params, n, field, s);
     if (st == CGH_OK)
-      st = cgh_backward(ctx, params, n, field, target,
-                        loss_log + 2 * (int64_t)ctx->c.B * (t - 1), nullptr, grads, s);
-    if (st == CGH_OK)
-      st = cgh_step(params, grads, m, v, count, t, lr, beta1, beta2, eps, nullptr, ctx->c.C, s);
+      st = cgh_backward_step(ctx, params, n, field, target,
+                             loss_log + 2 * (int64_t)ctx->c.B * (t - 1), nullptr,
+                             t == steps ? grads : nullptr, m, v, t, lr, beta1, beta2, eps, s);
     if (st != CGH_OK) return st;
   }
   return CGH_OK;

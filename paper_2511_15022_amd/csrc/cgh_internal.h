@@ -68,6 +68,24 @@ inline int rec_ext(int C) { return ((R_AMP + 2 * C) + 3) & ~3; }
 inline int rec_stride(int C) { return rec_ext(C) + 4; }
 inline int partial_stride(int C) { return ((2 * C + 5) + 3) & ~3; }
 
+// One Adam update (Kingma & Ba, Algorithm 1) of a parameter p with gradient g:
+// lr_scaled = lr / (1 - b1^t), inv_sqrt_bc2 = 1 / sqrt(1 - b2^t).
+__device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, float lr_scaled,
+                                         float b1, float b2, float eps, float inv_sqrt_bc2) {
+  m = fmaf(b1, m, (1.0f - b1) * g);
+  v = fmaf(b2, v, (1.0f - b2) * g * g);
+  const float denom = sqrtf(v) * inv_sqrt_bc2 + eps;
+  p -= lr_scaled * m / denom;
+}
+
+// Adam applied by the preprocess adjoint as it produces each Gaussian's
+// gradients (cgh_backward_step): the parameters p and moments m, v in the
+// parameter layout, with the step's scalars.
+struct AdamFuse {
+  float *p, *m, *v;
+  float lr_scaled, b1, b2, eps, inv_sqrt_bc2;
+};
+
 // Bits of the sticky non-finite word (status[3]) of a CGH_CHECK_FINITE context.
 constexpr uint32_t kNonFiniteParams = 1u, kNonFiniteGrads = 2u, kNonFiniteLoss = 4u;
 
@@ -187,8 +205,9 @@ hipError_t launch_zero_status(const Ctx &c, hipStream_t s);
 hipError_t launch_binning(Ctx &c, int n, hipStream_t s);  // sets c.sorted
 hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s);
 hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStream_t s);
+// grads may be null when adam is given (the fused Adam step)
 hipError_t launch_preprocess_adjoint(const Ctx &c, const float *params, int n, float *grads,
-                                     hipStream_t s);
+                                     hipStream_t s, const AdamFuse *adam = nullptr);
 
 hipError_t launch_adan(float *p, const float *g, float *m, float *d, float *s, float *gprev,
                        int64_t count, int t, float lr, float b1, float b2, float b3, float eps,

@@ -649,14 +649,15 @@ __device__ __forceinline__ int quarter_row(int b, int rows) {
   return (b & ~15) + 2 * (b & 7) + ((b >> 3) & 1);
 }
 
-// M-entry table exp(-2 pi i e / M) = every fourth entry of the Wp table
+// M-entry table exp(-2 pi i e / M) (every fourth entry of the Wp = 4 M table),
+// stored contiguously after that table
 template <int M, int T>
 __device__ __forceinline__ void load_quarter_table(float2 *tw, const float2 *__restrict__ twf_x,
                                                    int tid) {
   constexpr int KT = (M + T - 1) / T;
   float2 tv[KT];
 #pragma unroll
-  for (int k = 0; k < KT; ++k) tv[k] = at32(twf_x, 4 * min(tid + k * T, M - 1));
+  for (int k = 0; k < KT; ++k) tv[k] = at32(twf_x, 4 * M + min(tid + k * T, M - 1));
 #pragma unroll
   for (int k = 0; k < KT; ++k)
     if (KT * T == M || tid + k * T < M) tw[tid + k * T] = tv[k];
@@ -1269,7 +1270,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       w1[k] = at32(twf_y, n);
     }
 #pragma unroll
-    for (int k = 0; k < KT; ++k) tv[k] = at32(twf_y, 4 * min(tid + k * T, M - 1));  // w_M^k
+    for (int k = 0; k < KT; ++k) tv[k] = at32(twf_y, 4 * M + min(tid + k * T, M - 1));  // w_M^k
 #pragma unroll
     for (int k = 0; k < KT; ++k)
       if (tid + k * T < M) tw[tid + k * T] = tv[k];

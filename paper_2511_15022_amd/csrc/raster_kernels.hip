@@ -36,11 +36,18 @@ constexpr int rec_stride_c(int C) { return rec_ext_c(C) + 4; }
 constexpr int part_stride_c(int C) { return ((2 * C + 5) + 3) & ~3; }
 
 // ----------------------------------------------------------------------------
-// Preprocess (FP64): supplementary "Parameter Activation Functions",
-// "2D Covariance Matrix Computation", "2D Covariance Matrix Inversion".
+// Preprocess: supplementary "Parameter Activation Functions", "2D Covariance
+// Matrix Computation", "2D Covariance Matrix Inversion".  The mean's
+// activation runs in FP64 (its fraction of a pixel is stored, and FP32 would
+// round a position near x = 1920 to 1.2e-4 px); the rest in FP32.  Sigma is
+// R diag(l0, l1) R^T with l0 = s_x^2 + eps_Sigma, l1 = s_y^2 + eps_Sigma (the
+// regularised covariance), so its inverse is R diag(1 / l0, 1 / l1) R^T, with
+// no cancellation however elongated the Gaussian, and det = l0 l1 >= 0.0121:
+// the determinant clamp never applies.
 // ----------------------------------------------------------------------------
 struct Geom {
-  double mx, my, sx, sy, ct, st, s00, s01, s11, det, dsafe, i00, i01, i11, alpha;
+  double mx, my;
+  float sx, sy, ct, st, s00, s01, s11, i00, i01, i11, alpha;
 };
 
 __device__ __forceinline__ Geom geometry(const float *__restrict__ params, int n, int C, int g,
@@ -52,19 +59,19 @@ __device__ __forceinline__ Geom geometry(const float *__restrict__ params, int n
   Geom q;
   q.mx = 0.5 * (tanh((double)mp[2 * g]) + 1.0) * (double)W;
   q.my = 0.5 * (tanh((double)mp[2 * g + 1]) + 1.0) * (double)H;
-  q.sx = exp((double)ls[2 * g]) + 0.1;
-  q.sy = exp((double)ls[2 * g + 1]) + 0.1;
-  sincos((double)rot[g], &q.st, &q.ct);
-  const double sx2 = q.sx * q.sx, sy2 = q.sy * q.sy;
-  q.s00 = sx2 * q.ct * q.ct + sy2 * q.st * q.st + 0.1;
-  q.s01 = (sx2 - sy2) * q.ct * q.st;
-  q.s11 = sx2 * q.st * q.st + sy2 * q.ct * q.ct + 0.1;
-  q.det = q.s00 * q.s11 - q.s01 * q.s01;
-  q.dsafe = q.det > 1e-10 ? q.det : 1e-10;
-  q.i00 = q.s11 / q.dsafe;
-  q.i01 = -q.s01 / q.dsafe;
-  q.i11 = q.s00 / q.dsafe;
-  q.alpha = 1.0 / (1.0 + exp(-(double)op[g]));
+  q.sx = expf(ls[2 * g]) + 0.1f;
+  q.sy = expf(ls[2 * g + 1]) + 0.1f;
+  sincosf(rot[g], &q.st, &q.ct);
+  const float c = q.ct, s = q.st;
+  const float sx2 = q.sx * q.sx, sy2 = q.sy * q.sy;
+  q.s00 = sx2 * c * c + sy2 * s * s + 0.1f;
+  q.s01 = (sx2 - sy2) * c * s;
+  q.s11 = sx2 * s * s + sy2 * c * c + 0.1f;
+  const float e0 = 1.0f / (sx2 + 0.1f), e1 = 1.0f / (sy2 + 0.1f);
+  q.i00 = c * c * e0 + s * s * e1;
+  q.i01 = c * s * (e0 - e1);
+  q.i11 = s * s * e0 + c * c * e1;
+  q.alpha = 1.0f / (1.0f + expf(-op[g]));
   return q;
 }
 
@@ -97,121 +104,7 @@ __device__ __forceinline__ GaussIdx gauss_idx(int g, int n) {
   return r;
 }
 
-// tile shape: (1 << tlx) x (1 << tly) pixels
-template <int C>
-__global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ params_all, int n,
-                                                    int total, int W, int H, float k, int tlx,
-                                                    int tly, float *__restrict__ rec,
-                                                    uint2 *__restrict__ rect,
-                                                    uint32_t *__restrict__ counts, float thr,
-                                                    float2 *__restrict__ alim,
-                                                    uint32_t *__restrict__ finite_flag) {
-  constexpr int RS = rec_stride_c(C);
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const GaussIdx gi = gauss_idx<C>(g, n);
-  const float *params = params_all + gi.base;
-  if (finite_flag && !params_finite<C>(params, n, gi.gl)) atomicOr(finite_flag, kNonFiniteParams);
-  const Geom q = geometry(params, n, C, gi.gl, W, H);
-  const float *amp = params + 5 * (size_t)n + (size_t)gi.gl * C;
-  const float *ph = params + (size_t)(5 + C) * n + (size_t)gi.gl * C;
-  float r[RS];
-#pragma unroll
-  for (int i = 0; i < RS; ++i) r[i] = 0.f;
-  const double fx = floor(q.mx), fy = floor(q.my);
-  r[R_MIX] = __int_as_float((int)fx);
-  r[R_MIY] = __int_as_float((int)fy);
-  r[R_MFX] = (float)(q.mx - fx);
-  r[R_MFY] = (float)(q.my - fy);
-  r[R_A] = (float)(-0.5 * kLog2e * q.i00);
-  r[R_B] = (float)(-kLog2e * q.i01);
-  r[R_C] = (float)(-0.5 * kLog2e * q.i11);
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    double s, co;
-    sincos((double)ph[c], &s, &co);
-    const double a = q.alpha * (double)amp[c];
-    r[R_AMP + 2 * c] = (float)(a * co);
-    r[R_AMP + 2 * c + 1] = (float)(a * s);
-  }
-  // support box (k sqrt(Sigma00), k sqrt(Sigma11)) -> inclusive pixel range
-  uint32_t cnt = 0;
-  uint2 rc = make_uint2(0u, 0u);
-  double i0, i1, j0, j1;
-  if (k > 0.f) {
-    const double rx = (double)k * sqrt(q.s00), ry = (double)k * sqrt(q.s11);
-    r[R_RX] = (float)rx;
-    r[R_RY] = (float)ry;
-    const double pad = 1e-3;  // keeps every pixel the FP32 predicate could accept
-    i0 = fmax(0.0, ceil(q.mx - rx - pad));
-    i1 = fmin((double)(W - 1), floor(q.mx + rx + pad));
-    j0 = fmax(0.0, ceil(q.my - ry - pad));
-    j1 = fmin((double)(H - 1), floor(q.my + ry + pad));
-  } else {
-    r[R_RX] = 1e30f;
-    r[R_RY] = 1e30f;
-    i0 = 0; i1 = W - 1; j0 = 0; j1 = H - 1;
-  }
-  if (i0 <= i1 && j0 <= j1) {
-    const uint32_t tx0 = (uint32_t)i0 >> tlx, tx1 = (uint32_t)i1 >> tlx;
-    const uint32_t ty0 = (uint32_t)j0 >> tly, ty1 = (uint32_t)j1 >> tly;
-    cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-    rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
-  }
-  // row form of the exponent (completing the square in dx):
-  //   i00 dx^2 + 2 i01 dx dy + i11 dy^2 = i00 (dx - s dy)^2 + (i11 - i01^2 / i00) dy^2
-  r[rec_ext_c(C) + RX_S] = (float)(-q.i01 / q.i00);
-  r[rec_ext_c(C) + RX_KAPPA] = (float)(-0.5 * kLog2e * (q.i11 - q.i01 * q.i01 / q.i00));
-  r[rec_ext_c(C) + RX_RA] = (float)sqrt(0.5 * kLog2e * q.i00);
-  float4 *dst = reinterpret_cast<float4 *>(rec + (size_t)g * RS);
-#pragma unroll
-  for (int i = 0; i < RS / 4; ++i) dst[i] = make_float4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
-  counts[g] = cnt;
-  rect[g] = rc;
-  if (alim) {
-    // Alg. 2 weight w = min(0.99, alpha G), kept where alpha G >= 1/255: in the
-    // exponent p = log2 G, kept for p >= max(support threshold, log2(1/(255 alpha)))
-    // and clamped at log2(0.99 / alpha)
-    const double lo = log2(1.0 / (255.0 * q.alpha)), hi = log2(0.99 / q.alpha);
-    alim[g] = make_float2(fmaxf(thr, (float)lo), (float)hi);
-  }
-}
-
-static float support_threshold(float k) {
-  // log2 G >= -k^2/2 log2(e)  <=>  q <= k^2 ; k <= 0: everything
-  if (k <= 0.f) return -INFINITY;
-  return (float)(-0.5 * (double)k * (double)k * kLog2e);
-}
-
-static int log2i(int v) {
-  int r = 0;
-  while ((1 << r) < v) ++r;
-  return r;
-}
-
-hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s) {
-  const int total = (int)total_gaussians(c, n);
-  if (total <= 0) return hipSuccess;
-  dim3 grid((total + 255) / 256), block(256);
-  const float k = c.cfg.support_sigma, thr = support_threshold(k);
-  const int tlx = log2i(c.tile_w), tly = log2i(c.tile_h);
-#define CGH_PRE(CC)                                                                           \
-  hipLaunchKernelGGL(k_preprocess<CC>, grid, block, 0, s, params, n, total, c.W, c.H, k, tlx, \
-                     tly, c.rec, c.rect, c.counts, thr, c.alim, c.finite_flag)
-  switch (c.C) {
-    case 1: CGH_PRE(1); break;
-    case 2: CGH_PRE(2); break;
-    case 3: CGH_PRE(3); break;
-    default: CGH_PRE(4); break;
-  }
-#undef CGH_PRE
-  return hipGetLastError();
-}
-
-// ----------------------------------------------------------------------------
-// Exclusive scan of u32 (three kernels: per-block scan, scan of block sums,
-// add).
-// ----------------------------------------------------------------------------
+// Scans over one workgroup of 256 threads.
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -237,6 +130,153 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *t
   return off + incl - v;
 }
 
+// Gaussian g of all B n: its record, tile rectangle and tile count (returned);
+// tile shape (1 << tlx) x (1 << tly) pixels
+template <int C>
+__device__ __forceinline__ uint32_t preprocess_one(const float *__restrict__ params_all, int n,
+                                                   int g, int W, int H, float k, int tlx,
+                                                   int tly, float *__restrict__ rec,
+                                                   uint2 *__restrict__ rect,
+                                                   uint32_t *__restrict__ counts, float thr,
+                                                   float2 *__restrict__ alim,
+                                                   uint32_t *__restrict__ finite_flag) {
+  constexpr int RS = rec_stride_c(C);
+  const GaussIdx gi = gauss_idx<C>(g, n);
+  const float *params = params_all + gi.base;
+  if (finite_flag && !params_finite<C>(params, n, gi.gl)) atomicOr(finite_flag, kNonFiniteParams);
+  const Geom q = geometry(params, n, C, gi.gl, W, H);
+  const float *amp = params + 5 * (size_t)n + (size_t)gi.gl * C;
+  const float *ph = params + (size_t)(5 + C) * n + (size_t)gi.gl * C;
+  float r[RS];
+#pragma unroll
+  for (int i = 0; i < RS; ++i) r[i] = 0.f;
+  const double fx = floor(q.mx), fy = floor(q.my);
+  r[R_MIX] = __int_as_float((int)fx);
+  r[R_MIY] = __int_as_float((int)fy);
+  r[R_MFX] = (float)(q.mx - fx);
+  r[R_MFY] = (float)(q.my - fy);
+  constexpr float kL2e = (float)kLog2e;
+  r[R_A] = -0.5f * kL2e * q.i00;
+  r[R_B] = -kL2e * q.i01;
+  r[R_C] = -0.5f * kL2e * q.i11;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    float s, co;
+    sincosf(ph[c], &s, &co);
+    const float a = q.alpha * amp[c];
+    r[R_AMP + 2 * c] = a * co;
+    r[R_AMP + 2 * c + 1] = a * s;
+  }
+  // support box (k sqrt(Sigma00), k sqrt(Sigma11)) -> inclusive pixel range
+  uint32_t cnt = 0;
+  uint2 rc = make_uint2(0u, 0u);
+  double i0, i1, j0, j1;
+  if (k > 0.f) {
+    const float rxf = k * sqrtf(q.s00), ryf = k * sqrtf(q.s11);
+    const double rx = rxf, ry = ryf;
+    r[R_RX] = rxf;
+    r[R_RY] = ryf;
+    const double pad = 1e-3;  // keeps every pixel the FP32 predicate could accept
+    i0 = fmax(0.0, ceil(q.mx - rx - pad));
+    i1 = fmin((double)(W - 1), floor(q.mx + rx + pad));
+    j0 = fmax(0.0, ceil(q.my - ry - pad));
+    j1 = fmin((double)(H - 1), floor(q.my + ry + pad));
+  } else {
+    r[R_RX] = 1e30f;
+    r[R_RY] = 1e30f;
+    i0 = 0; i1 = W - 1; j0 = 0; j1 = H - 1;
+  }
+  if (i0 <= i1 && j0 <= j1) {
+    const uint32_t tx0 = (uint32_t)i0 >> tlx, tx1 = (uint32_t)i1 >> tlx;
+    const uint32_t ty0 = (uint32_t)j0 >> tly, ty1 = (uint32_t)j1 >> tly;
+    cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+  }
+  // row form of the exponent (completing the square in dx):
+  //   i00 dx^2 + 2 i01 dx dy + i11 dy^2 = i00 (dx - s dy)^2 + dy^2 / Sigma11,
+  //   s = -i01 / i00 = Sigma01 / Sigma11
+  r[rec_ext_c(C) + RX_S] = q.s01 / q.s11;
+  r[rec_ext_c(C) + RX_KAPPA] = -0.5f * kL2e / q.s11;
+  r[rec_ext_c(C) + RX_RA] = sqrtf(0.5f * kL2e * q.i00);
+  float4 *dst = reinterpret_cast<float4 *>(rec + (size_t)g * RS);
+#pragma unroll
+  for (int i = 0; i < RS / 4; ++i) dst[i] = make_float4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
+  counts[g] = cnt;
+  rect[g] = rc;
+  if (alim) {
+    // Alg. 2 weight w = min(0.99, alpha G), kept where alpha G >= 1/255: in the
+    // exponent p = log2 G, kept for p >= max(support threshold, log2(1/(255 alpha)))
+    // and clamped at log2(0.99 / alpha)
+    const float lo = -log2f(255.0f * q.alpha), hi = log2f(0.99f / q.alpha);
+    alim[g] = make_float2(fmaxf(thr, lo), hi);
+  }
+  return cnt;
+}
+
+// The preprocess of 256 Gaussians per workgroup, which also starts the
+// binning: the workgroup's exclusive scan of its tile counts goes to
+// offsets[g] and its total to chunk_sums[workgroup] (the emit adds the totals
+// of the workgroups before its own), and workgroup 0 clears the overflow flag
+// of this rasterize (*overflow).
+template <int C>
+__global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ params_all, int n,
+                                                    int total, int W, int H, float k, int tlx,
+                                                    int tly, float *__restrict__ rec,
+                                                    uint2 *__restrict__ rect,
+                                                    uint32_t *__restrict__ counts, float thr,
+                                                    float2 *__restrict__ alim,
+                                                    uint32_t *__restrict__ finite_flag,
+                                                    uint32_t *__restrict__ offsets,
+                                                    uint32_t *__restrict__ chunk_sums,
+                                                    uint32_t *__restrict__ overflow) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t cnt = 0;
+  if (g < total)
+    cnt = preprocess_one<C>(params_all, n, g, W, H, k, tlx, tly, rec, rect, counts, thr, alim,
+                            finite_flag);
+  uint32_t sum;
+  const uint32_t pre = block_exclusive_scan(cnt, &sum);  // every thread takes part
+  if (g < total) offsets[g] = pre;
+  if (threadIdx.x == 0) chunk_sums[blockIdx.x] = sum;
+  if (g == 0) *overflow = 0u;
+}
+
+static float support_threshold(float k) {
+  // log2 G >= -k^2/2 log2(e)  <=>  q <= k^2 ; k <= 0: everything
+  if (k <= 0.f) return -INFINITY;
+  return (float)(-0.5 * (double)k * (double)k * kLog2e);
+}
+
+static int log2i(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream_t s) {
+  const int total = (int)total_gaussians(c, n);
+  if (total <= 0) return hipSuccess;
+  dim3 grid((total + 255) / 256), block(256);
+  const float k = c.cfg.support_sigma, thr = support_threshold(k);
+  const int tlx = log2i(c.tile_w), tly = log2i(c.tile_h);
+#define CGH_PRE(CC)                                                                           \
+  hipLaunchKernelGGL(k_preprocess<CC>, grid, block, 0, s, params, n, total, c.W, c.H, k, tlx, \
+                     tly, c.rec, c.rect, c.counts, thr, c.alim, c.finite_flag, c.offsets,     \
+                     c.scan_tmp, c.status)
+  switch (c.C) {
+    case 1: CGH_PRE(1); break;
+    case 2: CGH_PRE(2); break;
+    case 3: CGH_PRE(3); break;
+    default: CGH_PRE(4); break;
+  }
+#undef CGH_PRE
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Exclusive scan of u32 (three kernels: per-block scan, scan of block sums,
+// add).
+// ----------------------------------------------------------------------------
 // per-block exclusive scans of kScanItems elements and the block sums; also
 // clears *zero_word (if given), which lets the binning skip a launch
 __global__ __launch_bounds__(256) void k_scan_local(const uint32_t *__restrict__ in,
@@ -305,9 +345,10 @@ static hipError_t scan_u32(const uint32_t *in, uint32_t *out, int len, uint32_t 
 // ----------------------------------------------------------------------------
 // Pairs of Gaussian g go to [offset(g), offset(g) + count(g)) in row-major
 // tile order; the key of tile (tx, ty) of hologram b = g / n_per is
-// b tiles_per + ty tiles_x + tx.  offsets[] holds per-chunk exclusive scans and
-// chunk_sums the (unscanned) chunk totals: each workgroup adds the totals of
-// the chunks before its own, and workgroup 0 writes the grand total to
+// b tiles_per + ty tiles_x + tx.  offsets[] holds the exclusive scans within
+// the preprocess workgroups (256 Gaussians, the same as an emit workgroup's)
+// and chunk_sums their (unscanned) totals: each workgroup adds the totals of
+// the workgroups before its own, and workgroup 0 writes the grand total to
 // offsets[n] and to the pair total status[1]; the final offset is written
 // back for the adjoint.
 __global__ __launch_bounds__(256) void k_emit(int n, int n_per, int tiles_per,
@@ -319,8 +360,7 @@ __global__ __launch_bounds__(256) void k_emit(int n, int n_per, int tiles_per,
                                               uint32_t *__restrict__ keys,
                                               uint32_t *__restrict__ vals,
                                               uint32_t *__restrict__ status) {
-  static_assert(kScanItems % 256 == 0, "a workgroup lies in one scan chunk");
-  const int upto = blockIdx.x == 0 ? nchunks : (int)(blockIdx.x * 256 / kScanItems);
+  const int upto = blockIdx.x == 0 ? nchunks : (int)blockIdx.x;
   uint32_t part = 0;
   for (int k = threadIdx.x; k < upto; k += 256) part += chunk_sums[k];
   uint32_t total;
@@ -564,12 +604,12 @@ hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
   // kernel clears the flag and the emit kernel writes the total
   const int total = (int)total_gaussians(c, n);
   if (total > 0) {
-    const int nb = (total + kScanItems - 1) / kScanItems;
-    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, c.counts, c.offsets, total,
-                       c.scan_tmp, c.status);
-    hipLaunchKernelGGL(k_emit, dim3((total + 255) / 256), dim3(256), 0, s, total, n, c.tiles_per,
-                       c.counts, c.offsets, c.scan_tmp, nb, c.rect, c.tiles_x, c.pair_cap,
-                       c.keys[0], c.vals[0], c.status);
+    // the preprocess has scanned the counts per workgroup of 256 and cleared
+    // the overflow flag
+    const int nb = (total + 255) / 256;
+    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, total, n, c.tiles_per, c.counts,
+                       c.offsets, c.scan_tmp, nb, c.rect, c.tiles_x, c.pair_cap, c.keys[0],
+                       c.vals[0], c.status);
   } else {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c.status, 2);
   }
@@ -1364,23 +1404,23 @@ __global__ __launch_bounds__(64) void k_raster_adj(
 //   inv = adj(Sigma) / eps_d
 //   Sigma -> (s_x, s_y, theta) and s = exp(s~) + eps_s.
 // ----------------------------------------------------------------------------
+// The 6 + 2C gradients of Gaussian gg (of all B n) in the order mean (2),
+// log-scale (2), rotation, amplitude (C), phase (C), opacity, from its pair
+// partials and its parameters.
 template <int C, bool PA>
-__global__ __launch_bounds__(256) void k_preprocess_adj(
-    const float *__restrict__ params_all, int n, int total, int W, int H,
-    const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets, int64_t cap,
-    const float *__restrict__ partials, float *__restrict__ grads_all,
-    uint32_t *__restrict__ finite_flag) {
+__device__ __forceinline__ void gaussian_grads(const float *params_all, int n, int W, int H, int gg,
+                                               const uint32_t *__restrict__ counts,
+                                               const uint32_t *__restrict__ offsets, int64_t cap,
+                                               const float *__restrict__ partials,
+                                               float (&gv)[6 + 2 * C]) {
   constexpr int PS = part_stride_c(C);
   // the 2C + 5 partial sums, plus the clamped-pixel sum with CGH_PAPER_ALPHA
   constexpr int NP = 2 * C + 5 + (PA ? 1 : 0);
   static_assert(NP <= PS, "spare partial slot");
-  const int gg = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gg >= total) return;
   // partial slots are indexed by the Gaussian's index among all B n; its
-  // parameters and gradients by its index g in its hologram's block
+  // parameters by its index g in its hologram's block
   const GaussIdx gi = gauss_idx<C>(gg, n);
   const float *params = params_all + gi.base;
-  float *grads = grads_all + gi.base;
   const int g = gi.gl;
   double S[NP];
 #pragma unroll
@@ -1412,63 +1452,148 @@ __global__ __launch_bounds__(256) void k_preprocess_adj(
   }
   const float *amp = params + 5 * (size_t)n;
   const float *ph = params + (size_t)(5 + C) * n;
-  float *g_mean = grads;
-  float *g_ls = grads + 2 * (size_t)n;
-  float *g_rot = grads + 4 * (size_t)n;
-  float *g_amp = grads + 5 * (size_t)n;
-  float *g_ph = grads + (size_t)(5 + C) * n;
-  float *g_op = grads + (size_t)(5 + 2 * C) * n;
-  double dalpha = 0.0;
+  // the 6 + 2C gradients of this Gaussian: mean (2), log-scale (2), rotation,
+  // amplitude (C), phase (C), opacity; the sums above are FP64, the chain rule
+  // FP32
+  float gm[2], gs[2], gr, ga[C], gph[C], go;
+  float dalpha = 0.f;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    double sn, cs;
-    sincos((double)ph[(size_t)g * C + c], &sn, &cs);
-    const double cc = amp[(size_t)g * C + c];
-    const double dP = S[2 * c], dQ = S[2 * c + 1];
-    const double proj = cs * dP + sn * dQ;
-    g_amp[(size_t)g * C + c] = (float)(q.alpha * proj);
-    g_ph[(size_t)g * C + c] = (float)(q.alpha * cc * (-sn * dP + cs * dQ));
+    float sn, cs;
+    sincosf(ph[(size_t)g * C + c], &sn, &cs);
+    const float cc = amp[(size_t)g * C + c];
+    const float dP = (float)S[2 * c], dQ = (float)S[2 * c + 1];
+    const float proj = cs * dP + sn * dQ;
+    ga[c] = q.alpha * proj;
+    gph[c] = q.alpha * cc * (-sn * dP + cs * dQ);
     dalpha += cc * proj;
   }
   // pixels where the Alg. 2 clamp is active contribute 0.99 c e^{j phi}, which
   // does not depend on alpha: their part of the amplitude sums comes off here
-  if constexpr (PA) dalpha -= S[2 * C + 5] / q.alpha;
-  g_op[g] = (float)(dalpha * q.alpha * (1.0 - q.alpha));
-  const double W1 = S[2 * C], W2 = S[2 * C + 1], W3 = S[2 * C + 2], W4 = S[2 * C + 3],
-               W5 = S[2 * C + 4];
-  const double dmx = q.i00 * W1 + q.i01 * W2;
-  const double dmy = q.i01 * W1 + q.i11 * W2;
-  const double tx = tanh((double)params[2 * g]), ty = tanh((double)params[2 * g + 1]);
-  g_mean[2 * g] = (float)(dmx * 0.5 * W * (1.0 - tx * tx));
-  g_mean[2 * g + 1] = (float)(dmy * 0.5 * H * (1.0 - ty * ty));
+  if constexpr (PA) dalpha -= (float)S[2 * C + 5] / q.alpha;
+  go = dalpha * q.alpha * (1.0f - q.alpha);
+  const float W1 = (float)S[2 * C], W2 = (float)S[2 * C + 1], W3 = (float)S[2 * C + 2],
+              W4 = (float)S[2 * C + 3], W5 = (float)S[2 * C + 4];
+  const float dmx = q.i00 * W1 + q.i01 * W2;
+  const float dmy = q.i01 * W1 + q.i11 * W2;
+  // d tanh(x) / dx = 1 - tanh^2 x = 4 / (e^x + e^-x)^2, without the cancellation
+  auto sech2 = [](float x) {
+    const float e = expf(-fabsf(x)), d = 1.0f + e * e;
+    return 4.0f * e * e / (d * d);
+  };
+  gm[0] = dmx * 0.5f * (float)W * sech2(params[2 * g]);
+  gm[1] = dmy * 0.5f * (float)H * sech2(params[2 * g + 1]);
   // gradient w.r.t. the stored inverse entries
-  const double g00 = -0.5 * W3, g01 = -W4, g11 = -0.5 * W5;
-  double d00, d01, d11;  // dL/dSigma00, dL/dSigma01 (stored once), dL/dSigma11
-  if (q.det > 1e-10) {
-    // symmetric gradient matrix Gm = [[g00, g01/2], [g01/2, g11]]; M = Sigma^{-1}
-    const double h01 = 0.5 * g01;
-    // T = M Gm
-    const double t00 = q.i00 * g00 + q.i01 * h01, t01 = q.i00 * h01 + q.i01 * g11;
-    const double t10 = q.i01 * g00 + q.i11 * h01, t11 = q.i01 * h01 + q.i11 * g11;
-    // -(T M)
-    d00 = -(t00 * q.i00 + t01 * q.i01);
-    d11 = -(t10 * q.i01 + t11 * q.i11);
-    d01 = -2.0 * (t00 * q.i01 + t01 * q.i11);
-  } else {
-    d00 = g11 / q.dsafe;
-    d11 = g00 / q.dsafe;
-    d01 = -g01 / q.dsafe;
+  const float g00 = -0.5f * W3, g01 = -W4, g11 = -0.5f * W5;
+  // dL/dSigma = -M Gm M with M = Sigma^{-1} and the symmetric gradient matrix
+  // Gm = [[g00, g01/2], [g01/2, g11]] (the stored off-diagonal counted twice)
+  const float h01 = 0.5f * g01;
+  const float t00 = q.i00 * g00 + q.i01 * h01, t01 = q.i00 * h01 + q.i01 * g11;
+  const float t10 = q.i01 * g00 + q.i11 * h01, t11 = q.i01 * h01 + q.i11 * g11;
+  const float d00 = -(t00 * q.i00 + t01 * q.i01);
+  const float d11 = -(t10 * q.i01 + t11 * q.i11);
+  const float d01 = -2.0f * (t00 * q.i01 + t01 * q.i11);
+  const float c = q.ct, s = q.st, sx = q.sx, sy = q.sy;
+  const float dsx = 2.0f * sx * (c * c * d00 + c * s * d01 + s * s * d11);
+  const float dsy = 2.0f * sy * (s * s * d00 - c * s * d01 + c * c * d11);
+  const float dth = 2.0f * (sy * sy - sx * sx) * c * s * d00 +
+                    (sx * sx - sy * sy) * (c * c - s * s) * d01 +
+                    2.0f * (sx * sx - sy * sy) * c * s * d11;
+  gs[0] = dsx * (sx - 0.1f);      // d s / d s~ = exp(s~)
+  gs[1] = dsy * (sy - 0.1f);
+  gr = dth;
+  gv[0] = gm[0]; gv[1] = gm[1]; gv[2] = gs[0]; gv[3] = gs[1]; gv[4] = gr;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    gv[5 + c] = ga[c];
+    gv[5 + C + c] = gph[c];
   }
-  const double c = q.ct, s = q.st, sx = q.sx, sy = q.sy;
-  const double dsx = 2.0 * sx * (c * c * d00 + c * s * d01 + s * s * d11);
-  const double dsy = 2.0 * sy * (s * s * d00 - c * s * d01 + c * c * d11);
-  const double dth = 2.0 * (sy * sy - sx * sx) * c * s * d00 +
-                     (sx * sx - sy * sy) * (c * c - s * s) * d01 +
-                     2.0 * (sx * sx - sy * sy) * c * s * d11;
-  g_ls[2 * g] = (float)(dsx * (sx - 0.1));      // d s / d s~ = exp(s~)
-  g_ls[2 * g + 1] = (float)(dsy * (sy - 0.1));
-  g_rot[g] = (float)dth;
-  if (finite_flag && !params_finite<C>(grads, n, g)) atomicOr(finite_flag, kNonFiniteGrads);
+  gv[5 + 2 * C] = go;
+}
+
+// offset of parameter k (in the order of gaussian_grads) of Gaussian g in its
+// hologram's block
+template <int C>
+__device__ __forceinline__ size_t param_offset(int k, int g, int n) {
+  if (k < 2) return 2 * (size_t)g + k;
+  if (k < 4) return 2 * (size_t)n + 2 * (size_t)g + (k - 2);
+  if (k == 4) return 4 * (size_t)n + g;
+  if (k < 5 + C) return 5 * (size_t)n + (size_t)g * C + (k - 5);
+  if (k < 5 + 2 * C) return (size_t)(5 + C) * n + (size_t)g * C + (k - 5 - C);
+  return (size_t)(5 + 2 * C) * n + g;
+}
+
+template <int C, bool PA>
+__global__ __launch_bounds__(256) void k_preprocess_adj(
+    const float *__restrict__ params_all, int n, int total, int W, int H,
+    const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets, int64_t cap,
+    const float *__restrict__ partials, float *__restrict__ grads_all,
+    uint32_t *__restrict__ finite_flag) {
+  const int gg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gg >= total) return;
+  float gv[6 + 2 * C];
+  gaussian_grads<C, PA>(params_all, n, W, H, gg, counts, offsets, cap, partials, gv);
+  const GaussIdx gi = gauss_idx<C>(gg, n);
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < 6 + 2 * C; ++k) {
+    finite = finite && isfinite(gv[k]);
+    grads_all[gi.base + param_offset<C>(k, gi.gl, n)] = gv[k];
+  }
+  if (finite_flag && !finite) atomicOr(finite_flag, kNonFiniteGrads);
+}
+
+// The same, followed by one Adam update of the workgroup's parameters
+// (cgh_backward_step).  The 256 Gaussians of a workgroup own, in each of the six
+// parameter blocks, one contiguous run (two where the workgroup straddles two
+// holograms); their gradients go through LDS so that the update then walks
+// those runs with consecutive threads on consecutive parameters.  grads_all
+// may be null.
+template <int C, bool PA>
+__global__ __launch_bounds__(256) void k_preprocess_adj_adam(
+    float *params_all, int n, int total, int W, int H,
+    const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets, int64_t cap,
+    const float *__restrict__ partials, float *__restrict__ grads_all,
+    uint32_t *__restrict__ finite_flag, AdamFuse adam) {
+  constexpr int NPAR = 6 + 2 * C;
+  __shared__ float sgv[NPAR][256];
+  const int tid = threadIdx.x;
+  const int g0 = blockIdx.x * 256;
+  const int gg = g0 + tid;
+  if (gg < total) {
+    float gv[NPAR];
+    gaussian_grads<C, PA>(params_all, n, W, H, gg, counts, offsets, cap, partials, gv);
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < NPAR; ++k) {
+      finite = finite && isfinite(gv[k]);
+      sgv[k][tid] = gv[k];
+    }
+    if (finite_flag && !finite) atomicOr(finite_flag, kNonFiniteGrads);
+  }
+  __syncthreads();  // every thread reaches it: no early return above
+  const int cnt = min(256, total - g0);
+  // element e of the workgroup's share of parameter block a (per-Gaussian
+  // width w_a: 2, 2, 1, C, C, 1) is component e % w_a of Gaussian e / w_a
+  int kbase = 0;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    constexpr int wid[6] = {2, 2, 1, C, C, 1};
+    const int w = wid[a];
+    for (int e = tid; e < cnt * w; e += 256) {
+      const int j = e / w, comp = e - j * w;
+      const GaussIdx gi = gauss_idx<C>(g0 + j, n);
+      const size_t o = gi.base + param_offset<C>(kbase + comp, gi.gl, n);
+      const float gk = sgv[kbase + comp][j];
+      float pk = params_all[o], mk = adam.m[o], vk = adam.v[o];
+      adam_one(pk, gk, mk, vk, adam.lr_scaled, adam.b1, adam.b2, adam.eps, adam.inv_sqrt_bc2);
+      params_all[o] = pk;
+      adam.m[o] = mk;
+      adam.v[o] = vk;
+      if (grads_all) grads_all[o] = gk;
+    }
+    kbase += w;
+  }
 }
 
 hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStream_t s) {
@@ -1494,19 +1619,28 @@ hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStre
 }
 
 hipError_t launch_preprocess_adjoint(const Ctx &c, const float *params, int n, float *grads,
-                                     hipStream_t s) {
+                                     hipStream_t s, const AdamFuse *adam) {
   const int total = (int)total_gaussians(c, n);
   if (total <= 0) return hipSuccess;
   dim3 g2((total + 255) / 256), block(256);
   const bool pa = c.alim != nullptr;
   with_channels(c.C, [&](auto cc) {
     constexpr int CC = decltype(cc)::value;
-    auto go = [&](auto kern) {
-      hipLaunchKernelGGL(kern, g2, block, 0, s, params, n, total, c.W, c.H, c.counts, c.offsets,
-                         c.pair_cap, c.partials, grads, c.finite_flag);
-    };
-    if (pa) go(k_preprocess_adj<CC, true>);
-    else go(k_preprocess_adj<CC, false>);
+    if (adam) {
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, g2, block, 0, s, adam->p, n, total, c.W, c.H, c.counts,
+                           c.offsets, c.pair_cap, c.partials, grads, c.finite_flag, *adam);
+      };
+      if (pa) go(k_preprocess_adj_adam<CC, true>);
+      else go(k_preprocess_adj_adam<CC, false>);
+    } else {
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, g2, block, 0, s, params, n, total, c.W, c.H, c.counts,
+                           c.offsets, c.pair_cap, c.partials, grads, c.finite_flag);
+      };
+      if (pa) go(k_preprocess_adj<CC, true>);
+      else go(k_preprocess_adj<CC, false>);
+    }
   });
   return hipGetLastError();
 }

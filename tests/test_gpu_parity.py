@@ -562,6 +562,54 @@ def test_adam_step_matches_oracle(O):
     assert np.max(np.abs(V.cpu().numpy() - vv) / np.maximum(vv, 1e-30)) < 1e-6
 
 
+@pytest.mark.parametrize("case", [
+    dict(H=64, W=96, C=3, n=700, B=1, pa=False),
+    dict(H=48, W=80, C=2, n=400, B=2, pa=False),
+    dict(H=40, W=60, C=1, n=300, B=1, pa=True),
+])
+def test_backward_step_matches_backward_then_step(O, case):
+    """cgh_backward_step (the Adam update fused into the per-Gaussian adjoint
+    stage) against cgh_backward followed by cgh_step: params, moments,
+    gradients, dL/dU0 and loss bitwise equal over three steps, for a batch of
+    holograms and for the Alg. 2 weight."""
+    say("backward_step", case)
+    H, W, C, n, B = case["H"], case["W"], case["C"], case["n"], case["B"]
+    lams = [639e-9, 515e-9, 473e-9][:C]
+    ctx = binding.Context(H, W, C, 8e-6, lams, [3e-3], max_gaussians=n, batch=B,
+                          paper_alpha=case["pa"])
+    P0 = torch.cat([gpu_params(synth.params(30 + b, n, H, W, C)) for b in range(B)])
+    T = torch.from_numpy(np.concatenate([synth.target(40 + b, C, H, W) for b in range(B)])).cuda()
+    runs = []
+    for fused in (False, True):
+        P = P0.clone()
+        M, V = torch.zeros_like(P), torch.zeros_like(P)
+        G = torch.zeros_like(P)
+        loss = torch.zeros(2 * B, dtype=torch.float64, device="cuda")
+        field = torch.empty(ctx.field_shape(), dtype=torch.complex64, device="cuda")
+        gfield = torch.empty_like(field)
+        for t in range(1, 4):
+            ctx.rasterize(P, n, field)
+            if fused:
+                ctx.backward_step(P, n, field, T, M, V, t, 1e-3, loss=loss, grad_field=gfield,
+                                  grads=G)
+            else:
+                ctx.backward(P, n, field, T, loss=loss, grad_field=gfield, grads=G)
+                binding.step(P, G, M, V, t, 1e-3)
+        torch.cuda.synchronize()
+        runs.append([x.clone() for x in (P, M, V, G, gfield, loss)])
+    for a, b, name in zip(runs[0], runs[1], ("params", "m", "v", "grads", "grad_field", "loss")):
+        assert torch.equal(a, b), name
+    # without a gradient buffer the update is the same
+    P = P0.clone()
+    M, V = torch.zeros_like(P), torch.zeros_like(P)
+    field = torch.empty(ctx.field_shape(), dtype=torch.complex64, device="cuda")
+    for t in range(1, 4):
+        ctx.rasterize(P, n, field)
+        ctx.backward_step(P, n, field, T, M, V, t, 1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(P, runs[0][0]) and torch.equal(M, runs[0][1])
+
+
 def test_rgb_1080p_full_size_parity(O):
     """The 1080p RGB workload (414,720 Gaussians, 2160 x 3840 padding) in the
     launch configuration the benchmark times: field at every pixel, loss,
