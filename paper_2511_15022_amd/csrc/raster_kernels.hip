@@ -1100,8 +1100,11 @@ hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
 //   S[2C+2] += w dx^2, S[2C+3] += w dx dy, S[2C+4] += w dy^2   (-> dL/dSigma^{-1})
 // with dx, dy = pixel - mean.  The clamped exponent has zero derivative.
 //
-// Work balance.  One wave owns a tile and takes its pair list in batches of
-// 64.  Each pair's pixel box is cut into segments of 8 pixels (the last one
+// Work balance.  A workgroup of three waves owns a tile: the tile's dL/dU0 is
+// staged in LDS once, the pair list is cut into three equal parts, and each
+// wave takes its part in batches of 64 with a pair table of its own in LDS
+// (three waves per tile rather than one keep more waves resident per CU,
+// since the staged tile is shared).  Each pair's pixel box is cut into segments of 8 pixels (the last one
 // padded), the segments of a batch are laid end to end, and the segment range
 // is cut into 64 equal contiguous pieces, one per lane, so every lane walks
 // the same number of pixels whatever the mix of box sizes.  A lane can move to
@@ -1113,7 +1116,8 @@ hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
 // depend only on the box areas, so the result is bitwise reproducible.
 // ----------------------------------------------------------------------------
 constexpr int kAdjBatch = 64;
-constexpr int kAdjSeg = 8;  // pixels per segment
+constexpr int kAdjSeg = 8;    // pixels per segment
+constexpr int kAdjWaves = 3;  // waves per tile; wave w takes part w of kAdjWaves of the list
 
 // per-pair quantities kept in LDS for the walk (floats):
 //   0-1 offx, offy (tile origin - floor(mean) - frac(mean))
@@ -1133,7 +1137,7 @@ template <int C, bool PA> struct AdjQ {
 // the sum of G gp over the pixels where the 0.99 clamp is active (their
 // weight does not depend on alpha), in the slot that the stride leaves spare.
 template <int C, bool CLAMP, bool PA, int TW, int TH>
-__global__ __launch_bounds__(64) void k_raster_adj(
+__global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
     const float *__restrict__ rec, const uint32_t *__restrict__ vals,
     const uint2 *__restrict__ ranges, const uint2 *__restrict__ rect,
     const uint32_t *__restrict__ offsets, int W, int H, int tiles_x, int tiles_per, float thr,
@@ -1149,34 +1153,48 @@ __global__ __launch_bounds__(64) void k_raster_adj(
   // dL/dU0 of the tile, plus one row of zeros (row TH) that the padding
   // pixels of a pair's last segment read when they run past the tile's last row
   __shared__ float2 sg[(TH + 1) * TW][C];
-  __shared__ float4 sq4[kAdjBatch * Q::N / 4];
-  float *sq = reinterpret_cast<float *>(sq4);
-  const int lane = threadIdx.x;
+  __shared__ float4 sq4[kAdjWaves][kAdjBatch * Q::N / 4];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // each wave's own pair table: after the tile's dL/dU0 is staged, the waves
+  // share nothing, and a wave's LDS operations execute in issue order
+  float *sq = reinterpret_cast<float *>(sq4[wave]);
+  auto wave_sync = [] {
+    if constexpr (kAdjWaves == 1) __syncthreads();
+    else asm volatile("" ::: "memory");
+  };
   const int tile = blockIdx.x;
   const int hb = tile / tiles_per, ltile = tile - hb * tiles_per;  // hologram, its tile
   const float2 *gfield = gfield_all + (size_t)hb * C * H * W;
   const int tx = ltile % tiles_x, ty = ltile / tiles_x;
   const int X0 = tx * TW, Y0 = ty * TH;
   {
-    // all C TP / 64 loads of a lane are issued before the first is stored
-    constexpr int K = C * TP / 64;
+    // all loads of a thread are issued before the first is stored
+    constexpr int NT = 64 * kAdjWaves, K = (C * TP + NT - 1) / NT;
+    const int tid = threadIdx.x;
     float2 v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int i = lane + 64 * k, c = i / TP, p = i % TP;
+      const int i = min(tid + NT * k, C * TP - 1), c = i / TP, p = i % TP;
       const int x = X0 + (p % TW), y = Y0 + (p / TW);
       v[k] = gfield[((size_t)c * H + min(y, H - 1)) * W + min(x, W - 1)];
       if (x >= W || y >= H) v[k] = make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int i = lane + 64 * k;
-      sg[i % TP][i / TP] = v[k];
+      const int i = tid + NT * k;
+      if ((C * TP) % NT == 0 || i < C * TP) sg[i % TP][i / TP] = v[k];
     }
-    for (int i = lane; i < TW * C; i += 64) sg[TP + i / C][i % C] = make_float2(0.f, 0.f);
+    for (int i = tid; i < TW * C; i += NT) sg[TP + i / C][i % C] = make_float2(0.f, 0.f);
   }
+  if constexpr (kAdjWaves > 1) __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint2 rg = ranges[tile];
+  uint2 rg = ranges[tile];
+  {
+    const uint32_t len = rg.y - rg.x;
+    rg = make_uint2(rg.x + (uint32_t)(((uint64_t)len * wave) / kAdjWaves),
+                    rg.x + (uint32_t)(((uint64_t)len * (wave + 1)) / kAdjWaves));
+  }
   for (uint32_t base = rg.x; base < rg.y; base += kAdjBatch) {
     // ---- set-up: one pair per lane --------------------------------------
     const int cnt = (int)min((uint32_t)kAdjBatch, rg.y - base);
@@ -1247,7 +1265,7 @@ __global__ __launch_bounds__(64) void k_raster_adj(
         q[Q::HI] = l.y;
       }
     }
-    __syncthreads();
+    wave_sync();
     if (total > 0) {
       // ---- walk: this lane owns segments [s0, s1) of the concatenated boxes
       const int chunk = (total + 63) / 64;
@@ -1384,7 +1402,7 @@ __global__ __launch_bounds__(64) void k_raster_adj(
       }
       if (span > 0) flush_global(j, S);
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
@@ -1606,7 +1624,7 @@ hipError_t launch_raster_adjoint(const Ctx &c, const float2 *grad_field, hipStre
     with_channels(c.C, [&](auto cc) {
       constexpr int CC = decltype(cc)::value;
       auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(c.num_tiles), dim3(64), 0, s, c.rec, vals, c.ranges,
+        hipLaunchKernelGGL(kern, dim3(c.num_tiles), dim3(64 * kAdjWaves), 0, s, c.rec, vals, c.ranges,
                            c.rect, c.offsets, c.W, c.H, c.tiles_x, c.tiles_per, thr, c.alim,
                            grad_field, c.pair_cap, c.partials);
       };
