@@ -50,39 +50,55 @@ __device__ __forceinline__ v8s conv_in8(const uint16_t *__restrict__ x1, int c1,
 }
 
 // ----------------------------------------------------------------------------
-// Convolution: a workgroup of 4 waves takes 128 consecutive pixels (row-major)
-// p0 .. p0 + 127 and 32 NB output channels.  For each block of 16 input
-// channels it stages in LDS the three input row segments that the 3 x 3 taps
-// of its pixels read (pixels p0 + (ky - 1) W - 1 .. p0 + (ky - 1) W + 128,
-// ky < 3, zero outside the image) and the weights of its output channels for
-// the 9 taps; wave w then takes its 32 pixels x 32 NB channels through the 9
-// taps from LDS.  A tap that leaves the image (a pixel in the first or last
-// column or row) reads zero.  Each block's global loads are issued before the
-// workgroup waits for the previous block's products.
+// Convolution: a workgroup of NWV waves takes 32 NWV consecutive pixels
+// (row-major) p0 .. p0 + 32 NWV - 1 and 32 NB output channels.  For each
+// block of 16 input channels it stages in LDS the three input row segments
+// that the 3 x 3 taps of its pixels read (pixels p0 + (ky - 1) W - 1 ..
+// p0 + (ky - 1) W + 32 NWV, ky < 3, zero outside the image) and the weights
+// of its output channels for the 9 taps; wave w then takes its 32 pixels x
+// 32 NB channels through the 9 taps from LDS.  A tap that leaves the image (a pixel in the first or last
+// column or row) reads zero.  With one output block (NB = 1) each input
+// block's global loads are issued before the workgroup waits for the previous
+// block's products; with two or four, the loads of block k + 1 are issued
+// before the products of block k.
 // ----------------------------------------------------------------------------
-constexpr int kSeg = 130;  // pixels per staged row segment: 128 + one on each side
 
-template <int NB>
-__global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1, int c1, int up,
-                                                 const uint16_t *__restrict__ x2, int c2, int H,
-                                                 int W, const uint16_t *__restrict__ w,
-                                                 const float *__restrict__ bias, int cout,
-                                                 int relu, float *__restrict__ out32,
-                                                 uint16_t *__restrict__ out16) {
-  constexpr int CO = 32 * NB;
+// waves (of 32 pixels each) per convolution workgroup: 8 halves the weight
+// traffic and the halo per pixel against 4 (16 was slower at every width)
+constexpr int kConvWaves = 8;
+
+// Workgroups are handed to the 8 XCDs in turn (block b to XCD b % 8).  This
+// bijection on [0, nb) gives XCD x one contiguous run of pixel blocks, taken
+// in order, so the three workgroups that read one input row (the blocks one
+// image row above and below) run on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+template <int NB, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_conv3x3(
+    const uint16_t *__restrict__ x1, int c1, int up, const uint16_t *__restrict__ x2, int c2,
+    int H, int W, const uint16_t *__restrict__ w, const float *__restrict__ bias, int cout,
+    int relu, float *__restrict__ out32, uint16_t *__restrict__ out16) {
+  constexpr int CO = 32 * NB, NT = 64 * NWV, PX = 32 * NWV;
+  constexpr int kSeg = PX + 2;  // pixels per staged row segment: one more on each side
   constexpr int NA = 3 * kSeg * 2, NW = 9 * CO * 2;  // 16-byte items: [ky][pixel][half], [t][co][half]
-  constexpr int KA = (NA + 255) / 256, KW = (NW + 255) / 256;
-  __shared__ v8s sa[NA];
-  __shared__ v8s sw[NW];
+  constexpr int KA = (NA + NT - 1) / NT, KW = (NW + NT - 1) / NT;
+  // the staged operands; after the products the same memory holds the
+  // output tile [PX][32] (FP32) of one output block for the store
+  static_assert((NA + NW) * 16 >= PX * 32 * 4, "output tile fits the staging memory");
+  __shared__ v8s smem[NA + NW];
+  v8s *const sa = smem, *const sw = smem + NA;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int P = H * W, cin = c1 + c2;
-  const int p0 = blockIdx.x * 128;
+  const int pb = xcd_block(blockIdx.x, gridDim.x);
+  const int p0 = pb * PX;
   const int i = wave * 32 + (lane & 31);  // this lane's A row: pixel p0 + i
   const int half = lane >> 5;             // its 8 channels of a block of 16
   const int p = p0 + i;
   const int co0 = blockIdx.y * CO;
-  const int py = p / W, px = p - py * W;
-  const bool valid = p < P;
+  const int px = p - (p / W) * W;  // this lane's pixel column
   const int nk = (cin + 15) / 16;  // channel blocks (a last block of 8 is zero-filled)
   const v8s z = {0, 0, 0, 0, 0, 0, 0, 0};
   v16f acc[NB];
@@ -90,46 +106,79 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
-  for (int kb = 0; kb < nk; ++kb) {
-    v8s ra[KA], rw[KW];
+  // The source of each staged item, worked out once: A item k is channel
+  // ah[k] + 16 kb of pixel q2[k] (q1[k] in x1, which may be the half-size
+  // image), or zero (q2[k] < 0); B item k is channel 8 (wo[k] & 1) + 16 kb of
+  // weight row wo[k] >> 1 (an element offset), or zero (wo[k] < 0).
+  int q2[KA], q1[KA], ah[KA], wo[KW];
+#pragma unroll
+  for (int k = 0; k < KA; ++k) {
+    const int item = tid + NT * k;
+    q2[k] = -1;
+    q1[k] = 0;
+    ah[k] = 0;
+    if (KA * NT == NA || item < NA) {
+      const int seg = item / (2 * kSeg), rem = item - seg * (2 * kSeg);
+      const int q = p0 + (seg - 1) * W - 1 + (rem >> 1);
+      ah[k] = 8 * (rem & 1);
+      if (q >= 0 && q < P) {
+        const int qy = q / W, qx = q - qy * W;
+        q2[k] = q;
+        q1[k] = up ? (qy >> 1) * (W >> 1) + (qx >> 1) : q;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int item = tid + NT * k;
+    wo[k] = -1;
+    if (KW * NT == NW || item < NW) {
+      const int t = item / (2 * CO), rem = item - t * (2 * CO);
+      const int co = co0 + (rem >> 1);
+      if (co < cout) wo[k] = 2 * ((co * 9 + t) * cin) + (rem & 1);
+    }
+  }
+  // block kb of 16 input channels: its staged A and B items, global -> registers
+  v8s ra[KA], rw[KW];
+  auto fetch = [&](int kb) {
 #pragma unroll
     for (int k = 0; k < KA; ++k) {
-      const int item = tid + 256 * k;
+      const int c0 = kb * 16 + ah[k];
       ra[k] = z;
-      if (KA * 256 == NA || item < NA) {
-        const int seg = item / (2 * kSeg), rem = item - seg * (2 * kSeg);
-        const int q = p0 + (seg - 1) * W - 1 + (rem >> 1);
-        if (q >= 0 && q < P) {
-          const int qy = q / W;
-          ra[k] = conv_in8(x1, c1, up, x2, c2, H, W, qy, q - qy * W, kb * 16 + 8 * (rem & 1));
-        }
+      if (q2[k] >= 0 && c0 < cin) {
+        const uint16_t *src = c0 < c1 ? x1 + (size_t)q1[k] * c1 + c0
+                                      : x2 + (size_t)q2[k] * c2 + (c0 - c1);
+        ra[k] = *reinterpret_cast<const v8s *>(src);
       }
     }
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
-      const int item = tid + 256 * k;
       rw[k] = z;
-      if (KW * 256 == NW || item < NW) {
-        const int t = item / (2 * CO), rem = item - t * (2 * CO);
-        const int co = co0 + (rem >> 1), c0 = kb * 16 + 8 * (rem & 1);
-        if (co < cout && c0 < cin)
-          rw[k] = *reinterpret_cast<const v8s *>(w + ((size_t)co * 9 + t) * cin + c0);
-      }
+      const int c0 = kb * 16 + 8 * (wo[k] & 1);
+      if (wo[k] >= 0 && c0 < cin)
+        rw[k] = *reinterpret_cast<const v8s *>(w + (size_t)(wo[k] >> 1) + c0);
     }
-    if (kb > 0) __syncthreads();  // every wave is done with the previous block
+  };
+  auto stage = [&]() {
 #pragma unroll
     for (int k = 0; k < KA; ++k)
-      if (KA * 256 == NA || tid + 256 * k < NA) sa[tid + 256 * k] = ra[k];
+      if (KA * NT == NA || tid + NT * k < NA) sa[tid + NT * k] = ra[k];
 #pragma unroll
     for (int k = 0; k < KW; ++k)
-      if (KW * 256 == NW || tid + 256 * k < NW) sw[tid + 256 * k] = rw[k];
-    __syncthreads();
+      if (KW * NT == NW || tid + NT * k < NW) sw[tid + NT * k] = rw[k];
+  };
+  // A tap above the first or below the last row reads a staged zero (its
+  // linear pixel index is outside [0, P)) unless it also leaves the image at
+  // the side; a tap that leaves at the side reads the neighbouring row's end
+  // pixel in the staged segment, so it is masked here.  Outputs past P are
+  // not stored.
+  const bool in_l = px != 0, in_r = px != W - 1;
+  auto products = [&]() {
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int ky = t / 3, kx = t - 3 * ky;
-      const int sy = py + ky - 1, sx = px + kx - 1;
-      const bool in = valid && sy >= 0 && sy < H && sx >= 0 && sx < W;
-      const v8s a = in ? sa[(ky * kSeg + i + kx) * 2 + half] : z;
+      const v8s sv = sa[(ky * kSeg + i + kx) * 2 + half];
+      const v8s a = kx == 0 ? (in_l ? sv : z) : (kx == 2 ? (in_r ? sv : z) : sv);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const v8s bb = sw[(t * CO + 32 * b + (lane & 31)) * 2 + half];
@@ -138,18 +187,76 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x1
                                                          0, 0, 0);
       }
     }
+  };
+  if constexpr (NB == 1) {
+    // each block's loads are issued before the workgroup waits for the
+    // previous block's products
+    for (int kb = 0; kb < nk; ++kb) {
+      fetch(kb);
+      if (kb > 0) __syncthreads();  // every wave is done with the previous block
+      stage();
+      __syncthreads();
+      products();
+    }
+  } else {
+    // the loads of block kb + 1 are issued before the products of block kb
+    // (more registers: faster where 2 or 4 output blocks give the products
+    // enough length to cover them, slower with one)
+    fetch(0);
+    stage();
+    __syncthreads();
+    for (int kb = 0; kb < nk; ++kb) {
+      if (kb + 1 < nk) fetch(kb + 1);
+      products();
+      if (kb + 1 < nk) {
+        __syncthreads();  // every wave is done with this block
+        stage();
+        __syncthreads();
+      }
+    }
   }
+  // Store, one output block at a time: the accumulators (lane l holds output
+  // channel l % 32 of 16 pixels) go through LDS as a [pixel][channel] FP32
+  // tile, which each thread then reads and writes 16 bytes at a time.
+  float *tile = reinterpret_cast<float *>(smem);
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int co = co0 + 32 * b + (lane & 31);
-    const float bv = (bias && co < cout) ? bias[co] : 0.f;
+    const int cb = co0 + 32 * b;  // first output channel of the block
+    {
+      const int col = lane & 31;
+      const float bv = (bias && cb + col < cout) ? bias[cb + col] : 0.f;
+      __syncthreads();  // every wave is done with the staged operands (or the previous tile)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int q = blockIdx.x * 128 + wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      if (q < P && co < cout) {
-        const float s = acc[b][v] + bv;
-        if (out32) out32[(size_t)q * cout + co] = s;
-        if (out16) out16[(size_t)q * cout + co] = to_bf16(relu ? fmaxf(s, 0.f) : s);
+      for (int v = 0; v < 16; ++v) {
+        const int row = wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        tile[row * 32 + col] = acc[b][v] + bv;
+      }
+      __syncthreads();
+    }
+    if (out32) {
+      // 8 chunks of 4 channels per pixel
+      for (int c = tid; c < PX * 8; c += NT) {
+        const int row = c >> 3, part = c & 7, q = p0 + row, co = cb + 4 * part;
+        if (q < P && co < cout) {
+          // cout is a multiple of 8, so the 4 channels are all below cout
+          *reinterpret_cast<float4 *>(out32 + (size_t)q * cout + co) =
+              *reinterpret_cast<const float4 *>(tile + row * 32 + 4 * part);
+        }
+      }
+    }
+    if (out16) {
+      // 4 chunks of 8 channels per pixel (cout is a multiple of 8)
+      for (int c = tid; c < PX * 4; c += NT) {
+        const int row = c >> 2, part = c & 3, q = p0 + row, co = cb + 8 * part;
+        if (q < P && co < cout) {
+          const float4 u0 = *reinterpret_cast<const float4 *>(tile + row * 32 + 8 * part);
+          const float4 u1 = *reinterpret_cast<const float4 *>(tile + row * 32 + 8 * part + 4);
+          const float f[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+          v8s o;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) o[e] = (short)to_bf16(relu ? fmaxf(f[e], 0.f) : f[e]);
+          *reinterpret_cast<v8s *>(out16 + (size_t)q * cout + co) = o;
+        }
       }
     }
   }
@@ -469,6 +576,7 @@ __global__ void k_features(const float *__restrict__ t, const float2 *__restrict
 
 unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+
 // the split of the weight-gradient GEMM: about 512 waves over the 16-pixel
 // row chunks of a Wr-wide image, and the byte offsets of its workspace parts
 struct WgPlan {
@@ -529,13 +637,13 @@ cgh_status cgh_net_conv3x3(const cgh_bf16 *x1, int32_t c1, int32_t up, const cgh
   if (st != CGH_OK) return st;
   NET_CHECK(w && cout > 0 && cout % 8 == 0, "w NULL or cout = %d not a multiple of 8", cout);
   NET_CHECK(out32 || out16, "no output");
-  NET_CHECK(al16(w), "w must be 16-byte aligned");
-  const int nb = cout % 128 == 0 ? 4 : (cout % 64 == 0 ? 2 : 1);
-  const dim3 grid(blocks_of((int64_t)H * W, 128), (cout + 32 * nb - 1) / (32 * nb));
+  NET_CHECK(al16(w) && al16(out32) && al16(out16), "w, out32 and out16 must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-#define NET_CONV(NB)                                                                       \
-  hipLaunchKernelGGL(k_conv3x3<NB>, grid, dim3(256), 0, s, x1, c1, up, x2, c2, H, W, w, bias, \
-                     cout, relu, out32, out16)
+  const int nb = cout % 128 == 0 ? 4 : (cout % 64 == 0 ? 2 : 1);
+  const dim3 grid(blocks_of((int64_t)H * W, 32 * kConvWaves), (cout + 32 * nb - 1) / (32 * nb));
+#define NET_CONV(NB)                                                                         \
+  hipLaunchKernelGGL((k_conv3x3<NB, kConvWaves>), grid, dim3(64 * kConvWaves), 0, s, x1, c1, up, \
+                     x2, c2, H, W, w, bias, cout, relu, out32, out16)
   if (nb == 4) NET_CONV(4);
   else if (nb == 2) NET_CONV(2);
   else NET_CONV(1);

@@ -54,6 +54,10 @@ def check(st):
     dict(H=7, W=9, c1=64, c2=0, up=False, cout=128, relu=True),     # 4 blocks of 32
     dict(H=12, W=8, c1=256, c2=128, up=True, cout=128, relu=True),  # widest decoder input
     dict(H=9, W=13, c1=32, c2=0, up=False, cout=8, relu=False),     # the head: 8 of 32 channels
+    # many workgroups of 256 pixels, the last one ragged; 24 input channels
+    # (a half-filled last block of 16); [up(x1), x2] with 24 outputs
+    dict(H=70, W=520, c1=24, c2=0, up=False, cout=32, relu=True),
+    dict(H=38, W=300, c1=16, c2=16, up=True, cout=24, relu=False),
 ])
 def test_conv_forward_and_adjoints(case):
     say("conv", case)
