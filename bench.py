@@ -581,12 +581,18 @@ def run_serving(binding, dev, holograms, steps, seed=300, candidates=(1, 2)):
     comes from the project's autotuner (a short captured solve of the class
     batch at every shape), then the stream count from ``candidates`` (a
     warm-up run and a timed run each); the reported batch is the timed run of
-    the best.  Beside it: the per-hologram graphs of the single-hologram path
-    on two streams, and the eager per-kernel calls on one stream."""
+    the best.  Then the per-hologram graphs of the single-hologram path on
+    two streams, and a mixed run in which each class takes whichever of the
+    two modes is faster per hologram and step (from the tile probe of its
+    batch and its single solve), its class batches and single requests
+    spread over two streams; the reported figures are those of the fastest
+    of the three.  Beside them: the eager per-kernel calls on one stream."""
     import torch
     from paper_2511_15022_amd import serve
     reqs = serve.make_requests(holograms, seed=seed, device=dev)
-    server = serve.BatchServer(steps, max_streams=max(candidates), device=dev)
+    # the batched, single-hologram and mixed servers share two streams
+    streams = [torch.cuda.Stream(device=dev) for _ in range(max(max(candidates), 2))]
+    server = serve.BatchServer(steps, device=dev, streams=streams[:max(candidates)])
     best, rates, runs, tile_ms = serve.autotune_batched(server, reqs, candidates)
     for k, r in rates.items():
         log(f"[bench]   batched serving: {k} stream(s): {r:.2f} holograms/s")
@@ -599,16 +605,34 @@ def run_serving(binding, dev, holograms, steps, seed=300, candidates=(1, 2)):
     final_psnr = [float(r.out_loss[-1, 1].item()) for r in reqs]
     first_psnr = [float(r.out_loss[0, 1].item()) for r in reqs]
     tiles = {f"{h}x{w}": list(server.tile_of(h, w)) for (h, w) in tile_ms}
-    del server
-    torch.cuda.empty_cache()
     # the single-hologram path: one graph per hologram, two streams
     for r in reqs:
         r.out_params = r.out_loss = None
-    single = serve.Server(steps, max_streams=2, device=dev)
+    single = serve.Server(steps, device=dev, streams=streams[:2])
     costs = single.measure_class_costs(reqs)
     single.run(reqs, streams=2)
     res2 = single.run(reqs, streams=2)
     per_holo = len(reqs) / res2["wall_s"]
+    # the mixed path: each class in its faster mode (per hologram and step,
+    # from the tile probe of its batch and its single solve), two streams
+    probe_steps = 20
+    first_batch = {}
+    for bt in serve.batches_of(reqs, server.max_batch):
+        first_batch.setdefault((bt[0].H, bt[0].W), len(bt))
+    batch_step_ms = {key: (tile_ms[key][server.tile_of(*key)] / probe_steps, first_batch[key])
+                     for key in tile_ms}
+    single_step_ms = {key: v / steps for key, v in costs.items()}
+    mixed = serve.MixedServer(server, single, batch_step_ms, single_step_ms)
+    if server.streams[:2] != single.streams:
+        raise RuntimeError("serving servers must share their streams")
+    for r in reqs:
+        r.out_params = r.out_loss = None
+    mixed.run(reqs, streams=2)
+    res3 = mixed.run(reqs, streams=2)
+    mixed_rate = len(reqs) / res3["wall_s"]
+    mixed_classes = sorted(f"{h}x{w}" for (h, w) in mixed.batched)
+    del mixed, server
+    torch.cuda.empty_cache()
     # eager comparator: the same solves, one host call per kernel group, one stream
     ctxs = {key: single.slot(0, *key, key[0] * key[1] // 5).ctx for key in costs}
     bufs = {key: torch.empty_like(next(r.params for r in reqs if (r.H, r.W) == key))
@@ -623,10 +647,27 @@ def run_serving(binding, dev, holograms, steps, seed=300, candidates=(1, 2)):
         serve.solve_eager(ctx, P, r.n, r.target, steps)
     torch.cuda.synchronize()
     eager_s = time.perf_counter() - t0
+    # the reported mode is the fastest of the three, each measured the same
+    # way (a warm-up run, then the timed run)
+    batched_rate = out["holograms_per_s"]
+    modes = {"batched": (batched_rate, best, None),
+             "single": (per_holo, 2, serve.summary(reqs, res2)),
+             "mixed": (mixed_rate, 2, serve.summary(reqs, res3))}
+    pick = max(modes, key=lambda k: modes[k][0])
+    if modes[pick][2] is not None:
+        out.update(modes[pick][2])
+    describe = {
+        "batched": "batched contexts: one launch per kernel per class batch, one graph per batch",
+        "single": "single-hologram contexts: one graph per hologram, two streams",
+        "mixed": "mixed: each class batched or one hologram at a time, whichever is faster "
+                 "per hologram, the jobs on two streams"}
     out.update({
         "steps_per_solve": steps,
-        "mode": "batched contexts: one launch per kernel per class batch, one graph per batch",
-        "streams": best,
+        "mode": describe[pick],
+        "holograms_per_s_by_mode": {k: v[0] for k, v in modes.items()},
+        "mixed_batched_classes": mixed_classes,
+        "streams": modes[pick][1],
+        "batched_streams": best,
         "autotune_holograms_per_s": {str(k): v for k, v in rates.items()},
         "tile_per_class": tiles,
         "tile_autotune_ms": {f"{h}x{w}": {f"{a}x{b}": round(v, 3) for (a, b), v in t.items()}
@@ -637,7 +678,7 @@ def run_serving(binding, dev, holograms, steps, seed=300, candidates=(1, 2)):
         "single_hologram_class_step_us": {f"{h}x{w}": 1e3 * v / steps
                                           for (h, w), v in costs.items()},
         "eager_one_stream_holograms_per_s": len(reqs) / eager_s,
-        "batched_speedup_vs_single_graphs": out["holograms_per_s"] / per_holo,
+        "batched_speedup_vs_single_graphs": batched_rate / per_holo,
         "psnr_db_first_step_median": float(np.median(first_psnr)),
         "psnr_db_last_step_median": float(np.median(final_psnr)),
         "data": "synthetic, seeded (serve.make_requests, seed 300)",
@@ -970,7 +1011,7 @@ def main():
             r.update(profile_figures(cls, npairs * per_pair, 1e12, FP32_VALU_PEAK_TFLOPS,
                                      t_launch))
             return r
-        label = {"binning": "latency (integer sort, nine short launches)",
+        label = {"binning": "latency (integer sort, eight short launches)",
                  "loss": "latency (one-block FP64 reduction)"}.get(cls, "latency")
         return {"kernel": cls, "bound": label}
 
@@ -1079,8 +1120,11 @@ def main():
             f"{args.serving_steps} steps")
         try:
             serving = run_serving(binding, dev, args.serving_holograms, args.serving_steps)
-            log(f"[bench]   {serving['holograms_per_s']:.2f} holograms/s on "
-                f"{serving['streams']} stream(s); latency p50 {serving['latency_p50_ms']:.1f} ms "
+            log(f"[bench]   by mode: " + ", ".join(
+                f"{k} {v:.2f}" for k, v in serving['holograms_per_s_by_mode'].items())
+                + f" holograms/s (mixed batches {serving['mixed_batched_classes']})")
+            log(f"[bench]   {serving['holograms_per_s']:.2f} holograms/s ({serving['mode']}); "
+                f"latency p50 {serving['latency_p50_ms']:.1f} ms "
                 f"p99 {serving['latency_p99_ms']:.1f} ms; eager "
                 f"{serving['eager_one_stream_holograms_per_s']:.2f} holograms/s")
         except Exception as e:

@@ -1422,52 +1422,76 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
 //   inv = adj(Sigma) / eps_d
 //   Sigma -> (s_x, s_y, theta) and s = exp(s~) + eps_s.
 // ----------------------------------------------------------------------------
+// the 2C + 5 partial sums of a pair, plus the clamped-pixel sum with CGH_PAPER_ALPHA
+template <int C, bool PA>
+constexpr int kPairSums = 2 * C + 5 + (PA ? 1 : 0);
+constexpr int kPairChunk = 512;  // pairs per LDS chunk of the per-Gaussian reduction
+
+// FP64 sums of the pair partials of Gaussian g0 + threadIdx.x, for the 256
+// Gaussians g0 .. g0 + 255 of a workgroup (all threads must call it).  A
+// Gaussian's pairs own the slots offset .. offset + count - 1 and the offsets
+// are the scan of the counts, so the workgroup's pairs are one contiguous run
+// of slots: it is read into LDS kPairChunk pairs at a time with every thread
+// on consecutive 16-byte words, and each thread adds its own pairs from LDS in
+// slot order (the same order, so the same sums, as reading them one by one).
+template <int C, bool PA>
+__device__ __forceinline__ void pair_sums_block(int g0, int total,
+                                                const uint32_t *__restrict__ counts,
+                                                const uint32_t *__restrict__ offsets, int64_t cap,
+                                                const float *__restrict__ partials,
+                                                float4 *__restrict__ chunk4,
+                                                double (&S)[kPairSums<C, PA>]) {
+  constexpr int PS = part_stride_c(C), NP = kPairSums<C, PA>;
+  static_assert(NP <= PS, "spare partial slot");
+  constexpr int NF4 = kPairChunk * PS / 4, KF = NF4 / 256;
+  static_assert(NF4 % 256 == 0, "chunk of whole float4 rounds");
+  const int tid = threadIdx.x, gg = g0 + tid;
+  const int last = min(total, g0 + 256) - 1;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) S[k] = 0.0;
+  uint64_t off = 0, end = 0;
+  if (gg < total) {
+    off = offsets[gg];
+    end = min(off + counts[gg], (uint64_t)cap);
+  }
+  const uint64_t run0 = offsets[g0];
+  const uint64_t run1 = min((uint64_t)offsets[last] + counts[last], (uint64_t)cap);
+  const float4 *src4 = reinterpret_cast<const float4 *>(partials);
+  for (uint64_t c0 = run0; c0 < run1; c0 += kPairChunk) {
+    const uint64_t c1 = min(c0 + kPairChunk, run1);
+    const int nf4 = (int)(c1 - c0) * (PS / 4);
+    float4 v[KF];
+#pragma unroll
+    for (int k = 0; k < KF; ++k) {
+      const int i = tid + 256 * k;
+      v[k] = i < nf4 ? src4[c0 * (PS / 4) + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();  // every thread is done with the previous chunk
+#pragma unroll
+    for (int k = 0; k < KF; ++k) chunk4[tid + 256 * k] = v[k];
+    __syncthreads();
+    const uint64_t p1 = min(end, c1);
+    for (uint64_t p = max(off, c0); p < p1; ++p) {
+      const float *r = reinterpret_cast<const float *>(chunk4) + (p - c0) * PS;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) S[k] += (double)r[k];
+    }
+  }
+}
+
 // The 6 + 2C gradients of Gaussian gg (of all B n) in the order mean (2),
-// log-scale (2), rotation, amplitude (C), phase (C), opacity, from its pair
-// partials and its parameters.
+// log-scale (2), rotation, amplitude (C), phase (C), opacity, from the sums of
+// its pair partials and its parameters.
 template <int C, bool PA>
 __device__ __forceinline__ void gaussian_grads(const float *params_all, int n, int W, int H, int gg,
-                                               const uint32_t *__restrict__ counts,
-                                               const uint32_t *__restrict__ offsets, int64_t cap,
-                                               const float *__restrict__ partials,
+                                               const double (&S)[kPairSums<C, PA>],
                                                float (&gv)[6 + 2 * C]) {
-  constexpr int PS = part_stride_c(C);
-  // the 2C + 5 partial sums, plus the clamped-pixel sum with CGH_PAPER_ALPHA
-  constexpr int NP = 2 * C + 5 + (PA ? 1 : 0);
-  static_assert(NP <= PS, "spare partial slot");
   // partial slots are indexed by the Gaussian's index among all B n; its
   // parameters by its index g in its hologram's block
   const GaussIdx gi = gauss_idx<C>(gg, n);
   const float *params = params_all + gi.base;
   const int g = gi.gl;
-  double S[NP];
-#pragma unroll
-  for (int k = 0; k < NP; ++k) S[k] = 0.0;
   const Geom q = geometry(params, n, C, g, W, H);
-  const uint64_t off = offsets[gg];
-  uint64_t end = off + counts[gg];
-  if ((int64_t)end > cap) end = (uint64_t)cap;
-  // pair partials in slot order, four slots' loads in flight at a time
-  constexpr int U = 4;
-  for (uint64_t p0 = off; p0 < end; p0 += U) {
-    float v[U][PS];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint64_t p = min(p0 + u, end - 1);
-      const float4 *src = reinterpret_cast<const float4 *>(partials + p * PS);
-#pragma unroll
-      for (int k = 0; k < PS / 4; ++k) {
-        const float4 t = src[k];
-        v[u][4 * k] = t.x; v[u][4 * k + 1] = t.y; v[u][4 * k + 2] = t.z; v[u][4 * k + 3] = t.w;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (p0 + u < end) {
-#pragma unroll
-        for (int k = 0; k < NP; ++k) S[k] += (double)v[u][k];
-      }
-  }
   const float *amp = params + 5 * (size_t)n;
   const float *ph = params + (size_t)(5 + C) * n;
   // the 6 + 2C gradients of this Gaussian: mean (2), log-scale (2), rotation,
@@ -1547,10 +1571,13 @@ __global__ __launch_bounds__(256) void k_preprocess_adj(
     const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets, int64_t cap,
     const float *__restrict__ partials, float *__restrict__ grads_all,
     uint32_t *__restrict__ finite_flag) {
-  const int gg = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float4 chunk4[kPairChunk * part_stride_c(C) / 4];
+  const int g0 = blockIdx.x * 256, gg = g0 + threadIdx.x;
+  double S[kPairSums<C, PA>];
+  pair_sums_block<C, PA>(g0, total, counts, offsets, cap, partials, chunk4, S);
   if (gg >= total) return;
   float gv[6 + 2 * C];
-  gaussian_grads<C, PA>(params_all, n, W, H, gg, counts, offsets, cap, partials, gv);
+  gaussian_grads<C, PA>(params_all, n, W, H, gg, S, gv);
   const GaussIdx gi = gauss_idx<C>(gg, n);
   bool finite = true;
 #pragma unroll
@@ -1575,12 +1602,15 @@ __global__ __launch_bounds__(256) void k_preprocess_adj_adam(
     uint32_t *__restrict__ finite_flag, AdamFuse adam) {
   constexpr int NPAR = 6 + 2 * C;
   __shared__ float sgv[NPAR][256];
+  __shared__ float4 chunk4[kPairChunk * part_stride_c(C) / 4];
   const int tid = threadIdx.x;
   const int g0 = blockIdx.x * 256;
   const int gg = g0 + tid;
+  double S[kPairSums<C, PA>];
+  pair_sums_block<C, PA>(g0, total, counts, offsets, cap, partials, chunk4, S);
   if (gg < total) {
     float gv[NPAR];
-    gaussian_grads<C, PA>(params_all, n, W, H, gg, counts, offsets, cap, partials, gv);
+    gaussian_grads<C, PA>(params_all, n, W, H, gg, S, gv);
     bool finite = true;
 #pragma unroll
     for (int k = 0; k < NPAR; ++k) {

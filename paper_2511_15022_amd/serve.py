@@ -32,6 +32,11 @@ class batch at every supported shape; ``autotune_batched`` then picks the
 stream count.  Results equal the single-hologram solves bit for bit (the
 same kernels over the same tile lists; tested).
 
+``MixedServer`` serves each class in whichever of the two modes costs less
+per hologram and step (measured: the tile probe of the class batch, the
+solve of one request alone), with the class batches and the single requests
+as jobs spread over shared streams longest first.
+
 All device work is the library's kernels; this module only owns buffers,
 streams and the order of the calls.
 """
@@ -129,9 +134,10 @@ class Slot:
 class Server:
     """Slots over up to ``max_streams`` streams; ``run`` serves a batch."""
 
-    def __init__(self, steps, lr=1e-3, max_streams=4, pitch=PITCH, device="cuda"):
+    def __init__(self, steps, lr=1e-3, max_streams=4, pitch=PITCH, device="cuda", streams=None):
         self.steps, self.lr, self.pitch, self.device = steps, lr, pitch, device
-        self.streams = [torch.cuda.Stream(device=device) for _ in range(max_streams)]
+        self.streams = (list(streams) if streams is not None else
+                        [torch.cuda.Stream(device=device) for _ in range(max_streams)])
         self.slots = {}
         self.class_cost = {}
 
@@ -314,10 +320,11 @@ class BatchServer:
     the batches spread over up to ``max_streams`` streams (longest first)."""
 
     def __init__(self, steps, lr=1e-3, max_streams=2, max_batch=binding.MAX_BATCH, pitch=PITCH,
-                 device="cuda"):
+                 device="cuda", streams=None):
         self.steps, self.lr, self.pitch, self.device = steps, lr, pitch, device
         self.max_batch = max_batch
-        self.streams = [torch.cuda.Stream(device=device) for _ in range(max_streams)]
+        self.streams = (list(streams) if streams is not None else
+                        [torch.cuda.Stream(device=device) for _ in range(max_streams)])
         self.slots = {}
         self.tiles = {}        # (H, W) -> tile shape (width, height)
         self.batch_ms = {}     # (H, W, B) -> measured solve time of a batch, ms
@@ -466,3 +473,125 @@ def autotune_batched(server, requests, candidates=(1, 2), probe_steps=20):
         rates[k] = len(requests) / runs[k]["wall_s"]
     best = max(rates, key=lambda k: (rates[k], -k))
     return best, rates, runs, tile_ms
+
+
+def mixed_jobs(requests, batched_classes, max_batch):
+    """The jobs of a mixed run: each class in ``batched_classes`` as its class
+    batches (as ``batches_of``), every other request on its own.  A job is a
+    list of requests; a single request is a list of one with ``batched``
+    False."""
+    jobs = []
+    for bt in batches_of(requests, max_batch):
+        if (bt[0].H, bt[0].W) in batched_classes:
+            jobs.append((True, bt))
+        else:
+            jobs.extend((False, [r]) for r in bt)
+    return jobs
+
+
+def plan_jobs(jobs, streams, cost):
+    """``plan_batches`` for (batched, requests) jobs: longest first onto the
+    least-loaded stream, then each queue shortest first; ties by the first
+    request's index."""
+    load = [0.0] * streams
+    queues = [[] for _ in range(streams)]
+    for i in sorted(range(len(jobs)), key=lambda i: (-cost(jobs[i]), jobs[i][1][0].index)):
+        si = min(range(streams), key=lambda k: (load[k], k))
+        load[si] += cost(jobs[i])
+        queues[si].append(jobs[i])
+    for q in queues:
+        q.sort(key=lambda j: (cost(j), j[1][0].index))
+    return queues
+
+
+def choose_modes(batch_step_ms, single_step_ms):
+    """The classes to batch: those whose measured time per hologram and step
+    is lower in a batched context than alone.  ``batch_step_ms`` maps a class
+    to (ms per step of its batch, batch size); ``single_step_ms`` to the ms per
+    step of one hologram alone."""
+    return {key for key, (ms, b) in batch_step_ms.items()
+            if key in single_step_ms and ms / b < single_step_ms[key]}
+
+
+class MixedServer:
+    """Serves each size class in the mode that is faster per hologram for it
+    (``choose_modes``): a batched context per class batch (``BatchServer``
+    slots) or one single-hologram solve per request (``Server`` slots).  Both
+    servers share the streams; the jobs (class batches and single requests)
+    are spread over them longest first (``plan_batches``) by their measured
+    cost, and each stream runs its queue shortest first."""
+
+    def __init__(self, batch_server, single_server, batch_step_ms, single_step_ms):
+        if batch_server.streams != single_server.streams:
+            raise ValueError("the two servers must share their streams")
+        self.b, self.s = batch_server, single_server
+        self.batch_step_ms, self.single_step_ms = dict(batch_step_ms), dict(single_step_ms)
+        self.batched = choose_modes(self.batch_step_ms, self.single_step_ms)
+        self.streams = batch_server.streams
+        self.steps, self.device = batch_server.steps, batch_server.device
+
+    def cost(self, job):
+        """Measured GPU time of a job alone: a class batch scaled from its
+        class's probe batch, a single request from its class's solve."""
+        batched, reqs = job
+        key = (reqs[0].H, reqs[0].W)
+        if batched:
+            ms, b = self.batch_step_ms[key]
+            return self.steps * ms * len(reqs) / b
+        return self.steps * self.single_step_ms.get(key, float(reqs[0].pixels))
+
+    def queues(self, requests, streams):
+        return plan_jobs(mixed_jobs(requests, self.batched, self.b.max_batch), streams, self.cost)
+
+    def slot(self, si, job):
+        batched, reqs = job
+        r = reqs[0]
+        return self.b.slot(si, r.H, r.W, r.n, len(reqs)) if batched else self.s.slot(si, r.H, r.W, r.n)
+
+    def run(self, requests, streams=None):
+        """As ``BatchServer.run``: batch wall time and per-request latency
+        (its job's span on its stream) and turnaround, from HIP events."""
+        streams = len(self.streams) if streams is None else streams
+        queues = self.queues(requests, streams)
+        for si, q in enumerate(queues):
+            for job in q:
+                self.slot(si, job)
+        for r in requests:
+            if r.out_params is None:
+                r.out_params = torch.empty_like(r.params)
+                r.out_loss = torch.empty((self.steps, 2), dtype=torch.float64,
+                                         device=self.device)
+        torch.cuda.synchronize()
+        main = torch.cuda.current_stream(self.device)
+        t0 = torch.cuda.Event(enable_timing=True)
+        marks = {}
+        host0 = time.perf_counter()
+        t0.record(main)
+        for si in range(streams):
+            self.streams[si].wait_event(t0)
+        depth = max((len(q) for q in queues), default=0)
+        for k in range(depth):
+            for si, q in enumerate(queues):
+                if k >= len(q):
+                    continue
+                job = q[k]
+                slot = self.slot(si, job)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(slot.stream)
+                slot.enqueue(job[1] if job[0] else job[1][0])
+                e1.record(slot.stream)
+                for r in job[1]:
+                    marks[r.index] = (e0, e1, si)
+        for si in range(streams):
+            main.wait_stream(self.streams[si])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - host0
+        for si, q in enumerate(queues):
+            for job in q:
+                self.slot(si, job).ctx.read_status()
+        latency = {i: e0.elapsed_time(e1) for i, (e0, e1, _) in marks.items()}
+        turnaround = {i: t0.elapsed_time(e1) for i, (_, e1, _) in marks.items()}
+        return {"wall_s": wall, "latency_ms": latency, "turnaround_ms": turnaround,
+                "stream_of": {i: si for i, (_, _, si) in marks.items()}}
+

@@ -173,6 +173,37 @@ def test_batch_server_matches_standalone_solves():
         assert torch.equal(r.out_loss, log)
 
 
+def test_mixed_server_matches_standalone_solves():
+    """Eight requests of three sizes served by the mixed server with two
+    classes batched (at most two holograms per batch) and one class one
+    hologram at a time, on two shared streams: every result equals the eager
+    solve of that request alone on a context with its optics (and, for a
+    batched class, its batch's tile), bit for bit."""
+    sizes = ((40, 60), (48, 64), (32, 32))
+    reqs = serve.make_requests(8, seed=171, sizes=sizes)
+    steps, lr = 5, 1e-3
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    bserver = serve.BatchServer(steps, lr=lr, max_batch=2, streams=streams)
+    bserver.tiles[(48, 64)] = (32, 8)
+    sserver = serve.Server(steps, lr=lr, streams=streams)
+    # made-up costs that batch (40, 60) and (48, 64) and keep (32, 32) single
+    batch_ms = {(40, 60): (1.0, 2), (48, 64): (1.0, 2), (32, 32): (4.0, 2)}
+    single_ms = {(40, 60): 1.0, (48, 64): 1.0, (32, 32): 1.0}
+    mixed = serve.MixedServer(bserver, sserver, batch_ms, single_ms)
+    assert mixed.batched == {(40, 60), (48, 64)}
+    res = mixed.run(reqs, streams=2)
+    assert len(res["latency_ms"]) == 8 and set(res["stream_of"].values()) <= {0, 1}
+    for r in reqs:
+        tile = bserver.tile_of(r.H, r.W) if (r.H, r.W) in mixed.batched else (16, 16)
+        ctx = binding.Context(r.H, r.W, 1, serve.PITCH, [r.wavelength], [r.z], max_gaussians=r.n,
+                              tile=tile)
+        P = r.params.clone()
+        log = _eager(ctx, P, r.n, r.target, steps, lr)
+        say("mixed request", r.index, r.H, r.W, tile)
+        assert torch.equal(r.out_params, P)
+        assert torch.equal(r.out_loss, log)
+
+
 @pytest.mark.parametrize("H,W", [(512, 512), (768, 1024)])
 def test_serving_sizes_forward_backward_match_oracle(O, H, W):
     """Full-size serving classes (pads 1024^2 and 1536 x 2048, the runtime

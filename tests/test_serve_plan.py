@@ -84,3 +84,55 @@ def test_batches_group_classes_and_respect_the_limit():
     assert sorted(id(b) for q in queues for b in q) == sorted(id(b) for b in bts)
     loads = [sum(len(b) for b in q) for q in queues]
     assert max(loads) - min(loads) <= 3
+
+
+class Q:
+    """A request of a size class for the mixed plan."""
+
+    def __init__(self, index, H, W):
+        self.index, self.H, self.W = index, H, W
+
+    @property
+    def pixels(self):
+        return self.H * self.W
+
+
+def test_modes_batch_only_the_classes_that_gain():
+    batch = {(8, 8): (2.0, 4), (16, 16): (9.0, 2), (32, 32): (3.0, 3)}
+    single = {(8, 8): 1.0, (16, 16): 4.0, (32, 32): 1.0}
+    # per hologram and step: 0.5 < 1 batches, 4.5 > 4 stays single, 1 = 1 stays single
+    assert serve.choose_modes(batch, single) == {(8, 8)}
+
+
+def test_mixed_jobs_cover_every_request_once():
+    reqs = [Q(i, *((8, 8) if i % 3 else (16, 16))) for i in range(17)]
+    jobs = serve.mixed_jobs(reqs, {(8, 8)}, max_batch=4)
+    seen = sorted(r.index for _, rs in jobs for r in rs)
+    assert seen == list(range(17))
+    for batched, rs in jobs:
+        assert all((r.H, r.W) == (rs[0].H, rs[0].W) for r in rs)
+        if batched:
+            assert (rs[0].H, rs[0].W) == (8, 8) and 1 <= len(rs) <= 4
+        else:
+            assert len(rs) == 1 and (rs[0].H, rs[0].W) == (16, 16)
+    # the batches of a class keep request order
+    b = [[r.index for r in rs] for batched, rs in jobs if batched]
+    assert [i for x in b for i in x] == sorted(i for x in b for i in x)
+
+
+def test_plan_jobs_lpt_and_shortest_first():
+    rng = np.random.default_rng(5)
+    cost = lambda j: j[1][0].c
+    for trial in range(15):
+        m = int(rng.integers(2, 4))
+        jobs = [(bool(rng.integers(2)), [R(i, float(rng.integers(1, 40)))])
+                for i in range(int(rng.integers(3, 8)))]
+        queues = serve.plan_jobs(jobs, m, cost)
+        assert sorted(j[1][0].index for q in queues for j in q) == list(range(len(jobs)))
+        for q in queues:
+            assert [cost(j) for j in q] == sorted(cost(j) for j in q)
+        got = max(sum(cost(j) for j in q) for q in queues)
+        best = min(
+            max(sum(cost(j) for j, a in zip(jobs, assign) if a == k) for k in range(m))
+            for assign in itertools.product(range(m), repeat=len(jobs)))
+        assert best <= got <= (4.0 / 3.0 - 1.0 / (3 * m)) * best + 1e-9
