@@ -303,11 +303,13 @@ def run_learned_init(binding, w, T, n_plain, dev, train_steps, opt_steps, target
     infer = a.elapsed_time(b) / 1e3
     a2, b2 = ev(), ev()
     x = big.features(Tt)
+    reps = 5  # back-to-back forwards, averaged
     a2.record()
-    big.net.forward(x)
+    for _ in range(reps):
+        big.net.forward(x)
     b2.record()
     torch.cuda.synchronize(dev)
-    fwd = a2.elapsed_time(b2) / 1e3
+    fwd = a2.elapsed_time(b2) / 1e3 / reps
     flops = unet_flops(big.net.layers, H, W)
     out = {"train": {"size": [train_size, train_size], "targets": pool, "steps": train_steps,
                      "seconds": secs, "ms_per_step": 1e3 * secs / train_steps, "lr": lr_train,

@@ -962,7 +962,11 @@ __global__ __launch_bounds__(TW * TH) void k_raster_seg(
 #pragma unroll
     for (int qd = 0; qd < QD; ++qd) {
       if (qd * 64 >= cnt) break;  // uniform
-      const bool valid = qd * 64 + lane < cnt;
+      // lanes past the batch end: a scalar mask, so that each segment's ballot
+      // takes its comparison's lane mask as it is
+      const int nv = min(64, cnt - qd * 64);
+      const uint64_t vmask = nv >= 64 ? ~0ull : ((1ull << nv) - 1ull);
+      const bool in_batch = lane < nv;
       const float oxt = (float)(Xt - __float_as_int(r0[qd].x)) - r0[qd].z;
       const float eyt = (float)(Yt - __float_as_int(r0[qd].y)) - r0[qd].w;
       const float s = rx[qd].x, kap = rx[qd].y, ra = rx[qd].z;
@@ -974,9 +978,9 @@ __global__ __launch_bounds__(TW * TH) void k_raster_seg(
         const float qm = kap * dy * dy;
         const float m = ra * fmaf(-s, dy, oxc);
         const float d = fmaxf(fmaf(-7.5f, ra, fabsf(m)), 0.f);
-        const bool hit = valid && fmaf(-d, d, qm) >= cull;
-        const uint64_t bm = __builtin_amdgcn_ballot_w64(hit);
-        if (hit) {
+        const bool pass = fmaf(-d, d, qm) >= cull;
+        const uint64_t bm = __builtin_amdgcn_ballot_w64(pass) & vmask;
+        if (pass && in_batch) {
           const int pos = nl[g] + (int)__builtin_amdgcn_mbcnt_hi(
                                       (uint32_t)(bm >> 32),
                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
@@ -1000,23 +1004,26 @@ __global__ __launch_bounds__(TW * TH) void k_raster_seg(
 #pragma unroll
       for (int k = 0; k < 2 * C; ++k) cv[k] = amp[k];
     };
-    float4 e;
-    float cv[2 * C];
-    if (nmax > 0) fetch(0, e, cv);
-    for (int b0 = 0; b0 < nmax; b0 += 16) {
-      // issued on every round (past the end it reads zero entries), so the
-      // wait before the steps covers only this round's loads
-      float4 en;
-      float cvn[2 * C];
-      fetch(b0 + 16, en, cvn);
+    auto walk_round = [&](int b0, const float4 &e, const float (&cv)[2 * C]) {
       const int left = nmax - b0;
       seg_steps<C, CLAMP, 0>(acc, cv, e.y, e.w, e.z, u, thr, fl);
       if (left > 4) seg_steps<C, CLAMP, 1>(acc, cv, e.y, e.w, e.z, u, thr, fl);
       if (left > 8) seg_steps<C, CLAMP, 2>(acc, cv, e.y, e.w, e.z, u, thr, fl);
       if (left > 12) seg_steps<C, CLAMP, 3>(acc, cv, e.y, e.w, e.z, u, thr, fl);
-      e = en;
-#pragma unroll
-      for (int k = 0; k < 2 * C; ++k) cv[k] = cvn[k];
+    };
+    // two rounds per iteration with the two entry sets in alternate roles, so
+    // no registers are copied between rounds; the next round's fetch is
+    // issued on every round (past the end it reads zero entries), so the wait
+    // before the steps covers only this round's loads
+    float4 ea, eb;
+    float ca[2 * C], cb[2 * C];
+    if (nmax > 0) fetch(0, ea, ca);
+    for (int b0 = 0; b0 < nmax; b0 += 32) {
+      fetch(b0 + 16, eb, cb);
+      walk_round(b0, ea, ca);
+      if (b0 + 16 >= nmax) break;
+      fetch(b0 + 32, ea, ca);
+      walk_round(b0 + 16, eb, cb);
     }
     __builtin_amdgcn_wave_barrier();
   }
