@@ -135,7 +135,8 @@ cgh_status setup(const cgh_config *cfg, cgh::Ctx *c) {
   c->num_tiles = B * c->tiles_per;
   int bits = 0;
   while ((1 << bits) < c->num_tiles) ++bits;
-  c->sort_passes = (bits + kSortBits - 1) / kSortBits;
+  // at least one pass: the last pass also writes the tile ranges
+  c->sort_passes = std::max(1, (bits + kSortBits - 1) / kSortBits);
   // about 3 (16 x 16) to 7 (8 x 8) tiles per Gaussian at the synthetic scales
   const int64_t per = tw * th <= 64 ? 16 : 8;
   int64_t cap = f.max_pairs ? f.max_pairs : per * B * f.max_gaussians + 65536;
@@ -224,8 +225,12 @@ size_t carve(Ctx *c, char *base) {
     c->vals[b] = (uint32_t *)take(sizeof(uint32_t) * cap);
   }
   c->ranges = (uint2 *)take(sizeof(uint2) * c->num_tiles);
-  c->hist = (uint32_t *)take(sizeof(uint32_t) * 256 * (size_t)c->sort_blocks);
-  const size_t scan_len = std::max(N + 1, (size_t)256 * c->sort_blocks);
+  // the first sort pass counts per preprocess workgroup (256 Gaussians), the
+  // later passes per sort block
+  const size_t hist_blocks = std::max((size_t)c->sort_blocks, (N + 255) / 256);
+  c->hist = (uint32_t *)take(sizeof(uint32_t) * 256 * hist_blocks);
+  const size_t scan_len = std::max(N + 1, (size_t)256 * hist_blocks);
+  c->hist_chunks = (uint32_t *)take(sizeof(uint32_t) * (scan_len / kScanItems + 2));
   // chunk sums: per kScanItems of a scan, or per preprocess workgroup (256 Gaussians)
   c->scan_tmp = (uint32_t *)take(sizeof(uint32_t) *
                                  std::max(scan_len / kScanItems + 2, (N + 255) / 256 + 2));

@@ -128,7 +128,9 @@ struct Ctx {
   uint32_t *offsets;                // [B max_gaussians + 1]
   uint32_t *keys[2], *vals[2];      // [pair_cap] ping-pong (tile id, Gaussian id)
   uint2 *ranges;                    // [num_tiles] [start, end) into the sorted list
-  uint32_t *hist;                   // [256 * sort_blocks] digit-major block histograms
+  uint32_t *hist;                   // digit-major block histograms: [256 * max(sort_blocks,
+                                    // preprocess workgroups)]
+  uint32_t *hist_chunks;            // chunk sums of the histogram scans
   uint32_t *scan_tmp;               // partial sums for scans
   float *partials;                  // [pair_cap][part_stride] raster-adjoint partials
   double *loss_part;                // [L][row-pass workgroups] FP64 loss partials (the

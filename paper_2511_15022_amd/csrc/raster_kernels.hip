@@ -139,7 +139,8 @@ __device__ __forceinline__ uint32_t preprocess_one(const float *__restrict__ par
                                                    uint2 *__restrict__ rect,
                                                    uint32_t *__restrict__ counts, float thr,
                                                    float2 *__restrict__ alim,
-                                                   uint32_t *__restrict__ finite_flag) {
+                                                   uint32_t *__restrict__ finite_flag,
+                                                   uint2 &rc_out) {
   constexpr int RS = rec_stride_c(C);
   const GaussIdx gi = gauss_idx<C>(g, n);
   const float *params = params_all + gi.base;
@@ -203,6 +204,7 @@ __device__ __forceinline__ uint32_t preprocess_one(const float *__restrict__ par
   for (int i = 0; i < RS / 4; ++i) dst[i] = make_float4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
   counts[g] = cnt;
   rect[g] = rc;
+  rc_out = rc;
   if (alim) {
     // Alg. 2 weight w = min(0.99, alpha G), kept where alpha G >= 1/255: in the
     // exponent p = log2 G, kept for p >= max(support threshold, log2(1/(255 alpha)))
@@ -216,8 +218,11 @@ __device__ __forceinline__ uint32_t preprocess_one(const float *__restrict__ par
 // The preprocess of 256 Gaussians per workgroup, which also starts the
 // binning: the workgroup's exclusive scan of its tile counts goes to
 // offsets[g] and its total to chunk_sums[workgroup] (the emit adds the totals
-// of the workgroups before its own), and workgroup 0 clears the overflow flag
-// of this rasterize (*overflow).
+// of the workgroups before its own), the histogram of the first sort digit
+// (tile id & 255) over the workgroup's pairs to hist1[digit * workgroups +
+// workgroup], every tile range is set to (0xffffffff, 0) (the last sort pass
+// narrows them with atomic min / max), and workgroup 0 clears the overflow
+// flag of this rasterize (*overflow).
 template <int C>
 __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ params_all, int n,
                                                     int total, int W, int H, float k, int tlx,
@@ -228,17 +233,38 @@ __global__ __launch_bounds__(256) void k_preprocess(const float *__restrict__ pa
                                                     uint32_t *__restrict__ finite_flag,
                                                     uint32_t *__restrict__ offsets,
                                                     uint32_t *__restrict__ chunk_sums,
-                                                    uint32_t *__restrict__ overflow) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+                                                    uint32_t *__restrict__ overflow,
+                                                    int tiles_x, int tiles_per,
+                                                    uint32_t *__restrict__ hist1,
+                                                    uint2 *__restrict__ ranges, int num_tiles) {
+  __shared__ uint32_t h1[256];
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x * blockDim.x + tid;
+  for (int t = blockIdx.x * blockDim.x + tid; t < num_tiles; t += gridDim.x * blockDim.x)
+    ranges[t] = make_uint2(0xffffffffu, 0u);
+  h1[tid] = 0u;
   uint32_t cnt = 0;
+  uint2 rc = make_uint2(0u, 0u);
   if (g < total)
     cnt = preprocess_one<C>(params_all, n, g, W, H, k, tlx, tly, rec, rect, counts, thr, alim,
-                            finite_flag);
+                            finite_flag, rc);
   uint32_t sum;
   const uint32_t pre = block_exclusive_scan(cnt, &sum);  // every thread takes part
   if (g < total) offsets[g] = pre;
-  if (threadIdx.x == 0) chunk_sums[blockIdx.x] = sum;
+  if (tid == 0) chunk_sums[blockIdx.x] = sum;
   if (g == 0) *overflow = 0u;
+  // (the scan's barriers order the clearing of h1 before the counting)
+  if (cnt) {
+    const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
+    const uint32_t kb = (uint32_t)(g / n) * (uint32_t)tiles_per;
+    uint32_t tx = tx0, ty = ty0;
+    for (uint32_t t = 0; t < cnt; ++t) {
+      atomicAdd(&h1[(kb + ty * (uint32_t)tiles_x + tx) & 255u], 1u);
+      if (++tx > tx1) { tx = tx0; ++ty; }
+    }
+  }
+  __syncthreads();
+  hist1[(size_t)tid * gridDim.x + blockIdx.x] = h1[tid];
 }
 
 static float support_threshold(float k) {
@@ -262,7 +288,8 @@ hipError_t launch_preprocess(const Ctx &c, const float *params, int n, hipStream
 #define CGH_PRE(CC)                                                                           \
   hipLaunchKernelGGL(k_preprocess<CC>, grid, block, 0, s, params, n, total, c.W, c.H, k, tlx, \
                      tly, c.rec, c.rect, c.counts, thr, c.alim, c.finite_flag, c.offsets,     \
-                     c.scan_tmp, c.status)
+                     c.scan_tmp, c.status, c.tiles_x, c.tiles_per, c.hist, c.ranges,          \
+                     c.num_tiles)
   switch (c.C) {
     case 1: CGH_PRE(1); break;
     case 2: CGH_PRE(2); break;
@@ -343,57 +370,6 @@ static hipError_t scan_u32(const uint32_t *in, uint32_t *out, int len, uint32_t 
 // ----------------------------------------------------------------------------
 // Binning: emit (tile, gaussian) pairs, stable radix sort, tile ranges.
 // ----------------------------------------------------------------------------
-// Pairs of Gaussian g go to [offset(g), offset(g) + count(g)) in row-major
-// tile order; the key of tile (tx, ty) of hologram b = g / n_per is
-// b tiles_per + ty tiles_x + tx.  offsets[] holds the exclusive scans within
-// the preprocess workgroups (256 Gaussians, the same as an emit workgroup's)
-// and chunk_sums their (unscanned) totals: each workgroup adds the totals of
-// the workgroups before its own, and workgroup 0 writes the grand total to
-// offsets[n] and to the pair total status[1]; the final offset is written
-// back for the adjoint.
-__global__ __launch_bounds__(256) void k_emit(int n, int n_per, int tiles_per,
-                                              const uint32_t *__restrict__ counts,
-                                              uint32_t *__restrict__ offsets,
-                                              const uint32_t *__restrict__ chunk_sums,
-                                              int nchunks, const uint2 *__restrict__ rect,
-                                              int tiles_x, int64_t cap,
-                                              uint32_t *__restrict__ keys,
-                                              uint32_t *__restrict__ vals,
-                                              uint32_t *__restrict__ status) {
-  const int upto = blockIdx.x == 0 ? nchunks : (int)blockIdx.x;
-  uint32_t part = 0;
-  for (int k = threadIdx.x; k < upto; k += 256) part += chunk_sums[k];
-  uint32_t total;
-  block_exclusive_scan(part, &total);  // every thread of the workgroup takes part
-  const uint32_t prefix = blockIdx.x == 0 ? 0u : total;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    offsets[n] = total;
-    status[1] = total;
-  }
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const uint32_t cnt = counts[g];
-  const uint32_t off32 = offsets[g] + prefix;
-  offsets[g] = off32;
-  if (cnt == 0) return;
-  const uint64_t off = off32;
-  const uint2 rc = rect[g];
-  const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
-  const uint32_t kb = (uint32_t)(g / n_per) * (uint32_t)tiles_per;
-  uint32_t tx = tx0, ty = ty0;
-  for (uint32_t t = 0; t < cnt; ++t) {
-    const uint64_t pos = off + t;
-    if ((int64_t)pos >= cap) {
-      atomicOr(&status[0], 1u);  // this rasterize
-      atomicOr(&status[2], 1u);  // sticky until the next status read
-      break;
-    }
-    keys[pos] = kb + ty * (uint32_t)tiles_x + tx;
-    vals[pos] = (uint32_t)g;
-    if (++tx > tx1) { tx = tx0; ++ty; }
-  }
-}
-
 __device__ __forceinline__ uint32_t pair_count(const uint32_t *status, int64_t cap) {
   const uint64_t total = status[1];
   return (uint32_t)((int64_t)total < cap ? total : cap);
@@ -437,6 +413,11 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
 // hist_scan holds the digit-major histogram scanned either globally
 // (chunk_sums == nullptr) or per chunk of kScanItems, with the chunk sums in
 // chunk_sums (at most kMaxScanChunks); then each block scans the chunk sums.
+// The last pass (ranges != nullptr) writes no keys: a block's keys, in the
+// order it writes them, are sorted (its input is sorted on the lower digits),
+// so each run of one tile id in it is a piece of that tile's final list, and
+// the block takes the tile's range to the piece's first and last positions
+// with atomic min / max (every tile's range starts as (0xffffffff, 0)).
 constexpr int kMaxScanChunks = 1024;
 
 __global__ __launch_bounds__(256) void k_radix_scatter(
@@ -444,7 +425,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
     const uint32_t *__restrict__ status, int64_t cap, int shift,
     const uint32_t *__restrict__ hist_scan, int nblocks,
-    const uint32_t *__restrict__ chunk_sums, int nchunks) {
+    const uint32_t *__restrict__ chunk_sums, int nchunks, uint2 *__restrict__ ranges,
+    uint32_t num_tiles) {
   constexpr int R = kSortItems / 256;  // rounds of 64 keys per wave
   __shared__ uint32_t wcnt[4][256];    // per-wave digit counts, then local offsets
   __shared__ uint32_t gofs[256];       // global position of local index 0 of each digit
@@ -537,38 +519,193 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
       const uint32_t k = skey[i];
       const uint32_t pos = gofs[(k >> shift) & 255u] + i;
       if (pos < count) {  // always true for a consistent histogram; guards the write
-        kout[pos] = k;
         vout[pos] = sval[i];
+        if (!ranges) {
+          kout[pos] = k;
+        } else if (k < num_tiles) {  // keys are tile ids; guards the atomics
+          if (i == 0 || skey[i - 1] != k) atomicMin(&ranges[k].x, pos);
+          if (i + 1 == nvalid || skey[i + 1] != k) atomicMax(&ranges[k].y, pos + 1u);
+        }
       }
     }
   }
 }
 
-// Tile ranges from the sorted keys; each tile without pairs gets an empty
-// range from the thread at the gap it falls in (every tile is written once).
-// A grid-stride loop: the grid is sized for the pair capacity's worth of
-// blocks at most, far fewer than one thread per pair.
-__global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ status,
-                         int64_t cap, uint2 *__restrict__ ranges, uint32_t num_tiles) {
-  const uint32_t count = pair_count(status, cap);
-  const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (count == 0) {
-    if (i0 == 0)
-      for (uint32_t t = 0; t < num_tiles; ++t) ranges[t] = make_uint2(0u, 0u);
-    return;
-  }
-  for (uint32_t i = i0; i < count; i += gridDim.x * blockDim.x) {
-    const uint32_t k = keys[i];
-    if (k >= num_tiles) continue;  // keys are tile ids; guards the writes
-    if (i == 0 || keys[i - 1] != k) {
-      ranges[k].x = i;
-      const uint32_t prev = i == 0 ? 0u : keys[i - 1] + 1u;
-      for (uint32_t t = prev; t < k; ++t) ranges[t] = make_uint2(0u, 0u);
+// The emit fused with the first sort pass.  Gaussian g's pairs own the pair
+// slots [offset(g), offset(g) + count(g)) in row-major tile order (the adjoint
+// writes its partial sums there); the key of tile (tx, ty) of hologram
+// b = g / n_per is b tiles_per + ty tiles_x + tx.  offsets[] holds the
+// exclusive scans within the preprocess workgroups (256 Gaussians, the same as
+// a workgroup here) and chunk_sums their totals: each workgroup adds the
+// totals of the workgroups before its own and writes the offsets back, and
+// workgroup 0 writes the grand total to offsets[n] and to the pair total
+// status[1] (and flags an overflow of the pair capacity).  The workgroup then
+// lays its pairs out in LDS in slot order, kEmitChunk at a time, and sorts
+// them on the first digit exactly as k_radix_scatter does, with the
+// preprocess's digit histogram of the workgroup (hist_scan: scanned, digit-
+// major over the workgroups; per chunk of kScanItems with the chunk sums in
+// hchunk_sums, or globally when hchunk_sums is null).  A pair's position is
+// below the pair total, and positions at or past the capacity are dropped.
+// ranges != nullptr: this is also the last pass (one digit covers every tile
+// id), and it narrows the tile ranges as the last pass of k_radix_scatter does.
+constexpr int kEmitChunk = 1024;  // 8 workgroups per CU fit in LDS
+
+__global__ __launch_bounds__(256) void k_emit_sort(
+    int n, int n_per, int tiles_per, const uint32_t *__restrict__ counts,
+    uint32_t *__restrict__ offsets, const uint32_t *__restrict__ chunk_sums, int nchunks,
+    const uint2 *__restrict__ rect, int tiles_x, int64_t cap,
+    const uint32_t *__restrict__ hist_scan, const uint32_t *__restrict__ hchunk_sums,
+    int hnchunks, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+    uint32_t *__restrict__ status, uint2 *__restrict__ ranges, uint32_t num_tiles) {
+  constexpr int R = kEmitChunk / 256;  // rounds of 64 pairs per wave
+  __shared__ uint32_t wcnt[4][256];    // per-wave digit counts, then local offsets
+  __shared__ uint32_t dnext[256];      // global position of the workgroup's next pair of each digit
+  __shared__ uint32_t gofs[256];       // global position of local index 0 of each digit
+  // the pairs of a chunk (keys, then values); before the first chunk, the
+  // scanned chunk sums of the histogram
+  __shared__ uint32_t spair[2 * kEmitChunk];
+  static_assert(2 * kEmitChunk >= kMaxScanChunks, "room for the chunk sums");
+  uint32_t *skey = spair, *sval = spair + kEmitChunk, *cpre = spair;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = gridDim.x;
+  const int upto = blockIdx.x == 0 ? nchunks : (int)blockIdx.x;
+  uint32_t part = 0;
+  for (int k = tid; k < upto; k += 256) part += chunk_sums[k];
+  uint32_t total;
+  block_exclusive_scan(part, &total);  // every thread of the workgroup takes part
+  const uint32_t prefix = blockIdx.x == 0 ? 0u : total;
+  if (blockIdx.x == 0 && tid == 0) {
+    offsets[n] = total;
+    status[1] = total;
+    if ((int64_t)total > cap) {
+      status[0] |= 1u;  // this rasterize
+      status[2] |= 1u;  // sticky until the next status read
     }
-    if (i + 1 == count || keys[i + 1] != k) {
-      ranges[k].y = i + 1;
-      if (i + 1 == count)
-        for (uint32_t t = k + 1; t < num_tiles; ++t) ranges[t] = make_uint2(0u, 0u);
+  }
+  const uint32_t npairs = chunk_sums[blockIdx.x];  // this workgroup's pairs
+  const int g = blockIdx.x * 256 + tid;
+  uint32_t cnt = 0, loc = 0, tx0 = 0, tx1 = 0, ty0 = 0, kb = 0;
+  if (g < n) {
+    cnt = counts[g];
+    loc = offsets[g];
+    offsets[g] = loc + prefix;
+    const uint2 rc = rect[g];
+    tx0 = rc.x & 0xffffu; tx1 = rc.x >> 16; ty0 = rc.y & 0xffffu;
+    kb = (uint32_t)(g / n_per) * (uint32_t)tiles_per;
+  }
+  if (hchunk_sums) {
+    // exclusive scan of the histogram's chunk sums, four per thread
+    uint32_t c4[4], sum = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = tid * 4 + e;
+      c4[e] = sum;
+      sum += i < hnchunks ? hchunk_sums[i] : 0u;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(sum, &tot);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) cpre[tid * 4 + e] = ex + c4[e];
+    __syncthreads();
+  }
+  {
+    const size_t e = (size_t)tid * nb + blockIdx.x;
+    dnext[tid] = hist_scan[e] + (hchunk_sums ? cpre[e / kScanItems] : 0u);
+  }
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t w = tx1 - tx0 + 1;
+  for (uint32_t c0 = 0; c0 < npairs; c0 += kEmitChunk) {  // uniform
+    const uint32_t nvalid = min((uint32_t)kEmitChunk, npairs - c0);
+    __syncthreads();  // the previous chunk's LDS reads are done
+    // this Gaussian's pairs whose slots fall in [c0, c0 + nvalid), in slot order
+    if (cnt && loc < c0 + nvalid && loc + cnt > c0) {
+      const uint32_t t0 = c0 > loc ? c0 - loc : 0u, t1 = min(cnt, c0 + nvalid - loc);
+      uint32_t ty = ty0 + t0 / w, tx = tx0 + t0 % w;
+      for (uint32_t t = t0; t < t1; ++t) {
+        skey[loc + t - c0] = kb + ty * (uint32_t)tiles_x + tx;
+        sval[loc + t - c0] = (uint32_t)g;
+        if (++tx > tx1) { tx = tx0; ++ty; }
+      }
+    }
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) wcnt[ww][tid] = 0;
+    __syncthreads();
+    // ranks: wave w owns local indices 64 q w + (0 .. 64 q - 1), 64 at a time in
+    // index order, with q = ceil(nvalid / 256) <= R rounds per wave
+    const uint32_t q = (nvalid + 255u) / 256u;
+    const uint32_t first = 64u * q * wave + lane;
+    uint32_t key[R], val[R], rank[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      key[r] = 0u;
+      val[r] = 0u;
+      rank[r] = 0u;
+      if ((uint32_t)r >= q) continue;  // uniform
+      const uint32_t i = first + 64u * r;
+      const bool valid = i < nvalid;
+      key[r] = valid ? skey[i] : 0u;
+      val[r] = valid ? sval[i] : 0u;
+      const uint32_t d = key[r] & 255u;
+      uint64_t m = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const uint64_t bb = __ballot(on);
+        m &= on ? bb : ~bb;
+      }
+      const uint32_t before = __popcll(m & lt);
+      const uint32_t prev = wcnt[wave][d];
+      rank[r] = prev + before;
+      // the lowest lane of each digit group advances the wave's count; this
+      // wave's LDS accesses complete in order, so the next round reads it
+      if (valid && before == 0) wcnt[wave][d] = prev + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    {
+      // thread tid = digit d: the chunk's local offsets of d per wave, and the
+      // global position of d's local index 0
+      uint32_t c[4], tot = 0;
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) { c[ww] = wcnt[ww][tid]; tot += c[ww]; }
+      uint32_t all;
+      const uint32_t lbase = block_exclusive_scan(tot, &all);
+      uint32_t run = lbase;
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        wcnt[ww][tid] = run;
+        run += c[ww];
+      }
+      gofs[tid] = dnext[tid] - lbase;
+      dnext[tid] += tot;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if ((uint32_t)r < q && first + 64u * r < nvalid) {
+        const uint32_t lp = wcnt[wave][key[r] & 255u] + rank[r];
+        if (lp < (uint32_t)kEmitChunk) {  // always true for consistent counts; guards the write
+          skey[lp] = key[r];
+          sval[lp] = val[r];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = (uint32_t)tid + 256u * r;
+      if ((uint32_t)r < q && i < nvalid) {
+        const uint32_t k = skey[i];
+        const uint32_t pos = gofs[k & 255u] + i;
+        if ((int64_t)pos < cap) {  // drops what is past the capacity
+          vout[pos] = sval[i];
+          if (!ranges) {
+            kout[pos] = k;
+          } else if (k < num_tiles) {  // keys are tile ids; guards the atomics
+            if (i == 0 || skey[i - 1] != k) atomicMin(&ranges[k].x, pos);
+            if (i + 1 == nvalid || skey[i + 1] != k) atomicMax(&ranges[k].y, pos + 1u);
+          }
+        }
+      }
     }
   }
 }
@@ -600,45 +737,57 @@ hipError_t launch_zero_status(const Ctx &c, hipStream_t s) {
 }
 
 hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
-  // status[0] (overflow) and status[1] (pair total) restart: the first scan
-  // kernel clears the flag and the emit kernel writes the total
+  // status[0] (overflow) and status[1] (pair total) restart: the preprocess
+  // clears the flag and the emit writes the total
   const int total = (int)total_gaussians(c, n);
-  if (total > 0) {
-    // the preprocess has scanned the counts per workgroup of 256 and cleared
-    // the overflow flag
-    const int nb = (total + 255) / 256;
-    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, total, n, c.tiles_per, c.counts,
-                       c.offsets, c.scan_tmp, nb, c.rect, c.tiles_x, c.pair_cap, c.keys[0],
-                       c.vals[0], c.status);
-  } else {
+  if (total <= 0) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c.status, 2);
+    const int words = 2 * c.num_tiles;  // every range empty: (0, 0)
+    hipLaunchKernelGGL(k_zero_u32, dim3((words + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t *>(c.ranges), words);
+    c.sorted = 0;
+    return hipGetLastError();
   }
-  const int hlen = 256 * c.sort_blocks;
-  const int nchunks = (hlen + kScanItems - 1) / kScanItems;
-  int cur = 0;
-  for (int pass = 0; pass < c.sort_passes; ++pass) {
+  // scans of the digit-major histograms: per chunk of kScanItems, each sort
+  // workgroup scanning the chunk sums itself, or globally for long histograms
+  auto scan_hist = [&](int hlen, const uint32_t **chunks, int *nchunks) -> hipError_t {
+    *nchunks = (hlen + kScanItems - 1) / kScanItems;
+    *chunks = nullptr;
+    if (*nchunks <= kMaxScanChunks) {
+      hipLaunchKernelGGL(k_scan_local, dim3(*nchunks), dim3(256), 0, s, c.hist, c.hist, hlen,
+                         c.hist_chunks, nullptr);
+      *chunks = c.hist_chunks;
+      return hipGetLastError();
+    }
+    return scan_u32(c.hist, c.hist, hlen, c.hist_chunks, nullptr, nullptr, s);
+  };
+  // first pass: the preprocess counted the first digit per workgroup of 256
+  // Gaussians; the emit sorts each workgroup's pairs on it
+  const int nb = (total + 255) / 256;
+  const uint32_t *chunks;
+  int nchunks;
+  hipError_t e = scan_hist(256 * nb, &chunks, &nchunks);
+  if (e != hipSuccess) return e;
+  bool last = c.sort_passes == 1;
+  hipLaunchKernelGGL(k_emit_sort, dim3(nb), dim3(256), 0, s, total, n, c.tiles_per, c.counts,
+                     c.offsets, c.scan_tmp, nb, c.rect, c.tiles_x, c.pair_cap, c.hist, chunks,
+                     nchunks, last ? nullptr : c.keys[1], c.vals[1], c.status,
+                     last ? c.ranges : nullptr, (uint32_t)c.num_tiles);
+  int cur = 1;
+  for (int pass = 1; pass < c.sort_passes; ++pass) {
     const int shift = pass * kSortBits;
     hipLaunchKernelGGL(k_radix_hist, dim3(c.sort_blocks), dim3(256), 0, s, c.keys[cur],
                        c.status, c.pair_cap, shift, c.hist, c.sort_blocks);
-    const uint32_t *chunks = nullptr;
-    if (nchunks <= kMaxScanChunks) {
-      // per-chunk scans only; each scatter block scans the chunk sums itself
-      hipLaunchKernelGGL(k_scan_local, dim3(nchunks), dim3(256), 0, s, c.hist, c.hist, hlen,
-                         c.scan_tmp, nullptr);
-      chunks = c.scan_tmp;
-    } else {
-      hipError_t e = scan_u32(c.hist, c.hist, hlen, c.scan_tmp, nullptr, nullptr, s);
-      if (e != hipSuccess) return e;
-    }
+    e = scan_hist(256 * c.sort_blocks, &chunks, &nchunks);
+    if (e != hipSuccess) return e;
+    last = pass + 1 == c.sort_passes;
     hipLaunchKernelGGL(k_radix_scatter, dim3(c.sort_blocks), dim3(256), 0, s, c.keys[cur],
-                       c.vals[cur], c.keys[cur ^ 1], c.vals[cur ^ 1], c.status, c.pair_cap,
-                       shift, c.hist, c.sort_blocks, chunks, nchunks);
+                       c.vals[cur], last ? nullptr : c.keys[cur ^ 1], c.vals[cur ^ 1], c.status,
+                       c.pair_cap, shift, c.hist, c.sort_blocks, chunks, nchunks,
+                       last ? c.ranges : nullptr, (uint32_t)c.num_tiles);
     cur ^= 1;
   }
   c.sorted = cur;
-  const int64_t grid = std::min<int64_t>((c.pair_cap + 255) / 256, (int64_t)c.num_cu * 8);
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, s, c.keys[cur], c.status,
-                     c.pair_cap, c.ranges, (uint32_t)c.num_tiles);
   return hipGetLastError();
 }
 
@@ -1159,13 +1308,16 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
   static_assert(TP % 64 == 0 && TW * C <= 64 * 4, "tile shape");
   // dL/dU0 of the tile, plus one row of zeros (row TH) that the padding
   // pixels of a pair's last segment read when they run past the tile's last row
-  __shared__ float2 sg[(TH + 1) * TW][C];
-  __shared__ float4 sq4[kAdjWaves][kAdjBatch * Q::N / 4];
+  // one LDS block, so that the staged tile starts at LDS address 0 and the
+  // walk's reads take their offsets as immediates
+  constexpr int kSg4 = ((TH + 1) * TW * C * 2 + 3) / 4, kSq4 = kAdjBatch * Q::N / 4;
+  __shared__ float4 lds4[kSg4 + kAdjWaves * kSq4];
+  float2 (*sg)[C] = reinterpret_cast<float2 (*)[C]>(lds4);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // each wave's own pair table: after the tile's dL/dU0 is staged, the waves
   // share nothing, and a wave's LDS operations execute in issue order
-  float *sq = reinterpret_cast<float *>(sq4[wave]);
+  float *sq = reinterpret_cast<float *>(lds4 + kSg4 + wave * kSq4);
   auto wave_sync = [] {
     if constexpr (kAdjWaves == 1) __syncthreads();
     else asm volatile("" ::: "memory");
@@ -1198,7 +1350,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint2 rg = ranges[tile];
   {
-    const uint32_t len = rg.y - rg.x;
+    // a tile without pairs has the range (0xffffffff, 0)
+    const uint32_t len = rg.y > rg.x ? rg.y - rg.x : 0u;
     rg = make_uint2(rg.x + (uint32_t)(((uint64_t)len * wave) / kAdjWaves),
                     rg.x + (uint32_t)(((uint64_t)len * (wave + 1)) / kAdjWaves));
   }
@@ -1284,7 +1437,16 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
         if (t < np && __float_as_int(sq[t * Q::N + Q::START]) <= s0) j = t;
       }
       float offx, offy, qa, qb, qc, amp[2 * C], plo = 0.f, phi = 0.f;
-      int bxa, bxb, lx, ly, sj, left, span = 0;
+      // the walk's pixel: tile-local column and row as exact FP32 integers, the
+      // LDS byte offset of its dL/dU0, and the box's first and last column
+      float fx, fy, fxa, fxb;
+      uint32_t la, lwrap;  // lwrap: the offset step from a box row's end to the next row
+      int bxa, bxb, bya, sj, left, span = 0;
+      auto set_pixel = [&](int x, int y) {
+        fx = (float)x;
+        fy = (float)y;
+        la = (uint32_t)((y * TW + x) * C) * (uint32_t)sizeof(float2);
+      };
       auto load_pair = [&](int jj) {
         const float *q = sq + jj * Q::N;
         offx = q[0]; offy = q[1];
@@ -1294,10 +1456,14 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
         for (int k = 0; k < 2 * C; ++k) amp[k] = q[Q::AMP + k];
         const int bx = __float_as_int(q[Q::BOX]);
         bxa = bx & 0xff; bxb = (bx >> 8) & 0xff;
-        const int bya = (bx >> 16) & 0xff, byb = (bx >> 24) & 0xff;
+        bya = (bx >> 16) & 0xff;
+        const int byb = (bx >> 24) & 0xff;
         sj = __float_as_int(q[Q::START]);
         left = ((bxb - bxa + 1) * (byb - bya + 1) + kAdjSeg - 1) / kAdjSeg;
-        lx = bxa; ly = bya;
+        fxa = (float)bxa;
+        fxb = (float)bxb;
+        lwrap = (uint32_t)((TW - (bxb - bxa)) * C) * (uint32_t)sizeof(float2);
+        set_pixel(bxa, bya);
       };
       auto flush_global = [&](int jj, const float *v) {
         const uint32_t sl = __float_as_uint(sq[jj * Q::N + Q::SLOT]);
@@ -1320,8 +1486,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
         {
           const int skip = s0 - sj, o = skip * kAdjSeg, wb = bxb - bxa + 1;
           const int oy = o / wb;
-          ly += oy;
-          lx = bxa + (o - oy * wb);
+          set_pixel(bxa + (o - oy * wb), bya + oy);
           left -= skip;
         }
         for (int s = s0; s < s1; ++s) {
@@ -1342,8 +1507,9 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
           for (int u = 0; u < kAdjSeg; ++u) {
             // The last segment of a pair is padded: its padding pixels run on
             // along the box rows, below the box (outside the support, so G = 0)
-            // or below the tile (the zero row, so every term is 0).
-            const float dy = (float)ly + offy, dx = (float)lx + offx;
+            // or below the tile (every offset from the zero row on reads the
+            // zero row, so every term is 0).
+            const float dy = fy + offy, dx = fx + offx;
             const float p2 = fmaf(dx, fmaf(qa, dx, qb * dy), qc * dy * dy);
             float G;
             if (PA)
@@ -1351,9 +1517,9 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
             else
               G = p2 >= thr ? __builtin_amdgcn_exp2f(CLAMP ? fmaxf(p2, kPowerFloor2) : p2)
                             : 0.f;
-            // 24-bit multiply (full rate) for the LDS offset
-            const float2 *gv =
-                &sg[0][0] + __umul24((unsigned)(min(ly, TH) * TW + lx), (unsigned)C);
+            const float2 *gv = reinterpret_cast<const float2 *>(
+                reinterpret_cast<const char *>(&sg[0][0]) +
+                min(la, (uint32_t)(TP * C * sizeof(float2))));
             float gp = 0.f;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -1378,7 +1544,11 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
             S[2 * C + 2] = fmaf(wx, dx, S[2 * C + 2]);
             S[2 * C + 3] = fmaf(wx, dy, S[2 * C + 3]);
             S[2 * C + 4] = fmaf(wy, dy, S[2 * C + 4]);
-            if (++lx > bxb) { lx = bxa; ++ly; }
+            const float fx1 = fx + 1.f;
+            const bool wrap = fx1 > fxb;
+            fx = wrap ? fxa : fx1;
+            fy = wrap ? fy + 1.f : fy;
+            la += wrap ? lwrap : (uint32_t)(C * sizeof(float2));
           }
           --left;
         }
