@@ -1799,25 +1799,47 @@ __global__ __launch_bounds__(256) void k_preprocess_adj_adam(
   __syncthreads();  // every thread reaches it: no early return above
   const int cnt = min(256, total - g0);
   // element e of the workgroup's share of parameter block a (per-Gaussian
-  // width w_a: 2, 2, 1, C, C, 1) is component e % w_a of Gaussian e / w_a
-  int kbase = 0;
+  // width w_a: 2, 2, 1, C, C, 1) is component e % w_a of Gaussian e / w_a;
+  // with cnt <= 256 a thread takes elements tid + 256 r, r < w_a, of block a:
+  // NPAR in all, whose operands are all loaded before the first update
+  constexpr int wid[6] = {2, 2, 1, C, C, 1};
+  size_t off[NPAR];
+  float pk[NPAR], mk[NPAR], vk[NPAR], gk[NPAR];
+  bool ok[NPAR];
+  {
+    int kbase = 0;
 #pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    constexpr int wid[6] = {2, 2, 1, C, C, 1};
-    const int w = wid[a];
-    for (int e = tid; e < cnt * w; e += 256) {
-      const int j = e / w, comp = e - j * w;
-      const GaussIdx gi = gauss_idx<C>(g0 + j, n);
-      const size_t o = gi.base + param_offset<C>(kbase + comp, gi.gl, n);
-      const float gk = sgv[kbase + comp][j];
-      float pk = params_all[o], mk = adam.m[o], vk = adam.v[o];
-      adam_one(pk, gk, mk, vk, adam.lr_scaled, adam.b1, adam.b2, adam.eps, adam.inv_sqrt_bc2);
-      params_all[o] = pk;
-      adam.m[o] = mk;
-      adam.v[o] = vk;
-      if (grads_all) grads_all[o] = gk;
+    for (int a = 0; a < 6; ++a) {
+      const int w = wid[a];
+#pragma unroll
+      for (int r = 0; r < w; ++r) {
+        const int sl = kbase + r, e = tid + 256 * r;
+        ok[sl] = e < cnt * w;
+        off[sl] = 0;
+        pk[sl] = mk[sl] = vk[sl] = gk[sl] = 0.f;
+        if (ok[sl]) {
+          const int j = e / w, comp = e - j * w;
+          const GaussIdx gi = gauss_idx<C>(g0 + j, n);
+          off[sl] = gi.base + param_offset<C>(kbase + comp, gi.gl, n);
+          gk[sl] = sgv[kbase + comp][j];
+          pk[sl] = params_all[off[sl]];
+          mk[sl] = adam.m[off[sl]];
+          vk[sl] = adam.v[off[sl]];
+        }
+      }
+      kbase += w;
     }
-    kbase += w;
+  }
+#pragma unroll
+  for (int sl = 0; sl < NPAR; ++sl) {
+    if (ok[sl]) {
+      adam_one(pk[sl], gk[sl], mk[sl], vk[sl], adam.lr_scaled, adam.b1, adam.b2, adam.eps,
+               adam.inv_sqrt_bc2);
+      params_all[off[sl]] = pk[sl];
+      adam.m[off[sl]] = mk[sl];
+      adam.v[off[sl]] = vk[sl];
+      if (grads_all) grads_all[off[sl]] = gk[sl];
+    }
   }
 }
 
