@@ -1742,6 +1742,16 @@ __device__ __forceinline__ size_t param_offset(int k, int g, int n) {
   return (size_t)(5 + 2 * C) * n + g;
 }
 
+// the 6 + 2C parameters of Gaussian gg, as the parameter block of a single
+// Gaussian (n = 1), so that they can be loaded before they are needed
+template <int C>
+__device__ __forceinline__ void load_one_gaussian(const float *params_all, int n, int gg,
+                                                  float (&lp)[6 + 2 * C]) {
+  const GaussIdx gi = gauss_idx<C>(gg, n);
+#pragma unroll
+  for (int k = 0; k < 6 + 2 * C; ++k) lp[k] = params_all[gi.base + param_offset<C>(k, gi.gl, n)];
+}
+
 template <int C, bool PA>
 __global__ __launch_bounds__(256) void k_preprocess_adj(
     const float *__restrict__ params_all, int n, int total, int W, int H,
@@ -1750,11 +1760,13 @@ __global__ __launch_bounds__(256) void k_preprocess_adj(
     uint32_t *__restrict__ finite_flag) {
   __shared__ float4 chunk4[kPairChunk * part_stride_c(C) / 4];
   const int g0 = blockIdx.x * 256, gg = g0 + threadIdx.x;
+  float lp[6 + 2 * C];
+  if (gg < total) load_one_gaussian<C>(params_all, n, gg, lp);
   double S[kPairSums<C, PA>];
   pair_sums_block<C, PA>(g0, total, counts, offsets, cap, partials, chunk4, S);
   if (gg >= total) return;
   float gv[6 + 2 * C];
-  gaussian_grads<C, PA>(params_all, n, W, H, gg, S, gv);
+  gaussian_grads<C, PA>(lp, 1, W, H, 0, S, gv);
   const GaussIdx gi = gauss_idx<C>(gg, n);
   bool finite = true;
 #pragma unroll
@@ -1783,25 +1795,16 @@ __global__ __launch_bounds__(256) void k_preprocess_adj_adam(
   const int tid = threadIdx.x;
   const int g0 = blockIdx.x * 256;
   const int gg = g0 + tid;
+  float lp[NPAR];
+  if (gg < total) load_one_gaussian<C>(params_all, n, gg, lp);
   double S[kPairSums<C, PA>];
   pair_sums_block<C, PA>(g0, total, counts, offsets, cap, partials, chunk4, S);
-  if (gg < total) {
-    float gv[NPAR];
-    gaussian_grads<C, PA>(params_all, n, W, H, gg, S, gv);
-    bool finite = true;
-#pragma unroll
-    for (int k = 0; k < NPAR; ++k) {
-      finite = finite && isfinite(gv[k]);
-      sgv[k][tid] = gv[k];
-    }
-    if (finite_flag && !finite) atomicOr(finite_flag, kNonFiniteGrads);
-  }
-  __syncthreads();  // every thread reaches it: no early return above
   const int cnt = min(256, total - g0);
   // element e of the workgroup's share of parameter block a (per-Gaussian
   // width w_a: 2, 2, 1, C, C, 1) is component e % w_a of Gaussian e / w_a;
   // with cnt <= 256 a thread takes elements tid + 256 r, r < w_a, of block a:
-  // NPAR in all, whose operands are all loaded before the first update
+  // NPAR in all, whose parameters and moments are all loaded before the chain
+  // rule, which hides their latency
   constexpr int wid[6] = {2, 2, 1, C, C, 1};
   size_t off[NPAR];
   float pk[NPAR], mk[NPAR], vk[NPAR], gk[NPAR];
@@ -1816,16 +1819,41 @@ __global__ __launch_bounds__(256) void k_preprocess_adj_adam(
         const int sl = kbase + r, e = tid + 256 * r;
         ok[sl] = e < cnt * w;
         off[sl] = 0;
-        pk[sl] = mk[sl] = vk[sl] = gk[sl] = 0.f;
+        pk[sl] = mk[sl] = vk[sl] = 0.f;
         if (ok[sl]) {
           const int j = e / w, comp = e - j * w;
           const GaussIdx gi = gauss_idx<C>(g0 + j, n);
           off[sl] = gi.base + param_offset<C>(kbase + comp, gi.gl, n);
-          gk[sl] = sgv[kbase + comp][j];
           pk[sl] = params_all[off[sl]];
           mk[sl] = adam.m[off[sl]];
           vk[sl] = adam.v[off[sl]];
         }
+      }
+      kbase += w;
+    }
+  }
+  if (gg < total) {
+    float gv[NPAR];
+    gaussian_grads<C, PA>(lp, 1, W, H, 0, S, gv);
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < NPAR; ++k) {
+      finite = finite && isfinite(gv[k]);
+      sgv[k][tid] = gv[k];
+    }
+    if (finite_flag && !finite) atomicOr(finite_flag, kNonFiniteGrads);
+  }
+  __syncthreads();  // every thread reaches it: no early return above
+  {
+    int kbase = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      const int w = wid[a];
+#pragma unroll
+      for (int r = 0; r < w; ++r) {
+        const int sl = kbase + r, e = tid + 256 * r;
+        const int j = e / w, comp = e - j * w;
+        gk[sl] = ok[sl] ? sgv[kbase + comp][j] : 0.f;
       }
       kbase += w;
     }
