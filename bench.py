@@ -1013,7 +1013,7 @@ def main():
             r.update(profile_figures(cls, npairs * per_pair, 1e12, FP32_VALU_PEAK_TFLOPS,
                                      t_launch))
             return r
-        label = {"binning": "latency (integer sort, eight short launches)",
+        label = {"binning": "latency (integer sort, five short launches)",
                  "loss": "latency (one-block FP64 reduction)"}.get(cls, "latency")
         return {"kernel": cls, "bound": label}
 
