@@ -1273,6 +1273,7 @@ hipError_t launch_raster_fwd(const Ctx &c, float2 *field, hipStream_t s) {
 // ----------------------------------------------------------------------------
 constexpr int kAdjBatch = 64;
 constexpr int kAdjSeg = 8;    // pixels per segment
+constexpr int kAdjRowPad = 1;  // float2 of padding after each staged tile row (bank spread)
 constexpr int kAdjWaves = 3;  // waves per tile; wave w takes part w of kAdjWaves of the list
 
 // per-pair quantities kept in LDS for the walk (floats):
@@ -1307,12 +1308,15 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
   constexpr int TP = TW * TH;  // pixels of the tile
   static_assert(TP % 64 == 0 && TW * C <= 64 * 4, "tile shape");
   // dL/dU0 of the tile, plus one row of zeros (row TH) that the padding
-  // pixels of a pair's last segment read when they run past the tile's last row
-  // one LDS block, so that the staged tile starts at LDS address 0 and the
-  // walk's reads take their offsets as immediates
-  constexpr int kSg4 = ((TH + 1) * TW * C * 2 + 3) / 4, kSq4 = kAdjBatch * Q::N / 4;
+  // pixels of a pair's last segment read when they run past the tile's last
+  // row; pixel (x, y) channel c at float2 y RS2 + x C + c (RS2: the row
+  // stride, kAdjRowPad float2 longer than a row).  One LDS block, so that the
+  // staged tile starts at LDS address 0 and the walk's reads take their
+  // offsets as immediates.
+  constexpr int RS2 = TW * C + kAdjRowPad;
+  constexpr int kSg4 = ((TH + 1) * RS2 * 2 + 3) / 4, kSq4 = kAdjBatch * Q::N / 4;
   __shared__ float4 lds4[kSg4 + kAdjWaves * kSq4];
-  float2 (*sg)[C] = reinterpret_cast<float2 (*)[C]>(lds4);
+  float2 *sg = reinterpret_cast<float2 *>(lds4);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // each wave's own pair table: after the tile's dL/dU0 is staged, the waves
@@ -1342,9 +1346,12 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = tid + NT * k;
-      if ((C * TP) % NT == 0 || i < C * TP) sg[i % TP][i / TP] = v[k];
+      if ((C * TP) % NT == 0 || i < C * TP) {
+        const int p = i % TP;
+        sg[(p / TW) * RS2 + (p % TW) * C + i / TP] = v[k];
+      }
     }
-    for (int i = tid; i < TW * C; i += NT) sg[TP + i / C][i % C] = make_float2(0.f, 0.f);
+    for (int i = tid; i < TW * C; i += NT) sg[TH * RS2 + i] = make_float2(0.f, 0.f);
   }
   if constexpr (kAdjWaves > 1) __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -1445,7 +1452,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
       auto set_pixel = [&](int x, int y) {
         fx = (float)x;
         fy = (float)y;
-        la = (uint32_t)((y * TW + x) * C) * (uint32_t)sizeof(float2);
+        la = (uint32_t)(y * RS2 + x * C) * (uint32_t)sizeof(float2);
       };
       auto load_pair = [&](int jj) {
         const float *q = sq + jj * Q::N;
@@ -1462,7 +1469,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
         left = ((bxb - bxa + 1) * (byb - bya + 1) + kAdjSeg - 1) / kAdjSeg;
         fxa = (float)bxa;
         fxb = (float)bxb;
-        lwrap = (uint32_t)((TW - (bxb - bxa)) * C) * (uint32_t)sizeof(float2);
+        lwrap = (uint32_t)(RS2 - (bxb - bxa) * C) * (uint32_t)sizeof(float2);
         set_pixel(bxa, bya);
       };
       auto flush_global = [&](int jj, const float *v) {
@@ -1518,8 +1525,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_raster_adj(
               G = p2 >= thr ? __builtin_amdgcn_exp2f(CLAMP ? fmaxf(p2, kPowerFloor2) : p2)
                             : 0.f;
             const float2 *gv = reinterpret_cast<const float2 *>(
-                reinterpret_cast<const char *>(&sg[0][0]) +
-                min(la, (uint32_t)(TP * C * sizeof(float2))));
+                reinterpret_cast<const char *>(sg) +
+                min(la, (uint32_t)(TH * RS2 * sizeof(float2))));
             float gp = 0.f;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
