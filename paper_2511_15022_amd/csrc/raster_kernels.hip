@@ -413,12 +413,16 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
 // hist_scan holds the digit-major histogram scanned either globally
 // (chunk_sums == nullptr) or per chunk of kScanItems, with the chunk sums in
 // chunk_sums (at most kMaxScanChunks); then each block scans the chunk sums.
-// The last pass (ranges != nullptr) writes no keys: a block's keys, in the
-// order it writes them, are sorted (its input is sorted on the lower digits),
-// so each run of one tile id in it is a piece of that tile's final list, and
-// the block takes the tile's range to the piece's first and last positions
-// with atomic min / max (every tile's range starts as (0xffffffff, 0)).
+// With ranges != nullptr (the last pass, up to kMaxAtomicRangeTiles tiles) no
+// keys are written: a block's keys, in the order it writes them, are sorted
+// (its input is sorted on the lower digits), so each run of one tile id in it
+// is a piece of that tile's final list, and the block takes the tile's range
+// to the piece's first and last positions with atomic min / max (every
+// tile's range starts as (0xffffffff, 0)).  A block holds about one piece per
+// value of its digit, so with many tiles the atomics cost more than a
+// separate ranges kernel (k_ranges).
 constexpr int kMaxScanChunks = 1024;
+constexpr int kMaxAtomicRangeTiles = 16384;
 
 __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
@@ -527,6 +531,32 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
           if (i + 1 == nvalid || skey[i + 1] != k) atomicMax(&ranges[k].y, pos + 1u);
         }
       }
+    }
+  }
+}
+
+// Tile ranges from the sorted keys, for contexts with more than
+// kMaxAtomicRangeTiles tiles; each tile without pairs gets an empty range
+// from the thread at the gap it falls in (every tile is written once).
+// A grid-stride loop: the grid is sized for the pair capacity's worth of
+// blocks at most, far fewer than one thread per pair.
+__global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ status,
+                         int64_t cap, uint2 *__restrict__ ranges, uint32_t num_tiles) {
+  const uint32_t count = pair_count(status, cap);
+  const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (count == 0) return;  // every range is still the preprocess's empty (0xffffffff, 0)
+  for (uint32_t i = i0; i < count; i += gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    if (k >= num_tiles) continue;  // keys are tile ids; guards the writes
+    if (i == 0 || keys[i - 1] != k) {
+      ranges[k].x = i;
+      const uint32_t prev = i == 0 ? 0u : keys[i - 1] + 1u;
+      for (uint32_t t = prev; t < k; ++t) ranges[t] = make_uint2(0u, 0u);
+    }
+    if (i + 1 == count || keys[i + 1] != k) {
+      ranges[k].y = i + 1;
+      if (i + 1 == count)
+        for (uint32_t t = k + 1; t < num_tiles; ++t) ranges[t] = make_uint2(0u, 0u);
     }
   }
 }
@@ -768,7 +798,8 @@ hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
   int nchunks;
   hipError_t e = scan_hist(256 * nb, &chunks, &nchunks);
   if (e != hipSuccess) return e;
-  bool last = c.sort_passes == 1;
+  const bool atomic_ranges = c.num_tiles <= kMaxAtomicRangeTiles;
+  bool last = c.sort_passes == 1 && atomic_ranges;
   hipLaunchKernelGGL(k_emit_sort, dim3(nb), dim3(256), 0, s, total, n, c.tiles_per, c.counts,
                      c.offsets, c.scan_tmp, nb, c.rect, c.tiles_x, c.pair_cap, c.hist, chunks,
                      nchunks, last ? nullptr : c.keys[1], c.vals[1], c.status,
@@ -780,7 +811,7 @@ hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
                        c.status, c.pair_cap, shift, c.hist, c.sort_blocks);
     e = scan_hist(256 * c.sort_blocks, &chunks, &nchunks);
     if (e != hipSuccess) return e;
-    last = pass + 1 == c.sort_passes;
+    last = pass + 1 == c.sort_passes && atomic_ranges;
     hipLaunchKernelGGL(k_radix_scatter, dim3(c.sort_blocks), dim3(256), 0, s, c.keys[cur],
                        c.vals[cur], last ? nullptr : c.keys[cur ^ 1], c.vals[cur ^ 1], c.status,
                        c.pair_cap, shift, c.hist, c.sort_blocks, chunks, nchunks,
@@ -788,6 +819,11 @@ hipError_t launch_binning(Ctx &c, int n, hipStream_t s) {
     cur ^= 1;
   }
   c.sorted = cur;
+  if (!atomic_ranges) {
+    const int64_t grid = std::min<int64_t>((c.pair_cap + 255) / 256, (int64_t)c.num_cu * 8);
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, s, c.keys[cur], c.status,
+                       c.pair_cap, c.ranges, (uint32_t)c.num_tiles);
+  }
   return hipGetLastError();
 }
 
