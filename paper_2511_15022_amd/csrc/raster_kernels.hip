@@ -1125,24 +1125,44 @@ __global__ __launch_bounds__(TW * TH) void k_raster_seg(
 #pragma unroll
   for (int k = 0; k < 2 * C; ++k) acc[k] = 0.f;
   const uint2 rng = ranges[tile];
+  // a batch's Gaussian ids and record heads; the next batch's ids are loaded
+  // before this batch is culled and its records before this batch is walked
+  constexpr int QD = kSegBatch / 64;
+  uint32_t ngid[QD];
+  float4 nr0[QD], nrx[QD];
+  auto load_ids = [&](uint32_t b) {
+#pragma unroll
+    for (int qd = 0; qd < QD; ++qd) {
+      const uint32_t idx = b + qd * 64 + lane;
+      ngid[qd] = idx < rng.y ? vals[idx] : zero_id;
+    }
+  };
+  auto load_heads = [&] {
+#pragma unroll
+    for (int qd = 0; qd < QD; ++qd) {
+      const float *g0 = rec + (size_t)ngid[qd] * RS;
+      nr0[qd] = reinterpret_cast<const float4 *>(g0)[0];       // mix, miy, mfx, mfy
+      nrx[qd] = reinterpret_cast<const float4 *>(g0 + RX)[0];  // s, kappa, ra
+    }
+  };
+  if (rng.x < rng.y) {
+    load_ids(rng.x);
+    load_heads();
+  }
   for (uint32_t base = rng.x; base < rng.y; base += kSegBatch) {
     const int cnt = (int)min((uint32_t)kSegBatch, rng.y - base);
     // ---- cull: each lane takes one Gaussian per round against the wave's
     // four segments; survivors are appended to the segment lists in order
-    constexpr int QD = kSegBatch / 64;
     uint32_t gid[QD];
     float4 r0[QD], rx[QD];
 #pragma unroll
     for (int qd = 0; qd < QD; ++qd) {
-      const int idx = qd * 64 + lane;
-      gid[qd] = idx < cnt ? vals[base + idx] : zero_id;
+      gid[qd] = ngid[qd];
+      r0[qd] = nr0[qd];
+      rx[qd] = nrx[qd];
     }
-#pragma unroll
-    for (int qd = 0; qd < QD; ++qd) {
-      const float *g0 = rec + (size_t)gid[qd] * RS;
-      r0[qd] = reinterpret_cast<const float4 *>(g0)[0];       // mix, miy, mfx, mfy
-      rx[qd] = reinterpret_cast<const float4 *>(g0 + RX)[0];  // s, kappa, ra
-    }
+    const bool more = base + kSegBatch < rng.y;  // uniform
+    if (more) load_ids(base + kSegBatch);
     int nl[4] = {0, 0, 0, 0};  // list lengths (wave-uniform)
 #pragma unroll
     for (int qd = 0; qd < QD; ++qd) {
@@ -1177,6 +1197,7 @@ __global__ __launch_bounds__(TW * TH) void k_raster_seg(
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (more) load_heads();
     // ---- walk: sixteen entries of each row's list per round; the entries
     // and amplitudes of the next round are loaded while this one runs
     const int nmax = max(max(nl[0], nl[1]), max(nl[2], nl[3]));
