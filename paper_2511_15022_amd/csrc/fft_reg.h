@@ -305,6 +305,24 @@ constexpr int pick_radix(int n) {
   return n;
 }
 
+// Measured plans that replace the greedy one for some lengths (n = 0: none).
+// With four chains over 512 threads a stage of radix R has 4 N / R
+// butterflies, one or more per thread.  For 960 the greedy 15 16 4 has a
+// radix-16 stage with 240 butterflies (half the threads idle) and two
+// radix-4 passes; 15 8 8 (256, 480, 480 butterflies) shortens the chain each
+// thread runs between barriers (row passes 36.7 -> 35.6 us, loss row pass
+// 65.3 -> 61.8 us at 1080p; 12 8 10, 8 12 10 and 10 12 8 were in between).
+template <int N>
+struct CPlanFixed {
+  static constexpr int n = 0;
+  static constexpr int r[1] = {1};
+};
+template <>
+struct CPlanFixed<960> {
+  static constexpr int n = 3;
+  static constexpr int r[3] = {15, 8, 8};
+};
+
 template <int N>
 struct CPlan {
   static constexpr int greedy(int s) {
@@ -313,6 +331,7 @@ struct CPlan {
     return pick_radix(n);
   }
   static constexpr int stages() {
+    if (CPlanFixed<N>::n) return CPlanFixed<N>::n;
     int n = N, s = 0;
     while (n > 1) {
       n /= pick_radix(n);
@@ -322,6 +341,7 @@ struct CPlan {
   }
   // s-th radix after moving the odd radices (in greedy order) to the front
   static constexpr int radix(int s) {
+    if (CPlanFixed<N>::n) return CPlanFixed<N>::r[s];
     int k = 0;
     for (int i = 0; i < stages(); ++i)
       if (greedy(i) % 2 == 1 && k++ == s) return greedy(i);
