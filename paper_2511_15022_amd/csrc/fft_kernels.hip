@@ -1218,7 +1218,7 @@ __global__ __launch_bounds__(T) void k_col_half_c(ColIO io, int H, int Wp, int W
 
 // ----------------------------------------------------------------------------
 // Column pass for Hp = 4 M with H <= 2 M, one wave per chain, M = R0 R1 R2
-// (1080 = 9 6 20 at 4K, 540 = 9 6 10 at 1080p); CONJ: multiply by conj(H)
+// (1080 = 9 6 20 at 4K, 540 = 12 5 9 at 1080p); CONJ: multiply by conj(H)
 // (the adjoint pass).
 // Output bin 4 m + p of the padded column is bin m of the M-point transform
 // of w^{p n} (x[n] + (-i)^p x[n + M]) (n < M; w = e^{-2 pi i / Hp}), so a
@@ -1391,7 +1391,7 @@ hipError_t launch_col_pass(const Ctx &c, int conj_h, int plane, const float2 *sr
     switch (col_wave4_m(c)) {
       case 1080: go(integral_constant<int, 9>{}, integral_constant<int, 6>{}, integral_constant<int, 20>{}); break;
       case 1024: go(integral_constant<int, 8>{}, integral_constant<int, 8>{}, integral_constant<int, 16>{}); break;
-      case 540: go(integral_constant<int, 9>{}, integral_constant<int, 6>{}, integral_constant<int, 10>{}); break;
+      case 540: go(integral_constant<int, 12>{}, integral_constant<int, 5>{}, integral_constant<int, 9>{}); break;
       case 512: go(integral_constant<int, 8>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
       case 384: go(integral_constant<int, 6>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
       default: go(integral_constant<int, 4>{}, integral_constant<int, 8>{}, integral_constant<int, 8>{}); break;
